@@ -1,0 +1,89 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds no arithmetic of the method: only parameter sets, seeded
+random draws and index bookkeeping of the patch labelling (how the eight
+C4v operations permute patch labels).  Both the GPU path and the CPU oracle
+receive what it produces; neither is imported here.
+
+The workloads are parametric (Sec. 4 of the paper uses a parameter set of the
+2D Hubbard model, not a data set), so every input is synthetic.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Parameter sets of the five workloads (t = 1 throughout).
+CONFIGS = {
+    # plain FP64, small: half filling, 40 fixed RK4 steps T = 1 -> 0.05
+    "C1": dict(t=1.0, tp=0.0, mu=0.0, U=2.0, N=16, n_rad=8, n_ang=8,
+               flow=dict(stepper="rk4", T0=1.0, T_min=0.05, fixed_steps=40, vmax=20.0)),
+    # production FP64: van Hove filling mu = 4t', adaptive DP5(4), stop at 20t or T = 1e-3
+    "C2": dict(t=1.0, tp=-0.25, mu=-1.0, U=3.0, N=48, n_rad=16, n_ang=16,
+               flow=dict(stepper="dp54", T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10,
+                         vmax=20.0, h0=-0.01)),
+    # precision form at N = 96
+    "C3": dict(t=1.0, tp=-0.3, mu=-1.2, U=3.0, N=96, n_rad=32, n_ang=16,
+               flow=dict(stepper="dp54", T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10,
+                         vmax=20.0, h0=-0.01)),
+    # large
+    "C5": dict(t=1.0, tp=-0.25, mu=-1.0, U=2.5, N=192, n_rad=32, n_ang=32,
+               flow=dict(stepper="dp54", T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10,
+                         vmax=20.0, h0=-0.01, max_steps=30)),
+}
+
+C4_SEED = 151007799
+C4_NS = (32, 48, 64, 96)
+
+
+def model_params(name: str) -> dict:
+    c = CONFIGS[name]
+    return {k: c[k] for k in ("t", "tp", "mu", "U", "N", "n_rad", "n_ang")}
+
+
+def c4_flows(n_per_N: int = 64, seed: int = C4_SEED, Ns=C4_NS, n_rad=16, n_ang=16):
+    """Batched workload: n_per_N flows for each N, (mu, t', U) uniform in
+    [-1.5,0] x [-0.35,0] x [1,4] from one seeded generator (PCG64)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for N in Ns:
+        for _ in range(n_per_N):
+            mu = rng.uniform(-1.5, 0.0)
+            tp = rng.uniform(-0.35, 0.0)
+            U = rng.uniform(1.0, 4.0)
+            out.append(dict(t=1.0, tp=float(tp), mu=float(mu), U=float(U), N=N,
+                            n_rad=n_rad, n_ang=n_ang))
+    return out
+
+
+def c4v_patch_perm(N: int, o: int) -> np.ndarray:
+    """Label of the image of patch j under C4v element o (0..7): even o rotate
+    by o*pi/4, odd o reflect about the axis at (o+1)*pi/8; patch j spans
+    angles [j, j+1) * 2pi/N."""
+    j = np.arange(N)
+    q = N // 4
+    if o % 2 == 0:
+        return (j + (o // 2) * q) % N
+    return (((o + 1) // 2) * q - 1 - j) % N
+
+
+def constant_vertex(N: int, U: float) -> np.ndarray:
+    return np.full((N, N, N), float(U))
+
+
+def random_vertex(N: int, U: float, seed: int, amp: float = 0.5, symmetrise: bool = True):
+    """V = U (1 + amp * eta), eta uniform in [-1, 1], optionally averaged over C4v."""
+    rng = np.random.default_rng(seed)
+    V = U * (1.0 + amp * rng.uniform(-1.0, 1.0, size=(N, N, N)))
+    if symmetrise:
+        acc = np.zeros_like(V)
+        for o in range(8):
+            g = c4v_patch_perm(N, o)
+            acc += V[np.ix_(g, g, g)]
+        V = acc / 8.0
+    return np.ascontiguousarray(V)
+
+
+def random_entries(N: int, n: int, seed: int) -> np.ndarray:
+    """n seeded triples (j1, j2, j3) uniform in N^3 (int32, shape [n, 3])."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, N, size=(n, 3), dtype=np.int64).astype(np.int32)
