@@ -1,0 +1,191 @@
+/*
+ * frg.h -- C ABI of libfrg, the MI355X (gfx950) engine for the right-hand side
+ * of the discretised one-loop fRG flow of the 2D Hubbard four-point vertex.
+ *
+ * The paper (Rohe, "Hierarchical Parallelisation of Functional Renormalisation
+ * Group Calculations - hp-fRG") states the problem in Sec. 2, Eq. (1):
+ * all discretised couplings live in one flat array V[i] that obeys
+ * dV[i]/dg = F[V[j]; g], integrated by an explicit stepper so that F is
+ * computed for every component with V frozen, after which the step is taken.
+ * Sec. 4 fixes the instance: the square-lattice Hubbard model (hoppings t, t',
+ * chemical potential mu), three one-loop diagrams (particle-particle, direct
+ * and crossed particle-hole) integrated over the Brillouin zone, N patches.
+ * Here the flow parameter is the temperature: F = dV/dT, integrated in
+ * s = ln T.
+ *
+ * Conventions shared by every call:
+ *  - Every call returns frg_status; no C++ exception crosses the ABI.
+ *    Argument errors are detected on the host before anything is enqueued and
+ *    leave device memory untouched.  Device errors surface as FRG_EDEVICE at
+ *    the call that detects them (launch errors at once, faults at the next
+ *    synchronising call).  frg_last_error() gives a thread-local message.
+ *  - Pointers named d_* are device pointers owned by the caller, 256-byte
+ *    aligned (any hipMalloc / torch CUDA allocation is), sized by frg_sizes.
+ *    The context owns its geometry tables and workspace.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    device work is enqueued asynchronously on it; frg_flow synchronises once
+ *    per step to read one status word.
+ *  - V and F are [N][N][N] row-major FP64, V[j1][j2][j3] = V(k1,k2,k3) with
+ *    k4 = k1 + k2 - k3.  F is dV/dT (not dV/ds).
+ *  - Bubble tensors are [row][a][b] (a: patch of the fine-grid loop line,
+ *    b: patch of the second line).  pp rows: pairs (i <= j) in lexicographic
+ *    order, transfer q = k_i + k_j.  ph rows: row 0 is Q = 0; then pairs
+ *    (x, y), x != y, lexicographic, transfer Q = k_x - k_y.
+ *  - A context is not thread-safe; use one per stream.
+ */
+#ifndef FRG_H
+#define FRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FRG_OK = 0,
+    FRG_EINVAL = 1,      /* bad argument (detected before any launch) */
+    FRG_ENOMEM = 2,      /* device or host allocation failed */
+    FRG_EDEVICE = 3,     /* HIP runtime / kernel error */
+    FRG_ENOTSUP = 4,     /* valid but unsupported size or mode */
+    FRG_ENONFINITE = 5   /* a flow produced NaN/Inf */
+} frg_status;
+
+typedef enum {
+    FRG_PREC_FP64 = 0,        /* FP64 bubbles, FP64 MFMA contraction */
+    FRG_PREC_SPLIT_BF16 = 1   /* FP32 compensated bubbles, split-BF16 (hi+lo) MFMA, FP32 accumulate */
+} frg_precision;
+
+typedef enum { FRG_RK4 = 0, FRG_DP54 = 1 } frg_stepper;
+
+typedef enum {
+    FRG_STOP_NONE = 0,
+    FRG_STOP_TMIN = 1,       /* reached T_min */
+    FRG_STOP_DIVERGED = 2,   /* max|V| > vmax after an accepted step: a result, not an error */
+    FRG_STOP_MAXSTEPS = 3,
+    FRG_STOP_NONFINITE = 4,
+    FRG_STOP_HMIN = 5        /* step size underflow */
+} frg_stop;
+
+/* Model: eps(k) = -2t(cos kx + cos ky) - 4t'(cos kx cos ky) - mu.
+ * N patches, 4 <= N <= 256, N % 4 == 0; n_rad x n_ang fine points per patch,
+ * 1 <= n_rad*n_ang <= 1024.  U is the bare coupling (V = U initially). */
+typedef struct {
+    double t, tp, mu, U;
+    int32_t N, n_rad, n_ang;
+} frg_params;
+
+/* Flow options.  stepper RK4: fixed_steps uniform steps in s = ln T from T0
+ * to T_min.  DP54: Dormand-Prince 5(4), first step h0 (in s, sign ignored:
+ * always towards T_min), err = max|y5-y4|/(atol + rtol max(|y|,|y5|)),
+ * accept if err <= 1, h <- h clamp(0.9 err^-1/5, 0.2, 5), last step clipped
+ * onto T_min.  Both stop after an accepted step with max|V| > vmax.
+ * max_steps > 0 caps accepted steps. */
+typedef struct {
+    frg_stepper stepper;
+    frg_precision prec;
+    double T0, T_min, rtol, atol, vmax, h0;
+    int32_t fixed_steps, max_steps;
+} frg_flow_opts;
+
+typedef struct {
+    frg_stop reason;
+    double T_end;        /* temperature of the final state */
+    double T_c;          /* T at the first accepted step with max|V| > vmax (NaN if none) */
+    double T_c_interp;   /* crossing interpolated linearly in s */
+    int32_t accepted, rejected, rhs_evals, first_step_rhs;
+} frg_flow_result;
+
+/* Device-side flow state used by frg_flow_step (FRG_STATE_LEN doubles). */
+#define FRG_STATE_LEN 32
+enum {
+    FRG_ST_S = 0,          /* current s = ln T */
+    FRG_ST_H = 1,          /* next step size */
+    FRG_ST_ERR = 2,        /* error norm of the last attempt */
+    FRG_ST_REASON = 3,     /* frg_stop of the flow (0 while running) */
+    FRG_ST_ACCEPTED = 4,
+    FRG_ST_REJECTED = 5,
+    FRG_ST_RHS = 6,        /* rhs evaluations so far */
+    FRG_ST_VMAX = 7,       /* max|V| of the current state */
+    FRG_ST_SC = 8,         /* s at divergence */
+    FRG_ST_SC_INTERP = 9,
+    FRG_ST_FIRST_RHS = 10, /* rhs evaluations spent up to the first accepted step */
+    FRG_ST_SMIN = 11,      /* target s = ln T_min */
+    FRG_ST_FSAL = 12       /* 1 when the stored first-stage derivative is valid */
+};
+
+typedef struct frg_ctx_s *frg_ctx;
+
+/* Build the host geometry (patch centres, sector boundaries, fine grid,
+ * transfer momenta; plain FP64 on the host, no FP contraction), upload it,
+ * and tabulate on the device the patch of every second loop line (one byte
+ * per (row, fine point); temperature independent).  Cost: one-off.
+ * Errors: EINVAL for bad parameters or out==NULL, ENOTSUP for n_f > 1024,
+ * ENOMEM, EDEVICE (no gfx950 device). */
+frg_status frg_create(const frg_params *p, frg_ctx *out);
+frg_status frg_destroy(frg_ctx ctx);
+
+/* Element counts: V/F entries (N^3), pp and ph bubble entries (rows*N*N),
+ * and the device workspace the context holds. Any pointer may be NULL. */
+frg_status frg_sizes(frg_ctx ctx, size_t *n_v, size_t *n_bpp, size_t *n_bph,
+                     size_t *workspace_bytes);
+
+/* Copy the host geometry out (host pointers, any may be NULL):
+ * kc[N][2], bnd[N+1][2], fine[N*n_f][4] = (px, py, w, xi), qpp[Tpp][2],
+ * qph[Tph][2], idx4[N][N][N] = patch of k1 + k2 - k3. */
+frg_status frg_tables(frg_ctx ctx, double *kc, double *bnd, double *fine, double *qpp,
+                      double *qph, int32_t *idx4);
+
+/* Host-only: build the geometry for p and copy it out as frg_tables does,
+ * without a context or a device (any output may be NULL). */
+frg_status frg_host_tables(const frg_params *p, double *kc, double *bnd, double *fine,
+                           double *qpp, double *qph, int32_t *idx4);
+
+/* Copy the device table of second-line patches (kind 0 = ph, 1 = pp) into
+ * d_out[rows][N*n_f] (uint8). */
+frg_status frg_bins(frg_ctx ctx, int32_t kind, uint8_t *d_out, void *stream);
+
+/* Bubble derivatives at temperature T > 0 (Sec. 4: the three one-loop
+ * diagrams share two kinds of bubble):
+ *   Bpp_q(a,b) = sum_{p in a, pi(q-p) = b} w_p dL_pp/dT(xi_p, eps(q-p))
+ *   Bph_Q(a,b) = sum_{p in a, pi(p+Q) = b} w_p dL_ph/dT(xi_p, eps(p+Q))
+ * FP64: d_bpp/d_bph are double; SPLIT_BF16: float (compensated sums).
+ * Either output may be NULL. */
+frg_status frg_bubbles(frg_ctx ctx, double T, frg_precision prec, void *d_bpp, void *d_bph,
+                       void *stream);
+
+/* One rhs evaluation F = dV/dT at temperature T for all N^3 entries (Eq. (1)
+ * with V frozen; the three one-loop channels).  d_V and d_F are [N][N][N]
+ * FP64 and must not overlap. */
+frg_status frg_rhs(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_precision prec,
+                   void *stream);
+
+/* Initialise a device flow state (FRG_STATE_LEN doubles) for o: s = ln T0,
+ * h = first step, counters zero.  d_V is the initial vertex (unchanged). */
+frg_status frg_flow_init(frg_ctx ctx, const frg_flow_opts *o, const double *d_V,
+                         double *d_state, void *stream);
+
+/* One step attempt (RK4: one step; DP54: one attempt, accepted or rejected)
+ * of the explicit stepper of Eq. (1) in s = ln T, entirely on the device:
+ * the stages, the FP64 error norm, the step control and the stop test read
+ * and write d_state; nothing is synchronised.  Does nothing once
+ * d_state[FRG_ST_REASON] != 0. */
+frg_status frg_flow_step(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_state,
+                         void *stream);
+
+/* Whole flow from V0 (in d_V, overwritten with the final state) until a stop
+ * condition.  d_log (nullable, device) receives 8 doubles per accepted step:
+ * s, h, err, max|V|, rhs_evals, rejected, accepted, reason (up to
+ * log_cap rows).  Synchronises once per step.  Returns FRG_ENONFINITE if the
+ * state became non-finite (r->reason = FRG_STOP_NONFINITE). */
+frg_status frg_flow(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_log,
+                    int32_t log_cap, frg_flow_result *r, void *stream);
+
+const char *frg_status_str(frg_status st);
+const char *frg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

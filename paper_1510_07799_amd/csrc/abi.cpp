@@ -1,0 +1,573 @@
+// C ABI of libfrg: argument checks, context and workspace ownership, the rhs
+// pipeline (bubbles -> operand layout -> channel contractions -> combine) and
+// the explicit flow of Eq. (1) in s = ln T with on-device step control.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "frg_internal.h"
+
+
+struct frg_ctx_s {
+    frg::Geometry g;
+    int device = 0;
+    int Trows = 0;
+    int64_t n3 = 0;
+    // temperature-independent device tables
+    double *d_bnd = nullptr, *d_xi = nullptr, *d_w = nullptr, *d_trig_row = nullptr,
+           *d_trig_pt = nullptr;
+    uint8_t *d_bins = nullptr;
+    int32_t *d_colrow_pp = nullptr, *d_colrow_ph = nullptr;
+    // rhs workspace
+    double *d_pa64 = nullptr, *d_T = nullptr;
+    float *d_pa32 = nullptr;
+    double *d_B64 = nullptr;
+    float *d_B32 = nullptr;
+    double *d_perm = nullptr;
+    uint16_t *d_ahl = nullptr;
+    float *d_g32 = nullptr;
+    double *d_C = nullptr;
+    // flow workspace
+    double *d_k[7] = {nullptr};
+    double *d_yt = nullptr, *d_y5 = nullptr, *d_partial = nullptr, *d_state = nullptr;
+    double *h_state = nullptr;
+    int nred = 256;
+    size_t ws_bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+frg_status fail(frg_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (expr);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(e_ == hipErrorOutOfMemory ? FRG_ENOMEM : FRG_EDEVICE,         \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));           \
+    } while (0)
+
+template <class T>
+frg_status dalloc(frg_ctx ctx, T **p, size_t n) {
+    if (*p) return FRG_OK;
+    void *q = nullptr;
+    const size_t bytes = sizeof(T) * (n ? n : 1);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(FRG_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    *p = static_cast<T *>(q);
+    ctx->ws_bytes += bytes;
+    return FRG_OK;
+}
+
+template <class T>
+frg_status upload(frg_ctx ctx, T **p, const T *src, size_t n) {
+    frg_status st = dalloc(ctx, p, n);
+    if (st) return st;
+    HIPCHK(hipMemcpy(*p, src, sizeof(T) * n, hipMemcpyHostToDevice));
+    return FRG_OK;
+}
+
+#define TRY(x)                        \
+    do {                              \
+        frg_status s_ = (x);          \
+        if (s_ != FRG_OK) return s_;  \
+    } while (0)
+
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+
+frg_status check_prec(frg_precision p) {
+    if (p != FRG_PREC_FP64 && p != FRG_PREC_SPLIT_BF16)
+        return fail(FRG_EINVAL, "unknown precision");
+    return FRG_OK;
+}
+
+frg_status ensure_rhs_ws(frg_ctx ctx, frg_precision prec) {
+    const auto &g = ctx->g;
+    const size_t NN = static_cast<size_t>(g.N) * g.N;
+    TRY(dalloc(ctx, &ctx->d_T, 4));
+    TRY(dalloc(ctx, &ctx->d_C, 3 * static_cast<size_t>(ctx->n3)));
+    if (prec == FRG_PREC_FP64) {
+        TRY(dalloc(ctx, &ctx->d_pa64, 3 * static_cast<size_t>(g.np)));
+        TRY(dalloc(ctx, &ctx->d_B64, NN * ctx->Trows));
+        TRY(dalloc(ctx, &ctx->d_perm, 5 * static_cast<size_t>(ctx->n3)));
+    } else {
+        TRY(dalloc(ctx, &ctx->d_pa32, 3 * static_cast<size_t>(g.np)));
+        TRY(dalloc(ctx, &ctx->d_B32, NN * ctx->Trows));
+        TRY(dalloc(ctx, &ctx->d_ahl, 8 * static_cast<size_t>(ctx->n3)));
+        TRY(dalloc(ctx, &ctx->d_g32, 3 * static_cast<size_t>(ctx->n3)));
+    }
+    return FRG_OK;
+}
+
+frg_status ensure_flow_ws(frg_ctx ctx) {
+    for (int j = 0; j < 7; ++j) TRY(dalloc(ctx, &ctx->d_k[j], ctx->n3));
+    TRY(dalloc(ctx, &ctx->d_yt, ctx->n3));
+    TRY(dalloc(ctx, &ctx->d_y5, ctx->n3));
+    TRY(dalloc(ctx, &ctx->d_partial, 2 * static_cast<size_t>(ctx->nred)));
+    TRY(dalloc(ctx, &ctx->d_state, FRG_STATE_LEN));
+    if (!ctx->h_state) HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&ctx->h_state),
+                                            sizeof(double) * FRG_STATE_LEN, hipHostMallocDefault));
+    return FRG_OK;
+}
+
+frg::BubbleArgs bubble_args(frg_ctx ctx, bool fp32, void *bpp, void *bph) {
+    const auto &g = ctx->g;
+    frg::BubbleArgs a;
+    a.N = g.N;
+    a.nf = g.nf;
+    a.np = g.np;
+    a.Tpp = g.Tpp;
+    a.Trows = ctx->Trows;
+    a.mt2 = -2.0 * g.t;
+    a.mt4p = 4.0 * g.tp;
+    a.mu = g.mu;
+    a.bins = ctx->d_bins;
+    a.trig_row = ctx->d_trig_row;
+    a.trig_pt = ctx->d_trig_pt;
+    a.pa64 = fp32 ? nullptr : ctx->d_pa64;
+    a.pa32 = fp32 ? ctx->d_pa32 : nullptr;
+    a.Tdev = ctx->d_T;
+    a.Bpp = bpp;
+    a.Bph = bph;
+    return a;
+}
+
+// prep + bubbles into the context's bubble tensor (or caller buffers)
+frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *state, double c,
+                       void *bpp, void *bph, hipStream_t s) {
+    frg::launch_point_prep(ctx->d_xi, ctx->d_w, ctx->g.np, T_host, state, c,
+                           split ? nullptr : ctx->d_pa64, split ? ctx->d_pa32 : nullptr, ctx->d_T, s);
+    frg::launch_bubbles(bubble_args(ctx, split, bpp, bph), split, s);
+    HIPCHK(hipGetLastError());
+    return FRG_OK;
+}
+
+// full rhs: F = scale * (-Cpp + Cc + Cd); scale = T when scale_by_T
+frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, double c,
+                   const double *V, double *F, int scale_by_T, hipStream_t s) {
+    const auto &g = ctx->g;
+    const int N = g.N;
+    const size_t NN = static_cast<size_t>(N) * N;
+    const int64_t n3 = ctx->n3;
+    void *bpp = split ? static_cast<void *>(ctx->d_B32) : static_cast<void *>(ctx->d_B64);
+    void *bph = split ? static_cast<void *>(ctx->d_B32 + NN * g.Tpp)
+                      : static_cast<void *>(ctx->d_B64 + NN * g.Tpp);
+    TRY(run_bubbles(ctx, split, T_host, state, c, bpp, bph, s));
+    double *Cpp = ctx->d_C, *Cc = ctx->d_C + n3, *Cd = ctx->d_C + 2 * n3;
+    frg::ContractArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.N = N;
+    if (!split) {
+        frg::launch_layout_f64(V, N, ctx->d_perm, s);
+        const double *P = ctx->d_perm;
+        a.term = frg::TERM_PP; a.B = bpp; a.colrow = ctx->d_colrow_pp;
+        a.A64[0] = P; a.G64[0] = V; a.C = Cpp;
+        frg::launch_contract(a, false, s);
+        a.term = frg::TERM_PHC; a.B = bph; a.colrow = ctx->d_colrow_ph;
+        a.A64[0] = V; a.G64[0] = P + n3; a.C = Cc;
+        frg::launch_contract(a, false, s);
+        a.term = frg::TERM_PHD;
+        a.A64[0] = P + 2 * n3; a.G64[0] = P + 4 * n3;
+        a.A64[1] = P + 3 * n3; a.G64[1] = P + 4 * n3; a.C = Cd;
+        frg::launch_contract(a, false, s);
+    } else {
+        frg::launch_layout_split(V, N, ctx->d_ahl, ctx->d_g32, s);
+        const uint16_t *H = ctx->d_ahl;
+        const float *G = ctx->d_g32;
+        a.term = frg::TERM_PP; a.B = bpp; a.colrow = ctx->d_colrow_pp;
+        a.Ahl[0] = H; a.G32[0] = G; a.C = Cpp;
+        frg::launch_contract(a, true, s);
+        a.term = frg::TERM_PHC; a.B = bph; a.colrow = ctx->d_colrow_ph;
+        a.Ahl[0] = H + 2 * n3; a.G32[0] = G + n3; a.C = Cc;
+        frg::launch_contract(a, true, s);
+        a.term = frg::TERM_PHD;
+        a.Ahl[0] = H + 4 * n3; a.G32[0] = G + 2 * n3;
+        a.Ahl[1] = H + 6 * n3; a.G32[1] = G + 2 * n3; a.C = Cd;
+        frg::launch_contract(a, true, s);
+    }
+    frg::launch_combine(Cpp, Cc, Cd, n3, ctx->d_T, scale_by_T, F, s);
+    HIPCHK(hipGetLastError());
+    return FRG_OK;
+}
+
+frg_status check_ctx(frg_ctx ctx) {
+    if (!ctx) return fail(FRG_EINVAL, "null context");
+    return FRG_OK;
+}
+
+frg_status check_opts(frg_ctx ctx, const frg_flow_opts *o) {
+    (void)ctx;
+    if (!o) return fail(FRG_EINVAL, "null flow options");
+    TRY(check_prec(o->prec));
+    if (o->stepper != FRG_RK4 && o->stepper != FRG_DP54) return fail(FRG_EINVAL, "unknown stepper");
+    if (!(o->T0 > 0.0) || !std::isfinite(o->T0) || !(o->T_min > 0.0) || !std::isfinite(o->T_min) ||
+        o->T0 == o->T_min)
+        return fail(FRG_EINVAL, "need finite T0 > 0, T_min > 0, T0 != T_min");
+    if (!(o->vmax > 0.0)) return fail(FRG_EINVAL, "vmax must be > 0");
+    if (o->stepper == FRG_RK4 && o->fixed_steps <= 0)
+        return fail(FRG_EINVAL, "RK4 needs fixed_steps > 0");
+    if (o->stepper == FRG_DP54 && (!(o->rtol > 0.0) || !(o->atol >= 0.0) || !std::isfinite(o->h0)))
+        return fail(FRG_EINVAL, "DP54 needs rtol > 0, atol >= 0, finite h0");
+    if (o->max_steps < 0) return fail(FRG_EINVAL, "max_steps must be >= 0");
+    return FRG_OK;
+}
+
+// Dormand & Prince (1980) 5(4) tableau
+const double DP_C[7] = {0.0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1.0, 1.0};
+const double DP_A[7][6] = {{0},
+                           {1.0 / 5},
+                           {3.0 / 40, 9.0 / 40},
+                           {44.0 / 45, -56.0 / 15, 32.0 / 9},
+                           {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729},
+                           {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656},
+                           {35.0 / 384, 0.0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+const double DP_E[7] = {35.0 / 384 - 5179.0 / 57600, 0.0, 500.0 / 1113 - 7571.0 / 16695,
+                        125.0 / 192 - 393.0 / 640, -2187.0 / 6784 + 92097.0 / 339200,
+                        11.0 / 84 - 187.0 / 2100, -1.0 / 40};
+
+int red_blocks(int64_t n) {
+    int64_t b = (n + 255) / 256;
+    return static_cast<int>(b < 256 ? (b < 1 ? 1 : b) : 256);
+}
+
+}  // namespace
+
+static frg_status check_params(const frg_params *p);
+
+extern "C" {
+
+const char *frg_status_str(frg_status st) {
+    switch (st) {
+    case FRG_OK: return "ok";
+    case FRG_EINVAL: return "invalid argument";
+    case FRG_ENOMEM: return "out of memory";
+    case FRG_EDEVICE: return "device error";
+    case FRG_ENOTSUP: return "not supported";
+    case FRG_ENONFINITE: return "non-finite state";
+    }
+    return "unknown status";
+}
+
+const char *frg_last_error(void) { return g_err.c_str(); }
+
+frg_status frg_create(const frg_params *p, frg_ctx *out) {
+    if (!out) return fail(FRG_EINVAL, "null output handle");
+    *out = nullptr;
+    TRY(check_params(p));
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(FRG_EDEVICE, "no HIP device");
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(FRG_EDEVICE, std::string("libfrg is built for gfx950, device is ") + prop.gcnArchName);
+
+    frg_ctx ctx = new frg_ctx_s();
+    ctx->device = dev;
+    frg::build_geometry(*p, ctx->g);
+    const auto &g = ctx->g;
+    ctx->Trows = g.Tpp + g.Tph;
+    ctx->n3 = static_cast<int64_t>(g.N) * g.N * g.N;
+    auto bail = [&](frg_status st) { std::string m = g_err; frg_destroy(ctx); g_err = m; return st; };
+
+    std::vector<double> qrow(2 * static_cast<size_t>(ctx->Trows)), trig_row(4 * static_cast<size_t>(ctx->Trows));
+    for (int r = 0; r < ctx->Trows; ++r) {
+        const double *q = r < g.Tpp ? &g.qpp[2 * r] : &g.qph[2 * (r - g.Tpp)];
+        qrow[2 * r] = q[0];
+        qrow[2 * r + 1] = q[1];
+        trig_row[4 * r] = std::cos(q[0]);
+        trig_row[4 * r + 1] = std::sin(q[0]);
+        trig_row[4 * r + 2] = std::cos(q[1]);
+        trig_row[4 * r + 3] = std::sin(q[1]);
+    }
+    std::vector<double> trig_pt(4 * static_cast<size_t>(g.np));
+    for (int i = 0; i < g.np; ++i) {
+        trig_pt[i] = std::cos(g.px[i]);
+        trig_pt[g.np + i] = std::sin(g.px[i]);
+        trig_pt[2 * g.np + i] = std::cos(g.py[i]);
+        trig_pt[3 * g.np + i] = std::sin(g.py[i]);
+    }
+    std::vector<int32_t> cpp(static_cast<size_t>(g.N) * g.N), cph(static_cast<size_t>(g.N) * g.N);
+    for (int y = 0; y < g.N; ++y)
+        for (int x = 0; x < g.N; ++x) {
+            cpp[y * g.N + x] = g.row_pp[y * g.N + x];   // column (j1=y, j2=x)
+            cph[y * g.N + x] = g.row_ph[x * g.N + y];   // column (y, x): transfer k_x - k_y
+        }
+    double *d_px = nullptr, *d_py = nullptr, *d_qrow = nullptr;
+    frg_status st;
+    if ((st = upload(ctx, &ctx->d_bnd, g.bnd.data(), g.bnd.size())) ||
+        (st = upload(ctx, &ctx->d_xi, g.xi.data(), g.xi.size())) ||
+        (st = upload(ctx, &ctx->d_w, g.w.data(), g.w.size())) ||
+        (st = upload(ctx, &ctx->d_trig_row, trig_row.data(), trig_row.size())) ||
+        (st = upload(ctx, &ctx->d_trig_pt, trig_pt.data(), trig_pt.size())) ||
+        (st = upload(ctx, &ctx->d_colrow_pp, cpp.data(), cpp.size())) ||
+        (st = upload(ctx, &ctx->d_colrow_ph, cph.data(), cph.size())) ||
+        (st = dalloc(ctx, &ctx->d_bins, static_cast<size_t>(ctx->Trows) * g.np)))
+        return bail(st);
+    size_t tmp_bytes = 0;
+    if ((st = upload(ctx, &d_px, g.px.data(), g.px.size())) ||
+        (st = upload(ctx, &d_py, g.py.data(), g.py.size())) ||
+        (st = upload(ctx, &d_qrow, qrow.data(), qrow.size()))) {
+        hipFree(d_px); hipFree(d_py); hipFree(d_qrow);
+        return bail(st);
+    }
+    tmp_bytes = sizeof(double) * (2 * g.np + qrow.size());
+    frg::launch_bins(ctx->d_bnd, d_px, d_py, d_qrow, g.N, g.np, g.Tpp, ctx->Trows, ctx->d_bins, nullptr);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    hipFree(d_px);
+    hipFree(d_py);
+    hipFree(d_qrow);
+    ctx->ws_bytes -= tmp_bytes;
+    if (e != hipSuccess) {
+        g_err = std::string("second-line table: ") + hipGetErrorString(e);
+        return bail(FRG_EDEVICE);
+    }
+    *out = ctx;
+    return FRG_OK;
+}
+
+frg_status frg_destroy(frg_ctx ctx) {
+    if (!ctx) return FRG_OK;
+    void *ptrs[] = {ctx->d_bnd, ctx->d_xi, ctx->d_w, ctx->d_trig_row, ctx->d_trig_pt, ctx->d_bins,
+                    ctx->d_colrow_pp, ctx->d_colrow_ph, ctx->d_pa64, ctx->d_T, ctx->d_pa32,
+                    ctx->d_B64, ctx->d_B32, ctx->d_perm, ctx->d_ahl, ctx->d_g32, ctx->d_C,
+                    ctx->d_yt, ctx->d_y5, ctx->d_partial, ctx->d_state};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    for (int j = 0; j < 7; ++j)
+        if (ctx->d_k[j]) hipFree(ctx->d_k[j]);
+    if (ctx->h_state) hipHostFree(ctx->h_state);
+    delete ctx;
+    return FRG_OK;
+}
+
+frg_status frg_sizes(frg_ctx ctx, size_t *n_v, size_t *n_bpp, size_t *n_bph, size_t *ws) {
+    TRY(check_ctx(ctx));
+    const size_t NN = static_cast<size_t>(ctx->g.N) * ctx->g.N;
+    if (n_v) *n_v = static_cast<size_t>(ctx->n3);
+    if (n_bpp) *n_bpp = NN * ctx->g.Tpp;
+    if (n_bph) *n_bph = NN * ctx->g.Tph;
+    if (ws) *ws = ctx->ws_bytes;
+    return FRG_OK;
+}
+
+frg_status frg_tables(frg_ctx ctx, double *kc, double *bnd, double *fine, double *qpp, double *qph,
+                      int32_t *idx4) {
+    TRY(check_ctx(ctx));
+    const auto &g = ctx->g;
+    if (kc) std::memcpy(kc, g.kc.data(), sizeof(double) * g.kc.size());
+    if (bnd) std::memcpy(bnd, g.bnd.data(), sizeof(double) * g.bnd.size());
+    if (fine)
+        for (int i = 0; i < g.np; ++i) {
+            fine[4 * i] = g.px[i];
+            fine[4 * i + 1] = g.py[i];
+            fine[4 * i + 2] = g.w[i];
+            fine[4 * i + 3] = g.xi[i];
+        }
+    if (qpp) std::memcpy(qpp, g.qpp.data(), sizeof(double) * g.qpp.size());
+    if (qph) std::memcpy(qph, g.qph.data(), sizeof(double) * g.qph.size());
+    if (idx4) frg::host_idx4(g, idx4);
+    return FRG_OK;
+}
+
+static frg_status check_params(const frg_params *p) {
+    if (!p) return fail(FRG_EINVAL, "null parameters");
+    if (p->N < 4 || p->N > 256 || p->N % 4 != 0)
+        return fail(FRG_EINVAL, "N must satisfy 4 <= N <= 256 and N % 4 == 0");
+    if (p->n_rad < 1 || p->n_ang < 1) return fail(FRG_EINVAL, "n_rad, n_ang must be >= 1");
+    if (static_cast<int64_t>(p->n_rad) * p->n_ang > 1024)
+        return fail(FRG_ENOTSUP, "n_rad * n_ang > 1024 points per patch is not supported");
+    if (!std::isfinite(p->t) || !std::isfinite(p->tp) || !std::isfinite(p->mu) ||
+        !std::isfinite(p->U) || p->t == 0.0)
+        return fail(FRG_EINVAL, "model parameters must be finite and t != 0");
+    return FRG_OK;
+}
+
+frg_status frg_host_tables(const frg_params *p, double *kc, double *bnd, double *fine, double *qpp,
+                           double *qph, int32_t *idx4) {
+    TRY(check_params(p));
+    frg_ctx_s tmp;
+    frg::build_geometry(*p, tmp.g);
+    return frg_tables(&tmp, kc, bnd, fine, qpp, qph, idx4);
+}
+
+frg_status frg_bins(frg_ctx ctx, int32_t kind, uint8_t *d_out, void *stream) {
+    TRY(check_ctx(ctx));
+    if (!d_out) return fail(FRG_EINVAL, "null output");
+    if (kind != 0 && kind != 1) return fail(FRG_EINVAL, "kind must be 0 (ph) or 1 (pp)");
+    const auto &g = ctx->g;
+    const size_t off = kind == 1 ? 0 : static_cast<size_t>(g.Tpp) * g.np;
+    const size_t n = static_cast<size_t>(kind == 1 ? g.Tpp : g.Tph) * g.np;
+    HIPCHK(hipMemcpyAsync(d_out, ctx->d_bins + off, n, hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(stream)));
+    return FRG_OK;
+}
+
+frg_status frg_bubbles(frg_ctx ctx, double T, frg_precision prec, void *d_bpp, void *d_bph,
+                       void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_prec(prec));
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(FRG_EINVAL, "T must be finite and > 0");
+    if ((d_bpp && !aligned8(d_bpp)) || (d_bph && !aligned8(d_bph)))
+        return fail(FRG_EINVAL, "misaligned output");
+    TRY(ensure_rhs_ws(ctx, prec));
+    return run_bubbles(ctx, prec == FRG_PREC_SPLIT_BF16, T, nullptr, 0.0, d_bpp, d_bph,
+                       static_cast<hipStream_t>(stream));
+}
+
+frg_status frg_rhs(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_precision prec,
+                   void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_prec(prec));
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(FRG_EINVAL, "T must be finite and > 0");
+    if (!d_V || !d_F) return fail(FRG_EINVAL, "null V or F");
+    if (!aligned8(d_V) || !aligned8(d_F)) return fail(FRG_EINVAL, "V and F must be 8-byte aligned");
+    const size_t bytes = sizeof(double) * static_cast<size_t>(ctx->n3);
+    if (overlap(d_V, bytes, d_F, bytes)) return fail(FRG_EINVAL, "V and F overlap");
+    TRY(ensure_rhs_ws(ctx, prec));
+    return run_rhs(ctx, prec == FRG_PREC_SPLIT_BF16, T, nullptr, 0.0, d_V, d_F, 0,
+                   static_cast<hipStream_t>(stream));
+}
+
+frg_status frg_flow_init(frg_ctx ctx, const frg_flow_opts *o, const double *d_V, double *d_state,
+                         void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_opts(ctx, o));
+    if (!d_V || !d_state || !aligned8(d_V) || !aligned8(d_state))
+        return fail(FRG_EINVAL, "null or misaligned V / state");
+    TRY(ensure_rhs_ws(ctx, o->prec));
+    TRY(ensure_flow_ws(ctx));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double s0 = std::log(o->T0), smin = std::log(o->T_min);
+    const double dir = smin < s0 ? -1.0 : 1.0;
+    double h;
+    if (o->stepper == FRG_RK4) {
+        h = (smin - s0) / static_cast<double>(o->fixed_steps);
+    } else {
+        h = o->h0 == 0.0 ? 0.01 : std::fabs(o->h0);
+        h *= dir;
+    }
+    frg::launch_state_init(d_state, s0, h, smin, s);
+    if (o->stepper == FRG_RK4) frg::launch_state_set(d_state, 27, o->fixed_steps, s);
+    frg::launch_maxabs_to(ctx->n3, d_V, d_state, 24, ctx->d_partial, red_blocks(ctx->n3), s);
+    if (o->stepper == FRG_DP54) {
+        // first stage of the first step (later steps reuse the last stage: FSAL)
+        TRY(run_rhs(ctx, o->prec == FRG_PREC_SPLIT_BF16, 0.0, d_state, 0.0, d_V, ctx->d_k[0], 1, s));
+        frg::launch_state_set(d_state, FRG_ST_RHS, 1.0, s);
+    }
+    HIPCHK(hipGetLastError());
+    return FRG_OK;
+}
+
+static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V, double *state,
+                                 double *log, int log_cap, hipStream_t s) {
+    const bool split = o->prec == FRG_PREC_SPLIT_BF16;
+    const int64_t n = ctx->n3;
+    frg::RkStageArgs sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.n = n;
+    sa.y = V;
+    sa.state = state;
+    for (int j = 0; j < 7; ++j) sa.k[j] = ctx->d_k[j];
+    if (o->stepper == FRG_DP54) {
+        frg::launch_pre_step(state, FRG_DP54, s);
+        for (int st = 1; st < 7; ++st) {
+            sa.nk = st;
+            for (int j = 0; j < 7; ++j) sa.coef[j] = j < st ? DP_A[st][j] : 0.0;
+            sa.out = st == 6 ? ctx->d_y5 : ctx->d_yt;
+            frg::launch_rk_stage(sa, s);
+            TRY(run_rhs(ctx, split, 0.0, state, DP_C[st], sa.out, ctx->d_k[st], 1, s));
+        }
+        const double *kk[7];
+        for (int j = 0; j < 7; ++j) kk[j] = ctx->d_k[j];
+        frg::launch_dp_error(n, V, ctx->d_y5, kk, DP_E, o->rtol, o->atol, state, ctx->d_partial,
+                             red_blocks(n), s);
+        frg::launch_dp_control(state, log, log_cap, o->vmax, o->max_steps, FRG_DP54, s);
+        frg::launch_accept_copy(n, state, ctx->d_y5, V, s);
+        frg::launch_accept_copy(n, state, ctx->d_k[6], ctx->d_k[0], s);
+    } else {
+        frg::launch_pre_step(state, FRG_RK4, s);
+        const double cs[4] = {0.0, 0.5, 0.5, 1.0};
+        for (int st = 0; st < 4; ++st) {
+            const double *in = V;
+            if (st > 0) {
+                sa.nk = st;
+                for (int j = 0; j < 7; ++j) sa.coef[j] = (j == st - 1) ? cs[st] : 0.0;
+                sa.out = ctx->d_yt;
+                frg::launch_rk_stage(sa, s);
+                in = ctx->d_yt;
+            }
+            TRY(run_rhs(ctx, split, 0.0, state, cs[st], in, ctx->d_k[st], 1, s));
+        }
+        sa.nk = 4;
+        const double b[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+        for (int j = 0; j < 7; ++j) sa.coef[j] = j < 4 ? b[j] : 0.0;
+        sa.out = ctx->d_y5;
+        frg::launch_rk_stage(sa, s);
+        frg::launch_maxabs_to(n, ctx->d_y5, state, 20, ctx->d_partial, red_blocks(n), s);
+        frg::launch_dp_control(state, log, log_cap, o->vmax, o->max_steps, FRG_RK4, s);
+        frg::launch_accept_copy(n, state, ctx->d_y5, V, s);
+    }
+    HIPCHK(hipGetLastError());
+    return FRG_OK;
+}
+
+frg_status frg_flow_step(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_state,
+                         void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_opts(ctx, o));
+    if (!d_V || !d_state || !aligned8(d_V) || !aligned8(d_state))
+        return fail(FRG_EINVAL, "null or misaligned V / state");
+    TRY(ensure_rhs_ws(ctx, o->prec));
+    TRY(ensure_flow_ws(ctx));
+    return flow_step_impl(ctx, o, d_V, d_state, nullptr, 0, static_cast<hipStream_t>(stream));
+}
+
+frg_status frg_flow(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_log,
+                    int32_t log_cap, frg_flow_result *r, void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_opts(ctx, o));
+    if (!r) return fail(FRG_EINVAL, "null result");
+    if (log_cap < 0 || (log_cap > 0 && !d_log)) return fail(FRG_EINVAL, "bad log buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TRY(ensure_rhs_ws(ctx, o->prec));
+    TRY(ensure_flow_ws(ctx));
+    TRY(frg_flow_init(ctx, o, d_V, ctx->d_state, stream));
+    const int cap = o->max_steps > 0 ? 4 * o->max_steps + 64 : 1000000;
+    double *hs = ctx->h_state;
+    for (int it = 0; it < cap; ++it) {
+        TRY(flow_step_impl(ctx, o, d_V, ctx->d_state, d_log, log_cap, s));
+        HIPCHK(hipMemcpyAsync(hs, ctx->d_state, sizeof(double) * FRG_STATE_LEN,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (hs[FRG_ST_REASON] != 0.0) break;
+    }
+    std::memset(r, 0, sizeof(*r));
+    r->reason = static_cast<frg_stop>(static_cast<int>(hs[FRG_ST_REASON]));
+    r->T_end = std::exp(hs[FRG_ST_S]);
+    r->T_c = std::exp(hs[FRG_ST_SC]);
+    r->T_c_interp = std::exp(hs[FRG_ST_SC_INTERP]);
+    r->accepted = static_cast<int32_t>(hs[FRG_ST_ACCEPTED]);
+    r->rejected = static_cast<int32_t>(hs[FRG_ST_REJECTED]);
+    r->rhs_evals = static_cast<int32_t>(hs[FRG_ST_RHS]);
+    r->first_step_rhs = static_cast<int32_t>(hs[FRG_ST_FIRST_RHS]);
+    if (r->reason == FRG_STOP_NONFINITE) return fail(FRG_ENONFINITE, "flow state became non-finite");
+    return FRG_OK;
+}
+
+}  // extern "C"

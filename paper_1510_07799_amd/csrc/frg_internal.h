@@ -1,0 +1,102 @@
+// Internal declarations of libfrg: host geometry, context, kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/frg.h"
+
+namespace frg {
+
+// ----------------------------------------------------------------- geometry
+// Host-side patch geometry in plain FP64 (built with -ffp-contract=off so
+// every product and sum is rounded exactly as written).
+struct Geometry {
+    int N = 0, n_rad = 0, n_ang = 0, nf = 0, np = 0, Tpp = 0, Tph = 0;
+    double t = 0, tp = 0, mu = 0, U = 0, dth = 0;
+    std::vector<double> kc, bnd;          // [N][2], [N+1][2]
+    std::vector<double> px, py, w, xi;    // [np]
+    std::vector<double> qpp, qph;         // [Tpp][2], [Tph][2]
+    std::vector<int32_t> row_pp, row_ph;  // [N][N]: (j1,j2) -> pp row, (x,y) -> ph row
+};
+
+void build_geometry(const frg_params &p, Geometry &g);
+double fold_bz(double x);
+int32_t host_patch(const Geometry &g, double kx, double ky);
+void host_idx4(const Geometry &g, int32_t *out);
+
+// ----------------------------------------------------------------- launchers
+// second-line patch of every (row, point); rows: pp rows then ph rows
+void launch_bins(const double *bnd, const double *px, const double *py, const double *qrow,
+                 int N, int np, int Tpp, int Trows, uint8_t *bins, hipStream_t s);
+
+// per-point temperature-dependent factors (a = xi/2T, h(a), -w/4T^2); T is
+// either T_host, or exp(state[s] + c*state[h]) when state != nullptr
+void launch_point_prep(const double *xi, const double *w, int np, double T_host,
+                       const double *state, double c_stage, double *pa64, float *pa32,
+                       double *Tout, hipStream_t s);
+
+struct BubbleArgs {
+    int N, nf, np, Tpp, Trows;
+    double mt2, mt4p, mu;          // -2t, 4t', mu
+    const uint8_t *bins;           // [Trows][np]
+    const double *trig_row;        // [Trows][4]: cos qx, sin qx, cos qy, sin qy
+    const double *trig_pt;         // [4][np]: cos px, sin px, cos py, sin py
+    const double *pa64;            // [3][np]: a, h(a), -w/4T^2   (FP64 path)
+    const float *pa32;             // [3][np]                      (split path)
+    const double *Tdev;            // [0] = T
+    void *Bpp, *Bph;               // outputs (double or float)
+};
+void launch_bubbles(const BubbleArgs &a, bool fp32, hipStream_t s);
+
+// permuted copies of V used as contraction operands (FP64)
+void launch_layout_f64(const double *V, int N, double *perm, hipStream_t s);
+// split-BF16 operands: hi/lo of the four A matrices + FP32 gather tables
+void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipStream_t s);
+
+enum Term { TERM_PP = 0, TERM_PHC = 1, TERM_PHD = 2 };
+struct ContractArgs {
+    int N;
+    int term;
+    const void *B;          // bubble rows (double or float), row-major [row][N*N]
+    const int32_t *colrow;  // column c -> bubble row
+    const double *A64[2];   // FP64 A operands [N][N*N]
+    const uint16_t *Ahl[2]; // split: [2][N][N*N] bf16 hi, lo
+    const double *G64[2];   // FP64 gather tables
+    const float *G32[2];    // FP32 gather tables
+    double *C;              // output [N^3] in F layout of the term
+};
+void launch_contract(const ContractArgs &a, bool split, hipStream_t s);
+
+// F = scale * (-Cpp + Cc + Cd), scale = T when Tdev != nullptr and scale_by_T
+void launch_combine(const double *Cpp, const double *Cc, const double *Cd, int64_t n,
+                    const double *Tdev, int scale_by_T, double *F, hipStream_t s);
+
+// ----------------------------------------------------------------- RK kernels
+struct RkStageArgs {
+    int64_t n;
+    const double *y;
+    const double *k[7];
+    double coef[7];
+    int nk;
+    const double *state;   // h = state[FRG_ST_H]
+    double *out;
+};
+void launch_rk_stage(const RkStageArgs &a, hipStream_t s);
+// DP5(4) error norm + max|y5|: partials then final (deterministic max)
+void launch_dp_error(int64_t n, const double *y, const double *y5, const double *const k[7],
+                     const double e[7], double rtol, double atol, double *state, double *partial,
+                     int nblocks, hipStream_t s);
+void launch_maxabs_to(int64_t n, const double *y, double *state, int slot, double *partial,
+                      int nblocks, hipStream_t s);
+void launch_state_set(double *state, int slot, double v, hipStream_t s);
+void launch_pre_step(double *state, int stepper, hipStream_t s);
+void launch_dp_control(double *state, double *log, int log_cap, double vmax, int max_steps,
+                       int stepper, hipStream_t s);
+void launch_accept_copy(int64_t n, const double *state, const double *src, double *dst,
+                        hipStream_t s);
+void launch_state_init(double *state, double s0, double h, double s_min, hipStream_t s);
+
+}  // namespace frg

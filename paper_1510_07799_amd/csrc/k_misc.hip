@@ -1,0 +1,456 @@
+// Small device kernels: second-line patch table, per-point temperature
+// factors, contraction operand layout, channel combine and the explicit
+// Runge-Kutta machinery (stage sums, FP64 error norm, on-device step control).
+#include <cmath>
+
+#include "frg_internal.h"
+
+namespace frg {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 2.0 * kPi;
+
+__device__ __forceinline__ double dev_fold(double x) {
+    while (x >= kPi) x -= kTwoPi;
+    while (x < -kPi) x += kTwoPi;
+    return x;
+}
+
+// cross(b, k) >= 0 and cross(b', k) < 0 with each product rounded on its own
+__device__ __forceinline__ bool dev_in_sector(const double *bnd, int j, double kx, double ky) {
+    const double u0 = __dmul_rn(bnd[2 * j], ky), v0 = __dmul_rn(bnd[2 * j + 1], kx);
+    const double u1 = __dmul_rn(bnd[2 * j + 2], ky), v1 = __dmul_rn(bnd[2 * j + 3], kx);
+    return __dsub_rn(u0, v0) >= 0.0 && __dsub_rn(u1, v1) < 0.0;
+}
+
+// patch of a folded momentum: unique sector j with cross(b_j,k) >= 0 and
+// cross(b_{j+1},k) < 0; an FP32 atan2 only picks where the search starts
+__device__ int dev_patch(const double *bnd, int N, double kx, double ky) {
+    if (kx == 0.0 && ky == 0.0) return 0;
+    float th = atan2f(static_cast<float>(ky), static_cast<float>(kx));
+    if (th < 0.f) th += 6.28318530717958647f;
+    int j0 = static_cast<int>(th * (static_cast<float>(N) * 0.159154943091895336f));
+    j0 = j0 < 0 ? 0 : (j0 >= N ? N - 1 : j0);
+    for (int d = 0; d <= N / 2; ++d) {
+        int j = j0 + d;
+        j = j >= N ? j - N : j;
+        if (dev_in_sector(bnd, j, kx, ky)) return j;
+        j = j0 - d;
+        j = j < 0 ? j + N : j;
+        if (dev_in_sector(bnd, j, kx, ky)) return j;
+    }
+    return 0;
+}
+
+__global__ void bins_kernel(const double *__restrict__ bnd, const double *__restrict__ px,
+                            const double *__restrict__ py, const double *__restrict__ qrow,
+                            int N, int np, int Tpp, int Trows, uint8_t *__restrict__ bins) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    for (int r = blockIdx.y; r < Trows; r += gridDim.y) {
+        const double qx = qrow[2 * r], qy = qrow[2 * r + 1];
+        double kx, ky;
+        if (r < Tpp) {          // pp: second line q - p
+            kx = dev_fold(qx - px[i]);
+            ky = dev_fold(qy - py[i]);
+        } else {                // ph: second line p + Q
+            kx = dev_fold(px[i] + qx);
+            ky = dev_fold(py[i] + qy);
+        }
+        bins[static_cast<size_t>(r) * np + i] = static_cast<uint8_t>(dev_patch(bnd, N, kx, ky));
+    }
+}
+
+__device__ __forceinline__ double sech2_d(double x) {
+    const double e = exp(-2.0 * fabs(x));
+    const double d = 1.0 + e;
+    return 4.0 * e / (d * d);
+}
+
+__global__ void point_prep_kernel(const double *__restrict__ xi, const double *__restrict__ w,
+                                  int np, double T_host, const double *__restrict__ state,
+                                  double c_stage, double *__restrict__ pa64,
+                                  float *__restrict__ pa32, double *__restrict__ Tout) {
+    const double T = state ? exp(state[FRG_ST_S] + c_stage * state[FRG_ST_H]) : T_host;
+    const double inv2T = 0.5 / T;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        Tout[0] = T;
+        Tout[1] = inv2T;
+    }
+    if (i >= np) return;
+    const double a = xi[i] * inv2T;
+    const double ha = a * sech2_d(a);
+    const double wf = -w[i] / (4.0 * T * T);
+    if (pa64) {
+        pa64[i] = a;
+        pa64[np + i] = ha;
+        pa64[2 * np + i] = wf;
+    }
+    if (pa32) {
+        pa32[i] = static_cast<float>(a);
+        pa32[np + i] = static_cast<float>(ha);
+        pa32[2 * np + i] = static_cast<float>(wf);
+    }
+}
+
+// perm blocks (each N^3, index [i][j][k]):
+//   0: V[j][k][i]            pp A operand   (row j3=i, column (a,b)=(j,k))
+//   1: V[k][i][j]            phc gather     (row (y,x)=(i,j), b=k)
+//   2: -2V[j][i][k]+V[i][j][k]  phd A operand (row j2=i, (a,b)=(j,k))
+//   3: V[j][i][k]            phd A operand
+//   4: V[i][k][j]            phd gather (row (y,x)=(i,j), b=k)
+//   5: V[i][k][j]            phd gather (y=i, (a,b)=(j,k)) -- same values as block 4
+__global__ void layout_f64_kernel(const double *__restrict__ V, int N, double *__restrict__ perm) {
+    const int64_t n3 = static_cast<int64_t>(N) * N * N;
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n3) return;
+    const int k = static_cast<int>(idx % N);
+    const int j = static_cast<int>((idx / N) % N);
+    const int i = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
+    auto at = [&](int x, int y, int z) { return V[(static_cast<int64_t>(x) * N + y) * N + z]; };
+    perm[idx] = at(j, k, i);
+    perm[n3 + idx] = at(k, i, j);
+    perm[2 * n3 + idx] = -2.0 * at(j, i, k) + at(i, j, k);
+    perm[3 * n3 + idx] = at(j, i, k);
+    perm[4 * n3 + idx] = at(i, k, j);
+}
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h) {
+    return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+// split path: A operands (blocks 0,2,3 above plus V itself for phc) as bf16
+// hi/lo, each [N][N*N]; ahl layout [4 operands][2 (hi,lo)][N^3].  FP32 gather
+// tables: g32 = [V (pp), block 1, block 4] each N^3.
+__global__ void layout_split_kernel(const double *__restrict__ V, int N, uint16_t *__restrict__ ahl,
+                                    float *__restrict__ g32) {
+    const int64_t n3 = static_cast<int64_t>(N) * N * N;
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx >= n3) return;
+    const int k = static_cast<int>(idx % N);
+    const int j = static_cast<int>((idx / N) % N);
+    const int i = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
+    auto at = [&](int x, int y, int z) { return V[(static_cast<int64_t>(x) * N + y) * N + z]; };
+    const float ops[4] = {static_cast<float>(at(j, k, i)), static_cast<float>(at(i, j, k)),
+                          static_cast<float>(-2.0 * at(j, i, k) + at(i, j, k)),
+                          static_cast<float>(at(j, i, k))};
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        const uint16_t hi = bf16_rne(ops[o]);
+        const uint16_t lo = bf16_rne(ops[o] - bf16_to_f(hi));
+        ahl[(2 * o) * n3 + idx] = hi;
+        ahl[(2 * o + 1) * n3 + idx] = lo;
+    }
+    g32[idx] = static_cast<float>(at(i, j, k));
+    g32[n3 + idx] = static_cast<float>(at(k, i, j));
+    g32[2 * n3 + idx] = static_cast<float>(at(i, k, j));
+}
+
+__global__ void combine_kernel(const double *__restrict__ Cpp, const double *__restrict__ Cc,
+                               const double *__restrict__ Cd, int64_t n,
+                               const double *__restrict__ Tdev, int scale_by_T,
+                               double *__restrict__ F) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v = (Cc[i] - Cpp[i]) + Cd[i];
+    F[i] = scale_by_T ? Tdev[0] * v : v;
+}
+
+// ----------------------------------------------------------------- RK
+__global__ void rk_stage_kernel(RkStageArgs a) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const double h = a.state[FRG_ST_H];
+    double acc = 0.0;
+    for (int j = 0; j < a.nk; ++j)
+        if (a.coef[j] != 0.0) acc += a.coef[j] * a.k[j][i];
+    a.out[i] = a.y[i] + h * acc;
+}
+
+__device__ __forceinline__ double block_max(double v, double *sh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = (o > v || o != o) ? o : v;   // propagate NaN
+    }
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < static_cast<int>(blockDim.x >> 6); ++w) {
+            const double o = sh[w];
+            v = (o > v || o != o) ? o : v;
+        }
+    }
+    return v;
+}
+
+struct ErrArgs {
+    int64_t n;
+    const double *y, *y5;
+    const double *k[7];
+    double e[7];
+    double rtol, atol;
+    const double *state;
+    double *partial;
+};
+
+__global__ void dp_error_partial(ErrArgs a) {
+    __shared__ double sh[2][16];
+    const double h = a.state[FRG_ST_H];
+    double emax = 0.0, vmax = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < a.n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        double d = 0.0;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) d += a.e[j] * a.k[j][i];
+        d = fabs(h * d);
+        const double y5 = a.y5[i];
+        const double sc = a.atol + a.rtol * fmax(fabs(a.y[i]), fabs(y5));
+        const double q = d / sc;
+        emax = (q > emax || q != q) ? q : emax;
+        const double av = fabs(y5);
+        vmax = (av > vmax || av != av) ? av : vmax;
+    }
+    emax = block_max(emax, sh[0]);
+    vmax = block_max(vmax, sh[1]);
+    if (threadIdx.x == 0) {
+        a.partial[2 * blockIdx.x] = emax;
+        a.partial[2 * blockIdx.x + 1] = vmax;
+    }
+}
+
+__global__ void maxabs_partial(int64_t n, const double *__restrict__ y, double *partial) {
+    __shared__ double sh[16];
+    double vmax = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const double av = fabs(y[i]);
+        vmax = (av > vmax || av != av) ? av : vmax;
+    }
+    vmax = block_max(vmax, sh);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = 0.0;
+        partial[2 * blockIdx.x + 1] = vmax;
+    }
+}
+
+// final reduction of the partials: error norm into state[slot_e] (if >= 0),
+// max|y| into state[slot_v]; fixed order, so the result is deterministic
+__global__ void reduce_partials(const double *partial, int nblocks, double *state, int slot_e,
+                                int slot_v) {
+    if (threadIdx.x != 0) return;
+    double e = 0.0, v = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+        const double pe = partial[2 * b], pv = partial[2 * b + 1];
+        e = (pe > e || pe != pe) ? pe : e;
+        v = (pv > v || pv != pv) ? pv : v;
+    }
+    if (slot_e >= 0) state[slot_e] = e;
+    state[slot_v] = v;
+}
+
+__global__ void state_set_kernel(double *state, int slot, double v) {
+    if (threadIdx.x == 0) state[slot] = v;
+}
+
+// pre-step: clip the step onto s_min (DP54) and remember whether this is the last
+__global__ void pre_step_kernel(double *state, int stepper) {
+    if (threadIdx.x != 0) return;
+    if (stepper == FRG_DP54) {
+        const double s = state[FRG_ST_S], smin = state[FRG_ST_SMIN];
+        double h = state[FRG_ST_H];
+        const double dir = state[21];
+        state[22] = 0.0;
+        if ((s + h - smin) * dir >= 0.0) {
+            h = smin - s;
+            state[22] = 1.0;
+        }
+        state[FRG_ST_H] = h;
+    }
+    state[23] = 0.0;  // accept flag of this attempt
+}
+
+// step control (one thread).  DP54: G10 rules; RK4: fixed step index.
+// state slots: 20 max|y_new|, 21 direction, 22 last, 23 accept, 24 m_prev,
+// 25 s0, 26 RK4 step index, 27 RK4 step count
+__global__ void control_kernel(double *state, double *log, int log_cap, double vmax,
+                               int max_steps, int stepper) {
+    if (threadIdx.x != 0) return;
+    if (state[FRG_ST_REASON] != 0.0) { state[23] = 0.0; return; }
+    const double mx = state[20];
+    const double s = state[FRG_ST_S], h = state[FRG_ST_H];
+    int accept;
+    double s_new;
+    if (stepper == FRG_DP54) {
+        const double err = state[FRG_ST_ERR];
+        state[FRG_ST_RHS] += 6.0;
+        if (!(err == err) || !(mx == mx) || isinf(err) || isinf(mx)) {
+            state[FRG_ST_REASON] = FRG_STOP_NONFINITE;
+            state[23] = 0.0;
+            return;
+        }
+        double fac = err == 0.0 ? 5.0 : 0.9 * pow(err, -0.2);
+        fac = fac < 0.2 ? 0.2 : (fac > 5.0 ? 5.0 : fac);
+        accept = err <= 1.0;
+        s_new = state[22] != 0.0 ? state[FRG_ST_SMIN] : s + h;
+        if (!accept) {
+            state[FRG_ST_REJECTED] += 1.0;
+            state[FRG_ST_H] = h * fac;
+            state[23] = 0.0;
+            if (!(fabs(h * fac) > 1e-14 * (1.0 + fabs(s)))) state[FRG_ST_REASON] = FRG_STOP_HMIN;
+            return;
+        }
+        state[FRG_ST_H] = h * fac;
+    } else {
+        state[FRG_ST_RHS] += 4.0;
+        if (!(mx == mx) || isinf(mx)) {
+            state[FRG_ST_REASON] = FRG_STOP_NONFINITE;
+            state[23] = 0.0;
+            return;
+        }
+        accept = 1;
+        const double idx = state[26] + 1.0;
+        state[26] = idx;
+        s_new = state[25] + idx * h;
+    }
+    state[23] = 1.0;
+    state[FRG_ST_ACCEPTED] += 1.0;
+    if (state[FRG_ST_ACCEPTED] == 1.0) state[FRG_ST_FIRST_RHS] = state[FRG_ST_RHS];
+    const double s_prev = s, m_prev = state[24];
+    state[FRG_ST_S] = s_new;
+    state[FRG_ST_VMAX] = mx;
+    double reason = 0.0;
+    if (mx > vmax) {
+        reason = FRG_STOP_DIVERGED;
+        state[FRG_ST_SC] = s_new;
+        state[FRG_ST_SC_INTERP] = s_prev + (vmax - m_prev) / (mx - m_prev) * (s_new - s_prev);
+    } else if (stepper == FRG_DP54 ? state[22] != 0.0 : state[26] >= state[27]) {
+        reason = FRG_STOP_TMIN;
+    } else if (max_steps > 0 && state[FRG_ST_ACCEPTED] >= max_steps) {
+        reason = FRG_STOP_MAXSTEPS;
+    }
+    state[24] = mx;
+    state[FRG_ST_REASON] = reason;
+    const int row = static_cast<int>(state[FRG_ST_ACCEPTED]) - 1;
+    if (log && row < log_cap) {
+        double *L = log + 8 * row;
+        L[0] = s_new; L[1] = h; L[2] = state[FRG_ST_ERR]; L[3] = mx;
+        L[4] = state[FRG_ST_RHS]; L[5] = state[FRG_ST_REJECTED]; L[6] = state[FRG_ST_ACCEPTED];
+        L[7] = reason;
+    }
+}
+
+__global__ void accept_copy_kernel(int64_t n, const double *state, const double *__restrict__ src,
+                                   double *__restrict__ dst) {
+    if (state[23] == 0.0) return;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ void state_init_kernel(double *state, double s0, double h, double s_min) {
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i < FRG_STATE_LEN; ++i) state[i] = 0.0;
+    state[FRG_ST_S] = s0;
+    state[FRG_ST_H] = h;
+    state[FRG_ST_SMIN] = s_min;
+    state[FRG_ST_SC] = NAN;
+    state[FRG_ST_SC_INTERP] = NAN;
+    state[21] = (s_min < s0) ? -1.0 : 1.0;
+    state[25] = s0;
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
+
+}  // namespace
+
+void launch_bins(const double *bnd, const double *px, const double *py, const double *qrow,
+                 int N, int np, int Tpp, int Trows, uint8_t *bins, hipStream_t s) {
+    dim3 grid(blocks_for(np, 256), Trows < 65535 ? Trows : 65535);
+    hipLaunchKernelGGL(bins_kernel, grid, dim3(256), 0, s, bnd, px, py, qrow, N, np, Tpp, Trows,
+                       bins);
+}
+
+void launch_point_prep(const double *xi, const double *w, int np, double T_host,
+                       const double *state, double c_stage, double *pa64, float *pa32,
+                       double *Tout, hipStream_t s) {
+    hipLaunchKernelGGL(point_prep_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, s, xi, w, np,
+                       T_host, state, c_stage, pa64, pa32, Tout);
+}
+
+void launch_layout_f64(const double *V, int N, double *perm, hipStream_t s) {
+    const int64_t n3 = static_cast<int64_t>(N) * N * N;
+    hipLaunchKernelGGL(layout_f64_kernel, dim3(blocks_for(n3, 256)), dim3(256), 0, s, V, N, perm);
+}
+
+void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipStream_t s) {
+    const int64_t n3 = static_cast<int64_t>(N) * N * N;
+    hipLaunchKernelGGL(layout_split_kernel, dim3(blocks_for(n3, 256)), dim3(256), 0, s, V, N, ahl,
+                       g32);
+}
+
+void launch_combine(const double *Cpp, const double *Cc, const double *Cd, int64_t n,
+                    const double *Tdev, int scale_by_T, double *F, hipStream_t s) {
+    hipLaunchKernelGGL(combine_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, Cpp, Cc, Cd, n,
+                       Tdev, scale_by_T, F);
+}
+
+void launch_rk_stage(const RkStageArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(rk_stage_kernel, dim3(blocks_for(a.n, 256)), dim3(256), 0, s, a);
+}
+
+void launch_dp_error(int64_t n, const double *y, const double *y5, const double *const k[7],
+                     const double e[7], double rtol, double atol, double *state, double *partial,
+                     int nblocks, hipStream_t s) {
+    ErrArgs a;
+    a.n = n;
+    a.y = y;
+    a.y5 = y5;
+    for (int j = 0; j < 7; ++j) { a.k[j] = k[j]; a.e[j] = e[j]; }
+    a.rtol = rtol;
+    a.atol = atol;
+    a.state = state;
+    a.partial = partial;
+    hipLaunchKernelGGL(dp_error_partial, dim3(nblocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(64), 0, s, partial, nblocks, state,
+                       static_cast<int>(FRG_ST_ERR), 20);
+}
+
+void launch_maxabs_to(int64_t n, const double *y, double *state, int slot, double *partial,
+                      int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(maxabs_partial, dim3(nblocks), dim3(256), 0, s, n, y, partial);
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(64), 0, s, partial, nblocks, state, -1, slot);
+}
+
+void launch_state_set(double *state, int slot, double v, hipStream_t s) {
+    hipLaunchKernelGGL(state_set_kernel, dim3(1), dim3(64), 0, s, state, slot, v);
+}
+
+void launch_dp_control(double *state, double *log, int log_cap, double vmax, int max_steps,
+                       int stepper, hipStream_t s) {
+    hipLaunchKernelGGL(control_kernel, dim3(1), dim3(64), 0, s, state, log, log_cap, vmax,
+                       max_steps, stepper);
+}
+
+void launch_pre_step(double *state, int stepper, hipStream_t s) {
+    hipLaunchKernelGGL(pre_step_kernel, dim3(1), dim3(64), 0, s, state, stepper);
+}
+
+void launch_accept_copy(int64_t n, const double *state, const double *src, double *dst,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(accept_copy_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, state,
+                       src, dst);
+}
+
+void launch_state_init(double *state, double s0, double h, double s_min, hipStream_t s) {
+    hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, state, s0, h, s_min);
+}
+
+}  // namespace frg

@@ -1,0 +1,234 @@
+"""Thin ctypes binding of libfrg (include/frg.h): argument marshalling only.
+
+Every computation runs in the HIP kernels of ``libfrg.so``; torch is used for
+device memory and the current stream.  If the library is missing the import
+of this module fails loudly -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfrg.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP, ENONFINITE = range(6)
+PREC_FP64, PREC_SPLIT_BF16 = 0, 1
+RK4, DP54 = 0, 1
+STOP_NONE, STOP_TMIN, STOP_DIVERGED, STOP_MAXSTEPS, STOP_NONFINITE, STOP_HMIN = range(6)
+STATE_LEN = 32
+ST_S, ST_H, ST_ERR, ST_REASON, ST_ACCEPTED, ST_REJECTED, ST_RHS, ST_VMAX = range(8)
+
+
+class FRGError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libfrg error {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("t", C.c_double), ("tp", C.c_double), ("mu", C.c_double), ("U", C.c_double),
+                ("N", C.c_int32), ("n_rad", C.c_int32), ("n_ang", C.c_int32)]
+
+
+class FlowOpts(C.Structure):
+    _fields_ = [("stepper", C.c_int32), ("prec", C.c_int32), ("T0", C.c_double),
+                ("T_min", C.c_double), ("rtol", C.c_double), ("atol", C.c_double),
+                ("vmax", C.c_double), ("h0", C.c_double), ("fixed_steps", C.c_int32),
+                ("max_steps", C.c_int32)]
+
+
+class FlowResult(C.Structure):
+    _fields_ = [("reason", C.c_int32), ("T_end", C.c_double), ("T_c", C.c_double),
+                ("T_c_interp", C.c_double), ("accepted", C.c_int32), ("rejected", C.c_int32),
+                ("rhs_evals", C.c_int32), ("first_step_rhs", C.c_int32)]
+
+
+_lib = None
+_P = C.c_void_p
+_DP = C.POINTER(C.c_double)
+_IP = C.POINTER(C.c_int32)
+_SZ = C.POINTER(C.c_size_t)
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "frg_create": (C.c_int, [C.POINTER(Params), C.POINTER(_P)]),
+    "frg_destroy": (C.c_int, [_P]),
+    "frg_sizes": (C.c_int, [_P, _SZ, _SZ, _SZ, _SZ]),
+    "frg_tables": (C.c_int, [_P, _DP, _DP, _DP, _DP, _DP, _IP]),
+    "frg_host_tables": (C.c_int, [C.POINTER(Params), _DP, _DP, _DP, _DP, _DP, _IP]),
+    "frg_bins": (C.c_int, [_P, C.c_int32, _P, _P]),
+    "frg_bubbles": (C.c_int, [_P, C.c_double, C.c_int, _P, _P, _P]),
+    "frg_rhs": (C.c_int, [_P, C.c_double, _P, _P, C.c_int, _P]),
+    "frg_flow_init": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, _P]),
+    "frg_flow_step": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, _P]),
+    "frg_flow": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, C.c_int32, C.POINTER(FlowResult), _P]),
+    "frg_status_str": (C.c_char_p, [C.c_int]),
+    "frg_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "or python -m paper_1510_07799_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != OK:
+        msg = lib().frg_last_error().decode(errors="replace")
+        raise FRGError(st, msg)
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def params(t=1.0, tp=0.0, mu=0.0, U=2.0, N=16, n_rad=8, n_ang=8) -> Params:
+    return Params(float(t), float(tp), float(mu), float(U), int(N), int(n_rad), int(n_ang))
+
+
+def host_tables(t=1.0, tp=0.0, mu=0.0, U=2.0, N=16, n_rad=8, n_ang=8, idx4=True) -> dict:
+    """Geometry tables built by the library's host code (no device needed)."""
+    p = params(t, tp, mu, U, N, n_rad, n_ang)
+    nf = n_rad * n_ang
+    Tpp, Tph = N * (N + 1) // 2, N * (N - 1) + 1
+    kc = np.zeros((N, 2))
+    bnd = np.zeros((N + 1, 2))
+    fine = np.zeros((N * nf, 4))
+    qpp = np.zeros((Tpp, 2))
+    qph = np.zeros((Tph, 2))
+    i4 = np.zeros((N, N, N), dtype=np.int32) if idx4 else None
+    dp = lambda a: a.ctypes.data_as(_DP)
+    _check(lib().frg_host_tables(C.byref(p), dp(kc), dp(bnd), dp(fine), dp(qpp), dp(qph),
+                                 i4.ctypes.data_as(_IP) if idx4 else None))
+    out = dict(kc=kc, bnd=bnd, px=fine[:, 0].copy(), py=fine[:, 1].copy(), w=fine[:, 2].copy(),
+               xi=fine[:, 3].copy(), qpp=qpp, qph=qph)
+    if idx4:
+        out["idx4"] = i4
+    return out
+
+
+def flow_opts(stepper="rk4", prec=PREC_FP64, T0=1.0, T_min=0.05, rtol=1e-6, atol=1e-10,
+              vmax=20.0, h0=-0.01, fixed_steps=40, max_steps=0) -> FlowOpts:
+    st = RK4 if stepper in ("rk4", RK4) else DP54
+    return FlowOpts(st, int(prec), float(T0), float(T_min), float(rtol), float(atol),
+                    float(vmax), float(h0), int(fixed_steps), int(max_steps))
+
+
+class Context:
+    """One parameter set on the current HIP device (owns geometry + workspace)."""
+
+    def __init__(self, t=1.0, tp=0.0, mu=0.0, U=2.0, N=16, n_rad=8, n_ang=8):
+        import torch
+        self.torch = torch
+        self.N, self.nf, self.U = int(N), int(n_rad) * int(n_ang), float(U)
+        self.Tpp, self.Tph = N * (N + 1) // 2, N * (N - 1) + 1
+        self.params = dict(t=t, tp=tp, mu=mu, U=U, N=N, n_rad=n_rad, n_ang=n_ang)
+        p = params(t, tp, mu, U, N, n_rad, n_ang)
+        h = _P()
+        _check(lib().frg_create(C.byref(p), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().frg_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def sizes(self):
+        a, b, c, d = C.c_size_t(), C.c_size_t(), C.c_size_t(), C.c_size_t()
+        _check(lib().frg_sizes(self._h, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return dict(n_v=a.value, n_bpp=b.value, n_bph=c.value, workspace_bytes=d.value)
+
+    def tables(self, idx4=True):
+        N, nf = self.N, self.nf
+        kc = np.zeros((N, 2))
+        bnd = np.zeros((N + 1, 2))
+        fine = np.zeros((N * nf, 4))
+        qpp = np.zeros((self.Tpp, 2))
+        qph = np.zeros((self.Tph, 2))
+        i4 = np.zeros((N, N, N), dtype=np.int32) if idx4 else None
+        dp = lambda a: a.ctypes.data_as(_DP)
+        _check(lib().frg_tables(self._h, dp(kc), dp(bnd), dp(fine), dp(qpp), dp(qph),
+                                i4.ctypes.data_as(_IP) if idx4 else None))
+        out = dict(kc=kc, bnd=bnd, px=fine[:, 0].copy(), py=fine[:, 1].copy(),
+                   w=fine[:, 2].copy(), xi=fine[:, 3].copy(), qpp=qpp, qph=qph)
+        if idx4:
+            out["idx4"] = i4
+        return out
+
+    def bins(self, kind: int):
+        torch = self.torch
+        rows = self.Tpp if kind == 1 else self.Tph
+        out = torch.empty((rows, self.N * self.nf), dtype=torch.uint8, device="cuda")
+        _check(lib().frg_bins(self._h, int(kind), _ptr(out), _stream()))
+        return out
+
+    def bubbles(self, T: float, prec=PREC_FP64):
+        torch = self.torch
+        dt = torch.float64 if prec == PREC_FP64 else torch.float32
+        N = self.N
+        Bpp = torch.empty((self.Tpp, N, N), dtype=dt, device="cuda")
+        Bph = torch.empty((self.Tph, N, N), dtype=dt, device="cuda")
+        _check(lib().frg_bubbles(self._h, float(T), int(prec), _ptr(Bpp), _ptr(Bph), _stream()))
+        return Bpp, Bph
+
+    def rhs(self, T: float, V, prec=PREC_FP64, out=None):
+        torch = self.torch
+        N = self.N
+        assert V.dtype == torch.float64 and V.is_cuda and V.is_contiguous() and V.numel() == N ** 3
+        F = out if out is not None else torch.empty_like(V)
+        _check(lib().frg_rhs(self._h, float(T), _ptr(V), _ptr(F), int(prec), _stream()))
+        return F
+
+    def flow_init(self, opts: FlowOpts, V, state):
+        _check(lib().frg_flow_init(self._h, C.byref(opts), _ptr(V), _ptr(state), _stream()))
+
+    def flow_step(self, opts: FlowOpts, V, state):
+        _check(lib().frg_flow_step(self._h, C.byref(opts), _ptr(V), _ptr(state), _stream()))
+
+    def flow(self, V, opts: FlowOpts, log_cap=4096):
+        """Run a whole flow in place on V; returns (result dict, log [accepted, 8])."""
+        torch = self.torch
+        log = torch.zeros((max(log_cap, 1), 8), dtype=torch.float64, device="cuda")
+        r = FlowResult()
+        st = lib().frg_flow(self._h, C.byref(opts), _ptr(V), _ptr(log), int(log_cap), C.byref(r),
+                            _stream())
+        res = {k: getattr(r, k) for k, _ in FlowResult._fields_}
+        if st not in (OK, ENONFINITE):
+            _check(st)
+        torch.cuda.synchronize()
+        n = min(res["accepted"], log_cap)
+        return res, log[:n].cpu().numpy()
+
+
+def T_of_s(s: float) -> float:
+    return math.exp(s)

@@ -1,0 +1,232 @@
+"""GPU path vs the CPU oracle, element by element, through the C ABI.
+
+Bars (from the arithmetic of each path):
+  - integer maps (second-line patch of every (row, point)): bit-exact;
+  - FP64 bubbles and rhs: normwise relative error <= 1e-10 (rounding-order only);
+  - split path (FP32 compensated bubbles, split-BF16 MFMA contraction with FP32
+    accumulation): normwise relative error <= 2e-4 on the rhs, 1e-5 on bubbles.
+Normwise error = max|x - x_ref| / max|x_ref| over the whole tensor.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1510_07799_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1510_07799_amd import frg  # noqa: E402  (loads libfrg.so; fails loudly if missing)
+
+RAGGED = dict(t=1.0, tp=-0.12, mu=-0.35, U=2.0, N=12, n_rad=5, n_ang=3)   # N%8 != 0, n_f = 15
+TINY = dict(t=1.0, tp=-0.15, mu=-0.3, U=2.0, N=4, n_rad=3, n_ang=2)
+SMALL_ODD = dict(t=1.0, tp=-0.2, mu=-0.6, U=2.5, N=24, n_rad=9, n_ang=10)  # n_f = 90 (ragged tiles)
+
+
+def nrel(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(x - ref).max() / np.abs(ref).max())
+
+
+_models = {}
+
+
+def pair(name_or_params):
+    key = name_or_params if isinstance(name_or_params, str) else tuple(sorted(name_or_params.items()))
+    if key not in _models:
+        p = I.model_params(name_or_params) if isinstance(name_or_params, str) else name_or_params
+        print(f"[gpu] create {p}", flush=True)
+        _models[key] = (O.Model(**p), frg.Context(**p))
+    return _models[key]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("cfg", ["C1", "C2", RAGGED, TINY, SMALL_ODD], ids=["C1", "C2", "ragged", "tiny", "odd"])
+def test_second_line_patches_bit_exact(cfg):
+    om, g = pair(cfg)
+    for kind in (O.PP, O.PH):
+        ref = om.bins(kind)
+        got = g.bins(kind).cpu().numpy().astype(np.int32)
+        assert got.shape == ref.shape
+        assert np.array_equal(got, ref), f"kind {kind}: {np.count_nonzero(got != ref)} mismatches"
+
+
+def test_tables_bit_exact_through_context():
+    om, g = pair("C2")
+    a, b = g.tables(), om.tables()
+    for k in b:
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("T", [0.5, 0.05, 1e-3])
+@pytest.mark.parametrize("cfg", ["C1", RAGGED, SMALL_ODD], ids=["C1", "ragged", "odd"])
+def test_bubbles_fp64(cfg, T):
+    om, g = pair(cfg)
+    Rpp, Rph = om.bubbles(T)
+    Bpp, Bph = g.bubbles(T, frg.PREC_FP64)
+    torch.cuda.synchronize()
+    assert nrel(Bpp.cpu().numpy(), Rpp) <= 1e-12
+    assert nrel(Bph.cpu().numpy(), Rph) <= 1e-12
+
+
+@pytest.mark.parametrize("T", [0.5, 0.05, 1e-3])
+def test_bubbles_split(T):
+    om, g = pair("C1")
+    Rpp, Rph = om.bubbles(T)
+    Bpp, Bph = g.bubbles(T, frg.PREC_SPLIT_BF16)
+    torch.cuda.synchronize()
+    assert nrel(Bpp.cpu().numpy(), Rpp) <= 1e-5
+    assert nrel(Bph.cpu().numpy(), Rph) <= 1e-5
+
+
+def test_bubbles_production_grid():
+    om, g = pair("C2")
+    for T in (0.07, 2e-3):
+        Rpp, Rph = om.bubbles(T)
+        Bpp, Bph = g.bubbles(T, frg.PREC_FP64)
+        Spp, Sph = g.bubbles(T, frg.PREC_SPLIT_BF16)
+        torch.cuda.synchronize()
+        assert nrel(Bpp.cpu().numpy(), Rpp) <= 1e-12 and nrel(Bph.cpu().numpy(), Rph) <= 1e-12
+        assert nrel(Spp.cpu().numpy(), Rpp) <= 1e-5 and nrel(Sph.cpu().numpy(), Rph) <= 1e-5
+
+
+def _vertices(N, U):
+    return {"const": I.constant_vertex(N, U),
+            "sym": I.random_vertex(N, U, seed=21, symmetrise=True),
+            "raw": I.random_vertex(N, U, seed=22, symmetrise=False)}
+
+
+@pytest.mark.parametrize("cfg", ["C1", RAGGED, TINY, SMALL_ODD, "C2"], ids=["C1", "ragged", "tiny", "odd", "C2"])
+def test_rhs_fp64(cfg):
+    om, g = pair(cfg)
+    N, U = om.N, om.U
+    for T in (0.3, 0.02):
+        for vname, V in _vertices(N, U).items():
+            ref = om.rhs(T, V)
+            got = g.rhs(T, dev(V), frg.PREC_FP64).cpu().numpy()
+            err = nrel(got, ref)
+            print(f"[fp64] N={N} T={T} {vname}: {err:.2e}", flush=True)
+            assert err <= 1e-10
+
+
+@pytest.mark.parametrize("cfg", ["C1", RAGGED, SMALL_ODD, "C2"], ids=["C1", "ragged", "odd", "C2"])
+def test_rhs_split(cfg):
+    om, g = pair(cfg)
+    N, U = om.N, om.U
+    for T in (0.3, 0.02):
+        for vname, V in _vertices(N, U).items():
+            ref = om.rhs(T, V)
+            got = g.rhs(T, dev(V), frg.PREC_SPLIT_BF16).cpu().numpy()
+            err = nrel(got, ref)
+            print(f"[split] N={N} T={T} {vname}: {err:.2e}", flush=True)
+            assert err <= 2e-4
+
+
+def test_rhs_deterministic():
+    om, g = pair("C2")
+    V = dev(I.random_vertex(om.N, om.U, seed=5))
+    a = g.rhs(0.05, V, frg.PREC_FP64).clone()
+    b = g.rhs(0.05, V, frg.PREC_FP64).clone()
+    assert torch.equal(a, b)
+    a = g.rhs(0.05, V, frg.PREC_SPLIT_BF16).clone()
+    b = g.rhs(0.05, V, frg.PREC_SPLIT_BF16).clone()
+    assert torch.equal(a, b)
+
+
+def test_rhs_full_size_sampled():
+    """N = 96, n_f = 512 (the benchmark workload): sampled entries against the
+    oracle's brute-force per-entry sum, plus a normwise bound from the sample."""
+    om, g = pair("C3")
+    N, U = om.N, om.U
+    V = I.random_vertex(N, U, seed=31, amp=0.3)
+    idx = I.random_entries(N, 24, seed=32)
+    for T in (0.05,):
+        ref = om.rhs_entries(T, V, idx)
+        F64 = g.rhs(T, dev(V), frg.PREC_FP64).cpu().numpy()
+        Fsp = g.rhs(T, dev(V), frg.PREC_SPLIT_BF16).cpu().numpy()
+        scale = np.abs(F64).max()
+        got64 = F64[idx[:, 0], idx[:, 1], idx[:, 2]]
+        gotsp = Fsp[idx[:, 0], idx[:, 1], idx[:, 2]]
+        e64 = np.abs(got64 - ref).max() / scale
+        esp = np.abs(gotsp - ref).max() / scale
+        print(f"[C3 sampled] fp64 {e64:.2e} split {esp:.2e}", flush=True)
+        assert e64 <= 1e-10
+        assert esp <= 2e-4
+        # whole-tensor agreement of the two GPU paths
+        assert nrel(Fsp, F64) <= 2e-4
+
+
+def test_rhs_argument_errors():
+    om, g = pair("C1")
+    N = om.N
+    V = torch.zeros(N ** 3, dtype=torch.float64, device="cuda")
+    with pytest.raises(frg.FRGError) as e:
+        g.rhs(0.0, V)
+    assert e.value.status == frg.EINVAL
+    with pytest.raises(frg.FRGError) as e:
+        g.rhs(float("nan"), V)
+    assert e.value.status == frg.EINVAL
+    with pytest.raises(frg.FRGError) as e:
+        g.rhs(0.1, V, out=V)
+    assert e.value.status == frg.EINVAL
+    with pytest.raises(frg.FRGError) as e:
+        frg.Context(t=1, tp=0, mu=0, U=1, N=10, n_rad=2, n_ang=2)
+    assert e.value.status == frg.EINVAL
+
+
+def test_flow_c1_rk4_matches_oracle():
+    om, g = pair("C1")
+    N, U = om.N, om.U
+    Vo, ro, _ = om.flow(stepper="rk4", fixed_steps=40, T_min=0.05, vmax=20.0)
+    V = dev(np.full((N, N, N), U))
+    res, log = g.flow(V, frg.flow_opts("rk4", frg.PREC_FP64, T0=1.0, T_min=0.05, fixed_steps=40, vmax=20.0))
+    print("[flow C1 rk4]", res, ro, flush=True)
+    assert res["reason"] == ro["reason"] == O.STOP_DIVERGED
+    assert res["accepted"] == ro["accepted"]
+    assert math.log(res["T_c_interp"]) == pytest.approx(ro["s_c_interp"], abs=1e-9)
+    assert nrel(V.cpu().numpy(), Vo) <= 1e-9
+
+
+def test_flow_dp54_matches_oracle_and_first_step():
+    om, g = pair("C1")
+    N, U = om.N, om.U
+    Vo, ro, lo = om.flow(stepper="dp54", T_min=0.05, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.01)
+    V = dev(np.full((N, N, N), U))
+    res, log = g.flow(V, frg.flow_opts("dp54", frg.PREC_FP64, T0=1.0, T_min=0.05, rtol=1e-6,
+                                       atol=1e-10, vmax=20.0, h0=-0.01))
+    print("[flow C1 dp54]", res, ro, flush=True)
+    assert res["first_step_rhs"] == 7 == ro["first_step_rhs"]
+    assert res["reason"] == ro["reason"]
+    assert res["accepted"] == ro["accepted"] and res["rejected"] == ro["rejected"]
+    assert np.allclose(log[:, 0], lo[:, 0], rtol=0, atol=1e-9)
+    assert nrel(V.cpu().numpy(), Vo) <= 1e-8
+
+
+def test_flow_step_api_and_tmin_stop():
+    """frg_flow_step driven from the host to T_min without divergence (small U)."""
+    p = dict(t=1.0, tp=-0.1, mu=-0.3, U=0.5, N=8, n_rad=4, n_ang=4)
+    om, g = pair(p)
+    N = om.N
+    Vo, ro, _ = om.flow(stepper="dp54", T0=1.0, T_min=0.2, rtol=1e-7, atol=1e-12, vmax=20.0, h0=-0.05)
+    V = dev(np.full((N, N, N), 0.5))
+    state = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+    o = frg.flow_opts("dp54", frg.PREC_FP64, T0=1.0, T_min=0.2, rtol=1e-7, atol=1e-12, vmax=20.0, h0=-0.05)
+    g.flow_init(o, V, state)
+    for _ in range(500):
+        g.flow_step(o, V, state)
+        if state[frg.ST_REASON].item() != 0:
+            break
+    st = state.cpu().numpy()
+    assert st[frg.ST_REASON] == O.STOP_TMIN == ro["reason"]
+    assert st[frg.ST_S] == pytest.approx(math.log(0.2), abs=1e-15)
+    assert int(st[frg.ST_ACCEPTED]) == ro["accepted"]
+    assert nrel(V.cpu().numpy(), Vo) <= 1e-9
