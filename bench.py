@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Benchmark: fRG rhs evaluations per second at N = 96 on one MI355X.
+
+Workload: 2D Hubbard model, N = 96 patches, 512 fine points per patch
+(32 radial x 16 angular), t' = -0.3, mu = -1.2 (van Hove filling), U = 3.
+One timed step is one Dormand-Prince 5(4) step of the temperature flow run
+entirely on the device: six rhs evaluations (bubble sweep, operand layout,
+three channel contractions, combine) plus the FP64 stage sums, error norm and
+step control.  `value` is the split-BF16 path's rhs evaluations per second;
+the FP64 path is timed the same way in its own region and reported beside it.
+
+Prints one JSON line.  --gpus N > 1 is not supported (one GPU per process).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+RHS_PER_STEP = 6   # DP5(4) with first-same-as-last: six new stages per step
+PEAK = {"hbm_GBs": 8000.0, "bf16_TFLOPs": 2500.0, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("k_contract.hip", "k_bubbles.hip"):
+        with open(os.path.join(ROOT, "paper_1510_07799_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def timed_flow_steps(frg, torch, ctx, prec, V0, steps, warmup):
+    opts = frg.flow_opts("dp54", prec, T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.01)
+    V = V0.clone()
+    state = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+    ctx.flow_init(opts, V, state)
+    for _ in range(warmup):
+        ctx.flow_step(opts, V, state)
+    torch.cuda.synchronize()
+    ctx.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.flow_step(opts, V, state)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_end()
+    st = state.cpu().numpy()
+    return t1 - t0, prof, st
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--legs", default="split,fp64", help="comma list of split,fp64")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
+              "layout is a design note only", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1510_07799_amd import frg, inputs as I
+
+    p = I.model_params("C3")
+    N = p["N"]
+    nf = p["n_rad"] * p["n_ang"]
+    ctx = frg.Context(**p)
+    V0 = torch.full((N, N, N), float(p["U"]), dtype=torch.float64, device="cuda")
+
+    # algorithmic work per launch (T independent): bubble-row occupancy from one sweep
+    Bpp, Bph = ctx.bubbles(0.05, frg.PREC_SPLIT_BF16)
+    nnz_pp = (Bpp != 0).sum(dim=(1, 2)).to(torch.float64)
+    nnz_ph = (Bph != 0).sum(dim=(1, 2)).to(torch.float64)
+    rows_pp = torch.tensor([[min(i, j) * N - min(i, j) * (min(i, j) - 1) // 2 + abs(i - j)
+                             for j in range(N)] for i in range(N)], device="cuda").reshape(-1)
+    colsum_pp = float(nnz_pp[rows_pp].sum())
+    # ph column (y, x) uses row of Q = k_x - k_y; every ordered pair occurs once, x == y uses row 0
+    colsum_ph = float(nnz_ph[1:].sum() + N * nnz_ph[0])
+    del Bpp, Bph
+    # pp: one product per column, phc: one, phd: two (N output rows each)
+    algo_flops = {"contract": 2.0 * N * colsum_pp + 2.0 * N * colsum_ph + 4.0 * N * colsum_ph}
+    dense_flops = 8.0 * N ** 5   # what the dense formulation executes (x3 passes in split mode)
+    evals_per_rhs = (ctx.Tpp + ctx.Tph) * N * nf
+
+    legs = [x.strip() for x in args.legs.split(",") if x.strip()]
+    results = {}
+    for leg in legs:
+        prec = frg.PREC_SPLIT_BF16 if leg == "split" else frg.PREC_FP64
+        dt, prof, st = timed_flow_steps(frg, torch, ctx, prec, V0, args.steps, args.warmup)
+        results[leg] = dict(seconds=dt, prof=prof, state=st)
+
+    head = results.get("split") or results[legs[0]]
+    dt = head["seconds"]
+    value = RHS_PER_STEP * args.steps / dt
+    out = {
+        "metric": "fRG rhs evals/sec at N=96 (split-BF16 vs FP64, same GPU); % MFMA/HBM roofline",
+        "value": round(value, 3),
+        "unit": "rhs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16x3-fp32" if "split" in results else "f64",
+        "data": "synthetic",
+        "config": {"workload": "hubbard-2d N=96 patches, 512 fine points/patch (32x16), "
+                               "t'=-0.3 mu=-1.2 U=3, DP5(4) temperature flow step (6 rhs)",
+                   "N": N, "n_f": nf, "rhs_per_step": RHS_PER_STEP, "parallelism": "1 GPU"},
+    }
+    for leg, r in results.items():
+        rps = RHS_PER_STEP * args.steps / r["seconds"]
+        out[f"{leg}_rhs_per_s"] = round(rps, 3)
+        out[f"{leg}_kernel_ms_per_rhs"] = {
+            k: round(ms / max(1, args.steps * RHS_PER_STEP), 4) for k, (ms, c) in r["prof"].items()}
+    if "split" in results and "fp64" in results:
+        out["split_over_fp64"] = round(out["split_rhs_per_s"] / out["fp64_rhs_per_s"], 3)
+
+    # roofline of the dominant kernel of the headline leg
+    prof = head["prof"]
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, cnt = prof[dom]
+    avg_s = ms / max(cnt, 1) * 1e-3
+    leg_name = "split" if "split" in results else legs[0]
+    if dom.startswith("contract"):
+        peak = PEAK["bf16_TFLOPs"] if leg_name == "split" else PEAK["fp64_TFLOPs"]
+        achieved = algo_flops[dom] / avg_s / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 4), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 6)}
+        passes = 3.0 if leg_name == "split" else 1.0
+        roof["dense_executed_frac"] = round(passes * dense_flops / avg_s / 1e12 / peak, 6)
+    elif dom == "bubbles":
+        # plain ALU bound: FP32/FP64 vector issue; algorithmic unit = one integrand evaluation
+        peak = PEAK["fp32_TFLOPs"] if leg_name == "split" else PEAK["fp64_TFLOPs"]
+        flops_per_eval = 40.0
+        achieved = evals_per_rhs * flops_per_eval / avg_s / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 4), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 6)}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK["hbm_GBs"],
+                "unit": "GB/s", "frac": None}
+    roof["avg_launch_ms"] = round(avg_s * 1e3, 4)
+    traffic = None
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        if tr.get("source_hash") == kernel_source_hash() and dom in tr.get("kernels", {}):
+            traffic = tr["kernels"][dom]["bytes_per_launch"]
+    except (OSError, ValueError):
+        traffic = None
+    roof["traffic"] = traffic
+    out["roofline"] = roof
+
+    if not args.no_cpu_baseline:
+        import oracle as O
+        O.build(force=False)
+        cores = os.cpu_count() or 1
+        cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+        O.set_threads(cores)
+        m = O.Model(**p)
+        Vh = np.full((N, N, N), float(p["U"]))
+        t0 = time.perf_counter()
+        m.rhs(0.05, Vh)
+        t_cpu = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(1.0 / t_cpu, 6), "unit": "rhs/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": "one full FP64 oracle rhs at the benchmark workload "
+                                         "(N=96, 512 points/patch, T=0.05): bubbles + contraction"}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -182,6 +182,19 @@ frg_status frg_flow_step(frg_ctx ctx, const frg_flow_opts *o, double *d_V, doubl
 frg_status frg_flow(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_log,
                     int32_t log_cap, frg_flow_result *r, void *stream);
 
+/* Kernel timing with HIP events recorded on the launch stream around every
+ * kernel of the rhs and flow pipelines (for measurement; off by default).
+ * frg_profile_begin clears and enables the record; frg_profile_end
+ * synchronises the recorded events, writes per kernel class the summed
+ * milliseconds and launch counts (arrays of FRG_KERNEL_CLASSES entries; either
+ * may be NULL) and disables recording. */
+enum {
+    FRG_K_PREP = 0, FRG_K_BUBBLES = 1, FRG_K_LAYOUT = 2, FRG_K_CONTRACT = 3,
+    FRG_K_COMBINE = 4, FRG_K_RK = 5, FRG_KERNEL_CLASSES = 6
+};
+frg_status frg_profile_begin(frg_ctx ctx);
+frg_status frg_profile_end(frg_ctx ctx, double *ms, int32_t *counts);
+
 const char *frg_status_str(frg_status st);
 const char *frg_last_error(void);
 

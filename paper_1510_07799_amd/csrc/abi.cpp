@@ -5,8 +5,10 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "frg_internal.h"
 
@@ -35,7 +37,15 @@ struct frg_ctx_s {
     double *d_yt = nullptr, *d_y5 = nullptr, *d_partial = nullptr, *d_state = nullptr;
     double *h_state = nullptr;
     int nred = 256;
+    int c_parts = 0;        // K parts the channel buffers d_C hold
+    int ks_override = 0;    // FRG_KSPLIT
     size_t ws_bytes = 0;
+    // event timing (frg_profile_begin/end)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    struct Rec { int cls; hipEvent_t a, b; };
+    std::vector<Rec> recs;
 };
 
 namespace {
@@ -98,7 +108,6 @@ frg_status ensure_rhs_ws(frg_ctx ctx, frg_precision prec) {
     const auto &g = ctx->g;
     const size_t NN = static_cast<size_t>(g.N) * g.N;
     TRY(dalloc(ctx, &ctx->d_T, 4));
-    TRY(dalloc(ctx, &ctx->d_C, 3 * static_cast<size_t>(ctx->n3)));
     if (prec == FRG_PREC_FP64) {
         TRY(dalloc(ctx, &ctx->d_pa64, 3 * static_cast<size_t>(g.np)));
         TRY(dalloc(ctx, &ctx->d_B64, NN * ctx->Trows));
@@ -122,6 +131,33 @@ frg_status ensure_flow_ws(frg_ctx ctx) {
                                             sizeof(double) * FRG_STATE_LEN, hipHostMallocDefault));
     return FRG_OK;
 }
+
+hipEvent_t next_event(frg_ctx ctx) {
+    if (ctx->ev_used == ctx->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ctx->ev_pool.push_back(e);
+    }
+    return ctx->ev_pool[ctx->ev_used++];
+}
+
+// Records events around the launches made while it is alive (profiling only).
+struct KTimer {
+    frg_ctx ctx;
+    int cls;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    KTimer(frg_ctx c, int k, hipStream_t st) : ctx(c), cls(k), s(st) {
+        if (ctx->prof && (a = next_event(ctx))) hipEventRecord(a, s);
+    }
+    ~KTimer() {
+        if (!a) return;
+        hipEvent_t b = next_event(ctx);
+        if (!b) return;
+        hipEventRecord(b, s);
+        ctx->recs.push_back({cls, a, b});
+    }
+};
 
 frg::BubbleArgs bubble_args(frg_ctx ctx, bool fp32, void *bpp, void *bph) {
     const auto &g = ctx->g;
@@ -148,10 +184,40 @@ frg::BubbleArgs bubble_args(frg_ctx ctx, bool fp32, void *bpp, void *bph) {
 // prep + bubbles into the context's bubble tensor (or caller buffers)
 frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *state, double c,
                        void *bpp, void *bph, hipStream_t s) {
-    frg::launch_point_prep(ctx->d_xi, ctx->d_w, ctx->g.np, T_host, state, c,
-                           split ? nullptr : ctx->d_pa64, split ? ctx->d_pa32 : nullptr, ctx->d_T, s);
-    frg::launch_bubbles(bubble_args(ctx, split, bpp, bph), split, s);
+    {
+        KTimer kt(ctx, FRG_K_PREP, s);
+        frg::launch_point_prep(ctx->d_xi, ctx->d_w, ctx->g.np, T_host, state, c,
+                               split ? nullptr : ctx->d_pa64, split ? ctx->d_pa32 : nullptr,
+                               ctx->d_T, s);
+    }
+    {
+        KTimer kt(ctx, FRG_K_BUBBLES, s);
+        frg::launch_bubbles(bubble_args(ctx, split, bpp, bph), split, s);
+    }
     HIPCHK(hipGetLastError());
+    return FRG_OK;
+}
+
+// K parts of the fused contraction: enough blocks for several rounds over the
+// 256 compute units (measured best at N = 96: 4 parts); FRG_KSPLIT overrides
+int ksplit(frg_ctx ctx) {
+    if (ctx->ks_override > 0) return ctx->ks_override;
+    const int N = ctx->g.N;
+    const int bm = frg::contract_block_rows(N);
+    const int64_t tiles = 3LL * ((N + bm - 1) / bm) * ((static_cast<int64_t>(N) * N + 63) / 64);
+    int64_t ks = (1728 + tiles - 1) / tiles;
+    return static_cast<int>(ks < 1 ? 1 : (ks > 8 ? 8 : ks));
+}
+
+frg_status ensure_c(frg_ctx ctx, int KS) {
+    if (ctx->c_parts >= KS) return FRG_OK;
+    if (ctx->d_C) {
+        hipFree(ctx->d_C);
+        ctx->ws_bytes -= sizeof(double) * 3 * static_cast<size_t>(ctx->c_parts) * ctx->n3;
+        ctx->d_C = nullptr;
+    }
+    TRY(dalloc(ctx, &ctx->d_C, 3 * static_cast<size_t>(KS) * ctx->n3));
+    ctx->c_parts = KS;
     return FRG_OK;
 }
 
@@ -166,39 +232,48 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     void *bph = split ? static_cast<void *>(ctx->d_B32 + NN * g.Tpp)
                       : static_cast<void *>(ctx->d_B64 + NN * g.Tpp);
     TRY(run_bubbles(ctx, split, T_host, state, c, bpp, bph, s));
-    double *Cpp = ctx->d_C, *Cc = ctx->d_C + n3, *Cd = ctx->d_C + 2 * n3;
-    frg::ContractArgs a;
+    const int KS = ksplit(ctx);
+    TRY(ensure_c(ctx, KS));
+    double *Cpp = ctx->d_C, *Cc = ctx->d_C + KS * n3, *Cd = ctx->d_C + 2 * KS * n3;
+    frg::FusedContractArgs a;
     std::memset(&a, 0, sizeof(a));
     a.N = N;
+    a.KS = KS;
+    a.n3 = n3;
+    a.B[frg::TERM_PP] = bpp;
+    a.B[frg::TERM_PHC] = a.B[frg::TERM_PHD] = bph;
+    a.colrow[frg::TERM_PP] = ctx->d_colrow_pp;
+    a.colrow[frg::TERM_PHC] = a.colrow[frg::TERM_PHD] = ctx->d_colrow_ph;
+    a.C[frg::TERM_PP] = Cpp;
+    a.C[frg::TERM_PHC] = Cc;
+    a.C[frg::TERM_PHD] = Cd;
+    {
+        KTimer kt(ctx, FRG_K_LAYOUT, s);
+        if (!split) frg::launch_layout_f64(V, N, ctx->d_perm, s);
+        else frg::launch_layout_split(V, N, ctx->d_ahl, ctx->d_g32, s);
+    }
     if (!split) {
-        frg::launch_layout_f64(V, N, ctx->d_perm, s);
         const double *P = ctx->d_perm;
-        a.term = frg::TERM_PP; a.B = bpp; a.colrow = ctx->d_colrow_pp;
-        a.A64[0] = P; a.G64[0] = V; a.C = Cpp;
-        frg::launch_contract(a, false, s);
-        a.term = frg::TERM_PHC; a.B = bph; a.colrow = ctx->d_colrow_ph;
-        a.A64[0] = V; a.G64[0] = P + n3; a.C = Cc;
-        frg::launch_contract(a, false, s);
-        a.term = frg::TERM_PHD;
-        a.A64[0] = P + 2 * n3; a.G64[0] = P + 4 * n3;
-        a.A64[1] = P + 3 * n3; a.G64[1] = P + 4 * n3; a.C = Cd;
-        frg::launch_contract(a, false, s);
+        a.A64[frg::TERM_PP][0] = P;          a.G64[frg::TERM_PP][0] = V;
+        a.A64[frg::TERM_PHC][0] = V;         a.G64[frg::TERM_PHC][0] = P + n3;
+        a.A64[frg::TERM_PHD][0] = P + 2 * n3; a.G64[frg::TERM_PHD][0] = P + 4 * n3;
+        a.A64[frg::TERM_PHD][1] = P + 3 * n3; a.G64[frg::TERM_PHD][1] = P + 4 * n3;
     } else {
-        frg::launch_layout_split(V, N, ctx->d_ahl, ctx->d_g32, s);
         const uint16_t *H = ctx->d_ahl;
         const float *G = ctx->d_g32;
-        a.term = frg::TERM_PP; a.B = bpp; a.colrow = ctx->d_colrow_pp;
-        a.Ahl[0] = H; a.G32[0] = G; a.C = Cpp;
-        frg::launch_contract(a, true, s);
-        a.term = frg::TERM_PHC; a.B = bph; a.colrow = ctx->d_colrow_ph;
-        a.Ahl[0] = H + 2 * n3; a.G32[0] = G + n3; a.C = Cc;
-        frg::launch_contract(a, true, s);
-        a.term = frg::TERM_PHD;
-        a.Ahl[0] = H + 4 * n3; a.G32[0] = G + 2 * n3;
-        a.Ahl[1] = H + 6 * n3; a.G32[1] = G + 2 * n3; a.C = Cd;
-        frg::launch_contract(a, true, s);
+        a.Ahl[frg::TERM_PP][0] = H;          a.G32[frg::TERM_PP][0] = G;
+        a.Ahl[frg::TERM_PHC][0] = H + 2 * n3; a.G32[frg::TERM_PHC][0] = G + n3;
+        a.Ahl[frg::TERM_PHD][0] = H + 4 * n3; a.G32[frg::TERM_PHD][0] = G + 2 * n3;
+        a.Ahl[frg::TERM_PHD][1] = H + 6 * n3; a.G32[frg::TERM_PHD][1] = G + 2 * n3;
     }
-    frg::launch_combine(Cpp, Cc, Cd, n3, ctx->d_T, scale_by_T, F, s);
+    {
+        KTimer kt(ctx, FRG_K_CONTRACT, s);
+        frg::launch_contract_fused(a, split, s);
+    }
+    {
+        KTimer kt(ctx, FRG_K_COMBINE, s);
+        frg::launch_combine(Cpp, Cc, Cd, n3, KS, ctx->d_T, scale_by_T, F, s);
+    }
     HIPCHK(hipGetLastError());
     return FRG_OK;
 }
@@ -278,6 +353,7 @@ frg_status frg_create(const frg_params *p, frg_ctx *out) {
 
     frg_ctx ctx = new frg_ctx_s();
     ctx->device = dev;
+    if (const char *e = std::getenv("FRG_KSPLIT")) ctx->ks_override = std::atoi(e);
     frg::build_geometry(*p, ctx->g);
     const auto &g = ctx->g;
     ctx->Trows = g.Tpp + g.Tph;
@@ -352,6 +428,7 @@ frg_status frg_destroy(frg_ctx ctx) {
     for (int j = 0; j < 7; ++j)
         if (ctx->d_k[j]) hipFree(ctx->d_k[j]);
     if (ctx->h_state) hipHostFree(ctx->h_state);
+    for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
     delete ctx;
     return FRG_OK;
 }
@@ -485,16 +562,20 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
     sa.state = state;
     for (int j = 0; j < 7; ++j) sa.k[j] = ctx->d_k[j];
     if (o->stepper == FRG_DP54) {
-        frg::launch_pre_step(state, FRG_DP54, s);
         for (int st = 1; st < 7; ++st) {
             sa.nk = st;
             for (int j = 0; j < 7; ++j) sa.coef[j] = j < st ? DP_A[st][j] : 0.0;
             sa.out = st == 6 ? ctx->d_y5 : ctx->d_yt;
-            frg::launch_rk_stage(sa, s);
+            {
+                KTimer kt(ctx, FRG_K_RK, s);
+                if (st == 1) frg::launch_pre_step(state, FRG_DP54, s);
+                frg::launch_rk_stage(sa, s);
+            }
             TRY(run_rhs(ctx, split, 0.0, state, DP_C[st], sa.out, ctx->d_k[st], 1, s));
         }
         const double *kk[7];
         for (int j = 0; j < 7; ++j) kk[j] = ctx->d_k[j];
+        KTimer kt(ctx, FRG_K_RK, s);
         frg::launch_dp_error(n, V, ctx->d_y5, kk, DP_E, o->rtol, o->atol, state, ctx->d_partial,
                              red_blocks(n), s);
         frg::launch_dp_control(state, log, log_cap, o->vmax, o->max_steps, FRG_DP54, s);
@@ -567,6 +648,35 @@ frg_status frg_flow(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_
     r->rhs_evals = static_cast<int32_t>(hs[FRG_ST_RHS]);
     r->first_step_rhs = static_cast<int32_t>(hs[FRG_ST_FIRST_RHS]);
     if (r->reason == FRG_STOP_NONFINITE) return fail(FRG_ENONFINITE, "flow state became non-finite");
+    return FRG_OK;
+}
+
+frg_status frg_profile_begin(frg_ctx ctx) {
+    TRY(check_ctx(ctx));
+    ctx->recs.clear();
+    ctx->ev_used = 0;
+    ctx->prof = true;
+    return FRG_OK;
+}
+
+frg_status frg_profile_end(frg_ctx ctx, double *ms, int32_t *counts) {
+    TRY(check_ctx(ctx));
+    ctx->prof = false;
+    double acc[FRG_KERNEL_CLASSES] = {0};
+    int32_t cnt[FRG_KERNEL_CLASSES] = {0};
+    for (const auto &r : ctx->recs) {
+        HIPCHK(hipEventSynchronize(r.b));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+        acc[r.cls] += t;
+        cnt[r.cls] += 1;
+    }
+    ctx->recs.clear();
+    ctx->ev_used = 0;
+    for (int k = 0; k < FRG_KERNEL_CLASSES; ++k) {
+        if (ms) ms[k] = acc[k];
+        if (counts) counts[k] = cnt[k];
+    }
     return FRG_OK;
 }
 

@@ -57,21 +57,24 @@ void launch_layout_f64(const double *V, int N, double *perm, hipStream_t s);
 void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipStream_t s);
 
 enum Term { TERM_PP = 0, TERM_PHC = 1, TERM_PHD = 2 };
-struct ContractArgs {
-    int N;
-    int term;
-    const void *B;          // bubble rows (double or float), row-major [row][N*N]
-    const int32_t *colrow;  // column c -> bubble row
-    const double *A64[2];   // FP64 A operands [N][N*N]
-    const uint16_t *Ahl[2]; // split: [2][N][N*N] bf16 hi, lo
-    const double *G64[2];   // FP64 gather tables
-    const float *G32[2];    // FP32 gather tables
-    double *C;              // output [N^3] in F layout of the term
-};
-void launch_contract(const ContractArgs &a, bool split, hipStream_t s);
 
-// F = scale * (-Cpp + Cc + Cd), scale = T when Tdev != nullptr and scale_by_T
-void launch_combine(const double *Cpp, const double *Cc, const double *Cd, int64_t n,
+// all three channels in one launch; term t writes C[t] + part * n3 for K part `part`
+struct FusedContractArgs {
+    int N, KS, mtiles, ctiles;
+    int64_t n3;
+    const void *B[3];             // bubble rows per term (pp: Bpp, phc/phd: Bph)
+    const int32_t *colrow[3];
+    const double *A64[3][2];
+    const uint16_t *Ahl[3][2];
+    const double *G64[3][2];
+    const float *G32[3][2];
+    double *C[3];
+};
+void launch_contract_fused(const FusedContractArgs &a, bool split, hipStream_t s);
+int contract_block_rows(int N);
+
+// F = scale * sum_parts (Cc - Cpp + Cd), scale = T when scale_by_T
+void launch_combine(const double *Cpp, const double *Cc, const double *Cd, int64_t n, int parts,
                     const double *Tdev, int scale_by_T, double *F, hipStream_t s);
 
 // ----------------------------------------------------------------- RK kernels

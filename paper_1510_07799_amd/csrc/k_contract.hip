@@ -10,11 +10,19 @@
 //   phc: m = j1, c = (j2,j3), A = V(j1,a,b),   g = V(b,j2,j3)
 //   phd: m = j2, c = (j1,j3), A = -2V(a,j2,b)+V(j2,a,b) with g = V(j1,b,j3),
 //                              plus A = V(a,j2,b)           with g = V(j1,b,a)
-// The A tile is staged through LDS; the B-side tile Z = B_row(c)[k] g(c,k) is
-// formed in registers from one bubble row per column and written to LDS in
-// the matrix-core operand layout.  FP64: v_mfma_f64_16x16x4f64.  Split path:
-// A and Z as bf16 hi + lo, three v_mfma_f32_16x16x32_bf16 per k-step
-// (hi*hi + hi*lo + lo*hi), FP32 accumulation, result widened to FP64.
+//
+// One launch covers all three channels.  A block owns a BM x BC output tile
+// of one channel over one K range (K split in KS parts to fill the chip; the
+// parts are summed in a fixed order afterwards, so the result is
+// deterministic).  Per K chunk the A tile is read with 16-byte loads and the
+// B-side tile Z = B_row(c)[k] g(c,k) is formed in registers from one bubble
+// row per column; both are stored to LDS in the matrix-core operand layout,
+// and the global loads of the next chunk are issued before the MFMAs of the
+// current one.  Four waves in a 2 x 2 arrangement each own (BM/2) x (BC/2),
+// so every operand fragment read from LDS feeds several MFMAs.
+//   FP64:  v_mfma_f64_16x16x4f64, K chunk 32.
+//   split: A and Z as bf16 hi + lo, three v_mfma_f32_16x16x32_bf16 per
+//          k-step (hi*hi + hi*lo + lo*hi), FP32 accumulation, K chunk 64.
 #include "frg_internal.h"
 
 namespace frg {
@@ -22,13 +30,13 @@ namespace frg {
 namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef double d2_t __attribute__((ext_vector_type(2)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
-typedef uint16_t u16x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 32;   // output rows (m) per block
-constexpr int BC = 64;   // output columns (c) per block
+constexpr int BC = 64;         // output columns (c) per block
 constexpr int kThreads = 256;
 
 // output index of C[m, c] in the F layout of the term
@@ -40,90 +48,6 @@ __device__ __forceinline__ int64_t out_index(int N, int m, int c) {
     return static_cast<int64_t>(c / N) * K + static_cast<int64_t>(m) * N + (c % N);  // F[j1][j2=m][j3]
 }
 
-// ------------------------------------------------------------------ FP64
-template <int TERM>
-__global__ __launch_bounds__(kThreads) void contract_f64_kernel(ContractArgs P) {
-    constexpr int BK = 16;
-    constexpr int NP = TERM == TERM_PHD ? 2 : 1;
-    __shared__ double sA[NP][BM][BK + 1];
-    __shared__ double sZ[NP][BC][BK + 1];
-    const int N = P.N;
-    const int K = N * N;
-    const int NC = N * N;
-    const int m0 = blockIdx.y * BM, c0 = blockIdx.x * BC;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const double *B = static_cast<const double *>(P.B);
-
-    // A loader: row ml, two consecutive k
-    const int ml = tid >> 3, ak = (tid & 7) * 2;
-    const bool mvalid = (m0 + ml) < N;
-    // Z loader: column cl, four consecutive k
-    const int cl = tid >> 2, zk = (tid & 3) * 4;
-    const int c = c0 + cl;
-    const bool cvalid = c < NC;
-    const double *brow = B + static_cast<int64_t>(cvalid ? P.colrow[c] : 0) * K;
-    const double *g0 = P.G64[0] + static_cast<int64_t>(cvalid ? c : 0) * N;
-    const double *g1 = TERM == TERM_PHD ? P.G64[1] + static_cast<int64_t>(cvalid ? c / N : 0) * K
-                                        : nullptr;
-
-    const int mb = wave & 1, cb0 = (wave >> 1) * 2;
-    d4_t acc[2];
-    acc[0] = d4_t{0.0, 0.0, 0.0, 0.0};
-    acc[1] = d4_t{0.0, 0.0, 0.0, 0.0};
-
-    for (int k0 = 0; k0 < K; k0 += BK) {
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const double *Ap = P.A64[p] + static_cast<int64_t>(m0 + ml) * K;
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int k = k0 + ak + q;
-                sA[p][ml][ak + q] = (mvalid && k < K) ? Ap[k] : 0.0;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = k0 + zk + q;
-            const bool ok = cvalid && k < K;
-            const int a = k / N, b = k - a * N;
-            const double bv = ok ? brow[k] : 0.0;
-            if (TERM == TERM_PP) {
-                sZ[0][cl][zk + q] = ok ? bv * g0[a] : 0.0;
-            } else if (TERM == TERM_PHC) {
-                sZ[0][cl][zk + q] = ok ? bv * g0[b] : 0.0;
-            } else {
-                sZ[0][cl][zk + q] = ok ? bv * g0[b] : 0.0;
-                sZ[NP - 1][cl][zk + q] = ok ? bv * g1[k] : 0.0;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < BK / 4; ++kk) {
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                const double af = sA[p][mb * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
-#pragma unroll
-                for (int ci = 0; ci < 2; ++ci) {
-                    const double bf = sZ[p][(cb0 + ci) * 16 + (lane & 15)][kk * 4 + (lane >> 4)];
-                    acc[ci] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf, acc[ci], 0, 0, 0);
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // f64 16x16x4 accumulator layout: lane l, register r holds row (l>>4) + 4r, column l&15
-#pragma unroll
-    for (int ci = 0; ci < 2; ++ci) {
-        const int cc = c0 + (cb0 + ci) * 16 + (lane & 15);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int m = m0 + mb * 16 + (lane >> 4) + 4 * r;
-            if (m < N && cc < NC) P.C[out_index<TERM>(N, m, cc)] = acc[ci][r];
-        }
-    }
-}
-
-// ------------------------------------------------------------------ split BF16
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
     uint32_t u = __float_as_uint(x);
     u += 0x7fffu + ((u >> 16) & 1u);
@@ -133,125 +57,393 @@ __device__ __forceinline__ float bf16_to_f(uint16_t h) {
     return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
 
-template <int TERM>
-__global__ __launch_bounds__(kThreads) void contract_split_kernel(ContractArgs P) {
-    constexpr int BK = 32;
-    constexpr int LD = BK + 8;   // bf16 row pitch (16-byte aligned rows)
+struct Work {
+    int term, mtile, ctile, ks;
+};
+
+// block -> (term, m tile, c tile, K part); heaviest channel (phd) first
+__device__ __forceinline__ Work decode_block(const FusedContractArgs &P) {
+    int id = blockIdx.x;
+    const int per_term = P.mtiles * P.ctiles * P.KS;
+    Work w;
+    const int order[3] = {TERM_PHD, TERM_PHC, TERM_PP};
+    const int t = id / per_term;
+    w.term = order[t];
+    id -= t * per_term;
+    w.ks = id % P.KS;
+    id /= P.KS;
+    w.ctile = id % P.ctiles;
+    w.mtile = id / P.ctiles;
+    return w;
+}
+
+// ------------------------------------------------------------------ FP64
+template <int TERM, int BM>
+__device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work &w, double *smem) {
+    constexpr int BK = 16;
+    constexpr int ZK = BK / 4;                          // k per thread in the Z loader
     constexpr int NP = TERM == TERM_PHD ? 2 : 1;
-    __shared__ __attribute__((aligned(16))) uint16_t sA[NP][2][BM][LD];
-    __shared__ __attribute__((aligned(16))) uint16_t sZ[NP][2][BC][LD];
+    constexpr int LDA = BK + 1;
+    constexpr int NCH = BM * BK / 2;                    // 16-byte A chunks per operand
+    constexpr int ACH = (NCH + kThreads - 1) / kThreads;
+    double *sA = smem;                        // [NP][BM][LDA]
+    double *sZ = smem + NP * BM * LDA;        // [NP][BC][LDA]
     const int N = P.N;
     const int K = N * N;
     const int NC = N * N;
-    const int64_t n3 = static_cast<int64_t>(N) * K;
-    const int m0 = blockIdx.y * BM, c0 = blockIdx.x * BC;
+    const int m0 = w.mtile * BM, c0 = w.ctile * BC;
+    const int kchunks = (K + BK - 1) / BK;
+    const int kc_lo = static_cast<int>((static_cast<int64_t>(kchunks) * w.ks) / P.KS);
+    const int kc_hi = static_cast<int>((static_cast<int64_t>(kchunks) * (w.ks + 1)) / P.KS);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const float *B = static_cast<const float *>(P.B);
+    const double *A0 = P.A64[TERM][0];
+    const double *A1 = P.A64[TERM][1];
+    const double *B = static_cast<const double *>(P.B[TERM]);
+    const int32_t *colrow = P.colrow[TERM];
 
-    const int ml = tid >> 3, ak = (tid & 7) * 4;       // A loader: 4 k per thread
-    const bool mvalid = (m0 + ml) < N;
-    const int cl = tid >> 2, zk = (tid & 3) * 8;       // Z loader: 8 k per thread
+    // Z loader: column cl, ZK consecutive k
+    const int cl = tid >> 2, zk = (tid & 3) * ZK;
     const int c = c0 + cl;
     const bool cvalid = c < NC;
-    const float *brow = B + static_cast<int64_t>(cvalid ? P.colrow[c] : 0) * K;
-    const float *g0 = P.G32[0] + static_cast<int64_t>(cvalid ? c : 0) * N;
-    const float *g1 = TERM == TERM_PHD ? P.G32[1] + static_cast<int64_t>(cvalid ? c / N : 0) * K
-                                       : nullptr;
+    const double *brow = B + static_cast<int64_t>(cvalid ? colrow[c] : 0) * K;
+    const double *g0 = P.G64[TERM][0] + static_cast<int64_t>(cvalid ? c : 0) * N;
+    const double *g1 = TERM == TERM_PHD ? P.G64[TERM][1] + static_cast<int64_t>(cvalid ? c / N : 0) * K
+                                        : nullptr;
 
-    const int mb = wave & 1, cb0 = (wave >> 1) * 2;
-    f4_t acc[2];
-    acc[0] = f4_t{0.f, 0.f, 0.f, 0.f};
-    acc[1] = f4_t{0.f, 0.f, 0.f, 0.f};
+    d2_t ra[NP][ACH];
+    double rb[ZK], rg0[ZK], rg1[ZK];
 
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    auto load = [&](int kc) {
+        const int k0 = kc * BK;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
+            const double *Ap = p == 0 ? A0 : A1;
 #pragma unroll
-            for (int hl = 0; hl < 2; ++hl) {
-                const uint16_t *Ap = P.Ahl[p] + hl * n3 + static_cast<int64_t>(m0 + ml) * K;
-                u16x4_t v;
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int k = k0 + ak + q;
-                    v[q] = (mvalid && k < K) ? Ap[k] : static_cast<uint16_t>(0);
+            for (int i = 0; i < ACH; ++i) {
+                const int ch = tid + i * kThreads;         // chunk id: row ch / (BK/2), col pair
+                const int row = ch / (BK / 2), kp = (ch % (BK / 2)) * 2;
+                const int m = m0 + row, k = k0 + kp;
+                if (ch >= NCH) {
+                    ra[p][i] = d2_t{0.0, 0.0};
+                } else if (m < N && k + 1 < K) {
+                    ra[p][i] = *reinterpret_cast<const d2_t *>(Ap + static_cast<int64_t>(m) * K + k);
+                } else {
+                    ra[p][i][0] = (m < N && k < K) ? Ap[static_cast<int64_t>(m) * K + k] : 0.0;
+                    ra[p][i][1] = 0.0;
                 }
-                *reinterpret_cast<u16x4_t *>(&sA[p][hl][ml][ak]) = v;
             }
         }
-        u16x8_t zh[NP], zl[NP];
+        const int kb = k0 + zk;
+        if (cvalid && kb + ZK <= K) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int k = k0 + zk + q;
-            const bool ok = cvalid && k < K;
-            const int a = k / N, b = k - a * N;
-            const float bv = ok ? brow[k] : 0.f;
-            float z[NP];
-            if (TERM == TERM_PP) {
-                z[0] = ok ? bv * g0[a] : 0.f;
-            } else if (TERM == TERM_PHC) {
-                z[0] = ok ? bv * g0[b] : 0.f;
-            } else {
-                z[0] = ok ? bv * g0[b] : 0.f;
-                z[NP - 1] = ok ? bv * g1[k] : 0.f;
+            for (int q = 0; q < ZK; q += 2) {
+                const d2_t v = *reinterpret_cast<const d2_t *>(brow + kb + q);
+                rb[q] = v[0];
+                rb[q + 1] = v[1];
             }
+        } else {
+#pragma unroll
+            for (int q = 0; q < ZK; ++q) rb[q] = (cvalid && kb + q < K) ? brow[kb + q] : 0.0;
+        }
+        int a = kb / N, b = kb - a * N;
+#pragma unroll
+        for (int q = 0; q < ZK; ++q) {
+            const bool ok = cvalid && kb + q < K;
+            if (TERM == TERM_PP) rg0[q] = ok ? g0[a] : 0.0;
+            else rg0[q] = ok ? g0[b] : 0.0;
+            if (TERM == TERM_PHD) rg1[q] = ok ? g1[kb + q] : 0.0;
+            if (++b == N) { b = 0; ++a; }
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int i = 0; i < ACH; ++i) {
+                const int ch = tid + i * kThreads;
+                if (ch >= NCH) continue;
+                const int row = ch / (BK / 2), kp = (ch % (BK / 2)) * 2;
+                sA[(p * BM + row) * LDA + kp] = ra[p][i][0];
+                sA[(p * BM + row) * LDA + kp + 1] = ra[p][i][1];
+            }
+#pragma unroll
+        for (int q = 0; q < ZK; ++q) {
+            sZ[cl * LDA + zk + q] = rb[q] * rg0[q];
+            if (TERM == TERM_PHD) sZ[(BC + cl) * LDA + zk + q] = rb[q] * rg1[q];
+        }
+    };
+
+    constexpr int RT = BM / 32;   // row tiles of 16 per wave
+    const int wm = wave & 1, wc = wave >> 1;
+    d4_t acc[RT][2];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        acc[i][0] = d4_t{0.0, 0.0, 0.0, 0.0};
+        acc[i][1] = d4_t{0.0, 0.0, 0.0, 0.0};
+    }
+    if (kc_lo < kc_hi) load(kc_lo);
+    for (int kc = kc_lo; kc < kc_hi; ++kc) {
+        store();
+        __syncthreads();
+        if (kc + 1 < kc_hi) load(kc + 1);
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                const uint16_t hi = bf16_rne(z[p]);
-                zh[p][q] = hi;
-                zl[p][q] = bf16_rne(z[p] - bf16_to_f(hi));
+                double bf[2];
+#pragma unroll
+                for (int ci = 0; ci < 2; ++ci)
+                    bf[ci] = sZ[(p * BC + wc * 32 + ci * 16 + (lane & 15)) * LDA + kk * 4 + (lane >> 4)];
+#pragma unroll
+                for (int ri = 0; ri < RT; ++ri) {
+                    const double af = sA[(p * BM + wm * (BM / 2) + ri * 16 + (lane & 15)) * LDA + kk * 4 + (lane >> 4)];
+#pragma unroll
+                    for (int ci = 0; ci < 2; ++ci)
+                        acc[ri][ci] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[ci], acc[ri][ci], 0, 0, 0);
+                }
             }
         }
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            *reinterpret_cast<u16x8_t *>(&sZ[p][0][cl][zk]) = zh[p];
-            *reinterpret_cast<u16x8_t *>(&sZ[p][1][cl][zk]) = zl[p];
-        }
         __syncthreads();
+    }
+    // f64 16x16x4 accumulator layout: lane l, register r holds row (l>>4) + 4r, column l&15
+    double *Cout = P.C[TERM] + static_cast<int64_t>(w.ks) * P.n3;
+#pragma unroll
+    for (int ri = 0; ri < RT; ++ri)
+#pragma unroll
+        for (int ci = 0; ci < 2; ++ci) {
+            const int cc = c0 + wc * 32 + ci * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm * (BM / 2) + ri * 16 + (lane >> 4) + 4 * r;
+                if (m < N && cc < NC) Cout[out_index<TERM>(N, m, cc)] = acc[ri][ci][r];
+            }
+        }
+}
+
+// ------------------------------------------------------------------ split BF16
+template <int TERM, int BM>
+__device__ __forceinline__ void body_split(const FusedContractArgs &P, const Work &w, uint16_t *smem) {
+    constexpr int BK = 32;
+    constexpr int ZK = BK / 4;    // k per thread in the Z loader
+    constexpr int LD = BK + 8;    // bf16 row pitch: rows stay 16-byte aligned
+    constexpr int NP = TERM == TERM_PHD ? 2 : 1;
+    constexpr int CPR = BK / 8;                         // 16-byte chunks per row and plane
+    constexpr int NCH = BM * CPR;
+    constexpr int ACH = (NCH + kThreads - 1) / kThreads;
+    uint16_t *sA = smem;                           // [NP][2][BM][LD]
+    uint16_t *sZ = smem + NP * 2 * BM * LD;        // [NP][2][BC][LD]
+    const int N = P.N;
+    const int K = N * N;
+    const int NC = N * N;
+    const int64_t n3 = P.n3;
+    const int m0 = w.mtile * BM, c0 = w.ctile * BC;
+    const int kchunks = (K + BK - 1) / BK;
+    const int kc_lo = static_cast<int>((static_cast<int64_t>(kchunks) * w.ks) / P.KS);
+    const int kc_hi = static_cast<int>((static_cast<int64_t>(kchunks) * (w.ks + 1)) / P.KS);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint16_t *Ahl[2] = {P.Ahl[TERM][0], P.Ahl[TERM][1]};
+    const float *B = static_cast<const float *>(P.B[TERM]);
+    const int32_t *colrow = P.colrow[TERM];
+
+    const int cl = tid >> 2, zk = (tid & 3) * ZK;   // Z loader: column cl, ZK consecutive k
+    const int c = c0 + cl;
+    const bool cvalid = c < NC;
+    const float *brow = B + static_cast<int64_t>(cvalid ? colrow[c] : 0) * K;
+    const float *g0 = P.G32[TERM][0] + static_cast<int64_t>(cvalid ? c : 0) * N;
+    const float *g1 = TERM == TERM_PHD ? P.G32[TERM][1] + static_cast<int64_t>(cvalid ? c / N : 0) * K
+                                       : nullptr;
+
+    u32x4_t ra[NP][2][ACH];
+    float rb[ZK], rg0[ZK], rg1[ZK];
+
+    auto load = [&](int kc) {
+        const int k0 = kc * BK;
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int hl = 0; hl < 2; ++hl)
+#pragma unroll
+                for (int i = 0; i < ACH; ++i) {
+                    const int ch = tid + i * kThreads;            // row ch / CPR, 8 bf16 per chunk
+                    const int row = ch / CPR, kq = (ch % CPR) * 8;
+                    const int m = m0 + row, k = k0 + kq;
+                    const uint16_t *src = Ahl[p] + hl * n3 + static_cast<int64_t>(m) * K + k;
+                    if (ch >= NCH) {
+                        ra[p][hl][i] = u32x4_t{0u, 0u, 0u, 0u};
+                    } else if (m < N && k + 8 <= K) {
+                        ra[p][hl][i] = *reinterpret_cast<const u32x4_t *>(src);
+                    } else {
+                        u16x8_t v;
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) v[q] = (m < N && k + q < K) ? src[q] : uint16_t(0);
+                        ra[p][hl][i] = *reinterpret_cast<u32x4_t *>(&v);
+                    }
+                }
+        const int kb = k0 + zk;
+        if (cvalid && kb + ZK <= K) {
+#pragma unroll
+            for (int q = 0; q < ZK; q += 4) {
+                const f4_t v = *reinterpret_cast<const f4_t *>(brow + kb + q);
+                rb[q] = v[0]; rb[q + 1] = v[1]; rb[q + 2] = v[2]; rb[q + 3] = v[3];
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < ZK; ++q) rb[q] = (cvalid && kb + q < K) ? brow[kb + q] : 0.f;
+        }
+        int a = kb / N, b = kb - a * N;
+        if (TERM != TERM_PP && cvalid && b + ZK <= N && (b & 3) == 0 && (N & 3) == 0) {
+#pragma unroll
+            for (int q = 0; q < ZK; q += 4) {
+                const f4_t v = *reinterpret_cast<const f4_t *>(g0 + b + q);
+                rg0[q] = v[0]; rg0[q + 1] = v[1]; rg0[q + 2] = v[2]; rg0[q + 3] = v[3];
+            }
+        } else {
+            int aa = a, bb = b;
+#pragma unroll
+            for (int q = 0; q < ZK; ++q) {
+                const bool ok = cvalid && kb + q < K;
+                rg0[q] = ok ? (TERM == TERM_PP ? g0[aa] : g0[bb]) : 0.f;
+                if (++bb == N) { bb = 0; ++aa; }
+            }
+        }
+        if (TERM == TERM_PHD) {
+            if (cvalid && kb + ZK <= K) {
+#pragma unroll
+                for (int q = 0; q < ZK; q += 4) {
+                    const f4_t v = *reinterpret_cast<const f4_t *>(g1 + kb + q);
+                    rg1[q] = v[0]; rg1[q + 1] = v[1]; rg1[q + 2] = v[2]; rg1[q + 3] = v[3];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < ZK; ++q) rg1[q] = (cvalid && kb + q < K) ? g1[kb + q] : 0.f;
+            }
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int hl = 0; hl < 2; ++hl)
+#pragma unroll
+                for (int i = 0; i < ACH; ++i) {
+                    const int ch = tid + i * kThreads;
+                    if (ch >= NCH) continue;
+                    const int row = ch / CPR, kq = (ch % CPR) * 8;
+                    *reinterpret_cast<u32x4_t *>(sA + ((p * 2 + hl) * BM + row) * LD + kq) = ra[p][hl][i];
+                }
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const int arow = mb * 16 + (lane & 15), kof = (lane >> 4) * 8;
-            const bf8_t ahi = *reinterpret_cast<const bf8_t *>(&sA[p][0][arow][kof]);
-            const bf8_t alo = *reinterpret_cast<const bf8_t *>(&sA[p][1][arow][kof]);
+            u16x8_t hi, lo;
 #pragma unroll
-            for (int ci = 0; ci < 2; ++ci) {
-                const int zrow = (cb0 + ci) * 16 + (lane & 15);
-                const bf8_t zhi = *reinterpret_cast<const bf8_t *>(&sZ[p][0][zrow][kof]);
-                const bf8_t zlo = *reinterpret_cast<const bf8_t *>(&sZ[p][1][zrow][kof]);
-                acc[ci] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, zhi, acc[ci], 0, 0, 0);
-                acc[ci] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, zlo, acc[ci], 0, 0, 0);
-                acc[ci] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, zhi, acc[ci], 0, 0, 0);
+            for (int q = 0; q < ZK; ++q) {
+                const float z = rb[q] * (p == 0 ? rg0[q] : rg1[q]);
+                const uint16_t zh = bf16_rne(z);
+                hi[q] = zh;
+                lo[q] = bf16_rne(z - bf16_to_f(zh));
+            }
+            *reinterpret_cast<u16x8_t *>(sZ + ((p * 2 + 0) * BC + cl) * LD + zk) = hi;
+            *reinterpret_cast<u16x8_t *>(sZ + ((p * 2 + 1) * BC + cl) * LD + zk) = lo;
+        }
+    };
+
+    constexpr int RT = BM / 32;
+    const int wm = wave & 1, wc = wave >> 1;
+    f4_t acc[RT][2];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+        acc[i][0] = f4_t{0.f, 0.f, 0.f, 0.f};
+        acc[i][1] = f4_t{0.f, 0.f, 0.f, 0.f};
+    }
+    if (kc_lo < kc_hi) load(kc_lo);
+    for (int kc = kc_lo; kc < kc_hi; ++kc) {
+        store();
+        __syncthreads();
+        if (kc + 1 < kc_hi) load(kc + 1);
+#pragma unroll
+        for (int ks = 0; ks < BK / 32; ++ks) {
+            const int kof = ks * 32 + (lane >> 4) * 8;
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                bf8_t zh[2], zl[2];
+#pragma unroll
+                for (int ci = 0; ci < 2; ++ci) {
+                    const int zr = wc * 32 + ci * 16 + (lane & 15);
+                    zh[ci] = *reinterpret_cast<const bf8_t *>(sZ + ((p * 2 + 0) * BC + zr) * LD + kof);
+                    zl[ci] = *reinterpret_cast<const bf8_t *>(sZ + ((p * 2 + 1) * BC + zr) * LD + kof);
+                }
+#pragma unroll
+                for (int ri = 0; ri < RT; ++ri) {
+                    const int ar = wm * (BM / 2) + ri * 16 + (lane & 15);
+                    const bf8_t ah = *reinterpret_cast<const bf8_t *>(sA + ((p * 2 + 0) * BM + ar) * LD + kof);
+                    const bf8_t al = *reinterpret_cast<const bf8_t *>(sA + ((p * 2 + 1) * BM + ar) * LD + kof);
+#pragma unroll
+                    for (int ci = 0; ci < 2; ++ci) {
+                        acc[ri][ci] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, zh[ci], acc[ri][ci], 0, 0, 0);
+                        acc[ri][ci] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, zl[ci], acc[ri][ci], 0, 0, 0);
+                        acc[ri][ci] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, zh[ci], acc[ri][ci], 0, 0, 0);
+                    }
+                }
             }
         }
         __syncthreads();
     }
     // bf16 16x16x32 accumulator layout: lane l, register r holds row 4(l>>4) + r, column l&15
+    double *Cout = P.C[TERM] + static_cast<int64_t>(w.ks) * P.n3;
 #pragma unroll
-    for (int ci = 0; ci < 2; ++ci) {
-        const int cc = c0 + (cb0 + ci) * 16 + (lane & 15);
+    for (int ri = 0; ri < RT; ++ri)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int m = m0 + mb * 16 + 4 * (lane >> 4) + r;
-            if (m < N && cc < NC) P.C[out_index<TERM>(N, m, cc)] = static_cast<double>(acc[ci][r]);
+        for (int ci = 0; ci < 2; ++ci) {
+            const int cc = c0 + wc * 32 + ci * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm * (BM / 2) + ri * 16 + 4 * (lane >> 4) + r;
+                if (m < N && cc < NC) Cout[out_index<TERM>(N, m, cc)] = static_cast<double>(acc[ri][ci][r]);
+            }
         }
-    }
 }
 
-template <int TERM>
-void launch_term(const ContractArgs &a, bool split, hipStream_t s) {
-    const int NC = a.N * a.N;
-    dim3 grid((NC + BC - 1) / BC, (a.N + BM - 1) / BM);
-    if (split)
-        hipLaunchKernelGGL(contract_split_kernel<TERM>, grid, dim3(kThreads), 0, s, a);
-    else
-        hipLaunchKernelGGL(contract_f64_kernel<TERM>, grid, dim3(kThreads), 0, s, a);
+template <int BM>
+__global__ __launch_bounds__(kThreads) void contract_f64_fused(FusedContractArgs P) {
+    extern __shared__ double smem_d[];
+    const Work w = decode_block(P);
+    if (w.term == TERM_PHD) body_f64<TERM_PHD, BM>(P, w, smem_d);
+    else if (w.term == TERM_PHC) body_f64<TERM_PHC, BM>(P, w, smem_d);
+    else body_f64<TERM_PP, BM>(P, w, smem_d);
+}
+
+template <int BM>
+__global__ __launch_bounds__(kThreads) void contract_split_fused(FusedContractArgs P) {
+    extern __shared__ double smem_d[];
+    uint16_t *smem = reinterpret_cast<uint16_t *>(smem_d);
+    const Work w = decode_block(P);
+    if (w.term == TERM_PHD) body_split<TERM_PHD, BM>(P, w, smem);
+    else if (w.term == TERM_PHC) body_split<TERM_PHC, BM>(P, w, smem);
+    else body_split<TERM_PP, BM>(P, w, smem);
+}
+
+template <int BM>
+void launch_bm(FusedContractArgs a, bool split, hipStream_t s) {
+    a.mtiles = (a.N + BM - 1) / BM;
+    a.ctiles = (a.N * a.N + BC - 1) / BC;
+    const int blocks = 3 * a.mtiles * a.ctiles * a.KS;
+    if (split) {
+        const size_t lds = sizeof(uint16_t) * (2 * 2 * BM * (32 + 8) + 2 * 2 * BC * (32 + 8));
+        hipLaunchKernelGGL(contract_split_fused<BM>, dim3(blocks), dim3(kThreads), lds, s, a);
+    } else {
+        const size_t lds = sizeof(double) * (2 * BM * 17 + 2 * BC * 17);
+        hipLaunchKernelGGL(contract_f64_fused<BM>, dim3(blocks), dim3(kThreads), lds, s, a);
+    }
 }
 
 }  // namespace
 
-void launch_contract(const ContractArgs &a, bool split, hipStream_t s) {
-    if (a.term == TERM_PP) launch_term<TERM_PP>(a, split, s);
-    else if (a.term == TERM_PHC) launch_term<TERM_PHC>(a, split, s);
-    else launch_term<TERM_PHD>(a, split, s);
+int contract_block_rows(int N) { return N <= 32 ? 32 : (N <= 64 ? 64 : 96); }
+
+void launch_contract_fused(const FusedContractArgs &a, bool split, hipStream_t s) {
+    const int bm = contract_block_rows(a.N);
+    if (bm == 32) launch_bm<32>(a, split, s);
+    else if (bm == 64) launch_bm<64>(a, split, s);
+    else launch_bm<96>(a, split, s);
 }
 
 }  // namespace frg

@@ -155,12 +155,16 @@ __global__ void layout_split_kernel(const double *__restrict__ V, int N, uint16_
 }
 
 __global__ void combine_kernel(const double *__restrict__ Cpp, const double *__restrict__ Cc,
-                               const double *__restrict__ Cd, int64_t n,
+                               const double *__restrict__ Cd, int64_t n, int parts,
                                const double *__restrict__ Tdev, int scale_by_T,
                                double *__restrict__ F) {
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const double v = (Cc[i] - Cpp[i]) + Cd[i];
+    double v = 0.0;
+    for (int s = 0; s < parts; ++s) {
+        const int64_t j = s * n + i;
+        v += (Cc[j] - Cpp[j]) + Cd[j];
+    }
     F[i] = scale_by_T ? Tdev[0] * v : v;
 }
 
@@ -396,10 +400,10 @@ void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipS
                        g32);
 }
 
-void launch_combine(const double *Cpp, const double *Cc, const double *Cd, int64_t n,
+void launch_combine(const double *Cpp, const double *Cc, const double *Cd, int64_t n, int parts,
                     const double *Tdev, int scale_by_T, double *F, hipStream_t s) {
     hipLaunchKernelGGL(combine_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, Cpp, Cc, Cd, n,
-                       Tdev, scale_by_T, F);
+                       parts, Tdev, scale_by_T, F);
 }
 
 void launch_rk_stage(const RkStageArgs &a, hipStream_t s) {

@@ -21,6 +21,7 @@ RK4, DP54 = 0, 1
 STOP_NONE, STOP_TMIN, STOP_DIVERGED, STOP_MAXSTEPS, STOP_NONFINITE, STOP_HMIN = range(6)
 STATE_LEN = 32
 ST_S, ST_H, ST_ERR, ST_REASON, ST_ACCEPTED, ST_REJECTED, ST_RHS, ST_VMAX = range(8)
+KERNEL_CLASSES = ("prep", "bubbles", "layout", "contract", "combine", "rk")
 
 
 class FRGError(RuntimeError):
@@ -66,6 +67,8 @@ SIGNATURES = {
     "frg_flow_init": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, _P]),
     "frg_flow_step": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, _P]),
     "frg_flow": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, C.c_int32, C.POINTER(FlowResult), _P]),
+    "frg_profile_begin": (C.c_int, [_P]),
+    "frg_profile_end": (C.c_int, [_P, _DP, _IP]),
     "frg_status_str": (C.c_char_p, [C.c_int]),
     "frg_last_error": (C.c_char_p, []),
 }
@@ -214,6 +217,16 @@ class Context:
 
     def flow_step(self, opts: FlowOpts, V, state):
         _check(lib().frg_flow_step(self._h, C.byref(opts), _ptr(V), _ptr(state), _stream()))
+
+    def profile_begin(self):
+        _check(lib().frg_profile_begin(self._h))
+
+    def profile_end(self):
+        """Summed event time (ms) and launch count per kernel class since profile_begin."""
+        ms = np.zeros(len(KERNEL_CLASSES))
+        cnt = np.zeros(len(KERNEL_CLASSES), dtype=np.int32)
+        _check(lib().frg_profile_end(self._h, ms.ctypes.data_as(_DP), cnt.ctypes.data_as(_IP)))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
     def flow(self, V, opts: FlowOpts, log_cap=4096):
         """Run a whole flow in place on V; returns (result dict, log [accepted, 8])."""
