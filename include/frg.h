@@ -182,6 +182,18 @@ frg_status frg_flow_step(frg_ctx ctx, const frg_flow_opts *o, double *d_V, doubl
 frg_status frg_flow(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_log,
                     int32_t log_cap, frg_flow_result *r, void *stream);
 
+/* C4v reduction of the bubble work (Sec. 4 counts independent couplings after
+ * using the lattice symmetries): for N % 8 == 0 the grid is bitwise C4v
+ * symmetric, B_{g t}(g a, g b) = B_t(a, b), and each rhs evaluates the bubble
+ * rows of one transfer per orbit only (about 1/8 of them); the contraction
+ * reads the other rows through the patch permutation.  frg_create enables it
+ * after checking the relation exactly on the second-line patch table (setting
+ * FRG_NO_SYM in the environment leaves it off).  frg_set_symmetry switches it
+ * (ENOTSUP when unavailable); frg_symmetry reports whether it is on and how
+ * many bubble rows one rhs computes. */
+frg_status frg_set_symmetry(frg_ctx ctx, int32_t enable);
+frg_status frg_symmetry(frg_ctx ctx, int32_t *active, int32_t *rows_computed);
+
 /* Kernel timing with HIP events recorded on the launch stream around every
  * kernel of the rhs and flow pipelines (for measurement; off by default).
  * frg_profile_begin clears and enables the record; frg_profile_end

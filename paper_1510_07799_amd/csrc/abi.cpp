@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -22,7 +23,12 @@ struct frg_ctx_s {
     double *d_bnd = nullptr, *d_xi = nullptr, *d_w = nullptr, *d_trig_row = nullptr,
            *d_trig_pt = nullptr;
     uint8_t *d_bins = nullptr;
-    int32_t *d_colrow_pp = nullptr, *d_colrow_ph = nullptr;
+    int32_t *d_colrow_pp = nullptr, *d_colrow_ph = nullptr;   // (row << 3): every row stored
+    // C4v orbit reduction of the bubble rows
+    bool sym_avail = false, sym_on = false;
+    int n_rep_pp = 0, n_rep_ph = 0;
+    int32_t *d_rowlist = nullptr;                              // representative rows (pp, then ph)
+    int32_t *d_colsym_pp = nullptr, *d_colsym_ph = nullptr;   // (compact rep << 3) | element
     // rhs workspace
     double *d_pa64 = nullptr, *d_T = nullptr;
     float *d_pa32 = nullptr;
@@ -178,12 +184,100 @@ frg::BubbleArgs bubble_args(frg_ctx ctx, bool fp32, void *bpp, void *bph) {
     a.Tdev = ctx->d_T;
     a.Bpp = bpp;
     a.Bph = bph;
+    a.nrows = ctx->Trows;
+    a.npp_out = g.Tpp;
+    a.rowlist = nullptr;
     return a;
+}
+
+int c4v_patch_host(int o, int j, int N) {
+    const int q = N / 4;
+    const int v = (o & 1) ? ((o + 1) / 2) * q - 1 - j : j + (o / 2) * q;
+    return ((v % N) + N) % N;
+}
+
+// C4v orbits of the transfer rows (N % 8 == 0 only: the grid is then
+// bitwise symmetric).  Builds the representative list, the per-column
+// (compact rep, element) tables and checks B_{g t}(g a, g b) = B_t(a, b)
+// on the device's second-line table; the reduction is enabled only if the
+// check finds no exception.
+frg_status build_orbits(frg_ctx ctx) {
+    const auto &g = ctx->g;
+    const int N = g.N;
+    if (N % 8 != 0) return FRG_OK;
+    std::vector<int> pi(g.Tpp), pj(g.Tpp), px(g.Tph), py(g.Tph);
+    for (int i = 0; i < N; ++i)
+        for (int j = i; j < N; ++j) { const int t = g.row_pp[i * N + j]; pi[t] = i; pj[t] = j; }
+    for (int x = 0; x < N; ++x)
+        for (int y = 0; y < N; ++y) { const int t = g.row_ph[x * N + y]; px[t] = x; py[t] = y; }
+    auto img_pp = [&](int o, int t) {
+        return g.row_pp[c4v_patch_host(o, pi[t], N) * N + c4v_patch_host(o, pj[t], N)];
+    };
+    auto img_ph = [&](int o, int t) {
+        if (t == 0) return 0;
+        return g.row_ph[c4v_patch_host(o, px[t], N) * N + c4v_patch_host(o, py[t], N)];
+    };
+    std::vector<int> rep_pp(g.Tpp), el_pp(g.Tpp), rep_ph(g.Tph), el_ph(g.Tph);
+    for (int t = 0; t < g.Tpp; ++t) {
+        int r = t;
+        for (int o = 1; o < 8; ++o) r = std::min(r, img_pp(o, t));
+        rep_pp[t] = r;
+        el_pp[t] = -1;
+        for (int o = 0; o < 8 && el_pp[t] < 0; ++o)
+            if (img_pp(o, r) == t) el_pp[t] = o;
+    }
+    for (int t = 0; t < g.Tph; ++t) {
+        int r = t;
+        for (int o = 1; o < 8; ++o) r = std::min(r, img_ph(o, t));
+        rep_ph[t] = r;
+        el_ph[t] = -1;
+        for (int o = 0; o < 8 && el_ph[t] < 0; ++o)
+            if (img_ph(o, r) == t) el_ph[t] = o;
+    }
+    std::vector<int32_t> rowlist, cidx_pp(g.Tpp, -1), cidx_ph(g.Tph, -1), orbit(ctx->Trows);
+    for (int t = 0; t < g.Tpp; ++t)
+        if (rep_pp[t] == t) { cidx_pp[t] = static_cast<int32_t>(rowlist.size()); rowlist.push_back(t); }
+    const int npp = static_cast<int>(rowlist.size());
+    for (int t = 0; t < g.Tph; ++t)
+        if (rep_ph[t] == t) { cidx_ph[t] = static_cast<int32_t>(rowlist.size()) - npp; rowlist.push_back(g.Tpp + t); }
+    const int nph = static_cast<int>(rowlist.size()) - npp;
+    for (int t = 0; t < g.Tpp; ++t) orbit[t] = (rep_pp[t] << 3) | el_pp[t];
+    for (int t = 0; t < g.Tph; ++t) orbit[g.Tpp + t] = ((g.Tpp + rep_ph[t]) << 3) | el_ph[t];
+    std::vector<int32_t> cs_pp(static_cast<size_t>(N) * N), cs_ph(static_cast<size_t>(N) * N);
+    for (int y = 0; y < N; ++y)
+        for (int x = 0; x < N; ++x) {
+            const int tp = g.row_pp[y * N + x];
+            cs_pp[y * N + x] = (cidx_pp[rep_pp[tp]] << 3) | el_pp[tp];
+            const int th = g.row_ph[x * N + y];
+            cs_ph[y * N + x] = (cidx_ph[rep_ph[th]] << 3) | el_ph[th];
+        }
+    int32_t *d_orbit = nullptr;
+    int *d_bad = nullptr;
+    TRY(upload(ctx, &d_orbit, orbit.data(), orbit.size()));
+    TRY(dalloc(ctx, &d_bad, 1));
+    HIPCHK(hipMemset(d_bad, 0, sizeof(int)));
+    frg::launch_sym_check(ctx->d_bins, d_orbit, N, g.n_rad, g.n_ang, ctx->Trows, d_bad, nullptr);
+    int bad = -1;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost);
+    hipFree(d_orbit);
+    hipFree(d_bad);
+    ctx->ws_bytes -= sizeof(int32_t) * orbit.size() + sizeof(int);
+    if (e != hipSuccess) return fail(FRG_EDEVICE, std::string("symmetry check: ") + hipGetErrorString(e));
+    if (bad != 0) return FRG_OK;   // an exception to exact covariance: keep every row
+    TRY(upload(ctx, &ctx->d_rowlist, rowlist.data(), rowlist.size()));
+    TRY(upload(ctx, &ctx->d_colsym_pp, cs_pp.data(), cs_pp.size()));
+    TRY(upload(ctx, &ctx->d_colsym_ph, cs_ph.data(), cs_ph.size()));
+    ctx->n_rep_pp = npp;
+    ctx->n_rep_ph = nph;
+    ctx->sym_avail = true;
+    ctx->sym_on = std::getenv("FRG_NO_SYM") == nullptr;
+    return FRG_OK;
 }
 
 // prep + bubbles into the context's bubble tensor (or caller buffers)
 frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *state, double c,
-                       void *bpp, void *bph, hipStream_t s) {
+                       void *bpp, void *bph, hipStream_t s, bool reps_only = false) {
     {
         KTimer kt(ctx, FRG_K_PREP, s);
         frg::launch_point_prep(ctx->d_xi, ctx->d_w, ctx->g.np, T_host, state, c,
@@ -192,7 +286,13 @@ frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *sta
     }
     {
         KTimer kt(ctx, FRG_K_BUBBLES, s);
-        frg::launch_bubbles(bubble_args(ctx, split, bpp, bph), split, s);
+        frg::BubbleArgs ba = bubble_args(ctx, split, bpp, bph);
+        if (reps_only) {
+            ba.rowlist = ctx->d_rowlist;
+            ba.nrows = ctx->n_rep_pp + ctx->n_rep_ph;
+            ba.npp_out = ctx->n_rep_pp;
+        }
+        frg::launch_bubbles(ba, split, s);
     }
     HIPCHK(hipGetLastError());
     return FRG_OK;
@@ -228,10 +328,12 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     const int N = g.N;
     const size_t NN = static_cast<size_t>(N) * N;
     const int64_t n3 = ctx->n3;
+    const bool sym = ctx->sym_on;
+    const size_t npp_rows = sym ? static_cast<size_t>(ctx->n_rep_pp) : static_cast<size_t>(g.Tpp);
     void *bpp = split ? static_cast<void *>(ctx->d_B32) : static_cast<void *>(ctx->d_B64);
-    void *bph = split ? static_cast<void *>(ctx->d_B32 + NN * g.Tpp)
-                      : static_cast<void *>(ctx->d_B64 + NN * g.Tpp);
-    TRY(run_bubbles(ctx, split, T_host, state, c, bpp, bph, s));
+    void *bph = split ? static_cast<void *>(ctx->d_B32 + NN * npp_rows)
+                      : static_cast<void *>(ctx->d_B64 + NN * npp_rows);
+    TRY(run_bubbles(ctx, split, T_host, state, c, bpp, bph, s, sym));
     const int KS = ksplit(ctx);
     TRY(ensure_c(ctx, KS));
     double *Cpp = ctx->d_C, *Cc = ctx->d_C + KS * n3, *Cd = ctx->d_C + 2 * KS * n3;
@@ -242,8 +344,8 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     a.n3 = n3;
     a.B[frg::TERM_PP] = bpp;
     a.B[frg::TERM_PHC] = a.B[frg::TERM_PHD] = bph;
-    a.colrow[frg::TERM_PP] = ctx->d_colrow_pp;
-    a.colrow[frg::TERM_PHC] = a.colrow[frg::TERM_PHD] = ctx->d_colrow_ph;
+    a.colrow[frg::TERM_PP] = sym ? ctx->d_colsym_pp : ctx->d_colrow_pp;
+    a.colrow[frg::TERM_PHC] = a.colrow[frg::TERM_PHD] = sym ? ctx->d_colsym_ph : ctx->d_colrow_ph;
     a.C[frg::TERM_PP] = Cpp;
     a.C[frg::TERM_PHC] = Cc;
     a.C[frg::TERM_PHD] = Cd;
@@ -380,8 +482,8 @@ frg_status frg_create(const frg_params *p, frg_ctx *out) {
     std::vector<int32_t> cpp(static_cast<size_t>(g.N) * g.N), cph(static_cast<size_t>(g.N) * g.N);
     for (int y = 0; y < g.N; ++y)
         for (int x = 0; x < g.N; ++x) {
-            cpp[y * g.N + x] = g.row_pp[y * g.N + x];   // column (j1=y, j2=x)
-            cph[y * g.N + x] = g.row_ph[x * g.N + y];   // column (y, x): transfer k_x - k_y
+            cpp[y * g.N + x] = g.row_pp[y * g.N + x] << 3;   // column (j1=y, j2=x)
+            cph[y * g.N + x] = g.row_ph[x * g.N + y] << 3;   // column (y, x): transfer k_x - k_y
         }
     double *d_px = nullptr, *d_py = nullptr, *d_qrow = nullptr;
     frg_status st;
@@ -413,6 +515,7 @@ frg_status frg_create(const frg_params *p, frg_ctx *out) {
         g_err = std::string("second-line table: ") + hipGetErrorString(e);
         return bail(FRG_EDEVICE);
     }
+    if ((st = build_orbits(ctx))) return bail(st);
     *out = ctx;
     return FRG_OK;
 }
@@ -422,7 +525,8 @@ frg_status frg_destroy(frg_ctx ctx) {
     void *ptrs[] = {ctx->d_bnd, ctx->d_xi, ctx->d_w, ctx->d_trig_row, ctx->d_trig_pt, ctx->d_bins,
                     ctx->d_colrow_pp, ctx->d_colrow_ph, ctx->d_pa64, ctx->d_T, ctx->d_pa32,
                     ctx->d_B64, ctx->d_B32, ctx->d_perm, ctx->d_ahl, ctx->d_g32, ctx->d_C,
-                    ctx->d_yt, ctx->d_y5, ctx->d_partial, ctx->d_state};
+                    ctx->d_yt, ctx->d_y5, ctx->d_partial, ctx->d_state, ctx->d_rowlist,
+                    ctx->d_colsym_pp, ctx->d_colsym_ph};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (int j = 0; j < 7; ++j)
@@ -648,6 +752,21 @@ frg_status frg_flow(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_
     r->rhs_evals = static_cast<int32_t>(hs[FRG_ST_RHS]);
     r->first_step_rhs = static_cast<int32_t>(hs[FRG_ST_FIRST_RHS]);
     if (r->reason == FRG_STOP_NONFINITE) return fail(FRG_ENONFINITE, "flow state became non-finite");
+    return FRG_OK;
+}
+
+frg_status frg_set_symmetry(frg_ctx ctx, int32_t enable) {
+    TRY(check_ctx(ctx));
+    if (enable && !ctx->sym_avail)
+        return fail(FRG_ENOTSUP, "C4v row reduction unavailable (N % 8 != 0 or covariance check failed)");
+    ctx->sym_on = enable != 0;
+    return FRG_OK;
+}
+
+frg_status frg_symmetry(frg_ctx ctx, int32_t *active, int32_t *rows_computed) {
+    TRY(check_ctx(ctx));
+    if (active) *active = ctx->sym_on ? 1 : 0;
+    if (rows_computed) *rows_computed = ctx->sym_on ? ctx->n_rep_pp + ctx->n_rep_ph : ctx->Trows;
     return FRG_OK;
 }
 

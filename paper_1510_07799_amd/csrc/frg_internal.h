@@ -48,8 +48,18 @@ struct BubbleArgs {
     const float *pa32;             // [3][np]                      (split path)
     const double *Tdev;            // [0] = T
     void *Bpp, *Bph;               // outputs (double or float)
+    // rows to compute: output position o < nrows evaluates transfer row
+    // rowlist[o] (or o itself when rowlist == nullptr); positions below
+    // npp_out go to Bpp, the rest to Bph
+    int nrows, npp_out;
+    const int32_t *rowlist;
 };
 void launch_bubbles(const BubbleArgs &a, bool fp32, hipStream_t s);
+
+// verify B_{g t}(g a, g b) = B_t(a, b) on the second-line table: counts the
+// (row, point) entries where bins[t'][p'] != g(bins[rep(t')][g^-1 p'])
+void launch_sym_check(const uint8_t *bins, const int32_t *orbit, int N, int n_rad, int n_ang,
+                      int Trows, int *mismatch, hipStream_t s);
 
 // permuted copies of V used as contraction operands (FP64)
 void launch_layout_f64(const double *V, int N, double *perm, hipStream_t s);
@@ -63,6 +73,8 @@ struct FusedContractArgs {
     int N, KS, mtiles, ctiles;
     int64_t n3;
     const void *B[3];             // bubble rows per term (pp: Bpp, phc/phd: Bph)
+    // column c -> (stored row << 3) | o: the column's bubble row is the stored
+    // row acted on by C4v element o, B_col(a', b') = B_stored(o^-1 a', o^-1 b')
     const int32_t *colrow[3];
     const double *A64[3][2];
     const uint16_t *Ahl[3][2];

@@ -103,8 +103,9 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel(BubbleArgs A) {
 
     const int row0 = blockIdx.x * kRowsPerBlock;
     for (int rr = wave; rr < kRowsPerBlock; rr += 4) {
-        const int r = row0 + rr;
-        const bool active = r < A.Trows;
+        const int slot_out = row0 + rr;                 // output row position
+        const bool active = slot_out < A.nrows;
+        const int r = active ? (A.rowlist ? A.rowlist[slot_out] : slot_out) : 0;   // transfer row
         if (active)
             for (int b = lane; b < N; b += 64) bins[b] = 0.0;
         __syncthreads();
@@ -172,8 +173,8 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel(BubbleArgs A) {
         __syncthreads();
         if (active) {
             const size_t NN = static_cast<size_t>(N) * N;
-            const bool pp = r < A.Tpp;
-            const size_t base = (pp ? static_cast<size_t>(r) : static_cast<size_t>(r - A.Tpp)) * NN +
+            const bool pp = slot_out < A.npp_out;
+            const size_t base = (pp ? static_cast<size_t>(slot_out) : static_cast<size_t>(slot_out - A.npp_out)) * NN +
                                 static_cast<size_t>(a_patch) * N;
             void *outp = pp ? A.Bpp : A.Bph;
             if (outp) {
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel(BubbleArgs A) {
 
 template <int P>
 void launch_p(const BubbleArgs &a, bool fp32, hipStream_t s) {
-    dim3 grid((a.Trows + kRowsPerBlock - 1) / kRowsPerBlock, a.N);
+    dim3 grid((a.nrows + kRowsPerBlock - 1) / kRowsPerBlock, a.N);
     const size_t lds = sizeof(double) * (7 * P * 64 + 4 * a.N);
     if (fp32)
         hipLaunchKernelGGL((bubble_kernel<P, true>), grid, dim3(kThreads), lds, s, a);

@@ -61,6 +61,74 @@ struct Work {
     int term, mtile, ctile, ks;
 };
 
+// Where a column's bubble row comes from: the stored row `row`, read through
+// the inverse of C4v element o (identity for o = 0).  Patch j of the image
+// row reads patch map(j) of the stored row: rotations shift, reflections
+// reverse.
+struct RowMap {
+    int row;      // stored row
+    bool refl;    // inverse element is a reflection
+    int shR;      // rotation: shift; reflection: R with map(j) = R - j (mod N)
+    __device__ __forceinline__ int map(int j, int N) const {
+        const int v = refl ? shR - j : j + shR;
+        return v >= N ? v - N : (v < 0 ? v + N : v);
+    }
+};
+
+__device__ __forceinline__ RowMap decode_rowmap(int info, int N) {
+    RowMap r;
+    r.row = info >> 3;
+    const int o = info & 7;
+    const int oinv = (o & 1) ? o : ((8 - o) & 7);
+    const int q = N >> 2;
+    r.refl = (oinv & 1) != 0;
+    r.shR = r.refl ? ((oinv + 1) >> 1) * q - 1 : (oinv >> 1) * q;
+    if (r.shR >= N) r.shR -= N;
+    return r;
+}
+
+// ZK consecutive entries k = kb .. kb+ZK-1 of a column's bubble row
+// (k = a'*N + b'), gathered through the row map; VW-wide vector loads when the
+// source window is contiguous and aligned, scalar loads otherwise.
+template <int ZK, int VW, typename T, typename VT>
+__device__ __forceinline__ void load_bubble_window(const T *brow, const RowMap &rm, int N, int K,
+                                                   int kb, bool ok, T *out) {
+    if (!ok) {
+#pragma unroll
+        for (int q = 0; q < ZK; ++q) out[q] = T(0);
+        return;
+    }
+    const int a1 = kb / N, b1 = kb - a1 * N;
+    if (kb + ZK <= K && b1 + ZK <= N) {
+        const int a = rm.map(a1, N);
+        const int bt = rm.map(b1, N);
+        const int lo = rm.refl ? bt - (ZK - 1) : bt;
+        if (lo >= 0 && lo + ZK <= N && ((a * N + lo) % VW) == 0) {
+            const T *src = brow + a * N + lo;
+            T tmp[ZK];
+#pragma unroll
+            for (int q = 0; q < ZK; q += VW) {
+                const VT v = *reinterpret_cast<const VT *>(src + q);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) tmp[q + e] = v[e];
+            }
+#pragma unroll
+            for (int q = 0; q < ZK; ++q) out[q] = rm.refl ? tmp[ZK - 1 - q] : tmp[q];
+            return;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < ZK; ++q) {
+        const int k = kb + q;
+        if (k < K) {
+            const int aa = k / N, bb = k - aa * N;
+            out[q] = brow[rm.map(aa, N) * N + rm.map(bb, N)];
+        } else {
+            out[q] = T(0);
+        }
+    }
+}
+
 // block -> (term, m tile, c tile, K part); heaviest channel (phd) first
 __device__ __forceinline__ Work decode_block(const FusedContractArgs &P) {
     int id = blockIdx.x;
@@ -105,7 +173,8 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
     const int cl = tid >> 2, zk = (tid & 3) * ZK;
     const int c = c0 + cl;
     const bool cvalid = c < NC;
-    const double *brow = B + static_cast<int64_t>(cvalid ? colrow[c] : 0) * K;
+    const RowMap rm = decode_rowmap(cvalid ? colrow[c] : 0, N);
+    const double *brow = B + static_cast<int64_t>(rm.row) * K;
     const double *g0 = P.G64[TERM][0] + static_cast<int64_t>(cvalid ? c : 0) * N;
     const double *g1 = TERM == TERM_PHD ? P.G64[TERM][1] + static_cast<int64_t>(cvalid ? c / N : 0) * K
                                         : nullptr;
@@ -134,17 +203,7 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
             }
         }
         const int kb = k0 + zk;
-        if (cvalid && kb + ZK <= K) {
-#pragma unroll
-            for (int q = 0; q < ZK; q += 2) {
-                const d2_t v = *reinterpret_cast<const d2_t *>(brow + kb + q);
-                rb[q] = v[0];
-                rb[q + 1] = v[1];
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < ZK; ++q) rb[q] = (cvalid && kb + q < K) ? brow[kb + q] : 0.0;
-        }
+        load_bubble_window<ZK, 2, double, d2_t>(brow, rm, N, K, kb, cvalid, rb);
         int a = kb / N, b = kb - a * N;
 #pragma unroll
         for (int q = 0; q < ZK; ++q) {
@@ -248,7 +307,8 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     const int cl = tid >> 2, zk = (tid & 3) * ZK;   // Z loader: column cl, ZK consecutive k
     const int c = c0 + cl;
     const bool cvalid = c < NC;
-    const float *brow = B + static_cast<int64_t>(cvalid ? colrow[c] : 0) * K;
+    const RowMap rm = decode_rowmap(cvalid ? colrow[c] : 0, N);
+    const float *brow = B + static_cast<int64_t>(rm.row) * K;
     const float *g0 = P.G32[TERM][0] + static_cast<int64_t>(cvalid ? c : 0) * N;
     const float *g1 = TERM == TERM_PHD ? P.G32[TERM][1] + static_cast<int64_t>(cvalid ? c / N : 0) * K
                                        : nullptr;
@@ -280,16 +340,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
                     }
                 }
         const int kb = k0 + zk;
-        if (cvalid && kb + ZK <= K) {
-#pragma unroll
-            for (int q = 0; q < ZK; q += 4) {
-                const f4_t v = *reinterpret_cast<const f4_t *>(brow + kb + q);
-                rb[q] = v[0]; rb[q + 1] = v[1]; rb[q + 2] = v[2]; rb[q + 3] = v[3];
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < ZK; ++q) rb[q] = (cvalid && kb + q < K) ? brow[kb + q] : 0.f;
-        }
+        load_bubble_window<ZK, 4, float, f4_t>(brow, rm, N, K, kb, cvalid, rb);
         int a = kb / N, b = kb - a * N;
         if (TERM != TERM_PP && cvalid && b + ZK <= N && (b & 3) == 0 && (N & 3) == 0) {
 #pragma unroll

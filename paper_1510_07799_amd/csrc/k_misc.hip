@@ -63,6 +63,36 @@ __global__ void bins_kernel(const double *__restrict__ bnd, const double *__rest
     }
 }
 
+// image of patch j under C4v element o (o even: rotation by o/2 quarter
+// turns; o odd: reflection about the axis at (o+1) pi/8)
+__device__ __forceinline__ int c4v_patch(int o, int j, int N) {
+    const int q = N >> 2;
+    const int v = (o & 1) ? ((o + 1) >> 1) * q - 1 - j : j + (o >> 1) * q;
+    return ((v % N) + N) % N;
+}
+
+// orbit[t'] = (rep row << 3) | o with t' = o . rep
+__global__ void sym_check_kernel(const uint8_t *__restrict__ bins, const int32_t *__restrict__ orbit,
+                                 int N, int n_rad, int n_ang, int Trows, int *mismatch) {
+    const int nf = n_rad * n_ang, np = N * nf;
+    const int ip = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ip >= np) return;
+    const int a1 = ip / nf, loc = ip - a1 * nf;
+    const int s1 = loc / n_rad, m = loc - s1 * n_rad;
+    int bad = 0;
+    for (int t = blockIdx.y; t < Trows; t += gridDim.y) {
+        const int info = orbit[t];
+        const int rep = info >> 3, o = info & 7;
+        if (o == 0) continue;
+        const int oinv = (o & 1) ? o : ((8 - o) & 7);
+        const int a = c4v_patch(oinv, a1, N);
+        const int s = (o & 1) ? n_ang - 1 - s1 : s1;
+        const int b = bins[static_cast<size_t>(rep) * np + a * nf + s * n_rad + m];
+        if (bins[static_cast<size_t>(t) * np + ip] != c4v_patch(o, b, N)) ++bad;
+    }
+    if (bad) atomicAdd(mismatch, bad);
+}
+
 __device__ __forceinline__ double sech2_d(double x) {
     const double e = exp(-2.0 * fabs(x));
     const double d = 1.0 + e;
@@ -380,6 +410,14 @@ void launch_bins(const double *bnd, const double *px, const double *py, const do
     dim3 grid(blocks_for(np, 256), Trows < 65535 ? Trows : 65535);
     hipLaunchKernelGGL(bins_kernel, grid, dim3(256), 0, s, bnd, px, py, qrow, N, np, Tpp, Trows,
                        bins);
+}
+
+void launch_sym_check(const uint8_t *bins, const int32_t *orbit, int N, int n_rad, int n_ang,
+                      int Trows, int *mismatch, hipStream_t s) {
+    const int np = N * n_rad * n_ang;
+    dim3 grid(blocks_for(np, 256), Trows < 4096 ? Trows : 4096);
+    hipLaunchKernelGGL(sym_check_kernel, grid, dim3(256), 0, s, bins, orbit, N, n_rad, n_ang, Trows,
+                       mismatch);
 }
 
 void launch_point_prep(const double *xi, const double *w, int np, double T_host,

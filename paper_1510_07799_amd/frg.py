@@ -67,6 +67,8 @@ SIGNATURES = {
     "frg_flow_init": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, _P]),
     "frg_flow_step": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, _P]),
     "frg_flow": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, C.c_int32, C.POINTER(FlowResult), _P]),
+    "frg_set_symmetry": (C.c_int, [_P, C.c_int32]),
+    "frg_symmetry": (C.c_int, [_P, _IP, _IP]),
     "frg_profile_begin": (C.c_int, [_P]),
     "frg_profile_end": (C.c_int, [_P, _DP, _IP]),
     "frg_status_str": (C.c_char_p, [C.c_int]),
@@ -217,6 +219,15 @@ class Context:
 
     def flow_step(self, opts: FlowOpts, V, state):
         _check(lib().frg_flow_step(self._h, C.byref(opts), _ptr(V), _ptr(state), _stream()))
+
+    def set_symmetry(self, enable: bool):
+        _check(lib().frg_set_symmetry(self._h, 1 if enable else 0))
+
+    def symmetry(self):
+        """(active, bubble rows computed per rhs)."""
+        a, r = C.c_int32(), C.c_int32()
+        _check(lib().frg_symmetry(self._h, C.byref(a), C.byref(r)))
+        return bool(a.value), int(r.value)
 
     def profile_begin(self):
         _check(lib().frg_profile_begin(self._h))

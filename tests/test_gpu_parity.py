@@ -230,3 +230,33 @@ def test_flow_step_api_and_tmin_stop():
     assert st[frg.ST_S] == pytest.approx(math.log(0.2), abs=1e-15)
     assert int(st[frg.ST_ACCEPTED]) == ro["accepted"]
     assert nrel(V.cpu().numpy(), Vo) <= 1e-9
+
+
+@pytest.mark.parametrize("cfg", ["C1", SMALL_ODD, "C2"], ids=["C1", "odd", "C2"])
+def test_c4v_row_reduction_matches_full_rows(cfg):
+    """Bubble rows computed for one transfer per C4v orbit and read through the
+    patch permutation give the same rhs as computing every row."""
+    om, g = pair(cfg)
+    active, rows = g.symmetry()
+    assert active and rows < (g.Tpp + g.Tph) / 6
+    V = dev(I.random_vertex(om.N, om.U, seed=41, symmetrise=False))
+    for prec, tol in ((frg.PREC_FP64, 1e-10), (frg.PREC_SPLIT_BF16, 2e-4)):
+        Fs = g.rhs(0.04, V, prec).cpu().numpy()
+        g.set_symmetry(False)
+        try:
+            assert g.symmetry() == (False, g.Tpp + g.Tph)
+            Ff = g.rhs(0.04, V, prec).cpu().numpy()
+        finally:
+            g.set_symmetry(True)
+        ref = om.rhs(0.04, V.cpu().numpy())
+        assert nrel(Fs, ref) <= tol and nrel(Ff, ref) <= tol
+        if prec == frg.PREC_FP64:
+            assert nrel(Fs, Ff) <= 1e-12
+
+
+def test_c4v_reduction_unavailable_for_n_not_multiple_of_8():
+    om, g = pair(RAGGED)
+    assert g.symmetry() == (False, g.Tpp + g.Tph)
+    with pytest.raises(frg.FRGError) as e:
+        g.set_symmetry(True)
+    assert e.value.status == frg.ENOTSUP
