@@ -62,7 +62,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--legs", default="split,fp64", help="comma list of split,fp64")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes three times (calibrates "
+                         "the HBM byte counters of a profiler run) and exit")
     args = ap.parse_args()
+    if args.copy_calib:
+        import torch
+        n = args.copy_calib // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": 4 * n, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}); the multi-GPU "
               "layout is a design note only", file=sys.stderr)
@@ -156,8 +169,9 @@ def main():
     try:
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        if tr.get("source_hash") == kernel_source_hash() and dom in tr.get("kernels", {}):
-            traffic = tr["kernels"][dom]["bytes_per_launch"]
+        per_leg = tr.get("kernels", {}).get(leg_name, {})
+        if tr.get("source_hash") == kernel_source_hash() and dom in per_leg:
+            traffic = per_leg[dom]["bytes_per_launch"]
     except (OSError, ValueError):
         traffic = None
     roof["traffic"] = traffic
