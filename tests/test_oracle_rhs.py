@@ -6,7 +6,9 @@ seven rhs evaluations in the first step.  The pins: binning conserves the
 unbinned sum, exact symmetries, the second-order identity for constant V,
 brute force without bubble tensors, and textbook ODE cases.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -182,7 +184,8 @@ def test_dp54_riccati_accuracy_and_first_step():
     assert abs(y[0] - exact(3.0)) < 1e-8
     assert r["reason"] == O.STOP_TMIN and r["s_end"] == 3.0
     # seven rhs evaluations in the first step (FSAL), as the paper reports
-    assert r["first_step_rhs"] == 7
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_counts.json")))
+    assert r["first_step_rhs"] == golden["rhs_evals_first_step"]["value"] == 7
 
 
 def test_dp54_local_order_five():
