@@ -182,6 +182,39 @@ frg_status frg_flow_step(frg_ctx ctx, const frg_flow_opts *o, double *d_V, doubl
 frg_status frg_flow(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_log,
                     int32_t log_cap, frg_flow_result *r, void *stream);
 
+/* Batches of independent flows (different model parameters, uneven N, the
+ * same n_rad x n_ang).  Each flow keeps its own geometry and workspace; every
+ * kernel of an RK stage runs once for the whole batch from work lists of
+ * (flow, block).  The channel contraction of all flows is one launch per
+ * block-height class over a work list sorted by cost, largest flows first,
+ * which the hardware dispatcher deals out dynamically as compute units free up
+ * (the dynamic schedule of Alg. 2 moved onto the device); setting
+ * FRG_BATCH_DISPATCH=persistent uses persistent blocks pulling from per-XCD
+ * queues through device counters instead.  Flows that have stopped are
+ * skipped on the device.  Errors as for the single-flow calls. */
+typedef struct frg_batch_s *frg_batch;
+frg_status frg_batch_create(const frg_params *params, int32_t n_flows, frg_batch *out);
+frg_status frg_batch_destroy(frg_batch b);
+/* the context of flow i (owned by the batch; do not destroy) */
+frg_status frg_batch_context(frg_batch b, int32_t i, frg_ctx *out);
+/* F_i = dV_i/dT at T[i] (host array) for every flow; d_V, d_F: host arrays of
+ * device pointers.  Synchronises the batch's internal stream. */
+frg_status frg_batch_rhs(frg_batch b, const double *T, double *const *d_V, double *const *d_F,
+                         frg_precision prec, void *stream);
+/* DP5(4) flows of all members, one batched step (captured once in a hipGraph)
+ * at a time, until every flow stopped.  d_log (nullable): [n_flows][log_cap][8]
+ * as for frg_flow.  r: n_flows results. */
+frg_status frg_batch_flow(frg_batch b, const frg_flow_opts *o, double *const *d_V, double *d_log,
+                          int32_t log_cap, frg_flow_result *r, void *stream);
+/* The same in pieces: initialise every member (first stage included), then
+ * enqueue one batched step at a time (no synchronisation), then read the
+ * members' results (synchronises; all_stopped nullable).  The V buffers must
+ * stay valid until the flow is finished. */
+frg_status frg_batch_flow_init(frg_batch b, const frg_flow_opts *o, double *const *d_V, double *d_log,
+                               int32_t log_cap, void *stream);
+frg_status frg_batch_flow_step(frg_batch b, void *stream);
+frg_status frg_batch_results(frg_batch b, frg_flow_result *r, int32_t *all_stopped);
+
 /* C4v reduction of the bubble work (Sec. 4 counts independent couplings after
  * using the lattice symmetries): for N % 8 == 0 the grid is bitwise C4v
  * symmetric, B_{g t}(g a, g b) = B_t(a, b), and each rhs evaluates the bubble

@@ -423,6 +423,7 @@ int red_blocks(int64_t n) {
 }  // namespace
 
 static frg_status check_params(const frg_params *p);
+extern "C" frg_status frg_batch_destroy(frg_batch b);
 
 extern "C" {
 
@@ -796,6 +797,467 @@ frg_status frg_profile_end(frg_ctx ctx, double *ms, int32_t *counts) {
         if (ms) ms[k] = acc[k];
         if (counts) counts[k] = cnt[k];
     }
+    return FRG_OK;
+}
+
+}  // extern "C"
+
+// =====================================================================
+// Batches of independent flows (uneven N, different model parameters):
+// every kernel of an RK stage runs once for all flows, driven by work lists
+// of (flow, block); the contraction is one persistent launch over the
+// cost-sorted work of all flows.  A whole DP5(4) step is captured once in a
+// hipGraph and replayed.
+// =====================================================================
+struct frg_batch_s {
+    std::vector<frg_ctx> ctx;
+    int n = 0, nf = 0, maxN = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    frg::FlowArgs *d_fa = nullptr;
+    frg::BubbleArgs *d_ba = nullptr;
+    frg::FusedContractArgs *d_ca[3] = {nullptr, nullptr, nullptr};   // per source (V, yt, y5)
+    double **d_states = nullptr;
+    double *d_state_all = nullptr, *h_state_all = nullptr;
+    int2 *d_it_prep = nullptr, *d_it_bub = nullptr, *d_it_n3 = nullptr, *d_it_red = nullptr,
+         *d_it_con = nullptr;
+    int n_prep = 0, n_bub = 0, n_n3 = 0, n_red = 0, n_con = 0;
+    // contraction work list grouped by block height class (32, 64, 96), each cut
+    // into 8 per-XCD queues: d_q[class] = {start[8], count[8]}
+    int con_count[3] = {0, 0, 0};
+    int *d_q = nullptr;         // [3][16]
+    int *d_counter = nullptr;   // [3][8]
+    int2 *d_it_flat = nullptr;  // same items, per class in flow order (one block per item)
+    int flat_start[3] = {0, 0, 0};
+    // contraction dispatch: one block per work item in cost order (default), or
+    // persistent blocks pulling from per-XCD queues (FRG_BATCH_DISPATCH=persistent;
+    // measured 1.95x slower at N = 96)
+    bool persistent = false;
+    int persistent_grid = 1024;
+    int built_prec = -1;            // precision the device arrays describe
+    hipGraphExec_t exec = nullptr;
+    int exec_prec = -1;
+    double *d_log = nullptr;
+    int log_cap = 0;
+    frg_flow_opts opts{};
+    bool initialised = false;
+};
+
+namespace {
+
+frg_status batch_fail_free(frg_batch b);
+
+template <class T>
+frg_status bupload(T **p, const std::vector<T> &v) {
+    if (*p) { hipFree(*p); *p = nullptr; }
+    void *q = nullptr;
+    HIPCHK(hipMalloc(&q, sizeof(T) * (v.empty() ? 1 : v.size())));
+    *p = static_cast<T *>(q);
+    if (!v.empty()) HIPCHK(hipMemcpy(*p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return FRG_OK;
+}
+
+// per-flow descriptors for precision prec; V of flow f is Vs[f]
+frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
+    const bool split = prec == FRG_PREC_SPLIT_BF16;
+    std::vector<frg::FlowArgs> fa(b->n);
+    std::vector<frg::BubbleArgs> ba(b->n);
+    std::vector<frg::FusedContractArgs> ca[3];
+    for (int s = 0; s < 3; ++s) ca[s].resize(b->n);
+    std::vector<double *> st(b->n);
+    std::vector<int2> it_prep, it_bub, it_n3, it_red;
+    struct Item { int2 it; int cls, queue; double flow_cost, cost; };
+    std::vector<Item> con;
+    for (int f = 0; f < b->n; ++f) {
+        frg_ctx c = b->ctx[f];
+        const auto &g = c->g;
+        TRY(ensure_rhs_ws(c, prec));
+        TRY(ensure_flow_ws(c));
+        // the single-flow K split keeps concurrently running blocks of a flow on
+        // one K range of its operands (L2 reuse); the same buffer serves frg_flow_init
+        const int KS = ksplit(c);
+        TRY(ensure_c(c, KS));
+        const int64_t n3 = c->n3;
+        const size_t NN = static_cast<size_t>(g.N) * g.N;
+        const bool sym = c->sym_on;
+        const size_t npp_rows = sym ? static_cast<size_t>(c->n_rep_pp) : static_cast<size_t>(g.Tpp);
+        void *bpp = split ? static_cast<void *>(c->d_B32) : static_cast<void *>(c->d_B64);
+        void *bph = split ? static_cast<void *>(c->d_B32 + NN * npp_rows)
+                          : static_cast<void *>(c->d_B64 + NN * npp_rows);
+        frg::FlowArgs &A = fa[f];
+        std::memset(&A, 0, sizeof(A));
+        A.N = g.N; A.np = g.np; A.nred = red_blocks(n3); A.n3 = n3;
+        A.xi = c->d_xi; A.w = c->d_w; A.pa64 = c->d_pa64; A.pa32 = c->d_pa32; A.Tdev = c->d_T;
+        A.V = Vs[f]; A.state = b->d_state_all + static_cast<size_t>(f) * FRG_STATE_LEN;
+        for (int j = 0; j < 7; ++j) A.k[j] = c->d_k[j];
+        A.yt = c->d_yt; A.y5 = c->d_y5; A.partial = c->d_partial;
+        A.perm = c->d_perm; A.ahl = c->d_ahl; A.g32 = c->d_g32; A.C = c->d_C; A.KS = KS;
+        st[f] = A.state;
+        frg::BubbleArgs bb = bubble_args(c, split, bpp, bph);
+        if (sym) {
+            bb.rowlist = c->d_rowlist;
+            bb.nrows = c->n_rep_pp + c->n_rep_ph;
+            bb.npp_out = c->n_rep_pp;
+        }
+        ba[f] = bb;
+        const double *srcs[3] = {Vs[f], c->d_yt, c->d_y5};
+        for (int s = 0; s < 3; ++s) {
+            frg::FusedContractArgs &a = ca[s][f];
+            std::memset(&a, 0, sizeof(a));
+            const double *V = srcs[s];
+            a.N = g.N; a.KS = KS; a.n3 = n3;
+            const int bm = frg::contract_block_rows(g.N);
+            a.mtiles = (g.N + bm - 1) / bm;
+            a.ctiles = static_cast<int>((NN + 63) / 64);
+            a.B[frg::TERM_PP] = bpp;
+            a.B[frg::TERM_PHC] = a.B[frg::TERM_PHD] = bph;
+            a.colrow[frg::TERM_PP] = sym ? c->d_colsym_pp : c->d_colrow_pp;
+            a.colrow[frg::TERM_PHC] = a.colrow[frg::TERM_PHD] = sym ? c->d_colsym_ph : c->d_colrow_ph;
+            a.C[frg::TERM_PP] = c->d_C;
+            a.C[frg::TERM_PHC] = c->d_C + KS * n3;
+            a.C[frg::TERM_PHD] = c->d_C + 2 * KS * n3;
+            if (!split) {
+                const double *P = c->d_perm;
+                a.A64[frg::TERM_PP][0] = P;          a.G64[frg::TERM_PP][0] = V;
+                a.A64[frg::TERM_PHC][0] = V;         a.G64[frg::TERM_PHC][0] = P + n3;
+                a.A64[frg::TERM_PHD][0] = P + 2 * n3; a.G64[frg::TERM_PHD][0] = P + 4 * n3;
+                a.A64[frg::TERM_PHD][1] = P + 3 * n3; a.G64[frg::TERM_PHD][1] = P + 4 * n3;
+            } else {
+                const uint16_t *H = c->d_ahl;
+                const float *G = c->d_g32;
+                a.Ahl[frg::TERM_PP][0] = H;          a.G32[frg::TERM_PP][0] = G;
+                a.Ahl[frg::TERM_PHC][0] = H + 2 * n3; a.G32[frg::TERM_PHC][0] = G + n3;
+                a.Ahl[frg::TERM_PHD][0] = H + 4 * n3; a.G32[frg::TERM_PHD][0] = G + 2 * n3;
+                a.Ahl[frg::TERM_PHD][1] = H + 6 * n3; a.G32[frg::TERM_PHD][1] = G + 2 * n3;
+            }
+        }
+        for (int k = 0; k < (g.np + 255) / 256; ++k) it_prep.push_back(make_int2(f, k));
+        const int rpb = frg::bubble_rows_per_block();
+        const int chunks = (bb.nrows + rpb - 1) / rpb;
+        for (int ch = 0; ch < chunks; ++ch)
+            for (int a = 0; a < g.N; ++a) it_bub.push_back(make_int2(f, (ch << 8) | a));
+        for (int64_t k = 0; k < (n3 + 255) / 256; ++k) it_n3.push_back(make_int2(f, static_cast<int>(k)));
+        for (int k = 0; k < A.nred; ++k) it_red.push_back(make_int2(f, k));
+        const frg::FusedContractArgs &a0 = ca[0][f];
+        const int per_term = a0.mtiles * a0.ctiles * KS;
+        const double kwork = static_cast<double>(NN) / KS * frg::contract_block_rows(g.N);
+        const double fcost = 4.0 * per_term * kwork;   // whole flow
+        const int bm = frg::contract_block_rows(g.N);
+        const int cls = bm == 32 ? 0 : (bm == 64 ? 1 : 2);
+        // K part ks of this flow is served by the XCDs q with q * KS / 8 == ks
+        std::vector<int> rr(KS, 0);
+        for (int id = 0; id < 3 * per_term; ++id) {
+            const double np_ = (id / per_term == 0) ? 2.0 : 1.0;   // phd first, two products
+            const int ks = id % KS;
+            int q;
+            if (KS >= 8) {
+                q = ks % 8;
+            } else {
+                const int lo = (ks * 8 + KS - 1) / KS, hi = ((ks + 1) * 8 + KS - 1) / KS;  // [lo, hi)
+                q = lo + (rr[ks]++ % std::max(1, hi - lo));
+            }
+            con.push_back({make_int2(f, id), cls, q, fcost, np_ * kwork});
+        }
+    }
+    // largest flows first; within a flow its own order (heaviest channel first), so
+    // the blocks running together share one flow's operands
+    std::stable_sort(con.begin(), con.end(), [](const Item &x, const Item &y) {
+        if (x.cls != y.cls) return x.cls > y.cls;
+        if (x.queue != y.queue) return x.queue < y.queue;
+        if (x.flow_cost != y.flow_cost) return x.flow_cost > y.flow_cost;
+        if (x.it.x != y.it.x) return x.it.x < y.it.x;
+        return x.cost > y.cost;
+    });
+    std::vector<int2> it_con(con.size());
+    std::vector<int> qtab(3 * 16, 0);
+    for (int k = 0; k < 3; ++k) b->con_count[k] = 0;
+    for (size_t i = 0; i < con.size(); ++i) {
+        it_con[i] = con[i].it;
+        const int k = con[i].cls, q = con[i].queue;
+        b->con_count[k]++;
+        if (qtab[k * 16 + 8 + q]++ == 0) qtab[k * 16 + q] = static_cast<int>(i);
+    }
+    TRY(bupload(&b->d_q, qtab));
+    {
+        std::vector<Item> flat = con;
+        std::stable_sort(flat.begin(), flat.end(), [](const Item &x, const Item &y) {
+            if (x.cls != y.cls) return x.cls > y.cls;
+            if (x.flow_cost != y.flow_cost) return x.flow_cost > y.flow_cost;
+            if (x.it.x != y.it.x) return x.it.x < y.it.x;
+            return x.it.y < y.it.y;
+        });
+        std::vector<int2> fl(flat.size());
+        int seen[3] = {0, 0, 0};
+        for (size_t i = 0; i < flat.size(); ++i) {
+            fl[i] = flat[i].it;
+            if (seen[flat[i].cls]++ == 0) b->flat_start[flat[i].cls] = static_cast<int>(i);
+        }
+        TRY(bupload(&b->d_it_flat, fl));
+    }
+    TRY(bupload(&b->d_fa, fa));
+    TRY(bupload(&b->d_ba, ba));
+    for (int s = 0; s < 3; ++s) TRY(bupload(&b->d_ca[s], ca[s]));
+    TRY(bupload(&b->d_states, st));
+    TRY(bupload(&b->d_it_prep, it_prep));
+    TRY(bupload(&b->d_it_bub, it_bub));
+    TRY(bupload(&b->d_it_n3, it_n3));
+    TRY(bupload(&b->d_it_red, it_red));
+    TRY(bupload(&b->d_it_con, it_con));
+    b->n_prep = static_cast<int>(it_prep.size());
+    b->n_bub = static_cast<int>(it_bub.size());
+    b->n_n3 = static_cast<int>(it_n3.size());
+    b->n_red = static_cast<int>(it_red.size());
+    b->n_con = static_cast<int>(it_con.size());
+    b->built_prec = prec;
+    if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; b->exec_prec = -1; }
+    return FRG_OK;
+}
+
+// rhs of every flow: input src (V, yt or y5), result T*F into k[stage]
+void batch_rhs_launch(frg_batch b, bool split, double c_stage, int src, int stage, hipStream_t s) {
+    const double *const *states = b->d_states;
+    frg::launch_prep_b(b->d_fa, b->d_it_prep, b->n_prep, c_stage, split, s);
+    frg::launch_bubbles_batched(b->d_ba, b->d_it_bub, b->n_bub, states, b->nf, b->maxN, split, s);
+    frg::launch_layout_b(b->d_fa, b->d_it_n3, b->n_n3, src, split, s);
+    const int bms[3] = {32, 64, 96};
+    for (int k = 2; k >= 0; --k) {
+        if (!b->con_count[k]) continue;
+        if (!b->persistent) {
+            frg::launch_contract_items(b->d_ca[src], b->d_it_flat + b->flat_start[k], b->con_count[k], states,
+                                       bms[k], split, s);
+            continue;
+        }
+        const int grid = std::min(std::max(8, b->con_count[k]), b->persistent_grid);
+        frg::launch_contract_persistent(b->d_ca[src], b->d_it_con, b->d_q + k * 16, b->d_q + k * 16 + 8,
+                                        b->d_counter + 8 * k, states, grid, bms[k], split, s);
+    }
+    frg::launch_combine_b(b->d_fa, b->d_it_n3, b->n_n3, stage, s);
+}
+
+void batch_step_launch(frg_batch b, const frg_flow_opts *o, hipStream_t s) {
+    const bool split = o->prec == FRG_PREC_SPLIT_BF16;
+    frg::launch_step_ctl_b(b->d_fa, b->n, 1, nullptr, 0, o->vmax, o->max_steps, s);
+    for (int st = 1; st < 7; ++st) {
+        double coef[7] = {0};
+        for (int j = 0; j < st; ++j) coef[j] = DP_A[st][j];
+        const int dst = st == 6 ? frg::SRC_Y5 : frg::SRC_YT;
+        frg::launch_rk_stage_b(b->d_fa, b->d_it_n3, b->n_n3, coef, st, dst, s);
+        batch_rhs_launch(b, split, DP_C[st], dst, st, s);
+    }
+    frg::launch_dp_error_b(b->d_fa, b->d_it_red, b->n_red, b->n, DP_E, o->rtol, o->atol, s);
+    frg::launch_step_ctl_b(b->d_fa, b->n, 2, b->d_log, b->log_cap, o->vmax, o->max_steps, s);
+    frg::launch_accept_b(b->d_fa, b->d_it_n3, b->n_n3, s);
+}
+
+frg_status batch_fail_free(frg_batch b) {
+    std::string m = g_err;
+    frg_batch_destroy(b);
+    g_err = m;
+    return FRG_EINVAL;
+}
+
+}  // namespace
+
+extern "C" {
+
+frg_status frg_batch_create(const frg_params *params, int32_t n_flows, frg_batch *out) {
+    if (!out || !params || n_flows < 1) return fail(FRG_EINVAL, "need params[n_flows] with n_flows >= 1");
+    *out = nullptr;
+    for (int f = 0; f < n_flows; ++f) {
+        TRY(check_params(&params[f]));
+        if (params[f].n_rad != params[0].n_rad || params[f].n_ang != params[0].n_ang)
+            return fail(FRG_EINVAL, "all flows of a batch must have the same n_rad and n_ang");
+    }
+    frg_batch b = new frg_batch_s();
+    b->n = n_flows;
+    if (const char *d = std::getenv("FRG_BATCH_DISPATCH")) b->persistent = std::strcmp(d, "persistent") == 0;
+    b->nf = params[0].n_rad * params[0].n_ang;
+    for (int f = 0; f < n_flows; ++f) {
+        frg_ctx c = nullptr;
+        frg_status st = frg_create(&params[f], &c);
+        if (st) { std::string m = g_err; frg_batch_destroy(b); g_err = m; return st; }
+        b->ctx.push_back(c);
+        b->maxN = std::max(b->maxN, params[f].N);
+    }
+    hipError_t e = hipStreamCreate(&b->stream);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&b->d_counter), 24 * sizeof(int));
+    if (e == hipSuccess)
+        e = hipMalloc(reinterpret_cast<void **>(&b->d_state_all), sizeof(double) * FRG_STATE_LEN * n_flows);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&b->h_state_all), sizeof(double) * FRG_STATE_LEN * n_flows,
+                          hipHostMallocDefault);
+    if (e == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, b->ctx[0]->device) == hipSuccess)
+            b->persistent_grid = 4 * prop.multiProcessorCount;
+    }
+    if (e != hipSuccess) {
+        g_err = std::string("batch setup: ") + hipGetErrorString(e);
+        frg_batch_destroy(b);
+        return FRG_EDEVICE;
+    }
+    *out = b;
+    return FRG_OK;
+}
+
+frg_status frg_batch_destroy(frg_batch b) {
+    if (!b) return FRG_OK;
+    for (frg_ctx c : b->ctx) frg_destroy(c);
+    void *ptrs[] = {b->d_fa, b->d_ba, b->d_ca[0], b->d_ca[1], b->d_ca[2], b->d_states, b->d_state_all,
+                    b->d_it_prep, b->d_it_bub, b->d_it_n3, b->d_it_red, b->d_it_con, b->d_counter,
+                    b->d_q, b->d_it_flat};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    if (b->h_state_all) hipHostFree(b->h_state_all);
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->ev_in) hipEventDestroy(b->ev_in);
+    if (b->ev_out) hipEventDestroy(b->ev_out);
+    if (b->stream) hipStreamDestroy(b->stream);
+    delete b;
+    return FRG_OK;
+}
+
+frg_status frg_batch_context(frg_batch b, int32_t i, frg_ctx *out) {
+    if (!b || !out || i < 0 || i >= b->n) return fail(FRG_EINVAL, "bad batch or flow index");
+    *out = b->ctx[i];
+    return FRG_OK;
+}
+
+frg_status frg_batch_flow_init(frg_batch b, const frg_flow_opts *o, double *const *d_V, double *d_log,
+                               int32_t log_cap, void *stream) {
+    if (!b) return fail(FRG_EINVAL, "null batch");
+    TRY(check_opts(b->ctx[0], o));
+    if (o->stepper != FRG_DP54) return fail(FRG_ENOTSUP, "batched flows use DP54");
+    if (!d_V) return fail(FRG_EINVAL, "null V array");
+    if (log_cap < 0 || (log_cap > 0 && !d_log)) return fail(FRG_EINVAL, "bad log buffer");
+    for (int f = 0; f < b->n; ++f)
+        if (!d_V[f] || !aligned8(d_V[f])) return fail(FRG_EINVAL, "null or misaligned V");
+    hipStream_t cs = static_cast<hipStream_t>(stream);
+    hipStream_t s = b->stream;
+    HIPCHK(hipEventRecord(b->ev_in, cs));
+    HIPCHK(hipStreamWaitEvent(s, b->ev_in, 0));
+    b->d_log = d_log;
+    b->log_cap = log_cap;
+    b->opts = *o;
+    TRY(batch_build(b, o->prec, d_V));
+    for (int f = 0; f < b->n; ++f)
+        TRY(frg_flow_init(b->ctx[f], o, d_V[f], b->d_state_all + static_cast<size_t>(f) * FRG_STATE_LEN, s));
+    HIPCHK(hipEventRecord(b->ev_out, s));
+    HIPCHK(hipStreamWaitEvent(cs, b->ev_out, 0));
+    b->initialised = true;
+    return FRG_OK;
+}
+
+frg_status frg_batch_flow_step(frg_batch b, void *stream) {
+    if (!b || !b->initialised) return fail(FRG_EINVAL, "batch flow not initialised");
+    hipStream_t cs = static_cast<hipStream_t>(stream);
+    hipStream_t s = b->stream;
+    HIPCHK(hipEventRecord(b->ev_in, cs));
+    HIPCHK(hipStreamWaitEvent(s, b->ev_in, 0));
+    if (std::getenv("FRG_NO_GRAPH") == nullptr) {
+        if (!b->exec) {
+            hipGraph_t graph = nullptr;
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            batch_step_launch(b, &b->opts, s);
+            HIPCHK(hipStreamEndCapture(s, &graph));
+            hipError_t e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) return fail(FRG_EDEVICE, std::string("graph: ") + hipGetErrorString(e));
+        }
+        HIPCHK(hipGraphLaunch(b->exec, s));
+    } else {
+        batch_step_launch(b, &b->opts, s);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(b->ev_out, s));
+    HIPCHK(hipStreamWaitEvent(cs, b->ev_out, 0));
+    return FRG_OK;
+}
+
+frg_status frg_batch_results(frg_batch b, frg_flow_result *r, int32_t *all_stopped) {
+    if (!b || !r) return fail(FRG_EINVAL, "null argument");
+    HIPCHK(hipMemcpyAsync(b->h_state_all, b->d_state_all, sizeof(double) * FRG_STATE_LEN * b->n,
+                          hipMemcpyDeviceToHost, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    frg_status ret = FRG_OK;
+    bool all = true;
+    for (int f = 0; f < b->n; ++f) {
+        const double *h = b->h_state_all + f * FRG_STATE_LEN;
+        frg_flow_result &R = r[f];
+        std::memset(&R, 0, sizeof(R));
+        R.reason = static_cast<frg_stop>(static_cast<int>(h[FRG_ST_REASON]));
+        R.T_end = std::exp(h[FRG_ST_S]);
+        R.T_c = std::exp(h[FRG_ST_SC]);
+        R.T_c_interp = std::exp(h[FRG_ST_SC_INTERP]);
+        R.accepted = static_cast<int32_t>(h[FRG_ST_ACCEPTED]);
+        R.rejected = static_cast<int32_t>(h[FRG_ST_REJECTED]);
+        R.rhs_evals = static_cast<int32_t>(h[FRG_ST_RHS]);
+        R.first_step_rhs = static_cast<int32_t>(h[FRG_ST_FIRST_RHS]);
+        if (R.reason == FRG_STOP_NONFINITE) ret = FRG_ENONFINITE;
+        all = all && R.reason != FRG_STOP_NONE;
+    }
+    if (all_stopped) *all_stopped = all ? 1 : 0;
+    if (ret) return fail(ret, "a flow of the batch became non-finite");
+    return FRG_OK;
+}
+
+frg_status frg_batch_flow(frg_batch b, const frg_flow_opts *o, double *const *d_V, double *d_log,
+                          int32_t log_cap, frg_flow_result *r, void *stream) {
+    if (!r) return fail(FRG_EINVAL, "null results");
+    TRY(frg_batch_flow_init(b, o, d_V, d_log, log_cap, stream));
+    const int cap = o->max_steps > 0 ? 4 * o->max_steps + 64 : 1000000;
+    frg_status st = FRG_OK;
+    for (int it = 0; it < cap; ++it) {
+        TRY(frg_batch_flow_step(b, stream));
+        int32_t all = 0;
+        st = frg_batch_results(b, r, &all);
+        if (st != FRG_OK || all) break;
+    }
+    // the captured step bakes in the options and the log buffer: re-capture next time
+    if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+    b->initialised = false;
+    return st;
+}
+
+frg_status frg_batch_rhs(frg_batch b, const double *T, double *const *d_V, double *const *d_F,
+                         frg_precision prec, void *stream) {
+    if (!b) return fail(FRG_EINVAL, "null batch");
+    TRY(check_prec(prec));
+    if (!T || !d_V || !d_F) return fail(FRG_EINVAL, "null argument");
+    for (int f = 0; f < b->n; ++f) {
+        if (!(T[f] > 0.0) || !std::isfinite(T[f])) return fail(FRG_EINVAL, "T must be finite and > 0");
+        if (!d_V[f] || !d_F[f] || !aligned8(d_V[f]) || !aligned8(d_F[f]))
+            return fail(FRG_EINVAL, "null or misaligned V/F");
+        const size_t bytes = sizeof(double) * static_cast<size_t>(b->ctx[f]->n3);
+        if (overlap(d_V[f], bytes, d_F[f], bytes)) return fail(FRG_EINVAL, "V and F overlap");
+    }
+    hipStream_t cs = static_cast<hipStream_t>(stream);
+    hipStream_t s = b->stream;
+    HIPCHK(hipEventRecord(b->ev_in, cs));
+    HIPCHK(hipStreamWaitEvent(s, b->ev_in, 0));
+    TRY(batch_build(b, prec, d_V));
+    // per-flow state: s = ln T, h = 0, running; the result goes to k[0], then to F
+    for (int f = 0; f < b->n; ++f) {
+        double *h = b->h_state_all + f * FRG_STATE_LEN;
+        for (int i = 0; i < FRG_STATE_LEN; ++i) h[i] = 0.0;
+        h[FRG_ST_S] = std::log(T[f]);
+    }
+    HIPCHK(hipMemcpyAsync(b->d_state_all, b->h_state_all, sizeof(double) * FRG_STATE_LEN * b->n,
+                          hipMemcpyHostToDevice, s));
+    batch_rhs_launch(b, prec == FRG_PREC_SPLIT_BF16, 0.0, frg::SRC_V, 0, s);
+    for (int f = 0; f < b->n; ++f) {
+        frg_ctx c = b->ctx[f];
+        // F from the channel partials (the batched combine left T*F in k[0])
+        const int KS = ksplit(c);
+        frg::launch_combine(c->d_C, c->d_C + KS * c->n3, c->d_C + 2 * KS * c->n3, c->n3, KS, c->d_T, 0,
+                            d_F[f], s);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(b->ev_out, s));
+    HIPCHK(hipStreamWaitEvent(cs, b->ev_out, 0));
+    HIPCHK(hipStreamSynchronize(s));
     return FRG_OK;
 }
 

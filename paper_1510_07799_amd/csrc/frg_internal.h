@@ -114,4 +114,47 @@ void launch_accept_copy(int64_t n, const double *state, const double *src, doubl
                         hipStream_t s);
 void launch_state_init(double *state, double s0, double h, double s_min, hipStream_t s);
 
+// ----------------------------------------------------------------- batches
+// Per-flow pointers used by the batched launches (one entry per flow, in
+// device memory); work lists are arrays of (flow, local block).
+struct FlowArgs {
+    int N, np, nred;
+    int64_t n3;
+    const double *xi, *w;
+    double *pa64;
+    float *pa32;
+    double *Tdev;
+    double *V, *state;
+    double *k[7];
+    double *yt, *y5, *partial;
+    double *perm;
+    uint16_t *ahl;
+    float *g32;
+    double *C;   // [3][KS][n3]
+    int KS;
+};
+enum { SRC_V = 0, SRC_YT = 1, SRC_Y5 = 2 };
+
+int bubble_rows_per_block();
+void launch_bubbles_batched(const BubbleArgs *args, const int2 *items, int nitems,
+                            const double *const *states, int nf, int maxN, bool fp32, hipStream_t s);
+size_t contract_lds_bytes(bool split);
+void launch_contract_items(const FusedContractArgs *args, const int2 *items, int nitems,
+                           const double *const *states, int bm, bool split, hipStream_t s);
+void launch_contract_persistent(const FusedContractArgs *args, const int2 *items, const int *qstart,
+                                const int *qcount, int *counters, const double *const *states, int grid,
+                                int bm, bool split, hipStream_t s);
+void launch_prep_b(const FlowArgs *fa, const int2 *items, int nitems, double c_stage, bool split,
+                   hipStream_t s);
+void launch_layout_b(const FlowArgs *fa, const int2 *items, int nitems, int src, bool split,
+                     hipStream_t s);
+void launch_combine_b(const FlowArgs *fa, const int2 *items, int nitems, int stage, hipStream_t s);
+void launch_rk_stage_b(const FlowArgs *fa, const int2 *items, int nitems, const double coef[7],
+                       int nk, int dst, hipStream_t s);
+void launch_dp_error_b(const FlowArgs *fa, const int2 *items, int nitems, int nflows,
+                       const double e[7], double rtol, double atol, hipStream_t s);
+void launch_step_ctl_b(const FlowArgs *fa, int nflows, int phase, double *log_base, int log_cap,
+                       double vmax, int max_steps, hipStream_t s);
+void launch_accept_b(const FlowArgs *fa, const int2 *items, int nitems, hipStream_t s);
+
 }  // namespace frg

@@ -66,12 +66,10 @@ __device__ __forceinline__ float div_h32(float a, float ha, float b) {
 }
 
 template <int P, bool F32>
-__global__ __launch_bounds__(kThreads) void bubble_kernel(BubbleArgs A) {
-    extern __shared__ double smem[];
+__device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int a_patch, double *smem) {
     constexpr int S = P * 64;          // slots per array
     double *pt = smem;                 // [7][S]: cpx spx cpy spy a ha wf
     const int N = A.N, nf = A.nf, np = A.np;
-    const int a_patch = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *bins = smem + 7 * S + wave * N;
 
@@ -101,7 +99,7 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel(BubbleArgs A) {
     const double mt2 = A.mt2, mt4p = A.mt4p, mu = A.mu;
     __syncthreads();
 
-    const int row0 = blockIdx.x * kRowsPerBlock;
+    const int row0 = chunk * kRowsPerBlock;
     for (int rr = wave; rr < kRowsPerBlock; rr += 4) {
         const int slot_out = row0 + rr;                 // output row position
         const bool active = slot_out < A.nrows;
@@ -188,6 +186,24 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel(BubbleArgs A) {
     }
 }
 
+template <int P, bool F32>
+__global__ __launch_bounds__(kThreads) void bubble_kernel(BubbleArgs A) {
+    extern __shared__ double smem[];
+    bubble_body<P, F32>(A, blockIdx.x, blockIdx.y, smem);
+}
+
+// batched: item = (flow, chunk << 8 | patch); skips flows whose state says stop
+template <int P, bool F32>
+__global__ __launch_bounds__(kThreads) void bubble_kernel_batched(const BubbleArgs *__restrict__ args,
+                                                                  const int2 *__restrict__ items,
+                                                                  const double *const *__restrict__ states) {
+    extern __shared__ double smem[];
+    const int2 it = items[blockIdx.x];
+    if (states && states[it.x][FRG_ST_REASON] != 0.0) return;
+    const BubbleArgs A = args[it.x];
+    bubble_body<P, F32>(A, it.y >> 8, it.y & 255, smem);
+}
+
 template <int P>
 void launch_p(const BubbleArgs &a, bool fp32, hipStream_t s) {
     dim3 grid((a.nrows + kRowsPerBlock - 1) / kRowsPerBlock, a.N);
@@ -198,7 +214,31 @@ void launch_p(const BubbleArgs &a, bool fp32, hipStream_t s) {
         hipLaunchKernelGGL((bubble_kernel<P, false>), grid, dim3(kThreads), lds, s, a);
 }
 
+template <int P>
+void launch_pb(const BubbleArgs *args, const int2 *items, int nitems, const double *const *states,
+               int maxN, bool fp32, hipStream_t s) {
+    const size_t lds = sizeof(double) * (7 * P * 64 + 4 * maxN);
+    if (fp32)
+        hipLaunchKernelGGL((bubble_kernel_batched<P, true>), dim3(nitems), dim3(kThreads), lds, s, args,
+                           items, states);
+    else
+        hipLaunchKernelGGL((bubble_kernel_batched<P, false>), dim3(nitems), dim3(kThreads), lds, s, args,
+                           items, states);
+}
+
 }  // namespace
+
+int bubble_rows_per_block() { return kRowsPerBlock; }
+
+void launch_bubbles_batched(const BubbleArgs *args, const int2 *items, int nitems,
+                            const double *const *states, int nf, int maxN, bool fp32, hipStream_t s) {
+    const int P = (nf + 63) / 64;
+    if (P <= 1) launch_pb<1>(args, items, nitems, states, maxN, fp32, s);
+    else if (P <= 2) launch_pb<2>(args, items, nitems, states, maxN, fp32, s);
+    else if (P <= 4) launch_pb<4>(args, items, nitems, states, maxN, fp32, s);
+    else if (P <= 8) launch_pb<8>(args, items, nitems, states, maxN, fp32, s);
+    else launch_pb<16>(args, items, nitems, states, maxN, fp32, s);
+}
 
 void launch_bubbles(const BubbleArgs &a, bool fp32, hipStream_t s) {
     const int P = (a.nf + 63) / 64;

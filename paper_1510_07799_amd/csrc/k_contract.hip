@@ -37,6 +37,20 @@ typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int BC = 64;         // output columns (c) per block
+
+// Pointers read from a descriptor in memory are generic to the compiler, which
+// then emits FLAT accesses (they share the LDS wait counter and serialise the
+// prefetch against the operand reads); every operand is in global memory, so
+// say so.
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ const GLOBAL_AS T *gload_ptr(const T *p) {
+    return reinterpret_cast<const GLOBAL_AS T *>(reinterpret_cast<uintptr_t>(p));
+}
+template <class T>
+__device__ __forceinline__ GLOBAL_AS T *gstore_ptr(T *p) {
+    return reinterpret_cast<GLOBAL_AS T *>(reinterpret_cast<uintptr_t>(p));
+}
 constexpr int kThreads = 256;
 
 // output index of C[m, c] in the F layout of the term
@@ -60,6 +74,8 @@ __device__ __forceinline__ float bf16_to_f(uint16_t h) {
 struct Work {
     int term, mtile, ctile, ks;
 };
+
+__host__ __device__ __forceinline__ int block_rows_of(int N) { return N <= 32 ? 32 : (N <= 64 ? 64 : 96); }
 
 // Where a column's bubble row comes from: the stored row `row`, read through
 // the inverse of C4v element o (identity for o = 0).  Patch j of the image
@@ -91,7 +107,7 @@ __device__ __forceinline__ RowMap decode_rowmap(int info, int N) {
 // (k = a'*N + b'), gathered through the row map; VW-wide vector loads when the
 // source window is contiguous and aligned, scalar loads otherwise.
 template <int ZK, int VW, typename T, typename VT>
-__device__ __forceinline__ void load_bubble_window(const T *brow, const RowMap &rm, int N, int K,
+__device__ __forceinline__ void load_bubble_window(const GLOBAL_AS T *brow, const RowMap &rm, int N, int K,
                                                    int kb, bool ok, T *out) {
     if (!ok) {
 #pragma unroll
@@ -104,11 +120,11 @@ __device__ __forceinline__ void load_bubble_window(const T *brow, const RowMap &
         const int bt = rm.map(b1, N);
         const int lo = rm.refl ? bt - (ZK - 1) : bt;
         if (lo >= 0 && lo + ZK <= N && ((a * N + lo) % VW) == 0) {
-            const T *src = brow + a * N + lo;
+            const GLOBAL_AS T *src = brow + a * N + lo;
             T tmp[ZK];
 #pragma unroll
             for (int q = 0; q < ZK; q += VW) {
-                const VT v = *reinterpret_cast<const VT *>(src + q);
+                const VT v = *reinterpret_cast<const GLOBAL_AS VT *>(src + q);
 #pragma unroll
                 for (int e = 0; e < VW; ++e) tmp[q + e] = v[e];
             }
@@ -130,8 +146,7 @@ __device__ __forceinline__ void load_bubble_window(const T *brow, const RowMap &
 }
 
 // block -> (term, m tile, c tile, K part); heaviest channel (phd) first
-__device__ __forceinline__ Work decode_block(const FusedContractArgs &P) {
-    int id = blockIdx.x;
+__device__ __forceinline__ Work decode_block(const FusedContractArgs &P, int id) {
     const int per_term = P.mtiles * P.ctiles * P.KS;
     Work w;
     const int order[3] = {TERM_PHD, TERM_PHC, TERM_PP};
@@ -164,20 +179,21 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
     const int kc_lo = static_cast<int>((static_cast<int64_t>(kchunks) * w.ks) / P.KS);
     const int kc_hi = static_cast<int>((static_cast<int64_t>(kchunks) * (w.ks + 1)) / P.KS);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const double *A0 = P.A64[TERM][0];
-    const double *A1 = P.A64[TERM][1];
-    const double *B = static_cast<const double *>(P.B[TERM]);
-    const int32_t *colrow = P.colrow[TERM];
+    const GLOBAL_AS double *A0 = gload_ptr(P.A64[TERM][0]);
+    const GLOBAL_AS double *A1 = gload_ptr(P.A64[TERM][1]);
+    const GLOBAL_AS double *B = gload_ptr(static_cast<const double *>(P.B[TERM]));
+    const GLOBAL_AS int32_t *colrow = gload_ptr(P.colrow[TERM]);
 
     // Z loader: column cl, ZK consecutive k
     const int cl = tid >> 2, zk = (tid & 3) * ZK;
     const int c = c0 + cl;
     const bool cvalid = c < NC;
     const RowMap rm = decode_rowmap(cvalid ? colrow[c] : 0, N);
-    const double *brow = B + static_cast<int64_t>(rm.row) * K;
-    const double *g0 = P.G64[TERM][0] + static_cast<int64_t>(cvalid ? c : 0) * N;
-    const double *g1 = TERM == TERM_PHD ? P.G64[TERM][1] + static_cast<int64_t>(cvalid ? c / N : 0) * K
-                                        : nullptr;
+    const GLOBAL_AS double *brow = B + static_cast<int64_t>(rm.row) * K;
+    const GLOBAL_AS double *g0 = gload_ptr(P.G64[TERM][0]) + static_cast<int64_t>(cvalid ? c : 0) * N;
+    const GLOBAL_AS double *g1 = TERM == TERM_PHD
+                                     ? gload_ptr(P.G64[TERM][1]) + static_cast<int64_t>(cvalid ? c / N : 0) * K
+                                     : nullptr;
 
     d2_t ra[NP][ACH];
     double rb[ZK], rg0[ZK], rg1[ZK];
@@ -186,7 +202,7 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
         const int k0 = kc * BK;
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const double *Ap = p == 0 ? A0 : A1;
+            const GLOBAL_AS double *Ap = p == 0 ? A0 : A1;
 #pragma unroll
             for (int i = 0; i < ACH; ++i) {
                 const int ch = tid + i * kThreads;         // chunk id: row ch / (BK/2), col pair
@@ -195,7 +211,7 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
                 if (ch >= NCH) {
                     ra[p][i] = d2_t{0.0, 0.0};
                 } else if (m < N && k + 1 < K) {
-                    ra[p][i] = *reinterpret_cast<const d2_t *>(Ap + static_cast<int64_t>(m) * K + k);
+                    ra[p][i] = *reinterpret_cast<const GLOBAL_AS d2_t *>(Ap + static_cast<int64_t>(m) * K + k);
                 } else {
                     ra[p][i][0] = (m < N && k < K) ? Ap[static_cast<int64_t>(m) * K + k] : 0.0;
                     ra[p][i][1] = 0.0;
@@ -265,7 +281,7 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
         __syncthreads();
     }
     // f64 16x16x4 accumulator layout: lane l, register r holds row (l>>4) + 4r, column l&15
-    double *Cout = P.C[TERM] + static_cast<int64_t>(w.ks) * P.n3;
+    GLOBAL_AS double *Cout = gstore_ptr(P.C[TERM]) + static_cast<int64_t>(w.ks) * P.n3;
 #pragma unroll
     for (int ri = 0; ri < RT; ++ri)
 #pragma unroll
@@ -300,18 +316,19 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     const int kc_lo = static_cast<int>((static_cast<int64_t>(kchunks) * w.ks) / P.KS);
     const int kc_hi = static_cast<int>((static_cast<int64_t>(kchunks) * (w.ks + 1)) / P.KS);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint16_t *Ahl[2] = {P.Ahl[TERM][0], P.Ahl[TERM][1]};
-    const float *B = static_cast<const float *>(P.B[TERM]);
-    const int32_t *colrow = P.colrow[TERM];
+    const GLOBAL_AS uint16_t *Ahl[2] = {gload_ptr(P.Ahl[TERM][0]), gload_ptr(P.Ahl[TERM][1])};
+    const GLOBAL_AS float *B = gload_ptr(static_cast<const float *>(P.B[TERM]));
+    const GLOBAL_AS int32_t *colrow = gload_ptr(P.colrow[TERM]);
 
     const int cl = tid >> 2, zk = (tid & 3) * ZK;   // Z loader: column cl, ZK consecutive k
     const int c = c0 + cl;
     const bool cvalid = c < NC;
     const RowMap rm = decode_rowmap(cvalid ? colrow[c] : 0, N);
-    const float *brow = B + static_cast<int64_t>(rm.row) * K;
-    const float *g0 = P.G32[TERM][0] + static_cast<int64_t>(cvalid ? c : 0) * N;
-    const float *g1 = TERM == TERM_PHD ? P.G32[TERM][1] + static_cast<int64_t>(cvalid ? c / N : 0) * K
-                                       : nullptr;
+    const GLOBAL_AS float *brow = B + static_cast<int64_t>(rm.row) * K;
+    const GLOBAL_AS float *g0 = gload_ptr(P.G32[TERM][0]) + static_cast<int64_t>(cvalid ? c : 0) * N;
+    const GLOBAL_AS float *g1 = TERM == TERM_PHD
+                                    ? gload_ptr(P.G32[TERM][1]) + static_cast<int64_t>(cvalid ? c / N : 0) * K
+                                    : nullptr;
 
     u32x4_t ra[NP][2][ACH];
     float rb[ZK], rg0[ZK], rg1[ZK];
@@ -327,11 +344,11 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
                     const int ch = tid + i * kThreads;            // row ch / CPR, 8 bf16 per chunk
                     const int row = ch / CPR, kq = (ch % CPR) * 8;
                     const int m = m0 + row, k = k0 + kq;
-                    const uint16_t *src = Ahl[p] + hl * n3 + static_cast<int64_t>(m) * K + k;
+                    const GLOBAL_AS uint16_t *src = Ahl[p] + hl * n3 + static_cast<int64_t>(m) * K + k;
                     if (ch >= NCH) {
                         ra[p][hl][i] = u32x4_t{0u, 0u, 0u, 0u};
                     } else if (m < N && k + 8 <= K) {
-                        ra[p][hl][i] = *reinterpret_cast<const u32x4_t *>(src);
+                        ra[p][hl][i] = *reinterpret_cast<const GLOBAL_AS u32x4_t *>(src);
                     } else {
                         u16x8_t v;
 #pragma unroll
@@ -345,7 +362,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
         if (TERM != TERM_PP && cvalid && b + ZK <= N && (b & 3) == 0 && (N & 3) == 0) {
 #pragma unroll
             for (int q = 0; q < ZK; q += 4) {
-                const f4_t v = *reinterpret_cast<const f4_t *>(g0 + b + q);
+                const f4_t v = *reinterpret_cast<const GLOBAL_AS f4_t *>(g0 + b + q);
                 rg0[q] = v[0]; rg0[q + 1] = v[1]; rg0[q + 2] = v[2]; rg0[q + 3] = v[3];
             }
         } else {
@@ -361,7 +378,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
             if (cvalid && kb + ZK <= K) {
 #pragma unroll
                 for (int q = 0; q < ZK; q += 4) {
-                    const f4_t v = *reinterpret_cast<const f4_t *>(g1 + kb + q);
+                    const f4_t v = *reinterpret_cast<const GLOBAL_AS f4_t *>(g1 + kb + q);
                     rg1[q] = v[0]; rg1[q + 1] = v[1]; rg1[q + 2] = v[2]; rg1[q + 3] = v[3];
                 }
             } else {
@@ -439,7 +456,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
         __syncthreads();
     }
     // bf16 16x16x32 accumulator layout: lane l, register r holds row 4(l>>4) + r, column l&15
-    double *Cout = P.C[TERM] + static_cast<int64_t>(w.ks) * P.n3;
+    GLOBAL_AS double *Cout = gstore_ptr(P.C[TERM]) + static_cast<int64_t>(w.ks) * P.n3;
 #pragma unroll
     for (int ri = 0; ri < RT; ++ri)
 #pragma unroll
@@ -453,23 +470,82 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
         }
 }
 
+template <int BM, bool SPLIT>
+__device__ __forceinline__ void run_work(const FusedContractArgs &P, const Work &w, double *smem_d) {
+    if (SPLIT) {
+        uint16_t *smem = reinterpret_cast<uint16_t *>(smem_d);
+        if (w.term == TERM_PHD) body_split<TERM_PHD, BM>(P, w, smem);
+        else if (w.term == TERM_PHC) body_split<TERM_PHC, BM>(P, w, smem);
+        else body_split<TERM_PP, BM>(P, w, smem);
+    } else {
+        if (w.term == TERM_PHD) body_f64<TERM_PHD, BM>(P, w, smem_d);
+        else if (w.term == TERM_PHC) body_f64<TERM_PHC, BM>(P, w, smem_d);
+        else body_f64<TERM_PP, BM>(P, w, smem_d);
+    }
+}
+
 template <int BM>
 __global__ __launch_bounds__(kThreads) void contract_f64_fused(FusedContractArgs P) {
     extern __shared__ double smem_d[];
-    const Work w = decode_block(P);
-    if (w.term == TERM_PHD) body_f64<TERM_PHD, BM>(P, w, smem_d);
-    else if (w.term == TERM_PHC) body_f64<TERM_PHC, BM>(P, w, smem_d);
-    else body_f64<TERM_PP, BM>(P, w, smem_d);
+    run_work<BM, false>(P, decode_block(P, blockIdx.x), smem_d);
 }
 
 template <int BM>
 __global__ __launch_bounds__(kThreads) void contract_split_fused(FusedContractArgs P) {
     extern __shared__ double smem_d[];
-    uint16_t *smem = reinterpret_cast<uint16_t *>(smem_d);
-    const Work w = decode_block(P);
-    if (w.term == TERM_PHD) body_split<TERM_PHD, BM>(P, w, smem);
-    else if (w.term == TERM_PHC) body_split<TERM_PHC, BM>(P, w, smem);
-    else body_split<TERM_PP, BM>(P, w, smem);
+    run_work<BM, true>(P, decode_block(P, blockIdx.x), smem_d);
+}
+
+// Persistent launch over a work list of many flows.  The list of one block
+// height class is cut into 8 queues, one per XCD: items of K part p of a flow
+// go to the queues of the XCDs that own p (block b runs on XCD b mod 8), so
+// each XCD's L2 sees one K range of the operands, as in the single-flow
+// launch.  A block drains its own queue, then steals from the others; within a
+// queue the items are sorted by cost, largest first, and items of flows that
+// have stopped are skipped.
+template <bool SPLIT, int BM>
+__global__ __launch_bounds__(kThreads) void contract_persistent(const FusedContractArgs *__restrict__ args,
+                                                                const int2 *__restrict__ items,
+                                                                const int *__restrict__ qstart,
+                                                                const int *__restrict__ qcount, int *counters,
+                                                                const double *const *__restrict__ states) {
+    extern __shared__ double smem_d[];
+    __shared__ int next;
+    const int q0 = blockIdx.x & 7;
+    for (int r = 0; r < 8; ++r) {
+        const int q = (q0 + r) & 7;
+        const int n = qcount[q];
+        const int2 *qi = items + qstart[q];
+        for (;;) {
+            if (threadIdx.x == 0) next = atomicAdd(&counters[q], 1);
+            __syncthreads();
+            const int i = __builtin_amdgcn_readfirstlane(next);
+            __syncthreads();
+            if (i >= n) break;
+            const int2 it = qi[i];
+            if (states && states[it.x][FRG_ST_REASON] != 0.0) continue;
+            const FusedContractArgs P = args[it.x];
+            run_work<BM, SPLIT>(P, decode_block(P, it.y), smem_d);
+            __syncthreads();
+        }
+    }
+}
+
+// One block per work item of the list, dealt by the hardware dispatcher in
+// list order (the alternative to the persistent queues).
+template <bool SPLIT, int BM>
+__global__ __launch_bounds__(kThreads) void contract_items(const FusedContractArgs *__restrict__ args,
+                                                           const int2 *__restrict__ items,
+                                                           const double *const *__restrict__ states) {
+    extern __shared__ double smem_d[];
+    const int2 it = items[blockIdx.x];
+    if (states && states[it.x][FRG_ST_REASON] != 0.0) return;
+    const FusedContractArgs P = args[it.x];
+    run_work<BM, SPLIT>(P, decode_block(P, it.y), smem_d);
+}
+
+__global__ void reset_counters(int *counters, int n) {
+    if (static_cast<int>(threadIdx.x) < n) counters[threadIdx.x] = 0;
 }
 
 template <int BM>
@@ -488,7 +564,57 @@ void launch_bm(FusedContractArgs a, bool split, hipStream_t s) {
 
 }  // namespace
 
-int contract_block_rows(int N) { return N <= 32 ? 32 : (N <= 64 ? 64 : 96); }
+
+int contract_block_rows(int N) { return block_rows_of(N); }
+
+size_t contract_lds_bytes(bool split) {
+    return split ? sizeof(uint16_t) * (2 * 2 * 96 * (32 + 8) + 2 * 2 * BC * (32 + 8))
+                 : sizeof(double) * (2 * 96 * 17 + 2 * BC * 17);
+}
+
+template <bool SPLIT, int BM>
+void launch_persistent_bm(const FusedContractArgs *args, const int2 *items, const int *qstart,
+                          const int *qcount, int *counters, const double *const *states, int grid,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, counters, 8);
+    hipLaunchKernelGGL((contract_persistent<SPLIT, BM>), dim3(grid), dim3(kThreads), contract_lds_bytes(SPLIT),
+                       s, args, items, qstart, qcount, counters, states);
+}
+
+template <bool SPLIT, int BM>
+void launch_items_bm(const FusedContractArgs *args, const int2 *items, int nitems, const double *const *states,
+                     hipStream_t s) {
+    hipLaunchKernelGGL((contract_items<SPLIT, BM>), dim3(nitems), dim3(kThreads), contract_lds_bytes(SPLIT), s,
+                       args, items, states);
+}
+
+void launch_contract_items(const FusedContractArgs *args, const int2 *items, int nitems,
+                           const double *const *states, int bm, bool split, hipStream_t s) {
+    if (split) {
+        if (bm == 32) launch_items_bm<true, 32>(args, items, nitems, states, s);
+        else if (bm == 64) launch_items_bm<true, 64>(args, items, nitems, states, s);
+        else launch_items_bm<true, 96>(args, items, nitems, states, s);
+    } else {
+        if (bm == 32) launch_items_bm<false, 32>(args, items, nitems, states, s);
+        else if (bm == 64) launch_items_bm<false, 64>(args, items, nitems, states, s);
+        else launch_items_bm<false, 96>(args, items, nitems, states, s);
+    }
+}
+
+// items of flows whose block height is bm, cut into 8 per-XCD queues
+void launch_contract_persistent(const FusedContractArgs *args, const int2 *items, const int *qstart,
+                                const int *qcount, int *counters, const double *const *states, int grid,
+                                int bm, bool split, hipStream_t s) {
+    if (split) {
+        if (bm == 32) launch_persistent_bm<true, 32>(args, items, qstart, qcount, counters, states, grid, s);
+        else if (bm == 64) launch_persistent_bm<true, 64>(args, items, qstart, qcount, counters, states, grid, s);
+        else launch_persistent_bm<true, 96>(args, items, qstart, qcount, counters, states, grid, s);
+    } else {
+        if (bm == 32) launch_persistent_bm<false, 32>(args, items, qstart, qcount, counters, states, grid, s);
+        else if (bm == 64) launch_persistent_bm<false, 64>(args, items, qstart, qcount, counters, states, grid, s);
+        else launch_persistent_bm<false, 96>(args, items, qstart, qcount, counters, states, grid, s);
+    }
+}
 
 void launch_contract_fused(const FusedContractArgs &a, bool split, hipStream_t s) {
     const int bm = contract_block_rows(a.N);

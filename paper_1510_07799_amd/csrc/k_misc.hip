@@ -296,8 +296,7 @@ __global__ void state_set_kernel(double *state, int slot, double v) {
 }
 
 // pre-step: clip the step onto s_min (DP54) and remember whether this is the last
-__global__ void pre_step_kernel(double *state, int stepper) {
-    if (threadIdx.x != 0) return;
+__device__ void pre_step_body(double *state, int stepper) {
     if (stepper == FRG_DP54) {
         const double s = state[FRG_ST_S], smin = state[FRG_ST_SMIN];
         double h = state[FRG_ST_H];
@@ -312,12 +311,15 @@ __global__ void pre_step_kernel(double *state, int stepper) {
     state[23] = 0.0;  // accept flag of this attempt
 }
 
+__global__ void pre_step_kernel(double *state, int stepper) {
+    if (threadIdx.x == 0) pre_step_body(state, stepper);
+}
+
 // step control (one thread).  DP54: G10 rules; RK4: fixed step index.
 // state slots: 20 max|y_new|, 21 direction, 22 last, 23 accept, 24 m_prev,
 // 25 s0, 26 RK4 step index, 27 RK4 step count
-__global__ void control_kernel(double *state, double *log, int log_cap, double vmax,
-                               int max_steps, int stepper) {
-    if (threadIdx.x != 0) return;
+__device__ void control_body(double *state, double *log, int log_cap, double vmax,
+                             int max_steps, int stepper) {
     if (state[FRG_ST_REASON] != 0.0) { state[23] = 0.0; return; }
     const double mx = state[20];
     const double s = state[FRG_ST_S], h = state[FRG_ST_H];
@@ -382,6 +384,11 @@ __global__ void control_kernel(double *state, double *log, int log_cap, double v
     }
 }
 
+__global__ void control_kernel(double *state, double *log, int log_cap, double vmax,
+                               int max_steps, int stepper) {
+    if (threadIdx.x == 0) control_body(state, log, log_cap, vmax, max_steps, stepper);
+}
+
 __global__ void accept_copy_kernel(int64_t n, const double *state, const double *__restrict__ src,
                                    double *__restrict__ dst) {
     if (state[23] == 0.0) return;
@@ -399,6 +406,177 @@ __global__ void state_init_kernel(double *state, double s0, double h, double s_m
     state[FRG_ST_SC_INTERP] = NAN;
     state[21] = (s_min < s0) ? -1.0 : 1.0;
     state[25] = s0;
+}
+
+
+// ----------------------------------------------------------------- batched (work list of (flow, block))
+__device__ __forceinline__ bool flow_stopped(const FlowArgs &f) { return f.state[FRG_ST_REASON] != 0.0; }
+
+__global__ void prep_b_kernel(const FlowArgs *__restrict__ fa, const int2 *__restrict__ items,
+                              double c_stage, int split) {
+    const int2 it = items[blockIdx.x];
+    const FlowArgs &f = fa[it.x];
+    if (flow_stopped(f)) return;
+    const double T = exp(f.state[FRG_ST_S] + c_stage * f.state[FRG_ST_H]);
+    const double inv2T = 0.5 / T;
+    const int i = it.y * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        f.Tdev[0] = T;
+        f.Tdev[1] = inv2T;
+    }
+    if (i >= f.np) return;
+    const double a = f.xi[i] * inv2T;
+    const double ha = a * sech2_d(a);
+    const double wf = -f.w[i] / (4.0 * T * T);
+    if (split) {
+        f.pa32[i] = static_cast<float>(a);
+        f.pa32[f.np + i] = static_cast<float>(ha);
+        f.pa32[2 * f.np + i] = static_cast<float>(wf);
+    } else {
+        f.pa64[i] = a;
+        f.pa64[f.np + i] = ha;
+        f.pa64[2 * f.np + i] = wf;
+    }
+}
+
+__device__ __forceinline__ const double *src_of(const FlowArgs &f, int src) {
+    return src == SRC_V ? f.V : (src == SRC_YT ? f.yt : f.y5);
+}
+
+__global__ void layout_b_kernel(const FlowArgs *__restrict__ fa, const int2 *__restrict__ items,
+                                int src, int split) {
+    const int2 it = items[blockIdx.x];
+    const FlowArgs &f = fa[it.x];
+    if (flow_stopped(f)) return;
+    const int N = f.N;
+    const int64_t n3 = f.n3;
+    const int64_t idx = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x;
+    if (idx >= n3) return;
+    const double *V = src_of(f, src);
+    const int k = static_cast<int>(idx % N);
+    const int j = static_cast<int>((idx / N) % N);
+    const int i = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
+    auto at = [&](int x, int y, int z) { return V[(static_cast<int64_t>(x) * N + y) * N + z]; };
+    if (!split) {
+        double *perm = f.perm;
+        perm[idx] = at(j, k, i);
+        perm[n3 + idx] = at(k, i, j);
+        perm[2 * n3 + idx] = -2.0 * at(j, i, k) + at(i, j, k);
+        perm[3 * n3 + idx] = at(j, i, k);
+        perm[4 * n3 + idx] = at(i, k, j);
+    } else {
+        const float ops[4] = {static_cast<float>(at(j, k, i)), static_cast<float>(at(i, j, k)),
+                              static_cast<float>(-2.0 * at(j, i, k) + at(i, j, k)),
+                              static_cast<float>(at(j, i, k))};
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            const uint16_t hi = bf16_rne(ops[o]);
+            f.ahl[(2 * o) * n3 + idx] = hi;
+            f.ahl[(2 * o + 1) * n3 + idx] = bf16_rne(ops[o] - bf16_to_f(hi));
+        }
+        f.g32[idx] = static_cast<float>(at(i, j, k));
+        f.g32[n3 + idx] = static_cast<float>(at(k, i, j));
+        f.g32[2 * n3 + idx] = static_cast<float>(at(i, k, j));
+    }
+}
+
+__global__ void combine_b_kernel(const FlowArgs *__restrict__ fa, const int2 *__restrict__ items, int stage) {
+    const int2 it = items[blockIdx.x];
+    const FlowArgs &f = fa[it.x];
+    if (flow_stopped(f)) return;
+    const int64_t n = f.n3;
+    const int64_t i = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int KS = f.KS;
+    const double *Cpp = f.C, *Cc = f.C + KS * n, *Cd = f.C + 2 * KS * n;
+    double v = 0.0;
+    for (int s = 0; s < KS; ++s) {
+        const int64_t j = s * n + i;
+        v += (Cc[j] - Cpp[j]) + Cd[j];
+    }
+    f.k[stage][i] = f.Tdev[0] * v;
+}
+
+struct Coef7 { double c[7]; };
+
+__global__ void rk_stage_b_kernel(const FlowArgs *__restrict__ fa, const int2 *__restrict__ items,
+                                  Coef7 coef, int nk, int dst) {
+    const int2 it = items[blockIdx.x];
+    const FlowArgs &f = fa[it.x];
+    if (flow_stopped(f)) return;
+    const int64_t i = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x;
+    if (i >= f.n3) return;
+    const double h = f.state[FRG_ST_H];
+    double acc = 0.0;
+    for (int j = 0; j < nk; ++j)
+        if (coef.c[j] != 0.0) acc += coef.c[j] * f.k[j][i];
+    double *out = dst == SRC_YT ? f.yt : f.y5;
+    out[i] = f.V[i] + h * acc;
+}
+
+// error norm partials: item block it.y of flow it.x covers a grid-stride slice
+__global__ void dp_error_b_kernel(const FlowArgs *__restrict__ fa, const int2 *__restrict__ items,
+                                  Coef7 e, double rtol, double atol) {
+    __shared__ double sh[2][16];
+    const int2 it = items[blockIdx.x];
+    const FlowArgs &f = fa[it.x];
+    if (flow_stopped(f)) return;
+    const double h = f.state[FRG_ST_H];
+    double emax = 0.0, vmax = 0.0;
+    for (int64_t i = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x; i < f.n3;
+         i += static_cast<int64_t>(f.nred) * blockDim.x) {
+        double d = 0.0;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) d += e.c[j] * f.k[j][i];
+        d = fabs(h * d);
+        const double y5 = f.y5[i];
+        const double q = d / (atol + rtol * fmax(fabs(f.V[i]), fabs(y5)));
+        emax = (q > emax || q != q) ? q : emax;
+        const double av = fabs(y5);
+        vmax = (av > vmax || av != av) ? av : vmax;
+    }
+    emax = block_max(emax, sh[0]);
+    vmax = block_max(vmax, sh[1]);
+    if (threadIdx.x == 0) {
+        f.partial[2 * it.y] = emax;
+        f.partial[2 * it.y + 1] = vmax;
+    }
+}
+
+// one thread per flow: phase 0 = reduce error partials, 1 = pre-step, 2 = step control
+__global__ void step_ctl_b_kernel(const FlowArgs *__restrict__ fa, int nflows, int phase, double *log_base,
+                                  int log_cap, double vmax, int max_steps) {
+    const int fl = blockIdx.x * blockDim.x + threadIdx.x;
+    if (fl >= nflows) return;
+    const FlowArgs &f = fa[fl];
+    if (phase == 0) {
+        if (flow_stopped(f)) return;
+        double e = 0.0, v = 0.0;
+        for (int b = 0; b < f.nred; ++b) {
+            const double pe = f.partial[2 * b], pv = f.partial[2 * b + 1];
+            e = (pe > e || pe != pe) ? pe : e;
+            v = (pv > v || pv != pv) ? pv : v;
+        }
+        f.state[FRG_ST_ERR] = e;
+        f.state[20] = v;
+    } else if (phase == 1) {
+        if (flow_stopped(f)) return;
+        pre_step_body(f.state, FRG_DP54);
+    } else {
+        control_body(f.state, log_base ? log_base + static_cast<size_t>(fl) * 8 * log_cap : nullptr,
+                     log_cap, vmax, max_steps, FRG_DP54);
+    }
+}
+
+// accepted steps: V <- y5 and the first stage <- last stage (FSAL)
+__global__ void accept_b_kernel(const FlowArgs *__restrict__ fa, const int2 *__restrict__ items) {
+    const int2 it = items[blockIdx.x];
+    const FlowArgs &f = fa[it.x];
+    if (f.state[23] == 0.0) return;
+    const int64_t i = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x;
+    if (i >= f.n3) return;
+    f.V[i] = f.y5[i];
+    f.k[0][i] = f.k[6][i];
 }
 
 inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n + bs - 1) / bs); }
@@ -489,6 +667,40 @@ void launch_accept_copy(int64_t n, const double *state, const double *src, doubl
                         hipStream_t s) {
     hipLaunchKernelGGL(accept_copy_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, state,
                        src, dst);
+}
+
+void launch_prep_b(const FlowArgs *fa, const int2 *items, int nitems, double c_stage, bool split,
+                   hipStream_t s) {
+    hipLaunchKernelGGL(prep_b_kernel, dim3(nitems), dim3(256), 0, s, fa, items, c_stage, split ? 1 : 0);
+}
+void launch_layout_b(const FlowArgs *fa, const int2 *items, int nitems, int src, bool split,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(layout_b_kernel, dim3(nitems), dim3(256), 0, s, fa, items, src, split ? 1 : 0);
+}
+void launch_combine_b(const FlowArgs *fa, const int2 *items, int nitems, int stage, hipStream_t s) {
+    hipLaunchKernelGGL(combine_b_kernel, dim3(nitems), dim3(256), 0, s, fa, items, stage);
+}
+void launch_rk_stage_b(const FlowArgs *fa, const int2 *items, int nitems, const double coef[7],
+                       int nk, int dst, hipStream_t s) {
+    Coef7 c;
+    for (int j = 0; j < 7; ++j) c.c[j] = coef[j];
+    hipLaunchKernelGGL(rk_stage_b_kernel, dim3(nitems), dim3(256), 0, s, fa, items, c, nk, dst);
+}
+void launch_dp_error_b(const FlowArgs *fa, const int2 *items, int nitems, int nflows,
+                       const double e[7], double rtol, double atol, hipStream_t s) {
+    Coef7 c;
+    for (int j = 0; j < 7; ++j) c.c[j] = e[j];
+    hipLaunchKernelGGL(dp_error_b_kernel, dim3(nitems), dim3(256), 0, s, fa, items, c, rtol, atol);
+    hipLaunchKernelGGL(step_ctl_b_kernel, dim3(blocks_for(nflows, 64)), dim3(64), 0, s, fa, nflows, 0,
+                       static_cast<double *>(nullptr), 0, 0.0, 0);
+}
+void launch_step_ctl_b(const FlowArgs *fa, int nflows, int phase, double *log_base, int log_cap,
+                       double vmax, int max_steps, hipStream_t s) {
+    hipLaunchKernelGGL(step_ctl_b_kernel, dim3(blocks_for(nflows, 64)), dim3(64), 0, s, fa, nflows, phase,
+                       log_base, log_cap, vmax, max_steps);
+}
+void launch_accept_b(const FlowArgs *fa, const int2 *items, int nitems, hipStream_t s) {
+    hipLaunchKernelGGL(accept_b_kernel, dim3(nitems), dim3(256), 0, s, fa, items);
 }
 
 void launch_state_init(double *state, double s0, double h, double s_min, hipStream_t s) {

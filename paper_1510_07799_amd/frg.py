@@ -67,6 +67,15 @@ SIGNATURES = {
     "frg_flow_init": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, _P]),
     "frg_flow_step": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, _P]),
     "frg_flow": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, C.c_int32, C.POINTER(FlowResult), _P]),
+    "frg_batch_create": (C.c_int, [C.POINTER(Params), C.c_int32, C.POINTER(_P)]),
+    "frg_batch_destroy": (C.c_int, [_P]),
+    "frg_batch_context": (C.c_int, [_P, C.c_int32, C.POINTER(_P)]),
+    "frg_batch_rhs": (C.c_int, [_P, _DP, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int, _P]),
+    "frg_batch_flow": (C.c_int, [_P, C.POINTER(FlowOpts), C.POINTER(C.c_void_p), _P, C.c_int32,
+                                 C.POINTER(FlowResult), _P]),
+    "frg_batch_flow_init": (C.c_int, [_P, C.POINTER(FlowOpts), C.POINTER(C.c_void_p), _P, C.c_int32, _P]),
+    "frg_batch_flow_step": (C.c_int, [_P, _P]),
+    "frg_batch_results": (C.c_int, [_P, C.POINTER(FlowResult), _IP]),
     "frg_set_symmetry": (C.c_int, [_P, C.c_int32]),
     "frg_symmetry": (C.c_int, [_P, _IP, _IP]),
     "frg_profile_begin": (C.c_int, [_P]),
@@ -252,6 +261,85 @@ class Context:
         torch.cuda.synchronize()
         n = min(res["accepted"], log_cap)
         return res, log[:n].cpu().numpy()
+
+
+class Batch:
+    """Independent flows (different parameters, uneven N, same n_rad x n_ang) run together."""
+
+    def __init__(self, param_dicts):
+        import torch
+        self.torch = torch
+        self.params = [dict(p) for p in param_dicts]
+        n = len(self.params)
+        arr = (Params * n)(*[params(**p) for p in self.params])
+        h = _P()
+        _check(lib().frg_batch_create(arr, n, C.byref(h)))
+        self._h = h
+        self.n = n
+        self.Ns = [int(p["N"]) for p in self.params]
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().frg_batch_destroy(self._h)
+            self._h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, tensors):
+        arr = (C.c_void_p * self.n)(*[t.data_ptr() for t in tensors])
+        return arr
+
+    def rhs(self, Ts, Vs, prec=PREC_FP64):
+        torch = self.torch
+        Fs = [torch.empty_like(V) for V in Vs]
+        T = np.ascontiguousarray(Ts, dtype=np.float64)
+        _check(lib().frg_batch_rhs(self._h, T.ctypes.data_as(_DP), self._ptrs(Vs), self._ptrs(Fs),
+                                   int(prec), _stream()))
+        return Fs
+
+    def symmetry(self):
+        """(active, bubble rows per rhs) of every member."""
+        out = []
+        for i in range(self.n):
+            h = _P()
+            _check(lib().frg_batch_context(self._h, i, C.byref(h)))
+            a, r = C.c_int32(), C.c_int32()
+            _check(lib().frg_symmetry(h, C.byref(a), C.byref(r)))
+            out.append((bool(a.value), int(r.value)))
+        return out
+
+    def flow_init(self, Vs, opts: FlowOpts):
+        self._keep = (list(Vs), opts)
+        _check(lib().frg_batch_flow_init(self._h, C.byref(opts), self._ptrs(Vs), None, 0, _stream()))
+
+    def flow_step(self):
+        _check(lib().frg_batch_flow_step(self._h, _stream()))
+
+    def results(self):
+        res = (FlowResult * self.n)()
+        allst = C.c_int32()
+        st = lib().frg_batch_results(self._h, res, C.byref(allst))
+        if st not in (OK, ENONFINITE):
+            _check(st)
+        return [{k: getattr(r, k) for k, _ in FlowResult._fields_} for r in res], bool(allst.value)
+
+    def flow(self, Vs, opts: FlowOpts, log_cap=0):
+        """Run all flows in place on Vs; returns (list of result dicts, log or None)."""
+        torch = self.torch
+        log = (torch.zeros((self.n, log_cap, 8), dtype=torch.float64, device="cuda")
+               if log_cap > 0 else None)
+        res = (FlowResult * self.n)()
+        st = lib().frg_batch_flow(self._h, C.byref(opts), self._ptrs(Vs), _ptr(log), int(log_cap),
+                                  res, _stream())
+        if st not in (OK, ENONFINITE):
+            _check(st)
+        torch.cuda.synchronize()
+        out = [{k: getattr(r, k) for k, _ in FlowResult._fields_} for r in res]
+        return out, (log.cpu().numpy() if log is not None else None)
 
 
 def T_of_s(s: float) -> float:

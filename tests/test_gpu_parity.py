@@ -263,3 +263,43 @@ def test_c4v_reduction_unavailable_for_n_not_multiple_of_8():
     with pytest.raises(frg.FRGError) as e:
         g.set_symmetry(True)
     assert e.value.status == frg.ENOTSUP
+
+
+BATCH = [dict(t=1.0, tp=-0.1, mu=-0.3, U=2.0, N=16, n_rad=4, n_ang=4),
+         dict(t=1.0, tp=-0.3, mu=-0.9, U=2.5, N=24, n_rad=4, n_ang=4),
+         dict(t=1.0, tp=0.0, mu=0.0, U=1.5, N=32, n_rad=4, n_ang=4),
+         dict(t=1.0, tp=-0.2, mu=-0.5, U=3.0, N=12, n_rad=4, n_ang=4)]
+
+
+def test_batch_rhs_matches_single_flows_and_oracle():
+    b = frg.Batch(BATCH)
+    Vs = [dev(I.random_vertex(p["N"], p["U"], seed=50 + i, symmetrise=False)) for i, p in enumerate(BATCH)]
+    Ts = [0.3, 0.05, 0.1, 0.02]
+    for prec, tol in ((frg.PREC_FP64, 1e-12), (frg.PREC_SPLIT_BF16, 2e-4)):
+        Fs = b.rhs(Ts, Vs, prec)
+        for i, p in enumerate(BATCH):
+            om, g = pair(p)
+            single = g.rhs(Ts[i], Vs[i], prec).cpu().numpy()
+            got = Fs[i].cpu().numpy()
+            assert nrel(got, single) <= (1e-12 if prec == frg.PREC_FP64 else 1e-5), (i, prec)
+            if i in (0, 3):
+                assert nrel(got, om.rhs(Ts[i], Vs[i].cpu().numpy())) <= (1e-10 if prec == frg.PREC_FP64 else tol)
+    b.close()
+
+
+def test_batch_flow_matches_single_flows():
+    b = frg.Batch(BATCH)
+    o = frg.flow_opts("dp54", frg.PREC_FP64, T0=1.0, T_min=0.02, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.01)
+    Vs = [torch.full((p["N"],) * 3, p["U"], dtype=torch.float64, device="cuda") for p in BATCH]
+    res, log = b.flow(Vs, o, log_cap=256)
+    for i, p in enumerate(BATCH):
+        om, g = pair(p)
+        V1 = torch.full((p["N"],) * 3, p["U"], dtype=torch.float64, device="cuda")
+        r1, l1 = g.flow(V1, o)
+        print("[batch flow]", i, res[i], r1, flush=True)
+        assert res[i]["reason"] == r1["reason"]
+        assert res[i]["accepted"] == r1["accepted"] and res[i]["rejected"] == r1["rejected"]
+        assert res[i]["first_step_rhs"] == 7
+        assert np.allclose(log[i, :res[i]["accepted"], 0], l1[:, 0], rtol=0, atol=1e-9)
+        assert nrel(Vs[i].cpu().numpy(), V1.cpu().numpy()) <= 1e-9
+    b.close()
