@@ -227,6 +227,23 @@ frg_status frg_batch_results(frg_batch b, frg_flow_result *r, int32_t *all_stopp
 frg_status frg_set_symmetry(frg_ctx ctx, int32_t enable);
 frg_status frg_symmetry(frg_ctx ctx, int32_t *active, int32_t *rows_computed);
 
+/* Zero-block skipping in the channel contractions (Sec. 4, Eq. (3)-(5): the
+ * sums over the loop patch pair (a, b) of a bubble row).  The entry (a, b) of
+ * a bubble row is a sum over the fine points of patch a whose second momentum
+ * lies in patch b, so it is exactly zero whenever there is no such point; the
+ * pattern is fixed by the patch geometry, independent of T.  frg_create orders
+ * the contraction columns along a Hilbert curve of their transfer momentum and
+ * lists, per tile of 64 columns, the 8-wide k chunks (k = a*N + b) where any
+ * of the tile's rows has a point; the contraction then visits only those.
+ * Skipped terms are exact zeros, so the result changes only by the order of
+ * the FP sums.  frg_set_kskip(ctx, 0) switches to the dense contraction
+ * (natural column order, every chunk; allocates its lists on first use);
+ * frg_kskip reports whether skipping is on and the executed share of the
+ * dense multiply-adds (channels weighted pp 1, phc 1, phd 2).  Batches made
+ * by frg_batch_create always skip. */
+frg_status frg_set_kskip(frg_ctx ctx, int32_t enable);
+frg_status frg_kskip(frg_ctx ctx, int32_t *active, double *executed_frac);
+
 /* Kernel timing with HIP events recorded on the launch stream around every
  * kernel of the rhs and flow pipelines (for measurement; off by default).
  * frg_profile_begin clears and enables the record; frg_profile_end

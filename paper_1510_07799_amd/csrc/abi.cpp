@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -29,6 +30,14 @@ struct frg_ctx_s {
     int n_rep_pp = 0, n_rep_ph = 0;
     int32_t *d_rowlist = nullptr;                              // representative rows (pp, then ph)
     int32_t *d_colsym_pp = nullptr, *d_colsym_ph = nullptr;   // (compact rep << 3) | element
+    // column tiles of the contraction ([0]: pp columns, [1]: ph columns):
+    // Hilbert-ordered columns and the active 8-wide k chunks of each tile;
+    // the dense alternative (natural order, every chunk) is made on demand
+    bool kskip_on = true;
+    int32_t *d_cperm[2] = {nullptr, nullptr}, *d_koff[2] = {nullptr, nullptr},
+            *d_klist[2] = {nullptr, nullptr}, *d_cpos[2] = {nullptr, nullptr};
+    int32_t *d_cperm_id = nullptr, *d_koff_dense = nullptr, *d_klist_dense = nullptr;
+    int64_t kchunks_active[2] = {0, 0};
     // rhs workspace
     double *d_pa64 = nullptr, *d_T = nullptr;
     float *d_pa32 = nullptr;
@@ -117,7 +126,7 @@ frg_status ensure_rhs_ws(frg_ctx ctx, frg_precision prec) {
     if (prec == FRG_PREC_FP64) {
         TRY(dalloc(ctx, &ctx->d_pa64, 3 * static_cast<size_t>(g.np)));
         TRY(dalloc(ctx, &ctx->d_B64, NN * ctx->Trows));
-        TRY(dalloc(ctx, &ctx->d_perm, 5 * static_cast<size_t>(ctx->n3)));
+        TRY(dalloc(ctx, &ctx->d_perm, 6 * static_cast<size_t>(ctx->n3)));
     } else {
         TRY(dalloc(ctx, &ctx->d_pa32, 3 * static_cast<size_t>(g.np)));
         TRY(dalloc(ctx, &ctx->d_B32, NN * ctx->Trows));
@@ -275,6 +284,143 @@ frg_status build_orbits(frg_ctx ctx) {
     return FRG_OK;
 }
 
+// K parts of the fused contraction: enough blocks for several rounds over the
+// 256 compute units (measured best at N = 96: 4 parts); FRG_KSPLIT overrides
+int ksplit(frg_ctx ctx) {
+    if (ctx->ks_override > 0) return ctx->ks_override;
+    const int N = ctx->g.N;
+    const int bm = frg::contract_block_rows(N);
+    const int64_t tiles = 3LL * ((N + bm - 1) / bm) * ((static_cast<int64_t>(N) * N + 63) / 64);
+    int64_t ks = (1728 + tiles - 1) / tiles;
+    return static_cast<int>(ks < 1 ? 1 : (ks > 8 ? 8 : ks));
+}
+
+// position along a Hilbert curve over the Brillouin zone [-pi, pi)^2 (2^16 x 2^16 cells)
+uint64_t hilbert_key(double qx, double qy) {
+    const uint32_t n = 1u << 16;
+    auto quant = [&](double v) {
+        const double u = (v + M_PI) / (2.0 * M_PI) * n;
+        return u <= 0.0 ? 0u : (u >= n - 1.0 ? n - 1u : static_cast<uint32_t>(u));
+    };
+    uint32_t x = quant(qx), y = quant(qy);
+    uint64_t d = 0;
+    for (uint32_t sq = n / 2; sq > 0; sq /= 2) {
+        const uint32_t rx = (x & sq) ? 1u : 0u, ry = (y & sq) ? 1u : 0u;
+        d += static_cast<uint64_t>(sq) * sq * ((3u * rx) ^ ry);
+        if (ry == 0) {
+            if (rx == 1) { x = n - 1 - x; y = n - 1 - y; }
+            std::swap(x, y);
+        }
+    }
+    return d;
+}
+
+// Column tiles of the contraction.  Columns (pp: (j1, j2), ph: (y, x)) are
+// ordered along the Hilbert curve of their transfer momentum; for every tile
+// of 64 consecutive columns the second-line table gives the k chunks where
+// any of its bubble rows can be nonzero (T independent); tile t's entries are
+// klist[koff[t] .. koff[t+1]).
+frg_status build_ktiles(frg_ctx ctx) {
+    const auto &g = ctx->g;
+    const int N = g.N, NC = N * N;
+    const int tiles = (NC + frg::kContractCols - 1) / frg::kContractCols;
+    const int nch = NC / frg::kContractChunk;
+    std::vector<uint8_t> flags(static_cast<size_t>(tiles) * nch);
+    for (int cls = 0; cls < 2; ++cls) {
+        std::vector<int32_t> colfull(NC), perm(NC);
+        std::vector<uint64_t> key(NC);
+        for (int y = 0; y < N; ++y)
+            for (int x = 0; x < N; ++x) {
+                const int c = y * N + x;
+                const int row = cls == 0 ? g.row_pp[y * N + x] : g.row_ph[x * N + y];
+                const double *q = cls == 0 ? &g.qpp[2 * row] : &g.qph[2 * row];
+                colfull[c] = cls == 0 ? row : g.Tpp + row;
+                key[c] = hilbert_key(q[0], q[1]);
+            }
+        std::iota(perm.begin(), perm.end(), 0);
+        std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+        TRY(upload(ctx, &ctx->d_cperm[cls], perm.data(), perm.size()));
+        std::vector<int32_t> pos(NC);
+        for (int i = 0; i < NC; ++i) pos[perm[i]] = i;
+        TRY(upload(ctx, &ctx->d_cpos[cls], pos.data(), pos.size()));
+        int32_t *d_colfull = nullptr;
+        uint8_t *d_flags = nullptr;
+        hipError_t e = hipMalloc(&d_colfull, sizeof(int32_t) * NC);
+        if (e == hipSuccess) e = hipMalloc(&d_flags, flags.size());
+        if (e == hipSuccess) e = hipMemcpy(d_colfull, colfull.data(), sizeof(int32_t) * NC, hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            frg::launch_tile_pattern(ctx->d_bins, d_colfull, ctx->d_cperm[cls], N, g.nf, g.np, d_flags, nullptr);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = hipMemcpy(flags.data(), d_flags, flags.size(), hipMemcpyDeviceToHost);
+        if (d_colfull) hipFree(d_colfull);
+        if (d_flags) hipFree(d_flags);
+        if (e != hipSuccess) return fail(FRG_EDEVICE, std::string("column tiles: ") + hipGetErrorString(e));
+        std::vector<int32_t> koff(tiles + 1), klist;
+        for (int t = 0; t < tiles; ++t) {
+            koff[t] = static_cast<int32_t>(klist.size());
+            for (int j = 0; j < nch; ++j)
+                if (flags[static_cast<size_t>(t) * nch + j]) klist.push_back(j);
+        }
+        koff[tiles] = static_cast<int32_t>(klist.size());
+        ctx->kchunks_active[cls] = static_cast<int64_t>(klist.size());
+        TRY(upload(ctx, &ctx->d_koff[cls], koff.data(), koff.size()));
+        TRY(upload(ctx, &ctx->d_klist[cls], klist.data(), klist.size()));
+    }
+    return FRG_OK;
+}
+
+// natural column order with every k chunk (the dense contraction)
+frg_status ensure_dense_tiles(frg_ctx ctx) {
+    if (ctx->d_klist_dense) return FRG_OK;
+    const int NC = ctx->g.N * ctx->g.N;
+    const int tiles = (NC + frg::kContractCols - 1) / frg::kContractCols;
+    const int nch = NC / frg::kContractChunk;
+    std::vector<int32_t> perm(NC), koff(tiles + 1), klist(static_cast<size_t>(tiles) * nch);
+    std::iota(perm.begin(), perm.end(), 0);
+    for (int t = 0; t <= tiles; ++t) koff[t] = t * nch;
+    for (size_t i = 0; i < klist.size(); ++i) klist[i] = static_cast<int32_t>(i % nch);
+    TRY(upload(ctx, &ctx->d_cperm_id, perm.data(), perm.size()));
+    TRY(upload(ctx, &ctx->d_koff_dense, koff.data(), koff.size()));
+    TRY(upload(ctx, &ctx->d_klist_dense, klist.data(), klist.size()));
+    return FRG_OK;
+}
+
+// Operand pointers of the fused contraction in the layout the layout kernels
+// write: FP64 perm = [pp A, phc A, phd A0, phd A1 (chunk-major), phc gather,
+// phd gather]; split ahl = four A operands x (hi, lo), g32 = [V, phc gather,
+// phd gather].
+void set_operands(frg::FusedContractArgs &a, bool split, const double *V, const double *P, const uint16_t *H,
+                  const float *G, int64_t n3) {
+    using frg::TERM_PP;
+    using frg::TERM_PHC;
+    using frg::TERM_PHD;
+    if (!split) {
+        a.A64[TERM_PP][0] = P;           a.G64[TERM_PP][0] = V;
+        a.A64[TERM_PHC][0] = P + n3;     a.G64[TERM_PHC][0] = P + 4 * n3;
+        a.A64[TERM_PHD][0] = P + 2 * n3; a.G64[TERM_PHD][0] = P + 5 * n3;
+        a.A64[TERM_PHD][1] = P + 3 * n3; a.G64[TERM_PHD][1] = P + 5 * n3;
+    } else {
+        a.Ahl[TERM_PP][0] = H;           a.G32[TERM_PP][0] = G;
+        a.Ahl[TERM_PHC][0] = H + 2 * n3; a.G32[TERM_PHC][0] = G + n3;
+        a.Ahl[TERM_PHD][0] = H + 4 * n3; a.G32[TERM_PHD][0] = G + 2 * n3;
+        a.Ahl[TERM_PHD][1] = H + 6 * n3; a.G32[TERM_PHD][1] = G + 2 * n3;
+    }
+}
+
+// tile position of every column (cls 0: pp, 1: ph) in the current column order
+const int32_t *col_pos(frg_ctx ctx, int cls) { return ctx->kskip_on ? ctx->d_cpos[cls] : ctx->d_cperm_id; }
+
+void set_tiles(frg_ctx ctx, frg::FusedContractArgs &a) {
+    const bool on = ctx->kskip_on;
+    for (int t = 0; t < 3; ++t) {
+        const int cls = t == frg::TERM_PP ? 0 : 1;
+        a.cperm[t] = on ? ctx->d_cperm[cls] : ctx->d_cperm_id;
+        a.koff[t] = on ? ctx->d_koff[cls] : ctx->d_koff_dense;
+        a.klist[t] = on ? ctx->d_klist[cls] : ctx->d_klist_dense;
+    }
+}
+
 // prep + bubbles into the context's bubble tensor (or caller buffers)
 frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *state, double c,
                        void *bpp, void *bph, hipStream_t s, bool reps_only = false) {
@@ -296,17 +442,6 @@ frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *sta
     }
     HIPCHK(hipGetLastError());
     return FRG_OK;
-}
-
-// K parts of the fused contraction: enough blocks for several rounds over the
-// 256 compute units (measured best at N = 96: 4 parts); FRG_KSPLIT overrides
-int ksplit(frg_ctx ctx) {
-    if (ctx->ks_override > 0) return ctx->ks_override;
-    const int N = ctx->g.N;
-    const int bm = frg::contract_block_rows(N);
-    const int64_t tiles = 3LL * ((N + bm - 1) / bm) * ((static_cast<int64_t>(N) * N + 63) / 64);
-    int64_t ks = (1728 + tiles - 1) / tiles;
-    return static_cast<int>(ks < 1 ? 1 : (ks > 8 ? 8 : ks));
 }
 
 frg_status ensure_c(frg_ctx ctx, int KS) {
@@ -346,6 +481,7 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     a.B[frg::TERM_PHC] = a.B[frg::TERM_PHD] = bph;
     a.colrow[frg::TERM_PP] = sym ? ctx->d_colsym_pp : ctx->d_colrow_pp;
     a.colrow[frg::TERM_PHC] = a.colrow[frg::TERM_PHD] = sym ? ctx->d_colsym_ph : ctx->d_colrow_ph;
+    set_tiles(ctx, a);
     a.C[frg::TERM_PP] = Cpp;
     a.C[frg::TERM_PHC] = Cc;
     a.C[frg::TERM_PHD] = Cd;
@@ -354,27 +490,14 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
         if (!split) frg::launch_layout_f64(V, N, ctx->d_perm, s);
         else frg::launch_layout_split(V, N, ctx->d_ahl, ctx->d_g32, s);
     }
-    if (!split) {
-        const double *P = ctx->d_perm;
-        a.A64[frg::TERM_PP][0] = P;          a.G64[frg::TERM_PP][0] = V;
-        a.A64[frg::TERM_PHC][0] = V;         a.G64[frg::TERM_PHC][0] = P + n3;
-        a.A64[frg::TERM_PHD][0] = P + 2 * n3; a.G64[frg::TERM_PHD][0] = P + 4 * n3;
-        a.A64[frg::TERM_PHD][1] = P + 3 * n3; a.G64[frg::TERM_PHD][1] = P + 4 * n3;
-    } else {
-        const uint16_t *H = ctx->d_ahl;
-        const float *G = ctx->d_g32;
-        a.Ahl[frg::TERM_PP][0] = H;          a.G32[frg::TERM_PP][0] = G;
-        a.Ahl[frg::TERM_PHC][0] = H + 2 * n3; a.G32[frg::TERM_PHC][0] = G + n3;
-        a.Ahl[frg::TERM_PHD][0] = H + 4 * n3; a.G32[frg::TERM_PHD][0] = G + 2 * n3;
-        a.Ahl[frg::TERM_PHD][1] = H + 6 * n3; a.G32[frg::TERM_PHD][1] = G + 2 * n3;
-    }
+    set_operands(a, split, V, ctx->d_perm, ctx->d_ahl, ctx->d_g32, n3);
     {
         KTimer kt(ctx, FRG_K_CONTRACT, s);
         frg::launch_contract_fused(a, split, s);
     }
     {
         KTimer kt(ctx, FRG_K_COMBINE, s);
-        frg::launch_combine(Cpp, Cc, Cd, n3, KS, ctx->d_T, scale_by_T, F, s);
+        frg::launch_combine(Cpp, Cc, Cd, N, KS, col_pos(ctx, 0), col_pos(ctx, 1), ctx->d_T, scale_by_T, F, s);
     }
     HIPCHK(hipGetLastError());
     return FRG_OK;
@@ -517,6 +640,7 @@ frg_status frg_create(const frg_params *p, frg_ctx *out) {
         return bail(FRG_EDEVICE);
     }
     if ((st = build_orbits(ctx))) return bail(st);
+    if ((st = build_ktiles(ctx))) return bail(st);
     *out = ctx;
     return FRG_OK;
 }
@@ -527,7 +651,10 @@ frg_status frg_destroy(frg_ctx ctx) {
                     ctx->d_colrow_pp, ctx->d_colrow_ph, ctx->d_pa64, ctx->d_T, ctx->d_pa32,
                     ctx->d_B64, ctx->d_B32, ctx->d_perm, ctx->d_ahl, ctx->d_g32, ctx->d_C,
                     ctx->d_yt, ctx->d_y5, ctx->d_partial, ctx->d_state, ctx->d_rowlist,
-                    ctx->d_colsym_pp, ctx->d_colsym_ph};
+                    ctx->d_colsym_pp, ctx->d_colsym_ph, ctx->d_cperm[0], ctx->d_cperm[1],
+                    ctx->d_koff[0], ctx->d_koff[1], ctx->d_klist[0], ctx->d_klist[1],
+                    ctx->d_cperm_id, ctx->d_koff_dense, ctx->d_klist_dense, ctx->d_cpos[0],
+                    ctx->d_cpos[1]};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (int j = 0; j < 7; ++j)
@@ -771,6 +898,28 @@ frg_status frg_symmetry(frg_ctx ctx, int32_t *active, int32_t *rows_computed) {
     return FRG_OK;
 }
 
+frg_status frg_set_kskip(frg_ctx ctx, int32_t enable) {
+    TRY(check_ctx(ctx));
+    if (!enable) TRY(ensure_dense_tiles(ctx));
+    ctx->kskip_on = enable != 0;
+    return FRG_OK;
+}
+
+frg_status frg_kskip(frg_ctx ctx, int32_t *active, double *executed_frac) {
+    TRY(check_ctx(ctx));
+    if (active) *active = ctx->kskip_on ? 1 : 0;
+    if (executed_frac) {
+        const int NC = ctx->g.N * ctx->g.N;
+        const double dense = static_cast<double>((NC + frg::kContractCols - 1) / frg::kContractCols) *
+                             (NC / frg::kContractChunk);
+        // work weights of the channels: pp 1, phc 1, phd 2 products per chunk
+        *executed_frac = ctx->kskip_on
+                             ? (ctx->kchunks_active[0] + 3.0 * ctx->kchunks_active[1]) / (4.0 * dense)
+                             : 1.0;
+    }
+    return FRG_OK;
+}
+
 frg_status frg_profile_begin(frg_ctx ctx) {
     TRY(check_ctx(ctx));
     ctx->recs.clear();
@@ -820,8 +969,8 @@ struct frg_batch_s {
     double **d_states = nullptr;
     double *d_state_all = nullptr, *h_state_all = nullptr;
     int2 *d_it_prep = nullptr, *d_it_bub = nullptr, *d_it_n3 = nullptr, *d_it_red = nullptr,
-         *d_it_con = nullptr;
-    int n_prep = 0, n_bub = 0, n_n3 = 0, n_red = 0, n_con = 0;
+         *d_it_con = nullptr, *d_it_comb = nullptr;
+    int n_prep = 0, n_bub = 0, n_n3 = 0, n_red = 0, n_con = 0, n_comb = 0;
     // contraction work list grouped by block height class (32, 64, 96), each cut
     // into 8 per-XCD queues: d_q[class] = {start[8], count[8]}
     int con_count[3] = {0, 0, 0};
@@ -865,7 +1014,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     std::vector<frg::FusedContractArgs> ca[3];
     for (int s = 0; s < 3; ++s) ca[s].resize(b->n);
     std::vector<double *> st(b->n);
-    std::vector<int2> it_prep, it_bub, it_n3, it_red;
+    std::vector<int2> it_prep, it_bub, it_n3, it_red, it_comb;
     struct Item { int2 it; int cls, queue; double flow_cost, cost; };
     std::vector<Item> con;
     for (int f = 0; f < b->n; ++f) {
@@ -892,6 +1041,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         for (int j = 0; j < 7; ++j) A.k[j] = c->d_k[j];
         A.yt = c->d_yt; A.y5 = c->d_y5; A.partial = c->d_partial;
         A.perm = c->d_perm; A.ahl = c->d_ahl; A.g32 = c->d_g32; A.C = c->d_C; A.KS = KS;
+        A.ppos = col_pos(c, 0); A.phpos = col_pos(c, 1);
         st[f] = A.state;
         frg::BubbleArgs bb = bubble_args(c, split, bpp, bph);
         if (sym) {
@@ -913,23 +1063,11 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
             a.B[frg::TERM_PHC] = a.B[frg::TERM_PHD] = bph;
             a.colrow[frg::TERM_PP] = sym ? c->d_colsym_pp : c->d_colrow_pp;
             a.colrow[frg::TERM_PHC] = a.colrow[frg::TERM_PHD] = sym ? c->d_colsym_ph : c->d_colrow_ph;
+            set_tiles(c, a);
             a.C[frg::TERM_PP] = c->d_C;
             a.C[frg::TERM_PHC] = c->d_C + KS * n3;
             a.C[frg::TERM_PHD] = c->d_C + 2 * KS * n3;
-            if (!split) {
-                const double *P = c->d_perm;
-                a.A64[frg::TERM_PP][0] = P;          a.G64[frg::TERM_PP][0] = V;
-                a.A64[frg::TERM_PHC][0] = V;         a.G64[frg::TERM_PHC][0] = P + n3;
-                a.A64[frg::TERM_PHD][0] = P + 2 * n3; a.G64[frg::TERM_PHD][0] = P + 4 * n3;
-                a.A64[frg::TERM_PHD][1] = P + 3 * n3; a.G64[frg::TERM_PHD][1] = P + 4 * n3;
-            } else {
-                const uint16_t *H = c->d_ahl;
-                const float *G = c->d_g32;
-                a.Ahl[frg::TERM_PP][0] = H;          a.G32[frg::TERM_PP][0] = G;
-                a.Ahl[frg::TERM_PHC][0] = H + 2 * n3; a.G32[frg::TERM_PHC][0] = G + n3;
-                a.Ahl[frg::TERM_PHD][0] = H + 4 * n3; a.G32[frg::TERM_PHD][0] = G + 2 * n3;
-                a.Ahl[frg::TERM_PHD][1] = H + 6 * n3; a.G32[frg::TERM_PHD][1] = G + 2 * n3;
-            }
+            set_operands(a, split, V, c->d_perm, c->d_ahl, c->d_g32, n3);
         }
         for (int k = 0; k < (g.np + 255) / 256; ++k) it_prep.push_back(make_int2(f, k));
         const int rpb = frg::bubble_rows_per_block();
@@ -937,6 +1075,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         for (int ch = 0; ch < chunks; ++ch)
             for (int a = 0; a < g.N; ++a) it_bub.push_back(make_int2(f, (ch << 8) | a));
         for (int64_t k = 0; k < (n3 + 255) / 256; ++k) it_n3.push_back(make_int2(f, static_cast<int>(k)));
+        for (int k = 0; k < frg::combine_tiles(g.N); ++k) it_comb.push_back(make_int2(f, k));
         for (int k = 0; k < A.nred; ++k) it_red.push_back(make_int2(f, k));
         const frg::FusedContractArgs &a0 = ca[0][f];
         const int per_term = a0.mtiles * a0.ctiles * KS;
@@ -1003,11 +1142,13 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     TRY(bupload(&b->d_it_n3, it_n3));
     TRY(bupload(&b->d_it_red, it_red));
     TRY(bupload(&b->d_it_con, it_con));
+    TRY(bupload(&b->d_it_comb, it_comb));
     b->n_prep = static_cast<int>(it_prep.size());
     b->n_bub = static_cast<int>(it_bub.size());
     b->n_n3 = static_cast<int>(it_n3.size());
     b->n_red = static_cast<int>(it_red.size());
     b->n_con = static_cast<int>(it_con.size());
+    b->n_comb = static_cast<int>(it_comb.size());
     b->built_prec = prec;
     if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; b->exec_prec = -1; }
     return FRG_OK;
@@ -1031,7 +1172,7 @@ void batch_rhs_launch(frg_batch b, bool split, double c_stage, int src, int stag
         frg::launch_contract_persistent(b->d_ca[src], b->d_it_con, b->d_q + k * 16, b->d_q + k * 16 + 8,
                                         b->d_counter + 8 * k, states, grid, bms[k], split, s);
     }
-    frg::launch_combine_b(b->d_fa, b->d_it_n3, b->n_n3, stage, s);
+    frg::launch_combine_b(b->d_fa, b->d_it_comb, b->n_comb, stage, s);
 }
 
 void batch_step_launch(frg_batch b, const frg_flow_opts *o, hipStream_t s) {
@@ -1107,7 +1248,7 @@ frg_status frg_batch_destroy(frg_batch b) {
     for (frg_ctx c : b->ctx) frg_destroy(c);
     void *ptrs[] = {b->d_fa, b->d_ba, b->d_ca[0], b->d_ca[1], b->d_ca[2], b->d_states, b->d_state_all,
                     b->d_it_prep, b->d_it_bub, b->d_it_n3, b->d_it_red, b->d_it_con, b->d_counter,
-                    b->d_q, b->d_it_flat};
+                    b->d_q, b->d_it_flat, b->d_it_comb};
     for (void *p : ptrs)
         if (p) hipFree(p);
     if (b->h_state_all) hipHostFree(b->h_state_all);
@@ -1251,8 +1392,8 @@ frg_status frg_batch_rhs(frg_batch b, const double *T, double *const *d_V, doubl
         frg_ctx c = b->ctx[f];
         // F from the channel partials (the batched combine left T*F in k[0])
         const int KS = ksplit(c);
-        frg::launch_combine(c->d_C, c->d_C + KS * c->n3, c->d_C + 2 * KS * c->n3, c->n3, KS, c->d_T, 0,
-                            d_F[f], s);
+        frg::launch_combine(c->d_C, c->d_C + KS * c->n3, c->d_C + 2 * KS * c->n3, c->g.N, KS,
+                            col_pos(c, 0), col_pos(c, 1), c->d_T, 0, d_F[f], s);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(b->ev_out, s));

@@ -68,7 +68,8 @@ void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipS
 
 enum Term { TERM_PP = 0, TERM_PHC = 1, TERM_PHD = 2 };
 
-// all three channels in one launch; term t writes C[t] + part * n3 for K part `part`
+// all three channels in one launch; term t writes C[t] + part * n3 for K part
+// `part`, laid out [tile position p][m] (p holds column cperm[t][p])
 struct FusedContractArgs {
     int N, KS, mtiles, ctiles;
     int64_t n3;
@@ -76,6 +77,13 @@ struct FusedContractArgs {
     // column c -> (stored row << 3) | o: the column's bubble row is the stored
     // row acted on by C4v element o, B_col(a', b') = B_stored(o^-1 a', o^-1 b')
     const int32_t *colrow[3];
+    // column tiles: tile position -> column (columns ordered so that a tile's
+    // transfers are close in k space), and per tile the list of 8-wide k
+    // chunks that hold a structural nonzero of any of its bubble rows
+    // (klist[koff[t] .. koff[t+1]) in increasing order)
+    const int32_t *cperm[3];
+    const int32_t *koff[3];
+    const int32_t *klist[3];
     const double *A64[3][2];
     const uint16_t *Ahl[3][2];
     const double *G64[3][2];
@@ -84,10 +92,21 @@ struct FusedContractArgs {
 };
 void launch_contract_fused(const FusedContractArgs &a, bool split, hipStream_t s);
 int contract_block_rows(int N);
+constexpr int kContractCols = 64;     // columns per contraction tile
+constexpr int kContractChunk = 8;     // k chunk of the active lists
+// flags[t][j] = 1 if some column at tile position t*64 .. t*64+63 has a
+// point of the second-line table in k chunk j (k = a*N + b, chunk = k / 8);
+// colfull[c] is the full row (pp rows, then ph rows) of column c
+void launch_tile_pattern(const uint8_t *bins, const int32_t *colfull, const int32_t *cperm, int N,
+                         int nf, int np, uint8_t *flags, hipStream_t s);
 
-// F = scale * sum_parts (Cc - Cpp + Cd), scale = T when scale_by_T
-void launch_combine(const double *Cpp, const double *Cc, const double *Cd, int64_t n, int parts,
-                    const double *Tdev, int scale_by_T, double *F, hipStream_t s);
+// F[j1][j2][j3] = scale * (-Cpp[ppos(j1,j2)][j3] + Cc[phpos(j2,j3)][j1] + Cd[phpos(j1,j3)][j2]),
+// each summed over the K parts; ppos / phpos give the tile position of a
+// column (pp: j1*N+j2, ph: y*N+x); scale = T when scale_by_T
+void launch_combine(const double *Cpp, const double *Cc, const double *Cd, int N, int parts,
+                    const int32_t *ppos, const int32_t *phpos, const double *Tdev, int scale_by_T,
+                    double *F, hipStream_t s);
+int combine_tiles(int N);   // blocks of one combine
 
 // ----------------------------------------------------------------- RK kernels
 struct RkStageArgs {
@@ -132,6 +151,7 @@ struct FlowArgs {
     float *g32;
     double *C;   // [3][KS][n3]
     int KS;
+    const int32_t *ppos, *phpos;   // tile position of each pp / ph column
 };
 enum { SRC_V = 0, SRC_YT = 1, SRC_Y5 = 2 };
 

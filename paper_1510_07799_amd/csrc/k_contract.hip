@@ -14,15 +14,26 @@
 // One launch covers all three channels.  A block owns a BM x BC output tile
 // of one channel over one K range (K split in KS parts to fill the chip; the
 // parts are summed in a fixed order afterwards, so the result is
-// deterministic).  Per K chunk the A tile is read with 16-byte loads and the
+// deterministic).
+//
+// A bubble row is zero wherever no fine point of patch a has its second
+// momentum in patch b (about 80% of the entries at N = 96); which entries
+// these are does not depend on T.  Columns are ordered along a Hilbert curve
+// of their transfer momentum, so the 64 columns of a tile have nearly the
+// same nonzero pattern, and each tile iterates only over the 8-wide k chunks
+// where any of its rows has a point (a list made once per context from the
+// second-line table).  The skipped products are exact zeros.
+//
+// Per K step the A tile is read with 16-byte loads and the
 // B-side tile Z = B_row(c)[k] g(c,k) is formed in registers from one bubble
 // row per column; both are stored to LDS in the matrix-core operand layout,
-// and the global loads of the next chunk are issued before the MFMAs of the
+// and the global loads of the next step are issued before the MFMAs of the
 // current one.  Four waves in a 2 x 2 arrangement each own (BM/2) x (BC/2),
 // so every operand fragment read from LDS feeds several MFMAs.
-//   FP64:  v_mfma_f64_16x16x4f64, K chunk 32.
+//   FP64:  v_mfma_f64_16x16x4f64, K step 16 (two list chunks).
 //   split: A and Z as bf16 hi + lo, three v_mfma_f32_16x16x32_bf16 per
-//          k-step (hi*hi + hi*lo + lo*hi), FP32 accumulation, K chunk 64.
+//          k-step (hi*hi + hi*lo + lo*hi), FP32 accumulation, K step 32
+//          (four list chunks).
 #include "frg_internal.h"
 
 namespace frg {
@@ -36,7 +47,7 @@ typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
-constexpr int BC = 64;         // output columns (c) per block
+constexpr int BC = kContractCols;   // output columns (c) per block
 
 // Pointers read from a descriptor in memory are generic to the compiler, which
 // then emits FLAT accesses (they share the LDS wait counter and serialise the
@@ -52,15 +63,6 @@ __device__ __forceinline__ GLOBAL_AS T *gstore_ptr(T *p) {
     return reinterpret_cast<GLOBAL_AS T *>(reinterpret_cast<uintptr_t>(p));
 }
 constexpr int kThreads = 256;
-
-// output index of C[m, c] in the F layout of the term
-template <int TERM>
-__device__ __forceinline__ int64_t out_index(int N, int m, int c) {
-    const int64_t K = static_cast<int64_t>(N) * N;
-    if (TERM == TERM_PP) return static_cast<int64_t>(c) * N + m;          // F[j1][j2][j3=m]
-    if (TERM == TERM_PHC) return static_cast<int64_t>(m) * K + c;         // F[j1=m][j2][j3], c=j2*N+j3
-    return static_cast<int64_t>(c / N) * K + static_cast<int64_t>(m) * N + (c % N);  // F[j1][j2=m][j3]
-}
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
     uint32_t u = __float_as_uint(x);
@@ -160,6 +162,32 @@ __device__ __forceinline__ Work decode_block(const FusedContractArgs &P, int id)
     return w;
 }
 
+// The active k chunks of a block: entries [st_lo*G, st_hi*G) of its column
+// tile's list, G chunks per step (K part ks of KS takes an equal share of the
+// tile's steps).  Entries past the list read as -1 (a zero chunk).  Each
+// thread reads only the entries of the list slots its loads serve, one step
+// ahead of their use, as ordinary vector loads: a uniform (scalar) load would
+// share its wait counter with the LDS traffic of the MFMA loop.
+template <int G>
+struct TileK {
+    const GLOBAL_AS int32_t *kl;
+    int nk, st_lo, st_hi;
+    __device__ __forceinline__ TileK(const FusedContractArgs &P, int term, const Work &w) {
+        const GLOBAL_AS int32_t *koff = gload_ptr(P.koff[term]);
+        const int kbeg = koff[w.ctile];
+        nk = koff[w.ctile + 1] - kbeg;
+        kl = gload_ptr(P.klist[term]) + kbeg;
+        const int nst = (nk + G - 1) / G;
+        st_lo = static_cast<int>((static_cast<int64_t>(nst) * w.ks) / P.KS);
+        st_hi = static_cast<int>((static_cast<int64_t>(nst) * (w.ks + 1)) / P.KS);
+    }
+    // chunk id in slot `slot` (0 .. G-1) of step st
+    __device__ __forceinline__ int entry(int st, int slot) const {
+        const int i = st * G + slot;
+        return i < nk ? kl[i] : -1;
+    }
+};
+
 // ------------------------------------------------------------------ FP64
 template <int TERM, int BM>
 __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work &w, double *smem) {
@@ -167,7 +195,8 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
     constexpr int ZK = BK / 4;                          // k per thread in the Z loader
     constexpr int NP = TERM == TERM_PHD ? 2 : 1;
     constexpr int LDA = BK + 1;
-    constexpr int NCH = BM * BK / 2;                    // 16-byte A chunks per operand
+    constexpr int G = BK / kContractChunk;
+    constexpr int NCH = G * BM * 4;                     // 16-byte A pieces per operand and step
     constexpr int ACH = (NCH + kThreads - 1) / kThreads;
     double *sA = smem;                        // [NP][BM][LDA]
     double *sZ = smem + NP * BM * LDA;        // [NP][BC][LDA]
@@ -175,55 +204,60 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
     const int K = N * N;
     const int NC = N * N;
     const int m0 = w.mtile * BM, c0 = w.ctile * BC;
-    const int kchunks = (K + BK - 1) / BK;
-    const int kc_lo = static_cast<int>((static_cast<int64_t>(kchunks) * w.ks) / P.KS);
-    const int kc_hi = static_cast<int>((static_cast<int64_t>(kchunks) * (w.ks + 1)) / P.KS);
+    const TileK<G> tk(P, TERM, w);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const GLOBAL_AS double *A0 = gload_ptr(P.A64[TERM][0]);
     const GLOBAL_AS double *A1 = gload_ptr(P.A64[TERM][1]);
     const GLOBAL_AS double *B = gload_ptr(static_cast<const double *>(P.B[TERM]));
     const GLOBAL_AS int32_t *colrow = gload_ptr(P.colrow[TERM]);
 
-    // Z loader: column cl, ZK consecutive k
+    // A loader (chunk-major operand): piece ch is 16 bytes of row `row` of list
+    // slot `slot`; consecutive lanes read consecutive bytes of one chunk
+    auto apiece = [&](int i, int &slot, int &row, int &part) {
+        const int ch = tid + i * kThreads;
+        slot = ch / (BM * 4);
+        row = (ch % (BM * 4)) >> 2;
+        part = ch & 3;
+    };
+    // Z loader: column at tile position cl, ZK consecutive k of one list chunk
     const int cl = tid >> 2, zk = (tid & 3) * ZK;
-    const int c = c0 + cl;
-    const bool cvalid = c < NC;
+    const int zslot = zk / kContractChunk, zoff = zk % kContractChunk;
+    const bool cvalid = c0 + cl < NC;
+    const int c = cvalid ? gload_ptr(P.cperm[TERM])[c0 + cl] : 0;
     const RowMap rm = decode_rowmap(cvalid ? colrow[c] : 0, N);
     const GLOBAL_AS double *brow = B + static_cast<int64_t>(rm.row) * K;
-    const GLOBAL_AS double *g0 = gload_ptr(P.G64[TERM][0]) + static_cast<int64_t>(cvalid ? c : 0) * N;
+    const GLOBAL_AS double *g0 = gload_ptr(P.G64[TERM][0]) + static_cast<int64_t>(c) * N;
     const GLOBAL_AS double *g1 = TERM == TERM_PHD
-                                     ? gload_ptr(P.G64[TERM][1]) + static_cast<int64_t>(cvalid ? c / N : 0) * K
+                                     ? gload_ptr(P.G64[TERM][1]) + static_cast<int64_t>(c / N) * K
                                      : nullptr;
 
     d2_t ra[NP][ACH];
     double rb[ZK], rg0[ZK], rg1[ZK];
 
-    auto load = [&](int kc) {
-        const int k0 = kc * BK;
+    // ea[i]: list entry of the slot of A piece i; ez: of the Z window
+    auto load = [&](const int (&ea)[ACH], int ez) {
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const GLOBAL_AS double *Ap = p == 0 ? A0 : A1;
 #pragma unroll
             for (int i = 0; i < ACH; ++i) {
-                const int ch = tid + i * kThreads;         // chunk id: row ch / (BK/2), col pair
-                const int row = ch / (BK / 2), kp = (ch % (BK / 2)) * 2;
-                const int m = m0 + row, k = k0 + kp;
-                if (ch >= NCH) {
+                int slot, row, part;
+                apiece(i, slot, row, part);
+                const int m = m0 + row;
+                if (tid + i * kThreads < NCH && ea[i] >= 0 && m < N)
+                    ra[p][i] = *reinterpret_cast<const GLOBAL_AS d2_t *>(
+                        Ap + (static_cast<int64_t>(ea[i]) * N + m) * kContractChunk + part * 2);
+                else
                     ra[p][i] = d2_t{0.0, 0.0};
-                } else if (m < N && k + 1 < K) {
-                    ra[p][i] = *reinterpret_cast<const GLOBAL_AS d2_t *>(Ap + static_cast<int64_t>(m) * K + k);
-                } else {
-                    ra[p][i][0] = (m < N && k < K) ? Ap[static_cast<int64_t>(m) * K + k] : 0.0;
-                    ra[p][i][1] = 0.0;
-                }
             }
         }
-        const int kb = k0 + zk;
-        load_bubble_window<ZK, 2, double, d2_t>(brow, rm, N, K, kb, cvalid, rb);
+        const bool zok = cvalid && ez >= 0;
+        const int kb = zok ? ez * kContractChunk + zoff : 0;
+        load_bubble_window<ZK, 2, double, d2_t>(brow, rm, N, K, kb, zok, rb);
         int a = kb / N, b = kb - a * N;
 #pragma unroll
         for (int q = 0; q < ZK; ++q) {
-            const bool ok = cvalid && kb + q < K;
+            const bool ok = zok && kb + q < K;
             if (TERM == TERM_PP) rg0[q] = ok ? g0[a] : 0.0;
             else rg0[q] = ok ? g0[b] : 0.0;
             if (TERM == TERM_PHD) rg1[q] = ok ? g1[kb + q] : 0.0;
@@ -235,9 +269,10 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
         for (int p = 0; p < NP; ++p)
 #pragma unroll
             for (int i = 0; i < ACH; ++i) {
-                const int ch = tid + i * kThreads;
-                if (ch >= NCH) continue;
-                const int row = ch / (BK / 2), kp = (ch % (BK / 2)) * 2;
+                if (tid + i * kThreads >= NCH) continue;
+                int slot, row, part;
+                apiece(i, slot, row, part);
+                const int kp = slot * kContractChunk + part * 2;
                 sA[(p * BM + row) * LDA + kp] = ra[p][i][0];
                 sA[(p * BM + row) * LDA + kp + 1] = ra[p][i][1];
             }
@@ -256,11 +291,28 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
         acc[i][0] = d4_t{0.0, 0.0, 0.0, 0.0};
         acc[i][1] = d4_t{0.0, 0.0, 0.0, 0.0};
     }
-    if (kc_lo < kc_hi) load(kc_lo);
-    for (int kc = kc_lo; kc < kc_hi; ++kc) {
+    int aslot[ACH];
+#pragma unroll
+    for (int i = 0; i < ACH; ++i) {
+        int row, part;
+        apiece(i, aslot[i], row, part);
+    }
+    int ea[ACH], ez;
+    auto fetch = [&](int st) {
+#pragma unroll
+        for (int i = 0; i < ACH; ++i) ea[i] = tid + i * kThreads < NCH ? tk.entry(st, aslot[i]) : -1;
+        ez = tk.entry(st, zslot);
+    };
+    fetch(tk.st_lo);
+    if (tk.st_lo < tk.st_hi) load(ea, ez);
+    fetch(tk.st_lo + 1);
+    for (int st = tk.st_lo; st < tk.st_hi; ++st) {
         store();
         __syncthreads();
-        if (kc + 1 < kc_hi) load(kc + 1);
+        if (st + 1 < tk.st_hi) {
+            load(ea, ez);
+            fetch(st + 2);
+        }
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
 #pragma unroll
@@ -280,19 +332,21 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
         }
         __syncthreads();
     }
-    // f64 16x16x4 accumulator layout: lane l, register r holds row (l>>4) + 4r, column l&15
+    // f64 16x16x4 accumulator layout: lane l, register r holds row (l>>4) + 4r, column l&15;
+    // output C[ks][tile position][m]: a block's tile is one contiguous range
     GLOBAL_AS double *Cout = gstore_ptr(P.C[TERM]) + static_cast<int64_t>(w.ks) * P.n3;
 #pragma unroll
-    for (int ri = 0; ri < RT; ++ri)
+    for (int ci = 0; ci < 2; ++ci) {
+        const int pos = c0 + wc * 32 + ci * 16 + (lane & 15);
+        if (pos >= NC) continue;
 #pragma unroll
-        for (int ci = 0; ci < 2; ++ci) {
-            const int cc = c0 + wc * 32 + ci * 16 + (lane & 15);
+        for (int ri = 0; ri < RT; ++ri)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int m = m0 + wm * (BM / 2) + ri * 16 + (lane >> 4) + 4 * r;
-                if (m < N && cc < NC) Cout[out_index<TERM>(N, m, cc)] = acc[ri][ci][r];
+                if (m < N) Cout[static_cast<int64_t>(pos) * N + m] = acc[ri][ci][r];
             }
-        }
+    }
 }
 
 // ------------------------------------------------------------------ split BF16
@@ -302,8 +356,8 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     constexpr int ZK = BK / 4;    // k per thread in the Z loader
     constexpr int LD = BK + 8;    // bf16 row pitch: rows stay 16-byte aligned
     constexpr int NP = TERM == TERM_PHD ? 2 : 1;
-    constexpr int CPR = BK / 8;                         // 16-byte chunks per row and plane
-    constexpr int NCH = BM * CPR;
+    constexpr int G = BK / kContractChunk;
+    constexpr int NCH = G * BM;                         // 16-byte A pieces (one chunk of one row)
     constexpr int ACH = (NCH + kThreads - 1) / kThreads;
     uint16_t *sA = smem;                           // [NP][2][BM][LD]
     uint16_t *sZ = smem + NP * 2 * BM * LD;        // [NP][2][BC][LD]
@@ -312,54 +366,51 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     const int NC = N * N;
     const int64_t n3 = P.n3;
     const int m0 = w.mtile * BM, c0 = w.ctile * BC;
-    const int kchunks = (K + BK - 1) / BK;
-    const int kc_lo = static_cast<int>((static_cast<int64_t>(kchunks) * w.ks) / P.KS);
-    const int kc_hi = static_cast<int>((static_cast<int64_t>(kchunks) * (w.ks + 1)) / P.KS);
+    const TileK<G> tk(P, TERM, w);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const GLOBAL_AS uint16_t *Ahl[2] = {gload_ptr(P.Ahl[TERM][0]), gload_ptr(P.Ahl[TERM][1])};
     const GLOBAL_AS float *B = gload_ptr(static_cast<const float *>(P.B[TERM]));
     const GLOBAL_AS int32_t *colrow = gload_ptr(P.colrow[TERM]);
 
-    const int cl = tid >> 2, zk = (tid & 3) * ZK;   // Z loader: column cl, ZK consecutive k
-    const int c = c0 + cl;
-    const bool cvalid = c < NC;
+    // A piece ch = tid + i * kThreads: row ch % BM of list slot ch / BM, so
+    // consecutive lanes read consecutive rows of one chunk (chunk-major operand)
+    static_assert(ZK == kContractChunk && G == 4, "split slots");
+    // Z loader: column at tile position cl, list slot zslot (one chunk)
+    const int zslot = tid & 3;
+    const int cl = tid >> 2, zk = zslot * ZK;
+    const bool cvalid = c0 + cl < NC;
+    const int c = cvalid ? gload_ptr(P.cperm[TERM])[c0 + cl] : 0;
     const RowMap rm = decode_rowmap(cvalid ? colrow[c] : 0, N);
     const GLOBAL_AS float *brow = B + static_cast<int64_t>(rm.row) * K;
-    const GLOBAL_AS float *g0 = gload_ptr(P.G32[TERM][0]) + static_cast<int64_t>(cvalid ? c : 0) * N;
+    const GLOBAL_AS float *g0 = gload_ptr(P.G32[TERM][0]) + static_cast<int64_t>(c) * N;
     const GLOBAL_AS float *g1 = TERM == TERM_PHD
-                                    ? gload_ptr(P.G32[TERM][1]) + static_cast<int64_t>(cvalid ? c / N : 0) * K
+                                    ? gload_ptr(P.G32[TERM][1]) + static_cast<int64_t>(c / N) * K
                                     : nullptr;
 
     u32x4_t ra[NP][2][ACH];
     float rb[ZK], rg0[ZK], rg1[ZK];
 
-    auto load = [&](int kc) {
-        const int k0 = kc * BK;
+    // ea[i]: list entry of the slot of A piece i; e: of the Z window
+    auto load = [&](const int (&ea)[ACH], int e) {
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
             for (int hl = 0; hl < 2; ++hl)
 #pragma unroll
                 for (int i = 0; i < ACH; ++i) {
-                    const int ch = tid + i * kThreads;            // row ch / CPR, 8 bf16 per chunk
-                    const int row = ch / CPR, kq = (ch % CPR) * 8;
-                    const int m = m0 + row, k = k0 + kq;
-                    const GLOBAL_AS uint16_t *src = Ahl[p] + hl * n3 + static_cast<int64_t>(m) * K + k;
-                    if (ch >= NCH) {
+                    const int ch = tid + i * kThreads;
+                    const int m = m0 + ch % BM;
+                    if (ch < NCH && ea[i] >= 0 && m < N)
+                        ra[p][hl][i] = *reinterpret_cast<const GLOBAL_AS u32x4_t *>(
+                            Ahl[p] + hl * n3 + (static_cast<int64_t>(ea[i]) * N + m) * kContractChunk);
+                    else
                         ra[p][hl][i] = u32x4_t{0u, 0u, 0u, 0u};
-                    } else if (m < N && k + 8 <= K) {
-                        ra[p][hl][i] = *reinterpret_cast<const GLOBAL_AS u32x4_t *>(src);
-                    } else {
-                        u16x8_t v;
-#pragma unroll
-                        for (int q = 0; q < 8; ++q) v[q] = (m < N && k + q < K) ? src[q] : uint16_t(0);
-                        ra[p][hl][i] = *reinterpret_cast<u32x4_t *>(&v);
-                    }
                 }
-        const int kb = k0 + zk;
-        load_bubble_window<ZK, 4, float, f4_t>(brow, rm, N, K, kb, cvalid, rb);
+        const bool zok = cvalid && e >= 0;
+        const int kb = zok ? e * kContractChunk : 0;
+        load_bubble_window<ZK, 4, float, f4_t>(brow, rm, N, K, kb, zok, rb);
         int a = kb / N, b = kb - a * N;
-        if (TERM != TERM_PP && cvalid && b + ZK <= N && (b & 3) == 0 && (N & 3) == 0) {
+        if (TERM != TERM_PP && zok && b + ZK <= N && (b & 3) == 0 && (N & 3) == 0) {
 #pragma unroll
             for (int q = 0; q < ZK; q += 4) {
                 const f4_t v = *reinterpret_cast<const GLOBAL_AS f4_t *>(g0 + b + q);
@@ -369,13 +420,13 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
             int aa = a, bb = b;
 #pragma unroll
             for (int q = 0; q < ZK; ++q) {
-                const bool ok = cvalid && kb + q < K;
+                const bool ok = zok && kb + q < K;
                 rg0[q] = ok ? (TERM == TERM_PP ? g0[aa] : g0[bb]) : 0.f;
                 if (++bb == N) { bb = 0; ++aa; }
             }
         }
         if (TERM == TERM_PHD) {
-            if (cvalid && kb + ZK <= K) {
+            if (zok && kb + ZK <= K) {
 #pragma unroll
                 for (int q = 0; q < ZK; q += 4) {
                     const f4_t v = *reinterpret_cast<const GLOBAL_AS f4_t *>(g1 + kb + q);
@@ -383,7 +434,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
                 }
             } else {
 #pragma unroll
-                for (int q = 0; q < ZK; ++q) rg1[q] = (cvalid && kb + q < K) ? g1[kb + q] : 0.f;
+                for (int q = 0; q < ZK; ++q) rg1[q] = (zok && kb + q < K) ? g1[kb + q] : 0.f;
             }
         }
     };
@@ -396,7 +447,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
                 for (int i = 0; i < ACH; ++i) {
                     const int ch = tid + i * kThreads;
                     if (ch >= NCH) continue;
-                    const int row = ch / CPR, kq = (ch % CPR) * 8;
+                    const int row = ch % BM, kq = (ch / BM) * kContractChunk;
                     *reinterpret_cast<u32x4_t *>(sA + ((p * 2 + hl) * BM + row) * LD + kq) = ra[p][hl][i];
                 }
 #pragma unroll
@@ -422,11 +473,25 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
         acc[i][0] = f4_t{0.f, 0.f, 0.f, 0.f};
         acc[i][1] = f4_t{0.f, 0.f, 0.f, 0.f};
     }
-    if (kc_lo < kc_hi) load(kc_lo);
-    for (int kc = kc_lo; kc < kc_hi; ++kc) {
+    int ea[ACH], ez;
+    auto fetch = [&](int st) {
+#pragma unroll
+        for (int i = 0; i < ACH; ++i) {
+            const int ch = tid + i * kThreads;
+            ea[i] = ch < NCH ? tk.entry(st, ch / BM) : -1;
+        }
+        ez = tk.entry(st, zslot);
+    };
+    fetch(tk.st_lo);
+    if (tk.st_lo < tk.st_hi) load(ea, ez);
+    fetch(tk.st_lo + 1);
+    for (int st = tk.st_lo; st < tk.st_hi; ++st) {
         store();
         __syncthreads();
-        if (kc + 1 < kc_hi) load(kc + 1);
+        if (st + 1 < tk.st_hi) {
+            load(ea, ez);
+            fetch(st + 2);
+        }
 #pragma unroll
         for (int ks = 0; ks < BK / 32; ++ks) {
             const int kof = ks * 32 + (lane >> 4) * 8;
@@ -456,18 +521,23 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
         __syncthreads();
     }
     // bf16 16x16x32 accumulator layout: lane l, register r holds row 4(l>>4) + r, column l&15
+    // output C[ks][tile position][m]: four consecutive m per lane, one 32-byte store
+    // (N % 4 == 0, so a group of four rows is either wholly inside or outside)
     GLOBAL_AS double *Cout = gstore_ptr(P.C[TERM]) + static_cast<int64_t>(w.ks) * P.n3;
 #pragma unroll
-    for (int ri = 0; ri < RT; ++ri)
+    for (int ci = 0; ci < 2; ++ci) {
+        const int pos = c0 + wc * 32 + ci * 16 + (lane & 15);
+        if (pos >= NC) continue;
 #pragma unroll
-        for (int ci = 0; ci < 2; ++ci) {
-            const int cc = c0 + wc * 32 + ci * 16 + (lane & 15);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = m0 + wm * (BM / 2) + ri * 16 + 4 * (lane >> 4) + r;
-                if (m < N && cc < NC) Cout[out_index<TERM>(N, m, cc)] = static_cast<double>(acc[ri][ci][r]);
+        for (int ri = 0; ri < RT; ++ri) {
+            const int m = m0 + wm * (BM / 2) + ri * 16 + 4 * (lane >> 4);
+            if (m < N) {
+                const d4_t v{static_cast<double>(acc[ri][ci][0]), static_cast<double>(acc[ri][ci][1]),
+                             static_cast<double>(acc[ri][ci][2]), static_cast<double>(acc[ri][ci][3])};
+                *reinterpret_cast<GLOBAL_AS d4_t *>(Cout + static_cast<int64_t>(pos) * N + m) = v;
             }
         }
+    }
 }
 
 template <int BM, bool SPLIT>
@@ -562,10 +632,39 @@ void launch_bm(FusedContractArgs a, bool split, hipStream_t s) {
     }
 }
 
+// flags of the k chunks of one column tile (block = tile)
+__global__ __launch_bounds__(256) void tile_pattern_kernel(const uint8_t *__restrict__ bins,
+                                                           const int32_t *__restrict__ colfull,
+                                                           const int32_t *__restrict__ cperm, int N,
+                                                           int nf, int np, uint8_t *__restrict__ flags) {
+    extern __shared__ uint8_t sflag[];
+    const int NC = N * N, nch = NC / kContractChunk;
+    for (int j = threadIdx.x; j < nch; j += blockDim.x) sflag[j] = 0;
+    __syncthreads();
+    const int p0 = blockIdx.x * BC;
+    for (int cl = 0; cl < BC && p0 + cl < NC; ++cl) {
+        const uint8_t *row = bins + static_cast<int64_t>(colfull[cperm[p0 + cl]]) * np;
+        for (int p = threadIdx.x; p < np; p += blockDim.x) {
+            const int k = (p / nf) * N + row[p];
+            sflag[k / kContractChunk] = 1;
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < nch; j += blockDim.x) flags[static_cast<int64_t>(blockIdx.x) * nch + j] = sflag[j];
+}
+
 }  // namespace
 
 
 int contract_block_rows(int N) { return block_rows_of(N); }
+
+void launch_tile_pattern(const uint8_t *bins, const int32_t *colfull, const int32_t *cperm, int N, int nf,
+                         int np, uint8_t *flags, hipStream_t s) {
+    const int tiles = (N * N + BC - 1) / BC;
+    const size_t lds = static_cast<size_t>(N) * N / kContractChunk;
+    hipLaunchKernelGGL(tile_pattern_kernel, dim3(tiles), dim3(256), lds, s, bins, colfull, cperm, N, nf, np,
+                       flags);
+}
 
 size_t contract_lds_bytes(bool split) {
     return split ? sizeof(uint16_t) * (2 * 2 * 96 * (32 + 8) + 2 * 2 * BC * (32 + 8))

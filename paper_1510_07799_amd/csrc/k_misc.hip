@@ -126,26 +126,46 @@ __global__ void point_prep_kernel(const double *__restrict__ xi, const double *_
     }
 }
 
-// perm blocks (each N^3, index [i][j][k]):
-//   0: V[j][k][i]            pp A operand   (row j3=i, column (a,b)=(j,k))
-//   1: V[k][i][j]            phc gather     (row (y,x)=(i,j), b=k)
-//   2: -2V[j][i][k]+V[i][j][k]  phd A operand (row j2=i, (a,b)=(j,k))
-//   3: V[j][i][k]            phd A operand
-//   4: V[i][k][j]            phd gather (row (y,x)=(i,j), b=k)
-//   5: V[i][k][j]            phd gather (y=i, (a,b)=(j,k)) -- same values as block 4
-__global__ void layout_f64_kernel(const double *__restrict__ V, int N, double *__restrict__ perm) {
-    const int64_t n3 = static_cast<int64_t>(N) * N * N;
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= n3) return;
+// Contraction operands of V (each N^3; row m = i, contraction index
+// kk = j*N + k, i.e. (a, b) = (j, k)).  The A operands are stored chunk-major,
+// [kk / 8][m][kk % 8], so that one 8-wide k chunk of all rows is one
+// contiguous run: the contraction reads the chunks of a column tile's active
+// list, which need not be adjacent.  The gather tables stay row-major.
+//   FP64 perm blocks:
+//     0: V[j][k][i]                pp A       (row j3 = i)
+//     1: V[i][j][k]                phc A      (row j1 = i)
+//     2: -2 V[j][i][k] + V[i][j][k]  phd A      (row j2 = i)
+//     3: V[j][i][k]                phd A
+//     4: V[k][i][j]                phc gather (column (y, x) = (i, j), b = k)
+//     5: V[i][k][j]                phd gather (column (y, x) = (i, j), b = k;
+//                                              and y = i, (a, b) = (j, k))
+//   split: ahl = the four A blocks as bf16 hi, lo ([4][2][N^3], chunk-major);
+//          g32 = [V (pp gather), block 4, block 5] in FP32.
+__device__ __forceinline__ int64_t chunk_major(int64_t idx, int N) {
+    const int64_t K = static_cast<int64_t>(N) * N;
+    const int64_t i = idx / K, kk = idx - i * K;
+    return ((kk >> 3) * N + i) * 8 + (kk & 7);
+}
+
+__device__ __forceinline__ void layout_f64_elem(const double *__restrict__ V, int N, int64_t n3, int64_t idx,
+                                                double *__restrict__ perm) {
     const int k = static_cast<int>(idx % N);
     const int j = static_cast<int>((idx / N) % N);
     const int i = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
     auto at = [&](int x, int y, int z) { return V[(static_cast<int64_t>(x) * N + y) * N + z]; };
-    perm[idx] = at(j, k, i);
-    perm[n3 + idx] = at(k, i, j);
-    perm[2 * n3 + idx] = -2.0 * at(j, i, k) + at(i, j, k);
-    perm[3 * n3 + idx] = at(j, i, k);
-    perm[4 * n3 + idx] = at(i, k, j);
+    const int64_t cm = chunk_major(idx, N);
+    perm[cm] = at(j, k, i);
+    perm[n3 + cm] = at(i, j, k);
+    perm[2 * n3 + cm] = -2.0 * at(j, i, k) + at(i, j, k);
+    perm[3 * n3 + cm] = at(j, i, k);
+    perm[4 * n3 + idx] = at(k, i, j);
+    perm[5 * n3 + idx] = at(i, k, j);
+}
+
+__global__ void layout_f64_kernel(const double *__restrict__ V, int N, double *__restrict__ perm) {
+    const int64_t n3 = static_cast<int64_t>(N) * N * N;
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx < n3) layout_f64_elem(V, N, n3, idx, perm);
 }
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
@@ -157,14 +177,8 @@ __device__ __forceinline__ float bf16_to_f(uint16_t h) {
     return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
 
-// split path: A operands (blocks 0,2,3 above plus V itself for phc) as bf16
-// hi/lo, each [N][N*N]; ahl layout [4 operands][2 (hi,lo)][N^3].  FP32 gather
-// tables: g32 = [V (pp), block 1, block 4] each N^3.
-__global__ void layout_split_kernel(const double *__restrict__ V, int N, uint16_t *__restrict__ ahl,
-                                    float *__restrict__ g32) {
-    const int64_t n3 = static_cast<int64_t>(N) * N * N;
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx >= n3) return;
+__device__ __forceinline__ void layout_split_elem(const double *__restrict__ V, int N, int64_t n3, int64_t idx,
+                                                  uint16_t *__restrict__ ahl, float *__restrict__ g32) {
     const int k = static_cast<int>(idx % N);
     const int j = static_cast<int>((idx / N) % N);
     const int i = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
@@ -172,30 +186,95 @@ __global__ void layout_split_kernel(const double *__restrict__ V, int N, uint16_
     const float ops[4] = {static_cast<float>(at(j, k, i)), static_cast<float>(at(i, j, k)),
                           static_cast<float>(-2.0 * at(j, i, k) + at(i, j, k)),
                           static_cast<float>(at(j, i, k))};
+    const int64_t cm = chunk_major(idx, N);
 #pragma unroll
     for (int o = 0; o < 4; ++o) {
         const uint16_t hi = bf16_rne(ops[o]);
-        const uint16_t lo = bf16_rne(ops[o] - bf16_to_f(hi));
-        ahl[(2 * o) * n3 + idx] = hi;
-        ahl[(2 * o + 1) * n3 + idx] = lo;
+        ahl[(2 * o) * n3 + cm] = hi;
+        ahl[(2 * o + 1) * n3 + cm] = bf16_rne(ops[o] - bf16_to_f(hi));
     }
     g32[idx] = static_cast<float>(at(i, j, k));
     g32[n3 + idx] = static_cast<float>(at(k, i, j));
     g32[2 * n3 + idx] = static_cast<float>(at(i, k, j));
 }
 
-__global__ void combine_kernel(const double *__restrict__ Cpp, const double *__restrict__ Cc,
-                               const double *__restrict__ Cd, int64_t n, int parts,
-                               const double *__restrict__ Tdev, int scale_by_T,
-                               double *__restrict__ F) {
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double v = 0.0;
-    for (int s = 0; s < parts; ++s) {
-        const int64_t j = s * n + i;
-        v += (Cc[j] - Cpp[j]) + Cd[j];
+__global__ void layout_split_kernel(const double *__restrict__ V, int N, uint16_t *__restrict__ ahl,
+                                    float *__restrict__ g32) {
+    const int64_t n3 = static_cast<int64_t>(N) * N * N;
+    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (idx < n3) layout_split_elem(V, N, n3, idx, ahl, g32);
+}
+
+// The channel partials are stored per column tile position, [p][m], so each
+// channel sees F through its own index frame.  A block assembles an 8 x 8 x 32
+// cube (j1, j2, j3) of F in LDS, reading each channel along its contiguous
+// index: pp along j3 (32 values), phc along j1 and phd along j2 (8 values).
+constexpr int CB_J = 8, CB_K = 32, CB_P = CB_K + 1;
+
+int combine_tiles_of(int N) {
+    const int nj = (N + CB_J - 1) / CB_J, nk = (N + CB_K - 1) / CB_K;
+    return nj * nj * nk;
+}
+
+__device__ void combine_body(int N, int KS, int64_t n3, const double *__restrict__ Cpp,
+                             const double *__restrict__ Cc, const double *__restrict__ Cd,
+                             const int32_t *__restrict__ ppos, const int32_t *__restrict__ phpos,
+                             double scale, double *__restrict__ F, int tile, double *sF) {
+    const int nj = (N + CB_J - 1) / CB_J, nk = (N + CB_K - 1) / CB_K;
+    const int t3 = tile % nk, t2 = (tile / nk) % nj, t1 = tile / (nk * nj);
+    const int a0 = t1 * CB_J, b0 = t2 * CB_J, c0 = t3 * CB_K;
+    constexpr int NE = CB_J * CB_J * CB_K;
+    // pp: lanes along j3
+    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+        const int i3 = e % CB_K, i2 = (e / CB_K) % CB_J, i1 = e / (CB_K * CB_J);
+        const int j1 = a0 + i1, j2 = b0 + i2, j3 = c0 + i3;
+        if (j1 >= N || j2 >= N || j3 >= N) continue;
+        const int64_t at = static_cast<int64_t>(ppos[j1 * N + j2]) * N + j3;
+        double v = 0.0;
+        for (int s = 0; s < KS; ++s) v += Cpp[s * n3 + at];
+        sF[(i1 * CB_J + i2) * CB_P + i3] = -v;
     }
-    F[i] = scale_by_T ? Tdev[0] * v : v;
+    __syncthreads();
+    // phc: m = j1, column (j2, j3); lanes along j1
+    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+        const int i1 = e % CB_J, i3 = (e / CB_J) % CB_K, i2 = e / (CB_J * CB_K);
+        const int j1 = a0 + i1, j2 = b0 + i2, j3 = c0 + i3;
+        if (j1 >= N || j2 >= N || j3 >= N) continue;
+        const int64_t at = static_cast<int64_t>(phpos[j2 * N + j3]) * N + j1;
+        double v = 0.0;
+        for (int s = 0; s < KS; ++s) v += Cc[s * n3 + at];
+        sF[(i1 * CB_J + i2) * CB_P + i3] += v;
+    }
+    __syncthreads();
+    // phd: m = j2, column (j1, j3); lanes along j2
+    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+        const int i2 = e % CB_J, i3 = (e / CB_J) % CB_K, i1 = e / (CB_J * CB_K);
+        const int j1 = a0 + i1, j2 = b0 + i2, j3 = c0 + i3;
+        if (j1 >= N || j2 >= N || j3 >= N) continue;
+        const int64_t at = static_cast<int64_t>(phpos[j1 * N + j3]) * N + j2;
+        double v = 0.0;
+        for (int s = 0; s < KS; ++s) v += Cd[s * n3 + at];
+        sF[(i1 * CB_J + i2) * CB_P + i3] += v;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+        const int i3 = e % CB_K, i2 = (e / CB_K) % CB_J, i1 = e / (CB_K * CB_J);
+        const int j1 = a0 + i1, j2 = b0 + i2, j3 = c0 + i3;
+        if (j1 >= N || j2 >= N || j3 >= N) continue;
+        F[(static_cast<int64_t>(j1) * N + j2) * N + j3] = scale * sF[(i1 * CB_J + i2) * CB_P + i3];
+    }
+}
+
+__global__ __launch_bounds__(256) void combine_kernel(const double *__restrict__ Cpp,
+                                                      const double *__restrict__ Cc,
+                                                      const double *__restrict__ Cd, int N, int parts,
+                                                      const int32_t *__restrict__ ppos,
+                                                      const int32_t *__restrict__ phpos,
+                                                      const double *__restrict__ Tdev, int scale_by_T,
+                                                      double *__restrict__ F) {
+    __shared__ double sF[CB_J * CB_J * CB_P];
+    const int64_t n3 = static_cast<int64_t>(N) * N * N;
+    combine_body(N, parts, n3, Cpp, Cc, Cd, ppos, phpos, scale_by_T ? Tdev[0] : 1.0, F, blockIdx.x, sF);
 }
 
 // ----------------------------------------------------------------- RK
@@ -448,53 +527,22 @@ __global__ void layout_b_kernel(const FlowArgs *__restrict__ fa, const int2 *__r
     const int2 it = items[blockIdx.x];
     const FlowArgs &f = fa[it.x];
     if (flow_stopped(f)) return;
-    const int N = f.N;
-    const int64_t n3 = f.n3;
     const int64_t idx = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x;
-    if (idx >= n3) return;
-    const double *V = src_of(f, src);
-    const int k = static_cast<int>(idx % N);
-    const int j = static_cast<int>((idx / N) % N);
-    const int i = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
-    auto at = [&](int x, int y, int z) { return V[(static_cast<int64_t>(x) * N + y) * N + z]; };
-    if (!split) {
-        double *perm = f.perm;
-        perm[idx] = at(j, k, i);
-        perm[n3 + idx] = at(k, i, j);
-        perm[2 * n3 + idx] = -2.0 * at(j, i, k) + at(i, j, k);
-        perm[3 * n3 + idx] = at(j, i, k);
-        perm[4 * n3 + idx] = at(i, k, j);
-    } else {
-        const float ops[4] = {static_cast<float>(at(j, k, i)), static_cast<float>(at(i, j, k)),
-                              static_cast<float>(-2.0 * at(j, i, k) + at(i, j, k)),
-                              static_cast<float>(at(j, i, k))};
-#pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            const uint16_t hi = bf16_rne(ops[o]);
-            f.ahl[(2 * o) * n3 + idx] = hi;
-            f.ahl[(2 * o + 1) * n3 + idx] = bf16_rne(ops[o] - bf16_to_f(hi));
-        }
-        f.g32[idx] = static_cast<float>(at(i, j, k));
-        f.g32[n3 + idx] = static_cast<float>(at(k, i, j));
-        f.g32[2 * n3 + idx] = static_cast<float>(at(i, k, j));
-    }
+    if (idx >= f.n3) return;
+    if (!split) layout_f64_elem(src_of(f, src), f.N, f.n3, idx, f.perm);
+    else layout_split_elem(src_of(f, src), f.N, f.n3, idx, f.ahl, f.g32);
 }
 
-__global__ void combine_b_kernel(const FlowArgs *__restrict__ fa, const int2 *__restrict__ items, int stage) {
+__global__ __launch_bounds__(256) void combine_b_kernel(const FlowArgs *__restrict__ fa,
+                                                        const int2 *__restrict__ items, int stage) {
+    __shared__ double sF[CB_J * CB_J * CB_P];
     const int2 it = items[blockIdx.x];
     const FlowArgs &f = fa[it.x];
     if (flow_stopped(f)) return;
     const int64_t n = f.n3;
-    const int64_t i = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
     const int KS = f.KS;
-    const double *Cpp = f.C, *Cc = f.C + KS * n, *Cd = f.C + 2 * KS * n;
-    double v = 0.0;
-    for (int s = 0; s < KS; ++s) {
-        const int64_t j = s * n + i;
-        v += (Cc[j] - Cpp[j]) + Cd[j];
-    }
-    f.k[stage][i] = f.Tdev[0] * v;
+    combine_body(f.N, KS, n, f.C, f.C + KS * n, f.C + 2 * KS * n, f.ppos, f.phpos, f.Tdev[0], f.k[stage],
+                 it.y, sF);
 }
 
 struct Coef7 { double c[7]; };
@@ -616,10 +664,13 @@ void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipS
                        g32);
 }
 
-void launch_combine(const double *Cpp, const double *Cc, const double *Cd, int64_t n, int parts,
+int combine_tiles(int N) { return combine_tiles_of(N); }
+
+void launch_combine(const double *Cpp, const double *Cc, const double *Cd, int N, int parts,
+                    const int32_t *ppos, const int32_t *phpos,
                     const double *Tdev, int scale_by_T, double *F, hipStream_t s) {
-    hipLaunchKernelGGL(combine_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, Cpp, Cc, Cd, n,
-                       parts, Tdev, scale_by_T, F);
+    hipLaunchKernelGGL(combine_kernel, dim3(combine_tiles_of(N)), dim3(256), 0, s, Cpp, Cc, Cd, N, parts,
+                       ppos, phpos, Tdev, scale_by_T, F);
 }
 
 void launch_rk_stage(const RkStageArgs &a, hipStream_t s) {

@@ -78,6 +78,8 @@ SIGNATURES = {
     "frg_batch_results": (C.c_int, [_P, C.POINTER(FlowResult), _IP]),
     "frg_set_symmetry": (C.c_int, [_P, C.c_int32]),
     "frg_symmetry": (C.c_int, [_P, _IP, _IP]),
+    "frg_set_kskip": (C.c_int, [_P, C.c_int32]),
+    "frg_kskip": (C.c_int, [_P, _IP, _DP]),
     "frg_profile_begin": (C.c_int, [_P]),
     "frg_profile_end": (C.c_int, [_P, _DP, _IP]),
     "frg_status_str": (C.c_char_p, [C.c_int]),
@@ -237,6 +239,15 @@ class Context:
         a, r = C.c_int32(), C.c_int32()
         _check(lib().frg_symmetry(self._h, C.byref(a), C.byref(r)))
         return bool(a.value), int(r.value)
+
+    def set_kskip(self, enable: bool):
+        _check(lib().frg_set_kskip(self._h, 1 if enable else 0))
+
+    def kskip(self):
+        """(zero-block skipping on, executed share of the dense contraction work)."""
+        a, f = C.c_int32(), C.c_double()
+        _check(lib().frg_kskip(self._h, C.byref(a), C.byref(f)))
+        return bool(a.value), float(f.value)
 
     def profile_begin(self):
         _check(lib().frg_profile_begin(self._h))

@@ -158,7 +158,7 @@ def test_rhs_full_size_sampled():
         gotsp = Fsp[idx[:, 0], idx[:, 1], idx[:, 2]]
         e64 = np.abs(got64 - ref).max() / scale
         esp = np.abs(gotsp - ref).max() / scale
-        print(f"[C3 sampled] fp64 {e64:.2e} split {esp:.2e}", flush=True)
+        print(f"[C3 sampled] fp64 {e64:.2e} split {esp:.2e} kskip {g.kskip()}", flush=True)
         assert e64 <= 1e-10
         assert esp <= 2e-4
         # whole-tensor agreement of the two GPU paths
@@ -263,6 +263,32 @@ def test_c4v_reduction_unavailable_for_n_not_multiple_of_8():
     with pytest.raises(frg.FRGError) as e:
         g.set_symmetry(True)
     assert e.value.status == frg.ENOTSUP
+
+
+@pytest.mark.parametrize("cfg", ["C1", RAGGED, SMALL_ODD, "C2"], ids=["C1", "ragged", "odd", "C2"])
+def test_zero_block_skipping_matches_dense(cfg):
+    """Visiting only the k chunks where some bubble row of a column tile has a
+    fine point gives the dense contraction's rhs (skipped terms are exact
+    zeros; only the summation order differs)."""
+    om, g = pair(cfg)
+    on, frac = g.kskip()
+    assert on and 0.0 < frac <= 1.0
+    print(f"[kskip] N={om.N}: executed share {frac:.3f}", flush=True)
+    if om.N >= 48:
+        assert frac < 0.8
+    V = dev(I.random_vertex(om.N, om.U, seed=43, symmetrise=False))
+    ref = om.rhs(0.03, V.cpu().numpy())
+    for prec, tol in ((frg.PREC_FP64, 1e-10), (frg.PREC_SPLIT_BF16, 2e-4)):
+        Fs = g.rhs(0.03, V, prec).cpu().numpy()
+        g.set_kskip(False)
+        try:
+            assert g.kskip() == (False, 1.0)
+            Fd = g.rhs(0.03, V, prec).cpu().numpy()
+        finally:
+            g.set_kskip(True)
+        assert nrel(Fs, ref) <= tol and nrel(Fd, ref) <= tol
+        if prec == frg.PREC_FP64:
+            assert nrel(Fs, Fd) <= 1e-12
 
 
 BATCH = [dict(t=1.0, tp=-0.1, mu=-0.3, U=2.0, N=16, n_rad=4, n_ang=4),

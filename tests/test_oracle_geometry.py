@@ -188,3 +188,24 @@ def test_transfer_rows():
     for x in range(N):
         assert m.row_ph(x, x) == 0
     assert np.array_equal(tb["qph"][0], [0.0, 0.0])
+
+
+@pytest.mark.parametrize("name", ["C1", "C2"])
+def test_bubbles_vanish_exactly_off_the_point_pattern(name):
+    """Entry (a, b) of a bubble row is a sum over the fine points of patch a
+    whose second momentum falls in patch b: it is exactly zero when the
+    second-line table has no such point, and a nonzero sum otherwise.  (This is
+    what lets the contraction skip k chunks: the pattern is fixed by geometry.)"""
+    m = O.Model(**I.model_params(name))
+    N, nf = m.N, m.nf
+    Bpp, Bph = m.bubbles(0.2)
+    a = np.repeat(np.arange(N), nf)
+    for kind, B in ((O.PP, Bpp), (O.PH, Bph)):
+        bins = m.bins(kind)
+        pat = np.zeros((bins.shape[0], N * N), dtype=bool)
+        pat[np.repeat(np.arange(bins.shape[0]), N * nf), (a[None, :] * N + bins).reshape(-1)] = True
+        Bf = B.reshape(B.shape[0], -1)
+        assert np.all(Bf[~pat] == 0.0)
+        assert np.all(Bf[pat] != 0.0)
+        # most of each row is structurally zero at these grids
+        assert pat.mean() < 0.4
