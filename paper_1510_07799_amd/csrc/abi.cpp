@@ -285,13 +285,13 @@ frg_status build_orbits(frg_ctx ctx) {
 }
 
 // K parts of the fused contraction: enough blocks for several rounds over the
-// 256 compute units (measured best at N = 96: 4 parts); FRG_KSPLIT overrides
+// 256 compute units (measured best at N = 96: 8 parts); FRG_KSPLIT overrides
 int ksplit(frg_ctx ctx) {
     if (ctx->ks_override > 0) return ctx->ks_override;
     const int N = ctx->g.N;
     const int bm = frg::contract_block_rows(N);
     const int64_t tiles = 3LL * ((N + bm - 1) / bm) * ((static_cast<int64_t>(N) * N + 63) / 64);
-    int64_t ks = (1728 + tiles - 1) / tiles;
+    int64_t ks = (3456 + tiles - 1) / tiles;
     return static_cast<int>(ks < 1 ? 1 : (ks > 8 ? 8 : ks));
 }
 

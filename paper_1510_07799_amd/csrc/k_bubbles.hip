@@ -4,13 +4,13 @@
 // (Sec. 4: the three one-loop diagrams integrated over the Brillouin zone;
 // here each transfer's bubble row is shared by every vertex entry that uses it).
 //
-// Work decomposition: one block per (patch a, chunk of rows); the patch's fine
-// points are staged once in LDS (lane-major so lane L's P points sit at
-// slot j*64 + L), and each wave sweeps whole rows: lane L evaluates the P
-// consecutive points L*P .. L*P+P-1 (radially adjacent, so mostly one bin),
-// accumulates runs of equal bin in registers and flushes each run into the
-// wave's private LDS bins with one LDS add; the wave then writes the row
-// B_row(a, 0..N-1) with coalesced stores.  The bin table (one byte per
+// Work decomposition: one block per (patch a, chunk of rows); lane L holds the
+// P consecutive fine points L*P .. L*P+P-1 of the patch (radially adjacent,
+// so mostly one bin) in registers for all rows, and each wave sweeps whole
+// rows independently (in the FP64 path the points sit in LDS instead, to keep
+// the register count down): it accumulates runs of equal bin in registers, flushes
+// each run into the wave's private LDS bins with one LDS add, and writes the
+// row B_row(a, 0..N-1) with coalesced stores (no block-wide barriers).  The bin table (one byte per
 // evaluation) and the cos/sin of points and transfers are temperature
 // independent; eps(second line) uses cos(q -/+ p) = cos q cos p +/- sin q sin p.
 //
@@ -18,6 +18,7 @@
 // error is divided by 2T), the integrand in FP32 with hardware exp/rcp, runs
 // summed with Kahan compensation, bins accumulated in double, output float.
 #include <cmath>
+#include <type_traits>
 
 #include "frg_internal.h"
 
@@ -65,124 +66,175 @@ __device__ __forceinline__ float div_h32(float a, float ha, float b) {
     return (ha - hb) * __builtin_amdgcn_rcpf(d);
 }
 
+// order the LDS accesses of one wave (its bins are private to it)
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Bins of wave w at smem[w*N ..); in LDS mode the point data follow them.
+template <int P, bool F32>
+constexpr bool points_in_registers() { return F32 && P <= 8; }
+
+template <int P, bool F32>
+size_t bubble_lds_bytes(int N) {
+    return sizeof(double) * (4 * static_cast<size_t>(N) + (points_in_registers<P, F32>() ? 0 : 7 * P * 64));
+}
+
 template <int P, bool F32>
 __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int a_patch, double *smem) {
-    constexpr int S = P * 64;          // slots per array
-    double *pt = smem;                 // [7][S]: cpx spx cpy spy a ha wf
+    using PT = typename std::conditional<F32, float, double>::type;
+    // The lane's P radially consecutive points: in registers for every row
+    // (split path, up to 8 points per lane), or, where that would cost too
+    // many registers (FP64 path, 16 points per lane),
+    // staged once in LDS lane-major (lane L's point j at slot j*64 + L).
+    constexpr bool REG = points_in_registers<P, F32>();
+    constexpr int PR = REG ? P : 1;
+    constexpr int S = P * 64;
     const int N = A.N, nf = A.nf, np = A.np;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double *bins = smem + 7 * S + wave * N;
+    double *bins = smem + wave * N;
+    double *pt = smem + 4 * N;                 // LDS mode: [7][S] cpx spx cpy spy a ha wf
 
-    for (int k = threadIdx.x; k < S; k += kThreads) {
-        const int L = k / P, j = k % P;
-        const int slot = j * 64 + L;
-        if (k < nf) {
-            const int i = a_patch * nf + k;
-            pt[0 * S + slot] = A.trig_pt[i];
-            pt[1 * S + slot] = A.trig_pt[np + i];
-            pt[2 * S + slot] = A.trig_pt[2 * np + i];
-            pt[3 * S + slot] = A.trig_pt[3 * np + i];
-            if (F32) {
-                pt[4 * S + slot] = A.pa32[i];
-                pt[5 * S + slot] = A.pa32[np + i];
-                pt[6 * S + slot] = A.pa32[2 * np + i];
-            } else {
-                pt[4 * S + slot] = A.pa64[i];
-                pt[5 * S + slot] = A.pa64[np + i];
-                pt[6 * S + slot] = A.pa64[2 * np + i];
-            }
-        } else {
-            for (int q = 0; q < 7; ++q) pt[q * S + slot] = 0.0;
+    double cpx[PR], spx[PR], cpy[PR], spy[PR];
+    PT pa[PR], pha[PR], pwf[PR];
+    if constexpr (REG) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const int k = lane * P + j;
+            const bool ok = k < nf;
+            const int i = a_patch * nf + (ok ? k : 0);
+            cpx[j] = ok ? A.trig_pt[i] : 1.0;
+            spx[j] = ok ? A.trig_pt[np + i] : 0.0;
+            cpy[j] = ok ? A.trig_pt[2 * np + i] : 1.0;
+            spy[j] = ok ? A.trig_pt[3 * np + i] : 0.0;
+            pa[j] = ok ? static_cast<PT>(F32 ? A.pa32[i] : A.pa64[i]) : PT(0);
+            pha[j] = ok ? static_cast<PT>(F32 ? A.pa32[np + i] : A.pa64[np + i]) : PT(0);
+            pwf[j] = ok ? static_cast<PT>(F32 ? A.pa32[2 * np + i] : A.pa64[2 * np + i]) : PT(0);
         }
+    } else {
+        for (int k = threadIdx.x; k < S; k += kThreads) {
+            const int slot = (k % P) * 64 + k / P;
+            const bool ok = k < nf;
+            const int i = a_patch * nf + (ok ? k : 0);
+            pt[0 * S + slot] = ok ? A.trig_pt[i] : 1.0;
+            pt[1 * S + slot] = ok ? A.trig_pt[np + i] : 0.0;
+            pt[2 * S + slot] = ok ? A.trig_pt[2 * np + i] : 1.0;
+            pt[3 * S + slot] = ok ? A.trig_pt[3 * np + i] : 0.0;
+            pt[4 * S + slot] = ok ? (F32 ? A.pa32[i] : A.pa64[i]) : 0.0;
+            pt[5 * S + slot] = ok ? (F32 ? A.pa32[np + i] : A.pa64[np + i]) : 0.0;
+            pt[6 * S + slot] = ok ? (F32 ? A.pa32[2 * np + i] : A.pa64[2 * np + i]) : 0.0;
+        }
+        __syncthreads();
     }
+    auto pval = [&](int q, int j) -> double {
+        if constexpr (REG) {
+            return q == 0 ? cpx[j] : q == 1 ? spx[j] : q == 2 ? cpy[j] : q == 3 ? spy[j]
+                 : q == 4 ? static_cast<double>(pa[j]) : q == 5 ? static_cast<double>(pha[j])
+                 : static_cast<double>(pwf[j]);
+        } else {
+            return pt[q * S + j * 64 + lane];
+        }
+    };
     const double inv2T = A.Tdev[1];
     const double mt2 = A.mt2, mt4p = A.mt4p, mu = A.mu;
-    __syncthreads();
+    // second-line patches of the lane's points: one P-byte load when aligned
+    const bool vec_bins = (nf % P) == 0 && (P == 4 || P == 8 || P == 16);
 
     const int row0 = chunk * kRowsPerBlock;
     for (int rr = wave; rr < kRowsPerBlock; rr += 4) {
-        const int slot_out = row0 + rr;                 // output row position
-        const bool active = slot_out < A.nrows;
-        const int r = active ? (A.rowlist ? A.rowlist[slot_out] : slot_out) : 0;   // transfer row
-        if (active)
-            for (int b = lane; b < N; b += 64) bins[b] = 0.0;
-        __syncthreads();
-        if (active) {
-            const bool pp = r < A.Tpp;
-            const double cqx = A.trig_row[4 * r], sqx = A.trig_row[4 * r + 1];
-            const double cqy = A.trig_row[4 * r + 2], sqy = A.trig_row[4 * r + 3];
-            const uint8_t *brow = A.bins + static_cast<size_t>(r) * np + static_cast<size_t>(a_patch) * nf;
-            int bcur = -1;
-            double acc64 = 0.0;
-            float acc32 = 0.0f, comp32 = 0.0f;
+        const int slot_out = row0 + rr;                 // output row position (wave-uniform)
+        if (slot_out >= A.nrows) break;
+        const int r = A.rowlist ? A.rowlist[slot_out] : slot_out;   // transfer row
+        for (int b = lane; b < N; b += 64) bins[b] = 0.0;
+        const bool pp = r < A.Tpp;
+        const double cqx = A.trig_row[4 * r], sqx = A.trig_row[4 * r + 1];
+        const double cqy = A.trig_row[4 * r + 2], sqy = A.trig_row[4 * r + 3];
+        const uint8_t *brow = A.bins + static_cast<size_t>(r) * np + static_cast<size_t>(a_patch) * nf;
+        uint8_t bn[P];
+        if (vec_bins && lane * P < nf) {
+            if (P == 4) {
+                const uint32_t v = *reinterpret_cast<const uint32_t *>(brow + lane * P);
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-                const int k = lane * P + j;
-                if (k < nf) {
-                    const int slot = j * 64 + lane;
-                    const double cpx = pt[slot], spx = pt[S + slot];
-                    const double cpy = pt[2 * S + slot], spy = pt[3 * S + slot];
-                    double cx, cy;
-                    if (pp) {   // cos(q - p)
-                        cx = cqx * cpx + sqx * spx;
-                        cy = cqy * cpy + sqy * spy;
-                    } else {    // cos(p + Q)
-                        cx = cpx * cqx - spx * sqx;
-                        cy = cpy * cqy - spy * sqy;
+                for (int j = 0; j < P; ++j) bn[j] = static_cast<uint8_t>(v >> (8 * (j & 3)));
+            } else {
+#pragma unroll
+                for (int h = 0; h < P / 8; ++h) {
+                    const uint64_t v = *reinterpret_cast<const uint64_t *>(brow + lane * P + 8 * h);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) bn[8 * h + j] = static_cast<uint8_t>(v >> (8 * j));
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < P; ++j) bn[j] = lane * P + j < nf ? brow[lane * P + j] : 0;
+        }
+        wave_sync();
+        int bcur = -1;
+        double acc64 = 0.0;
+        float acc32 = 0.0f, comp32 = 0.0f;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            if (lane * P + j < nf) {
+                const double c_px = pval(0, j), s_px = pval(1, j), c_py = pval(2, j), s_py = pval(3, j);
+                double cx, cy;
+                if (pp) {   // cos(q - p)
+                    cx = cqx * c_px + sqx * s_px;
+                    cy = cqy * c_py + sqy * s_py;
+                } else {    // cos(p + Q)
+                    cx = c_px * cqx - s_px * sqx;
+                    cy = c_py * cqy - s_py * sqy;
+                }
+                const double xi2 = mt2 * (cx + cy) - mt4p * (cx * cy) - mu;
+                double b2 = xi2 * inv2T;
+                if (pp) b2 = -b2;
+                const int bin = bn[j];
+                if (F32) {
+                    const float v = static_cast<float>(pval(6, j)) *
+                                    div_h32(static_cast<float>(pval(4, j)), static_cast<float>(pval(5, j)),
+                                            static_cast<float>(b2));
+                    if (bin != bcur) {
+                        if (bcur >= 0)
+                            atomicAdd(&bins[bcur], static_cast<double>(acc32) - static_cast<double>(comp32));
+                        bcur = bin;
+                        acc32 = v;
+                        comp32 = 0.0f;
+                    } else {   // Kahan step
+                        const float y = v - comp32;
+                        const float t = acc32 + y;
+                        comp32 = (t - acc32) - y;
+                        acc32 = t;
                     }
-                    const double xi2 = mt2 * (cx + cy) - mt4p * (cx * cy) - mu;
-                    double b2 = xi2 * inv2T;
-                    if (pp) b2 = -b2;
-                    const int bin = brow[k];
-                    if (F32) {
-                        const float v = static_cast<float>(pt[6 * S + slot]) *
-                                        div_h32(static_cast<float>(pt[4 * S + slot]),
-                                                static_cast<float>(pt[5 * S + slot]),
-                                                static_cast<float>(b2));
-                        if (bin != bcur) {
-                            if (bcur >= 0)
-                                atomicAdd(&bins[bcur], static_cast<double>(acc32) - static_cast<double>(comp32));
-                            bcur = bin;
-                            acc32 = v;
-                            comp32 = 0.0f;
-                        } else {   // Kahan step
-                            const float y = v - comp32;
-                            const float t = acc32 + y;
-                            comp32 = (t - acc32) - y;
-                            acc32 = t;
-                        }
+                } else {
+                    const double v = pval(6, j) * div_h64(pval(4, j), pval(5, j), b2);
+                    if (bin != bcur) {
+                        if (bcur >= 0) atomicAdd(&bins[bcur], acc64);
+                        bcur = bin;
+                        acc64 = v;
                     } else {
-                        const double v = pt[6 * S + slot] * div_h64(pt[4 * S + slot], pt[5 * S + slot], b2);
-                        if (bin != bcur) {
-                            if (bcur >= 0) atomicAdd(&bins[bcur], acc64);
-                            bcur = bin;
-                            acc64 = v;
-                        } else {
-                            acc64 += v;
-                        }
+                        acc64 += v;
                     }
                 }
             }
-            if (bcur >= 0) {
-                if (F32) atomicAdd(&bins[bcur], static_cast<double>(acc32) - static_cast<double>(comp32));
-                else atomicAdd(&bins[bcur], acc64);
+        }
+        if (bcur >= 0) {
+            if (F32) atomicAdd(&bins[bcur], static_cast<double>(acc32) - static_cast<double>(comp32));
+            else atomicAdd(&bins[bcur], acc64);
+        }
+        wave_sync();
+        const size_t NN = static_cast<size_t>(N) * N;
+        const bool pp_out = slot_out < A.npp_out;
+        const size_t base = (pp_out ? static_cast<size_t>(slot_out) : static_cast<size_t>(slot_out - A.npp_out)) * NN +
+                            static_cast<size_t>(a_patch) * N;
+        void *outp = pp_out ? A.Bpp : A.Bph;
+        if (outp) {
+            for (int b = lane; b < N; b += 64) {
+                if (F32) static_cast<float *>(outp)[base + b] = static_cast<float>(bins[b]);
+                else static_cast<double *>(outp)[base + b] = bins[b];
             }
         }
-        __syncthreads();
-        if (active) {
-            const size_t NN = static_cast<size_t>(N) * N;
-            const bool pp = slot_out < A.npp_out;
-            const size_t base = (pp ? static_cast<size_t>(slot_out) : static_cast<size_t>(slot_out - A.npp_out)) * NN +
-                                static_cast<size_t>(a_patch) * N;
-            void *outp = pp ? A.Bpp : A.Bph;
-            if (outp) {
-                for (int b = lane; b < N; b += 64) {
-                    if (F32) static_cast<float *>(outp)[base + b] = static_cast<float>(bins[b]);
-                    else static_cast<double *>(outp)[base + b] = bins[b];
-                }
-            }
-        }
-        __syncthreads();
+        wave_sync();
     }
 }
 
@@ -207,7 +259,7 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel_batched(const BubbleAr
 template <int P>
 void launch_p(const BubbleArgs &a, bool fp32, hipStream_t s) {
     dim3 grid((a.nrows + kRowsPerBlock - 1) / kRowsPerBlock, a.N);
-    const size_t lds = sizeof(double) * (7 * P * 64 + 4 * a.N);
+    const size_t lds = fp32 ? bubble_lds_bytes<P, true>(a.N) : bubble_lds_bytes<P, false>(a.N);
     if (fp32)
         hipLaunchKernelGGL((bubble_kernel<P, true>), grid, dim3(kThreads), lds, s, a);
     else
@@ -217,7 +269,7 @@ void launch_p(const BubbleArgs &a, bool fp32, hipStream_t s) {
 template <int P>
 void launch_pb(const BubbleArgs *args, const int2 *items, int nitems, const double *const *states,
                int maxN, bool fp32, hipStream_t s) {
-    const size_t lds = sizeof(double) * (7 * P * 64 + 4 * maxN);
+    const size_t lds = fp32 ? bubble_lds_bytes<P, true>(maxN) : bubble_lds_bytes<P, false>(maxN);
     if (fp32)
         hipLaunchKernelGGL((bubble_kernel_batched<P, true>), dim3(nitems), dim3(kThreads), lds, s, args,
                            items, states);
