@@ -86,9 +86,9 @@ template <int P, bool F32>
 __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int a_patch, double *smem) {
     using PT = typename std::conditional<F32, float, double>::type;
     // The lane's P radially consecutive points: in registers for every row
-    // (split path, up to 8 points per lane), or, where that would cost too
-    // many registers (FP64 path, 16 points per lane),
-    // staged once in LDS lane-major (lane L's point j at slot j*64 + L).
+    // (split path with up to 8 points per lane), or, where that would cost too
+    // many registers (the FP64 path; 16 points per lane), staged once in LDS
+    // lane-major (lane L's point j at slot j*64 + L).
     constexpr bool REG = points_in_registers<P, F32>();
     constexpr int PR = REG ? P : 1;
     constexpr int S = P * 64;
