@@ -295,6 +295,13 @@ int ksplit(frg_ctx ctx) {
     return static_cast<int>(ks < 1 ? 1 : (ks > 8 ? 8 : ks));
 }
 
+// entry of a chunk list: chunk id j (k = 8j .. 8j+7) and the patch pair
+// (a, b) of k = 8j = a*N + b, packed as j | a << 13 | b << 21 (N <= 256)
+int32_t list_entry(int j, int N) {
+    const int k = j * frg::kContractChunk;
+    return static_cast<int32_t>(j | ((k / N) << 13) | ((k % N) << 21));
+}
+
 // position along a Hilbert curve over the Brillouin zone [-pi, pi)^2 (2^16 x 2^16 cells)
 uint64_t hilbert_key(double qx, double qy) {
     const uint32_t n = 1u << 16;
@@ -360,7 +367,7 @@ frg_status build_ktiles(frg_ctx ctx) {
         for (int t = 0; t < tiles; ++t) {
             koff[t] = static_cast<int32_t>(klist.size());
             for (int j = 0; j < nch; ++j)
-                if (flags[static_cast<size_t>(t) * nch + j]) klist.push_back(j);
+                if (flags[static_cast<size_t>(t) * nch + j]) klist.push_back(list_entry(j, N));
         }
         koff[tiles] = static_cast<int32_t>(klist.size());
         ctx->kchunks_active[cls] = static_cast<int64_t>(klist.size());
@@ -379,7 +386,7 @@ frg_status ensure_dense_tiles(frg_ctx ctx) {
     std::vector<int32_t> perm(NC), koff(tiles + 1), klist(static_cast<size_t>(tiles) * nch);
     std::iota(perm.begin(), perm.end(), 0);
     for (int t = 0; t <= tiles; ++t) koff[t] = t * nch;
-    for (size_t i = 0; i < klist.size(); ++i) klist[i] = static_cast<int32_t>(i % nch);
+    for (size_t i = 0; i < klist.size(); ++i) klist[i] = list_entry(static_cast<int>(i % nch), ctx->g.N);
     TRY(upload(ctx, &ctx->d_cperm_id, perm.data(), perm.size()));
     TRY(upload(ctx, &ctx->d_koff_dense, koff.data(), koff.size()));
     TRY(upload(ctx, &ctx->d_klist_dense, klist.data(), klist.size()));
@@ -1085,8 +1092,8 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         const int cls = bm == 32 ? 0 : (bm == 64 ? 1 : 2);
         // K part ks of this flow is served by the XCDs q with q * KS / 8 == ks
         std::vector<int> rr(KS, 0);
-        for (int id = 0; id < 3 * per_term; ++id) {
-            const double np_ = (id / per_term == 0) ? 2.0 : 1.0;   // phd first, two products
+        for (int id = 0; id < frg::contract_kinds(split) * per_term; ++id) {
+            const double np_ = frg::contract_kind_products(split, id / per_term);   // heaviest kind first
             const int ks = id % KS;
             int q;
             if (KS >= 8) {

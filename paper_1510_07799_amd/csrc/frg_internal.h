@@ -66,7 +66,8 @@ void launch_layout_f64(const double *V, int N, double *perm, hipStream_t s);
 // split-BF16 operands: hi/lo of the four A matrices + FP32 gather tables
 void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipStream_t s);
 
-enum Term { TERM_PP = 0, TERM_PHC = 1, TERM_PHD = 2 };
+enum Term { TERM_PP = 0, TERM_PHC = 1, TERM_PHD = 2,
+            TERM_PH = 3 };   // TERM_PH: phc and phd in one block (split path)
 
 // all three channels in one launch; term t writes C[t] + part * n3 for K part
 // `part`, laid out [tile position p][m] (p holds column cperm[t][p])
@@ -80,7 +81,9 @@ struct FusedContractArgs {
     // column tiles: tile position -> column (columns ordered so that a tile's
     // transfers are close in k space), and per tile the list of 8-wide k
     // chunks that hold a structural nonzero of any of its bubble rows
-    // (klist[koff[t] .. koff[t+1]) in increasing order)
+    // (klist[koff[t] .. koff[t+1]) in increasing order; an entry packs the
+    // chunk id j and the patch pair (a, b) of k = 8j = a*N + b as
+    // j | a << 13 | b << 21)
     const int32_t *cperm[3];
     const int32_t *koff[3];
     const int32_t *klist[3];
@@ -92,6 +95,11 @@ struct FusedContractArgs {
 };
 void launch_contract_fused(const FusedContractArgs &a, bool split, hipStream_t s);
 int contract_block_rows(int N);
+// block kinds of one (m tile, column tile, K part), heaviest first, and the
+// number of products each multiplies: FP64 {phd: 2, phc: 1, pp: 1},
+// split {phc+phd: 3, pp: 1}
+int contract_kinds(bool split);
+int contract_kind_products(bool split, int kind);
 constexpr int kContractCols = 64;     // columns per contraction tile
 constexpr int kContractChunk = 8;     // k chunk of the active lists
 // flags[t][j] = 1 if some column at tile position t*64 .. t*64+63 has a

@@ -44,7 +44,6 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef double d2_t __attribute__((ext_vector_type(2)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
-typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int BC = kContractCols;   // output columns (c) per block
@@ -63,15 +62,6 @@ __device__ __forceinline__ GLOBAL_AS T *gstore_ptr(T *p) {
     return reinterpret_cast<GLOBAL_AS T *>(reinterpret_cast<uintptr_t>(p));
 }
 constexpr int kThreads = 256;
-
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return static_cast<uint16_t>(u >> 16);
-}
-__device__ __forceinline__ float bf16_to_f(uint16_t h) {
-    return __uint_as_float(static_cast<uint32_t>(h) << 16);
-}
 
 struct Work {
     int term, mtile, ctile, ks;
@@ -105,18 +95,24 @@ __device__ __forceinline__ RowMap decode_rowmap(int info, int N) {
     return r;
 }
 
+// A list entry: chunk id (bits 0-12) and the patch pair (a, b) of its first
+// k = 8 * chunk = a*N + b (bits 13-20 and 21-28), so no division by N is
+// needed in the loop.
+__device__ __forceinline__ int ent_chunk(int e) { return e & 0x1fff; }
+__device__ __forceinline__ int ent_a(int e) { return (e >> 13) & 0xff; }
+__device__ __forceinline__ int ent_b(int e) { return (e >> 21) & 0xff; }
+
 // ZK consecutive entries k = kb .. kb+ZK-1 of a column's bubble row
-// (k = a'*N + b'), gathered through the row map; VW-wide vector loads when the
-// source window is contiguous and aligned, scalar loads otherwise.
+// (k = a'*N + b', kb = a1*N + b1), gathered through the row map; VW-wide vector
+// loads when the source window is contiguous and aligned, scalar loads otherwise.
 template <int ZK, int VW, typename T, typename VT>
 __device__ __forceinline__ void load_bubble_window(const GLOBAL_AS T *brow, const RowMap &rm, int N, int K,
-                                                   int kb, bool ok, T *out) {
+                                                   int kb, int a1, int b1, bool ok, T *out) {
     if (!ok) {
 #pragma unroll
         for (int q = 0; q < ZK; ++q) out[q] = T(0);
         return;
     }
-    const int a1 = kb / N, b1 = kb - a1 * N;
     if (kb + ZK <= K && b1 + ZK <= N) {
         const int a = rm.map(a1, N);
         const int bt = rm.map(b1, N);
@@ -130,30 +126,33 @@ __device__ __forceinline__ void load_bubble_window(const GLOBAL_AS T *brow, cons
 #pragma unroll
                 for (int e = 0; e < VW; ++e) tmp[q + e] = v[e];
             }
+            // a per-lane select between two fixed register orders (an index
+            // computed from refl would become a dynamic register-array access)
+            const bool refl = rm.refl;
 #pragma unroll
-            for (int q = 0; q < ZK; ++q) out[q] = rm.refl ? tmp[ZK - 1 - q] : tmp[q];
+            for (int q = 0; q < ZK; ++q) {
+                const T fwd = tmp[q], rev = tmp[ZK - 1 - q];
+                out[q] = refl ? rev : fwd;
+            }
             return;
         }
     }
+    int aa = a1, bb = b1;
 #pragma unroll
     for (int q = 0; q < ZK; ++q) {
-        const int k = kb + q;
-        if (k < K) {
-            const int aa = k / N, bb = k - aa * N;
-            out[q] = brow[rm.map(aa, N) * N + rm.map(bb, N)];
-        } else {
-            out[q] = T(0);
-        }
+        out[q] = kb + q < K ? brow[rm.map(aa, N) * N + rm.map(bb, N)] : T(0);
+        if (++bb == N) { bb = 0; ++aa; }
     }
 }
 
-// block -> (term, m tile, c tile, K part); heaviest channel (phd) first
+// block -> (kind, m tile, c tile, K part); heaviest kind first
+template <bool SPLIT>
 __device__ __forceinline__ Work decode_block(const FusedContractArgs &P, int id) {
     const int per_term = P.mtiles * P.ctiles * P.KS;
     Work w;
-    const int order[3] = {TERM_PHD, TERM_PHC, TERM_PP};
     const int t = id / per_term;
-    w.term = order[t];
+    if (SPLIT) w.term = t == 0 ? TERM_PH : TERM_PP;
+    else w.term = t == 0 ? TERM_PHD : (t == 1 ? TERM_PHC : TERM_PP);
     id -= t * per_term;
     w.ks = id % P.KS;
     id /= P.KS;
@@ -246,15 +245,16 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
                 const int m = m0 + row;
                 if (tid + i * kThreads < NCH && ea[i] >= 0 && m < N)
                     ra[p][i] = *reinterpret_cast<const GLOBAL_AS d2_t *>(
-                        Ap + (static_cast<int64_t>(ea[i]) * N + m) * kContractChunk + part * 2);
+                        Ap + (static_cast<int64_t>(ent_chunk(ea[i])) * N + m) * kContractChunk + part * 2);
                 else
                     ra[p][i] = d2_t{0.0, 0.0};
             }
         }
         const bool zok = cvalid && ez >= 0;
-        const int kb = zok ? ez * kContractChunk + zoff : 0;
-        load_bubble_window<ZK, 2, double, d2_t>(brow, rm, N, K, kb, zok, rb);
-        int a = kb / N, b = kb - a * N;
+        const int kb = zok ? ent_chunk(ez) * kContractChunk + zoff : 0;
+        int a = zok ? ent_a(ez) : 0, b = zok ? ent_b(ez) + zoff : 0;
+        if (b >= N) { b -= N; ++a; }
+        load_bubble_window<ZK, 2, double, d2_t>(brow, rm, N, K, kb, a, b, zok, rb);
 #pragma unroll
         for (int q = 0; q < ZK; ++q) {
             const bool ok = zok && kb + q < K;
@@ -350,12 +350,25 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
 }
 
 // ------------------------------------------------------------------ split BF16
-template <int TERM, int BM>
+// bf16 offset of (row r, 16-byte chunk c) in a [rows][32] LDS tile: the four
+// chunks of a row are XOR-swizzled by bits 2-3 of the row, so the 16 rows an
+// MFMA operand read touches (and the rows written together) fall in distinct
+// banks without padding the rows.
+__device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 2) & 3)) << 3); }
+
+// KIND = TERM_PP: one product.  KIND = TERM_PH: the phc product and both phd
+// products in one block; all three read the same ph bubble row of a column,
+// so its window (and the index work around it) is loaded once for three
+// Z tiles.  Product p feeds accumulator 0 (phc) for p = 0, else 1 (phd).
+template <int KIND, int BM>
 __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Work &w, uint16_t *smem) {
+    constexpr bool PH = KIND == TERM_PH;
+    constexpr int TT = PH ? TERM_PHC : TERM_PP;   // term whose bubble rows and tile lists are read
     constexpr int BK = 32;
     constexpr int ZK = BK / 4;    // k per thread in the Z loader
-    constexpr int LD = BK + 8;    // bf16 row pitch: rows stay 16-byte aligned
-    constexpr int NP = TERM == TERM_PHD ? 2 : 1;
+    constexpr int LD = BK;        // bf16 row pitch; chunks swizzled by swz()
+    constexpr int NP = PH ? 3 : 1;
+    constexpr int NACC = PH ? 2 : 1;
     constexpr int G = BK / kContractChunk;
     constexpr int NCH = G * BM;                         // 16-byte A pieces (one chunk of one row)
     constexpr int ACH = (NCH + kThreads - 1) / kThreads;
@@ -366,29 +379,36 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     const int NC = N * N;
     const int64_t n3 = P.n3;
     const int m0 = w.mtile * BM, c0 = w.ctile * BC;
-    const TileK<G> tk(P, TERM, w);
+    const TileK<G> tk(P, TT, w);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const GLOBAL_AS uint16_t *Ahl[2] = {gload_ptr(P.Ahl[TERM][0]), gload_ptr(P.Ahl[TERM][1])};
-    const GLOBAL_AS float *B = gload_ptr(static_cast<const float *>(P.B[TERM]));
-    const GLOBAL_AS int32_t *colrow = gload_ptr(P.colrow[TERM]);
+    const GLOBAL_AS uint16_t *Ahl[NP];
+    if constexpr (PH) {
+        Ahl[0] = gload_ptr(P.Ahl[TERM_PHC][0]);
+        Ahl[1] = gload_ptr(P.Ahl[TERM_PHD][0]);
+        Ahl[2] = gload_ptr(P.Ahl[TERM_PHD][1]);
+    } else {
+        Ahl[0] = gload_ptr(P.Ahl[TERM_PP][0]);
+    }
+    const GLOBAL_AS float *B = gload_ptr(static_cast<const float *>(P.B[TT]));
+    const GLOBAL_AS int32_t *colrow = gload_ptr(P.colrow[TT]);
 
     // A piece ch = tid + i * kThreads: row ch % BM of list slot ch / BM, so
     // consecutive lanes read consecutive rows of one chunk (chunk-major operand)
     static_assert(ZK == kContractChunk && G == 4, "split slots");
     // Z loader: column at tile position cl, list slot zslot (one chunk)
     const int zslot = tid & 3;
-    const int cl = tid >> 2, zk = zslot * ZK;
+    const int cl = tid >> 2;
     const bool cvalid = c0 + cl < NC;
-    const int c = cvalid ? gload_ptr(P.cperm[TERM])[c0 + cl] : 0;
+    const int c = cvalid ? gload_ptr(P.cperm[TT])[c0 + cl] : 0;
     const RowMap rm = decode_rowmap(cvalid ? colrow[c] : 0, N);
     const GLOBAL_AS float *brow = B + static_cast<int64_t>(rm.row) * K;
-    const GLOBAL_AS float *g0 = gload_ptr(P.G32[TERM][0]) + static_cast<int64_t>(c) * N;
-    const GLOBAL_AS float *g1 = TERM == TERM_PHD
-                                    ? gload_ptr(P.G32[TERM][1]) + static_cast<int64_t>(c / N) * K
-                                    : nullptr;
+    // gather factors: pp V(j1,j2,a); phc V(b,j2,j3); phd V(j1,b,j3) and V(j1,b,a)
+    const GLOBAL_AS float *g0 = gload_ptr(P.G32[TT][0]) + static_cast<int64_t>(c) * N;
+    const GLOBAL_AS float *gd = PH ? gload_ptr(P.G32[TERM_PHD][0]) + static_cast<int64_t>(c) * N : nullptr;
+    const GLOBAL_AS float *g1 = PH ? gload_ptr(P.G32[TERM_PHD][1]) + static_cast<int64_t>(c / N) * K : nullptr;
 
     u32x4_t ra[NP][2][ACH];
-    float rb[ZK], rg0[ZK], rg1[ZK];
+    float rb[ZK], rg[NP][ZK];
 
     // ea[i]: list entry of the slot of A piece i; e: of the Z window
     auto load = [&](const int (&ea)[ACH], int e) {
@@ -402,39 +422,64 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
                     const int m = m0 + ch % BM;
                     if (ch < NCH && ea[i] >= 0 && m < N)
                         ra[p][hl][i] = *reinterpret_cast<const GLOBAL_AS u32x4_t *>(
-                            Ahl[p] + hl * n3 + (static_cast<int64_t>(ea[i]) * N + m) * kContractChunk);
+                            Ahl[p] + hl * n3 + (static_cast<int64_t>(ent_chunk(ea[i])) * N + m) * kContractChunk);
                     else
                         ra[p][hl][i] = u32x4_t{0u, 0u, 0u, 0u};
                 }
         const bool zok = cvalid && e >= 0;
-        const int kb = zok ? e * kContractChunk : 0;
-        load_bubble_window<ZK, 4, float, f4_t>(brow, rm, N, K, kb, zok, rb);
-        int a = kb / N, b = kb - a * N;
-        if (TERM != TERM_PP && zok && b + ZK <= N && (b & 3) == 0 && (N & 3) == 0) {
+        const int kb = zok ? ent_chunk(e) * kContractChunk : 0;
+        const int a = zok ? ent_a(e) : 0, b = zok ? ent_b(e) : 0;
+        load_bubble_window<ZK, 4, float, f4_t>(brow, rm, N, K, kb, a, b, zok, rb);
+        if (!zok) {
 #pragma unroll
-            for (int q = 0; q < ZK; q += 4) {
-                const f4_t v = *reinterpret_cast<const GLOBAL_AS f4_t *>(g0 + b + q);
-                rg0[q] = v[0]; rg0[q + 1] = v[1]; rg0[q + 2] = v[2]; rg0[q + 3] = v[3];
+            for (int p = 0; p < NP; ++p)
+#pragma unroll
+                for (int q = 0; q < ZK; ++q) rg[p][q] = 0.f;
+            return;
+        }
+        const bool inrow = b + ZK <= N;   // the window stays in one a (always when N % 8 == 0)
+        if constexpr (!PH) {
+            if (inrow) {
+                const float v = g0[a];
+#pragma unroll
+                for (int q = 0; q < ZK; ++q) rg[0][q] = v;
+            } else {
+                int aa = a, bb = b;
+#pragma unroll
+                for (int q = 0; q < ZK; ++q) {
+                    rg[0][q] = kb + q < K ? g0[aa] : 0.f;
+                    if (++bb == N) { bb = 0; ++aa; }
+                }
             }
         } else {
-            int aa = a, bb = b;
+            if (inrow && (b & 3) == 0) {
 #pragma unroll
-            for (int q = 0; q < ZK; ++q) {
-                const bool ok = zok && kb + q < K;
-                rg0[q] = ok ? (TERM == TERM_PP ? g0[aa] : g0[bb]) : 0.f;
-                if (++bb == N) { bb = 0; ++aa; }
+                for (int q = 0; q < ZK; q += 4) {
+                    const f4_t u = *reinterpret_cast<const GLOBAL_AS f4_t *>(g0 + b + q);
+                    const f4_t v = *reinterpret_cast<const GLOBAL_AS f4_t *>(gd + b + q);
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) { rg[0][q + t] = u[t]; rg[1][q + t] = v[t]; }
+                }
+            } else {
+                int bb = b;
+#pragma unroll
+                for (int q = 0; q < ZK; ++q) {
+                    const bool ok = kb + q < K;
+                    rg[0][q] = ok ? g0[bb] : 0.f;
+                    rg[1][q] = ok ? gd[bb] : 0.f;
+                    if (++bb == N) bb = 0;
+                }
             }
-        }
-        if (TERM == TERM_PHD) {
-            if (zok && kb + ZK <= K) {
+            if (kb + ZK <= K) {
 #pragma unroll
                 for (int q = 0; q < ZK; q += 4) {
                     const f4_t v = *reinterpret_cast<const GLOBAL_AS f4_t *>(g1 + kb + q);
-                    rg1[q] = v[0]; rg1[q + 1] = v[1]; rg1[q + 2] = v[2]; rg1[q + 3] = v[3];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) rg[2][q + t] = v[t];
                 }
             } else {
 #pragma unroll
-                for (int q = 0; q < ZK; ++q) rg1[q] = (zok && kb + q < K) ? g1[kb + q] : 0.f;
+                for (int q = 0; q < ZK; ++q) rg[2][q] = kb + q < K ? g1[kb + q] : 0.f;
             }
         }
     };
@@ -447,32 +492,33 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
                 for (int i = 0; i < ACH; ++i) {
                     const int ch = tid + i * kThreads;
                     if (ch >= NCH) continue;
-                    const int row = ch % BM, kq = (ch / BM) * kContractChunk;
-                    *reinterpret_cast<u32x4_t *>(sA + ((p * 2 + hl) * BM + row) * LD + kq) = ra[p][hl][i];
+                    *reinterpret_cast<u32x4_t *>(sA + (p * 2 + hl) * BM * LD + swz(ch % BM, ch / BM)) = ra[p][hl][i];
                 }
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            u16x8_t hi, lo;
+            bf8_t hi, lo;   // round-to-nearest-even conversions (v_cvt_pk_bf16_f32)
 #pragma unroll
             for (int q = 0; q < ZK; ++q) {
-                const float z = rb[q] * (p == 0 ? rg0[q] : rg1[q]);
-                const uint16_t zh = bf16_rne(z);
+                const float z = rb[q] * rg[p][q];
+                const __bf16 zh = static_cast<__bf16>(z);
                 hi[q] = zh;
-                lo[q] = bf16_rne(z - bf16_to_f(zh));
+                lo[q] = static_cast<__bf16>(z - static_cast<float>(zh));
             }
-            *reinterpret_cast<u16x8_t *>(sZ + ((p * 2 + 0) * BC + cl) * LD + zk) = hi;
-            *reinterpret_cast<u16x8_t *>(sZ + ((p * 2 + 1) * BC + cl) * LD + zk) = lo;
+            *reinterpret_cast<bf8_t *>(sZ + (p * 2 + 0) * BC * LD + swz(cl, zslot)) = hi;
+            *reinterpret_cast<bf8_t *>(sZ + (p * 2 + 1) * BC * LD + swz(cl, zslot)) = lo;
         }
     };
 
     constexpr int RT = BM / 32;
     const int wm = wave & 1, wc = wave >> 1;
-    f4_t acc[RT][2];
+    f4_t acc[NACC][RT][2];
 #pragma unroll
-    for (int i = 0; i < RT; ++i) {
-        acc[i][0] = f4_t{0.f, 0.f, 0.f, 0.f};
-        acc[i][1] = f4_t{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int u = 0; u < NACC; ++u)
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            acc[u][i][0] = f4_t{0.f, 0.f, 0.f, 0.f};
+            acc[u][i][1] = f4_t{0.f, 0.f, 0.f, 0.f};
+        }
     int ea[ACH], ez;
     auto fetch = [&](int st) {
 #pragma unroll
@@ -492,29 +538,28 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
             load(ea, ez);
             fetch(st + 2);
         }
+        const int kch = lane >> 4;   // the lane's 8-wide k chunk of the step
 #pragma unroll
-        for (int ks = 0; ks < BK / 32; ++ks) {
-            const int kof = ks * 32 + (lane >> 4) * 8;
+        for (int p = 0; p < NP; ++p) {
+            const int u = (PH && p > 0) ? 1 : 0;
+            bf8_t zh[2], zl[2];
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                bf8_t zh[2], zl[2];
+            for (int ci = 0; ci < 2; ++ci) {
+                const int zr = wc * 32 + ci * 16 + (lane & 15);
+                zh[ci] = *reinterpret_cast<const bf8_t *>(sZ + (p * 2 + 0) * BC * LD + swz(zr, kch));
+                zl[ci] = *reinterpret_cast<const bf8_t *>(sZ + (p * 2 + 1) * BC * LD + swz(zr, kch));
+            }
+#pragma unroll
+            for (int ri = 0; ri < RT; ++ri) {
+                const int ar = wm * (BM / 2) + ri * 16 + (lane & 15);
+                const bf8_t ah = *reinterpret_cast<const bf8_t *>(sA + (p * 2 + 0) * BM * LD + swz(ar, kch));
+                const bf8_t al = *reinterpret_cast<const bf8_t *>(sA + (p * 2 + 1) * BM * LD + swz(ar, kch));
 #pragma unroll
                 for (int ci = 0; ci < 2; ++ci) {
-                    const int zr = wc * 32 + ci * 16 + (lane & 15);
-                    zh[ci] = *reinterpret_cast<const bf8_t *>(sZ + ((p * 2 + 0) * BC + zr) * LD + kof);
-                    zl[ci] = *reinterpret_cast<const bf8_t *>(sZ + ((p * 2 + 1) * BC + zr) * LD + kof);
-                }
-#pragma unroll
-                for (int ri = 0; ri < RT; ++ri) {
-                    const int ar = wm * (BM / 2) + ri * 16 + (lane & 15);
-                    const bf8_t ah = *reinterpret_cast<const bf8_t *>(sA + ((p * 2 + 0) * BM + ar) * LD + kof);
-                    const bf8_t al = *reinterpret_cast<const bf8_t *>(sA + ((p * 2 + 1) * BM + ar) * LD + kof);
-#pragma unroll
-                    for (int ci = 0; ci < 2; ++ci) {
-                        acc[ri][ci] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, zh[ci], acc[ri][ci], 0, 0, 0);
-                        acc[ri][ci] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, zl[ci], acc[ri][ci], 0, 0, 0);
-                        acc[ri][ci] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, zh[ci], acc[ri][ci], 0, 0, 0);
-                    }
+                    f4_t &d = acc[u][ri][ci];
+                    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, zh[ci], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, zl[ci], d, 0, 0, 0);
+                    d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, zh[ci], d, 0, 0, 0);
                 }
             }
         }
@@ -523,18 +568,23 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     // bf16 16x16x32 accumulator layout: lane l, register r holds row 4(l>>4) + r, column l&15
     // output C[ks][tile position][m]: four consecutive m per lane, one 32-byte store
     // (N % 4 == 0, so a group of four rows is either wholly inside or outside)
-    GLOBAL_AS double *Cout = gstore_ptr(P.C[TERM]) + static_cast<int64_t>(w.ks) * P.n3;
 #pragma unroll
-    for (int ci = 0; ci < 2; ++ci) {
-        const int pos = c0 + wc * 32 + ci * 16 + (lane & 15);
-        if (pos >= NC) continue;
+    for (int u = 0; u < NACC; ++u) {
+        const int term = PH ? (u == 0 ? TERM_PHC : TERM_PHD) : TERM_PP;
+        GLOBAL_AS double *Cout = gstore_ptr(P.C[term]) + static_cast<int64_t>(w.ks) * P.n3;
 #pragma unroll
-        for (int ri = 0; ri < RT; ++ri) {
-            const int m = m0 + wm * (BM / 2) + ri * 16 + 4 * (lane >> 4);
-            if (m < N) {
-                const d4_t v{static_cast<double>(acc[ri][ci][0]), static_cast<double>(acc[ri][ci][1]),
-                             static_cast<double>(acc[ri][ci][2]), static_cast<double>(acc[ri][ci][3])};
-                *reinterpret_cast<GLOBAL_AS d4_t *>(Cout + static_cast<int64_t>(pos) * N + m) = v;
+        for (int ci = 0; ci < 2; ++ci) {
+            const int pos = c0 + wc * 32 + ci * 16 + (lane & 15);
+            if (pos >= NC) continue;
+#pragma unroll
+            for (int ri = 0; ri < RT; ++ri) {
+                const int m = m0 + wm * (BM / 2) + ri * 16 + 4 * (lane >> 4);
+                if (m < N) {
+                    const f4_t &a4 = acc[u][ri][ci];
+                    const d4_t v{static_cast<double>(a4[0]), static_cast<double>(a4[1]),
+                                 static_cast<double>(a4[2]), static_cast<double>(a4[3])};
+                    *reinterpret_cast<GLOBAL_AS d4_t *>(Cout + static_cast<int64_t>(pos) * N + m) = v;
+                }
             }
         }
     }
@@ -544,8 +594,7 @@ template <int BM, bool SPLIT>
 __device__ __forceinline__ void run_work(const FusedContractArgs &P, const Work &w, double *smem_d) {
     if (SPLIT) {
         uint16_t *smem = reinterpret_cast<uint16_t *>(smem_d);
-        if (w.term == TERM_PHD) body_split<TERM_PHD, BM>(P, w, smem);
-        else if (w.term == TERM_PHC) body_split<TERM_PHC, BM>(P, w, smem);
+        if (w.term == TERM_PH) body_split<TERM_PH, BM>(P, w, smem);
         else body_split<TERM_PP, BM>(P, w, smem);
     } else {
         if (w.term == TERM_PHD) body_f64<TERM_PHD, BM>(P, w, smem_d);
@@ -557,13 +606,13 @@ __device__ __forceinline__ void run_work(const FusedContractArgs &P, const Work 
 template <int BM>
 __global__ __launch_bounds__(kThreads) void contract_f64_fused(FusedContractArgs P) {
     extern __shared__ double smem_d[];
-    run_work<BM, false>(P, decode_block(P, blockIdx.x), smem_d);
+    run_work<BM, false>(P, decode_block<false>(P, blockIdx.x), smem_d);
 }
 
 template <int BM>
 __global__ __launch_bounds__(kThreads) void contract_split_fused(FusedContractArgs P) {
     extern __shared__ double smem_d[];
-    run_work<BM, true>(P, decode_block(P, blockIdx.x), smem_d);
+    run_work<BM, true>(P, decode_block<true>(P, blockIdx.x), smem_d);
 }
 
 // Persistent launch over a work list of many flows.  The list of one block
@@ -595,7 +644,7 @@ __global__ __launch_bounds__(kThreads) void contract_persistent(const FusedContr
             const int2 it = qi[i];
             if (states && states[it.x][FRG_ST_REASON] != 0.0) continue;
             const FusedContractArgs P = args[it.x];
-            run_work<BM, SPLIT>(P, decode_block(P, it.y), smem_d);
+            run_work<BM, SPLIT>(P, decode_block<SPLIT>(P, it.y), smem_d);
             __syncthreads();
         }
     }
@@ -611,25 +660,31 @@ __global__ __launch_bounds__(kThreads) void contract_items(const FusedContractAr
     const int2 it = items[blockIdx.x];
     if (states && states[it.x][FRG_ST_REASON] != 0.0) return;
     const FusedContractArgs P = args[it.x];
-    run_work<BM, SPLIT>(P, decode_block(P, it.y), smem_d);
+    run_work<BM, SPLIT>(P, decode_block<SPLIT>(P, it.y), smem_d);
 }
 
 __global__ void reset_counters(int *counters, int n) {
     if (static_cast<int>(threadIdx.x) < n) counters[threadIdx.x] = 0;
 }
 
+constexpr int contract_kinds_of(bool split) { return split ? 2 : 3; }
+
+// LDS of one block: split [3 products][hi, lo] A (BM x 32) and Z (64 x 32)
+// bf16 tiles; FP64 [2 products] A (BM x 17) and Z (64 x 17) tiles
+constexpr size_t lds_bytes(bool split, int bm) {
+    return split ? sizeof(uint16_t) * (3 * 2 * bm * 32 + 3 * 2 * BC * 32)
+                 : sizeof(double) * (2 * bm * 17 + 2 * BC * 17);
+}
+
 template <int BM>
 void launch_bm(FusedContractArgs a, bool split, hipStream_t s) {
     a.mtiles = (a.N + BM - 1) / BM;
     a.ctiles = (a.N * a.N + BC - 1) / BC;
-    const int blocks = 3 * a.mtiles * a.ctiles * a.KS;
-    if (split) {
-        const size_t lds = sizeof(uint16_t) * (2 * 2 * BM * (32 + 8) + 2 * 2 * BC * (32 + 8));
-        hipLaunchKernelGGL(contract_split_fused<BM>, dim3(blocks), dim3(kThreads), lds, s, a);
-    } else {
-        const size_t lds = sizeof(double) * (2 * BM * 17 + 2 * BC * 17);
-        hipLaunchKernelGGL(contract_f64_fused<BM>, dim3(blocks), dim3(kThreads), lds, s, a);
-    }
+    const int blocks = contract_kinds_of(split) * a.mtiles * a.ctiles * a.KS;
+    if (split)
+        hipLaunchKernelGGL(contract_split_fused<BM>, dim3(blocks), dim3(kThreads), lds_bytes(true, BM), s, a);
+    else
+        hipLaunchKernelGGL(contract_f64_fused<BM>, dim3(blocks), dim3(kThreads), lds_bytes(false, BM), s, a);
 }
 
 // flags of the k chunks of one column tile (block = tile)
@@ -666,9 +721,13 @@ void launch_tile_pattern(const uint8_t *bins, const int32_t *colfull, const int3
                        flags);
 }
 
-size_t contract_lds_bytes(bool split) {
-    return split ? sizeof(uint16_t) * (2 * 2 * 96 * (32 + 8) + 2 * 2 * BC * (32 + 8))
-                 : sizeof(double) * (2 * 96 * 17 + 2 * BC * 17);
+size_t contract_lds_bytes(bool split) { return lds_bytes(split, 96); }
+
+int contract_kinds(bool split) { return contract_kinds_of(split); }
+
+int contract_kind_products(bool split, int kind) {
+    if (split) return kind == 0 ? 3 : 1;
+    return kind == 0 ? 2 : 1;
 }
 
 template <bool SPLIT, int BM>
