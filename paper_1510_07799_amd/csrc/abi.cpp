@@ -38,6 +38,8 @@ struct frg_ctx_s {
             *d_klist[2] = {nullptr, nullptr}, *d_cpos[2] = {nullptr, nullptr};
     int32_t *d_cperm_id = nullptr, *d_koff_dense = nullptr, *d_klist_dense = nullptr;
     int64_t kchunks_active[2] = {0, 0};
+    int kparts = 0;        // K parts the list offsets are cut for (fixed at create)
+    bool kfixed = false;   // parts by fixed chunk ranges (FRG_KPARTS=fixed) or equal shares
     // rhs workspace
     double *d_pa64 = nullptr, *d_T = nullptr;
     float *d_pa32 = nullptr;
@@ -287,6 +289,7 @@ frg_status build_orbits(frg_ctx ctx) {
 // K parts of the fused contraction: enough blocks for several rounds over the
 // 256 compute units (measured best at N = 96: 8 parts); FRG_KSPLIT overrides
 int ksplit(frg_ctx ctx) {
+    if (ctx->kparts > 0) return ctx->kparts;
     if (ctx->ks_override > 0) return ctx->ks_override;
     const int N = ctx->g.N;
     const int bm = frg::contract_block_rows(N);
@@ -325,13 +328,37 @@ uint64_t hilbert_key(double qx, double qy) {
 // Column tiles of the contraction.  Columns (pp: (j1, j2), ph: (y, x)) are
 // ordered along the Hilbert curve of their transfer momentum; for every tile
 // of 64 consecutive columns the second-line table gives the k chunks where
-// any of its bubble rows can be nonzero (T independent); tile t's entries are
-// klist[koff[t] .. koff[t+1]).
+// any of its bubble rows can be nonzero (T independent).  Tile t's list is cut
+// into the contraction's KS parts: part ks is klist[koff[t*(KS+1)+ks] ..
+// koff[t*(KS+1)+ks+1]), either an equal share of the entries (cut at multiples
+// of 4 entries, one split-path step) or, with FRG_KPARTS=fixed, the entries
+// with chunk ids in [ks*nch/KS, (ks+1)*nch/KS) (the same k range in every
+// tile, so the blocks of one part share one slice of the A operands).
+void cut_parts(const std::vector<int32_t> &chunk_of_entry, int begin, int end, int KS, int nch, bool fixed,
+               int32_t *off) {
+    const int n = end - begin;
+    for (int ks = 0; ks <= KS; ++ks) {
+        if (!fixed) {
+            const int64_t e = (static_cast<int64_t>((n + 3) / 4) * ks / KS) * 4;
+            off[ks] = begin + static_cast<int32_t>(std::min<int64_t>(e, n));
+        } else {
+            const int lim = static_cast<int>(static_cast<int64_t>(nch) * ks / KS);
+            int i = begin;
+            while (i < end && chunk_of_entry[i] < lim) ++i;
+            off[ks] = i;
+        }
+    }
+}
+
 frg_status build_ktiles(frg_ctx ctx) {
     const auto &g = ctx->g;
     const int N = g.N, NC = N * N;
     const int tiles = (NC + frg::kContractCols - 1) / frg::kContractCols;
     const int nch = NC / frg::kContractChunk;
+    const char *kp = std::getenv("FRG_KPARTS");
+    ctx->kfixed = kp && std::strcmp(kp, "fixed") == 0;
+    const int KS = ksplit(ctx);
+    ctx->kparts = KS;
     std::vector<uint8_t> flags(static_cast<size_t>(tiles) * nch);
     for (int cls = 0; cls < 2; ++cls) {
         std::vector<int32_t> colfull(NC), perm(NC);
@@ -363,13 +390,17 @@ frg_status build_ktiles(frg_ctx ctx) {
         if (d_colfull) hipFree(d_colfull);
         if (d_flags) hipFree(d_flags);
         if (e != hipSuccess) return fail(FRG_EDEVICE, std::string("column tiles: ") + hipGetErrorString(e));
-        std::vector<int32_t> koff(tiles + 1), klist;
+        std::vector<int32_t> koff(static_cast<size_t>(tiles) * (KS + 1)), klist, chunk;
         for (int t = 0; t < tiles; ++t) {
-            koff[t] = static_cast<int32_t>(klist.size());
+            const int begin = static_cast<int>(klist.size());
             for (int j = 0; j < nch; ++j)
-                if (flags[static_cast<size_t>(t) * nch + j]) klist.push_back(list_entry(j, N));
+                if (flags[static_cast<size_t>(t) * nch + j]) {
+                    klist.push_back(list_entry(j, N));
+                    chunk.push_back(j);
+                }
+            cut_parts(chunk, begin, static_cast<int>(klist.size()), KS, nch, ctx->kfixed,
+                      &koff[static_cast<size_t>(t) * (KS + 1)]);
         }
-        koff[tiles] = static_cast<int32_t>(klist.size());
         ctx->kchunks_active[cls] = static_cast<int64_t>(klist.size());
         TRY(upload(ctx, &ctx->d_koff[cls], koff.data(), koff.size()));
         TRY(upload(ctx, &ctx->d_klist[cls], klist.data(), klist.size()));
@@ -383,10 +414,16 @@ frg_status ensure_dense_tiles(frg_ctx ctx) {
     const int NC = ctx->g.N * ctx->g.N;
     const int tiles = (NC + frg::kContractCols - 1) / frg::kContractCols;
     const int nch = NC / frg::kContractChunk;
-    std::vector<int32_t> perm(NC), koff(tiles + 1), klist(static_cast<size_t>(tiles) * nch);
+    const int KS = ctx->kparts;
+    std::vector<int32_t> perm(NC), koff(static_cast<size_t>(tiles) * (KS + 1)),
+        klist(static_cast<size_t>(tiles) * nch), chunk(klist.size());
     std::iota(perm.begin(), perm.end(), 0);
-    for (int t = 0; t <= tiles; ++t) koff[t] = t * nch;
-    for (size_t i = 0; i < klist.size(); ++i) klist[i] = list_entry(static_cast<int>(i % nch), ctx->g.N);
+    for (size_t i = 0; i < klist.size(); ++i) {
+        chunk[i] = static_cast<int32_t>(i % nch);
+        klist[i] = list_entry(chunk[i], ctx->g.N);
+    }
+    for (int t = 0; t < tiles; ++t)
+        cut_parts(chunk, t * nch, (t + 1) * nch, KS, nch, ctx->kfixed, &koff[static_cast<size_t>(t) * (KS + 1)]);
     TRY(upload(ctx, &ctx->d_cperm_id, perm.data(), perm.size()));
     TRY(upload(ctx, &ctx->d_koff_dense, koff.data(), koff.size()));
     TRY(upload(ctx, &ctx->d_klist_dense, klist.data(), klist.size()));

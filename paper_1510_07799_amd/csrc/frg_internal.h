@@ -81,7 +81,8 @@ struct FusedContractArgs {
     // column tiles: tile position -> column (columns ordered so that a tile's
     // transfers are close in k space), and per tile the list of 8-wide k
     // chunks that hold a structural nonzero of any of its bubble rows
-    // (klist[koff[t] .. koff[t+1]) in increasing order; an entry packs the
+    // in increasing order; K part ks of tile t is klist[koff[t*(KS+1)+ks] ..
+    // koff[t*(KS+1)+ks+1]), KS being the value the offsets were cut for; an entry packs the
     // chunk id j and the patch pair (a, b) of k = 8j = a*N + b as
     // j | a << 13 | b << 21)
     const int32_t *cperm[3];

@@ -161,9 +161,9 @@ __device__ __forceinline__ Work decode_block(const FusedContractArgs &P, int id)
     return w;
 }
 
-// The active k chunks of a block: entries [st_lo*G, st_hi*G) of its column
-// tile's list, G chunks per step (K part ks of KS takes an equal share of the
-// tile's steps).  Entries past the list read as -1 (a zero chunk).  Each
+// The active k chunks of a block: the entries of its K part of its column
+// tile's list, G chunks per step; entries past the part read as -1 (a zero
+// chunk).  Each
 // thread reads only the entries of the list slots its loads serve, one step
 // ahead of their use, as ordinary vector loads: a uniform (scalar) load would
 // share its wait counter with the LDS traffic of the MFMA loop.
@@ -172,13 +172,12 @@ struct TileK {
     const GLOBAL_AS int32_t *kl;
     int nk, st_lo, st_hi;
     __device__ __forceinline__ TileK(const FusedContractArgs &P, int term, const Work &w) {
-        const GLOBAL_AS int32_t *koff = gload_ptr(P.koff[term]);
-        const int kbeg = koff[w.ctile];
-        nk = koff[w.ctile + 1] - kbeg;
+        const GLOBAL_AS int32_t *koff = gload_ptr(P.koff[term]) + static_cast<int64_t>(w.ctile) * (P.KS + 1) + w.ks;
+        const int kbeg = koff[0];
+        nk = koff[1] - kbeg;
         kl = gload_ptr(P.klist[term]) + kbeg;
-        const int nst = (nk + G - 1) / G;
-        st_lo = static_cast<int>((static_cast<int64_t>(nst) * w.ks) / P.KS);
-        st_hi = static_cast<int>((static_cast<int64_t>(nst) * (w.ks + 1)) / P.KS);
+        st_lo = 0;
+        st_hi = (nk + G - 1) / G;
     }
     // chunk id in slot `slot` (0 .. G-1) of step st
     __device__ __forceinline__ int entry(int st, int slot) const {
