@@ -492,10 +492,11 @@ frg_status ensure_c(frg_ctx ctx, int KS) {
     if (ctx->c_parts >= KS) return FRG_OK;
     if (ctx->d_C) {
         hipFree(ctx->d_C);
-        ctx->ws_bytes -= sizeof(double) * 3 * static_cast<size_t>(ctx->c_parts) * ctx->n3;
+        ctx->ws_bytes -= sizeof(double) * 3 * static_cast<size_t>(ctx->c_parts + 1) * ctx->n3;
         ctx->d_C = nullptr;
     }
-    TRY(dalloc(ctx, &ctx->d_C, 3 * static_cast<size_t>(KS) * ctx->n3));
+    // K-part partials [3][KS][n3], then their sums [3][n3]
+    TRY(dalloc(ctx, &ctx->d_C, 3 * static_cast<size_t>(KS + 1) * ctx->n3));
     ctx->c_parts = KS;
     return FRG_OK;
 }
@@ -541,7 +542,10 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     }
     {
         KTimer kt(ctx, FRG_K_COMBINE, s);
-        frg::launch_combine(Cpp, Cc, Cd, N, KS, col_pos(ctx, 0), col_pos(ctx, 1), ctx->d_T, scale_by_T, F, s);
+        double *Cs = ctx->d_C + 3 * KS * n3;
+        frg::launch_sum_parts(ctx->d_C, split, KS, n3, Cs, s);
+        frg::launch_combine(Cs, Cs + n3, Cs + 2 * n3, false, N, 1, col_pos(ctx, 0), col_pos(ctx, 1), ctx->d_T,
+                            scale_by_T, F, s);
     }
     HIPCHK(hipGetLastError());
     return FRG_OK;
@@ -1013,8 +1017,8 @@ struct frg_batch_s {
     double **d_states = nullptr;
     double *d_state_all = nullptr, *h_state_all = nullptr;
     int2 *d_it_prep = nullptr, *d_it_bub = nullptr, *d_it_n3 = nullptr, *d_it_red = nullptr,
-         *d_it_con = nullptr, *d_it_comb = nullptr;
-    int n_prep = 0, n_bub = 0, n_n3 = 0, n_red = 0, n_con = 0, n_comb = 0;
+         *d_it_con = nullptr, *d_it_comb = nullptr, *d_it_sum = nullptr;
+    int n_prep = 0, n_bub = 0, n_n3 = 0, n_red = 0, n_con = 0, n_comb = 0, n_sum = 0;
     // contraction work list grouped by block height class (32, 64, 96), each cut
     // into 8 per-XCD queues: d_q[class] = {start[8], count[8]}
     int con_count[3] = {0, 0, 0};
@@ -1058,7 +1062,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     std::vector<frg::FusedContractArgs> ca[3];
     for (int s = 0; s < 3; ++s) ca[s].resize(b->n);
     std::vector<double *> st(b->n);
-    std::vector<int2> it_prep, it_bub, it_n3, it_red, it_comb;
+    std::vector<int2> it_prep, it_bub, it_n3, it_red, it_comb, it_sum;
     struct Item { int2 it; int cls, queue; double flow_cost, cost; };
     std::vector<Item> con;
     for (int f = 0; f < b->n; ++f) {
@@ -1085,6 +1089,8 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         for (int j = 0; j < 7; ++j) A.k[j] = c->d_k[j];
         A.yt = c->d_yt; A.y5 = c->d_y5; A.partial = c->d_partial;
         A.perm = c->d_perm; A.ahl = c->d_ahl; A.g32 = c->d_g32; A.C = c->d_C; A.KS = KS;
+        A.f32parts = split ? 1 : 0;
+        A.Csum = c->d_C + 3 * KS * n3;
         A.ppos = col_pos(c, 0); A.phpos = col_pos(c, 1);
         st[f] = A.state;
         frg::BubbleArgs bb = bubble_args(c, split, bpp, bph);
@@ -1120,6 +1126,8 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
             for (int a = 0; a < g.N; ++a) it_bub.push_back(make_int2(f, (ch << 8) | a));
         for (int64_t k = 0; k < (n3 + 255) / 256; ++k) it_n3.push_back(make_int2(f, static_cast<int>(k)));
         for (int k = 0; k < frg::combine_tiles(g.N); ++k) it_comb.push_back(make_int2(f, k));
+        for (int64_t k = 0; k < (3 * n3 + frg::kSumPartsPerBlock - 1) / frg::kSumPartsPerBlock; ++k)
+            it_sum.push_back(make_int2(f, static_cast<int>(k)));
         for (int k = 0; k < A.nred; ++k) it_red.push_back(make_int2(f, k));
         const frg::FusedContractArgs &a0 = ca[0][f];
         const int per_term = a0.mtiles * a0.ctiles * KS;
@@ -1187,12 +1195,14 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     TRY(bupload(&b->d_it_red, it_red));
     TRY(bupload(&b->d_it_con, it_con));
     TRY(bupload(&b->d_it_comb, it_comb));
+    TRY(bupload(&b->d_it_sum, it_sum));
     b->n_prep = static_cast<int>(it_prep.size());
     b->n_bub = static_cast<int>(it_bub.size());
     b->n_n3 = static_cast<int>(it_n3.size());
     b->n_red = static_cast<int>(it_red.size());
     b->n_con = static_cast<int>(it_con.size());
     b->n_comb = static_cast<int>(it_comb.size());
+    b->n_sum = static_cast<int>(it_sum.size());
     b->built_prec = prec;
     if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; b->exec_prec = -1; }
     return FRG_OK;
@@ -1216,6 +1226,7 @@ void batch_rhs_launch(frg_batch b, bool split, double c_stage, int src, int stag
         frg::launch_contract_persistent(b->d_ca[src], b->d_it_con, b->d_q + k * 16, b->d_q + k * 16 + 8,
                                         b->d_counter + 8 * k, states, grid, bms[k], split, s);
     }
+    frg::launch_sum_parts_b(b->d_fa, b->d_it_sum, b->n_sum, s);
     frg::launch_combine_b(b->d_fa, b->d_it_comb, b->n_comb, stage, s);
 }
 
@@ -1292,7 +1303,7 @@ frg_status frg_batch_destroy(frg_batch b) {
     for (frg_ctx c : b->ctx) frg_destroy(c);
     void *ptrs[] = {b->d_fa, b->d_ba, b->d_ca[0], b->d_ca[1], b->d_ca[2], b->d_states, b->d_state_all,
                     b->d_it_prep, b->d_it_bub, b->d_it_n3, b->d_it_red, b->d_it_con, b->d_counter,
-                    b->d_q, b->d_it_flat, b->d_it_comb};
+                    b->d_q, b->d_it_flat, b->d_it_comb, b->d_it_sum};
     for (void *p : ptrs)
         if (p) hipFree(p);
     if (b->h_state_all) hipHostFree(b->h_state_all);
@@ -1436,7 +1447,9 @@ frg_status frg_batch_rhs(frg_batch b, const double *T, double *const *d_V, doubl
         frg_ctx c = b->ctx[f];
         // F from the channel partials (the batched combine left T*F in k[0])
         const int KS = ksplit(c);
-        frg::launch_combine(c->d_C, c->d_C + KS * c->n3, c->d_C + 2 * KS * c->n3, c->g.N, KS,
+        double *Cs = c->d_C + 3 * KS * c->n3;
+        frg::launch_sum_parts(c->d_C, prec == FRG_PREC_SPLIT_BF16, KS, c->n3, Cs, s);
+        frg::launch_combine(Cs, Cs + c->n3, Cs + 2 * c->n3, false, c->g.N, 1,
                             col_pos(c, 0), col_pos(c, 1), c->d_T, 0, d_F[f], s);
     }
     HIPCHK(hipGetLastError());

@@ -92,7 +92,7 @@ struct FusedContractArgs {
     const uint16_t *Ahl[3][2];
     const double *G64[3][2];
     const float *G32[3][2];
-    double *C[3];
+    void *C[3];   // partials: float in the split path, double in the FP64 path
 };
 void launch_contract_fused(const FusedContractArgs &a, bool split, hipStream_t s);
 int contract_block_rows(int N);
@@ -110,12 +110,18 @@ void launch_tile_pattern(const uint8_t *bins, const int32_t *colfull, const int3
                          int nf, int np, uint8_t *flags, hipStream_t s);
 
 // F[j1][j2][j3] = scale * (-Cpp[ppos(j1,j2)][j3] + Cc[phpos(j2,j3)][j1] + Cd[phpos(j1,j3)][j2]),
-// each summed over the K parts; ppos / phpos give the tile position of a
-// column (pp: j1*N+j2, ph: y*N+x); scale = T when scale_by_T
-void launch_combine(const double *Cpp, const double *Cc, const double *Cd, int N, int parts,
+// each summed (in FP64) over the K parts; ppos / phpos give the tile position
+// of a column (pp: j1*N+j2, ph: y*N+x); scale = T when scale_by_T; the
+// partials are float when f32parts, else double
+void launch_combine(const void *Cpp, const void *Cc, const void *Cd, bool f32parts, int N, int parts,
                     const int32_t *ppos, const int32_t *phpos, const double *Tdev, int scale_by_T,
                     double *F, hipStream_t s);
 int combine_tiles(int N);   // blocks of one combine
+// out[t][i] = sum_ks C_t[ks][i] in FP64 for the three channels t, where C_t
+// starts at double offset t*KS*n3 of C and holds float (f32parts) or double
+// partials; out is [3][n3]
+void launch_sum_parts(const double *C, bool f32parts, int KS, int64_t n3, double *out, hipStream_t s);
+constexpr int kSumPartsPerBlock = 1024;   // elements of out per block of the batched sum
 
 // ----------------------------------------------------------------- RK kernels
 struct RkStageArgs {
@@ -158,8 +164,10 @@ struct FlowArgs {
     double *perm;
     uint16_t *ahl;
     float *g32;
-    double *C;   // [3][KS][n3]
+    double *C;   // [3][KS][n3] doubles; the split path keeps float partials in it
     int KS;
+    int f32parts;  // partials are float (split path)
+    double *Csum;  // [3][n3]: partials summed over the K parts
     const int32_t *ppos, *phpos;   // tile position of each pp / ph column
 };
 enum { SRC_V = 0, SRC_YT = 1, SRC_Y5 = 2 };
@@ -178,6 +186,7 @@ void launch_prep_b(const FlowArgs *fa, const int2 *items, int nitems, double c_s
 void launch_layout_b(const FlowArgs *fa, const int2 *items, int nitems, int src, bool split,
                      hipStream_t s);
 void launch_combine_b(const FlowArgs *fa, const int2 *items, int nitems, int stage, hipStream_t s);
+void launch_sum_parts_b(const FlowArgs *fa, const int2 *items, int nitems, hipStream_t s);
 void launch_rk_stage_b(const FlowArgs *fa, const int2 *items, int nitems, const double coef[7],
                        int nk, int dst, hipStream_t s);
 void launch_dp_error_b(const FlowArgs *fa, const int2 *items, int nitems, int nflows,

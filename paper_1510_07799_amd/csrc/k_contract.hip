@@ -333,7 +333,7 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
     }
     // f64 16x16x4 accumulator layout: lane l, register r holds row (l>>4) + 4r, column l&15;
     // output C[ks][tile position][m]: a block's tile is one contiguous range
-    GLOBAL_AS double *Cout = gstore_ptr(P.C[TERM]) + static_cast<int64_t>(w.ks) * P.n3;
+    GLOBAL_AS double *Cout = gstore_ptr(static_cast<double *>(P.C[TERM])) + static_cast<int64_t>(w.ks) * P.n3;
 #pragma unroll
     for (int ci = 0; ci < 2; ++ci) {
         const int pos = c0 + wc * 32 + ci * 16 + (lane & 15);
@@ -565,12 +565,13 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
         __syncthreads();
     }
     // bf16 16x16x32 accumulator layout: lane l, register r holds row 4(l>>4) + r, column l&15
-    // output C[ks][tile position][m]: four consecutive m per lane, one 32-byte store
-    // (N % 4 == 0, so a group of four rows is either wholly inside or outside)
+    // output C[ks][tile position][m] in float (the accumulators' own precision):
+    // four consecutive m per lane, one 16-byte store (N % 4 == 0, so a group of
+    // four rows is either wholly inside or outside)
 #pragma unroll
     for (int u = 0; u < NACC; ++u) {
         const int term = PH ? (u == 0 ? TERM_PHC : TERM_PHD) : TERM_PP;
-        GLOBAL_AS double *Cout = gstore_ptr(P.C[term]) + static_cast<int64_t>(w.ks) * P.n3;
+        GLOBAL_AS float *Cout = gstore_ptr(static_cast<float *>(P.C[term])) + static_cast<int64_t>(w.ks) * P.n3;
 #pragma unroll
         for (int ci = 0; ci < 2; ++ci) {
             const int pos = c0 + wc * 32 + ci * 16 + (lane & 15);
@@ -578,12 +579,8 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
 #pragma unroll
             for (int ri = 0; ri < RT; ++ri) {
                 const int m = m0 + wm * (BM / 2) + ri * 16 + 4 * (lane >> 4);
-                if (m < N) {
-                    const f4_t &a4 = acc[u][ri][ci];
-                    const d4_t v{static_cast<double>(a4[0]), static_cast<double>(a4[1]),
-                                 static_cast<double>(a4[2]), static_cast<double>(a4[3])};
-                    *reinterpret_cast<GLOBAL_AS d4_t *>(Cout + static_cast<int64_t>(pos) * N + m) = v;
-                }
+                if (m < N)
+                    *reinterpret_cast<GLOBAL_AS f4_t *>(Cout + static_cast<int64_t>(pos) * N + m) = acc[u][ri][ci];
             }
         }
     }

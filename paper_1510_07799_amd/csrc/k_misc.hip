@@ -216,8 +216,9 @@ int combine_tiles_of(int N) {
     return nj * nj * nk;
 }
 
-__device__ void combine_body(int N, int KS, int64_t n3, const double *__restrict__ Cpp,
-                             const double *__restrict__ Cc, const double *__restrict__ Cd,
+template <typename PT>
+__device__ void combine_body(int N, int KS, int64_t n3, const PT *__restrict__ Cpp,
+                             const PT *__restrict__ Cc, const PT *__restrict__ Cd,
                              const int32_t *__restrict__ ppos, const int32_t *__restrict__ phpos,
                              double scale, double *__restrict__ F, int tile, double *sF) {
     const int nj = (N + CB_J - 1) / CB_J, nk = (N + CB_K - 1) / CB_K;
@@ -265,9 +266,44 @@ __device__ void combine_body(int N, int KS, int64_t n3, const double *__restrict
     }
 }
 
-__global__ __launch_bounds__(256) void combine_kernel(const double *__restrict__ Cpp,
-                                                      const double *__restrict__ Cc,
-                                                      const double *__restrict__ Cd, int N, int parts,
+// Sum of the K-part partials, four consecutive elements per thread (streams
+// of contiguous loads, one per part).
+template <typename PT>
+__device__ __forceinline__ void sum_parts_body(const double *__restrict__ C, int KS, int64_t n3,
+                                               double *__restrict__ out, int64_t q) {
+    const int64_t i0 = 4 * q;
+    if (i0 >= 3 * n3) return;
+    const int t = static_cast<int>(i0 / n3);
+    const int64_t i = i0 - t * n3;
+    const PT *Ct = reinterpret_cast<const PT *>(C + t * static_cast<int64_t>(KS) * n3);
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i + 4 <= n3) {   // n3 = N^3 with N % 4 == 0: always taken
+        for (int s = 0; s < KS; ++s) {
+            const PT *src = Ct + s * n3 + i;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] += static_cast<double>(src[e]);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) out[t * n3 + i + e] = v[e];
+    } else {
+        for (int e = 0; e < 4 && i + e < n3; ++e) {
+            double w = 0.0;
+            for (int s = 0; s < KS; ++s) w += static_cast<double>(Ct[s * n3 + i + e]);
+            out[t * n3 + i + e] = w;
+        }
+    }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void sum_parts_kernel(const double *__restrict__ C, int KS, int64_t n3,
+                                                        double *__restrict__ out) {
+    sum_parts_body<PT>(C, KS, n3, out, static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void combine_kernel(const PT *__restrict__ Cpp,
+                                                      const PT *__restrict__ Cc,
+                                                      const PT *__restrict__ Cd, int N, int parts,
                                                       const int32_t *__restrict__ ppos,
                                                       const int32_t *__restrict__ phpos,
                                                       const double *__restrict__ Tdev, int scale_by_T,
@@ -541,8 +577,20 @@ __global__ __launch_bounds__(256) void combine_b_kernel(const FlowArgs *__restri
     if (flow_stopped(f)) return;
     const int64_t n = f.n3;
     const int KS = f.KS;
-    combine_body(f.N, KS, n, f.C, f.C + KS * n, f.C + 2 * KS * n, f.ppos, f.phpos, f.Tdev[0], f.k[stage],
-                 it.y, sF);
+    (void)KS;
+    combine_body(f.N, 1, n, static_cast<const double *>(f.Csum), f.Csum + n, f.Csum + 2 * n, f.ppos, f.phpos,
+                 f.Tdev[0], f.k[stage], it.y, sF);
+}
+
+// batched sum of the K parts: item = (flow, block of kSumPartsPerBlock elements)
+__global__ __launch_bounds__(256) void sum_parts_b_kernel(const FlowArgs *__restrict__ fa,
+                                                          const int2 *__restrict__ items) {
+    const int2 it = items[blockIdx.x];
+    const FlowArgs &f = fa[it.x];
+    if (flow_stopped(f)) return;
+    const int64_t q = static_cast<int64_t>(it.y) * (kSumPartsPerBlock / 4) + threadIdx.x;
+    if (f.f32parts) sum_parts_body<float>(f.C, f.KS, f.n3, f.Csum, q);
+    else sum_parts_body<double>(f.C, f.KS, f.n3, f.Csum, q);
 }
 
 struct Coef7 { double c[7]; };
@@ -666,11 +714,17 @@ void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipS
 
 int combine_tiles(int N) { return combine_tiles_of(N); }
 
-void launch_combine(const double *Cpp, const double *Cc, const double *Cd, int N, int parts,
+void launch_combine(const void *Cpp, const void *Cc, const void *Cd, bool f32parts, int N, int parts,
                     const int32_t *ppos, const int32_t *phpos,
                     const double *Tdev, int scale_by_T, double *F, hipStream_t s) {
-    hipLaunchKernelGGL(combine_kernel, dim3(combine_tiles_of(N)), dim3(256), 0, s, Cpp, Cc, Cd, N, parts,
-                       ppos, phpos, Tdev, scale_by_T, F);
+    if (f32parts)
+        hipLaunchKernelGGL(combine_kernel<float>, dim3(combine_tiles_of(N)), dim3(256), 0, s,
+                           static_cast<const float *>(Cpp), static_cast<const float *>(Cc),
+                           static_cast<const float *>(Cd), N, parts, ppos, phpos, Tdev, scale_by_T, F);
+    else
+        hipLaunchKernelGGL(combine_kernel<double>, dim3(combine_tiles_of(N)), dim3(256), 0, s,
+                           static_cast<const double *>(Cpp), static_cast<const double *>(Cc),
+                           static_cast<const double *>(Cd), N, parts, ppos, phpos, Tdev, scale_by_T, F);
 }
 
 void launch_rk_stage(const RkStageArgs &a, hipStream_t s) {
@@ -728,6 +782,18 @@ void launch_layout_b(const FlowArgs *fa, const int2 *items, int nitems, int src,
                      hipStream_t s) {
     hipLaunchKernelGGL(layout_b_kernel, dim3(nitems), dim3(256), 0, s, fa, items, src, split ? 1 : 0);
 }
+void launch_sum_parts(const double *C, bool f32parts, int KS, int64_t n3, double *out, hipStream_t s) {
+    const int64_t quads = (3 * n3 + 3) / 4;
+    if (f32parts)
+        hipLaunchKernelGGL(sum_parts_kernel<float>, dim3(blocks_for(quads, 256)), dim3(256), 0, s, C, KS, n3, out);
+    else
+        hipLaunchKernelGGL(sum_parts_kernel<double>, dim3(blocks_for(quads, 256)), dim3(256), 0, s, C, KS, n3, out);
+}
+
+void launch_sum_parts_b(const FlowArgs *fa, const int2 *items, int nitems, hipStream_t s) {
+    hipLaunchKernelGGL(sum_parts_b_kernel, dim3(nitems), dim3(kSumPartsPerBlock / 4), 0, s, fa, items);
+}
+
 void launch_combine_b(const FlowArgs *fa, const int2 *items, int nitems, int stage, hipStream_t s) {
     hipLaunchKernelGGL(combine_b_kernel, dim3(nitems), dim3(256), 0, s, fa, items, stage);
 }
