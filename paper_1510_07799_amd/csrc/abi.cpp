@@ -452,6 +452,23 @@ void set_operands(frg::FusedContractArgs &a, bool split, const double *V, const 
     }
 }
 
+// bubble-row operands of the contraction: pointers, sizes and whether the
+// split path may take its buffer-load fast path
+void set_bubbles(frg_ctx ctx, bool split, bool sym, void *bpp, void *bph, frg::FusedContractArgs &a) {
+    const auto &g = ctx->g;
+    const int64_t NN = static_cast<int64_t>(g.N) * g.N;
+    const int64_t elem = split ? 4 : 8;
+    const int64_t bpp_bytes = (sym ? ctx->n_rep_pp : g.Tpp) * NN * elem;
+    const int64_t bph_bytes = (sym ? ctx->n_rep_ph : g.Tph) * NN * elem;
+    a.B[frg::TERM_PP] = bpp;
+    a.B[frg::TERM_PHC] = a.B[frg::TERM_PHD] = bph;
+    a.Bbytes[frg::TERM_PP] = bpp_bytes;
+    a.Bbytes[frg::TERM_PHC] = a.Bbytes[frg::TERM_PHD] = bph_bytes;
+    const int64_t lim = int64_t(1) << 31;
+    a.fast = split && g.N % 32 == 0 && bpp_bytes < lim && bph_bytes < lim && 4 * ctx->n3 < lim &&
+             std::getenv("FRG_NO_FAST") == nullptr;
+}
+
 // tile position of every column (cls 0: pp, 1: ph) in the current column order
 const int32_t *col_pos(frg_ctx ctx, int cls) { return ctx->kskip_on ? ctx->d_cpos[cls] : ctx->d_cperm_id; }
 
@@ -522,8 +539,7 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     a.N = N;
     a.KS = KS;
     a.n3 = n3;
-    a.B[frg::TERM_PP] = bpp;
-    a.B[frg::TERM_PHC] = a.B[frg::TERM_PHD] = bph;
+    set_bubbles(ctx, split, sym, bpp, bph, a);
     a.colrow[frg::TERM_PP] = sym ? ctx->d_colsym_pp : ctx->d_colrow_pp;
     a.colrow[frg::TERM_PHC] = a.colrow[frg::TERM_PHD] = sym ? ctx->d_colsym_ph : ctx->d_colrow_ph;
     set_tiles(ctx, a);
@@ -1109,8 +1125,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
             const int bm = frg::contract_block_rows(g.N);
             a.mtiles = (g.N + bm - 1) / bm;
             a.ctiles = static_cast<int>((NN + 63) / 64);
-            a.B[frg::TERM_PP] = bpp;
-            a.B[frg::TERM_PHC] = a.B[frg::TERM_PHD] = bph;
+            set_bubbles(c, split, sym, bpp, bph, a);
             a.colrow[frg::TERM_PP] = sym ? c->d_colsym_pp : c->d_colrow_pp;
             a.colrow[frg::TERM_PHC] = a.colrow[frg::TERM_PHD] = sym ? c->d_colsym_ph : c->d_colrow_ph;
             set_tiles(c, a);

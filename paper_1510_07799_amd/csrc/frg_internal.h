@@ -73,8 +73,10 @@ enum Term { TERM_PP = 0, TERM_PHC = 1, TERM_PHD = 2,
 // `part`, laid out [tile position p][m] (p holds column cperm[t][p])
 struct FusedContractArgs {
     int N, KS, mtiles, ctiles;
+    int fast;   // split path: buffer-load fast path (N % 32 == 0, bubble rows < 2 GiB)
     int64_t n3;
     const void *B[3];             // bubble rows per term (pp: Bpp, phc/phd: Bph)
+    int64_t Bbytes[3];            // their sizes in bytes
     // column c -> (stored row << 3) | o: the column's bubble row is the stored
     // row acted on by C4v element o, B_col(a', b') = B_stored(o^-1 a', o^-1 b')
     const int32_t *colrow[3];

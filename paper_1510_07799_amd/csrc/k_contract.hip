@@ -359,7 +359,7 @@ __device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 
 // products in one block; all three read the same ph bubble row of a column,
 // so its window (and the index work around it) is loaded once for three
 // Z tiles.  Product p feeds accumulator 0 (phc) for p = 0, else 1 (phd).
-template <int KIND, int BM>
+template <int KIND, int BM, bool FAST>
 __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Work &w, uint16_t *smem) {
     constexpr bool PH = KIND == TERM_PH;
     constexpr int TT = PH ? TERM_PHC : TERM_PP;   // term whose bubble rows and tile lists are read
@@ -409,8 +409,92 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     u32x4_t ra[NP][2][ACH];
     float rb[ZK], rg[NP][ZK];
 
+    // Buffer resources for the FAST path: 32-bit offsets, and an offset past
+    // the end (kOOB) reads zeros, so padding entries and invalid columns need
+    // no branches.  FAST needs N % 32 == 0 (a window of 8 k then stays in one
+    // row of patches and contiguous after every C4v patch map) and bubble
+    // rows below 2 GiB; the host checks both.
+    constexpr uint32_t kOOB = 0x80000000u;
+    constexpr int kFlags = 0x00020000;   // raw buffer, 32-bit data format (gfx9)
+    __amdgpu_buffer_rsrc_t rA[NP], rB, rG0, rGd, rG1;
+    if constexpr (FAST) {
+        const uint16_t *Araw[3] = {PH ? P.Ahl[TERM_PHC][0] : P.Ahl[TERM_PP][0], P.Ahl[TERM_PHD][0],
+                                   P.Ahl[TERM_PHD][1]};
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+            rA[p] = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(Araw[p]), 0, static_cast<int>(4 * n3),
+                                                      kFlags);
+        rB = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(P.B[TT]), 0, static_cast<int>(P.Bbytes[TT]),
+                                               kFlags);
+        rG0 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(P.G32[TT][0]), 0, static_cast<int>(4 * n3),
+                                                kFlags);
+        if constexpr (PH) {
+            rGd = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(P.G32[TERM_PHD][0]), 0,
+                                                    static_cast<int>(4 * n3), kFlags);
+            rG1 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(P.G32[TERM_PHD][1]), 0,
+                                                    static_cast<int>(4 * n3), kFlags);
+        }
+    }
+    // byte offsets of the column's bubble row and gather rows
+    const uint32_t brow_off = static_cast<uint32_t>(rm.row) * static_cast<uint32_t>(K) * 4u;
+    const uint32_t g0_off = static_cast<uint32_t>(c) * static_cast<uint32_t>(N) * 4u;
+    const uint32_t g1_off = static_cast<uint32_t>(c / N) * static_cast<uint32_t>(K) * 4u;
+
+    auto load_fast = [&](const int (&ea)[ACH], int e) {
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+#pragma unroll
+            for (int hl = 0; hl < 2; ++hl)
+#pragma unroll
+                for (int i = 0; i < ACH; ++i) {
+                    const int ch = tid + i * kThreads;
+                    if (ch >= NCH) continue;   // uniform per wave
+                    const int m = m0 + ch % BM;
+                    const uint32_t off = (ea[i] >= 0 && m < N)
+                        ? ((static_cast<uint32_t>(ent_chunk(ea[i])) * N + m) * kContractChunk +
+                           static_cast<uint32_t>(hl * n3)) * 2u
+                        : kOOB;
+                    ra[p][hl][i] = __builtin_bit_cast(u32x4_t, __builtin_amdgcn_raw_buffer_load_b128(rA[p], off, 0, 0));
+                }
+        const bool zok = cvalid && e >= 0;
+        const int a = ent_a(e), b = ent_b(e);
+        // bubble-row window: 8 contiguous floats at (map(a), lo) of the stored row
+        const int am = rm.map(a, N), bt = rm.map(b, N);
+        const int lo = rm.refl ? bt - (ZK - 1) : bt;
+        const uint32_t boff = zok ? brow_off + static_cast<uint32_t>(am * N + lo) * 4u : kOOB;
+        const f4_t w0 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rB, boff, 0, 0));
+        const f4_t w1 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rB, boff + 16u, 0, 0));
+        const bool refl = rm.refl;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            rb[q] = refl ? w1[3 - q] : w0[q];
+            rb[q + 4] = refl ? w0[3 - q] : w1[q];
+        }
+        if constexpr (!PH) {
+            const uint32_t go = zok ? g0_off + static_cast<uint32_t>(a) * 4u : kOOB;
+            const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rG0, go, 0, 0));
+#pragma unroll
+            for (int q = 0; q < ZK; ++q) rg[0][q] = v;
+        } else {
+            const uint32_t go = zok ? g0_off + static_cast<uint32_t>(b) * 4u : kOOB;
+            const uint32_t g1o = zok ? g1_off + static_cast<uint32_t>(ent_chunk(e) * kContractChunk) * 4u : kOOB;
+            const f4_t u0 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rG0, go, 0, 0));
+            const f4_t u1 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rG0, go + 16u, 0, 0));
+            const f4_t v0 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rGd, go, 0, 0));
+            const f4_t v1 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rGd, go + 16u, 0, 0));
+            const f4_t x0 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rG1, g1o, 0, 0));
+            const f4_t x1 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rG1, g1o + 16u, 0, 0));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                rg[0][q] = u0[q]; rg[0][q + 4] = u1[q];
+                rg[1][q] = v0[q]; rg[1][q + 4] = v1[q];
+                rg[2][q] = x0[q]; rg[2][q + 4] = x1[q];
+            }
+        }
+    };
+
     // ea[i]: list entry of the slot of A piece i; e: of the Z window
-    auto load = [&](const int (&ea)[ACH], int e) {
+    auto load_general = [&](const int (&ea)[ACH], int e) {
 #pragma unroll
         for (int p = 0; p < NP; ++p)
 #pragma unroll
@@ -481,6 +565,10 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
                 for (int q = 0; q < ZK; ++q) rg[2][q] = kb + q < K ? g1[kb + q] : 0.f;
             }
         }
+    };
+    auto load = [&](const int (&ea)[ACH], int e) {
+        if constexpr (FAST) load_fast(ea, e);
+        else load_general(ea, e);
     };
     auto store = [&]() {
 #pragma unroll
@@ -590,8 +678,13 @@ template <int BM, bool SPLIT>
 __device__ __forceinline__ void run_work(const FusedContractArgs &P, const Work &w, double *smem_d) {
     if (SPLIT) {
         uint16_t *smem = reinterpret_cast<uint16_t *>(smem_d);
-        if (w.term == TERM_PH) body_split<TERM_PH, BM>(P, w, smem);
-        else body_split<TERM_PP, BM>(P, w, smem);
+        if (P.fast) {
+            if (w.term == TERM_PH) body_split<TERM_PH, BM, true>(P, w, smem);
+            else body_split<TERM_PP, BM, true>(P, w, smem);
+        } else {
+            if (w.term == TERM_PH) body_split<TERM_PH, BM, false>(P, w, smem);
+            else body_split<TERM_PP, BM, false>(P, w, smem);
+        }
     } else {
         if (w.term == TERM_PHD) body_f64<TERM_PHD, BM>(P, w, smem_d);
         else if (w.term == TERM_PHC) body_f64<TERM_PHC, BM>(P, w, smem_d);

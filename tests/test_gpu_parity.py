@@ -26,6 +26,9 @@ from paper_1510_07799_amd import frg  # noqa: E402  (loads libfrg.so; fails loud
 RAGGED = dict(t=1.0, tp=-0.12, mu=-0.35, U=2.0, N=12, n_rad=5, n_ang=3)   # N%8 != 0, n_f = 15
 TINY = dict(t=1.0, tp=-0.15, mu=-0.3, U=2.0, N=4, n_rad=3, n_ang=2)
 SMALL_ODD = dict(t=1.0, tp=-0.2, mu=-0.6, U=2.5, N=24, n_rad=9, n_ang=10)  # n_f = 90 (ragged tiles)
+# N % 32 == 0: the split contraction's buffer-load path
+FAST32 = dict(t=1.0, tp=-0.25, mu=-0.9, U=2.5, N=32, n_rad=6, n_ang=4)
+FAST64 = dict(t=1.0, tp=-0.3, mu=-1.1, U=3.0, N=64, n_rad=4, n_ang=3)
 
 
 def nrel(x, ref):
@@ -105,7 +108,8 @@ def _vertices(N, U):
             "raw": I.random_vertex(N, U, seed=22, symmetrise=False)}
 
 
-@pytest.mark.parametrize("cfg", ["C1", RAGGED, TINY, SMALL_ODD, "C2"], ids=["C1", "ragged", "tiny", "odd", "C2"])
+@pytest.mark.parametrize("cfg", ["C1", RAGGED, TINY, SMALL_ODD, "C2", FAST32, FAST64],
+                         ids=["C1", "ragged", "tiny", "odd", "C2", "n32", "n64"])
 def test_rhs_fp64(cfg):
     om, g = pair(cfg)
     N, U = om.N, om.U
@@ -118,7 +122,8 @@ def test_rhs_fp64(cfg):
             assert err <= 1e-10
 
 
-@pytest.mark.parametrize("cfg", ["C1", RAGGED, SMALL_ODD, "C2"], ids=["C1", "ragged", "odd", "C2"])
+@pytest.mark.parametrize("cfg", ["C1", RAGGED, SMALL_ODD, "C2", FAST32, FAST64],
+                         ids=["C1", "ragged", "odd", "C2", "n32", "n64"])
 def test_rhs_split(cfg):
     om, g = pair(cfg)
     N, U = om.N, om.U
@@ -235,7 +240,7 @@ def test_flow_step_api_and_tmin_stop():
     assert nrel(V.cpu().numpy(), Vo) <= 1e-9
 
 
-@pytest.mark.parametrize("cfg", ["C1", SMALL_ODD, "C2"], ids=["C1", "odd", "C2"])
+@pytest.mark.parametrize("cfg", ["C1", SMALL_ODD, "C2", FAST64], ids=["C1", "odd", "C2", "n64"])
 def test_c4v_row_reduction_matches_full_rows(cfg):
     """Bubble rows computed for one transfer per C4v orbit and read through the
     patch permutation give the same rhs as computing every row."""
@@ -265,7 +270,7 @@ def test_c4v_reduction_unavailable_for_n_not_multiple_of_8():
     assert e.value.status == frg.ENOTSUP
 
 
-@pytest.mark.parametrize("cfg", ["C1", RAGGED, SMALL_ODD, "C2"], ids=["C1", "ragged", "odd", "C2"])
+@pytest.mark.parametrize("cfg", ["C1", RAGGED, SMALL_ODD, "C2", FAST64], ids=["C1", "ragged", "odd", "C2", "n64"])
 def test_zero_block_skipping_matches_dense(cfg):
     """Visiting only the k chunks where some bubble row of a column tile has a
     fine point gives the dense contraction's rhs (skipped terms are exact
@@ -289,6 +294,21 @@ def test_zero_block_skipping_matches_dense(cfg):
         assert nrel(Fs, ref) <= tol and nrel(Fd, ref) <= tol
         if prec == frg.PREC_FP64:
             assert nrel(Fs, Fd) <= 1e-12
+
+
+@pytest.mark.parametrize("cfg", [FAST32, FAST64, "C3"], ids=["n32", "n64", "C3"])
+def test_split_buffer_path_matches_general_path(cfg, monkeypatch):
+    """For N % 32 == 0 the split contraction reads its operands with buffer
+    loads (out-of-range offsets read zero); FRG_NO_FAST forces the general
+    loads.  Both paths do the same arithmetic in the same order."""
+    om, g = pair(cfg)
+    V = dev(I.random_vertex(om.N, om.U, seed=47, symmetrise=False))
+    Ff = g.rhs(0.03, V, frg.PREC_SPLIT_BF16).cpu().numpy()
+    monkeypatch.setenv("FRG_NO_FAST", "1")
+    Fg = g.rhs(0.03, V, frg.PREC_SPLIT_BF16).cpu().numpy()
+    monkeypatch.delenv("FRG_NO_FAST")
+    print(f"[fast/general] N={om.N}: {nrel(Ff, Fg):.2e}", flush=True)
+    assert np.array_equal(Ff, Fg)
 
 
 BATCH = [dict(t=1.0, tp=-0.1, mu=-0.3, U=2.0, N=16, n_rad=4, n_ang=4),
