@@ -57,6 +57,44 @@ def timed_flow_steps(frg, torch, ctx, prec, V0, steps, warmup):
     return t1 - t0, prof, st
 
 
+def roofline(head, results, algo_flops, dense_flops, exec_share, evals_per_rhs):
+    prof = head["prof"]
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms, cnt = prof[dom]
+    avg_s = ms / max(cnt, 1) * 1e-3
+    leg_name = "split" if "split" in results else [k for k in results][0]
+    if dom.startswith("contract"):
+        peak = PEAK["bf16_TFLOPs"] if leg_name == "split" else PEAK["fp64_TFLOPs"]
+        achieved = algo_flops[dom] / avg_s / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 4), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 6)}
+        passes = 3.0 if leg_name == "split" else 1.0
+        roof["executed_frac"] = round(passes * dense_flops * exec_share / avg_s / 1e12 / peak, 6)
+        roof["kskip_executed_share"] = round(exec_share, 4)
+    elif dom == "bubbles":
+        # plain ALU bound: FP32/FP64 vector issue; algorithmic unit = one integrand evaluation
+        peak = PEAK["fp32_TFLOPs"] if leg_name == "split" else PEAK["fp64_TFLOPs"]
+        flops_per_eval = 40.0
+        achieved = evals_per_rhs * flops_per_eval / avg_s / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 4), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 6)}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK["hbm_GBs"],
+                "unit": "GB/s", "frac": None}
+    roof["avg_launch_ms"] = round(avg_s * 1e3, 4)
+    traffic = None
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        per_leg = tr.get("kernels", {}).get(leg_name, {})
+        if tr.get("source_hash") == kernel_source_hash() and dom in per_leg:
+            traffic = per_leg[dom]["bytes_per_launch"]
+    except (OSError, ValueError):
+        traffic = None
+    roof["traffic"] = traffic
+    return roof
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,7 +147,7 @@ def main():
     algo_flops = {"contract": 2.0 * N * colsum_pp + 2.0 * N * colsum_ph + 4.0 * N * colsum_ph}
     dense_flops = 8.0 * N ** 5   # what the dense formulation executes (x3 passes in split mode)
     _, exec_share = ctx.kskip()   # share of the dense k chunks the contraction visits
-    evals_per_rhs = (ctx.Tpp + ctx.Tph) * N * nf
+    evals_per_rhs = ctx.symmetry()[1] * N * nf   # bubble rows one rhs evaluates (C4v-reduced)
 
     legs = [x.strip() for x in args.legs.split(",") if x.strip()]
     results = {}
@@ -146,8 +184,8 @@ def main():
         b.close()
         del Vs
 
-    head = results.get("split") or results[[k for k in results][0]]
-    dt = head["seconds"]
+    head = results.get("split") or (results[next(iter(results))] if results else None)
+    dt = head["seconds"] if head else batch["seconds"]
     value = RHS_PER_STEP * args.steps / dt
     if batch is not None:
         value = batch["rhs"] / batch["seconds"]
@@ -186,42 +224,12 @@ def main():
         out["config"]["workload"] += (f"; value = batched split-BF16 rhs/s of {batch['flows']} flows "
                                       "at N=96 with (mu, t', U) drawn as in the batched configuration")
 
-    # roofline of the dominant kernel of the headline leg
-    prof = head["prof"]
-    dom = max(prof, key=lambda k: prof[k][0])
-    ms, cnt = prof[dom]
-    avg_s = ms / max(cnt, 1) * 1e-3
-    leg_name = "split" if "split" in results else [k for k in results][0]
-    if dom.startswith("contract"):
-        peak = PEAK["bf16_TFLOPs"] if leg_name == "split" else PEAK["fp64_TFLOPs"]
-        achieved = algo_flops[dom] / avg_s / 1e12
-        roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 4), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 6)}
-        passes = 3.0 if leg_name == "split" else 1.0
-        roof["executed_frac"] = round(passes * dense_flops * exec_share / avg_s / 1e12 / peak, 6)
-        roof["kskip_executed_share"] = round(exec_share, 4)
-    elif dom == "bubbles":
-        # plain ALU bound: FP32/FP64 vector issue; algorithmic unit = one integrand evaluation
-        peak = PEAK["fp32_TFLOPs"] if leg_name == "split" else PEAK["fp64_TFLOPs"]
-        flops_per_eval = 40.0
-        achieved = evals_per_rhs * flops_per_eval / avg_s / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 4), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 6)}
+    # roofline of the dominant kernel of the headline leg (a single-flow leg)
+    if head is None:
+        out["roofline"] = {"kernel": None, "bound": None, "achieved": None, "peak": None, "unit": None,
+                           "frac": None, "traffic": None, "note": "needs a single-flow leg"}
     else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK["hbm_GBs"],
-                "unit": "GB/s", "frac": None}
-    roof["avg_launch_ms"] = round(avg_s * 1e3, 4)
-    traffic = None
-    try:
-        with open(TRAFFIC_FILE) as fh:
-            tr = json.load(fh)
-        per_leg = tr.get("kernels", {}).get(leg_name, {})
-        if tr.get("source_hash") == kernel_source_hash() and dom in per_leg:
-            traffic = per_leg[dom]["bytes_per_launch"]
-    except (OSError, ValueError):
-        traffic = None
-    roof["traffic"] = traffic
-    out["roofline"] = roof
+        out["roofline"] = roofline(head, results, algo_flops, dense_flops, exec_share, evals_per_rhs)
 
     if not args.no_cpu_baseline:
         import oracle as O

@@ -628,7 +628,13 @@ const char *frg_status_str(frg_status st) {
 
 const char *frg_last_error(void) { return g_err.c_str(); }
 
-frg_status frg_create(const frg_params *p, frg_ctx *out) {
+static frg_status create_impl(const frg_params *p, int ks_hint, frg_ctx *out);
+
+frg_status frg_create(const frg_params *p, frg_ctx *out) { return create_impl(p, 0, out); }
+
+// ks_hint > 0: K parts of the contraction for this context (a batch of many
+// flows needs fewer parts per flow to fill the chip); FRG_KSPLIT overrides
+static frg_status create_impl(const frg_params *p, int ks_hint, frg_ctx *out) {
     if (!out) return fail(FRG_EINVAL, "null output handle");
     *out = nullptr;
     TRY(check_params(p));
@@ -643,6 +649,7 @@ frg_status frg_create(const frg_params *p, frg_ctx *out) {
 
     frg_ctx ctx = new frg_ctx_s();
     ctx->device = dev;
+    ctx->ks_override = ks_hint;
     if (const char *e = std::getenv("FRG_KSPLIT")) ctx->ks_override = std::atoi(e);
     frg::build_geometry(*p, ctx->g);
     const auto &g = ctx->g;
@@ -1285,7 +1292,13 @@ frg_status frg_batch_create(const frg_params *params, int32_t n_flows, frg_batch
     b->nf = params[0].n_rad * params[0].n_ang;
     for (int f = 0; f < n_flows; ++f) {
         frg_ctx c = nullptr;
-        frg_status st = frg_create(&params[f], &c);
+        // K parts: enough blocks over the whole batch (measured best at 16 flows of
+        // N = 96: 2 parts), between 2 and 8
+        const int N = params[f].N, bm = frg::contract_block_rows(N);
+        const int64_t tiles = 3LL * ((N + bm - 1) / bm) * ((static_cast<int64_t>(N) * N + 63) / 64);
+        const int ks = static_cast<int>(std::min<int64_t>(8, std::max<int64_t>(2, (13824 + tiles * n_flows - 1) /
+                                                                                     (tiles * n_flows))));
+        frg_status st = create_impl(&params[f], ks, &c);
         if (st) { std::string m = g_err; frg_batch_destroy(b); g_err = m; return st; }
         b->ctx.push_back(c);
         b->maxN = std::max(b->maxN, params[f].N);
