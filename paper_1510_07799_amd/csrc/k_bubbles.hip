@@ -16,7 +16,7 @@
 //
 // FP64 path: everything in double.  Split path: eps in double (its absolute
 // error is divided by 2T), the integrand in FP32 with hardware exp/rcp, runs
-// summed with Kahan compensation, bins accumulated in double, output float.
+// and bins accumulated in double, output float.
 #include <cmath>
 #include <type_traits>
 
@@ -173,7 +173,6 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
         wave_sync();
         int bcur = -1;
         double acc64 = 0.0;
-        float acc32 = 0.0f, comp32 = 0.0f;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             if (lane * P + j < nf) {
@@ -190,38 +189,24 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
                 double b2 = xi2 * inv2T;
                 if (pp) b2 = -b2;
                 const int bin = bn[j];
-                if (F32) {
-                    const float v = static_cast<float>(pval(6, j)) *
-                                    div_h32(static_cast<float>(pval(4, j)), static_cast<float>(pval(5, j)),
-                                            static_cast<float>(b2));
-                    if (bin != bcur) {
-                        if (bcur >= 0)
-                            atomicAdd(&bins[bcur], static_cast<double>(acc32) - static_cast<double>(comp32));
-                        bcur = bin;
-                        acc32 = v;
-                        comp32 = 0.0f;
-                    } else {   // Kahan step
-                        const float y = v - comp32;
-                        const float t = acc32 + y;
-                        comp32 = (t - acc32) - y;
-                        acc32 = t;
-                    }
+                double v;
+                if (F32)
+                    v = static_cast<double>(static_cast<float>(pval(6, j)) *
+                                            div_h32(static_cast<float>(pval(4, j)), static_cast<float>(pval(5, j)),
+                                                    static_cast<float>(b2)));
+                else
+                    v = pval(6, j) * div_h64(pval(4, j), pval(5, j), b2);
+                // runs of equal bin summed in FP64 in registers, one LDS add per run
+                if (bin != bcur) {
+                    if (bcur >= 0) atomicAdd(&bins[bcur], acc64);
+                    bcur = bin;
+                    acc64 = v;
                 } else {
-                    const double v = pval(6, j) * div_h64(pval(4, j), pval(5, j), b2);
-                    if (bin != bcur) {
-                        if (bcur >= 0) atomicAdd(&bins[bcur], acc64);
-                        bcur = bin;
-                        acc64 = v;
-                    } else {
-                        acc64 += v;
-                    }
+                    acc64 += v;
                 }
             }
         }
-        if (bcur >= 0) {
-            if (F32) atomicAdd(&bins[bcur], static_cast<double>(acc32) - static_cast<double>(comp32));
-            else atomicAdd(&bins[bcur], acc64);
-        }
+        if (bcur >= 0) atomicAdd(&bins[bcur], acc64);
         wave_sync();
         const size_t NN = static_cast<size_t>(N) * N;
         const bool pp_out = slot_out < A.npp_out;
