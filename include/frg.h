@@ -244,6 +244,25 @@ frg_status frg_symmetry(frg_ctx ctx, int32_t *active, int32_t *rows_computed);
 frg_status frg_set_kskip(frg_ctx ctx, int32_t enable);
 frg_status frg_kskip(frg_ctx ctx, int32_t *active, double *executed_frac);
 
+/* Symmetric-vertex mode (Sec. 4: the independent couplings are counted after
+ * using the lattice symmetries).  For a vertex that is invariant under the
+ * C4v point group, V(g k1, g k2, g k3) = V(k1, k2, k3), the rhs is invariant
+ * too, and with the exactly covariant grid (N % 8 == 0) the contraction needs
+ * one output column per C4v orbit of column pairs (about N^2/8 of them,
+ * i.e. about N^3/8 independent entries); the combine writes every entry of F
+ * from them.  frg_set_vsym(ctx, 1) asserts that every V passed to frg_rhs
+ * is invariant (not checked there); frg_flow_init checks V0 (relative
+ * deviation at most 1e-12, else FRG_EINVAL), and a flow from an invariant V0
+ * stays invariant.  ENOTSUP when N % 8 != 0 or the covariance check at
+ * creation failed.  frg_vsym reports the mode and the columns computed per
+ * channel.  frg_check_vsym computes max_{g,j} |V(g j) - V(j)| / max |V| for a
+ * device V (synchronises the stream).  frg_batch_set_vsym sets the mode for
+ * every flow of a batch; the batch must be flow_init'ed again afterwards. */
+frg_status frg_set_vsym(frg_ctx ctx, int32_t enable);
+frg_status frg_vsym(frg_ctx ctx, int32_t *active, int32_t *columns);
+frg_status frg_check_vsym(frg_ctx ctx, const double *d_V, double *rel_dev, void *stream);
+frg_status frg_batch_set_vsym(frg_batch b, int32_t enable);
+
 /* Kernel timing with HIP events recorded on the launch stream around every
  * kernel of the rhs and flow pipelines (for measurement; off by default).
  * frg_profile_begin clears and enables the record; frg_profile_end

@@ -15,6 +15,16 @@
 #include "frg_internal.h"
 
 
+// Column tiles of one class: positions (tile order) -> natural columns, the
+// combine's map of every natural column to (position << 3) | C4v element, and
+// per tile and K part the list of active k chunks.
+struct TileSet {
+    int ncol = 0;
+    int kparts = 1;   // K parts the chunk lists are cut into
+    int32_t *d_cperm = nullptr, *d_cmap = nullptr, *d_koff = nullptr, *d_klist = nullptr;
+    int64_t chunks = 0;
+};
+
 struct frg_ctx_s {
     frg::Geometry g;
     int device = 0;
@@ -30,15 +40,18 @@ struct frg_ctx_s {
     int n_rep_pp = 0, n_rep_ph = 0;
     int32_t *d_rowlist = nullptr;                              // representative rows (pp, then ph)
     int32_t *d_colsym_pp = nullptr, *d_colsym_ph = nullptr;   // (compact rep << 3) | element
-    // column tiles of the contraction ([0]: pp columns, [1]: ph columns):
-    // Hilbert-ordered columns and the active 8-wide k chunks of each tile;
-    // the dense alternative (natural order, every chunk) is made on demand
+    // column tiles of the contraction, per class ([0]: pp columns, [1]: ph):
+    // all columns in Hilbert order with their active 8-wide k chunks (ts_full);
+    // one column per C4v orbit of column pairs, for a C4v-invariant vertex
+    // (ts_vsym); all columns in natural order with every chunk (ts_dense, made
+    // on demand)
     bool kskip_on = true;
-    int32_t *d_cperm[2] = {nullptr, nullptr}, *d_koff[2] = {nullptr, nullptr},
-            *d_klist[2] = {nullptr, nullptr}, *d_cpos[2] = {nullptr, nullptr};
-    int32_t *d_cperm_id = nullptr, *d_koff_dense = nullptr, *d_klist_dense = nullptr;
-    int64_t kchunks_active[2] = {0, 0};
-    int kparts = 0;        // K parts the list offsets are cut for (fixed at create)
+    bool vsym_on = false;
+    TileSet ts_full[2], ts_vsym[2], ts_dense[2];
+    int16_t *d_perm8 = nullptr;   // [8][N] C4v patch maps (identity rows when N % 8 != 0)
+    // K parts of the contraction: enough blocks (ks_target per flow) over the
+    // tiles of the column set in use, at least ks_lo
+    int ks_target = 3456, ks_lo = 1;
     bool kfixed = false;   // parts by fixed chunk ranges (FRG_KPARTS=fixed) or equal shares
     // rhs workspace
     double *d_pa64 = nullptr, *d_T = nullptr;
@@ -286,16 +299,17 @@ frg_status build_orbits(frg_ctx ctx) {
     return FRG_OK;
 }
 
-// K parts of the fused contraction: enough blocks for several rounds over the
-// 256 compute units (measured best at N = 96: 8 parts); FRG_KSPLIT overrides
-int ksplit(frg_ctx ctx) {
-    if (ctx->kparts > 0) return ctx->kparts;
+// K parts of the fused contraction over ncol columns: enough blocks for several
+// rounds over the 256 compute units (measured best at N = 96: 8 parts for all
+// columns, 16 for one column per C4v orbit; 2 per flow in a batch of 16);
+// FRG_KSPLIT overrides
+int ksplit_for(frg_ctx ctx, int ncol, int hi) {
     if (ctx->ks_override > 0) return ctx->ks_override;
     const int N = ctx->g.N;
     const int bm = frg::contract_block_rows(N);
-    const int64_t tiles = 3LL * ((N + bm - 1) / bm) * ((static_cast<int64_t>(N) * N + 63) / 64);
-    int64_t ks = (3456 + tiles - 1) / tiles;
-    return static_cast<int>(ks < 1 ? 1 : (ks > 8 ? 8 : ks));
+    const int64_t tiles = 3LL * ((N + bm - 1) / bm) * ((ncol + 63) / 64);
+    const int64_t ks = (ctx->ks_target + tiles - 1) / tiles;
+    return static_cast<int>(std::min<int64_t>(hi, std::max<int64_t>(ctx->ks_lo, ks)));
 }
 
 // entry of a chunk list: chunk id j (k = 8j .. 8j+7) and the patch pair
@@ -350,83 +364,126 @@ void cut_parts(const std::vector<int32_t> &chunk_of_entry, int begin, int end, i
     }
 }
 
-frg_status build_ktiles(frg_ctx ctx) {
+// Tile set of class cls over the columns `cols` (natural indices; rep[c] and
+// h[c] give, for every natural column c, the computed column whose values it
+// takes and the C4v element carrying c's free index to it).  Hilbert order of
+// the columns' transfer momenta unless natural; active chunks from the
+// second-line table unless every chunk is kept.
+frg_status build_tileset(frg_ctx ctx, int cls, const std::vector<int32_t> &cols, const std::vector<int32_t> &rep,
+                         const std::vector<int8_t> &h, bool natural, bool all_chunks, int KS, TileSet &ts) {
     const auto &g = ctx->g;
     const int N = g.N, NC = N * N;
-    const int tiles = (NC + frg::kContractCols - 1) / frg::kContractCols;
+    const int ncol = static_cast<int>(cols.size());
+    const int tiles = (ncol + frg::kContractCols - 1) / frg::kContractCols;
     const int nch = NC / frg::kContractChunk;
-    const char *kp = std::getenv("FRG_KPARTS");
-    ctx->kfixed = kp && std::strcmp(kp, "fixed") == 0;
-    const int KS = ksplit(ctx);
-    ctx->kparts = KS;
-    std::vector<uint8_t> flags(static_cast<size_t>(tiles) * nch);
-    for (int cls = 0; cls < 2; ++cls) {
-        std::vector<int32_t> colfull(NC), perm(NC);
-        std::vector<uint64_t> key(NC);
-        for (int y = 0; y < N; ++y)
-            for (int x = 0; x < N; ++x) {
-                const int c = y * N + x;
-                const int row = cls == 0 ? g.row_pp[y * N + x] : g.row_ph[x * N + y];
-                const double *q = cls == 0 ? &g.qpp[2 * row] : &g.qph[2 * row];
-                colfull[c] = cls == 0 ? row : g.Tpp + row;
-                key[c] = hilbert_key(q[0], q[1]);
-            }
-        std::iota(perm.begin(), perm.end(), 0);
-        std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
-        TRY(upload(ctx, &ctx->d_cperm[cls], perm.data(), perm.size()));
-        std::vector<int32_t> pos(NC);
-        for (int i = 0; i < NC; ++i) pos[perm[i]] = i;
-        TRY(upload(ctx, &ctx->d_cpos[cls], pos.data(), pos.size()));
+    std::vector<int32_t> colfull(NC), perm(cols);
+    std::vector<uint64_t> key(NC);
+    for (int y = 0; y < N; ++y)
+        for (int x = 0; x < N; ++x) {
+            const int c = y * N + x;
+            const int row = cls == 0 ? g.row_pp[y * N + x] : g.row_ph[x * N + y];
+            const double *q = cls == 0 ? &g.qpp[2 * row] : &g.qph[2 * row];
+            colfull[c] = cls == 0 ? row : g.Tpp + row;
+            key[c] = hilbert_key(q[0], q[1]);
+        }
+    if (!natural) std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+    std::vector<int32_t> pos(NC, -1), cmap(NC);
+    for (int i = 0; i < ncol; ++i) pos[perm[i]] = i;
+    for (int c = 0; c < NC; ++c) cmap[c] = (pos[rep[c]] << 3) | h[c];
+    TRY(upload(ctx, &ts.d_cperm, perm.data(), perm.size()));
+    TRY(upload(ctx, &ts.d_cmap, cmap.data(), cmap.size()));
+    std::vector<uint8_t> flags(static_cast<size_t>(tiles) * nch, 1);
+    if (!all_chunks) {
         int32_t *d_colfull = nullptr;
         uint8_t *d_flags = nullptr;
         hipError_t e = hipMalloc(&d_colfull, sizeof(int32_t) * NC);
         if (e == hipSuccess) e = hipMalloc(&d_flags, flags.size());
         if (e == hipSuccess) e = hipMemcpy(d_colfull, colfull.data(), sizeof(int32_t) * NC, hipMemcpyHostToDevice);
         if (e == hipSuccess) {
-            frg::launch_tile_pattern(ctx->d_bins, d_colfull, ctx->d_cperm[cls], N, g.nf, g.np, d_flags, nullptr);
+            frg::launch_tile_pattern(ctx->d_bins, d_colfull, ts.d_cperm, ncol, N, g.nf, g.np, d_flags, nullptr);
             e = hipGetLastError();
         }
         if (e == hipSuccess) e = hipMemcpy(flags.data(), d_flags, flags.size(), hipMemcpyDeviceToHost);
         if (d_colfull) hipFree(d_colfull);
         if (d_flags) hipFree(d_flags);
         if (e != hipSuccess) return fail(FRG_EDEVICE, std::string("column tiles: ") + hipGetErrorString(e));
-        std::vector<int32_t> koff(static_cast<size_t>(tiles) * (KS + 1)), klist, chunk;
-        for (int t = 0; t < tiles; ++t) {
-            const int begin = static_cast<int>(klist.size());
-            for (int j = 0; j < nch; ++j)
-                if (flags[static_cast<size_t>(t) * nch + j]) {
-                    klist.push_back(list_entry(j, N));
-                    chunk.push_back(j);
-                }
-            cut_parts(chunk, begin, static_cast<int>(klist.size()), KS, nch, ctx->kfixed,
-                      &koff[static_cast<size_t>(t) * (KS + 1)]);
-        }
-        ctx->kchunks_active[cls] = static_cast<int64_t>(klist.size());
-        TRY(upload(ctx, &ctx->d_koff[cls], koff.data(), koff.size()));
-        TRY(upload(ctx, &ctx->d_klist[cls], klist.data(), klist.size()));
     }
+    std::vector<int32_t> koff(static_cast<size_t>(tiles) * (KS + 1)), klist, chunk;
+    for (int t = 0; t < tiles; ++t) {
+        const int begin = static_cast<int>(klist.size());
+        for (int j = 0; j < nch; ++j)
+            if (flags[static_cast<size_t>(t) * nch + j]) {
+                klist.push_back(list_entry(j, N));
+                chunk.push_back(j);
+            }
+        cut_parts(chunk, begin, static_cast<int>(klist.size()), KS, nch, ctx->kfixed,
+                  &koff[static_cast<size_t>(t) * (KS + 1)]);
+    }
+    ts.ncol = ncol;
+    ts.kparts = KS;
+    ts.chunks = static_cast<int64_t>(klist.size());
+    TRY(upload(ctx, &ts.d_koff, koff.data(), koff.size()));
+    TRY(upload(ctx, &ts.d_klist, klist.data(), klist.size()));
+    return FRG_OK;
+}
+
+// every column computed, each its own representative
+void all_columns(int N, std::vector<int32_t> &cols, std::vector<int32_t> &rep, std::vector<int8_t> &h) {
+    cols.resize(static_cast<size_t>(N) * N);
+    std::iota(cols.begin(), cols.end(), 0);
+    rep = cols;
+    h.assign(cols.size(), 0);
+}
+
+// Tile sets made at creation: ts_full (and, where the grid is exactly C4v
+// covariant, ts_vsym: one column per orbit of the pair action
+// g (y, x) = (g y, g x); the representative is the orbit's smallest natural
+// index, and h[c] = g^-1 for c = g rep, because F(g c, g m) = F(c, m) for a
+// C4v-invariant vertex).  Also the [8][N] patch maps.
+frg_status build_ktiles(frg_ctx ctx) {
+    const int N = ctx->g.N, NC = N * N;
+    const char *kp = std::getenv("FRG_KPARTS");
+    ctx->kfixed = kp && std::strcmp(kp, "fixed") == 0;
+    std::vector<int16_t> perm8(8 * static_cast<size_t>(N));
+    for (int o = 0; o < 8; ++o)
+        for (int j = 0; j < N; ++j)
+            perm8[o * N + j] = static_cast<int16_t>(N % 8 == 0 ? c4v_patch_host(o, j, N) : j);
+    TRY(upload(ctx, &ctx->d_perm8, perm8.data(), perm8.size()));
+    std::vector<int32_t> cols, rep;
+    std::vector<int8_t> h;
+    all_columns(N, cols, rep, h);
+    const int ks_full = ksplit_for(ctx, NC, 8);
+    for (int cls = 0; cls < 2; ++cls)
+        TRY(build_tileset(ctx, cls, cols, rep, h, false, false, ks_full, ctx->ts_full[cls]));
+    if (!ctx->sym_avail) return FRG_OK;
+    cols.clear();
+    for (int c = 0; c < NC; ++c) {
+        const int y = c / N, x = c % N;
+        int r = c, ro = 0;
+        for (int o = 1; o < 8; ++o) {
+            const int gc = c4v_patch_host(o, y, N) * N + c4v_patch_host(o, x, N);
+            if (gc < r) { r = gc; ro = o; }
+        }
+        // c = g rep with g the inverse of the element ro that carries c to rep;
+        // the value at c, m is the value at rep, ro(m)
+        rep[c] = r;
+        h[c] = static_cast<int8_t>(ro);
+        if (r == c) cols.push_back(c);
+    }
+    const int ks_v = ksplit_for(ctx, static_cast<int>(cols.size()), 16);
+    for (int cls = 0; cls < 2; ++cls)
+        TRY(build_tileset(ctx, cls, cols, rep, h, false, false, ks_v, ctx->ts_vsym[cls]));
     return FRG_OK;
 }
 
 // natural column order with every k chunk (the dense contraction)
 frg_status ensure_dense_tiles(frg_ctx ctx) {
-    if (ctx->d_klist_dense) return FRG_OK;
-    const int NC = ctx->g.N * ctx->g.N;
-    const int tiles = (NC + frg::kContractCols - 1) / frg::kContractCols;
-    const int nch = NC / frg::kContractChunk;
-    const int KS = ctx->kparts;
-    std::vector<int32_t> perm(NC), koff(static_cast<size_t>(tiles) * (KS + 1)),
-        klist(static_cast<size_t>(tiles) * nch), chunk(klist.size());
-    std::iota(perm.begin(), perm.end(), 0);
-    for (size_t i = 0; i < klist.size(); ++i) {
-        chunk[i] = static_cast<int32_t>(i % nch);
-        klist[i] = list_entry(chunk[i], ctx->g.N);
-    }
-    for (int t = 0; t < tiles; ++t)
-        cut_parts(chunk, t * nch, (t + 1) * nch, KS, nch, ctx->kfixed, &koff[static_cast<size_t>(t) * (KS + 1)]);
-    TRY(upload(ctx, &ctx->d_cperm_id, perm.data(), perm.size()));
-    TRY(upload(ctx, &ctx->d_koff_dense, koff.data(), koff.size()));
-    TRY(upload(ctx, &ctx->d_klist_dense, klist.data(), klist.size()));
+    if (ctx->ts_dense[0].d_klist) return FRG_OK;
+    std::vector<int32_t> cols, rep;
+    std::vector<int8_t> h;
+    all_columns(ctx->g.N, cols, rep, h);
+    for (int cls = 0; cls < 2; ++cls)
+        TRY(build_tileset(ctx, cls, cols, rep, h, true, true, ctx->ts_full[0].kparts, ctx->ts_dense[cls]));
     return FRG_OK;
 }
 
@@ -469,16 +526,27 @@ void set_bubbles(frg_ctx ctx, bool split, bool sym, void *bpp, void *bph, frg::F
              std::getenv("FRG_NO_FAST") == nullptr;
 }
 
-// tile position of every column (cls 0: pp, 1: ph) in the current column order
-const int32_t *col_pos(frg_ctx ctx, int cls) { return ctx->kskip_on ? ctx->d_cpos[cls] : ctx->d_cperm_id; }
+// the tile set in use for class cls
+const TileSet &tiles_of(frg_ctx ctx, int cls) {
+    if (!ctx->kskip_on) return ctx->ts_dense[cls];
+    return ctx->vsym_on ? ctx->ts_vsym[cls] : ctx->ts_full[cls];
+}
+const int32_t *col_pos(frg_ctx ctx, int cls) { return tiles_of(ctx, cls).d_cmap; }
+// K parts of the column set in use
+int ksplit(frg_ctx ctx) { return tiles_of(ctx, 0).kparts; }
+
+// channel elements one rhs computes (computed columns x N), for the K-part sum
+int64_t computed_elems(frg_ctx ctx) {
+    return static_cast<int64_t>(std::max(tiles_of(ctx, 0).ncol, tiles_of(ctx, 1).ncol)) * ctx->g.N;
+}
 
 void set_tiles(frg_ctx ctx, frg::FusedContractArgs &a) {
-    const bool on = ctx->kskip_on;
     for (int t = 0; t < 3; ++t) {
-        const int cls = t == frg::TERM_PP ? 0 : 1;
-        a.cperm[t] = on ? ctx->d_cperm[cls] : ctx->d_cperm_id;
-        a.koff[t] = on ? ctx->d_koff[cls] : ctx->d_koff_dense;
-        a.klist[t] = on ? ctx->d_klist[cls] : ctx->d_klist_dense;
+        const TileSet &ts = tiles_of(ctx, t == frg::TERM_PP ? 0 : 1);
+        a.cperm[t] = ts.d_cperm;
+        a.koff[t] = ts.d_koff;
+        a.klist[t] = ts.d_klist;
+        a.ncol[t] = ts.ncol;
     }
 }
 
@@ -559,11 +627,34 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     {
         KTimer kt(ctx, FRG_K_COMBINE, s);
         double *Cs = ctx->d_C + 3 * KS * n3;
-        frg::launch_sum_parts(ctx->d_C, split, KS, n3, Cs, s);
-        frg::launch_combine(Cs, Cs + n3, Cs + 2 * n3, false, N, 1, col_pos(ctx, 0), col_pos(ctx, 1), ctx->d_T,
+        frg::launch_sum_parts(ctx->d_C, split, KS, n3, computed_elems(ctx), Cs, s);
+        frg::launch_combine(Cs, Cs + n3, Cs + 2 * n3, false, N, 1, col_pos(ctx, 0), col_pos(ctx, 1), ctx->d_perm8,
+                            ctx->d_T,
                             scale_by_T, F, s);
     }
     HIPCHK(hipGetLastError());
+    return FRG_OK;
+}
+
+// max over g, j of |V(g j) - V(j)| / max |V| (synchronises the stream)
+constexpr double kVsymTol = 1e-12;
+frg_status vsym_deviation(frg_ctx ctx, const double *V, hipStream_t s, double *rel) {
+    const int nb = frg::vsym_check_blocks(ctx->g.N);
+    double *d_part = nullptr;
+    HIPCHK(hipMalloc(&d_part, sizeof(double) * 2 * nb));
+    std::vector<double> h(2 * static_cast<size_t>(nb));
+    frg::launch_vsym_check(V, ctx->g.N, ctx->d_perm8, d_part, s);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(d_part);
+    if (e != hipSuccess) return fail(FRG_EDEVICE, std::string("symmetry check: ") + hipGetErrorString(e));
+    double dev = 0.0, vmax = 0.0;
+    for (int i = 0; i < nb; ++i) {
+        dev = std::max(dev, h[i]);
+        vmax = std::max(vmax, h[nb + i]);
+    }
+    *rel = vmax > 0.0 ? dev / vmax : dev;
     return FRG_OK;
 }
 
@@ -628,13 +719,13 @@ const char *frg_status_str(frg_status st) {
 
 const char *frg_last_error(void) { return g_err.c_str(); }
 
-static frg_status create_impl(const frg_params *p, int ks_hint, frg_ctx *out);
+static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out);
 
-frg_status frg_create(const frg_params *p, frg_ctx *out) { return create_impl(p, 0, out); }
+frg_status frg_create(const frg_params *p, frg_ctx *out) { return create_impl(p, 1, out); }
 
-// ks_hint > 0: K parts of the contraction for this context (a batch of many
-// flows needs fewer parts per flow to fill the chip); FRG_KSPLIT overrides
-static frg_status create_impl(const frg_params *p, int ks_hint, frg_ctx *out) {
+// n_batch: flows of the batch this context belongs to (1 alone): a batch
+// needs fewer K parts per flow to fill the chip; FRG_KSPLIT overrides
+static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out) {
     if (!out) return fail(FRG_EINVAL, "null output handle");
     *out = nullptr;
     TRY(check_params(p));
@@ -649,7 +740,10 @@ static frg_status create_impl(const frg_params *p, int ks_hint, frg_ctx *out) {
 
     frg_ctx ctx = new frg_ctx_s();
     ctx->device = dev;
-    ctx->ks_override = ks_hint;
+    if (n_batch > 1) {
+        ctx->ks_target = (13824 + n_batch - 1) / n_batch;
+        ctx->ks_lo = 2;
+    }
     if (const char *e = std::getenv("FRG_KSPLIT")) ctx->ks_override = std::atoi(e);
     frg::build_geometry(*p, ctx->g);
     const auto &g = ctx->g;
@@ -722,12 +816,13 @@ frg_status frg_destroy(frg_ctx ctx) {
                     ctx->d_colrow_pp, ctx->d_colrow_ph, ctx->d_pa64, ctx->d_T, ctx->d_pa32,
                     ctx->d_B64, ctx->d_B32, ctx->d_perm, ctx->d_ahl, ctx->d_g32, ctx->d_C,
                     ctx->d_yt, ctx->d_y5, ctx->d_partial, ctx->d_state, ctx->d_rowlist,
-                    ctx->d_colsym_pp, ctx->d_colsym_ph, ctx->d_cperm[0], ctx->d_cperm[1],
-                    ctx->d_koff[0], ctx->d_koff[1], ctx->d_klist[0], ctx->d_klist[1],
-                    ctx->d_cperm_id, ctx->d_koff_dense, ctx->d_klist_dense, ctx->d_cpos[0],
-                    ctx->d_cpos[1]};
+                    ctx->d_colsym_pp, ctx->d_colsym_ph, ctx->d_perm8};
     for (void *p : ptrs)
         if (p) hipFree(p);
+    for (int c = 0; c < 2; ++c)
+        for (TileSet *ts : {&ctx->ts_full[c], &ctx->ts_vsym[c], &ctx->ts_dense[c]})
+            for (int32_t *p : {ts->d_cperm, ts->d_cmap, ts->d_koff, ts->d_klist})
+                if (p) hipFree(p);
     for (int j = 0; j < 7; ++j)
         if (ctx->d_k[j]) hipFree(ctx->d_k[j]);
     if (ctx->h_state) hipHostFree(ctx->h_state);
@@ -830,6 +925,13 @@ frg_status frg_flow_init(frg_ctx ctx, const frg_flow_opts *o, const double *d_V,
     TRY(check_opts(ctx, o));
     if (!d_V || !d_state || !aligned8(d_V) || !aligned8(d_state))
         return fail(FRG_EINVAL, "null or misaligned V / state");
+    if (ctx->vsym_on) {   // a flow from a C4v-invariant vertex stays invariant
+        double dev = 0.0;
+        TRY(vsym_deviation(ctx, d_V, static_cast<hipStream_t>(stream), &dev));
+        if (!(dev <= kVsymTol))
+            return fail(FRG_EINVAL, "symmetric-vertex mode needs a C4v-invariant V (relative deviation " +
+                                        std::to_string(dev) + ")");
+    }
     TRY(ensure_rhs_ws(ctx, o->prec));
     TRY(ensure_flow_ws(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -969,6 +1071,27 @@ frg_status frg_symmetry(frg_ctx ctx, int32_t *active, int32_t *rows_computed) {
     return FRG_OK;
 }
 
+frg_status frg_set_vsym(frg_ctx ctx, int32_t enable) {
+    TRY(check_ctx(ctx));
+    if (enable && !ctx->sym_avail)
+        return fail(FRG_ENOTSUP, "symmetric-vertex mode needs an exactly C4v covariant grid (N % 8 == 0)");
+    ctx->vsym_on = enable != 0;
+    return FRG_OK;
+}
+
+frg_status frg_vsym(frg_ctx ctx, int32_t *active, int32_t *columns) {
+    TRY(check_ctx(ctx));
+    if (active) *active = ctx->vsym_on ? 1 : 0;
+    if (columns) *columns = ctx->vsym_on ? ctx->ts_vsym[0].ncol : ctx->g.N * ctx->g.N;
+    return FRG_OK;
+}
+
+frg_status frg_check_vsym(frg_ctx ctx, const double *d_V, double *rel_dev, void *stream) {
+    TRY(check_ctx(ctx));
+    if (!d_V || !rel_dev || !aligned8(d_V)) return fail(FRG_EINVAL, "null or misaligned argument");
+    return vsym_deviation(ctx, d_V, static_cast<hipStream_t>(stream), rel_dev);
+}
+
 frg_status frg_set_kskip(frg_ctx ctx, int32_t enable) {
     TRY(check_ctx(ctx));
     if (!enable) TRY(ensure_dense_tiles(ctx));
@@ -980,13 +1103,13 @@ frg_status frg_kskip(frg_ctx ctx, int32_t *active, double *executed_frac) {
     TRY(check_ctx(ctx));
     if (active) *active = ctx->kskip_on ? 1 : 0;
     if (executed_frac) {
+        // against every chunk of every column (natural tiles); work weights of
+        // the channels: pp 1, phc 1, phd 2 products per chunk
         const int NC = ctx->g.N * ctx->g.N;
         const double dense = static_cast<double>((NC + frg::kContractCols - 1) / frg::kContractCols) *
                              (NC / frg::kContractChunk);
-        // work weights of the channels: pp 1, phc 1, phd 2 products per chunk
-        *executed_frac = ctx->kskip_on
-                             ? (ctx->kchunks_active[0] + 3.0 * ctx->kchunks_active[1]) / (4.0 * dense)
-                             : 1.0;
+        const TileSet &pp = tiles_of(ctx, 0), &ph = tiles_of(ctx, 1);
+        *executed_frac = ctx->kskip_on ? (pp.chunks + 3.0 * ph.chunks) / (4.0 * dense) : 1.0;
     }
     return FRG_OK;
 }
@@ -1115,6 +1238,8 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         A.f32parts = split ? 1 : 0;
         A.Csum = c->d_C + 3 * KS * n3;
         A.ppos = col_pos(c, 0); A.phpos = col_pos(c, 1);
+        A.perm8 = c->d_perm8;
+        A.nel = computed_elems(c);
         st[f] = A.state;
         frg::BubbleArgs bb = bubble_args(c, split, bpp, bph);
         if (sym) {
@@ -1131,11 +1256,11 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
             a.N = g.N; a.KS = KS; a.n3 = n3;
             const int bm = frg::contract_block_rows(g.N);
             a.mtiles = (g.N + bm - 1) / bm;
-            a.ctiles = static_cast<int>((NN + 63) / 64);
             set_bubbles(c, split, sym, bpp, bph, a);
             a.colrow[frg::TERM_PP] = sym ? c->d_colsym_pp : c->d_colrow_pp;
             a.colrow[frg::TERM_PHC] = a.colrow[frg::TERM_PHD] = sym ? c->d_colsym_ph : c->d_colrow_ph;
             set_tiles(c, a);
+            a.ctiles = (std::max(a.ncol[frg::TERM_PP], a.ncol[frg::TERM_PHC]) + 63) / 64;
             a.C[frg::TERM_PP] = c->d_C;
             a.C[frg::TERM_PHC] = c->d_C + KS * n3;
             a.C[frg::TERM_PHD] = c->d_C + 2 * KS * n3;
@@ -1148,7 +1273,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
             for (int a = 0; a < g.N; ++a) it_bub.push_back(make_int2(f, (ch << 8) | a));
         for (int64_t k = 0; k < (n3 + 255) / 256; ++k) it_n3.push_back(make_int2(f, static_cast<int>(k)));
         for (int k = 0; k < frg::combine_tiles(g.N); ++k) it_comb.push_back(make_int2(f, k));
-        for (int64_t k = 0; k < (3 * n3 + frg::kSumPartsPerBlock - 1) / frg::kSumPartsPerBlock; ++k)
+        for (int64_t k = 0; k < (3 * A.nel + frg::kSumPartsPerBlock - 1) / frg::kSumPartsPerBlock; ++k)
             it_sum.push_back(make_int2(f, static_cast<int>(k)));
         for (int k = 0; k < A.nred; ++k) it_red.push_back(make_int2(f, k));
         const frg::FusedContractArgs &a0 = ca[0][f];
@@ -1292,13 +1417,7 @@ frg_status frg_batch_create(const frg_params *params, int32_t n_flows, frg_batch
     b->nf = params[0].n_rad * params[0].n_ang;
     for (int f = 0; f < n_flows; ++f) {
         frg_ctx c = nullptr;
-        // K parts: enough blocks over the whole batch (measured best at 16 flows of
-        // N = 96: 2 parts), between 2 and 8
-        const int N = params[f].N, bm = frg::contract_block_rows(N);
-        const int64_t tiles = 3LL * ((N + bm - 1) / bm) * ((static_cast<int64_t>(N) * N + 63) / 64);
-        const int ks = static_cast<int>(std::min<int64_t>(8, std::max<int64_t>(2, (13824 + tiles * n_flows - 1) /
-                                                                                     (tiles * n_flows))));
-        frg_status st = create_impl(&params[f], ks, &c);
+        frg_status st = create_impl(&params[f], n_flows, &c);
         if (st) { std::string m = g_err; frg_batch_destroy(b); g_err = m; return st; }
         b->ctx.push_back(c);
         b->maxN = std::max(b->maxN, params[f].N);
@@ -1340,6 +1459,19 @@ frg_status frg_batch_destroy(frg_batch b) {
     if (b->ev_out) hipEventDestroy(b->ev_out);
     if (b->stream) hipStreamDestroy(b->stream);
     delete b;
+    return FRG_OK;
+}
+
+frg_status frg_batch_set_vsym(frg_batch b, int32_t enable) {
+    if (!b) return fail(FRG_EINVAL, "null batch");
+    for (frg_ctx c : b->ctx)
+        if (enable && !c->sym_avail)
+            return fail(FRG_ENOTSUP, "symmetric-vertex mode needs N % 8 == 0 for every flow");
+    for (frg_ctx c : b->ctx) c->vsym_on = enable != 0;
+    // descriptors and the captured step describe the old mode: flow_init again
+    b->initialised = false;
+    b->built_prec = -1;
+    if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; b->exec_prec = -1; }
     return FRG_OK;
 }
 
@@ -1476,9 +1608,9 @@ frg_status frg_batch_rhs(frg_batch b, const double *T, double *const *d_V, doubl
         // F from the channel partials (the batched combine left T*F in k[0])
         const int KS = ksplit(c);
         double *Cs = c->d_C + 3 * KS * c->n3;
-        frg::launch_sum_parts(c->d_C, prec == FRG_PREC_SPLIT_BF16, KS, c->n3, Cs, s);
+        frg::launch_sum_parts(c->d_C, prec == FRG_PREC_SPLIT_BF16, KS, c->n3, computed_elems(c), Cs, s);
         frg::launch_combine(Cs, Cs + c->n3, Cs + 2 * c->n3, false, c->g.N, 1,
-                            col_pos(c, 0), col_pos(c, 1), c->d_T, 0, d_F[f], s);
+                            col_pos(c, 0), col_pos(c, 1), c->d_perm8, c->d_T, 0, d_F[f], s);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(b->ev_out, s));

@@ -74,6 +74,7 @@ enum Term { TERM_PP = 0, TERM_PHC = 1, TERM_PHD = 2,
 struct FusedContractArgs {
     int N, KS, mtiles, ctiles;
     int fast;   // split path: buffer-load fast path (N % 32 == 0, bubble rows < 2 GiB)
+    int ncol[3];  // columns computed per term (N^2, or one per C4v orbit of column pairs)
     int64_t n3;
     const void *B[3];             // bubble rows per term (pp: Bpp, phc/phd: Bph)
     int64_t Bbytes[3];            // their sizes in bytes
@@ -105,24 +106,32 @@ int contract_kinds(bool split);
 int contract_kind_products(bool split, int kind);
 constexpr int kContractCols = 64;     // columns per contraction tile
 constexpr int kContractChunk = 8;     // k chunk of the active lists
-// flags[t][j] = 1 if some column at tile position t*64 .. t*64+63 has a
-// point of the second-line table in k chunk j (k = a*N + b, chunk = k / 8);
+// flags[t][j] = 1 if some column at tile position t*64 .. t*64+63 (< ncol) has
+// a point of the second-line table in k chunk j (k = a*N + b, chunk = k / 8);
 // colfull[c] is the full row (pp rows, then ph rows) of column c
-void launch_tile_pattern(const uint8_t *bins, const int32_t *colfull, const int32_t *cperm, int N,
+void launch_tile_pattern(const uint8_t *bins, const int32_t *colfull, const int32_t *cperm, int ncol, int N,
                          int nf, int np, uint8_t *flags, hipStream_t s);
 
-// F[j1][j2][j3] = scale * (-Cpp[ppos(j1,j2)][j3] + Cc[phpos(j2,j3)][j1] + Cd[phpos(j1,j3)][j2]),
-// each summed (in FP64) over the K parts; ppos / phpos give the tile position
-// of a column (pp: j1*N+j2, ph: y*N+x); scale = T when scale_by_T; the
+// F[j1][j2][j3] = scale * (-Cpp(j1,j2; j3) + Cc(j2,j3; j1) + Cd(j1,j3; j2)), each
+// channel summed (in FP64) over the K parts.  Channel value C(c; m) of column c
+// (pp: j1*N+j2, ph: y*N+x) and free index m is C[pos][perm8[h][m]] with
+// cmap[c] = (pos << 3) | h: pos the tile position of the computed column, h
+// the C4v element that carries c's frame to it (0 when every column is
+// computed; perm8 = [8][N] patch maps).  scale = T when scale_by_T; the
 // partials are float when f32parts, else double
 void launch_combine(const void *Cpp, const void *Cc, const void *Cd, bool f32parts, int N, int parts,
-                    const int32_t *ppos, const int32_t *phpos, const double *Tdev, int scale_by_T,
-                    double *F, hipStream_t s);
+                    const int32_t *ppos, const int32_t *phpos, const int16_t *perm8, const double *Tdev,
+                    int scale_by_T, double *F, hipStream_t s);
+// largest |V(g j1, g j2, g j3) - V(j1, j2, j3)| over the C4v elements g, and
+// max |V|: per-block partials [2][nblocks] (host reduces)
+int vsym_check_blocks(int N);
+void launch_vsym_check(const double *V, int N, const int16_t *perm8, double *partials, hipStream_t s);
 int combine_tiles(int N);   // blocks of one combine
-// out[t][i] = sum_ks C_t[ks][i] in FP64 for the three channels t, where C_t
-// starts at double offset t*KS*n3 of C and holds float (f32parts) or double
-// partials; out is [3][n3]
-void launch_sum_parts(const double *C, bool f32parts, int KS, int64_t n3, double *out, hipStream_t s);
+// out[t][i] = sum_ks C_t[ks][i] in FP64 for the three channels t and i < nel,
+// where C_t starts at double offset t*KS*n3 of C and holds float (f32parts)
+// or double partials (part stride n3); out is [3][n3]
+void launch_sum_parts(const double *C, bool f32parts, int KS, int64_t n3, int64_t nel, double *out,
+                      hipStream_t s);
 constexpr int kSumPartsPerBlock = 1024;   // elements of out per block of the batched sum
 
 // ----------------------------------------------------------------- RK kernels
@@ -170,6 +179,8 @@ struct FlowArgs {
     int KS;
     int f32parts;  // partials are float (split path)
     double *Csum;  // [3][n3]: partials summed over the K parts
+    int64_t nel;   // elements per channel actually computed (ncol * N)
+    const int16_t *perm8;   // [8][N] C4v patch maps
     const int32_t *ppos, *phpos;   // tile position of each pp / ph column
 };
 enum { SRC_V = 0, SRC_YT = 1, SRC_Y5 = 2 };

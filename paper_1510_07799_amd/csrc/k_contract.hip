@@ -34,6 +34,8 @@
 //   split: A and Z as bf16 hi + lo, three v_mfma_f32_16x16x32_bf16 per
 //          k-step (hi*hi + hi*lo + lo*hi), FP32 accumulation, K step 32
 //          (four list chunks).
+#include <algorithm>
+
 #include "frg_internal.h"
 
 namespace frg {
@@ -200,8 +202,9 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
     double *sZ = smem + NP * BM * LDA;        // [NP][BC][LDA]
     const int N = P.N;
     const int K = N * N;
-    const int NC = N * N;
+    const int NC = P.ncol[TERM];
     const int m0 = w.mtile * BM, c0 = w.ctile * BC;
+    if (c0 >= NC) return;
     const TileK<G> tk(P, TERM, w);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const GLOBAL_AS double *A0 = gload_ptr(P.A64[TERM][0]);
@@ -375,9 +378,10 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     uint16_t *sZ = smem + NP * 2 * BM * LD;        // [NP][2][BC][LD]
     const int N = P.N;
     const int K = N * N;
-    const int NC = N * N;
+    const int NC = P.ncol[TT];
     const int64_t n3 = P.n3;
     const int m0 = w.mtile * BM, c0 = w.ctile * BC;
+    if (c0 >= NC) return;
     const TileK<G> tk(P, TT, w);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const GLOBAL_AS uint16_t *Ahl[NP];
@@ -768,7 +772,7 @@ constexpr size_t lds_bytes(bool split, int bm) {
 template <int BM>
 void launch_bm(FusedContractArgs a, bool split, hipStream_t s) {
     a.mtiles = (a.N + BM - 1) / BM;
-    a.ctiles = (a.N * a.N + BC - 1) / BC;
+    a.ctiles = (std::max(a.ncol[TERM_PP], a.ncol[TERM_PHC]) + BC - 1) / BC;
     const int blocks = contract_kinds_of(split) * a.mtiles * a.ctiles * a.KS;
     if (split)
         hipLaunchKernelGGL(contract_split_fused<BM>, dim3(blocks), dim3(kThreads), lds_bytes(true, BM), s, a);
@@ -779,14 +783,14 @@ void launch_bm(FusedContractArgs a, bool split, hipStream_t s) {
 // flags of the k chunks of one column tile (block = tile)
 __global__ __launch_bounds__(256) void tile_pattern_kernel(const uint8_t *__restrict__ bins,
                                                            const int32_t *__restrict__ colfull,
-                                                           const int32_t *__restrict__ cperm, int N,
+                                                           const int32_t *__restrict__ cperm, int ncol, int N,
                                                            int nf, int np, uint8_t *__restrict__ flags) {
     extern __shared__ uint8_t sflag[];
     const int NC = N * N, nch = NC / kContractChunk;
     for (int j = threadIdx.x; j < nch; j += blockDim.x) sflag[j] = 0;
     __syncthreads();
     const int p0 = blockIdx.x * BC;
-    for (int cl = 0; cl < BC && p0 + cl < NC; ++cl) {
+    for (int cl = 0; cl < BC && p0 + cl < ncol; ++cl) {
         const uint8_t *row = bins + static_cast<int64_t>(colfull[cperm[p0 + cl]]) * np;
         for (int p = threadIdx.x; p < np; p += blockDim.x) {
             const int k = (p / nf) * N + row[p];
@@ -802,12 +806,12 @@ __global__ __launch_bounds__(256) void tile_pattern_kernel(const uint8_t *__rest
 
 int contract_block_rows(int N) { return block_rows_of(N); }
 
-void launch_tile_pattern(const uint8_t *bins, const int32_t *colfull, const int32_t *cperm, int N, int nf,
-                         int np, uint8_t *flags, hipStream_t s) {
-    const int tiles = (N * N + BC - 1) / BC;
+void launch_tile_pattern(const uint8_t *bins, const int32_t *colfull, const int32_t *cperm, int ncol, int N,
+                         int nf, int np, uint8_t *flags, hipStream_t s) {
+    const int tiles = (ncol + BC - 1) / BC;
     const size_t lds = static_cast<size_t>(N) * N / kContractChunk;
-    hipLaunchKernelGGL(tile_pattern_kernel, dim3(tiles), dim3(256), lds, s, bins, colfull, cperm, N, nf, np,
-                       flags);
+    hipLaunchKernelGGL(tile_pattern_kernel, dim3(tiles), dim3(256), lds, s, bins, colfull, cperm, ncol, N, nf,
+                       np, flags);
 }
 
 size_t contract_lds_bytes(bool split) { return lds_bytes(split, 96); }

@@ -1,6 +1,7 @@
 // Small device kernels: second-line patch table, per-point temperature
 // factors, contraction operand layout, channel combine and the explicit
 // Runge-Kutta machinery (stage sums, FP64 error norm, on-device step control).
+#include <algorithm>
 #include <cmath>
 
 #include "frg_internal.h"
@@ -220,7 +221,12 @@ template <typename PT>
 __device__ void combine_body(int N, int KS, int64_t n3, const PT *__restrict__ Cpp,
                              const PT *__restrict__ Cc, const PT *__restrict__ Cd,
                              const int32_t *__restrict__ ppos, const int32_t *__restrict__ phpos,
-                             double scale, double *__restrict__ F, int tile, double *sF) {
+                             const int16_t *__restrict__ perm8, double scale, double *__restrict__ F, int tile,
+                             double *sF) {
+    // channel value at column map entry cm and free index m
+    auto at_of = [&](int32_t cm, int m) -> int64_t {
+        return static_cast<int64_t>(cm >> 3) * N + perm8[(cm & 7) * N + m];
+    };
     const int nj = (N + CB_J - 1) / CB_J, nk = (N + CB_K - 1) / CB_K;
     const int t3 = tile % nk, t2 = (tile / nk) % nj, t1 = tile / (nk * nj);
     const int a0 = t1 * CB_J, b0 = t2 * CB_J, c0 = t3 * CB_K;
@@ -230,7 +236,7 @@ __device__ void combine_body(int N, int KS, int64_t n3, const PT *__restrict__ C
         const int i3 = e % CB_K, i2 = (e / CB_K) % CB_J, i1 = e / (CB_K * CB_J);
         const int j1 = a0 + i1, j2 = b0 + i2, j3 = c0 + i3;
         if (j1 >= N || j2 >= N || j3 >= N) continue;
-        const int64_t at = static_cast<int64_t>(ppos[j1 * N + j2]) * N + j3;
+        const int64_t at = at_of(ppos[j1 * N + j2], j3);
         double v = 0.0;
         for (int s = 0; s < KS; ++s) v += Cpp[s * n3 + at];
         sF[(i1 * CB_J + i2) * CB_P + i3] = -v;
@@ -241,7 +247,7 @@ __device__ void combine_body(int N, int KS, int64_t n3, const PT *__restrict__ C
         const int i1 = e % CB_J, i3 = (e / CB_J) % CB_K, i2 = e / (CB_J * CB_K);
         const int j1 = a0 + i1, j2 = b0 + i2, j3 = c0 + i3;
         if (j1 >= N || j2 >= N || j3 >= N) continue;
-        const int64_t at = static_cast<int64_t>(phpos[j2 * N + j3]) * N + j1;
+        const int64_t at = at_of(phpos[j2 * N + j3], j1);
         double v = 0.0;
         for (int s = 0; s < KS; ++s) v += Cc[s * n3 + at];
         sF[(i1 * CB_J + i2) * CB_P + i3] += v;
@@ -252,7 +258,7 @@ __device__ void combine_body(int N, int KS, int64_t n3, const PT *__restrict__ C
         const int i2 = e % CB_J, i3 = (e / CB_J) % CB_K, i1 = e / (CB_J * CB_K);
         const int j1 = a0 + i1, j2 = b0 + i2, j3 = c0 + i3;
         if (j1 >= N || j2 >= N || j3 >= N) continue;
-        const int64_t at = static_cast<int64_t>(phpos[j1 * N + j3]) * N + j2;
+        const int64_t at = at_of(phpos[j1 * N + j3], j2);
         double v = 0.0;
         for (int s = 0; s < KS; ++s) v += Cd[s * n3 + at];
         sF[(i1 * CB_J + i2) * CB_P + i3] += v;
@@ -269,35 +275,65 @@ __device__ void combine_body(int N, int KS, int64_t n3, const PT *__restrict__ C
 // Sum of the K-part partials, four consecutive elements per thread (streams
 // of contiguous loads, one per part).
 template <typename PT>
-__device__ __forceinline__ void sum_parts_body(const double *__restrict__ C, int KS, int64_t n3,
+__device__ __forceinline__ void sum_parts_body(const double *__restrict__ C, int KS, int64_t n3, int64_t nel,
                                                double *__restrict__ out, int64_t q) {
-    const int64_t i0 = 4 * q;
-    if (i0 >= 3 * n3) return;
-    const int t = static_cast<int>(i0 / n3);
-    const int64_t i = i0 - t * n3;
+    // q runs over [3][nel / 4] quads (nel % 4 == 0: nel = ncol * N, N % 4 == 0)
+    const int64_t qpt = nel / 4;
+    if (q >= 3 * qpt) return;
+    const int t = static_cast<int>(q / qpt);
+    const int64_t i = 4 * (q - t * qpt);
     const PT *Ct = reinterpret_cast<const PT *>(C + t * static_cast<int64_t>(KS) * n3);
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (i + 4 <= n3) {   // n3 = N^3 with N % 4 == 0: always taken
-        for (int s = 0; s < KS; ++s) {
-            const PT *src = Ct + s * n3 + i;
+    for (int s = 0; s < KS; ++s) {
+        const PT *src = Ct + s * n3 + i;
 #pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] += static_cast<double>(src[e]);
-        }
-#pragma unroll
-        for (int e = 0; e < 4; ++e) out[t * n3 + i + e] = v[e];
-    } else {
-        for (int e = 0; e < 4 && i + e < n3; ++e) {
-            double w = 0.0;
-            for (int s = 0; s < KS; ++s) w += static_cast<double>(Ct[s * n3 + i + e]);
-            out[t * n3 + i + e] = w;
-        }
+        for (int e = 0; e < 4; ++e) v[e] += static_cast<double>(src[e]);
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[t * n3 + i + e] = v[e];
 }
 
 template <typename PT>
 __global__ __launch_bounds__(256) void sum_parts_kernel(const double *__restrict__ C, int KS, int64_t n3,
-                                                        double *__restrict__ out) {
-    sum_parts_body<PT>(C, KS, n3, out, static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+                                                        int64_t nel, double *__restrict__ out) {
+    sum_parts_body<PT>(C, KS, n3, nel, out, static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+}
+
+// V(g j1, g j2, g j3) - V(j1, j2, j3) over the seven non-trivial C4v elements:
+// per block the largest deviation and the largest |V| (fixed-order host max)
+constexpr int kVsymBlocks = 1024;
+__global__ __launch_bounds__(256) void vsym_check_kernel(const double *__restrict__ V, int N,
+                                                         const int16_t *__restrict__ perm8,
+                                                         double *__restrict__ partials) {
+    __shared__ double sd[256], sv[256];
+    const int64_t n3 = static_cast<int64_t>(N) * N * N;
+    double dev = 0.0, vmax = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n3;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int j3 = static_cast<int>(i % N), j2 = static_cast<int>((i / N) % N);
+        const int j1 = static_cast<int>(i / (static_cast<int64_t>(N) * N));
+        const double v = V[i];
+        vmax = fmax(vmax, fabs(v));
+        for (int o = 1; o < 8; ++o) {
+            const int64_t k = (static_cast<int64_t>(perm8[o * N + j1]) * N + perm8[o * N + j2]) * N +
+                              perm8[o * N + j3];
+            dev = fmax(dev, fabs(V[k] - v));
+        }
+    }
+    sd[threadIdx.x] = dev;
+    sv[threadIdx.x] = vmax;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) {
+            sd[threadIdx.x] = fmax(sd[threadIdx.x], sd[threadIdx.x + w]);
+            sv[threadIdx.x] = fmax(sv[threadIdx.x], sv[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = sd[0];
+        partials[gridDim.x + blockIdx.x] = sv[0];
+    }
 }
 
 template <typename PT>
@@ -306,11 +342,12 @@ __global__ __launch_bounds__(256) void combine_kernel(const PT *__restrict__ Cpp
                                                       const PT *__restrict__ Cd, int N, int parts,
                                                       const int32_t *__restrict__ ppos,
                                                       const int32_t *__restrict__ phpos,
+                                                      const int16_t *__restrict__ perm8,
                                                       const double *__restrict__ Tdev, int scale_by_T,
                                                       double *__restrict__ F) {
     __shared__ double sF[CB_J * CB_J * CB_P];
     const int64_t n3 = static_cast<int64_t>(N) * N * N;
-    combine_body(N, parts, n3, Cpp, Cc, Cd, ppos, phpos, scale_by_T ? Tdev[0] : 1.0, F, blockIdx.x, sF);
+    combine_body(N, parts, n3, Cpp, Cc, Cd, ppos, phpos, perm8, scale_by_T ? Tdev[0] : 1.0, F, blockIdx.x, sF);
 }
 
 // ----------------------------------------------------------------- RK
@@ -579,7 +616,7 @@ __global__ __launch_bounds__(256) void combine_b_kernel(const FlowArgs *__restri
     const int KS = f.KS;
     (void)KS;
     combine_body(f.N, 1, n, static_cast<const double *>(f.Csum), f.Csum + n, f.Csum + 2 * n, f.ppos, f.phpos,
-                 f.Tdev[0], f.k[stage], it.y, sF);
+                 f.perm8, f.Tdev[0], f.k[stage], it.y, sF);
 }
 
 // batched sum of the K parts: item = (flow, block of kSumPartsPerBlock elements)
@@ -589,8 +626,8 @@ __global__ __launch_bounds__(256) void sum_parts_b_kernel(const FlowArgs *__rest
     const FlowArgs &f = fa[it.x];
     if (flow_stopped(f)) return;
     const int64_t q = static_cast<int64_t>(it.y) * (kSumPartsPerBlock / 4) + threadIdx.x;
-    if (f.f32parts) sum_parts_body<float>(f.C, f.KS, f.n3, f.Csum, q);
-    else sum_parts_body<double>(f.C, f.KS, f.n3, f.Csum, q);
+    if (f.f32parts) sum_parts_body<float>(f.C, f.KS, f.n3, f.nel, f.Csum, q);
+    else sum_parts_body<double>(f.C, f.KS, f.n3, f.nel, f.Csum, q);
 }
 
 struct Coef7 { double c[7]; };
@@ -715,16 +752,16 @@ void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipS
 int combine_tiles(int N) { return combine_tiles_of(N); }
 
 void launch_combine(const void *Cpp, const void *Cc, const void *Cd, bool f32parts, int N, int parts,
-                    const int32_t *ppos, const int32_t *phpos,
+                    const int32_t *ppos, const int32_t *phpos, const int16_t *perm8,
                     const double *Tdev, int scale_by_T, double *F, hipStream_t s) {
     if (f32parts)
         hipLaunchKernelGGL(combine_kernel<float>, dim3(combine_tiles_of(N)), dim3(256), 0, s,
                            static_cast<const float *>(Cpp), static_cast<const float *>(Cc),
-                           static_cast<const float *>(Cd), N, parts, ppos, phpos, Tdev, scale_by_T, F);
+                           static_cast<const float *>(Cd), N, parts, ppos, phpos, perm8, Tdev, scale_by_T, F);
     else
         hipLaunchKernelGGL(combine_kernel<double>, dim3(combine_tiles_of(N)), dim3(256), 0, s,
                            static_cast<const double *>(Cpp), static_cast<const double *>(Cc),
-                           static_cast<const double *>(Cd), N, parts, ppos, phpos, Tdev, scale_by_T, F);
+                           static_cast<const double *>(Cd), N, parts, ppos, phpos, perm8, Tdev, scale_by_T, F);
 }
 
 void launch_rk_stage(const RkStageArgs &a, hipStream_t s) {
@@ -782,12 +819,24 @@ void launch_layout_b(const FlowArgs *fa, const int2 *items, int nitems, int src,
                      hipStream_t s) {
     hipLaunchKernelGGL(layout_b_kernel, dim3(nitems), dim3(256), 0, s, fa, items, src, split ? 1 : 0);
 }
-void launch_sum_parts(const double *C, bool f32parts, int KS, int64_t n3, double *out, hipStream_t s) {
-    const int64_t quads = (3 * n3 + 3) / 4;
+void launch_sum_parts(const double *C, bool f32parts, int KS, int64_t n3, int64_t nel, double *out,
+                      hipStream_t s) {
+    const int64_t quads = 3 * (nel / 4);
     if (f32parts)
-        hipLaunchKernelGGL(sum_parts_kernel<float>, dim3(blocks_for(quads, 256)), dim3(256), 0, s, C, KS, n3, out);
+        hipLaunchKernelGGL(sum_parts_kernel<float>, dim3(blocks_for(quads, 256)), dim3(256), 0, s, C, KS, n3, nel,
+                           out);
     else
-        hipLaunchKernelGGL(sum_parts_kernel<double>, dim3(blocks_for(quads, 256)), dim3(256), 0, s, C, KS, n3, out);
+        hipLaunchKernelGGL(sum_parts_kernel<double>, dim3(blocks_for(quads, 256)), dim3(256), 0, s, C, KS, n3, nel,
+                           out);
+}
+
+int vsym_check_blocks(int N) {
+    const int64_t n3 = static_cast<int64_t>(N) * N * N;
+    return static_cast<int>(std::min<int64_t>(kVsymBlocks, (n3 + 255) / 256));
+}
+
+void launch_vsym_check(const double *V, int N, const int16_t *perm8, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(vsym_check_kernel, dim3(vsym_check_blocks(N)), dim3(256), 0, s, V, N, perm8, partials);
 }
 
 void launch_sum_parts_b(const FlowArgs *fa, const int2 *items, int nitems, hipStream_t s) {

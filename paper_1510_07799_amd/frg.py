@@ -80,6 +80,10 @@ SIGNATURES = {
     "frg_symmetry": (C.c_int, [_P, _IP, _IP]),
     "frg_set_kskip": (C.c_int, [_P, C.c_int32]),
     "frg_kskip": (C.c_int, [_P, _IP, _DP]),
+    "frg_set_vsym": (C.c_int, [_P, C.c_int32]),
+    "frg_vsym": (C.c_int, [_P, _IP, _IP]),
+    "frg_check_vsym": (C.c_int, [_P, _P, _DP, _P]),
+    "frg_batch_set_vsym": (C.c_int, [_P, C.c_int32]),
     "frg_profile_begin": (C.c_int, [_P]),
     "frg_profile_end": (C.c_int, [_P, _DP, _IP]),
     "frg_status_str": (C.c_char_p, [C.c_int]),
@@ -243,6 +247,21 @@ class Context:
     def set_kskip(self, enable: bool):
         _check(lib().frg_set_kskip(self._h, 1 if enable else 0))
 
+    def set_vsym(self, enable: bool):
+        _check(lib().frg_set_vsym(self._h, 1 if enable else 0))
+
+    def vsym(self):
+        """(symmetric-vertex mode on, columns computed per channel)."""
+        a, n = C.c_int32(), C.c_int32()
+        _check(lib().frg_vsym(self._h, C.byref(a), C.byref(n)))
+        return bool(a.value), int(n.value)
+
+    def check_vsym(self, V):
+        """Largest relative deviation of V from C4v invariance."""
+        d = C.c_double()
+        _check(lib().frg_check_vsym(self._h, _ptr(V), C.byref(d), _stream()))
+        return float(d.value)
+
     def kskip(self):
         """(zero-block skipping on, executed share of the dense contraction work)."""
         a, f = C.c_int32(), C.c_double()
@@ -311,6 +330,10 @@ class Batch:
         _check(lib().frg_batch_rhs(self._h, T.ctypes.data_as(_DP), self._ptrs(Vs), self._ptrs(Fs),
                                    int(prec), _stream()))
         return Fs
+
+    def set_vsym(self, enable: bool):
+        """Symmetric-vertex mode for every flow (flow_init again afterwards)."""
+        _check(lib().frg_batch_set_vsym(self._h, 1 if enable else 0))
 
     def symmetry(self):
         """(active, bubble rows per rhs) of every member."""

@@ -376,3 +376,84 @@ def test_batch_flow_matches_single_flows():
         assert np.allclose(log[i, :res[i]["accepted"], 0], l1[:, 0], rtol=0, atol=1e-9)
         assert nrel(Vs[i].cpu().numpy(), V1.cpu().numpy()) <= 1e-9
     b.close()
+
+
+@pytest.mark.parametrize("cfg", ["C1", FAST64, "C3"], ids=["C1", "n64", "C3"])
+def test_symmetric_vertex_mode_matches_full_rhs(cfg):
+    """For a C4v-invariant V the rhs from one column per C4v orbit equals the
+    rhs from every column, and F is exactly invariant."""
+    om, g = pair(cfg)
+    N = om.N
+    V = dev(I.random_vertex(N, om.U, seed=51, amp=0.3, symmetrise=True))
+    assert g.check_vsym(V) <= 1e-15
+    ref = om.rhs(0.04, V.cpu().numpy()) if N <= 64 else None
+    for prec, tol in ((frg.PREC_FP64, 1e-12), (frg.PREC_SPLIT_BF16, 2e-4)):
+        Ff = g.rhs(0.04, V, prec).cpu().numpy()
+        g.set_vsym(True)
+        try:
+            active, cols = g.vsym()
+            assert active and N * N <= 8 * cols <= N * N + 8 * N
+            Fs = g.rhs(0.04, V, prec).cpu().numpy()
+        finally:
+            g.set_vsym(False)
+        print(f"[vsym] N={N} prec={prec} cols={cols}: {nrel(Fs, Ff):.2e}", flush=True)
+        assert nrel(Fs, Ff) <= tol
+        if ref is not None:
+            assert nrel(Fs, ref) <= (1e-10 if prec == frg.PREC_FP64 else 2e-4)
+        for o in range(1, 8):
+            p = I.c4v_patch_perm(N, o)
+            assert np.array_equal(Fs[np.ix_(p, p, p)], Fs)
+
+
+def test_symmetric_vertex_orbit_count_and_checks():
+    """About N^3/8 independent entries (the paper's count at N = 32 is 4072,
+    which also uses spin and time-reversal symmetry); the mode refuses a grid
+    without exact covariance and a flow from a non-invariant vertex."""
+    om, g = pair(FAST32)
+    N = om.N
+    g.set_vsym(True)
+    try:
+        _, cols = g.vsym()
+        assert abs(cols * N - N ** 3 / 8) / (N ** 3 / 8) < 0.05
+        V = dev(I.random_vertex(N, om.U, seed=52, symmetrise=False))
+        assert g.check_vsym(V) > 1e-3
+        state = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+        opts = frg.flow_opts("rk4", frg.PREC_FP64, T0=1.0, T_min=0.5, fixed_steps=2, vmax=1e9)
+        with pytest.raises(frg.FRGError) as e:
+            g.flow_init(opts, V, state)
+        assert e.value.status == frg.EINVAL
+    finally:
+        g.set_vsym(False)
+    _, gr = pair(RAGGED)
+    with pytest.raises(frg.FRGError) as e:
+        gr.set_vsym(True)
+    assert e.value.status == frg.ENOTSUP
+
+
+def test_symmetric_vertex_flows_single_and_batched():
+    """A DP5(4) flow from V = U (invariant) in symmetric-vertex mode follows the
+    full-vertex flow step for step, alone and in a batch."""
+    cfgs = [p for p in BATCH if p["N"] % 8 == 0]
+    o = frg.flow_opts("dp54", frg.PREC_FP64, T0=1.0, T_min=0.02, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.01)
+    ref = []
+    for p in cfgs:
+        om, g = pair(p)
+        V1 = torch.full((p["N"],) * 3, p["U"], dtype=torch.float64, device="cuda")
+        r1, _ = g.flow(V1, o)
+        ref.append((r1, V1.cpu().numpy()))
+        g.set_vsym(True)
+        try:
+            V2 = torch.full((p["N"],) * 3, p["U"], dtype=torch.float64, device="cuda")
+            r2, _ = g.flow(V2, o)
+        finally:
+            g.set_vsym(False)
+        assert (r2["reason"], r2["accepted"], r2["rejected"]) == (r1["reason"], r1["accepted"], r1["rejected"])
+        assert nrel(V2.cpu().numpy(), ref[-1][1]) <= 1e-9
+    b = frg.Batch(cfgs)
+    b.set_vsym(True)
+    Vs = [torch.full((p["N"],) * 3, p["U"], dtype=torch.float64, device="cuda") for p in cfgs]
+    res, _ = b.flow(Vs, o, log_cap=256)
+    for i, (r1, v1) in enumerate(ref):
+        assert res[i]["accepted"] == r1["accepted"] and res[i]["reason"] == r1["reason"]
+        assert nrel(Vs[i].cpu().numpy(), v1) <= 1e-9
+    b.close()
