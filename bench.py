@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 RHS_PER_STEP = 6   # DP5(4) with first-same-as-last: six new stages per step
-PEAK = {"hbm_GBs": 8000.0, "bf16_TFLOPs": 2500.0, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3}
+PEAK = {"hbm_GBs": 8000.0, "bf16_TFLOPs": 2500.0, "fp64_TFLOPs": 78.6, "fp32_TFLOPs": 157.3,
+        "valu_TFLOPs": 78.6}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -57,9 +58,9 @@ def timed_flow_steps(frg, torch, ctx, prec, V0, steps, warmup):
     return t1 - t0, prof, st
 
 
-def roofline(head, results, algo_flops, dense_flops, exec_share, evals_per_rhs):
+def roofline(head, results, algo_flops, dense_flops, exec_share, evals_per_rhs, kernel=None):
     prof = head["prof"]
-    dom = max(prof, key=lambda k: prof[k][0])
+    dom = kernel or max(prof, key=lambda k: prof[k][0])
     ms, cnt = prof[dom]
     avg_s = ms / max(cnt, 1) * 1e-3
     leg_name = "split" if "split" in results else [k for k in results][0]
@@ -72,8 +73,10 @@ def roofline(head, results, algo_flops, dense_flops, exec_share, evals_per_rhs):
         roof["executed_frac"] = round(passes * dense_flops * exec_share / avg_s / 1e12 / peak, 6)
         roof["kskip_executed_share"] = round(exec_share, 4)
     elif dom == "bubbles":
-        # plain ALU bound: FP32/FP64 vector issue; algorithmic unit = one integrand evaluation
-        peak = PEAK["fp32_TFLOPs"] if leg_name == "split" else PEAK["fp64_TFLOPs"]
+        # plain ALU bound: vector FMA issue without packed FP32 (the build disables it),
+        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s for FP32 and FP64;
+        # algorithmic unit = one integrand evaluation, 40 flop-equivalents
+        peak = PEAK["valu_TFLOPs"]
         flops_per_eval = 40.0
         achieved = evals_per_rhs * flops_per_eval / avg_s / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 4), "peak": peak,
@@ -101,7 +104,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="split,fp64,batch", help="comma list of split,fp64,batch")
+    ap.add_argument("--legs", default="split,fp64,batch,split_full",
+                    help="comma list of split,fp64,batch (symmetric-vertex mode) and split_full "
+                         "(every column computed)")
     ap.add_argument("--batch-flows", type=int, default=16,
                     help="flows in the batched leg (N=96, 512 points/patch, drawn parameters)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
@@ -143,10 +148,17 @@ def main():
     # ph column (y, x) uses row of Q = k_x - k_y; every ordered pair occurs once, x == y uses row 0
     colsum_ph = float(nnz_ph[1:].sum() + N * nnz_ph[0])
     del Bpp, Bph
-    # pp: one product per column, phc: one, phd: two (N output rows each)
-    algo_flops = {"contract": 2.0 * N * colsum_pp + 2.0 * N * colsum_ph + 4.0 * N * colsum_ph}
+    # pp: one product per column, phc: one, phd: two (N output rows each); with a
+    # C4v-invariant vertex only one column per orbit is needed (every column of an
+    # orbit has the same bubble-row occupancy)
+    ctx.set_vsym(True)
+    vsym_cols = ctx.vsym()[1]
+    ctx.set_vsym(False)
+    algo_full = 2.0 * N * colsum_pp + 2.0 * N * colsum_ph + 4.0 * N * colsum_ph
+    algo_flops = {"contract": algo_full * vsym_cols / (N * N)}
     dense_flops = 8.0 * N ** 5   # what the dense formulation executes (x3 passes in split mode)
-    _, exec_share = ctx.kskip()   # share of the dense k chunks the contraction visits
+    ctx.set_vsym(True)
+    _, exec_share = ctx.kskip()   # share of the dense k chunks (all columns) the contraction visits
     evals_per_rhs = ctx.symmetry()[1] * N * nf   # bubble rows one rhs evaluates (C4v-reduced)
 
     legs = [x.strip() for x in args.legs.split(",") if x.strip()]
@@ -154,14 +166,17 @@ def main():
     for leg in legs:
         if leg == "batch":
             continue
-        prec = frg.PREC_SPLIT_BF16 if leg == "split" else frg.PREC_FP64
+        prec = frg.PREC_FP64 if leg == "fp64" else frg.PREC_SPLIT_BF16
+        ctx.set_vsym(leg != "split_full")   # the flows start from V = U: C4v invariant
         dt, prof, st = timed_flow_steps(frg, torch, ctx, prec, V0, args.steps, args.warmup)
         results[leg] = dict(seconds=dt, prof=prof, state=st)
+    ctx.set_vsym(True)
     batch = None
     if "batch" in legs:
         # batched workload at N = 96: (mu, t', U) from the seeded draws of the batched configuration
         draws = I.c4_flows(n_per_N=args.batch_flows, Ns=(96,), n_rad=p["n_rad"], n_ang=p["n_ang"])
         b = frg.Batch(draws)
+        b.set_vsym(True)
         sym = b.symmetry()
         Vs = [torch.full((N, N, N), float(d["U"]), dtype=torch.float64, device="cuda") for d in draws]
         o = frg.flow_opts("dp54", frg.PREC_SPLIT_BF16, T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10,
@@ -203,8 +218,11 @@ def main():
         "dtype": "bf16x3-fp32" if "split" in results else "f64",
         "data": "synthetic",
         "config": {"workload": "hubbard-2d N=96 patches, 512 fine points/patch (32x16), "
-                               "t'=-0.3 mu=-1.2 U=3, DP5(4) temperature flow step (6 rhs)",
-                   "N": N, "n_f": nf, "rhs_per_step": RHS_PER_STEP, "parallelism": "1 GPU"},
+                               "t'=-0.3 mu=-1.2 U=3, DP5(4) temperature flow step (6 rhs) from V=U",
+                   "N": N, "n_f": nf, "rhs_per_step": RHS_PER_STEP, "parallelism": "1 GPU",
+                   "symmetry": f"C4v: bubble rows per transfer orbit; vertex C4v invariant, "
+                               f"{vsym_cols} of {N * N} columns per channel computed "
+                               f"({vsym_cols * N} independent entries; split_full computes all)"},
     }
     for leg, r in results.items():
         rps = RHS_PER_STEP * args.steps / r["seconds"]
@@ -230,6 +248,9 @@ def main():
                            "frac": None, "traffic": None, "note": "needs a single-flow leg"}
     else:
         out["roofline"] = roofline(head, results, algo_flops, dense_flops, exec_share, evals_per_rhs)
+        if out["roofline"]["kernel"] != "contract":
+            out["contract_roofline"] = roofline(head, results, algo_flops, dense_flops, exec_share,
+                                                evals_per_rhs, kernel="contract")
 
     if not args.no_cpu_baseline:
         import oracle as O
