@@ -138,16 +138,24 @@ def main():
     ctx = frg.Context(**p)
     V0 = torch.full((N, N, N), float(p["U"]), dtype=torch.float64, device="cuda")
 
-    # algorithmic work per launch (T independent): bubble-row occupancy from one sweep
-    Bpp, Bph = ctx.bubbles(0.05, frg.PREC_SPLIT_BF16)
-    nnz_pp = (Bpp != 0).sum(dim=(1, 2)).to(torch.float64)
-    nnz_ph = (Bph != 0).sum(dim=(1, 2)).to(torch.float64)
+    # algorithmic work per launch (T independent): bubble-row occupancy, i.e. the
+    # (a, b) pairs of row t for which some fine point of patch a has its second
+    # line in patch b (the structurally nonzero entries), counted from the
+    # second-line tables so that no extra bubble sweep enters the profile
+    def occupancy(kind):
+        bins = ctx.bins(kind).to(torch.int64)
+        rows = bins.shape[0]
+        patch = torch.arange(N * nf, device="cuda") // nf
+        key = (torch.arange(rows, device="cuda")[:, None] * N + patch[None, :]) * N + bins
+        hit = torch.zeros(rows * N * N, dtype=torch.bool, device="cuda")
+        hit[key.reshape(-1)] = True
+        return hit.reshape(rows, N * N).sum(dim=1).to(torch.float64)
+    nnz_pp, nnz_ph = occupancy(1), occupancy(0)
     rows_pp = torch.tensor([[min(i, j) * N - min(i, j) * (min(i, j) - 1) // 2 + abs(i - j)
                              for j in range(N)] for i in range(N)], device="cuda").reshape(-1)
     colsum_pp = float(nnz_pp[rows_pp].sum())
     # ph column (y, x) uses row of Q = k_x - k_y; every ordered pair occurs once, x == y uses row 0
     colsum_ph = float(nnz_ph[1:].sum() + N * nnz_ph[0])
-    del Bpp, Bph
     # pp: one product per column, phc: one, phd: two (N output rows each); with a
     # C4v-invariant vertex only one column per orbit is needed (every column of an
     # orbit has the same bubble-row occupancy)
