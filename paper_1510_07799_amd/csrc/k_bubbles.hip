@@ -15,8 +15,8 @@
 // independent; eps(second line) uses cos(q -/+ p) = cos q cos p +/- sin q sin p.
 //
 // FP64 path: everything in double.  Split path: eps in double (its absolute
-// error is divided by 2T), the integrand in FP32 with hardware exp/rcp, runs
-// and bins accumulated in double, output float.
+// error is divided by 2T), the integrand in FP32 with hardware exp2/rcp, runs
+// of at most P points summed in FP32, bins accumulated in double, output float.
 #include <cmath>
 #include <type_traits>
 
@@ -29,41 +29,61 @@ namespace {
 constexpr int kRowsPerBlock = 64;   // 16 rows per wave
 constexpr int kThreads = 256;
 
-// divided difference of h(x) = x sech^2 x, with the Taylor form near x = y
+// Divided difference (h(a) - h(b)) / (a - b) of h(x) = x sech^2 x, with its
+// Taylor form h1(m) + d^2 h3(m) / 24 around m = (a + b) / 2 when d = a - b is
+// small (h1, h3: first and third derivatives).  With e = exp(-2|x|),
+// sech^2 x = 4e / (1 + e)^2 and tanh x = sign(x) (1 - e) / (1 + e); away from the
+// diagonal the difference is taken over one common denominator,
+// (ha (1+e)^2 - 4 b e) / ((1+e)^2 d), so that one division (one reciprocal in
+// FP32) serves it.
 __device__ __forceinline__ double div_h64(double a, double ha, double b) {
     const double d = a - b;
     if (fabs(d) < 2e-3) {
         const double m = 0.5 * (a + b);
         const double e = exp(-2.0 * fabs(m));
-        const double q = 1.0 + e;
-        const double S = 4.0 * e / (q * q);
-        const double tau = copysign((1.0 - e) / q, m);
+        const double r = 1.0 / (1.0 + e);
+        const double S = 4.0 * e * r * r;
+        const double tau = copysign((1.0 - e) * r, m);
         const double h1 = S * (1.0 - 2.0 * m * tau);
-        const double h3 = 12.0 * S - 18.0 * S * S - 8.0 * m * S * tau * (1.0 - 3.0 * S);
+        const double h3 = S * (12.0 - 18.0 * S - 8.0 * m * tau * (1.0 - 3.0 * S));
         return h1 + d * d * h3 / 24.0;
     }
     const double e = exp(-2.0 * fabs(b));
     const double q = 1.0 + e;
-    const double hb = b * (4.0 * e / (q * q));
-    return (ha - hb) / d;
+    const double q2 = q * q;
+    return fma(ha, q2, -4.0 * b * e) / (q2 * d);
 }
 
+// FP32 form of div_h64 with hardware exp2 and reciprocal.  The Taylor form is
+// used for |d| < 0.02: its truncation (the d^4 term, h5 / 1920) stays below
+// 1e-8 there, and the common-denominator form beyond it loses at most about
+// 2e-7 / |d| < 1e-5 (absolute) to the rounding of ha and of the exponential.
+constexpr float kTaylor32 = 0.02f;
+constexpr float kM2Log2e = -2.8853900817779268f;   // -2 / ln 2: exp(-2x) = exp2(kM2Log2e x)
 __device__ __forceinline__ float div_h32(float a, float ha, float b) {
     const float d = a - b;
-    if (fabsf(d) < 0.1f) {
+    if (fabsf(d) < kTaylor32) {
         const float m = 0.5f * (a + b);
-        const float e = __expf(-2.0f * fabsf(m));
-        const float q = 1.0f + e;
-        const float S = 4.0f * e * __builtin_amdgcn_rcpf(q * q);
-        const float tau = copysignf((1.0f - e) * __builtin_amdgcn_rcpf(q), m);
+        const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(m));
+        const float r = __builtin_amdgcn_rcpf(1.0f + e);
+        const float S = 4.0f * e * r * r;
+        const float tau = copysignf((1.0f - e) * r, m);
         const float h1 = S * (1.0f - 2.0f * m * tau);
-        const float h3 = 12.0f * S - 18.0f * S * S - 8.0f * m * S * tau * (1.0f - 3.0f * S);
-        return h1 + d * d * h3 * (1.0f / 24.0f);
+        const float h3 = S * (12.0f - 18.0f * S - 8.0f * m * tau * (1.0f - 3.0f * S));
+        return fmaf(d * d, h3 * (1.0f / 24.0f), h1);
     }
-    const float e = __expf(-2.0f * fabsf(b));
+    const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(b));
     const float q = 1.0f + e;
-    const float hb = b * (4.0f * e * __builtin_amdgcn_rcpf(q * q));
-    return (ha - hb) * __builtin_amdgcn_rcpf(d);
+    const float q2 = q * q;
+    return fmaf(ha, q2, -4.0f * b * e) * __builtin_amdgcn_rcpf(q2 * d);
+}
+
+// a wave-uniform double held in scalar registers
+__device__ __forceinline__ double uniform_f64(double x) {
+    const uint64_t u = __double_as_longlong(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+    return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
 }
 
 // order the LDS accesses of one wave (its bins are private to it)
@@ -137,8 +157,10 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             return pt[q * S + j * 64 + lane];
         }
     };
+    // eps / 2T = K1 (cx + cy) - K2 cx cy - K3, computed once and kept in scalar registers
     const double inv2T = A.Tdev[1];
-    const double mt2 = A.mt2, mt4p = A.mt4p, mu = A.mu;
+    const double K1 = uniform_f64(A.mt2 * inv2T), K2 = uniform_f64(A.mt4p * inv2T),
+                 K3 = uniform_f64(A.mu * inv2T);
     // second-line patches of the lane's points: one P-byte load when aligned
     const bool vec_bins = (nf % P) == 0 && (P == 4 || P == 8 || P == 16);
 
@@ -146,11 +168,18 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     for (int rr = wave; rr < kRowsPerBlock; rr += 4) {
         const int slot_out = row0 + rr;                 // output row position (wave-uniform)
         if (slot_out >= A.nrows) break;
-        const int r = A.rowlist ? A.rowlist[slot_out] : slot_out;   // transfer row
+        // transfer row (wave-uniform: kept in scalar registers with its constants)
+        const int r = __builtin_amdgcn_readfirstlane(A.rowlist ? A.rowlist[slot_out] : slot_out);
         for (int b = lane; b < N; b += 64) bins[b] = 0.0;
+        // Row-uniform factors.  pp: cos(q - p) = cos q cos p + sin q sin p and the
+        // second line enters as -eps / 2T; ph: cos(p + Q) = cos p cos Q - sin p sin Q
+        // and +eps / 2T.  Both signs are folded into the row's constants, so a
+        // point costs b = k1 (cx + cy) - k2 cx cy - k3 with cx = cqx cos px + sx sin px.
         const bool pp = r < A.Tpp;
-        const double cqx = A.trig_row[4 * r], sqx = A.trig_row[4 * r + 1];
-        const double cqy = A.trig_row[4 * r + 2], sqy = A.trig_row[4 * r + 3];
+        const double cqx = A.trig_row[4 * r], cqy = A.trig_row[4 * r + 2];
+        const double sx = pp ? A.trig_row[4 * r + 1] : -A.trig_row[4 * r + 1];
+        const double sy = pp ? A.trig_row[4 * r + 3] : -A.trig_row[4 * r + 3];
+        const double k1 = pp ? -K1 : K1, k2 = pp ? -K2 : K2, k3 = pp ? -K3 : K3;
         const uint8_t *brow = A.bins + static_cast<size_t>(r) * np + static_cast<size_t>(a_patch) * nf;
         uint8_t bn[P];
         if (vec_bins && lane * P < nf) {
@@ -172,41 +201,32 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
         }
         wave_sync();
         int bcur = -1;
-        double acc64 = 0.0;
+        PT acc = PT(0);
+        // padding points (past n_f) carry zero weight and bin 0: no test needed
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-            if (lane * P + j < nf) {
-                const double c_px = pval(0, j), s_px = pval(1, j), c_py = pval(2, j), s_py = pval(3, j);
-                double cx, cy;
-                if (pp) {   // cos(q - p)
-                    cx = cqx * c_px + sqx * s_px;
-                    cy = cqy * c_py + sqy * s_py;
-                } else {    // cos(p + Q)
-                    cx = c_px * cqx - s_px * sqx;
-                    cy = c_py * cqy - s_py * sqy;
-                }
-                const double xi2 = mt2 * (cx + cy) - mt4p * (cx * cy) - mu;
-                double b2 = xi2 * inv2T;
-                if (pp) b2 = -b2;
-                const int bin = bn[j];
-                double v;
-                if (F32)
-                    v = static_cast<double>(static_cast<float>(pval(6, j)) *
-                                            div_h32(static_cast<float>(pval(4, j)), static_cast<float>(pval(5, j)),
-                                                    static_cast<float>(b2)));
-                else
-                    v = pval(6, j) * div_h64(pval(4, j), pval(5, j), b2);
-                // runs of equal bin summed in FP64 in registers, one LDS add per run
-                if (bin != bcur) {
-                    if (bcur >= 0) atomicAdd(&bins[bcur], acc64);
-                    bcur = bin;
-                    acc64 = v;
-                } else {
-                    acc64 += v;
-                }
+            const double cx = cqx * pval(0, j) + sx * pval(1, j);
+            const double cy = cqy * pval(2, j) + sy * pval(3, j);
+            const double b2 = k1 * (cx + cy) - k2 * (cx * cy) - k3;
+            const int bin = bn[j];
+            PT v;
+            if constexpr (F32)
+                v = static_cast<float>(pval(6, j)) *
+                    div_h32(static_cast<float>(pval(4, j)), static_cast<float>(pval(5, j)),
+                            static_cast<float>(b2));
+            else
+                v = pval(6, j) * div_h64(pval(4, j), pval(5, j), b2);
+            // runs of equal bin summed in registers (at most P terms), one
+            // FP64 LDS add per run
+            if (bin != bcur) {
+                if (bcur >= 0) atomicAdd(&bins[bcur], static_cast<double>(acc));
+                bcur = bin;
+                acc = v;
+            } else {
+                acc += v;
             }
         }
-        if (bcur >= 0) atomicAdd(&bins[bcur], acc64);
+        if (bcur >= 0) atomicAdd(&bins[bcur], static_cast<double>(acc));
         wave_sync();
         const size_t NN = static_cast<size_t>(N) * N;
         const bool pp_out = slot_out < A.npp_out;
