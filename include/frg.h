@@ -143,7 +143,8 @@ frg_status frg_host_tables(const frg_params *p, double *kc, double *bnd, double 
                            double *qpp, double *qph, int32_t *idx4);
 
 /* Copy the device table of second-line patches (kind 0 = ph, 1 = pp) into
- * d_out[rows][N*n_f] (uint8). */
+ * d_out[rows][N*n_f] (uint8), points in the fine-grid order of frg_tables
+ * (the device keeps each patch's points in its own order). */
 frg_status frg_bins(frg_ctx ctx, int32_t kind, uint8_t *d_out, void *stream);
 
 /* Bubble derivatives at temperature T > 0 (Sec. 4: the three one-loop

@@ -195,6 +195,8 @@ frg::BubbleArgs bubble_args(frg_ctx ctx, bool fp32, void *bpp, void *bph) {
     a.N = g.N;
     a.nf = g.nf;
     a.np = g.np;
+    a.n_rad = g.n_rad;
+    a.n_ang = g.n_ang;
     a.Tpp = g.Tpp;
     a.Trows = ctx->Trows;
     a.mt2 = -2.0 * g.t;
@@ -793,7 +795,8 @@ static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out) {
         return bail(st);
     }
     tmp_bytes = sizeof(double) * (2 * g.np + qrow.size());
-    frg::launch_bins(ctx->d_bnd, d_px, d_py, d_qrow, g.N, g.np, g.Tpp, ctx->Trows, ctx->d_bins, nullptr);
+    frg::launch_bins(ctx->d_bnd, d_px, d_py, d_qrow, g.N, g.n_rad, g.n_ang, g.Tpp, ctx->Trows, ctx->d_bins,
+                     nullptr);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipDeviceSynchronize();
     hipFree(d_px);
@@ -886,10 +889,9 @@ frg_status frg_bins(frg_ctx ctx, int32_t kind, uint8_t *d_out, void *stream) {
     if (!d_out) return fail(FRG_EINVAL, "null output");
     if (kind != 0 && kind != 1) return fail(FRG_EINVAL, "kind must be 0 (ph) or 1 (pp)");
     const auto &g = ctx->g;
-    const size_t off = kind == 1 ? 0 : static_cast<size_t>(g.Tpp) * g.np;
-    const size_t n = static_cast<size_t>(kind == 1 ? g.Tpp : g.Tph) * g.np;
-    HIPCHK(hipMemcpyAsync(d_out, ctx->d_bins + off, n, hipMemcpyDeviceToDevice,
-                          static_cast<hipStream_t>(stream)));
+    frg::launch_bins_export(ctx->d_bins, g.N, g.n_rad, g.n_ang, kind == 1 ? 0 : g.Tpp, kind == 1 ? g.Tpp : g.Tph,
+                            d_out, static_cast<hipStream_t>(stream));
+    HIPCHK(hipGetLastError());
     return FRG_OK;
 }
 

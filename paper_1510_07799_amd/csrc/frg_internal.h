@@ -28,9 +28,14 @@ int32_t host_patch(const Geometry &g, double kx, double ky);
 void host_idx4(const Geometry &g, int32_t *out);
 
 // ----------------------------------------------------------------- launchers
-// second-line patch of every (row, point); rows: pp rows then ph rows
+// second-line patch of every (row, point); rows: pp rows then ph rows.  Within
+// a row each patch's points are stored angular-fastest: fine point (s, m) of
+// patch a (fine-grid index a*n_f + s*n_rad + m) at a*n_f + m*n_ang + s
 void launch_bins(const double *bnd, const double *px, const double *py, const double *qrow,
-                 int N, int np, int Tpp, int Trows, uint8_t *bins, hipStream_t s);
+                 int N, int n_rad, int n_ang, int Tpp, int Trows, uint8_t *bins, hipStream_t s);
+// rows r0 .. r0 + nrows - 1 of the table copied out in fine-grid order
+void launch_bins_export(const uint8_t *bins, int N, int n_rad, int n_ang, int r0, int nrows, uint8_t *out,
+                        hipStream_t s);
 
 // per-point temperature-dependent factors (a = xi/2T, h(a), -w/4T^2); T is
 // either T_host, or exp(state[s] + c*state[h]) when state != nullptr
@@ -40,8 +45,9 @@ void launch_point_prep(const double *xi, const double *w, int np, double T_host,
 
 struct BubbleArgs {
     int N, nf, np, Tpp, Trows;
+    int n_rad, n_ang;              // fine grid of a patch (n_f = n_rad * n_ang)
     double mt2, mt4p, mu;          // -2t, 4t', mu
-    const uint8_t *bins;           // [Trows][np]
+    const uint8_t *bins;           // [Trows][np], patches' points angular-fastest
     const double *trig_row;        // [Trows][4]: cos qx, sin qx, cos qy, sin qy
     const double *trig_pt;         // [4][np]: cos px, sin px, cos py, sin py
     const double *pa64;            // [3][np]: a, h(a), -w/4T^2   (FP64 path)

@@ -5,14 +5,15 @@
 // here each transfer's bubble row is shared by every vertex entry that uses it).
 //
 // Work decomposition: one block per (patch a, chunk of rows); lane L holds the
-// P consecutive fine points L*P .. L*P+P-1 of the patch (radially adjacent,
-// so mostly one bin) in registers for all rows, and each wave sweeps whole
-// rows independently (in the FP64 path the points sit in LDS instead, to keep
-// the register count down): it accumulates runs of equal bin in registers, flushes
-// each run into the wave's private LDS bins with one LDS add, and writes the
-// row B_row(a, 0..N-1) with coalesced stores (no block-wide barriers).  The bin table (one byte per
-// evaluation) and the cos/sin of points and transfers are temperature
-// independent; eps(second line) uses cos(q -/+ p) = cos q cos p +/- sin q sin p.
+// P fine points at table positions L*P .. L*P+P-1 of the patch (angular
+// neighbours at one radius, so mostly one bin) in registers for all rows, and
+// each wave sweeps whole rows independently (in the FP64 path the points sit in
+// LDS instead, to keep the register count down): it accumulates runs of equal
+// bin in registers, flushes each run into the wave's private LDS bins with one
+// LDS add, and writes the row B_row(a, 0..N-1) with coalesced stores (no
+// block-wide barriers).  The bin table (one byte per evaluation) and the cos/sin
+// of points and transfers are temperature independent; eps(second line) uses
+// cos(q -/+ p) = cos q cos p +/- sin q sin p.
 //
 // FP64 path: everything in double.  Split path: eps in double (its absolute
 // error is divided by 2T), the integrand in FP32 with hardware exp2/rcp, runs
@@ -122,9 +123,9 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     if constexpr (REG) {
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-            const int k = lane * P + j;
+            const int k = lane * P + j;   // table position; fine point (s, m) = (k % n_ang, k / n_ang)
             const bool ok = k < nf;
-            const int i = a_patch * nf + (ok ? k : 0);
+            const int i = a_patch * nf + (ok ? (k % A.n_ang) * A.n_rad + k / A.n_ang : 0);
             cpx[j] = ok ? A.trig_pt[i] : 1.0;
             spx[j] = ok ? A.trig_pt[np + i] : 0.0;
             cpy[j] = ok ? A.trig_pt[2 * np + i] : 1.0;
@@ -137,7 +138,7 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
         for (int k = threadIdx.x; k < S; k += kThreads) {
             const int slot = (k % P) * 64 + k / P;
             const bool ok = k < nf;
-            const int i = a_patch * nf + (ok ? k : 0);
+            const int i = a_patch * nf + (ok ? (k % A.n_ang) * A.n_rad + k / A.n_ang : 0);
             pt[0 * S + slot] = ok ? A.trig_pt[i] : 1.0;
             pt[1 * S + slot] = ok ? A.trig_pt[np + i] : 0.0;
             pt[2 * S + slot] = ok ? A.trig_pt[2 * np + i] : 1.0;

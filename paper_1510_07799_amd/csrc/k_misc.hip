@@ -45,11 +45,25 @@ __device__ int dev_patch(const double *bnd, int N, double kx, double ky) {
     return 0;
 }
 
+// The table keeps each patch's points in angular-fastest order: fine point
+// (s, m) of patch a (sub-ray s, radius m; fine-grid index a*n_f + s*n_rad + m)
+// sits at a*n_f + m*n_ang + s.  A lane of the bubble sweep takes consecutive
+// entries, i.e. angular neighbours at one radius, whose second lines mostly
+// share a patch.
+__device__ __forceinline__ int bin_slot(int i, int n_rad, int n_ang) {
+    const int nf = n_rad * n_ang;
+    const int a = i / nf, loc = i - a * nf;
+    const int s = loc / n_rad, m = loc - s * n_rad;
+    return a * nf + m * n_ang + s;
+}
+
 __global__ void bins_kernel(const double *__restrict__ bnd, const double *__restrict__ px,
                             const double *__restrict__ py, const double *__restrict__ qrow,
-                            int N, int np, int Tpp, int Trows, uint8_t *__restrict__ bins) {
+                            int N, int n_rad, int n_ang, int Tpp, int Trows, uint8_t *__restrict__ bins) {
+    const int np = N * n_rad * n_ang;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= np) return;
+    const int slot = bin_slot(i, n_rad, n_ang);
     for (int r = blockIdx.y; r < Trows; r += gridDim.y) {
         const double qx = qrow[2 * r], qy = qrow[2 * r + 1];
         double kx, ky;
@@ -60,8 +74,19 @@ __global__ void bins_kernel(const double *__restrict__ bnd, const double *__rest
             kx = dev_fold(px[i] + qx);
             ky = dev_fold(py[i] + qy);
         }
-        bins[static_cast<size_t>(r) * np + i] = static_cast<uint8_t>(dev_patch(bnd, N, kx, ky));
+        bins[static_cast<size_t>(r) * np + slot] = static_cast<uint8_t>(dev_patch(bnd, N, kx, ky));
     }
+}
+
+// the table in fine-grid order (rows r0 .. r0 + nrows - 1)
+__global__ void bins_export_kernel(const uint8_t *__restrict__ bins, int N, int n_rad, int n_ang, int r0,
+                                   int nrows, uint8_t *__restrict__ out) {
+    const int np = N * n_rad * n_ang;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= np) return;
+    const int slot = bin_slot(i, n_rad, n_ang);
+    for (int r = blockIdx.y; r < nrows; r += gridDim.y)
+        out[static_cast<size_t>(r) * np + i] = bins[static_cast<size_t>(r0 + r) * np + slot];
 }
 
 // image of patch j under C4v element o (o even: rotation by o/2 quarter
@@ -88,8 +113,8 @@ __global__ void sym_check_kernel(const uint8_t *__restrict__ bins, const int32_t
         const int oinv = (o & 1) ? o : ((8 - o) & 7);
         const int a = c4v_patch(oinv, a1, N);
         const int s = (o & 1) ? n_ang - 1 - s1 : s1;
-        const int b = bins[static_cast<size_t>(rep) * np + a * nf + s * n_rad + m];
-        if (bins[static_cast<size_t>(t) * np + ip] != c4v_patch(o, b, N)) ++bad;
+        const int b = bins[static_cast<size_t>(rep) * np + a * nf + m * n_ang + s];
+        if (bins[static_cast<size_t>(t) * np + a1 * nf + m * n_ang + s1] != c4v_patch(o, b, N)) ++bad;
     }
     if (bad) atomicAdd(mismatch, bad);
 }
@@ -717,10 +742,19 @@ inline unsigned blocks_for(int64_t n, int bs) { return static_cast<unsigned>((n 
 }  // namespace
 
 void launch_bins(const double *bnd, const double *px, const double *py, const double *qrow,
-                 int N, int np, int Tpp, int Trows, uint8_t *bins, hipStream_t s) {
+                 int N, int n_rad, int n_ang, int Tpp, int Trows, uint8_t *bins, hipStream_t s) {
+    const int np = N * n_rad * n_ang;
     dim3 grid(blocks_for(np, 256), Trows < 65535 ? Trows : 65535);
-    hipLaunchKernelGGL(bins_kernel, grid, dim3(256), 0, s, bnd, px, py, qrow, N, np, Tpp, Trows,
+    hipLaunchKernelGGL(bins_kernel, grid, dim3(256), 0, s, bnd, px, py, qrow, N, n_rad, n_ang, Tpp, Trows,
                        bins);
+}
+
+void launch_bins_export(const uint8_t *bins, int N, int n_rad, int n_ang, int r0, int nrows, uint8_t *out,
+                        hipStream_t s) {
+    const int np = N * n_rad * n_ang;
+    if (nrows <= 0) return;
+    dim3 grid(blocks_for(np, 256), nrows < 65535 ? nrows : 65535);
+    hipLaunchKernelGGL(bins_export_kernel, grid, dim3(256), 0, s, bins, N, n_rad, n_ang, r0, nrows, out);
 }
 
 void launch_sym_check(const uint8_t *bins, const int32_t *orbit, int N, int n_rad, int n_ang,
