@@ -1165,8 +1165,8 @@ struct frg_batch_s {
     double **d_states = nullptr;
     double *d_state_all = nullptr, *h_state_all = nullptr;
     int2 *d_it_prep = nullptr, *d_it_bub = nullptr, *d_it_n3 = nullptr, *d_it_red = nullptr,
-         *d_it_con = nullptr, *d_it_comb = nullptr, *d_it_sum = nullptr;
-    int n_prep = 0, n_bub = 0, n_n3 = 0, n_red = 0, n_con = 0, n_comb = 0, n_sum = 0;
+         *d_it_con = nullptr, *d_it_comb = nullptr, *d_it_sum = nullptr, *d_it_lay = nullptr;
+    int n_prep = 0, n_bub = 0, n_n3 = 0, n_red = 0, n_con = 0, n_comb = 0, n_sum = 0, n_lay = 0;
     // contraction work list grouped by block height class (32, 64, 96), each cut
     // into 8 per-XCD queues: d_q[class] = {start[8], count[8]}
     int con_count[3] = {0, 0, 0};
@@ -1210,7 +1210,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     std::vector<frg::FusedContractArgs> ca[3];
     for (int s = 0; s < 3; ++s) ca[s].resize(b->n);
     std::vector<double *> st(b->n);
-    std::vector<int2> it_prep, it_bub, it_n3, it_red, it_comb, it_sum;
+    std::vector<int2> it_prep, it_bub, it_n3, it_red, it_comb, it_sum, it_lay;
     struct Item { int2 it; int cls, queue; double flow_cost, cost; };
     std::vector<Item> con;
     for (int f = 0; f < b->n; ++f) {
@@ -1274,6 +1274,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         for (int ch = 0; ch < chunks; ++ch)
             for (int a = 0; a < g.N; ++a) it_bub.push_back(make_int2(f, (ch << 8) | a));
         for (int64_t k = 0; k < (n3 + 255) / 256; ++k) it_n3.push_back(make_int2(f, static_cast<int>(k)));
+        for (int k = 0; k < frg::layout_blocks(g.N); ++k) it_lay.push_back(make_int2(f, k));
         for (int k = 0; k < frg::combine_tiles(g.N); ++k) it_comb.push_back(make_int2(f, k));
         for (int64_t k = 0; k < (3 * A.nel + frg::kSumPartsPerBlock - 1) / frg::kSumPartsPerBlock; ++k)
             it_sum.push_back(make_int2(f, static_cast<int>(k)));
@@ -1345,6 +1346,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     TRY(bupload(&b->d_it_con, it_con));
     TRY(bupload(&b->d_it_comb, it_comb));
     TRY(bupload(&b->d_it_sum, it_sum));
+    TRY(bupload(&b->d_it_lay, it_lay));
     b->n_prep = static_cast<int>(it_prep.size());
     b->n_bub = static_cast<int>(it_bub.size());
     b->n_n3 = static_cast<int>(it_n3.size());
@@ -1352,6 +1354,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     b->n_con = static_cast<int>(it_con.size());
     b->n_comb = static_cast<int>(it_comb.size());
     b->n_sum = static_cast<int>(it_sum.size());
+    b->n_lay = static_cast<int>(it_lay.size());
     b->built_prec = prec;
     if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; b->exec_prec = -1; }
     return FRG_OK;
@@ -1362,7 +1365,7 @@ void batch_rhs_launch(frg_batch b, bool split, double c_stage, int src, int stag
     const double *const *states = b->d_states;
     frg::launch_prep_b(b->d_fa, b->d_it_prep, b->n_prep, c_stage, split, s);
     frg::launch_bubbles_batched(b->d_ba, b->d_it_bub, b->n_bub, states, b->nf, b->maxN, split, s);
-    frg::launch_layout_b(b->d_fa, b->d_it_n3, b->n_n3, src, split, s);
+    frg::launch_layout_b(b->d_fa, b->d_it_lay, b->n_lay, src, split, s);
     const int bms[3] = {32, 64, 96};
     for (int k = 2; k >= 0; --k) {
         if (!b->con_count[k]) continue;
@@ -1452,7 +1455,7 @@ frg_status frg_batch_destroy(frg_batch b) {
     for (frg_ctx c : b->ctx) frg_destroy(c);
     void *ptrs[] = {b->d_fa, b->d_ba, b->d_ca[0], b->d_ca[1], b->d_ca[2], b->d_states, b->d_state_all,
                     b->d_it_prep, b->d_it_bub, b->d_it_n3, b->d_it_red, b->d_it_con, b->d_counter,
-                    b->d_q, b->d_it_flat, b->d_it_comb, b->d_it_sum};
+                    b->d_q, b->d_it_flat, b->d_it_comb, b->d_it_sum, b->d_it_lay};
     for (void *p : ptrs)
         if (p) hipFree(p);
     if (b->h_state_all) hipHostFree(b->h_state_all);

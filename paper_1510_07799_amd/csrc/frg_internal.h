@@ -71,6 +71,7 @@ void launch_sym_check(const uint8_t *bins, const int32_t *orbit, int N, int n_ra
 void launch_layout_f64(const double *V, int N, double *perm, hipStream_t s);
 // split-BF16 operands: hi/lo of the four A matrices + FP32 gather tables
 void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipStream_t s);
+int layout_blocks(int N);   // blocks (of 256 threads) of one layout pass
 
 enum Term { TERM_PP = 0, TERM_PHC = 1, TERM_PHD = 2,
             TERM_PH = 3 };   // TERM_PH: phc and phd in one block (split path)
@@ -202,6 +203,7 @@ void launch_contract_persistent(const FusedContractArgs *args, const int2 *items
                                 int bm, bool split, hipStream_t s);
 void launch_prep_b(const FlowArgs *fa, const int2 *items, int nitems, double c_stage, bool split,
                    hipStream_t s);
+// items: (flow, block < layout_blocks(N) of the flow)
 void launch_layout_b(const FlowArgs *fa, const int2 *items, int nitems, int src, bool split,
                      hipStream_t s);
 void launch_combine_b(const FlowArgs *fa, const int2 *items, int nitems, int stage, hipStream_t s);

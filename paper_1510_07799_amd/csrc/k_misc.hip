@@ -167,32 +167,17 @@ __global__ void point_prep_kernel(const double *__restrict__ xi, const double *_
 //                                              and y = i, (a, b) = (j, k))
 //   split: ahl = the four A blocks as bf16 hi, lo ([4][2][N^3], chunk-major);
 //          g32 = [V (pp gather), block 4, block 5] in FP32.
-__device__ __forceinline__ int64_t chunk_major(int64_t idx, int N) {
-    const int64_t K = static_cast<int64_t>(N) * N;
-    const int64_t i = idx / K, kk = idx - i * K;
-    return ((kk >> 3) * N + i) * 8 + (kk & 7);
-}
-
-__device__ __forceinline__ void layout_f64_elem(const double *__restrict__ V, int N, int64_t n3, int64_t idx,
-                                                double *__restrict__ perm) {
-    const int k = static_cast<int>(idx % N);
-    const int j = static_cast<int>((idx / N) % N);
-    const int i = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
-    auto at = [&](int x, int y, int z) { return V[(static_cast<int64_t>(x) * N + y) * N + z]; };
-    const int64_t cm = chunk_major(idx, N);
-    perm[cm] = at(j, k, i);
-    perm[n3 + cm] = at(i, j, k);
-    perm[2 * n3 + cm] = -2.0 * at(j, i, k) + at(i, j, k);
-    perm[3 * n3 + cm] = at(j, i, k);
-    perm[4 * n3 + idx] = at(k, i, j);
-    perm[5 * n3 + idx] = at(i, k, j);
-}
-
-__global__ void layout_f64_kernel(const double *__restrict__ V, int N, double *__restrict__ perm) {
-    const int64_t n3 = static_cast<int64_t>(N) * N * N;
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx < n3) layout_f64_elem(V, N, n3, idx, perm);
-}
+//
+// One layout pass is a grid of layout_blocks(N) blocks of 256 threads:
+//  - A part: a thread makes one (chunk c, row i) run of 8 entries of every A
+//    operand (i fastest, so a wave's stores are contiguous).  pp reads
+//    V[kk][i] (coalesced across the rows i); phc and phd read 8 consecutive
+//    entries of a row of V.  The split path also writes the pp gather table
+//    (a copy of V in FP32) from the phc reads.
+//  - gather part: 32 x 32 tiles transposed through LDS, block 4 as the
+//    transpose of V seen as [k][(i, j)], block 5 per i as that of V[i] seen as
+//    [k][j].
+constexpr int kLayoutTile = 32;
 
 __device__ __forceinline__ uint16_t bf16_rne(float x) {
     uint32_t u = __float_as_uint(x);
@@ -203,32 +188,149 @@ __device__ __forceinline__ float bf16_to_f(uint16_t h) {
     return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
 
-__device__ __forceinline__ void layout_split_elem(const double *__restrict__ V, int N, int64_t n3, int64_t idx,
-                                                  uint16_t *__restrict__ ahl, float *__restrict__ g32) {
-    const int k = static_cast<int>(idx % N);
-    const int j = static_cast<int>((idx / N) % N);
-    const int i = static_cast<int>(idx / (static_cast<int64_t>(N) * N));
-    auto at = [&](int x, int y, int z) { return V[(static_cast<int64_t>(x) * N + y) * N + z]; };
-    const float ops[4] = {static_cast<float>(at(j, k, i)), static_cast<float>(at(i, j, k)),
-                          static_cast<float>(-2.0 * at(j, i, k) + at(i, j, k)),
-                          static_cast<float>(at(j, i, k))};
-    const int64_t cm = chunk_major(idx, N);
+__host__ __device__ __forceinline__ int layout_a_blocks(int N) {
+    return static_cast<int>((static_cast<int64_t>(N) * N * N / 8 + 255) / 256);
+}
+__host__ __device__ __forceinline__ int layout_t_tiles(int N) { return (N + kLayoutTile - 1) / kLayoutTile; }
+
+// A operands of chunk c, row i
+template <bool SPLIT>
+__device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int N, int64_t n3, int64_t u,
+                                              uint16_t *__restrict__ ahl, float *__restrict__ g32,
+                                              double *__restrict__ perm) {
+    const int64_t NN = static_cast<int64_t>(N) * N;
+    const int i = static_cast<int>(u % N);
+    const int64_t c = u / N;
+    const int64_t kk0 = 8 * c;
+    double pp[8], phc[8], phd[8];
+    const double *vrow = V + i * NN + kk0;
+    if (N % 8 == 0) {   // the chunk lies in one j row: contiguous 64-byte runs
+        const int j = static_cast<int>(kk0 / N), k0 = static_cast<int>(kk0 - static_cast<int64_t>(j) * N);
+        const double *drow = V + (static_cast<int64_t>(j) * N + i) * N + k0;
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-        const uint16_t hi = bf16_rne(ops[o]);
-        ahl[(2 * o) * n3 + cm] = hi;
-        ahl[(2 * o + 1) * n3 + cm] = bf16_rne(ops[o] - bf16_to_f(hi));
+        for (int t = 0; t < 8; t += 2) {
+            const double2 a = *reinterpret_cast<const double2 *>(vrow + t);
+            const double2 b = *reinterpret_cast<const double2 *>(drow + t);
+            phc[t] = a.x; phc[t + 1] = a.y;
+            phd[t] = b.x; phd[t + 1] = b.y;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int64_t kk = kk0 + t;
+            const int64_t j = kk / N, k = kk - j * N;
+            phc[t] = vrow[t];
+            phd[t] = V[(j * N + i) * N + k];
+        }
     }
-    g32[idx] = static_cast<float>(at(i, j, k));
-    g32[n3 + idx] = static_cast<float>(at(k, i, j));
-    g32[2 * n3 + idx] = static_cast<float>(at(i, k, j));
+#pragma unroll
+    for (int t = 0; t < 8; ++t) pp[t] = V[(kk0 + t) * N + i];
+    const int64_t cm = (c * N + i) * 8;
+    if constexpr (SPLIT) {
+        float ops[4][8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            ops[0][t] = static_cast<float>(pp[t]);
+            ops[1][t] = static_cast<float>(phc[t]);
+            ops[2][t] = static_cast<float>(-2.0 * phd[t] + phc[t]);
+            ops[3][t] = static_cast<float>(phd[t]);
+        }
+#pragma unroll
+        for (int o = 0; o < 4; ++o) {
+            uint32_t hw[4], lw[4];
+#pragma unroll
+            for (int t = 0; t < 8; t += 2) {
+                const uint16_t h0 = bf16_rne(ops[o][t]), h1 = bf16_rne(ops[o][t + 1]);
+                const uint16_t l0 = bf16_rne(ops[o][t] - bf16_to_f(h0));
+                const uint16_t l1 = bf16_rne(ops[o][t + 1] - bf16_to_f(h1));
+                hw[t / 2] = static_cast<uint32_t>(h0) | (static_cast<uint32_t>(h1) << 16);
+                lw[t / 2] = static_cast<uint32_t>(l0) | (static_cast<uint32_t>(l1) << 16);
+            }
+            *reinterpret_cast<uint4 *>(ahl + (2 * o) * n3 + cm) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
+            *reinterpret_cast<uint4 *>(ahl + (2 * o + 1) * n3 + cm) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
+        }
+        float4 *g = reinterpret_cast<float4 *>(g32 + i * NN + kk0);
+        g[0] = make_float4(ops[1][0], ops[1][1], ops[1][2], ops[1][3]);
+        g[1] = make_float4(ops[1][4], ops[1][5], ops[1][6], ops[1][7]);
+    } else {
+#pragma unroll
+        for (int t = 0; t < 8; t += 2) {
+            *reinterpret_cast<double2 *>(perm + cm + t) = make_double2(pp[t], pp[t + 1]);
+            *reinterpret_cast<double2 *>(perm + n3 + cm + t) = make_double2(phc[t], phc[t + 1]);
+            *reinterpret_cast<double2 *>(perm + 2 * n3 + cm + t) =
+                make_double2(-2.0 * phd[t] + phc[t], -2.0 * phd[t + 1] + phc[t + 1]);
+            *reinterpret_cast<double2 *>(perm + 3 * n3 + cm + t) = make_double2(phd[t], phd[t + 1]);
+        }
+    }
 }
 
-__global__ void layout_split_kernel(const double *__restrict__ V, int N, uint16_t *__restrict__ ahl,
-                                    float *__restrict__ g32) {
+// one 32 x 32 tile of out[r][col] = in[col][r] (in: rows x cols, row stride ld_in;
+// out: cols x rows, row stride ld_out), stored as OUT
+template <typename OUT>
+__device__ __forceinline__ void layout_transpose_tile(const double *__restrict__ in, int rows, int64_t cols,
+                                                      int64_t ld_in, int r0, int64_t c0, OUT *__restrict__ out,
+                                                      int64_t ld_out, double (*tile)[kLayoutTile + 1]) {
+    const int tx = threadIdx.x & (kLayoutTile - 1), ty = threadIdx.x / kLayoutTile;   // 32 x 8
+#pragma unroll
+    for (int p = 0; p < kLayoutTile; p += 8) {
+        const int r = r0 + ty + p;
+        const int64_t c = c0 + tx;
+        tile[ty + p][tx] = (r < rows && c < cols) ? in[r * ld_in + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kLayoutTile; p += 8) {
+        const int64_t c = c0 + ty + p;
+        const int r = r0 + tx;
+        if (r < rows && c < cols) out[c * ld_out + r] = static_cast<OUT>(tile[tx][ty + p]);
+    }
+}
+
+// block blk of a layout pass
+template <bool SPLIT>
+__device__ __forceinline__ void layout_block(const double *__restrict__ V, int N, int64_t n3, int blk,
+                                             uint16_t *__restrict__ ahl, float *__restrict__ g32,
+                                             double *__restrict__ perm) {
+    __shared__ double tile[kLayoutTile][kLayoutTile + 1];
+    const int na = layout_a_blocks(N), nt = layout_t_tiles(N);
+    const int64_t NN = static_cast<int64_t>(N) * N;
+    if (blk < na) {
+        const int64_t u = static_cast<int64_t>(blk) * 256 + threadIdx.x;
+        if (u < n3 / 8) layout_a_unit<SPLIT>(V, N, n3, u, ahl, g32, perm);
+        return;
+    }
+    blk -= na;
+    const int nt1 = nt * static_cast<int>((NN + kLayoutTile - 1) / kLayoutTile);
+    if (blk < nt1) {   // block 4: out[(i, j)][k] = V[k][(i, j)]
+        const int rt = blk % nt;
+        const int64_t ct = blk / nt;
+        if constexpr (SPLIT)
+            layout_transpose_tile<float>(V, N, NN, NN, rt * kLayoutTile, ct * kLayoutTile, g32 + n3, N, tile);
+        else
+            layout_transpose_tile<double>(V, N, NN, NN, rt * kLayoutTile, ct * kLayoutTile, perm + 4 * n3, N, tile);
+        return;
+    }
+    blk -= nt1;        // block 5: out[i][j][k] = V[i][k][j]
+    const int i = blk / (nt * nt), rem = blk - i * nt * nt;
+    const int rt = rem % nt, ct = rem / nt;
+    if constexpr (SPLIT)
+        layout_transpose_tile<float>(V + i * NN, N, N, N, rt * kLayoutTile, ct * kLayoutTile, g32 + 2 * n3 + i * NN,
+                                     N, tile);
+    else
+        layout_transpose_tile<double>(V + i * NN, N, N, N, rt * kLayoutTile, ct * kLayoutTile,
+                                      perm + 5 * n3 + i * NN, N, tile);
+}
+
+__global__ __launch_bounds__(256) void layout_f64_kernel(const double *__restrict__ V, int N,
+                                                         double *__restrict__ perm) {
     const int64_t n3 = static_cast<int64_t>(N) * N * N;
-    const int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (idx < n3) layout_split_elem(V, N, n3, idx, ahl, g32);
+    layout_block<false>(V, N, n3, blockIdx.x, nullptr, nullptr, perm);
+}
+
+__global__ __launch_bounds__(256) void layout_split_kernel(const double *__restrict__ V, int N,
+                                                           uint16_t *__restrict__ ahl, float *__restrict__ g32) {
+    const int64_t n3 = static_cast<int64_t>(N) * N * N;
+    layout_block<true>(V, N, n3, blockIdx.x, ahl, g32, nullptr);
 }
 
 // The channel partials are stored per column tile position, [p][m], so each
@@ -620,15 +722,14 @@ __device__ __forceinline__ const double *src_of(const FlowArgs &f, int src) {
     return src == SRC_V ? f.V : (src == SRC_YT ? f.yt : f.y5);
 }
 
-__global__ void layout_b_kernel(const FlowArgs *__restrict__ fa, const int2 *__restrict__ items,
-                                int src, int split) {
+// items: (flow, block of that flow's layout pass)
+__global__ __launch_bounds__(256) void layout_b_kernel(const FlowArgs *__restrict__ fa,
+                                                       const int2 *__restrict__ items, int src, int split) {
     const int2 it = items[blockIdx.x];
     const FlowArgs &f = fa[it.x];
     if (flow_stopped(f)) return;
-    const int64_t idx = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x;
-    if (idx >= f.n3) return;
-    if (!split) layout_f64_elem(src_of(f, src), f.N, f.n3, idx, f.perm);
-    else layout_split_elem(src_of(f, src), f.N, f.n3, idx, f.ahl, f.g32);
+    if (!split) layout_block<false>(src_of(f, src), f.N, f.n3, it.y, nullptr, nullptr, f.perm);
+    else layout_block<true>(src_of(f, src), f.N, f.n3, it.y, f.ahl, f.g32, nullptr);
 }
 
 __global__ __launch_bounds__(256) void combine_b_kernel(const FlowArgs *__restrict__ fa,
@@ -772,15 +873,18 @@ void launch_point_prep(const double *xi, const double *w, int np, double T_host,
                        T_host, state, c_stage, pa64, pa32, Tout);
 }
 
+int layout_blocks(int N) {
+    const int nt = layout_t_tiles(N);
+    const int64_t NN = static_cast<int64_t>(N) * N;
+    return layout_a_blocks(N) + nt * static_cast<int>((NN + kLayoutTile - 1) / kLayoutTile) + N * nt * nt;
+}
+
 void launch_layout_f64(const double *V, int N, double *perm, hipStream_t s) {
-    const int64_t n3 = static_cast<int64_t>(N) * N * N;
-    hipLaunchKernelGGL(layout_f64_kernel, dim3(blocks_for(n3, 256)), dim3(256), 0, s, V, N, perm);
+    hipLaunchKernelGGL(layout_f64_kernel, dim3(layout_blocks(N)), dim3(256), 0, s, V, N, perm);
 }
 
 void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipStream_t s) {
-    const int64_t n3 = static_cast<int64_t>(N) * N * N;
-    hipLaunchKernelGGL(layout_split_kernel, dim3(blocks_for(n3, 256)), dim3(256), 0, s, V, N, ahl,
-                       g32);
+    hipLaunchKernelGGL(layout_split_kernel, dim3(layout_blocks(N)), dim3(256), 0, s, V, N, ahl, g32);
 }
 
 int combine_tiles(int N) { return combine_tiles_of(N); }
