@@ -30,53 +30,57 @@ namespace {
 constexpr int kRowsPerBlock = 64;   // 16 rows per wave
 constexpr int kThreads = 256;
 
-// Divided difference (h(a) - h(b)) / (a - b) of h(x) = x sech^2 x, with its
-// Taylor form h1(m) + d^2 h3(m) / 24 around m = (a + b) / 2 when d = a - b is
-// small (h1, h3: first and third derivatives).  With e = exp(-2|x|),
-// sech^2 x = 4e / (1 + e)^2 and tanh x = sign(x) (1 - e) / (1 + e); away from the
-// diagonal the difference is taken over one common denominator,
-// (ha (1+e)^2 - 4 b e) / ((1+e)^2 d), so that one division (one reciprocal in
-// FP32) serves it.
-__device__ __forceinline__ double div_h64(double a, double ha, double b) {
-    const double d = a - b;
-    if (fabs(d) < 2e-3) {
-        const double m = 0.5 * (a + b);
-        const double e = exp(-2.0 * fabs(m));
-        const double r = 1.0 / (1.0 + e);
-        const double S = 4.0 * e * r * r;
-        const double tau = copysign((1.0 - e) * r, m);
-        const double h1 = S * (1.0 - 2.0 * m * tau);
-        const double h3 = S * (12.0 - 18.0 * S - 8.0 * m * tau * (1.0 - 3.0 * S));
-        return h1 + d * d * h3 / 24.0;
-    }
+// Weighted divided difference w (h(a) - h(b)) / (a - b) of h(x) = x sech^2 x,
+// given c1 = w h(a) and c2 = -4 w.  With e = exp(-2|x|), sech^2 x = 4e / (1+e)^2
+// and tanh x = sign(x) (1 - e) / (1 + e).  Away from the diagonal (wdiv_*_far)
+// the difference is taken over one common denominator,
+//   w (h(a) - h(b)) / d = (c1 (1+e)^2 + c2 b e) / ((1+e)^2 d),   e = exp(-2|b|),
+// so one division (one reciprocal in FP32) serves it.  Near it (wdiv_*_near,
+// small d = a - b) the Taylor form h1(m) + d^2 h3(m) / 24 around m = (a + b) / 2
+// is used (h1, h3: first and third derivatives of h), scaled by w = -c2 / 4.
+// The far form has no branch, so a lane's points are evaluated side by side and
+// the few near ones are redone afterwards.
+__device__ __forceinline__ double wdiv_h64_far(double c1, double c2, double b, double d) {
     const double e = exp(-2.0 * fabs(b));
     const double q = 1.0 + e;
     const double q2 = q * q;
-    return fma(ha, q2, -4.0 * b * e) / (q2 * d);
+    return fma(c2, b * e, c1 * q2) / (q2 * d);
 }
+__device__ __forceinline__ double wdiv_h64_near(double a, double c2, double b) {
+    const double d = a - b;
+    const double m = 0.5 * (a + b);
+    const double e = exp(-2.0 * fabs(m));
+    const double r = 1.0 / (1.0 + e);
+    const double S = 4.0 * e * r * r;
+    const double tau = copysign((1.0 - e) * r, m);
+    const double h1 = S * (1.0 - 2.0 * m * tau);
+    const double h3 = S * (12.0 - 18.0 * S - 8.0 * m * tau * (1.0 - 3.0 * S));
+    return (-0.25 * c2) * (h1 + d * d * h3 / 24.0);
+}
+constexpr double kTaylor64 = 2e-3;
 
-// FP32 form of div_h64 with hardware exp2 and reciprocal.  The Taylor form is
-// used for |d| < 0.02: its truncation (the d^4 term, h5 / 1920) stays below
-// 1e-8 there, and the common-denominator form beyond it loses at most about
-// 2e-7 / |d| < 1e-5 (absolute) to the rounding of ha and of the exponential.
+// FP32 forms with hardware exp2 and reciprocal.  The Taylor form is used for
+// |d| < 0.02: its truncation (the d^4 term, h5 / 1920) stays below 1e-8 there,
+// and the far form beyond it loses at most about 2e-7 / |d| < 1e-5 (relative to
+// w) to the rounding of h(a) and of the exponential.
 constexpr float kTaylor32 = 0.02f;
 constexpr float kM2Log2e = -2.8853900817779268f;   // -2 / ln 2: exp(-2x) = exp2(kM2Log2e x)
-__device__ __forceinline__ float div_h32(float a, float ha, float b) {
-    const float d = a - b;
-    if (fabsf(d) < kTaylor32) {
-        const float m = 0.5f * (a + b);
-        const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(m));
-        const float r = __builtin_amdgcn_rcpf(1.0f + e);
-        const float S = 4.0f * e * r * r;
-        const float tau = copysignf((1.0f - e) * r, m);
-        const float h1 = S * (1.0f - 2.0f * m * tau);
-        const float h3 = S * (12.0f - 18.0f * S - 8.0f * m * tau * (1.0f - 3.0f * S));
-        return fmaf(d * d, h3 * (1.0f / 24.0f), h1);
-    }
+__device__ __forceinline__ float wdiv_h32_far(float c1, float c2, float b, float d) {
     const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(b));
     const float q = 1.0f + e;
     const float q2 = q * q;
-    return fmaf(ha, q2, -4.0f * b * e) * __builtin_amdgcn_rcpf(q2 * d);
+    return fmaf(c2, b * e, c1 * q2) * __builtin_amdgcn_rcpf(q2 * d);
+}
+__device__ __forceinline__ float wdiv_h32_near(float a, float c2, float b) {
+    const float d = a - b;
+    const float m = 0.5f * (a + b);
+    const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(m));
+    const float r = __builtin_amdgcn_rcpf(1.0f + e);
+    const float S = 4.0f * e * r * r;
+    const float tau = copysignf((1.0f - e) * r, m);
+    const float h1 = S * (1.0f - 2.0f * m * tau);
+    const float h3 = S * (12.0f - 18.0f * S - 8.0f * m * tau * (1.0f - 3.0f * S));
+    return (-0.25f * c2) * fmaf(d * d, h3 * (1.0f / 24.0f), h1);
 }
 
 // a wave-uniform double held in scalar registers
@@ -116,10 +120,12 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     const int N = A.N, nf = A.nf, np = A.np;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *bins = smem + wave * N;
-    double *pt = smem + 4 * N;                 // LDS mode: [7][S] cpx spx cpy spy a ha wf
+    double *pt = smem + 4 * N;                 // LDS mode: [7][S] cpx spx cpy spy a c1 c2
 
+    // per point: cos/sin of px, py; a = xi / 2T; c1 = w h(a), c2 = -4 w with
+    // w = -w_p / 4T^2 (the weighted divided difference takes these)
     double cpx[PR], spx[PR], cpy[PR], spy[PR];
-    PT pa[PR], pha[PR], pwf[PR];
+    PT pa[PR], pc1[PR], pc2[PR];
     if constexpr (REG) {
 #pragma unroll
         for (int j = 0; j < P; ++j) {
@@ -130,9 +136,10 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             spx[j] = ok ? A.trig_pt[np + i] : 0.0;
             cpy[j] = ok ? A.trig_pt[2 * np + i] : 1.0;
             spy[j] = ok ? A.trig_pt[3 * np + i] : 0.0;
+            const PT wf = ok ? static_cast<PT>(F32 ? A.pa32[2 * np + i] : A.pa64[2 * np + i]) : PT(0);
             pa[j] = ok ? static_cast<PT>(F32 ? A.pa32[i] : A.pa64[i]) : PT(0);
-            pha[j] = ok ? static_cast<PT>(F32 ? A.pa32[np + i] : A.pa64[np + i]) : PT(0);
-            pwf[j] = ok ? static_cast<PT>(F32 ? A.pa32[2 * np + i] : A.pa64[2 * np + i]) : PT(0);
+            pc1[j] = wf * (ok ? static_cast<PT>(F32 ? A.pa32[np + i] : A.pa64[np + i]) : PT(0));
+            pc2[j] = PT(-4) * wf;
         }
     } else {
         for (int k = threadIdx.x; k < S; k += kThreads) {
@@ -143,22 +150,24 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             pt[1 * S + slot] = ok ? A.trig_pt[np + i] : 0.0;
             pt[2 * S + slot] = ok ? A.trig_pt[2 * np + i] : 1.0;
             pt[3 * S + slot] = ok ? A.trig_pt[3 * np + i] : 0.0;
+            const PT wf = ok ? static_cast<PT>(F32 ? A.pa32[2 * np + i] : A.pa64[2 * np + i]) : PT(0);
             pt[4 * S + slot] = ok ? (F32 ? A.pa32[i] : A.pa64[i]) : 0.0;
-            pt[5 * S + slot] = ok ? (F32 ? A.pa32[np + i] : A.pa64[np + i]) : 0.0;
-            pt[6 * S + slot] = ok ? (F32 ? A.pa32[2 * np + i] : A.pa64[2 * np + i]) : 0.0;
+            pt[5 * S + slot] = wf * (ok ? static_cast<PT>(F32 ? A.pa32[np + i] : A.pa64[np + i]) : PT(0));
+            pt[6 * S + slot] = PT(-4) * wf;
         }
         __syncthreads();
     }
     auto pval = [&](int q, int j) -> double {
         if constexpr (REG) {
             return q == 0 ? cpx[j] : q == 1 ? spx[j] : q == 2 ? cpy[j] : q == 3 ? spy[j]
-                 : q == 4 ? static_cast<double>(pa[j]) : q == 5 ? static_cast<double>(pha[j])
-                 : static_cast<double>(pwf[j]);
+                 : q == 4 ? static_cast<double>(pa[j]) : q == 5 ? static_cast<double>(pc1[j])
+                 : static_cast<double>(pc2[j]);
         } else {
             return pt[q * S + j * 64 + lane];
         }
     };
-    // eps / 2T = K1 (cx + cy) - K2 cx cy - K3, computed once and kept in scalar registers
+    // eps / 2T = K1 (cx + cy) - K2 cx cy - K3, the constants computed once and
+    // kept in scalar registers
     const double inv2T = A.Tdev[1];
     const double K1 = uniform_f64(A.mt2 * inv2T), K2 = uniform_f64(A.mt4p * inv2T),
                  K3 = uniform_f64(A.mu * inv2T);
@@ -175,59 +184,72 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
         // Row-uniform factors.  pp: cos(q - p) = cos q cos p + sin q sin p and the
         // second line enters as -eps / 2T; ph: cos(p + Q) = cos p cos Q - sin p sin Q
         // and +eps / 2T.  Both signs are folded into the row's constants, so a
-        // point costs b = k1 (cx + cy) - k2 cx cy - k3 with cx = cqx cos px + sx sin px.
+        // point costs b = cx (k1 - k2 cy) + (k1 cy - k3) with cx = cqx cos px + sx sin px
+        // (seven FP64 operations).
         const bool pp = r < A.Tpp;
         const double cqx = A.trig_row[4 * r], cqy = A.trig_row[4 * r + 2];
         const double sx = pp ? A.trig_row[4 * r + 1] : -A.trig_row[4 * r + 1];
         const double sy = pp ? A.trig_row[4 * r + 3] : -A.trig_row[4 * r + 3];
         const double k1 = pp ? -K1 : K1, k2 = pp ? -K2 : K2, k3 = pp ? -K3 : K3;
         const uint8_t *brow = A.bins + static_cast<size_t>(r) * np + static_cast<size_t>(a_patch) * nf;
-        uint8_t bn[P];
-        if (vec_bins && lane * P < nf) {
-            if (P == 4) {
-                const uint32_t v = *reinterpret_cast<const uint32_t *>(brow + lane * P);
-#pragma unroll
-                for (int j = 0; j < P; ++j) bn[j] = static_cast<uint8_t>(v >> (8 * (j & 3)));
-            } else {
+        // second-line patches of the lane's points, four to a word
+        constexpr int W = (P + 3) / 4;
+        uint32_t bw[W];
+        if (vec_bins) {   // wave-uniform; lanes past n_f read the patch start (zero-weight points)
+            const uint8_t *src = brow + (lane * P < nf ? lane * P : 0);
+            if constexpr (P == 4) {
+                bw[0] = *reinterpret_cast<const uint32_t *>(src);
+            } else if constexpr (P >= 8) {
 #pragma unroll
                 for (int h = 0; h < P / 8; ++h) {
-                    const uint64_t v = *reinterpret_cast<const uint64_t *>(brow + lane * P + 8 * h);
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) bn[8 * h + j] = static_cast<uint8_t>(v >> (8 * j));
+                    const uint64_t v = *reinterpret_cast<const uint64_t *>(src + 8 * h);
+                    bw[2 * h] = static_cast<uint32_t>(v);
+                    bw[2 * h + 1] = static_cast<uint32_t>(v >> 32);
                 }
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < P; ++j) bn[j] = lane * P + j < nf ? brow[lane * P + j] : 0;
-        }
-        wave_sync();
-        int bcur = -1;
-        PT acc = PT(0);
-        // padding points (past n_f) carry zero weight and bin 0: no test needed
+            for (int w = 0; w < W; ++w) bw[w] = 0;
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            const double cx = cqx * pval(0, j) + sx * pval(1, j);
-            const double cy = cqy * pval(2, j) + sy * pval(3, j);
-            const double b2 = k1 * (cx + cy) - k2 * (cx * cy) - k3;
-            const int bin = bn[j];
-            PT v;
-            if constexpr (F32)
-                v = static_cast<float>(pval(6, j)) *
-                    div_h32(static_cast<float>(pval(4, j)), static_cast<float>(pval(5, j)),
-                            static_cast<float>(b2));
-            else
-                v = pval(6, j) * div_h64(pval(4, j), pval(5, j), b2);
-            // runs of equal bin summed in registers (at most P terms), one
-            // FP64 LDS add per run
-            if (bin != bcur) {
-                if (bcur >= 0) atomicAdd(&bins[bcur], static_cast<double>(acc));
-                bcur = bin;
-                acc = v;
-            } else {
-                acc += v;
-            }
+            for (int j = 0; j < P; ++j)
+                bw[j >> 2] |= static_cast<uint32_t>(lane * P + j < nf ? brow[lane * P + j] : 0) << (8 * (j & 3));
         }
-        if (bcur >= 0) atomicAdd(&bins[bcur], static_cast<double>(acc));
+        auto bin_of = [&](int j) -> int { return (bw[j >> 2] >> (8 * (j & 3))) & 0xff; };
+        // weighted divided difference of point j: the far form for every lane,
+        // then the Taylor form where the lane is close to the diagonal
+        auto value = [&](int j) -> PT {
+            const double cy = cqy * pval(2, j) + sy * pval(3, j);
+            const double cx = cqx * pval(0, j) + sx * pval(1, j);
+            const PT b = static_cast<PT>(cx * (k1 - k2 * cy) + (k1 * cy - k3));
+            const PT a = static_cast<PT>(pval(4, j)), c2 = static_cast<PT>(pval(6, j));
+            const PT d = a - b;
+            PT v;
+            if constexpr (F32) {
+                v = wdiv_h32_far(static_cast<float>(pval(5, j)), c2, b, d);
+                if (fabsf(d) < kTaylor32) v = wdiv_h32_near(a, c2, b);
+            } else {
+                v = wdiv_h64_far(pval(5, j), c2, b, d);
+                if (fabs(d) < kTaylor64) v = wdiv_h64_near(a, c2, b);
+            }
+            return v;
+        };
+        wave_sync();
+        // Runs of equal bin summed in registers (at most P terms), one FP64 LDS
+        // add per run.  Padding points (past n_f) carry zero weight.
+        int bcur = bin_of(0);
+        PT acc = value(0);
+#pragma unroll
+        for (int j = 1; j < P; ++j) {
+            const PT v = value(j);
+            const int bin = bin_of(j);
+            if (bin != bcur) {
+                atomicAdd(&bins[bcur], static_cast<double>(acc));
+                acc = PT(0);
+            }
+            acc += v;
+            bcur = bin;
+        }
+        atomicAdd(&bins[bcur], static_cast<double>(acc));
         wave_sync();
         const size_t NN = static_cast<size_t>(N) * N;
         const bool pp_out = slot_out < A.npp_out;
