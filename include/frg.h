@@ -100,7 +100,7 @@ typedef struct {
 /* Device-side flow state used by frg_flow_step (FRG_STATE_LEN doubles). */
 #define FRG_STATE_LEN 32
 enum {
-    FRG_ST_S = 0,          /* current s = ln T */
+    FRG_ST_S = 0,          /* current s = ln T (g in an interaction flow) */
     FRG_ST_H = 1,          /* next step size */
     FRG_ST_ERR = 2,        /* error norm of the last attempt */
     FRG_ST_REASON = 3,     /* frg_stop of the flow (0 while running) */
@@ -182,6 +182,61 @@ frg_status frg_flow_step(frg_ctx ctx, const frg_flow_opts *o, double *d_V, doubl
  * state became non-finite (r->reason = FRG_STOP_NONFINITE). */
 frg_status frg_flow(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_log,
                     int32_t log_cap, frg_flow_result *r, void *stream);
+
+/* ---- Interaction flow (Sec. 4's working example) ----------------------
+ * At fixed temperature T the flow parameter g scales the bare on-site
+ * interaction (the propagator carries sqrt(g)); the one-loop equation for the
+ * vertex then has the same three channels as the temperature flow with the
+ * full bubble L_T in place of dL/dT:
+ *   dV/dg = F_L[V],  F_L = the rhs of frg_rhs with B = binned w_p L(xi_p, xi2; T),
+ *   Lpp = D[tanh](a, -b) / 4T,  Lph = D[tanh](a, b) / 4T  (a = xi_p / 2T,
+ *   b = xi2 / 2T, D[f](x, y) = (f(x) - f(y)) / (x - y)).
+ * The bubbles do not depend on g: a flow computes them once and every rhs is
+ * the contraction alone.  The flow starts from V(g0) = V0 (V0 = U at g0 = 0:
+ * the bare vertex; g V(g) is the effective interaction of the model whose
+ * bare interaction is g U). */
+typedef struct {
+    frg_stepper stepper;
+    frg_precision prec;
+    double T;            /* fixed temperature (> 0) */
+    double g0, g1;       /* flow range, g0 != g1 (0 -> 1 for the full interaction) */
+    double rtol, atol, vmax, h0;
+    int32_t fixed_steps, max_steps;
+} frg_iflow_opts;
+
+typedef struct {
+    frg_stop reason;     /* FRG_STOP_TMIN: g1 reached */
+    double g_end;        /* g of the final state */
+    double g_c;          /* g at the first accepted step with max|V| > vmax (NaN if none) */
+    double g_c_interp;   /* crossing interpolated linearly in g */
+    int32_t accepted, rejected, rhs_evals, first_step_rhs;
+} frg_iflow_result;
+
+/* Full bubbles L_T (not their T-derivative) into d_bpp / d_bph, laid out as in
+ * frg_bubbles (every row; FP64 or FP32 by prec).  Either output may be NULL. */
+frg_status frg_bubbles_full(frg_ctx ctx, double T, frg_precision prec, void *d_bpp, void *d_bph,
+                            void *stream);
+
+/* One evaluation of F_L[V] = dV/dg at temperature T (bubbles and contraction;
+ * the symmetry, zero-chunk and symmetric-vertex settings apply as in frg_rhs).
+ * d_V and d_F are [N][N][N] FP64 and must not overlap. */
+frg_status frg_rhs_full(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_precision prec,
+                        void *stream);
+
+/* Interaction flow, step by step: frg_iflow_init computes the bubbles L_T into
+ * the context (they stay valid until another rhs, bubble or flow call on the
+ * context) and initialises d_state (FRG_STATE_LEN doubles; FRG_ST_S holds g);
+ * frg_iflow_step makes one step attempt on the device as frg_flow_step does
+ * (EINVAL if the context's bubbles are no longer those of o->T). */
+frg_status frg_iflow_init(frg_ctx ctx, const frg_iflow_opts *o, const double *d_V, double *d_state,
+                          void *stream);
+frg_status frg_iflow_step(frg_ctx ctx, const frg_iflow_opts *o, double *d_V, double *d_state,
+                          void *stream);
+
+/* Whole interaction flow from V0 (in d_V, overwritten with the final state);
+ * the log rows are as in frg_flow with g in place of s. */
+frg_status frg_iflow(frg_ctx ctx, const frg_iflow_opts *o, double *d_V, double *d_log, int32_t log_cap,
+                     frg_iflow_result *r, void *stream);
 
 /* Batches of independent flows (different model parameters, uneven N, the
  * same n_rad x n_ang).  Each flow keeps its own geometry and workspace; every

@@ -248,6 +248,30 @@ class Model:
         lib().orc_rhs(self._h, float(T), _dp(V), _dp(F))
         return F
 
+    def rhs_full(self, T: float, V: np.ndarray) -> np.ndarray:
+        """Interaction flow (Sec. 4's working example: at fixed T the bare
+        on-site interaction carries the flow parameter g): dV/dg has the three
+        one-loop channels of the temperature flow with the full bubbles L_T in
+        place of their T-derivative."""
+        Bpp, Bph = self.bubbles(T, deriv=0)
+        return self.contract(Bpp, Bph, np.ascontiguousarray(V, dtype=np.float64).reshape(self.N, self.N, self.N))
+
+    def iflow(self, T: float, V0=None, stepper="rk4", g0=0.0, g1=1.0, fixed_steps=40, rtol=1e-6,
+              atol=1e-10, vmax=20.0, h0=0.01, max_steps=0, log_cap=4096):
+        """Interaction flow dV/dg = F_L(V) from V(g0) = V0 (default U) to g1; the
+        bubbles L_T are computed once.  Returns (V, result, log)."""
+        N = self.N
+        V = (np.full((N, N, N), float(self.U)) if V0 is None
+             else np.ascontiguousarray(V0, dtype=np.float64).copy())
+        Bpp, Bph = self.bubbles(T, deriv=0)
+        f = lambda g, y: self.contract(Bpp, Bph, y.reshape(N, N, N)).ravel()
+        if stepper == "rk4":
+            y, res = rk4(f, V.ravel(), g0, g1, fixed_steps, vmax)
+            log = np.zeros((0, 6))
+        else:
+            y, res, log = dp54(f, V.ravel(), g0, g1, h0, rtol, atol, vmax, max_steps, log_cap)
+        return y.reshape(N, N, N), res, log
+
     def rhs_entries(self, T: float, V: np.ndarray, j123) -> np.ndarray:
         V = np.ascontiguousarray(V, dtype=np.float64)
         idx = np.ascontiguousarray(np.asarray(j123, dtype=np.int32).reshape(-1, 3))

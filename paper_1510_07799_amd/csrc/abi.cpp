@@ -47,6 +47,10 @@ struct frg_ctx_s {
     // on demand)
     bool kskip_on = true;
     bool vsym_on = false;
+    // interaction flow: the context's bubble buffer holds L_T for this T and
+    // precision (set by frg_iflow_init, cleared by any other bubble sweep into it)
+    double iflow_T = 0.0;
+    int iflow_prec = -1;
     TileSet ts_full[2], ts_vsym[2], ts_dense[2];
     int16_t *d_perm8 = nullptr;   // [8][N] C4v patch maps (identity rows when N % 8 != 0)
     // K parts of the contraction: enough blocks (ks_target per flow) over the
@@ -554,7 +558,7 @@ void set_tiles(frg_ctx ctx, frg::FusedContractArgs &a) {
 
 // prep + bubbles into the context's bubble tensor (or caller buffers)
 frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *state, double c,
-                       void *bpp, void *bph, hipStream_t s, bool reps_only = false) {
+                       void *bpp, void *bph, hipStream_t s, bool reps_only = false, bool full = false) {
     {
         KTimer kt(ctx, FRG_K_PREP, s);
         frg::launch_point_prep(ctx->d_xi, ctx->d_w, ctx->g.np, T_host, state, c,
@@ -569,7 +573,7 @@ frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *sta
             ba.nrows = ctx->n_rep_pp + ctx->n_rep_ph;
             ba.npp_out = ctx->n_rep_pp;
         }
-        frg::launch_bubbles(ba, split, s);
+        frg::launch_bubbles(ba, split, full, s);
     }
     HIPCHK(hipGetLastError());
     return FRG_OK;
@@ -588,9 +592,16 @@ frg_status ensure_c(frg_ctx ctx, int KS) {
     return FRG_OK;
 }
 
+// where the rhs takes its bubbles from
+enum RhsMode {
+    RHS_DT = 0,       // dL/dT at T (temperature flow)
+    RHS_FULL = 1,     // L at T (interaction flow, one evaluation)
+    RHS_STORED = 2    // the L_T already in the context's buffer (interaction flow steps)
+};
+
 // full rhs: F = scale * (-Cpp + Cc + Cd); scale = T when scale_by_T
 frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, double c,
-                   const double *V, double *F, int scale_by_T, hipStream_t s) {
+                   const double *V, double *F, int scale_by_T, hipStream_t s, RhsMode mode = RHS_DT) {
     const auto &g = ctx->g;
     const int N = g.N;
     const size_t NN = static_cast<size_t>(N) * N;
@@ -600,7 +611,10 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     void *bpp = split ? static_cast<void *>(ctx->d_B32) : static_cast<void *>(ctx->d_B64);
     void *bph = split ? static_cast<void *>(ctx->d_B32 + NN * npp_rows)
                       : static_cast<void *>(ctx->d_B64 + NN * npp_rows);
-    TRY(run_bubbles(ctx, split, T_host, state, c, bpp, bph, s, sym));
+    if (mode != RHS_STORED) {
+        ctx->iflow_prec = -1;
+        TRY(run_bubbles(ctx, split, T_host, state, c, bpp, bph, s, sym, mode == RHS_FULL));
+    }
     const int KS = ksplit(ctx);
     TRY(ensure_c(ctx, KS));
     double *Cpp = ctx->d_C, *Cc = ctx->d_C + KS * n3, *Cd = ctx->d_C + 2 * KS * n3;
@@ -958,8 +972,12 @@ frg_status frg_flow_init(frg_ctx ctx, const frg_flow_opts *o, const double *d_V,
     return FRG_OK;
 }
 
+// one step attempt; iflow: an interaction-flow step (stored bubbles, rhs not
+// scaled by T), else a temperature-flow step in s = ln T
 static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V, double *state,
-                                 double *log, int log_cap, hipStream_t s) {
+                                 double *log, int log_cap, hipStream_t s, bool iflow = false) {
+    const RhsMode mode = iflow ? RHS_STORED : RHS_DT;
+    const int scale = iflow ? 0 : 1;
     const bool split = o->prec == FRG_PREC_SPLIT_BF16;
     const int64_t n = ctx->n3;
     frg::RkStageArgs sa;
@@ -978,7 +996,7 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
                 if (st == 1) frg::launch_pre_step(state, FRG_DP54, s);
                 frg::launch_rk_stage(sa, s);
             }
-            TRY(run_rhs(ctx, split, 0.0, state, DP_C[st], sa.out, ctx->d_k[st], 1, s));
+            TRY(run_rhs(ctx, split, 0.0, state, DP_C[st], sa.out, ctx->d_k[st], scale, s, mode));
         }
         const double *kk[7];
         for (int j = 0; j < 7; ++j) kk[j] = ctx->d_k[j];
@@ -1000,7 +1018,7 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
                 frg::launch_rk_stage(sa, s);
                 in = ctx->d_yt;
             }
-            TRY(run_rhs(ctx, split, 0.0, state, cs[st], in, ctx->d_k[st], 1, s));
+            TRY(run_rhs(ctx, split, 0.0, state, cs[st], in, ctx->d_k[st], scale, s, mode));
         }
         sa.nk = 4;
         const double b[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
@@ -1058,10 +1076,177 @@ frg_status frg_flow(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_
     return FRG_OK;
 }
 
+}  // extern "C"
+
+// ---- interaction flow (Sec. 4's working example): dV/dg = F_L[V] at fixed T
+
+namespace {
+
+frg_status check_iopts(const frg_iflow_opts *o) {
+    if (!o) return fail(FRG_EINVAL, "null interaction-flow options");
+    TRY(check_prec(o->prec));
+    if (o->stepper != FRG_RK4 && o->stepper != FRG_DP54) return fail(FRG_EINVAL, "unknown stepper");
+    if (!(o->T > 0.0) || !std::isfinite(o->T)) return fail(FRG_EINVAL, "T must be finite and > 0");
+    if (!std::isfinite(o->g0) || !std::isfinite(o->g1) || o->g0 == o->g1)
+        return fail(FRG_EINVAL, "need finite g0 != g1");
+    if (!(o->vmax > 0.0)) return fail(FRG_EINVAL, "vmax must be > 0");
+    if (o->stepper == FRG_RK4 && o->fixed_steps <= 0) return fail(FRG_EINVAL, "RK4 needs fixed_steps > 0");
+    if (o->stepper == FRG_DP54 && (!(o->rtol > 0.0) || !(o->atol >= 0.0) || !std::isfinite(o->h0)))
+        return fail(FRG_EINVAL, "DP54 needs rtol > 0, atol >= 0, finite h0");
+    if (o->max_steps < 0) return fail(FRG_EINVAL, "max_steps must be >= 0");
+    return FRG_OK;
+}
+
+// the stepper options of an interaction flow (the temperature fields are unused)
+frg_flow_opts stepper_opts(const frg_iflow_opts *o) {
+    frg_flow_opts f;
+    std::memset(&f, 0, sizeof(f));
+    f.stepper = o->stepper;
+    f.prec = o->prec;
+    f.T0 = 1.0;
+    f.T_min = 0.5;
+    f.rtol = o->rtol;
+    f.atol = o->atol;
+    f.vmax = o->vmax;
+    f.h0 = o->h0;
+    f.fixed_steps = o->fixed_steps;
+    f.max_steps = o->max_steps;
+    return f;
+}
+
+frg_status check_vsym_v(frg_ctx ctx, const double *d_V, hipStream_t s) {
+    if (!ctx->vsym_on) return FRG_OK;   // a flow from a C4v-invariant vertex stays invariant
+    double dev = 0.0;
+    TRY(vsym_deviation(ctx, d_V, s, &dev));
+    if (!(dev <= kVsymTol))
+        return fail(FRG_EINVAL, "symmetric-vertex mode needs a C4v-invariant V (relative deviation " +
+                                    std::to_string(dev) + ")");
+    return FRG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+frg_status frg_bubbles_full(frg_ctx ctx, double T, frg_precision prec, void *d_bpp, void *d_bph,
+                            void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_prec(prec));
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(FRG_EINVAL, "T must be finite and > 0");
+    TRY(ensure_rhs_ws(ctx, prec));
+    return run_bubbles(ctx, prec == FRG_PREC_SPLIT_BF16, T, nullptr, 0.0, d_bpp, d_bph,
+                       static_cast<hipStream_t>(stream), false, true);
+}
+
+frg_status frg_rhs_full(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_precision prec,
+                        void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_prec(prec));
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(FRG_EINVAL, "T must be finite and > 0");
+    if (!d_V || !d_F) return fail(FRG_EINVAL, "null V or F");
+    if (!aligned8(d_V) || !aligned8(d_F)) return fail(FRG_EINVAL, "V and F must be 8-byte aligned");
+    const size_t bytes = sizeof(double) * static_cast<size_t>(ctx->n3);
+    if (overlap(d_V, bytes, d_F, bytes)) return fail(FRG_EINVAL, "V and F overlap");
+    TRY(ensure_rhs_ws(ctx, prec));
+    return run_rhs(ctx, prec == FRG_PREC_SPLIT_BF16, T, nullptr, 0.0, d_V, d_F, 0,
+                   static_cast<hipStream_t>(stream), RHS_FULL);
+}
+
+frg_status frg_iflow_init(frg_ctx ctx, const frg_iflow_opts *o, const double *d_V, double *d_state,
+                          void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_iopts(o));
+    if (!d_V || !d_state || !aligned8(d_V) || !aligned8(d_state))
+        return fail(FRG_EINVAL, "null or misaligned V / state");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TRY(check_vsym_v(ctx, d_V, s));
+    TRY(ensure_rhs_ws(ctx, o->prec));
+    TRY(ensure_flow_ws(ctx));
+    const bool split = o->prec == FRG_PREC_SPLIT_BF16;
+    // the bubbles L_T, once for the whole flow, into the buffer the rhs reads
+    {
+        const size_t NN = static_cast<size_t>(ctx->g.N) * ctx->g.N;
+        const bool sym = ctx->sym_on;
+        const size_t npp_rows = sym ? static_cast<size_t>(ctx->n_rep_pp) : static_cast<size_t>(ctx->g.Tpp);
+        void *bpp = split ? static_cast<void *>(ctx->d_B32) : static_cast<void *>(ctx->d_B64);
+        void *bph = split ? static_cast<void *>(ctx->d_B32 + NN * npp_rows)
+                          : static_cast<void *>(ctx->d_B64 + NN * npp_rows);
+        TRY(run_bubbles(ctx, split, o->T, nullptr, 0.0, bpp, bph, s, sym, true));
+        ctx->iflow_T = o->T;
+        ctx->iflow_prec = o->prec;
+    }
+    const double dir = o->g1 < o->g0 ? -1.0 : 1.0;
+    double h;
+    if (o->stepper == FRG_RK4) {
+        h = (o->g1 - o->g0) / static_cast<double>(o->fixed_steps);
+    } else {
+        h = o->h0 == 0.0 ? 0.01 : std::fabs(o->h0);
+        h *= dir;
+    }
+    frg::launch_state_init(d_state, o->g0, h, o->g1, s);
+    if (o->stepper == FRG_RK4) frg::launch_state_set(d_state, 27, o->fixed_steps, s);
+    frg::launch_maxabs_to(ctx->n3, d_V, d_state, 24, ctx->d_partial, red_blocks(ctx->n3), s);
+    if (o->stepper == FRG_DP54) {
+        TRY(run_rhs(ctx, split, o->T, d_state, 0.0, d_V, ctx->d_k[0], 0, s, RHS_STORED));
+        frg::launch_state_set(d_state, FRG_ST_RHS, 1.0, s);
+    }
+    HIPCHK(hipGetLastError());
+    return FRG_OK;
+}
+
+frg_status frg_iflow_step(frg_ctx ctx, const frg_iflow_opts *o, double *d_V, double *d_state, void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_iopts(o));
+    if (!d_V || !d_state || !aligned8(d_V) || !aligned8(d_state))
+        return fail(FRG_EINVAL, "null or misaligned V / state");
+    if (ctx->iflow_prec != o->prec || ctx->iflow_T != o->T)
+        return fail(FRG_EINVAL, "the context no longer holds the bubbles of this interaction flow "
+                                "(call frg_iflow_init again)");
+    const frg_flow_opts f = stepper_opts(o);
+    return flow_step_impl(ctx, &f, d_V, d_state, nullptr, 0, static_cast<hipStream_t>(stream), true);
+}
+
+frg_status frg_iflow(frg_ctx ctx, const frg_iflow_opts *o, double *d_V, double *d_log, int32_t log_cap,
+                     frg_iflow_result *r, void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_iopts(o));
+    if (!r) return fail(FRG_EINVAL, "null result");
+    if (log_cap < 0 || (log_cap > 0 && !d_log)) return fail(FRG_EINVAL, "bad log buffer");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TRY(ensure_rhs_ws(ctx, o->prec));
+    TRY(ensure_flow_ws(ctx));
+    TRY(frg_iflow_init(ctx, o, d_V, ctx->d_state, stream));
+    const frg_flow_opts f = stepper_opts(o);
+    const int cap = o->max_steps > 0 ? 4 * o->max_steps + 64 : 1000000;
+    double *hs = ctx->h_state;
+    for (int it = 0; it < cap; ++it) {
+        TRY(flow_step_impl(ctx, &f, d_V, ctx->d_state, d_log, log_cap, s, true));
+        HIPCHK(hipMemcpyAsync(hs, ctx->d_state, sizeof(double) * FRG_STATE_LEN, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (hs[FRG_ST_REASON] != 0.0) break;
+    }
+    std::memset(r, 0, sizeof(*r));
+    r->reason = static_cast<frg_stop>(static_cast<int>(hs[FRG_ST_REASON]));
+    r->g_end = hs[FRG_ST_S];
+    r->g_c = hs[FRG_ST_SC];
+    r->g_c_interp = hs[FRG_ST_SC_INTERP];
+    r->accepted = static_cast<int32_t>(hs[FRG_ST_ACCEPTED]);
+    r->rejected = static_cast<int32_t>(hs[FRG_ST_REJECTED]);
+    r->rhs_evals = static_cast<int32_t>(hs[FRG_ST_RHS]);
+    r->first_step_rhs = static_cast<int32_t>(hs[FRG_ST_FIRST_RHS]);
+    if (r->reason == FRG_STOP_NONFINITE) return fail(FRG_ENONFINITE, "flow state became non-finite");
+    return FRG_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
 frg_status frg_set_symmetry(frg_ctx ctx, int32_t enable) {
     TRY(check_ctx(ctx));
     if (enable && !ctx->sym_avail)
         return fail(FRG_ENOTSUP, "C4v row reduction unavailable (N % 8 != 0 or covariance check failed)");
+    if (ctx->sym_on != (enable != 0)) ctx->iflow_prec = -1;   // the bubble rows change layout
     ctx->sym_on = enable != 0;
     return FRG_OK;
 }

@@ -60,7 +60,8 @@ struct BubbleArgs {
     int nrows, npp_out;
     const int32_t *rowlist;
 };
-void launch_bubbles(const BubbleArgs &a, bool fp32, hipStream_t s);
+// full: the bubble L itself (interaction flow) instead of dL/dT
+void launch_bubbles(const BubbleArgs &a, bool fp32, bool full, hipStream_t s);
 
 // verify B_{g t}(g a, g b) = B_t(a, b) on the second-line table: counts the
 // (row, point) entries where bins[t'][p'] != g(bins[rep(t')][g^-1 p'])

@@ -83,6 +83,44 @@ __device__ __forceinline__ float wdiv_h32_near(float a, float c2, float b) {
     return (-0.25f * c2) * fmaf(d * d, h3 * (1.0f / 24.0f), h1);
 }
 
+// The full bubble (not its T-derivative) has the weighted divided difference
+// W (tanh a - tanh b) / (a - b) with W = w_p / 4T, given c1 = W tanh(a) and
+// c2 = W: far from the diagonal over one common denominator,
+//   (c1 (1+e) - c2 sign(b) (1-e)) / ((1+e) d),   e = exp(-2|b|),
+// near it the Taylor form S(m) + d^2 (4S - 6S^2)(m) / 24 with S = sech^2 (the
+// first and third derivatives of tanh).
+__device__ __forceinline__ double wdiv_t64_far(double c1, double c2, double b, double d) {
+    const double e = exp(-2.0 * fabs(b));
+    const double q = 1.0 + e;
+    return (c1 * q - c2 * copysign(1.0 - e, b)) / (q * d);
+}
+__device__ __forceinline__ double wdiv_t64_near(double a, double c2, double b) {
+    const double d = a - b;
+    const double m = 0.5 * (a + b);
+    const double e = exp(-2.0 * fabs(m));
+    const double r = 1.0 / (1.0 + e);
+    const double S = 4.0 * e * r * r;
+    return c2 * (S + d * d * (4.0 * S - 6.0 * S * S) / 24.0);
+}
+__device__ __forceinline__ float wdiv_t32_far(float c1, float c2, float b, float d) {
+    const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(b));
+    const float q = 1.0f + e;
+    return (c1 * q - c2 * copysignf(1.0f - e, b)) * __builtin_amdgcn_rcpf(q * d);
+}
+__device__ __forceinline__ float wdiv_t32_near(float a, float c2, float b) {
+    const float d = a - b;
+    const float m = 0.5f * (a + b);
+    const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(m));
+    const float r = __builtin_amdgcn_rcpf(1.0f + e);
+    const float S = 4.0f * e * r * r;
+    return c2 * fmaf(d * d, (4.0f * S - 6.0f * S * S) * (1.0f / 24.0f), S);
+}
+
+__device__ __forceinline__ double tanh_d(double x) {
+    const double e = exp(-2.0 * fabs(x));
+    return copysign((1.0 - e) / (1.0 + e), x);
+}
+
 // a wave-uniform double held in scalar registers
 __device__ __forceinline__ double uniform_f64(double x) {
     const uint64_t u = __double_as_longlong(x);
@@ -107,13 +145,14 @@ size_t bubble_lds_bytes(int N) {
     return sizeof(double) * (4 * static_cast<size_t>(N) + (points_in_registers<P, F32>() ? 0 : 7 * P * 64));
 }
 
-template <int P, bool F32>
+// FULL: the full bubble L instead of dL/dT (the interaction flow).
+template <int P, bool F32, bool FULL>
 __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int a_patch, double *smem) {
     using PT = typename std::conditional<F32, float, double>::type;
-    // The lane's P radially consecutive points: in registers for every row
-    // (split path with up to 8 points per lane), or, where that would cost too
-    // many registers (the FP64 path; 16 points per lane), staged once in LDS
-    // lane-major (lane L's point j at slot j*64 + L).
+    // The lane's P points (table positions lane*P .. lane*P+P-1, angular
+    // neighbours at one radius): in registers for every row (split path with up
+    // to 8 points per lane), or, where that would cost too many registers (the
+    // FP64 path), staged once in LDS lane-major (lane L's point j at slot j*64 + L).
     constexpr bool REG = points_in_registers<P, F32>();
     constexpr int PR = REG ? P : 1;
     constexpr int S = P * 64;
@@ -123,7 +162,23 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     double *pt = smem + 4 * N;                 // LDS mode: [7][S] cpx spx cpy spy a c1 c2
 
     // per point: cos/sin of px, py; a = xi / 2T; c1 = w h(a), c2 = -4 w with
-    // w = -w_p / 4T^2 (the weighted divided difference takes these)
+    // w = -w_p / 4T^2 (the weighted divided difference takes these); for the
+    // full bubble c1 = W tanh(a), c2 = W with W = w_p / 4T = -w T
+    const double Tcur = A.Tdev[0];
+    auto point_consts = [&](bool ok, int i, PT &a, PT &c1, PT &c2) {
+        const double wf = ok ? (F32 ? static_cast<double>(A.pa32[2 * np + i]) : A.pa64[2 * np + i]) : 0.0;
+        const double av = ok ? (F32 ? static_cast<double>(A.pa32[i]) : A.pa64[i]) : 0.0;
+        a = static_cast<PT>(av);
+        if constexpr (FULL) {
+            const double W = -wf * Tcur;
+            c1 = static_cast<PT>(W * tanh_d(av));
+            c2 = static_cast<PT>(W);
+        } else {
+            const PT w = static_cast<PT>(wf);
+            c1 = w * (ok ? static_cast<PT>(F32 ? A.pa32[np + i] : A.pa64[np + i]) : PT(0));
+            c2 = PT(-4) * w;
+        }
+    };
     double cpx[PR], spx[PR], cpy[PR], spy[PR];
     PT pa[PR], pc1[PR], pc2[PR];
     if constexpr (REG) {
@@ -136,10 +191,7 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             spx[j] = ok ? A.trig_pt[np + i] : 0.0;
             cpy[j] = ok ? A.trig_pt[2 * np + i] : 1.0;
             spy[j] = ok ? A.trig_pt[3 * np + i] : 0.0;
-            const PT wf = ok ? static_cast<PT>(F32 ? A.pa32[2 * np + i] : A.pa64[2 * np + i]) : PT(0);
-            pa[j] = ok ? static_cast<PT>(F32 ? A.pa32[i] : A.pa64[i]) : PT(0);
-            pc1[j] = wf * (ok ? static_cast<PT>(F32 ? A.pa32[np + i] : A.pa64[np + i]) : PT(0));
-            pc2[j] = PT(-4) * wf;
+            point_consts(ok, i, pa[j], pc1[j], pc2[j]);
         }
     } else {
         for (int k = threadIdx.x; k < S; k += kThreads) {
@@ -150,10 +202,11 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             pt[1 * S + slot] = ok ? A.trig_pt[np + i] : 0.0;
             pt[2 * S + slot] = ok ? A.trig_pt[2 * np + i] : 1.0;
             pt[3 * S + slot] = ok ? A.trig_pt[3 * np + i] : 0.0;
-            const PT wf = ok ? static_cast<PT>(F32 ? A.pa32[2 * np + i] : A.pa64[2 * np + i]) : PT(0);
-            pt[4 * S + slot] = ok ? (F32 ? A.pa32[i] : A.pa64[i]) : 0.0;
-            pt[5 * S + slot] = wf * (ok ? static_cast<PT>(F32 ? A.pa32[np + i] : A.pa64[np + i]) : PT(0));
-            pt[6 * S + slot] = PT(-4) * wf;
+            PT a, c1, c2;
+            point_consts(ok, i, a, c1, c2);
+            pt[4 * S + slot] = a;
+            pt[5 * S + slot] = c1;
+            pt[6 * S + slot] = c2;
         }
         __syncthreads();
     }
@@ -225,11 +278,21 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             const PT d = a - b;
             PT v;
             if constexpr (F32) {
-                v = wdiv_h32_far(static_cast<float>(pval(5, j)), c2, b, d);
-                if (fabsf(d) < kTaylor32) v = wdiv_h32_near(a, c2, b);
+                if constexpr (FULL) {
+                    v = wdiv_t32_far(static_cast<float>(pval(5, j)), c2, b, d);
+                    if (fabsf(d) < kTaylor32) v = wdiv_t32_near(a, c2, b);
+                } else {
+                    v = wdiv_h32_far(static_cast<float>(pval(5, j)), c2, b, d);
+                    if (fabsf(d) < kTaylor32) v = wdiv_h32_near(a, c2, b);
+                }
             } else {
-                v = wdiv_h64_far(pval(5, j), c2, b, d);
-                if (fabs(d) < kTaylor64) v = wdiv_h64_near(a, c2, b);
+                if constexpr (FULL) {
+                    v = wdiv_t64_far(pval(5, j), c2, b, d);
+                    if (fabs(d) < kTaylor64) v = wdiv_t64_near(a, c2, b);
+                } else {
+                    v = wdiv_h64_far(pval(5, j), c2, b, d);
+                    if (fabs(d) < kTaylor64) v = wdiv_h64_near(a, c2, b);
+                }
             }
             return v;
         };
@@ -266,10 +329,10 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     }
 }
 
-template <int P, bool F32>
+template <int P, bool F32, bool FULL>
 __global__ __launch_bounds__(kThreads) void bubble_kernel(BubbleArgs A) {
     extern __shared__ double smem[];
-    bubble_body<P, F32>(A, blockIdx.x, blockIdx.y, smem);
+    bubble_body<P, F32, FULL>(A, blockIdx.x, blockIdx.y, smem);
 }
 
 // batched: item = (flow, chunk << 8 | patch); skips flows whose state says stop
@@ -281,17 +344,21 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel_batched(const BubbleAr
     const int2 it = items[blockIdx.x];
     if (states && states[it.x][FRG_ST_REASON] != 0.0) return;
     const BubbleArgs A = args[it.x];
-    bubble_body<P, F32>(A, it.y >> 8, it.y & 255, smem);
+    bubble_body<P, F32, false>(A, it.y >> 8, it.y & 255, smem);
 }
 
 template <int P>
-void launch_p(const BubbleArgs &a, bool fp32, hipStream_t s) {
+void launch_p(const BubbleArgs &a, bool fp32, bool full, hipStream_t s) {
     dim3 grid((a.nrows + kRowsPerBlock - 1) / kRowsPerBlock, a.N);
     const size_t lds = fp32 ? bubble_lds_bytes<P, true>(a.N) : bubble_lds_bytes<P, false>(a.N);
-    if (fp32)
-        hipLaunchKernelGGL((bubble_kernel<P, true>), grid, dim3(kThreads), lds, s, a);
+    if (fp32 && !full)
+        hipLaunchKernelGGL((bubble_kernel<P, true, false>), grid, dim3(kThreads), lds, s, a);
+    else if (!fp32 && !full)
+        hipLaunchKernelGGL((bubble_kernel<P, false, false>), grid, dim3(kThreads), lds, s, a);
+    else if (fp32)
+        hipLaunchKernelGGL((bubble_kernel<P, true, true>), grid, dim3(kThreads), lds, s, a);
     else
-        hipLaunchKernelGGL((bubble_kernel<P, false>), grid, dim3(kThreads), lds, s, a);
+        hipLaunchKernelGGL((bubble_kernel<P, false, true>), grid, dim3(kThreads), lds, s, a);
 }
 
 template <int P>
@@ -320,13 +387,13 @@ void launch_bubbles_batched(const BubbleArgs *args, const int2 *items, int nitem
     else launch_pb<16>(args, items, nitems, states, maxN, fp32, s);
 }
 
-void launch_bubbles(const BubbleArgs &a, bool fp32, hipStream_t s) {
+void launch_bubbles(const BubbleArgs &a, bool fp32, bool full, hipStream_t s) {
     const int P = (a.nf + 63) / 64;
-    if (P <= 1) launch_p<1>(a, fp32, s);
-    else if (P <= 2) launch_p<2>(a, fp32, s);
-    else if (P <= 4) launch_p<4>(a, fp32, s);
-    else if (P <= 8) launch_p<8>(a, fp32, s);
-    else launch_p<16>(a, fp32, s);
+    if (P <= 1) launch_p<1>(a, fp32, full, s);
+    else if (P <= 2) launch_p<2>(a, fp32, full, s);
+    else if (P <= 4) launch_p<4>(a, fp32, full, s);
+    else if (P <= 8) launch_p<8>(a, fp32, full, s);
+    else launch_p<16>(a, fp32, full, s);
 }
 
 }  // namespace frg

@@ -48,6 +48,18 @@ class FlowResult(C.Structure):
                 ("rhs_evals", C.c_int32), ("first_step_rhs", C.c_int32)]
 
 
+class IFlowOpts(C.Structure):
+    _fields_ = [("stepper", C.c_int32), ("prec", C.c_int32), ("T", C.c_double), ("g0", C.c_double),
+                ("g1", C.c_double), ("rtol", C.c_double), ("atol", C.c_double), ("vmax", C.c_double),
+                ("h0", C.c_double), ("fixed_steps", C.c_int32), ("max_steps", C.c_int32)]
+
+
+class IFlowResult(C.Structure):
+    _fields_ = [("reason", C.c_int32), ("g_end", C.c_double), ("g_c", C.c_double),
+                ("g_c_interp", C.c_double), ("accepted", C.c_int32), ("rejected", C.c_int32),
+                ("rhs_evals", C.c_int32), ("first_step_rhs", C.c_int32)]
+
+
 _lib = None
 _P = C.c_void_p
 _DP = C.POINTER(C.c_double)
@@ -76,6 +88,11 @@ SIGNATURES = {
     "frg_batch_flow_init": (C.c_int, [_P, C.POINTER(FlowOpts), C.POINTER(C.c_void_p), _P, C.c_int32, _P]),
     "frg_batch_flow_step": (C.c_int, [_P, _P]),
     "frg_batch_results": (C.c_int, [_P, C.POINTER(FlowResult), _IP]),
+    "frg_bubbles_full": (C.c_int, [_P, C.c_double, C.c_int, _P, _P, _P]),
+    "frg_rhs_full": (C.c_int, [_P, C.c_double, _P, _P, C.c_int, _P]),
+    "frg_iflow_init": (C.c_int, [_P, C.POINTER(IFlowOpts), _P, _P, _P]),
+    "frg_iflow_step": (C.c_int, [_P, C.POINTER(IFlowOpts), _P, _P, _P]),
+    "frg_iflow": (C.c_int, [_P, C.POINTER(IFlowOpts), _P, _P, C.c_int32, C.POINTER(IFlowResult), _P]),
     "frg_set_symmetry": (C.c_int, [_P, C.c_int32]),
     "frg_symmetry": (C.c_int, [_P, _IP, _IP]),
     "frg_set_kskip": (C.c_int, [_P, C.c_int32]),
@@ -154,6 +171,13 @@ def flow_opts(stepper="rk4", prec=PREC_FP64, T0=1.0, T_min=0.05, rtol=1e-6, atol
                     float(vmax), float(h0), int(fixed_steps), int(max_steps))
 
 
+def iflow_opts(stepper="rk4", prec=PREC_FP64, T=0.1, g0=0.0, g1=1.0, rtol=1e-6, atol=1e-10,
+               vmax=20.0, h0=0.01, fixed_steps=40, max_steps=0) -> IFlowOpts:
+    st = RK4 if stepper in ("rk4", RK4) else DP54
+    return IFlowOpts(st, int(prec), float(T), float(g0), float(g1), float(rtol), float(atol),
+                     float(vmax), float(h0), int(fixed_steps), int(max_steps))
+
+
 class Context:
     """One parameter set on the current HIP device (owns geometry + workspace)."""
 
@@ -220,6 +244,44 @@ class Context:
         Bph = torch.empty((self.Tph, N, N), dtype=dt, device="cuda")
         _check(lib().frg_bubbles(self._h, float(T), int(prec), _ptr(Bpp), _ptr(Bph), _stream()))
         return Bpp, Bph
+
+    def bubbles_full(self, T: float, prec=PREC_FP64):
+        """The full bubbles L_T (interaction flow), every row."""
+        torch = self.torch
+        dt = torch.float64 if prec == PREC_FP64 else torch.float32
+        N = self.N
+        Bpp = torch.empty((self.Tpp, N, N), dtype=dt, device="cuda")
+        Bph = torch.empty((self.Tph, N, N), dtype=dt, device="cuda")
+        _check(lib().frg_bubbles_full(self._h, float(T), int(prec), _ptr(Bpp), _ptr(Bph), _stream()))
+        return Bpp, Bph
+
+    def rhs_full(self, T: float, V, prec=PREC_FP64, out=None):
+        """dV/dg of the interaction flow at temperature T."""
+        torch = self.torch
+        N = self.N
+        assert V.dtype == torch.float64 and V.is_cuda and V.is_contiguous() and V.numel() == N ** 3
+        F = out if out is not None else torch.empty_like(V)
+        _check(lib().frg_rhs_full(self._h, float(T), _ptr(V), _ptr(F), int(prec), _stream()))
+        return F
+
+    def iflow_init(self, opts: IFlowOpts, V, state):
+        _check(lib().frg_iflow_init(self._h, C.byref(opts), _ptr(V), _ptr(state), _stream()))
+
+    def iflow_step(self, opts: IFlowOpts, V, state):
+        _check(lib().frg_iflow_step(self._h, C.byref(opts), _ptr(V), _ptr(state), _stream()))
+
+    def iflow(self, V, opts: IFlowOpts, log_cap=4096):
+        """Run a whole interaction flow in place on V; returns (result dict, log [accepted, 8])."""
+        torch = self.torch
+        log = torch.zeros((max(log_cap, 1), 8), dtype=torch.float64, device="cuda")
+        r = IFlowResult()
+        st = lib().frg_iflow(self._h, C.byref(opts), _ptr(V), _ptr(log), int(log_cap), C.byref(r), _stream())
+        res = {k: getattr(r, k) for k, _ in IFlowResult._fields_}
+        if st not in (OK, ENONFINITE):
+            _check(st)
+        torch.cuda.synchronize()
+        n = min(res["accepted"], log_cap)
+        return res, log[:n].cpu().numpy()
 
     def rhs(self, T: float, V, prec=PREC_FP64, out=None):
         torch = self.torch

@@ -25,6 +25,12 @@ CONFIGS = {
     "C3": dict(t=1.0, tp=-0.3, mu=-1.2, U=3.0, N=96, n_rad=32, n_ang=16,
                flow=dict(stepper="dp54", T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10,
                          vmax=20.0, h0=-0.01)),
+    # the paper's own working example (Sec. 4): interaction flow at T = 0.1 with
+    # t' = -0.01, mu = -0.02 and 32 patches; U (the bare interaction reached at
+    # g = 1) is not given there and is set to 2 here
+    "P1": dict(t=1.0, tp=-0.01, mu=-0.02, U=2.0, N=32, n_rad=16, n_ang=16,
+               iflow=dict(T=0.1, g0=0.0, g1=1.0, stepper="dp54", rtol=1e-6, atol=1e-10,
+                          vmax=20.0, h0=0.01)),
     # large
     "C5": dict(t=1.0, tp=-0.25, mu=-1.0, U=2.5, N=192, n_rad=32, n_ang=32,
                flow=dict(stepper="dp54", T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10,

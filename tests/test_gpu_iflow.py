@@ -1,0 +1,150 @@
+"""Interaction flow on the GPU against the oracle, through the C ABI.
+
+Sec. 4's working example flows in the bare interaction g at fixed T: the full
+bubbles L_T replace dL/dT, they are computed once per flow, and each rhs is
+the channel contraction alone.  Bars as for the temperature flow: FP64
+bubbles <= 1e-12 and rhs <= 1e-10 (rounding order only), split bubbles
+<= 1e-5 and rhs <= 2e-4, flows <= 1e-9 (FP64).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1510_07799_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1510_07799_amd import frg  # noqa: E402  (loads libfrg.so; fails loudly if missing)
+
+RAGGED = dict(t=1.0, tp=-0.12, mu=-0.35, U=2.0, N=12, n_rad=5, n_ang=3)   # N % 8 != 0, n_f = 15
+SMALLP = dict(t=1.0, tp=-0.01, mu=-0.02, U=1.0, N=16, n_rad=8, n_ang=8)  # the example's band, small
+
+
+def nrel(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(x - ref).max() / np.abs(ref).max())
+
+
+_models = {}
+
+
+def pair(name_or_params):
+    key = name_or_params if isinstance(name_or_params, str) else tuple(sorted(name_or_params.items()))
+    if key not in _models:
+        p = I.model_params(name_or_params) if isinstance(name_or_params, str) else name_or_params
+        print(f"[gpu iflow] create {p}", flush=True)
+        _models[key] = (O.Model(**p), frg.Context(**p))
+    return _models[key]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("T", [0.1, 0.01])
+@pytest.mark.parametrize("cfg", ["P1", RAGGED, SMALLP], ids=["P1", "ragged", "smallp"])
+def test_full_bubbles(cfg, T):
+    om, g = pair(cfg)
+    Rpp, Rph = om.bubbles(T, deriv=0)
+    Bpp, Bph = g.bubbles_full(T, frg.PREC_FP64)
+    assert nrel(Bpp.cpu().numpy(), Rpp) <= 1e-12
+    assert nrel(Bph.cpu().numpy(), Rph) <= 1e-12
+    Spp, Sph = g.bubbles_full(T, frg.PREC_SPLIT_BF16)
+    e = max(nrel(Spp.cpu().numpy(), Rpp), nrel(Sph.cpu().numpy(), Rph))
+    print(f"[full bubbles split] {cfg} T={T}: {e:.2e}", flush=True)
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("cfg", ["P1", RAGGED, SMALLP], ids=["P1", "ragged", "smallp"])
+def test_full_rhs(cfg):
+    om, g = pair(cfg)
+    N, U = om.N, om.U
+    vs = {"const": I.constant_vertex(N, U),
+          "raw": I.random_vertex(N, U, seed=31, symmetrise=False)}
+    for T in (0.1, 0.02):
+        for vname, V in vs.items():
+            ref = om.rhs_full(T, V)
+            got = g.rhs_full(T, dev(V), frg.PREC_FP64).cpu().numpy()
+            e64 = nrel(got, ref)
+            gs = g.rhs_full(T, dev(V), frg.PREC_SPLIT_BF16).cpu().numpy()
+            es = nrel(gs, ref)
+            print(f"[full rhs] {cfg} T={T} {vname}: fp64 {e64:.2e} split {es:.2e}", flush=True)
+            assert e64 <= 1e-10
+            assert es <= 2e-4
+
+
+def test_full_rhs_symmetric_vertex_mode():
+    """P1 (N = 32): one column per C4v orbit gives the same dV/dg for an invariant V."""
+    om, g = pair("P1")
+    N, U = om.N, om.U
+    V = I.random_vertex(N, U, seed=32, symmetrise=True)
+    ref = om.rhs_full(0.1, V)
+    g.set_vsym(True)
+    try:
+        got = g.rhs_full(0.1, dev(V), frg.PREC_FP64).cpu().numpy()
+        gs = g.rhs_full(0.1, dev(V), frg.PREC_SPLIT_BF16).cpu().numpy()
+    finally:
+        g.set_vsym(False)
+    assert nrel(got, ref) <= 1e-10
+    assert nrel(gs, ref) <= 2e-4
+
+
+def test_iflow_rk4_matches_oracle():
+    om, g = pair(SMALLP)
+    N, U = om.N, om.U
+    Vo, ro, _ = om.iflow(0.1, stepper="rk4", fixed_steps=20, vmax=50.0)
+    V = dev(np.full((N, N, N), U))
+    res, log = g.iflow(V, frg.iflow_opts("rk4", frg.PREC_FP64, T=0.1, fixed_steps=20, vmax=50.0))
+    print("[iflow rk4]", res, ro, flush=True)
+    assert res["reason"] == ro["reason"] == O.STOP_TMIN
+    assert res["accepted"] == ro["accepted"] == 20 and res["g_end"] == pytest.approx(1.0, abs=1e-14)
+    assert nrel(V.cpu().numpy(), Vo) <= 1e-9
+
+
+def test_iflow_dp54_diverges_as_the_oracle():
+    """The paper's band at U = 2 on the 16-patch grid diverges before g = 1;
+    the device and the oracle take the same steps and find the same g_c."""
+    p = dict(SMALLP, U=2.0)
+    om, g = pair(p)
+    N = om.N
+    Vo, ro, lo = om.iflow(0.1, stepper="dp54", rtol=1e-6, atol=1e-10, vmax=20.0, h0=0.01)
+    V = dev(np.full((N, N, N), 2.0))
+    res, log = g.iflow(V, frg.iflow_opts("dp54", frg.PREC_FP64, T=0.1, rtol=1e-6, atol=1e-10, vmax=20.0,
+                                         h0=0.01))
+    print("[iflow dp54]", res, ro, flush=True)
+    assert res["reason"] == ro["reason"] == O.STOP_DIVERGED
+    assert res["accepted"] == ro["accepted"] and res["rejected"] == ro["rejected"]
+    assert res["first_step_rhs"] == ro["first_step_rhs"] == 7
+    assert np.allclose(log[:, 0], lo[:, 0], rtol=0, atol=1e-9)
+    assert res["g_c_interp"] == pytest.approx(ro["s_c_interp"], abs=1e-9)
+    assert nrel(V.cpu().numpy(), Vo) <= 1e-8
+
+
+def test_iflow_step_api_and_invalidation():
+    """frg_iflow_step from the host reaches g1; another rhs on the context
+    replaces its bubbles, after which a step is refused until init again."""
+    om, g = pair(SMALLP)
+    N, U = om.N, om.U
+    Vo, ro, _ = om.iflow(0.1, stepper="dp54", g1=0.5, rtol=1e-7, atol=1e-12, vmax=50.0, h0=0.05)
+    V = dev(np.full((N, N, N), U))
+    state = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+    o = frg.iflow_opts("dp54", frg.PREC_FP64, T=0.1, g1=0.5, rtol=1e-7, atol=1e-12, vmax=50.0, h0=0.05)
+    g.iflow_init(o, V, state)
+    for _ in range(500):
+        g.iflow_step(o, V, state)
+        if state[frg.ST_REASON].item() != 0:
+            break
+    st = state.cpu().numpy()
+    assert st[frg.ST_REASON] == O.STOP_TMIN == ro["reason"]
+    assert st[frg.ST_S] == 0.5
+    assert nrel(V.cpu().numpy(), Vo) <= 1e-9
+    g.rhs(0.3, dev(np.full((N, N, N), U)), frg.PREC_FP64)
+    with pytest.raises(frg.FRGError):
+        g.iflow_step(o, V, state)
+    g.iflow_init(o, V, state)
+    g.iflow_step(o, V, state)
