@@ -58,6 +58,27 @@ def timed_flow_steps(frg, torch, ctx, prec, V0, steps, warmup):
     return t1 - t0, prof, st
 
 
+def timed_iflow_steps(frg, torch, ctx, prec, V0, T, steps, warmup):
+    """DP5(4) steps of the interaction flow (bubbles once at T, contraction-only rhs)."""
+    opts = frg.iflow_opts("dp54", prec, T=T, rtol=1e-6, atol=1e-10, vmax=20.0, h0=0.01)
+    V = V0.clone()
+    state = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+    ctx.iflow_init(opts, V, state)
+    for _ in range(warmup):
+        ctx.iflow_step(opts, V, state)
+    torch.cuda.synchronize()
+    rhs0 = float(state[frg.ST_RHS].item())
+    ctx.profile_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.iflow_step(opts, V, state)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_end()
+    st = state.cpu().numpy()
+    return t1 - t0, prof, float(st[frg.ST_RHS]) - rhs0, st
+
+
 def roofline(head, results, algo_flops, dense_flops, exec_share, evals_per_rhs, kernel=None):
     prof = head["prof"]
     dom = kernel or max(prof, key=lambda k: prof[k][0])
@@ -104,9 +125,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="split,fp64,batch,split_full",
-                    help="comma list of split,fp64,batch (symmetric-vertex mode) and split_full "
-                         "(every column computed)")
+    ap.add_argument("--legs", default="split,fp64,batch,split_full,iflow",
+                    help="comma list of split,fp64,batch (symmetric-vertex mode), split_full "
+                         "(every column computed) and iflow (the interaction flow of the paper's "
+                         "working example, N=32)")
     ap.add_argument("--batch-flows", type=int, default=16,
                     help="flows in the batched leg (N=96, 512 points/patch, drawn parameters)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
@@ -172,7 +194,7 @@ def main():
     legs = [x.strip() for x in args.legs.split(",") if x.strip()]
     results = {}
     for leg in legs:
-        if leg == "batch":
+        if leg in ("batch", "iflow"):
             continue
         prec = frg.PREC_FP64 if leg == "fp64" else frg.PREC_SPLIT_BF16
         ctx.set_vsym(leg != "split_full")   # the flows start from V = U: C4v invariant
@@ -207,7 +229,29 @@ def main():
         b.close()
         del Vs
 
+    iflow = None
+    if "iflow" in legs:
+        # the paper's working example: interaction flow at T = 0.1, t' = -0.01,
+        # mu = -0.02, 32 patches (16 x 16 points each), from V = U; each rhs is
+        # the contraction alone (the bubbles are computed once per flow)
+        pi = I.model_params("P1")
+        Ni = pi["N"]
+        ci = frg.Context(**pi)
+        ci.set_vsym(True)
+        Vi = torch.full((Ni, Ni, Ni), float(pi["U"]), dtype=torch.float64, device="cuda")
+        iflow = {}
+        for prec, nm in ((frg.PREC_SPLIT_BF16, "split"), (frg.PREC_FP64, "fp64")):
+            t_i, prof_i, rhs_i, st_i = timed_iflow_steps(frg, torch, ci, prec, Vi, 0.1, args.steps, args.warmup)
+            iflow[nm] = {"rhs_per_s": round(rhs_i / t_i, 3), "rhs_evaluated": int(rhs_i),
+                         "g_reached": round(float(st_i[frg.ST_S]), 6),
+                         "kernel_ms_per_rhs": {k: round(ms / max(1.0, rhs_i), 4) for k, (ms, c) in prof_i.items()
+                                               if c}}
+        ci.close()
+
     head = results.get("split") or (results[next(iter(results))] if results else None)
+    if head is None and batch is None:
+        print(json.dumps({"iflow_p1": iflow}))
+        return
     dt = head["seconds"] if head else batch["seconds"]
     value = RHS_PER_STEP * args.steps / dt
     if batch is not None:
@@ -249,6 +293,11 @@ def main():
             out["batch_split_over_fp64"] = round(out["batch_split_rhs_per_s"] / out["fp64_rhs_per_s"], 3)
         out["config"]["workload"] += (f"; value = batched split-BF16 rhs/s of {batch['flows']} flows "
                                       "at N=96 with (mu, t', U) drawn as in the batched configuration")
+
+    if iflow is not None:
+        out["iflow_p1"] = dict(iflow, workload="interaction flow at T=0.1, N=32, 16x16 points/patch, "
+                                               "t'=-0.01 mu=-0.02, bare U(g=1)=2, DP5(4) steps from V=U, "
+                                               "symmetric-vertex mode; bubbles once per flow")
 
     # roofline of the dominant kernel of the headline leg (a single-flow leg)
     if head is None:
