@@ -39,7 +39,13 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+PROFILE_STEPS = 3   # extra steps timed per kernel class (eager launches, events between kernels)
+
+
 def timed_flow_steps(frg, torch, ctx, prec, V0, steps, warmup):
+    """DP5(4) steps of the temperature flow: `steps` timed as the library runs
+    them (one captured graph replayed per step), then PROFILE_STEPS more with
+    per-kernel-class HIP events (launched eagerly) for the breakdown."""
     opts = frg.flow_opts("dp54", prec, T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.01)
     V = V0.clone()
     state = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
@@ -47,19 +53,23 @@ def timed_flow_steps(frg, torch, ctx, prec, V0, steps, warmup):
     for _ in range(warmup):
         ctx.flow_step(opts, V, state)
     torch.cuda.synchronize()
-    ctx.profile_begin()
     t0 = time.perf_counter()
     for _ in range(steps):
         ctx.flow_step(opts, V, state)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ctx.profile_begin()
+    for _ in range(PROFILE_STEPS):
+        ctx.flow_step(opts, V, state)
+    torch.cuda.synchronize()
     prof = ctx.profile_end()
     st = state.cpu().numpy()
     return t1 - t0, prof, st
 
 
 def timed_iflow_steps(frg, torch, ctx, prec, V0, T, steps, warmup):
-    """DP5(4) steps of the interaction flow (bubbles once at T, contraction-only rhs)."""
+    """DP5(4) steps of the interaction flow (bubbles once at T, contraction-only
+    rhs), timed as timed_flow_steps does."""
     opts = frg.iflow_opts("dp54", prec, T=T, rtol=1e-6, atol=1e-10, vmax=20.0, h0=0.01)
     V = V0.clone()
     state = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
@@ -68,15 +78,20 @@ def timed_iflow_steps(frg, torch, ctx, prec, V0, T, steps, warmup):
         ctx.iflow_step(opts, V, state)
     torch.cuda.synchronize()
     rhs0 = float(state[frg.ST_RHS].item())
-    ctx.profile_begin()
     t0 = time.perf_counter()
     for _ in range(steps):
         ctx.iflow_step(opts, V, state)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    rhs1 = float(state[frg.ST_RHS].item())
+    ctx.profile_begin()
+    for _ in range(PROFILE_STEPS):
+        ctx.iflow_step(opts, V, state)
+    torch.cuda.synchronize()
     prof = ctx.profile_end()
+    rhs2 = float(state[frg.ST_RHS].item())
     st = state.cpu().numpy()
-    return t1 - t0, prof, float(st[frg.ST_RHS]) - rhs0, st
+    return t1 - t0, prof, rhs1 - rhs0, rhs2 - rhs1, st
 
 
 def roofline(head, results, algo_flops, dense_flops, exec_share, evals_per_rhs, kernel=None):
@@ -241,10 +256,11 @@ def main():
         Vi = torch.full((Ni, Ni, Ni), float(pi["U"]), dtype=torch.float64, device="cuda")
         iflow = {}
         for prec, nm in ((frg.PREC_SPLIT_BF16, "split"), (frg.PREC_FP64, "fp64")):
-            t_i, prof_i, rhs_i, st_i = timed_iflow_steps(frg, torch, ci, prec, Vi, 0.1, args.steps, args.warmup)
+            t_i, prof_i, rhs_i, rhs_p, st_i = timed_iflow_steps(frg, torch, ci, prec, Vi, 0.1, args.steps,
+                                                                args.warmup)
             iflow[nm] = {"rhs_per_s": round(rhs_i / t_i, 3), "rhs_evaluated": int(rhs_i),
                          "g_reached": round(float(st_i[frg.ST_S]), 6),
-                         "kernel_ms_per_rhs": {k: round(ms / max(1.0, rhs_i), 4) for k, (ms, c) in prof_i.items()
+                         "kernel_ms_per_rhs": {k: round(ms / max(1.0, rhs_p), 4) for k, (ms, c) in prof_i.items()
                                                if c}}
         ci.close()
 
@@ -280,7 +296,7 @@ def main():
         rps = RHS_PER_STEP * args.steps / r["seconds"]
         out[f"{leg}_rhs_per_s"] = round(rps, 3)
         out[f"{leg}_kernel_ms_per_rhs"] = {
-            k: round(ms / max(1, args.steps * RHS_PER_STEP), 4) for k, (ms, c) in r["prof"].items()}
+            k: round(ms / (PROFILE_STEPS * RHS_PER_STEP), 4) for k, (ms, c) in r["prof"].items()}
     if "split" in results and "fp64" in results:
         out["split_over_fp64"] = round(out["split_rhs_per_s"] / out["fp64_rhs_per_s"], 3)
     if batch is not None:

@@ -76,6 +76,13 @@ struct frg_ctx_s {
     size_t ws_bytes = 0;
     // event timing (frg_profile_begin/end)
     bool prof = false;
+    // one captured step of a single flow, replayed while its key matches
+    struct StepGraph {
+        hipGraphExec_t exec = nullptr;
+        hipStream_t stream = nullptr;       // the context's own stream (capture needs one)
+        hipEvent_t ev_in = nullptr, ev_out = nullptr;
+        std::vector<double> key;
+    } sg;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
     struct Rec { int cls; hipEvent_t a, b; };
@@ -307,8 +314,8 @@ frg_status build_orbits(frg_ctx ctx) {
 
 // K parts of the fused contraction over ncol columns: enough blocks for several
 // rounds over the 256 compute units (measured best at N = 96: 8 parts for all
-// columns, 16 for one column per C4v orbit; 2 per flow in a batch of 16);
-// FRG_KSPLIT overrides
+// columns, 16 for one column per C4v orbit; in a batch of 16, 2 for all
+// columns and 8 for the orbit columns); FRG_KSPLIT overrides
 int ksplit_for(frg_ctx ctx, int ncol, int hi) {
     if (ctx->ks_override > 0) return ctx->ks_override;
     const int N = ctx->g.N;
@@ -757,7 +764,7 @@ static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out) {
     frg_ctx ctx = new frg_ctx_s();
     ctx->device = dev;
     if (n_batch > 1) {
-        ctx->ks_target = (13824 + n_batch - 1) / n_batch;
+        ctx->ks_target = (6912 + n_batch - 1) / n_batch;
         ctx->ks_lo = 2;
     }
     if (const char *e = std::getenv("FRG_KSPLIT")) ctx->ks_override = std::atoi(e);
@@ -844,6 +851,10 @@ frg_status frg_destroy(frg_ctx ctx) {
         if (ctx->d_k[j]) hipFree(ctx->d_k[j]);
     if (ctx->h_state) hipHostFree(ctx->h_state);
     for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+    if (ctx->sg.exec) hipGraphExecDestroy(ctx->sg.exec);
+    if (ctx->sg.ev_in) hipEventDestroy(ctx->sg.ev_in);
+    if (ctx->sg.ev_out) hipEventDestroy(ctx->sg.ev_out);
+    if (ctx->sg.stream) hipStreamDestroy(ctx->sg.stream);
     delete ctx;
     return FRG_OK;
 }
@@ -1033,6 +1044,58 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
     return FRG_OK;
 }
 
+// One step through a captured graph of flow_step_impl, replayed while the
+// step's inputs are the same (buffers, stepper options, tile settings); the
+// eager path when kernels are being timed or FRG_NO_GRAPH is set.  The graph
+// runs on the context's own stream, ordered after the caller's stream by
+// events.  The workspace is sized before the capture, so nothing is
+// allocated inside it.
+static frg_status flow_step_graph(frg_ctx ctx, const frg_flow_opts *o, double *V, double *state, double *log,
+                                  int log_cap, hipStream_t cs, bool iflow) {
+    if (ctx->prof || std::getenv("FRG_NO_GRAPH")) return flow_step_impl(ctx, o, V, state, log, log_cap, cs, iflow);
+    if (!iflow) ctx->iflow_prec = -1;   // a replayed temperature step overwrites the bubbles too
+    auto P = [](const void *p) { return static_cast<double>(reinterpret_cast<uintptr_t>(p)); };
+    const std::vector<double> key = {P(V), P(state), P(log), static_cast<double>(log_cap),
+                                     static_cast<double>(o->stepper), static_cast<double>(o->prec), o->rtol,
+                                     o->atol, o->vmax, static_cast<double>(o->max_steps), iflow ? 1.0 : 0.0,
+                                     ctx->sym_on ? 1.0 : 0.0, ctx->vsym_on ? 1.0 : 0.0, ctx->kskip_on ? 1.0 : 0.0};
+    auto &g = ctx->sg;
+    if (!g.stream) {
+        HIPCHK(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&g.ev_in, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&g.ev_out, hipEventDisableTiming));
+    }
+    HIPCHK(hipEventRecord(g.ev_in, cs));
+    HIPCHK(hipStreamWaitEvent(g.stream, g.ev_in, 0));
+    if (!g.exec || g.key != key) {
+        if (g.exec) {
+            hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+        }
+        TRY(ensure_c(ctx, ksplit(ctx)));
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(g.stream, hipStreamCaptureModeThreadLocal));
+        const frg_status st = flow_step_impl(ctx, o, V, state, log, log_cap, g.stream, iflow);
+        const hipError_t ce = hipStreamEndCapture(g.stream, &graph);
+        if (st != FRG_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return st;
+        }
+        if (ce != hipSuccess) return fail(FRG_EDEVICE, std::string("step capture: ") + hipGetErrorString(ce));
+        const hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g.exec = nullptr;
+            return fail(FRG_EDEVICE, std::string("step graph: ") + hipGetErrorString(e));
+        }
+        g.key = key;
+    }
+    HIPCHK(hipGraphLaunch(g.exec, g.stream));
+    HIPCHK(hipEventRecord(g.ev_out, g.stream));
+    HIPCHK(hipStreamWaitEvent(cs, g.ev_out, 0));
+    return FRG_OK;
+}
+
 frg_status frg_flow_step(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_state,
                          void *stream) {
     TRY(check_ctx(ctx));
@@ -1041,7 +1104,7 @@ frg_status frg_flow_step(frg_ctx ctx, const frg_flow_opts *o, double *d_V, doubl
         return fail(FRG_EINVAL, "null or misaligned V / state");
     TRY(ensure_rhs_ws(ctx, o->prec));
     TRY(ensure_flow_ws(ctx));
-    return flow_step_impl(ctx, o, d_V, d_state, nullptr, 0, static_cast<hipStream_t>(stream));
+    return flow_step_graph(ctx, o, d_V, d_state, nullptr, 0, static_cast<hipStream_t>(stream), false);
 }
 
 frg_status frg_flow(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_log,
@@ -1057,7 +1120,7 @@ frg_status frg_flow(frg_ctx ctx, const frg_flow_opts *o, double *d_V, double *d_
     const int cap = o->max_steps > 0 ? 4 * o->max_steps + 64 : 1000000;
     double *hs = ctx->h_state;
     for (int it = 0; it < cap; ++it) {
-        TRY(flow_step_impl(ctx, o, d_V, ctx->d_state, d_log, log_cap, s));
+        TRY(flow_step_graph(ctx, o, d_V, ctx->d_state, d_log, log_cap, s, false));
         HIPCHK(hipMemcpyAsync(hs, ctx->d_state, sizeof(double) * FRG_STATE_LEN,
                               hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -1203,7 +1266,7 @@ frg_status frg_iflow_step(frg_ctx ctx, const frg_iflow_opts *o, double *d_V, dou
         return fail(FRG_EINVAL, "the context no longer holds the bubbles of this interaction flow "
                                 "(call frg_iflow_init again)");
     const frg_flow_opts f = stepper_opts(o);
-    return flow_step_impl(ctx, &f, d_V, d_state, nullptr, 0, static_cast<hipStream_t>(stream), true);
+    return flow_step_graph(ctx, &f, d_V, d_state, nullptr, 0, static_cast<hipStream_t>(stream), true);
 }
 
 frg_status frg_iflow(frg_ctx ctx, const frg_iflow_opts *o, double *d_V, double *d_log, int32_t log_cap,
@@ -1220,7 +1283,7 @@ frg_status frg_iflow(frg_ctx ctx, const frg_iflow_opts *o, double *d_V, double *
     const int cap = o->max_steps > 0 ? 4 * o->max_steps + 64 : 1000000;
     double *hs = ctx->h_state;
     for (int it = 0; it < cap; ++it) {
-        TRY(flow_step_impl(ctx, &f, d_V, ctx->d_state, d_log, log_cap, s, true));
+        TRY(flow_step_graph(ctx, &f, d_V, ctx->d_state, d_log, log_cap, s, true));
         HIPCHK(hipMemcpyAsync(hs, ctx->d_state, sizeof(double) * FRG_STATE_LEN, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (hs[FRG_ST_REASON] != 0.0) break;

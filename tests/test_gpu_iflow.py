@@ -148,3 +148,33 @@ def test_iflow_step_api_and_invalidation():
         g.iflow_step(o, V, state)
     g.iflow_init(o, V, state)
     g.iflow_step(o, V, state)
+
+
+def test_iflow_graph_replay_matches_eager():
+    import os
+    om, g = pair(SMALLP)
+    N, U = om.N, om.U
+    o = frg.iflow_opts("dp54", frg.PREC_SPLIT_BF16, T=0.1, rtol=1e-6, atol=1e-10, vmax=50.0, h0=0.02)
+
+    def run(graph):
+        if graph:
+            os.environ.pop("FRG_NO_GRAPH", None)
+        else:
+            os.environ["FRG_NO_GRAPH"] = "1"
+        try:
+            V = dev(np.full((N, N, N), U))
+            st = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+            g.iflow_init(o, V, st)
+            for _ in range(6):
+                g.iflow_step(o, V, st)
+                torch.cuda.synchronize()
+            return V.cpu().numpy(), st.cpu().numpy()
+        finally:
+            os.environ.pop("FRG_NO_GRAPH", None)
+
+    Ve, se = run(False)
+    Vg, sg = run(True)
+    diff = [(i, se[i], sg[i]) for i in range(len(se)) if not (se[i] == sg[i] or (se[i] != se[i] and sg[i] != sg[i]))]
+    print("[iflow graph] state differences:", diff, flush=True)
+    assert np.array_equal(Ve, Vg)
+    assert not diff

@@ -457,3 +457,38 @@ def test_symmetric_vertex_flows_single_and_batched():
         assert res[i]["accepted"] == r1["accepted"] and res[i]["reason"] == r1["reason"]
         assert nrel(Vs[i].cpu().numpy(), v1) <= 1e-9
     b.close()
+
+
+def test_flow_step_graph_replay_matches_eager():
+    """Single-flow steps replay one captured graph; with eager rhs work on the
+    same context between the replays they give bit for bit the state of the
+    eager launches (FRG_NO_GRAPH, read per call)."""
+    import os
+    om, g = pair("C1")
+    N, U = om.N, om.U
+    o = frg.flow_opts("dp54", frg.PREC_SPLIT_BF16, T0=1.0, T_min=0.05, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.02)
+
+    def run(graph):
+        if graph:
+            os.environ.pop("FRG_NO_GRAPH", None)
+        else:
+            os.environ["FRG_NO_GRAPH"] = "1"
+        try:
+            V = dev(np.full((N, N, N), U))
+            st = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+            g.flow_init(o, V, st)
+            other = dev(I.random_vertex(N, U, seed=7))
+            for _ in range(6):
+                g.flow_step(o, V, st)
+                g.rhs(0.3, other, frg.PREC_FP64)
+                torch.cuda.synchronize()
+            return V.cpu().numpy(), st.cpu().numpy()
+        finally:
+            os.environ.pop("FRG_NO_GRAPH", None)
+
+    Ve, se = run(False)
+    Vg, sg = run(True)
+    diff = [(i, se[i], sg[i]) for i in range(len(se)) if not (se[i] == sg[i] or (se[i] != se[i] and sg[i] != sg[i]))]
+    print("[flow graph] state differences:", diff, flush=True)
+    assert np.array_equal(Ve, Vg)
+    assert not diff
