@@ -412,6 +412,7 @@ frg_status build_tileset(frg_ctx ctx, int cls, const std::vector<int32_t> &cols,
         hipError_t e = hipMalloc(&d_colfull, sizeof(int32_t) * NC);
         if (e == hipSuccess) e = hipMalloc(&d_flags, flags.size());
         if (e == hipSuccess) e = hipMemcpy(d_colfull, colfull.data(), sizeof(int32_t) * NC, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(d_flags, 0, flags.size());
         if (e == hipSuccess) {
             frg::launch_tile_pattern(ctx->d_bins, d_colfull, ts.d_cperm, ncol, N, g.nf, g.np, d_flags, nullptr);
             e = hipGetLastError();

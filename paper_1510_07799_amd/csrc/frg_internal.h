@@ -116,7 +116,8 @@ constexpr int kContractCols = 64;     // columns per contraction tile
 constexpr int kContractChunk = 8;     // k chunk of the active lists
 // flags[t][j] = 1 if some column at tile position t*64 .. t*64+63 (< ncol) has
 // a point of the second-line table in k chunk j (k = a*N + b, chunk = k / 8);
-// colfull[c] is the full row (pp rows, then ph rows) of column c
+// colfull[c] is the full row (pp rows, then ph rows) of column c; flags must be
+// zeroed by the caller (only ones are written)
 void launch_tile_pattern(const uint8_t *bins, const int32_t *colfull, const int32_t *cperm, int ncol, int N,
                          int nf, int np, uint8_t *flags, hipStream_t s);
 

@@ -780,25 +780,23 @@ void launch_bm(FusedContractArgs a, bool split, hipStream_t s) {
         hipLaunchKernelGGL(contract_f64_fused<BM>, dim3(blocks), dim3(kThreads), lds_bytes(false, BM), s, a);
 }
 
-// flags of the k chunks of one column tile (block = tile)
+// flags of the k chunks of the column tiles: block p scans the second-line
+// table row of the column at tile position p and marks, in its tile's flags
+// (zeroed by the caller), every chunk k / 8 with k = a*N + b that holds a point
+// (byte stores of 1, so concurrent blocks of one tile need no atomics)
 __global__ __launch_bounds__(256) void tile_pattern_kernel(const uint8_t *__restrict__ bins,
                                                            const int32_t *__restrict__ colfull,
                                                            const int32_t *__restrict__ cperm, int ncol, int N,
                                                            int nf, int np, uint8_t *__restrict__ flags) {
-    extern __shared__ uint8_t sflag[];
     const int NC = N * N, nch = NC / kContractChunk;
-    for (int j = threadIdx.x; j < nch; j += blockDim.x) sflag[j] = 0;
-    __syncthreads();
-    const int p0 = blockIdx.x * BC;
-    for (int cl = 0; cl < BC && p0 + cl < ncol; ++cl) {
-        const uint8_t *row = bins + static_cast<int64_t>(colfull[cperm[p0 + cl]]) * np;
-        for (int p = threadIdx.x; p < np; p += blockDim.x) {
-            const int k = (p / nf) * N + row[p];
-            sflag[k / kContractChunk] = 1;
-        }
+    const int p = blockIdx.x;
+    if (p >= ncol) return;
+    uint8_t *tf = flags + static_cast<int64_t>(p / BC) * nch;
+    const uint8_t *row = bins + static_cast<int64_t>(colfull[cperm[p]]) * np;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        const int k = (i / nf) * N + row[i];
+        tf[k / kContractChunk] = 1;
     }
-    __syncthreads();
-    for (int j = threadIdx.x; j < nch; j += blockDim.x) flags[static_cast<int64_t>(blockIdx.x) * nch + j] = sflag[j];
 }
 
 }  // namespace
@@ -808,10 +806,8 @@ int contract_block_rows(int N) { return block_rows_of(N); }
 
 void launch_tile_pattern(const uint8_t *bins, const int32_t *colfull, const int32_t *cperm, int ncol, int N,
                          int nf, int np, uint8_t *flags, hipStream_t s) {
-    const int tiles = (ncol + BC - 1) / BC;
-    const size_t lds = static_cast<size_t>(N) * N / kContractChunk;
-    hipLaunchKernelGGL(tile_pattern_kernel, dim3(tiles), dim3(256), lds, s, bins, colfull, cperm, ncol, N, nf,
-                       np, flags);
+    hipLaunchKernelGGL(tile_pattern_kernel, dim3(ncol), dim3(256), 0, s, bins, colfull, cperm, ncol, N, nf, np,
+                       flags);
 }
 
 size_t contract_lds_bytes(bool split) { return lds_bytes(split, 96); }
