@@ -140,10 +140,10 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="split,fp64,batch,split_full,iflow",
-                    help="comma list of split,fp64,batch (symmetric-vertex mode), split_full "
-                         "(every column computed) and iflow (the interaction flow of the paper's "
-                         "working example, N=32)")
+    ap.add_argument("--legs", default="split,fp64,batch,batch64,split_full,fp64_full,iflow",
+                    help="comma list of split, fp64, batch (16 flows), batch64 (64 flows) in "
+                         "symmetric-vertex mode; split_full, fp64_full (every column computed); "
+                         "iflow (the interaction flow of the paper's working example, N=32)")
     ap.add_argument("--batch-flows", type=int, default=16,
                     help="flows in the batched leg (N=96, 512 points/patch, drawn parameters)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
@@ -209,17 +209,17 @@ def main():
     legs = [x.strip() for x in args.legs.split(",") if x.strip()]
     results = {}
     for leg in legs:
-        if leg in ("batch", "iflow"):
+        if leg in ("batch", "batch64", "iflow"):
             continue
-        prec = frg.PREC_FP64 if leg == "fp64" else frg.PREC_SPLIT_BF16
-        ctx.set_vsym(leg != "split_full")   # the flows start from V = U: C4v invariant
+        prec = frg.PREC_FP64 if leg.startswith("fp64") else frg.PREC_SPLIT_BF16
+        ctx.set_vsym(not leg.endswith("_full"))   # the flows start from V = U: C4v invariant
         dt, prof, st = timed_flow_steps(frg, torch, ctx, prec, V0, args.steps, args.warmup)
         results[leg] = dict(seconds=dt, prof=prof, state=st)
     ctx.set_vsym(True)
     batch = None
-    if "batch" in legs:
+    def run_batch(nflows):
         # batched workload at N = 96: (mu, t', U) from the seeded draws of the batched configuration
-        draws = I.c4_flows(n_per_N=args.batch_flows, Ns=(96,), n_rad=p["n_rad"], n_ang=p["n_ang"])
+        draws = I.c4_flows(n_per_N=nflows, Ns=(96,), n_rad=p["n_rad"], n_ang=p["n_ang"])
         b = frg.Batch(draws)
         b.set_vsym(True)
         sym = b.symmetry()
@@ -239,10 +239,15 @@ def main():
         res1, _ = b.results()
         active_steps = sum(1 for r in res1 if r["reason"] == 0)
         rhs_done = sum(r1["rhs_evals"] - r0["rhs_evals"] for r0, r1 in zip(res0, res1))
-        batch = dict(seconds=tb, rhs=rhs_done, flows=len(draws), still_running=active_steps,
+        out_b = dict(seconds=tb, rhs=rhs_done, flows=len(draws), still_running=active_steps,
                      reduced=sum(1 for a, _ in sym if a))
         b.close()
         del Vs
+        torch.cuda.empty_cache()
+        return out_b
+
+    batch = run_batch(args.batch_flows) if "batch" in legs else None
+    batch64 = run_batch(64) if "batch64" in legs else None
 
     iflow = None
     if "iflow" in legs:
@@ -290,7 +295,7 @@ def main():
                    "N": N, "n_f": nf, "rhs_per_step": RHS_PER_STEP, "parallelism": "1 GPU",
                    "symmetry": f"C4v: bubble rows per transfer orbit; vertex C4v invariant, "
                                f"{vsym_cols} of {N * N} columns per channel computed "
-                               f"({vsym_cols * N} independent entries; split_full computes all)"},
+                               f"({vsym_cols * N} independent entries; split_full and fp64_full compute all)"},
     }
     for leg, r in results.items():
         rps = RHS_PER_STEP * args.steps / r["seconds"]
@@ -307,8 +312,18 @@ def main():
                         "flows_with_c4v_reduction": batch["reduced"]}
         if "fp64" in results:
             out["batch_split_over_fp64"] = round(out["batch_split_rhs_per_s"] / out["fp64_rhs_per_s"], 3)
+        if "fp64_full" in results:
+            out["batch_split_over_fp64_full"] = round(out["batch_split_rhs_per_s"] / out["fp64_full_rhs_per_s"], 3)
         out["config"]["workload"] += (f"; value = batched split-BF16 rhs/s of {batch['flows']} flows "
                                       "at N=96 with (mu, t', U) drawn as in the batched configuration")
+    if batch64 is not None:
+        out["batch64_split_rhs_per_s"] = round(batch64["rhs"] / batch64["seconds"], 3)
+        out["batch64"] = {"flows": batch64["flows"], "rhs_evaluated": batch64["rhs"],
+                          "seconds": round(batch64["seconds"], 4),
+                          "flows_running_at_end": batch64["still_running"]}
+        for ref in ("fp64", "fp64_full"):
+            if ref in results:
+                out[f"batch64_split_over_{ref}"] = round(out["batch64_split_rhs_per_s"] / out[f"{ref}_rhs_per_s"], 3)
 
     if iflow is not None:
         out["iflow_p1"] = dict(iflow, workload="interaction flow at T=0.1, N=32, 16x16 points/patch, "
