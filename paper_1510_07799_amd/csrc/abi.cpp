@@ -38,7 +38,8 @@ struct frg_ctx_s {
     // C4v orbit reduction of the bubble rows
     bool sym_avail = false, sym_on = false;
     int n_rep_pp = 0, n_rep_ph = 0;
-    int32_t *d_rowlist = nullptr;                              // representative rows (pp, then ph)
+    int32_t *d_rowlist = nullptr;      // representative pp rows
+    int32_t *d_rowlist_ph = nullptr;   // per representative pp row q: the ph row of -q (its pair)
     int32_t *d_colsym_pp = nullptr, *d_colsym_ph = nullptr;   // (compact rep << 3) | element
     // column tiles of the contraction, per class ([0]: pp columns, [1]: ph):
     // all columns in Hilbert order with their active 8-wide k chunks (ts_full);
@@ -224,6 +225,7 @@ frg::BubbleArgs bubble_args(frg_ctx ctx, bool fp32, void *bpp, void *bph) {
     a.nrows = ctx->Trows;
     a.npp_out = g.Tpp;
     a.rowlist = nullptr;
+    a.rowlist_ph = nullptr;
     return a;
 }
 
@@ -238,6 +240,13 @@ int c4v_patch_host(int o, int j, int N) {
 // (compact rep, element) tables and checks B_{g t}(g a, g b) = B_t(a, b)
 // on the device's second-line table; the reduction is enabled only if the
 // check finds no exception.
+//
+// Only pp rows have representatives of their own.  With patch j + N/2
+// opposite to j (k_{j+N/2} = -k_j bitwise), every ph transfer
+// Q = k_x - k_y = -(k_y + k_{x+N/2}) is the opposite of a pp transfer, and the
+// ph row of -q has the second-line energy of the pp row q at every fine point.
+// So each representative pp row q is evaluated together with the ph row of -q
+// (its pair), and a ph row Q = g (-q) is the g-image of the pair's ph row.
 frg_status build_orbits(frg_ctx ctx) {
     const auto &g = ctx->g;
     const int N = g.N;
@@ -263,30 +272,35 @@ frg_status build_orbits(frg_ctx ctx) {
         for (int o = 0; o < 8 && el_pp[t] < 0; ++o)
             if (img_pp(o, r) == t) el_pp[t] = o;
     }
-    for (int t = 0; t < g.Tph; ++t) {
-        int r = t;
-        for (int o = 1; o < 8; ++o) r = std::min(r, img_ph(o, t));
-        rep_ph[t] = r;
-        el_ph[t] = -1;
-        for (int o = 0; o < 8 && el_ph[t] < 0; ++o)
-            if (img_ph(o, r) == t) el_ph[t] = o;
-    }
-    std::vector<int32_t> rowlist, cidx_pp(g.Tpp, -1), cidx_ph(g.Tph, -1), orbit(ctx->Trows);
+    std::vector<int32_t> rowlist, rowlist_ph, cidx_pp(g.Tpp, -1), orbit(ctx->Trows);
+    const int H = N / 2;
+    auto pair_ph = [&](int t) { return g.row_ph[((pi[t] + H) % N) * N + pj[t]]; };   // ph row of -q_t
     for (int t = 0; t < g.Tpp; ++t)
-        if (rep_pp[t] == t) { cidx_pp[t] = static_cast<int32_t>(rowlist.size()); rowlist.push_back(t); }
+        if (rep_pp[t] == t) {
+            cidx_pp[t] = static_cast<int32_t>(rowlist.size());
+            rowlist.push_back(t);
+            rowlist_ph.push_back(g.Tpp + pair_ph(t));
+        }
     const int npp = static_cast<int>(rowlist.size());
-    for (int t = 0; t < g.Tph; ++t)
-        if (rep_ph[t] == t) { cidx_ph[t] = static_cast<int32_t>(rowlist.size()) - npp; rowlist.push_back(g.Tpp + t); }
-    const int nph = static_cast<int>(rowlist.size()) - npp;
+    // ph row t = (x, y): -Q_t = k_y + k_{x+N/2} is the pp transfer t' = o . rep, so
+    // Q_t = o (-q_rep): the o-image of the pair row of rep
+    for (int t = 0; t < g.Tph; ++t) {
+        const int x = px[t], y = py[t];
+        const int u = (x + H) % N, lo = std::min(y, u), hi = std::max(y, u);
+        const int tp = g.row_pp[lo * N + hi];
+        rep_ph[t] = rep_pp[tp];
+        el_ph[t] = el_pp[tp];
+    }
+    (void)img_ph;
     for (int t = 0; t < g.Tpp; ++t) orbit[t] = (rep_pp[t] << 3) | el_pp[t];
-    for (int t = 0; t < g.Tph; ++t) orbit[g.Tpp + t] = ((g.Tpp + rep_ph[t]) << 3) | el_ph[t];
+    for (int t = 0; t < g.Tph; ++t) orbit[g.Tpp + t] = ((g.Tpp + pair_ph(rep_ph[t])) << 3) | el_ph[t];
     std::vector<int32_t> cs_pp(static_cast<size_t>(N) * N), cs_ph(static_cast<size_t>(N) * N);
     for (int y = 0; y < N; ++y)
         for (int x = 0; x < N; ++x) {
             const int tp = g.row_pp[y * N + x];
             cs_pp[y * N + x] = (cidx_pp[rep_pp[tp]] << 3) | el_pp[tp];
             const int th = g.row_ph[x * N + y];
-            cs_ph[y * N + x] = (cidx_ph[rep_ph[th]] << 3) | el_ph[th];
+            cs_ph[y * N + x] = (cidx_pp[rep_ph[th]] << 3) | el_ph[th];
         }
     int32_t *d_orbit = nullptr;
     int *d_bad = nullptr;
@@ -303,10 +317,11 @@ frg_status build_orbits(frg_ctx ctx) {
     if (e != hipSuccess) return fail(FRG_EDEVICE, std::string("symmetry check: ") + hipGetErrorString(e));
     if (bad != 0) return FRG_OK;   // an exception to exact covariance: keep every row
     TRY(upload(ctx, &ctx->d_rowlist, rowlist.data(), rowlist.size()));
+    TRY(upload(ctx, &ctx->d_rowlist_ph, rowlist_ph.data(), rowlist_ph.size()));
     TRY(upload(ctx, &ctx->d_colsym_pp, cs_pp.data(), cs_pp.size()));
     TRY(upload(ctx, &ctx->d_colsym_ph, cs_ph.data(), cs_ph.size()));
     ctx->n_rep_pp = npp;
-    ctx->n_rep_ph = nph;
+    ctx->n_rep_ph = npp;
     ctx->sym_avail = true;
     ctx->sym_on = std::getenv("FRG_NO_SYM") == nullptr;
     return FRG_OK;
@@ -578,7 +593,8 @@ frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *sta
         frg::BubbleArgs ba = bubble_args(ctx, split, bpp, bph);
         if (reps_only) {
             ba.rowlist = ctx->d_rowlist;
-            ba.nrows = ctx->n_rep_pp + ctx->n_rep_ph;
+            ba.rowlist_ph = ctx->d_rowlist_ph;
+            ba.nrows = ctx->n_rep_pp;
             ba.npp_out = ctx->n_rep_pp;
         }
         frg::launch_bubbles(ba, split, full, s);
@@ -840,7 +856,7 @@ frg_status frg_destroy(frg_ctx ctx) {
     void *ptrs[] = {ctx->d_bnd, ctx->d_xi, ctx->d_w, ctx->d_trig_row, ctx->d_trig_pt, ctx->d_bins,
                     ctx->d_colrow_pp, ctx->d_colrow_ph, ctx->d_pa64, ctx->d_T, ctx->d_pa32,
                     ctx->d_B64, ctx->d_B32, ctx->d_perm, ctx->d_ahl, ctx->d_g32, ctx->d_C,
-                    ctx->d_yt, ctx->d_y5, ctx->d_partial, ctx->d_state, ctx->d_rowlist,
+                    ctx->d_yt, ctx->d_y5, ctx->d_partial, ctx->d_state, ctx->d_rowlist, ctx->d_rowlist_ph,
                     ctx->d_colsym_pp, ctx->d_colsym_ph, ctx->d_perm8};
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -1495,7 +1511,8 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         frg::BubbleArgs bb = bubble_args(c, split, bpp, bph);
         if (sym) {
             bb.rowlist = c->d_rowlist;
-            bb.nrows = c->n_rep_pp + c->n_rep_ph;
+            bb.rowlist_ph = c->d_rowlist_ph;
+            bb.nrows = c->n_rep_pp;
             bb.npp_out = c->n_rep_pp;
         }
         ba[f] = bb;

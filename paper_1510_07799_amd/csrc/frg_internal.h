@@ -59,6 +59,9 @@ struct BubbleArgs {
     // npp_out go to Bpp, the rest to Bph
     int nrows, npp_out;
     const int32_t *rowlist;
+    // pairs: when set, position o evaluates the pp row rowlist[o] into Bpp and
+    // the ph row rowlist_ph[o] (the opposite transfer) into Bph, both at o
+    const int32_t *rowlist_ph;
 };
 // full: the bubble L itself (interaction flow) instead of dL/dT
 void launch_bubbles(const BubbleArgs &a, bool fp32, bool full, hipStream_t s);

@@ -116,6 +116,53 @@ __device__ __forceinline__ float wdiv_t32_near(float a, float c2, float b) {
     return c2 * fmaf(d * d, (4.0f * S - 6.0f * S * S) * (1.0f / 24.0f), S);
 }
 
+// Both rows of a pair (reading below): the second lines of the pp row q and of
+// the ph row -q have one energy, so b_ph = -b_pp exactly, and the two weighted
+// divided differences share exp(-2|b|) and the numerator's terms.  Each value
+// is bitwise the one the single-row form gives.
+__device__ __forceinline__ void wdiv_h32_pair(float a, float c1, float c2, float b, float &v0, float &v1) {
+    const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(b));
+    const float q = 1.0f + e;
+    const float q2 = q * q;
+    const float A = c1 * q2, be = b * e;
+    const float d0 = a - b, d1 = a + b;
+    v0 = fmaf(c2, be, A) * __builtin_amdgcn_rcpf(q2 * d0);
+    v1 = fmaf(c2, -be, A) * __builtin_amdgcn_rcpf(q2 * d1);
+    if (fabsf(d0) < kTaylor32) v0 = wdiv_h32_near(a, c2, b);
+    if (fabsf(d1) < kTaylor32) v1 = wdiv_h32_near(a, c2, -b);
+}
+__device__ __forceinline__ void wdiv_t32_pair(float a, float c1, float c2, float b, float &v0, float &v1) {
+    const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(b));
+    const float q = 1.0f + e;
+    const float A = c1 * q, t = c2 * copysignf(1.0f - e, b);
+    const float d0 = a - b, d1 = a + b;
+    v0 = (A - t) * __builtin_amdgcn_rcpf(q * d0);
+    v1 = (A + t) * __builtin_amdgcn_rcpf(q * d1);
+    if (fabsf(d0) < kTaylor32) v0 = wdiv_t32_near(a, c2, b);
+    if (fabsf(d1) < kTaylor32) v1 = wdiv_t32_near(a, c2, -b);
+}
+__device__ __forceinline__ void wdiv_h64_pair(double a, double c1, double c2, double b, double &v0, double &v1) {
+    const double e = exp(-2.0 * fabs(b));
+    const double q = 1.0 + e;
+    const double q2 = q * q;
+    const double A = c1 * q2, be = b * e;
+    const double d0 = a - b, d1 = a + b;
+    v0 = fma(c2, be, A) / (q2 * d0);
+    v1 = fma(c2, -be, A) / (q2 * d1);
+    if (fabs(d0) < kTaylor64) v0 = wdiv_h64_near(a, c2, b);
+    if (fabs(d1) < kTaylor64) v1 = wdiv_h64_near(a, c2, -b);
+}
+__device__ __forceinline__ void wdiv_t64_pair(double a, double c1, double c2, double b, double &v0, double &v1) {
+    const double e = exp(-2.0 * fabs(b));
+    const double q = 1.0 + e;
+    const double A = c1 * q, t = c2 * copysign(1.0 - e, b);
+    const double d0 = a - b, d1 = a + b;
+    v0 = (A - t) / (q * d0);
+    v1 = (A + t) / (q * d1);
+    if (fabs(d0) < kTaylor64) v0 = wdiv_t64_near(a, c2, b);
+    if (fabs(d1) < kTaylor64) v1 = wdiv_t64_near(a, c2, -b);
+}
+
 __device__ __forceinline__ double tanh_d(double x) {
     const double e = exp(-2.0 * fabs(x));
     return copysign((1.0 - e) / (1.0 + e), x);
@@ -136,17 +183,21 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Bins of wave w at smem[w*N ..); in LDS mode the point data follow them.
+// Bins of wave w at smem[w*N ..) (a pair's second row's at smem[(4 + w)*N ..));
+// in LDS mode the point data follow them.
 template <int P, bool F32>
 constexpr bool points_in_registers() { return F32 && P <= 8; }
 
 template <int P, bool F32>
-size_t bubble_lds_bytes(int N) {
-    return sizeof(double) * (4 * static_cast<size_t>(N) + (points_in_registers<P, F32>() ? 0 : 7 * P * 64));
+size_t bubble_lds_bytes(int N, bool paired) {
+    return sizeof(double) * ((paired ? 8 : 4) * static_cast<size_t>(N) +
+                             (points_in_registers<P, F32>() ? 0 : 7 * P * 64));
 }
 
-// FULL: the full bubble L instead of dL/dT (the interaction flow).
-template <int P, bool F32, bool FULL>
+// FULL: the full bubble L instead of dL/dT (the interaction flow).  PAIRED: each
+// output position evaluates a pp row q and the ph row of -q at once (rowlist,
+// rowlist_ph): their second lines q - p and p - q have one energy.
+template <int P, bool F32, bool FULL, bool PAIRED>
 __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int a_patch, double *smem) {
     using PT = typename std::conditional<F32, float, double>::type;
     // The lane's P points (table positions lane*P .. lane*P+P-1, angular
@@ -159,7 +210,8 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     const int N = A.N, nf = A.nf, np = A.np;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *bins = smem + wave * N;
-    double *pt = smem + 4 * N;                 // LDS mode: [7][S] cpx spx cpy spy a c1 c2
+    double *bins2 = smem + (4 + wave) * N;     // a pair's ph row
+    double *pt = smem + (PAIRED ? 8 : 4) * N;  // LDS mode: [7][S] cpx spx cpy spy a c1 c2
 
     // per point: cos/sin of px, py; a = xi / 2T; c1 = w h(a), c2 = -4 w with
     // w = -w_p / 4T^2 (the weighted divided difference takes these); for the
@@ -226,28 +278,10 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
                  K3 = uniform_f64(A.mu * inv2T);
     // second-line patches of the lane's points: one P-byte load when aligned
     const bool vec_bins = (nf % P) == 0 && (P == 4 || P == 8 || P == 16);
-
-    const int row0 = chunk * kRowsPerBlock;
-    for (int rr = wave; rr < kRowsPerBlock; rr += 4) {
-        const int slot_out = row0 + rr;                 // output row position (wave-uniform)
-        if (slot_out >= A.nrows) break;
-        // transfer row (wave-uniform: kept in scalar registers with its constants)
-        const int r = __builtin_amdgcn_readfirstlane(A.rowlist ? A.rowlist[slot_out] : slot_out);
-        for (int b = lane; b < N; b += 64) bins[b] = 0.0;
-        // Row-uniform factors.  pp: cos(q - p) = cos q cos p + sin q sin p and the
-        // second line enters as -eps / 2T; ph: cos(p + Q) = cos p cos Q - sin p sin Q
-        // and +eps / 2T.  Both signs are folded into the row's constants, so a
-        // point costs b = cx (k1 - k2 cy) + (k1 cy - k3) with cx = cqx cos px + sx sin px
-        // (seven FP64 operations).
-        const bool pp = r < A.Tpp;
-        const double cqx = A.trig_row[4 * r], cqy = A.trig_row[4 * r + 2];
-        const double sx = pp ? A.trig_row[4 * r + 1] : -A.trig_row[4 * r + 1];
-        const double sy = pp ? A.trig_row[4 * r + 3] : -A.trig_row[4 * r + 3];
-        const double k1 = pp ? -K1 : K1, k2 = pp ? -K2 : K2, k3 = pp ? -K3 : K3;
+    constexpr int W = (P + 3) / 4;
+    // second-line patches of the lane's points in table row r, four to a word
+    auto load_bins = [&](int r, uint32_t *bw) {
         const uint8_t *brow = A.bins + static_cast<size_t>(r) * np + static_cast<size_t>(a_patch) * nf;
-        // second-line patches of the lane's points, four to a word
-        constexpr int W = (P + 3) / 4;
-        uint32_t bw[W];
         if (vec_bins) {   // wave-uniform; lanes past n_f read the patch start (zero-weight points)
             const uint8_t *src = brow + (lane * P < nf ? lane * P : 0);
             if constexpr (P == 4) {
@@ -267,72 +301,121 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             for (int j = 0; j < P; ++j)
                 bw[j >> 2] |= static_cast<uint32_t>(lane * P + j < nf ? brow[lane * P + j] : 0) << (8 * (j & 3));
         }
-        auto bin_of = [&](int j) -> int { return (bw[j >> 2] >> (8 * (j & 3))) & 0xff; };
-        // weighted divided difference of point j: the far form for every lane,
-        // then the Taylor form where the lane is close to the diagonal
-        auto value = [&](int j) -> PT {
+    };
+    const size_t NN = static_cast<size_t>(N) * N;
+
+    const int row0 = chunk * kRowsPerBlock;
+    for (int rr = wave; rr < kRowsPerBlock; rr += 4) {
+        const int slot_out = row0 + rr;                 // output row position (wave-uniform)
+        if (slot_out >= A.nrows) break;
+        // transfer row (wave-uniform: kept in scalar registers with its constants);
+        // a pair's second row is the ph row of the opposite transfer
+        const int r = __builtin_amdgcn_readfirstlane(A.rowlist ? A.rowlist[slot_out] : slot_out);
+        for (int b = lane; b < N; b += 64) bins[b] = 0.0;
+        if constexpr (PAIRED)
+            for (int b = lane; b < N; b += 64) bins2[b] = 0.0;
+        // Row-uniform factors.  pp: cos(q - p) = cos q cos p + sin q sin p and the
+        // second line enters as -eps / 2T; ph: cos(p + Q) = cos p cos Q - sin p sin Q
+        // and +eps / 2T.  Both signs are folded into the row's constants, so a
+        // point costs b = cx (k1 - k2 cy) + (k1 cy - k3) with cx = cqx cos px + sx sin px
+        // (seven FP64 operations).  In a pair, r is the pp row.
+        const bool pp = PAIRED || r < A.Tpp;
+        const double cqx = A.trig_row[4 * r], cqy = A.trig_row[4 * r + 2];
+        const double sx = pp ? A.trig_row[4 * r + 1] : -A.trig_row[4 * r + 1];
+        const double sy = pp ? A.trig_row[4 * r + 3] : -A.trig_row[4 * r + 3];
+        const double k1 = pp ? -K1 : K1, k2 = pp ? -K2 : K2, k3 = pp ? -K3 : K3;
+        uint32_t bw[W], bw2[PAIRED ? W : 1];
+        load_bins(r, bw);
+        if constexpr (PAIRED) load_bins(__builtin_amdgcn_readfirstlane(A.rowlist_ph[slot_out]), bw2);
+        auto bin_of = [&](const uint32_t *w, int j) -> int { return (w[j >> 2] >> (8 * (j & 3))) & 0xff; };
+        // weighted divided difference(s) of point j: the far form for every
+        // lane, then the Taylor form where the lane is close to the diagonal
+        auto value = [&](int j, PT &v, PT &v2) {
             const double cy = cqy * pval(2, j) + sy * pval(3, j);
             const double cx = cqx * pval(0, j) + sx * pval(1, j);
             const PT b = static_cast<PT>(cx * (k1 - k2 * cy) + (k1 * cy - k3));
-            const PT a = static_cast<PT>(pval(4, j)), c2 = static_cast<PT>(pval(6, j));
+            const PT a = static_cast<PT>(pval(4, j)), c1 = static_cast<PT>(pval(5, j)),
+                     c2 = static_cast<PT>(pval(6, j));
+            if constexpr (PAIRED) {
+                if constexpr (F32 && FULL) wdiv_t32_pair(a, c1, c2, b, v, v2);
+                else if constexpr (F32) wdiv_h32_pair(a, c1, c2, b, v, v2);
+                else if constexpr (FULL) wdiv_t64_pair(a, c1, c2, b, v, v2);
+                else wdiv_h64_pair(a, c1, c2, b, v, v2);
+                return;
+            }
             const PT d = a - b;
-            PT v;
             if constexpr (F32) {
                 if constexpr (FULL) {
-                    v = wdiv_t32_far(static_cast<float>(pval(5, j)), c2, b, d);
+                    v = wdiv_t32_far(c1, c2, b, d);
                     if (fabsf(d) < kTaylor32) v = wdiv_t32_near(a, c2, b);
                 } else {
-                    v = wdiv_h32_far(static_cast<float>(pval(5, j)), c2, b, d);
+                    v = wdiv_h32_far(c1, c2, b, d);
                     if (fabsf(d) < kTaylor32) v = wdiv_h32_near(a, c2, b);
                 }
             } else {
                 if constexpr (FULL) {
-                    v = wdiv_t64_far(pval(5, j), c2, b, d);
+                    v = wdiv_t64_far(c1, c2, b, d);
                     if (fabs(d) < kTaylor64) v = wdiv_t64_near(a, c2, b);
                 } else {
-                    v = wdiv_h64_far(pval(5, j), c2, b, d);
+                    v = wdiv_h64_far(c1, c2, b, d);
                     if (fabs(d) < kTaylor64) v = wdiv_h64_near(a, c2, b);
                 }
             }
-            return v;
         };
         wave_sync();
         // Runs of equal bin summed in registers (at most P terms), one FP64 LDS
         // add per run.  Padding points (past n_f) carry zero weight.
-        int bcur = bin_of(0);
-        PT acc = value(0);
+        PT acc, acc2 = PT(0);
+        value(0, acc, acc2);
+        int bcur = bin_of(bw, 0), bcur2 = PAIRED ? bin_of(bw2, 0) : 0;
 #pragma unroll
         for (int j = 1; j < P; ++j) {
-            const PT v = value(j);
-            const int bin = bin_of(j);
+            PT v, v2 = PT(0);
+            value(j, v, v2);
+            const int bin = bin_of(bw, j);
             if (bin != bcur) {
                 atomicAdd(&bins[bcur], static_cast<double>(acc));
                 acc = PT(0);
             }
             acc += v;
             bcur = bin;
+            if constexpr (PAIRED) {
+                const int bin2 = bin_of(bw2, j);
+                if (bin2 != bcur2) {
+                    atomicAdd(&bins2[bcur2], static_cast<double>(acc2));
+                    acc2 = PT(0);
+                }
+                acc2 += v2;
+                bcur2 = bin2;
+            }
         }
         atomicAdd(&bins[bcur], static_cast<double>(acc));
+        if constexpr (PAIRED) atomicAdd(&bins2[bcur2], static_cast<double>(acc2));
         wave_sync();
-        const size_t NN = static_cast<size_t>(N) * N;
-        const bool pp_out = slot_out < A.npp_out;
-        const size_t base = (pp_out ? static_cast<size_t>(slot_out) : static_cast<size_t>(slot_out - A.npp_out)) * NN +
-                            static_cast<size_t>(a_patch) * N;
-        void *outp = pp_out ? A.Bpp : A.Bph;
-        if (outp) {
-            for (int b = lane; b < N; b += 64) {
-                if (F32) static_cast<float *>(outp)[base + b] = static_cast<float>(bins[b]);
-                else static_cast<double *>(outp)[base + b] = bins[b];
+        // outputs: a pair writes its pp row and its ph row at the same position
+        for (int k = 0; k < (PAIRED ? 2 : 1); ++k) {
+            const bool pp_out = PAIRED ? k == 0 : slot_out < A.npp_out;
+            const size_t pos = PAIRED ? static_cast<size_t>(slot_out)
+                                      : (pp_out ? static_cast<size_t>(slot_out)
+                                                : static_cast<size_t>(slot_out - A.npp_out));
+            const size_t base = pos * NN + static_cast<size_t>(a_patch) * N;
+            void *outp = pp_out ? A.Bpp : A.Bph;
+            const double *src = k == 0 ? bins : bins2;
+            if (outp) {
+                for (int b = lane; b < N; b += 64) {
+                    if (F32) static_cast<float *>(outp)[base + b] = static_cast<float>(src[b]);
+                    else static_cast<double *>(outp)[base + b] = src[b];
+                }
             }
         }
         wave_sync();
     }
 }
 
-template <int P, bool F32, bool FULL>
+template <int P, bool F32, bool FULL, bool PAIRED>
 __global__ __launch_bounds__(kThreads) void bubble_kernel(BubbleArgs A) {
     extern __shared__ double smem[];
-    bubble_body<P, F32, FULL>(A, blockIdx.x, blockIdx.y, smem);
+    bubble_body<P, F32, FULL, PAIRED>(A, blockIdx.x, blockIdx.y, smem);
 }
 
 // batched: item = (flow, chunk << 8 | patch); skips flows whose state says stop
@@ -344,27 +427,34 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel_batched(const BubbleAr
     const int2 it = items[blockIdx.x];
     if (states && states[it.x][FRG_ST_REASON] != 0.0) return;
     const BubbleArgs A = args[it.x];
-    bubble_body<P, F32, false>(A, it.y >> 8, it.y & 255, smem);
+    if (A.rowlist_ph) bubble_body<P, F32, false, true>(A, it.y >> 8, it.y & 255, smem);
+    else bubble_body<P, F32, false, false>(A, it.y >> 8, it.y & 255, smem);
+}
+
+template <int P, bool PAIRED>
+void launch_pp(const BubbleArgs &a, bool fp32, bool full, hipStream_t s) {
+    dim3 grid((a.nrows + kRowsPerBlock - 1) / kRowsPerBlock, a.N);
+    const size_t lds = fp32 ? bubble_lds_bytes<P, true>(a.N, PAIRED) : bubble_lds_bytes<P, false>(a.N, PAIRED);
+    if (fp32 && !full)
+        hipLaunchKernelGGL((bubble_kernel<P, true, false, PAIRED>), grid, dim3(kThreads), lds, s, a);
+    else if (!fp32 && !full)
+        hipLaunchKernelGGL((bubble_kernel<P, false, false, PAIRED>), grid, dim3(kThreads), lds, s, a);
+    else if (fp32)
+        hipLaunchKernelGGL((bubble_kernel<P, true, true, PAIRED>), grid, dim3(kThreads), lds, s, a);
+    else
+        hipLaunchKernelGGL((bubble_kernel<P, false, true, PAIRED>), grid, dim3(kThreads), lds, s, a);
 }
 
 template <int P>
 void launch_p(const BubbleArgs &a, bool fp32, bool full, hipStream_t s) {
-    dim3 grid((a.nrows + kRowsPerBlock - 1) / kRowsPerBlock, a.N);
-    const size_t lds = fp32 ? bubble_lds_bytes<P, true>(a.N) : bubble_lds_bytes<P, false>(a.N);
-    if (fp32 && !full)
-        hipLaunchKernelGGL((bubble_kernel<P, true, false>), grid, dim3(kThreads), lds, s, a);
-    else if (!fp32 && !full)
-        hipLaunchKernelGGL((bubble_kernel<P, false, false>), grid, dim3(kThreads), lds, s, a);
-    else if (fp32)
-        hipLaunchKernelGGL((bubble_kernel<P, true, true>), grid, dim3(kThreads), lds, s, a);
-    else
-        hipLaunchKernelGGL((bubble_kernel<P, false, true>), grid, dim3(kThreads), lds, s, a);
+    if (a.rowlist_ph) launch_pp<P, true>(a, fp32, full, s);
+    else launch_pp<P, false>(a, fp32, full, s);
 }
 
 template <int P>
 void launch_pb(const BubbleArgs *args, const int2 *items, int nitems, const double *const *states,
                int maxN, bool fp32, hipStream_t s) {
-    const size_t lds = fp32 ? bubble_lds_bytes<P, true>(maxN) : bubble_lds_bytes<P, false>(maxN);
+    const size_t lds = fp32 ? bubble_lds_bytes<P, true>(maxN, true) : bubble_lds_bytes<P, false>(maxN, true);
     if (fp32)
         hipLaunchKernelGGL((bubble_kernel_batched<P, true>), dim3(nitems), dim3(kThreads), lds, s, args,
                            items, states);
