@@ -110,13 +110,17 @@ def roofline(head, results, algo_flops, dense_flops, exec_share, evals_per_rhs, 
         roof["kskip_executed_share"] = round(exec_share, 4)
     elif dom == "bubbles":
         # plain ALU bound: vector FMA issue without packed FP32 (the build disables it),
-        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s for FP32 and FP64;
-        # algorithmic unit = one integrand evaluation, 40 flop-equivalents
+        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s for FP32 and FP64.
+        # Algorithmic work (flop-equivalents: FMA 2, a transcendental 4): per second-line
+        # energy 12 (FP64 eps) + 9 (exp(-2|b|) and the terms a pair shares), per bubble
+        # term 10 (its divided difference's own division and the run add); the
+        # unshared Taylor branch is not counted
         peak = PEAK["valu_TFLOPs"]
-        flops_per_eval = 40.0
-        achieved = evals_per_rhs * flops_per_eval / avg_s / 1e12
+        energies, terms = evals_per_rhs
+        achieved = (21.0 * energies + 10.0 * terms) / avg_s / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 4), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 6)}
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 6),
+                "work": {"energies_per_launch": energies, "terms_per_launch": terms}}
     else:
         roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK["hbm_GBs"],
                 "unit": "GB/s", "frac": None}
@@ -131,6 +135,20 @@ def roofline(head, results, algo_flops, dense_flops, exec_share, evals_per_rhs, 
     except (OSError, ValueError):
         traffic = None
     roof["traffic"] = traffic
+    if dom == "bubbles":
+        # hardware view from the profiler's instruction counts (same kernel sources):
+        # VALU issue cycles (4 per wave64 instruction on a 16-lane SIMD, 16 for a
+        # quarter-rate transcendental) over the 1024 SIMDs' cycles at 2.4 GHz
+        roof["valu_issue_frac"] = None
+        try:
+            with open(TRAFFIC_FILE) as fh:
+                tr = json.load(fh)
+            vb = tr.get("valu", {}).get(leg_name, {}).get("bubbles")
+            if tr.get("source_hash") == kernel_source_hash() and vb:
+                cyc = 4.0 * vb["insts_valu"] + 12.0 * vb["insts_trans_f32"]
+                roof["valu_issue_frac"] = round(cyc / (1024 * avg_s * 2.4e9), 4)
+        except (OSError, ValueError, KeyError):
+            pass
     return roof
 
 
@@ -204,7 +222,10 @@ def main():
     dense_flops = 8.0 * N ** 5   # what the dense formulation executes (x3 passes in split mode)
     ctx.set_vsym(True)
     _, exec_share = ctx.kskip()   # share of the dense k chunks (all columns) the contraction visits
-    evals_per_rhs = ctx.symmetry()[1] * N * nf   # bubble rows one rhs evaluates (C4v-reduced)
+    # bubble terms one rhs evaluates (C4v-reduced rows) and second-line energies
+    # (a pp row and the ph row of the opposite transfer share one energy)
+    sym_rows = ctx.symmetry()[1]
+    evals_per_rhs = (sym_rows // 2 * N * nf, sym_rows * N * nf)
 
     legs = [x.strip() for x in args.legs.split(",") if x.strip()]
     results = {}
