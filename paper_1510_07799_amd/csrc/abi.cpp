@@ -1431,6 +1431,7 @@ struct frg_batch_s {
     double *d_state_all = nullptr, *h_state_all = nullptr;
     int2 *d_it_prep = nullptr, *d_it_bub = nullptr, *d_it_n3 = nullptr, *d_it_red = nullptr,
          *d_it_con = nullptr, *d_it_comb = nullptr, *d_it_sum = nullptr, *d_it_lay = nullptr;
+    int n_bub_pair = 0;   // leading items of it_bub that belong to flows with row pairs
     int n_prep = 0, n_bub = 0, n_n3 = 0, n_red = 0, n_con = 0, n_comb = 0, n_sum = 0, n_lay = 0;
     // contraction work list grouped by block height class (32, 64, 96), each cut
     // into 8 per-XCD queues: d_q[class] = {start[8], count[8]}
@@ -1475,7 +1476,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     std::vector<frg::FusedContractArgs> ca[3];
     for (int s = 0; s < 3; ++s) ca[s].resize(b->n);
     std::vector<double *> st(b->n);
-    std::vector<int2> it_prep, it_bub, it_n3, it_red, it_comb, it_sum, it_lay;
+    std::vector<int2> it_prep, it_bub, it_bub_single, it_n3, it_red, it_comb, it_sum, it_lay;
     struct Item { int2 it; int cls, queue; double flow_cost, cost; };
     std::vector<Item> con;
     for (int f = 0; f < b->n; ++f) {
@@ -1538,7 +1539,8 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         const int rpb = frg::bubble_rows_per_block();
         const int chunks = (bb.nrows + rpb - 1) / rpb;
         for (int ch = 0; ch < chunks; ++ch)
-            for (int a = 0; a < g.N; ++a) it_bub.push_back(make_int2(f, (ch << 8) | a));
+            for (int a = 0; a < g.N; ++a)
+                (bb.rowlist_ph ? it_bub : it_bub_single).push_back(make_int2(f, (ch << 8) | a));
         for (int64_t k = 0; k < (n3 + 255) / 256; ++k) it_n3.push_back(make_int2(f, static_cast<int>(k)));
         for (int k = 0; k < frg::layout_blocks(g.N); ++k) it_lay.push_back(make_int2(f, k));
         for (int k = 0; k < frg::combine_tiles(g.N); ++k) it_comb.push_back(make_int2(f, k));
@@ -1606,6 +1608,8 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     for (int s = 0; s < 3; ++s) TRY(bupload(&b->d_ca[s], ca[s]));
     TRY(bupload(&b->d_states, st));
     TRY(bupload(&b->d_it_prep, it_prep));
+    b->n_bub_pair = static_cast<int>(it_bub.size());
+    it_bub.insert(it_bub.end(), it_bub_single.begin(), it_bub_single.end());
     TRY(bupload(&b->d_it_bub, it_bub));
     TRY(bupload(&b->d_it_n3, it_n3));
     TRY(bupload(&b->d_it_red, it_red));
@@ -1630,7 +1634,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
 void batch_rhs_launch(frg_batch b, bool split, double c_stage, int src, int stage, hipStream_t s) {
     const double *const *states = b->d_states;
     frg::launch_prep_b(b->d_fa, b->d_it_prep, b->n_prep, c_stage, split, s);
-    frg::launch_bubbles_batched(b->d_ba, b->d_it_bub, b->n_bub, states, b->nf, b->maxN, split, s);
+    frg::launch_bubbles_batched(b->d_ba, b->d_it_bub, b->n_bub_pair, b->n_bub, states, b->nf, b->maxN, split, s);
     frg::launch_layout_b(b->d_fa, b->d_it_lay, b->n_lay, src, split, s);
     const int bms[3] = {32, 64, 96};
     for (int k = 2; k >= 0; --k) {

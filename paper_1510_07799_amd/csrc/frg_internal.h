@@ -198,7 +198,8 @@ struct FlowArgs {
 enum { SRC_V = 0, SRC_YT = 1, SRC_Y5 = 2 };
 
 int bubble_rows_per_block();
-void launch_bubbles_batched(const BubbleArgs *args, const int2 *items, int nitems,
+// items: the first npaired belong to flows with row pairs (rowlist_ph set)
+void launch_bubbles_batched(const BubbleArgs *args, const int2 *items, int npaired, int nitems,
                             const double *const *states, int nf, int maxN, bool fp32, hipStream_t s);
 size_t contract_lds_bytes(bool split);
 void launch_contract_items(const FusedContractArgs *args, const int2 *items, int nitems,

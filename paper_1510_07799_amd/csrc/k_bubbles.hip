@@ -413,22 +413,22 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
 }
 
 template <int P, bool F32, bool FULL, bool PAIRED>
-__global__ __launch_bounds__(kThreads) void bubble_kernel(BubbleArgs A) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void bubble_kernel(BubbleArgs A) {
     extern __shared__ double smem[];
     bubble_body<P, F32, FULL, PAIRED>(A, blockIdx.x, blockIdx.y, smem);
 }
 
-// batched: item = (flow, chunk << 8 | patch); skips flows whose state says stop
-template <int P, bool F32>
-__global__ __launch_bounds__(kThreads) void bubble_kernel_batched(const BubbleArgs *__restrict__ args,
-                                                                  const int2 *__restrict__ items,
-                                                                  const double *const *__restrict__ states) {
+// batched: item = (flow, chunk << 8 | patch); skips flows whose state says stop.
+// The items of flows with row pairs and of flows without are separate launches.
+template <int P, bool F32, bool PAIRED>
+__global__ __launch_bounds__(kThreads) void bubble_kernel_batched(
+        const BubbleArgs *__restrict__ args, const int2 *__restrict__ items,
+        const double *const *__restrict__ states) {
     extern __shared__ double smem[];
     const int2 it = items[blockIdx.x];
     if (states && states[it.x][FRG_ST_REASON] != 0.0) return;
     const BubbleArgs A = args[it.x];
-    if (A.rowlist_ph) bubble_body<P, F32, false, true>(A, it.y >> 8, it.y & 255, smem);
-    else bubble_body<P, F32, false, false>(A, it.y >> 8, it.y & 255, smem);
+    bubble_body<P, F32, false, PAIRED>(A, it.y >> 8, it.y & 255, smem);
 }
 
 template <int P, bool PAIRED>
@@ -451,30 +451,38 @@ void launch_p(const BubbleArgs &a, bool fp32, bool full, hipStream_t s) {
     else launch_pp<P, false>(a, fp32, full, s);
 }
 
-template <int P>
-void launch_pb(const BubbleArgs *args, const int2 *items, int nitems, const double *const *states,
-               int maxN, bool fp32, hipStream_t s) {
-    const size_t lds = fp32 ? bubble_lds_bytes<P, true>(maxN, true) : bubble_lds_bytes<P, false>(maxN, true);
+template <int P, bool PAIRED>
+void launch_pbp(const BubbleArgs *args, const int2 *items, int nitems, const double *const *states,
+                int maxN, bool fp32, hipStream_t s) {
+    if (nitems <= 0) return;
+    const size_t lds = fp32 ? bubble_lds_bytes<P, true>(maxN, PAIRED) : bubble_lds_bytes<P, false>(maxN, PAIRED);
     if (fp32)
-        hipLaunchKernelGGL((bubble_kernel_batched<P, true>), dim3(nitems), dim3(kThreads), lds, s, args,
+        hipLaunchKernelGGL((bubble_kernel_batched<P, true, PAIRED>), dim3(nitems), dim3(kThreads), lds, s, args,
                            items, states);
     else
-        hipLaunchKernelGGL((bubble_kernel_batched<P, false>), dim3(nitems), dim3(kThreads), lds, s, args,
+        hipLaunchKernelGGL((bubble_kernel_batched<P, false, PAIRED>), dim3(nitems), dim3(kThreads), lds, s, args,
                            items, states);
+}
+
+template <int P>
+void launch_pb(const BubbleArgs *args, const int2 *items, int npaired, int nitems, const double *const *states,
+               int maxN, bool fp32, hipStream_t s) {
+    launch_pbp<P, true>(args, items, npaired, states, maxN, fp32, s);
+    launch_pbp<P, false>(args, items + npaired, nitems - npaired, states, maxN, fp32, s);
 }
 
 }  // namespace
 
 int bubble_rows_per_block() { return kRowsPerBlock; }
 
-void launch_bubbles_batched(const BubbleArgs *args, const int2 *items, int nitems,
+void launch_bubbles_batched(const BubbleArgs *args, const int2 *items, int npaired, int nitems,
                             const double *const *states, int nf, int maxN, bool fp32, hipStream_t s) {
     const int P = (nf + 63) / 64;
-    if (P <= 1) launch_pb<1>(args, items, nitems, states, maxN, fp32, s);
-    else if (P <= 2) launch_pb<2>(args, items, nitems, states, maxN, fp32, s);
-    else if (P <= 4) launch_pb<4>(args, items, nitems, states, maxN, fp32, s);
-    else if (P <= 8) launch_pb<8>(args, items, nitems, states, maxN, fp32, s);
-    else launch_pb<16>(args, items, nitems, states, maxN, fp32, s);
+    if (P <= 1) launch_pb<1>(args, items, npaired, nitems, states, maxN, fp32, s);
+    else if (P <= 2) launch_pb<2>(args, items, npaired, nitems, states, maxN, fp32, s);
+    else if (P <= 4) launch_pb<4>(args, items, npaired, nitems, states, maxN, fp32, s);
+    else if (P <= 8) launch_pb<8>(args, items, npaired, nitems, states, maxN, fp32, s);
+    else launch_pb<16>(args, items, npaired, nitems, states, maxN, fp32, s);
 }
 
 void launch_bubbles(const BubbleArgs &a, bool fp32, bool full, hipStream_t s) {
