@@ -427,8 +427,7 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel_batched(
     extern __shared__ double smem[];
     const int2 it = items[blockIdx.x];
     if (states && states[it.x][FRG_ST_REASON] != 0.0) return;
-    const BubbleArgs A = args[it.x];
-    bubble_body<P, F32, false, PAIRED>(A, it.y >> 8, it.y & 255, smem);
+    bubble_body<P, F32, false, PAIRED>(args[it.x], it.y >> 8, it.y & 255, smem);
 }
 
 template <int P, bool PAIRED>
