@@ -35,9 +35,10 @@ constexpr int kThreads = 256;
 // and tanh x = sign(x) (1 - e) / (1 + e).  Away from the diagonal (wdiv_*_far)
 // the difference is taken over one common denominator,
 //   w (h(a) - h(b)) / d = (c1 (1+e)^2 + c2 b e) / ((1+e)^2 d),   e = exp(-2|b|),
-// so one division (one reciprocal in FP32) serves it.  Near it (wdiv_*_near,
-// small d = a - b) the Taylor form h1(m) + d^2 h3(m) / 24 around m = (a + b) / 2
-// is used (h1, h3: first and third derivatives of h), scaled by w = -c2 / 4.
+// so one division (one reciprocal in FP32) serves it.  Near it (small d = a - b)
+// the FP64 path (wdiv_*64_near) takes the Taylor form h1(m) + d^2 h3(m) / 24
+// around m = (a + b) / 2 (h1, h3: first and third derivatives of h), scaled by
+// w = -c2 / 4; the FP32 path expands around a (below).
 // The far form has no branch, so a lane's points are evaluated side by side and
 // the few near ones are redone afterwards.
 __device__ __forceinline__ double wdiv_h64_far(double c1, double c2, double b, double d) {
@@ -59,10 +60,15 @@ __device__ __forceinline__ double wdiv_h64_near(double a, double c2, double b) {
 }
 constexpr double kTaylor64 = 2e-3;
 
-// FP32 forms with hardware exp2 and reciprocal.  The Taylor form is used for
-// |d| < 0.02: its truncation (the d^4 term, h5 / 1920) stays below 1e-8 there,
-// and the far form beyond it loses at most about 2e-7 / |d| < 1e-5 (relative to
-// w) to the rounding of h(a) and of the exponential.
+// FP32 forms with hardware exp2 and reciprocal.  Near the diagonal (|d| < 0.02)
+// the split path expands around the point's own a instead of the midpoint,
+//   w (h(a) - h(b)) / d = C0 + C1 d + C2 d^2 + C3 d^3,
+//   C0 = w h1(a), C1 = -w h2(a) / 2, C2 = w h3(a) / 6, C3 = -w h4(a) / 24
+// (hk: k-th derivative of h), whose coefficients depend on the point alone and
+// are made once per block (taylor_consts); the branch is then three FMAs.  The
+// truncation (the d^4 term, h5 / 120) stays below about 1e-7 of w there, and the
+// far form beyond it loses at most about 2e-7 / |d| < 1e-5 (relative to w) to
+// the rounding of h(a) and of the exponential.
 constexpr float kTaylor32 = 0.02f;
 constexpr float kM2Log2e = -2.8853900817779268f;   // -2 / ln 2: exp(-2x) = exp2(kM2Log2e x)
 __device__ __forceinline__ float wdiv_h32_far(float c1, float c2, float b, float d) {
@@ -71,16 +77,32 @@ __device__ __forceinline__ float wdiv_h32_far(float c1, float c2, float b, float
     const float q2 = q * q;
     return fmaf(c2, b * e, c1 * q2) * __builtin_amdgcn_rcpf(q2 * d);
 }
-__device__ __forceinline__ float wdiv_h32_near(float a, float c2, float b) {
-    const float d = a - b;
-    const float m = 0.5f * (a + b);
-    const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(m));
-    const float r = __builtin_amdgcn_rcpf(1.0f + e);
-    const float S = 4.0f * e * r * r;
-    const float tau = copysignf((1.0f - e) * r, m);
-    const float h1 = S * (1.0f - 2.0f * m * tau);
-    const float h3 = S * (12.0f - 18.0f * S - 8.0f * m * tau * (1.0f - 3.0f * S));
-    return (-0.25f * c2) * fmaf(d * d, h3 * (1.0f / 24.0f), h1);
+__device__ __forceinline__ float taylor_poly(const float4 &C, float d) {
+    return fmaf(d, fmaf(d, fmaf(d, C.w, C.z), C.y), C.x);
+}
+// The coefficients C0..C3 above at x (in FP64), for h (FULL false, weight w) or
+// for tanh (FULL true, weight W; its derivatives are S, -2 S tau, 4 S - 6 S^2
+// and -8 S tau (1 - 3 S)), with S = sech^2 x and tau = tanh x.
+template <bool FULL>
+__device__ __forceinline__ float4 taylor_consts(double x, double w) {
+    const double e = exp(-2.0 * fabs(x));
+    const double r = 1.0 / (1.0 + e);
+    const double S = 4.0 * e * r * r;
+    const double tau = copysign((1.0 - e) * r, x);
+    double k1, k2, k3, k4;
+    if constexpr (FULL) {
+        k1 = S;
+        k2 = -2.0 * S * tau;
+        k3 = S * (4.0 - 6.0 * S);
+        k4 = -8.0 * S * tau * (1.0 - 3.0 * S);
+    } else {
+        k1 = S * (1.0 - 2.0 * x * tau);
+        k2 = -2.0 * S * (2.0 * tau - 2.0 * x + 3.0 * x * S);
+        k3 = S * (12.0 - 18.0 * S - 8.0 * x * tau * (1.0 - 3.0 * S));
+        k4 = 8.0 * S * (tau * (12.0 * S - 4.0) + x * (2.0 - 15.0 * S + 15.0 * S * S));
+    }
+    return make_float4(static_cast<float>(w * k1), static_cast<float>(-w * k2 / 2.0),
+                       static_cast<float>(w * k3 / 6.0), static_cast<float>(-w * k4 / 24.0));
 }
 
 // The full bubble (not its T-derivative) has the weighted divided difference
@@ -107,20 +129,24 @@ __device__ __forceinline__ float wdiv_t32_far(float c1, float c2, float b, float
     const float q = 1.0f + e;
     return (c1 * q - c2 * copysignf(1.0f - e, b)) * __builtin_amdgcn_rcpf(q * d);
 }
-__device__ __forceinline__ float wdiv_t32_near(float a, float c2, float b) {
-    const float d = a - b;
-    const float m = 0.5f * (a + b);
-    const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(m));
-    const float r = __builtin_amdgcn_rcpf(1.0f + e);
-    const float S = 4.0f * e * r * r;
-    return c2 * fmaf(d * d, (4.0f * S - 6.0f * S * S) * (1.0f / 24.0f), S);
-}
 
 // Both rows of a pair (reading below): the second lines of the pp row q and of
 // the ph row -q have one energy, so b_ph = -b_pp exactly, and the two weighted
 // divided differences share exp(-2|b|) and the numerator's terms.  Each value
 // is bitwise the one the single-row form gives.
-__device__ __forceinline__ void wdiv_h32_pair(float a, float c1, float c2, float b, float &v0, float &v1) {
+// In FP32 the near forms of a pair fetch the point's coefficients once (coef()).
+template <class G>
+__device__ __forceinline__ void near32_pair(const G &coef, float d0, float d1, float &v0, float &v1) {
+    const bool n0 = fabsf(d0) < kTaylor32, n1 = fabsf(d1) < kTaylor32;
+    if (n0 || n1) {
+        const float4 C = coef();
+        if (n0) v0 = taylor_poly(C, d0);
+        if (n1) v1 = taylor_poly(C, d1);
+    }
+}
+template <class G>
+__device__ __forceinline__ void wdiv_h32_pair(float a, float c1, float c2, float b, const G &coef,
+                                              float &v0, float &v1) {
     const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(b));
     const float q = 1.0f + e;
     const float q2 = q * q;
@@ -128,18 +154,18 @@ __device__ __forceinline__ void wdiv_h32_pair(float a, float c1, float c2, float
     const float d0 = a - b, d1 = a + b;
     v0 = fmaf(c2, be, A) * __builtin_amdgcn_rcpf(q2 * d0);
     v1 = fmaf(c2, -be, A) * __builtin_amdgcn_rcpf(q2 * d1);
-    if (fabsf(d0) < kTaylor32) v0 = wdiv_h32_near(a, c2, b);
-    if (fabsf(d1) < kTaylor32) v1 = wdiv_h32_near(a, c2, -b);
+    near32_pair(coef, d0, d1, v0, v1);
 }
-__device__ __forceinline__ void wdiv_t32_pair(float a, float c1, float c2, float b, float &v0, float &v1) {
+template <class G>
+__device__ __forceinline__ void wdiv_t32_pair(float a, float c1, float c2, float b, const G &coef,
+                                              float &v0, float &v1) {
     const float e = __builtin_amdgcn_exp2f(kM2Log2e * fabsf(b));
     const float q = 1.0f + e;
     const float A = c1 * q, t = c2 * copysignf(1.0f - e, b);
     const float d0 = a - b, d1 = a + b;
     v0 = (A - t) * __builtin_amdgcn_rcpf(q * d0);
     v1 = (A + t) * __builtin_amdgcn_rcpf(q * d1);
-    if (fabsf(d0) < kTaylor32) v0 = wdiv_t32_near(a, c2, b);
-    if (fabsf(d1) < kTaylor32) v1 = wdiv_t32_near(a, c2, -b);
+    near32_pair(coef, d0, d1, v0, v1);
 }
 __device__ __forceinline__ void wdiv_h64_pair(double a, double c1, double c2, double b, double &v0, double &v1) {
     const double e = exp(-2.0 * fabs(b));
@@ -188,10 +214,12 @@ __device__ __forceinline__ void wave_sync() {
 template <int P, bool F32>
 constexpr bool points_in_registers() { return F32 && P <= 8; }
 
+// With the points in registers, the points' Taylor coefficients (one float4 per
+// point, lane-major) follow the bins instead.
 template <int P, bool F32>
 size_t bubble_lds_bytes(int N, bool paired) {
-    return sizeof(double) * ((paired ? 8 : 4) * static_cast<size_t>(N) +
-                             (points_in_registers<P, F32>() ? 0 : 7 * P * 64));
+    return sizeof(double) * ((paired ? 8 : 4) * static_cast<size_t>(N)) +
+           (points_in_registers<P, F32>() ? sizeof(float4) * P * 64 : sizeof(double) * 7 * P * 64);
 }
 
 // FULL: the full bubble L instead of dL/dT (the interaction flow).  PAIRED: each
@@ -212,6 +240,7 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     double *bins = smem + wave * N;
     double *bins2 = smem + (4 + wave) * N;     // a pair's ph row
     double *pt = smem + (PAIRED ? 8 : 4) * N;  // LDS mode: [7][S] cpx spx cpy spy a c1 c2
+    float4 *tay = reinterpret_cast<float4 *>(pt);  // register mode: [S] Taylor coefficients
 
     // per point: cos/sin of px, py; a = xi / 2T; c1 = w h(a), c2 = -4 w with
     // w = -w_p / 4T^2 (the weighted divided difference takes these); for the
@@ -244,7 +273,14 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             cpy[j] = ok ? A.trig_pt[2 * np + i] : 1.0;
             spy[j] = ok ? A.trig_pt[3 * np + i] : 0.0;
             point_consts(ok, i, pa[j], pc1[j], pc2[j]);
+            // the block's waves share the coefficients: wave j % 4 makes point j's
+            // (expanded around the a the sweep uses, rounded to FP32)
+            if ((j & 3) == wave) {
+                const double wf = ok ? static_cast<double>(A.pa32[2 * np + i]) : 0.0;
+                tay[j * 64 + lane] = taylor_consts<FULL>(static_cast<double>(pa[j]), FULL ? -wf * Tcur : wf);
+            }
         }
+        __syncthreads();
     } else {
         for (int k = threadIdx.x; k < S; k += kThreads) {
             const int slot = (k % P) * 64 + k / P;
@@ -274,8 +310,8 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     // eps / 2T = K1 (cx + cy) - K2 cx cy - K3, the constants computed once and
     // kept in scalar registers
     const double inv2T = A.Tdev[1];
-    const double K1 = uniform_f64(A.mt2 * inv2T), K2 = uniform_f64(A.mt4p * inv2T),
-                 K3 = uniform_f64(A.mu * inv2T);
+    const double K1 = uniform_f64(A.mt2 * inv2T), K3 = uniform_f64(A.mu * inv2T);
+    const double G = uniform_f64(A.mt4p / (A.mt2 * A.mt2) * (1.0 / inv2T));   // K2 / K1^2 (t != 0)
     // second-line patches of the lane's points: one P-byte load when aligned
     const bool vec_bins = (nf % P) == 0 && (P == 4 || P == 8 || P == 16);
     constexpr int W = (P + 3) / 4;
@@ -316,42 +352,48 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             for (int b = lane; b < N; b += 64) bins2[b] = 0.0;
         // Row-uniform factors.  pp: cos(q - p) = cos q cos p + sin q sin p and the
         // second line enters as -eps / 2T; ph: cos(p + Q) = cos p cos Q - sin p sin Q
-        // and +eps / 2T.  Both signs are folded into the row's constants, so a
-        // point costs b = cx (k1 - k2 cy) + (k1 cy - k3) with cx = cqx cos px + sx sin px
-        // (seven FP64 operations).  In a pair, r is the pp row.
+        // and +eps / 2T, so b = k1 (cx + cy) - k2 cx cy - k3 with the channel's
+        // signs in k1, k2, k3.  With X = k1 cx = (k1 cqx) cos px + (k1 sx) sin px and
+        // Y = k1 cy likewise, b = X (1 - (k2 / k1^2) Y) + (Y - k3): seven FP64
+        // operations, each with one scalar operand.  In a pair, r is the pp row.
         const bool pp = PAIRED || r < A.Tpp;
-        const double cqx = A.trig_row[4 * r], cqy = A.trig_row[4 * r + 2];
-        const double sx = pp ? A.trig_row[4 * r + 1] : -A.trig_row[4 * r + 1];
-        const double sy = pp ? A.trig_row[4 * r + 3] : -A.trig_row[4 * r + 3];
-        const double k1 = pp ? -K1 : K1, k2 = pp ? -K2 : K2, k3 = pp ? -K3 : K3;
+        const double k1 = pp ? -K1 : K1, g = pp ? -G : G, k3 = pp ? -K3 : K3;
+        const double cqx = uniform_f64(k1 * A.trig_row[4 * r]), cqy = uniform_f64(k1 * A.trig_row[4 * r + 2]);
+        const double sx = uniform_f64((pp ? k1 : -k1) * A.trig_row[4 * r + 1]);
+        const double sy = uniform_f64((pp ? k1 : -k1) * A.trig_row[4 * r + 3]);
         uint32_t bw[W], bw2[PAIRED ? W : 1];
         load_bins(r, bw);
         if constexpr (PAIRED) load_bins(__builtin_amdgcn_readfirstlane(A.rowlist_ph[slot_out]), bw2);
         auto bin_of = [&](const uint32_t *w, int j) -> int { return (w[j >> 2] >> (8 * (j & 3))) & 0xff; };
+        // FP32 Taylor coefficients of point j: from LDS in register mode, else made
+        // on the spot (w = -c2 / 4, or W = c2 for the full bubble)
+        auto coef = [&](int j) -> float4 {
+            if constexpr (REG) {
+                return tay[j * 64 + lane];
+            } else {
+                const double c2 = pval(6, j);
+                return taylor_consts<FULL>(pval(4, j), FULL ? c2 : -0.25 * c2);
+            }
+        };
         // weighted divided difference(s) of point j: the far form for every
         // lane, then the Taylor form where the lane is close to the diagonal
         auto value = [&](int j, PT &v, PT &v2) {
-            const double cy = cqy * pval(2, j) + sy * pval(3, j);
-            const double cx = cqx * pval(0, j) + sx * pval(1, j);
-            const PT b = static_cast<PT>(cx * (k1 - k2 * cy) + (k1 * cy - k3));
+            const double Y = cqy * pval(2, j) + sy * pval(3, j);
+            const double X = cqx * pval(0, j) + sx * pval(1, j);
+            const PT b = static_cast<PT>(fma(X, fma(-g, Y, 1.0), Y - k3));
             const PT a = static_cast<PT>(pval(4, j)), c1 = static_cast<PT>(pval(5, j)),
                      c2 = static_cast<PT>(pval(6, j));
             if constexpr (PAIRED) {
-                if constexpr (F32 && FULL) wdiv_t32_pair(a, c1, c2, b, v, v2);
-                else if constexpr (F32) wdiv_h32_pair(a, c1, c2, b, v, v2);
+                if constexpr (F32 && FULL) wdiv_t32_pair(a, c1, c2, b, [&] { return coef(j); }, v, v2);
+                else if constexpr (F32) wdiv_h32_pair(a, c1, c2, b, [&] { return coef(j); }, v, v2);
                 else if constexpr (FULL) wdiv_t64_pair(a, c1, c2, b, v, v2);
                 else wdiv_h64_pair(a, c1, c2, b, v, v2);
                 return;
             }
             const PT d = a - b;
             if constexpr (F32) {
-                if constexpr (FULL) {
-                    v = wdiv_t32_far(c1, c2, b, d);
-                    if (fabsf(d) < kTaylor32) v = wdiv_t32_near(a, c2, b);
-                } else {
-                    v = wdiv_h32_far(c1, c2, b, d);
-                    if (fabsf(d) < kTaylor32) v = wdiv_h32_near(a, c2, b);
-                }
+                v = FULL ? wdiv_t32_far(c1, c2, b, d) : wdiv_h32_far(c1, c2, b, d);
+                if (fabsf(d) < kTaylor32) v = taylor_poly(coef(j), d);
             } else {
                 if constexpr (FULL) {
                     v = wdiv_t64_far(c1, c2, b, d);
