@@ -71,6 +71,10 @@ struct frg_ctx_s {
     double *d_k[7] = {nullptr};
     double *d_yt = nullptr, *d_y5 = nullptr, *d_partial = nullptr, *d_state = nullptr;
     double *h_state = nullptr;
+    // reduced flow state (symmetric-vertex mode with orbit columns): nst entries,
+    // one per representative pp column and free index; y, the stage input and y5
+    int64_t nst = 0;
+    double *d_yr = nullptr, *d_ytr = nullptr, *d_y5r = nullptr;
     int nred = 256;
     int c_parts = 0;        // K parts the channel buffers d_C hold
     int ks_override = 0;    // FRG_KSPLIT
@@ -167,6 +171,11 @@ frg_status ensure_flow_ws(frg_ctx ctx) {
     for (int j = 0; j < 7; ++j) TRY(dalloc(ctx, &ctx->d_k[j], ctx->n3));
     TRY(dalloc(ctx, &ctx->d_yt, ctx->n3));
     TRY(dalloc(ctx, &ctx->d_y5, ctx->n3));
+    if (ctx->nst > 0) {
+        TRY(dalloc(ctx, &ctx->d_yr, static_cast<size_t>(ctx->nst)));
+        TRY(dalloc(ctx, &ctx->d_ytr, static_cast<size_t>(ctx->nst)));
+        TRY(dalloc(ctx, &ctx->d_y5r, static_cast<size_t>(ctx->nst)));
+    }
     TRY(dalloc(ctx, &ctx->d_partial, 2 * static_cast<size_t>(ctx->nred)));
     TRY(dalloc(ctx, &ctx->d_state, FRG_STATE_LEN));
     if (!ctx->h_state) HIPCHK(hipHostMalloc(reinterpret_cast<void **>(&ctx->h_state),
@@ -502,6 +511,7 @@ frg_status build_ktiles(frg_ctx ctx) {
     const int ks_v = ksplit_for(ctx, static_cast<int>(cols.size()), 16);
     for (int cls = 0; cls < 2; ++cls)
         TRY(build_tileset(ctx, cls, cols, rep, h, false, false, ks_v, ctx->ts_vsym[cls]));
+    ctx->nst = static_cast<int64_t>(ctx->ts_vsym[0].ncol) * N;
     return FRG_OK;
 }
 
@@ -561,6 +571,10 @@ const TileSet &tiles_of(frg_ctx ctx, int cls) {
     return ctx->vsym_on ? ctx->ts_vsym[cls] : ctx->ts_full[cls];
 }
 const int32_t *col_pos(frg_ctx ctx, int cls) { return tiles_of(ctx, cls).d_cmap; }
+// Flows keep their stage vectors reduced while the orbit columns are computed:
+// the rhs is then known at the representative columns only, and every other
+// entry is a copy (a C4v-invariant vertex stays invariant).
+bool red_state(frg_ctx ctx) { return ctx->vsym_on && ctx->kskip_on && ctx->nst > 0; }
 // K parts of the column set in use
 int ksplit(frg_ctx ctx) { return tiles_of(ctx, 0).kparts; }
 
@@ -623,9 +637,11 @@ enum RhsMode {
     RHS_STORED = 2    // the L_T already in the context's buffer (interaction flow steps)
 };
 
-// full rhs: F = scale * (-Cpp + Cc + Cd); scale = T when scale_by_T
+// full rhs: F = scale * (-Cpp + Cc + Cd); scale = T when scale_by_T.  red_out:
+// F at the representative entries only (the reduced flow state)
 frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, double c,
-                   const double *V, double *F, int scale_by_T, hipStream_t s, RhsMode mode = RHS_DT) {
+                   const double *V, double *F, int scale_by_T, hipStream_t s, RhsMode mode = RHS_DT,
+                   bool red_out = false) {
     const auto &g = ctx->g;
     const int N = g.N;
     const size_t NN = static_cast<size_t>(N) * N;
@@ -668,9 +684,12 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
         KTimer kt(ctx, FRG_K_COMBINE, s);
         double *Cs = ctx->d_C + 3 * KS * n3;
         frg::launch_sum_parts(ctx->d_C, split, KS, n3, computed_elems(ctx), Cs, s);
-        frg::launch_combine(Cs, Cs + n3, Cs + 2 * n3, false, N, 1, col_pos(ctx, 0), col_pos(ctx, 1), ctx->d_perm8,
-                            ctx->d_T,
-                            scale_by_T, F, s);
+        if (red_out)
+            frg::launch_combine_red(Cs, n3, N, ctx->nst, tiles_of(ctx, 0).d_cperm, col_pos(ctx, 1), ctx->d_perm8,
+                                    ctx->d_T, scale_by_T, F, s);
+        else
+            frg::launch_combine(Cs, Cs + n3, Cs + 2 * n3, false, N, 1, col_pos(ctx, 0), col_pos(ctx, 1),
+                                ctx->d_perm8, ctx->d_T, scale_by_T, F, s);
     }
     HIPCHK(hipGetLastError());
     return FRG_OK;
@@ -857,7 +876,7 @@ frg_status frg_destroy(frg_ctx ctx) {
                     ctx->d_colrow_pp, ctx->d_colrow_ph, ctx->d_pa64, ctx->d_T, ctx->d_pa32,
                     ctx->d_B64, ctx->d_B32, ctx->d_perm, ctx->d_ahl, ctx->d_g32, ctx->d_C,
                     ctx->d_yt, ctx->d_y5, ctx->d_partial, ctx->d_state, ctx->d_rowlist, ctx->d_rowlist_ph,
-                    ctx->d_colsym_pp, ctx->d_colsym_ph, ctx->d_perm8};
+                    ctx->d_colsym_pp, ctx->d_colsym_ph, ctx->d_perm8, ctx->d_yr, ctx->d_ytr, ctx->d_y5r};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (int c = 0; c < 2; ++c)
@@ -993,7 +1012,8 @@ frg_status frg_flow_init(frg_ctx ctx, const frg_flow_opts *o, const double *d_V,
     frg::launch_maxabs_to(ctx->n3, d_V, d_state, 24, ctx->d_partial, red_blocks(ctx->n3), s);
     if (o->stepper == FRG_DP54) {
         // first stage of the first step (later steps reuse the last stage: FSAL)
-        TRY(run_rhs(ctx, o->prec == FRG_PREC_SPLIT_BF16, 0.0, d_state, 0.0, d_V, ctx->d_k[0], 1, s));
+        TRY(run_rhs(ctx, o->prec == FRG_PREC_SPLIT_BF16, 0.0, d_state, 0.0, d_V, ctx->d_k[0], 1, s, RHS_DT,
+                    red_state(ctx)));
         frg::launch_state_set(d_state, FRG_ST_RHS, 1.0, s);
     }
     HIPCHK(hipGetLastError());
@@ -1007,32 +1027,54 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
     const RhsMode mode = iflow ? RHS_STORED : RHS_DT;
     const int scale = iflow ? 0 : 1;
     const bool split = o->prec == FRG_PREC_SPLIT_BF16;
-    const int64_t n = ctx->n3;
+    // reduced state: the stages combine nst-entry vectors (y gathered from V),
+    // and each stage input is expanded into a full vertex for the rhs
+    const bool red = red_state(ctx);
+    const int64_t n = red ? ctx->nst : ctx->n3;
+    const int N = ctx->g.N;
+    double *y = red ? ctx->d_yr : V, *yt = red ? ctx->d_ytr : ctx->d_yt, *y5 = red ? ctx->d_y5r : ctx->d_y5;
+    const int32_t *cperm = tiles_of(ctx, 0).d_cperm, *cmap = col_pos(ctx, 0);
+    // the rhs input of a stage whose combination went to out (its full form)
+    auto full_of = [&](double *out) -> const double * {
+        if (!red) return out;
+        double *full = out == y5 ? ctx->d_y5 : ctx->d_yt;
+        KTimer kt(ctx, FRG_K_RK, s);
+        frg::launch_vred_expand(out, N, cmap, ctx->d_perm8, nullptr, full, s);
+        return full;
+    };
+    // accepted step: V <- y5 (expanded when reduced)
+    auto accept_v = [&]() {
+        if (red) frg::launch_vred_expand(y5, N, cmap, ctx->d_perm8, state, V, s);
+        else frg::launch_accept_copy(n, state, y5, V, s);
+    };
+    if (red) {
+        KTimer kt(ctx, FRG_K_RK, s);
+        frg::launch_vred_gather(V, N, cperm, n, y, s);
+    }
     frg::RkStageArgs sa;
     std::memset(&sa, 0, sizeof(sa));
     sa.n = n;
-    sa.y = V;
+    sa.y = y;
     sa.state = state;
     for (int j = 0; j < 7; ++j) sa.k[j] = ctx->d_k[j];
     if (o->stepper == FRG_DP54) {
         for (int st = 1; st < 7; ++st) {
             sa.nk = st;
             for (int j = 0; j < 7; ++j) sa.coef[j] = j < st ? DP_A[st][j] : 0.0;
-            sa.out = st == 6 ? ctx->d_y5 : ctx->d_yt;
+            sa.out = st == 6 ? y5 : yt;
             {
                 KTimer kt(ctx, FRG_K_RK, s);
                 if (st == 1) frg::launch_pre_step(state, FRG_DP54, s);
                 frg::launch_rk_stage(sa, s);
             }
-            TRY(run_rhs(ctx, split, 0.0, state, DP_C[st], sa.out, ctx->d_k[st], scale, s, mode));
+            TRY(run_rhs(ctx, split, 0.0, state, DP_C[st], full_of(sa.out), ctx->d_k[st], scale, s, mode, red));
         }
         const double *kk[7];
         for (int j = 0; j < 7; ++j) kk[j] = ctx->d_k[j];
         KTimer kt(ctx, FRG_K_RK, s);
-        frg::launch_dp_error(n, V, ctx->d_y5, kk, DP_E, o->rtol, o->atol, state, ctx->d_partial,
-                             red_blocks(n), s);
+        frg::launch_dp_error(n, y, y5, kk, DP_E, o->rtol, o->atol, state, ctx->d_partial, red_blocks(n), s);
         frg::launch_dp_control(state, log, log_cap, o->vmax, o->max_steps, FRG_DP54, s);
-        frg::launch_accept_copy(n, state, ctx->d_y5, V, s);
+        accept_v();
         frg::launch_accept_copy(n, state, ctx->d_k[6], ctx->d_k[0], s);
     } else {
         frg::launch_pre_step(state, FRG_RK4, s);
@@ -1042,20 +1084,20 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
             if (st > 0) {
                 sa.nk = st;
                 for (int j = 0; j < 7; ++j) sa.coef[j] = (j == st - 1) ? cs[st] : 0.0;
-                sa.out = ctx->d_yt;
+                sa.out = yt;
                 frg::launch_rk_stage(sa, s);
-                in = ctx->d_yt;
+                in = full_of(yt);
             }
-            TRY(run_rhs(ctx, split, 0.0, state, cs[st], in, ctx->d_k[st], scale, s, mode));
+            TRY(run_rhs(ctx, split, 0.0, state, cs[st], in, ctx->d_k[st], scale, s, mode, red));
         }
         sa.nk = 4;
         const double b[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
         for (int j = 0; j < 7; ++j) sa.coef[j] = j < 4 ? b[j] : 0.0;
-        sa.out = ctx->d_y5;
+        sa.out = y5;
         frg::launch_rk_stage(sa, s);
-        frg::launch_maxabs_to(n, ctx->d_y5, state, 20, ctx->d_partial, red_blocks(n), s);
+        frg::launch_maxabs_to(n, y5, state, 20, ctx->d_partial, red_blocks(n), s);
         frg::launch_dp_control(state, log, log_cap, o->vmax, o->max_steps, FRG_RK4, s);
-        frg::launch_accept_copy(n, state, ctx->d_y5, V, s);
+        accept_v();
     }
     HIPCHK(hipGetLastError());
     return FRG_OK;
@@ -1194,6 +1236,26 @@ frg_flow_opts stepper_opts(const frg_iflow_opts *o) {
     return f;
 }
 
+// A toggle that changes the form of the flow state converts the rhs a running
+// flow keeps for its next step (k[0], first same as last) to the new form.
+frg_status convert_k0(frg_ctx ctx, bool was_red) {
+    const bool now = red_state(ctx);
+    if (was_red == now || !ctx->d_k[0] || !ctx->d_ytr) return FRG_OK;
+    HIPCHK(hipDeviceSynchronize());
+    const int N = ctx->g.N;
+    if (now) {
+        frg::launch_vred_gather(ctx->d_k[0], N, ctx->ts_vsym[0].d_cperm, ctx->nst, ctx->d_ytr, nullptr);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpy(ctx->d_k[0], ctx->d_ytr, sizeof(double) * ctx->nst, hipMemcpyDeviceToDevice));
+    } else {
+        frg::launch_vred_expand(ctx->d_k[0], N, ctx->ts_vsym[0].d_cmap, ctx->d_perm8, nullptr, ctx->d_yt, nullptr);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpy(ctx->d_k[0], ctx->d_yt, sizeof(double) * ctx->n3, hipMemcpyDeviceToDevice));
+    }
+    HIPCHK(hipDeviceSynchronize());
+    return FRG_OK;
+}
+
 frg_status check_vsym_v(frg_ctx ctx, const double *d_V, hipStream_t s) {
     if (!ctx->vsym_on) return FRG_OK;   // a flow from a C4v-invariant vertex stays invariant
     double dev = 0.0;
@@ -1267,7 +1329,7 @@ frg_status frg_iflow_init(frg_ctx ctx, const frg_iflow_opts *o, const double *d_
     if (o->stepper == FRG_RK4) frg::launch_state_set(d_state, 27, o->fixed_steps, s);
     frg::launch_maxabs_to(ctx->n3, d_V, d_state, 24, ctx->d_partial, red_blocks(ctx->n3), s);
     if (o->stepper == FRG_DP54) {
-        TRY(run_rhs(ctx, split, o->T, d_state, 0.0, d_V, ctx->d_k[0], 0, s, RHS_STORED));
+        TRY(run_rhs(ctx, split, o->T, d_state, 0.0, d_V, ctx->d_k[0], 0, s, RHS_STORED, red_state(ctx)));
         frg::launch_state_set(d_state, FRG_ST_RHS, 1.0, s);
     }
     HIPCHK(hipGetLastError());
@@ -1342,8 +1404,9 @@ frg_status frg_set_vsym(frg_ctx ctx, int32_t enable) {
     TRY(check_ctx(ctx));
     if (enable && !ctx->sym_avail)
         return fail(FRG_ENOTSUP, "symmetric-vertex mode needs an exactly C4v covariant grid (N % 8 == 0)");
+    const bool was_red = red_state(ctx);
     ctx->vsym_on = enable != 0;
-    return FRG_OK;
+    return convert_k0(ctx, was_red);
 }
 
 frg_status frg_vsym(frg_ctx ctx, int32_t *active, int32_t *columns) {
@@ -1362,8 +1425,9 @@ frg_status frg_check_vsym(frg_ctx ctx, const double *d_V, double *rel_dev, void 
 frg_status frg_set_kskip(frg_ctx ctx, int32_t enable) {
     TRY(check_ctx(ctx));
     if (!enable) TRY(ensure_dense_tiles(ctx));
+    const bool was_red = red_state(ctx);
     ctx->kskip_on = enable != 0;
-    return FRG_OK;
+    return convert_k0(ctx, was_red);
 }
 
 frg_status frg_kskip(frg_ctx ctx, int32_t *active, double *executed_frac) {
@@ -1429,6 +1493,8 @@ struct frg_batch_s {
     frg::FusedContractArgs *d_ca[3] = {nullptr, nullptr, nullptr};   // per source (V, yt, y5)
     double **d_states = nullptr;
     double *d_state_all = nullptr, *h_state_all = nullptr;
+    int2 *d_it_st = nullptr;   // (flow, block of 256 entries of its state: reduced or full)
+    int n_st = 0;
     int2 *d_it_prep = nullptr, *d_it_bub = nullptr, *d_it_n3 = nullptr, *d_it_red = nullptr,
          *d_it_con = nullptr, *d_it_comb = nullptr, *d_it_sum = nullptr, *d_it_lay = nullptr;
     int n_bub_pair = 0;   // leading items of it_bub that belong to flows with row pairs
@@ -1476,7 +1542,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     std::vector<frg::FusedContractArgs> ca[3];
     for (int s = 0; s < 3; ++s) ca[s].resize(b->n);
     std::vector<double *> st(b->n);
-    std::vector<int2> it_prep, it_bub, it_bub_single, it_n3, it_red, it_comb, it_sum, it_lay;
+    std::vector<int2> it_prep, it_bub, it_bub_single, it_n3, it_st, it_red, it_comb, it_sum, it_lay;
     struct Item { int2 it; int cls, queue; double flow_cost, cost; };
     std::vector<Item> con;
     for (int f = 0; f < b->n; ++f) {
@@ -1508,6 +1574,10 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         A.ppos = col_pos(c, 0); A.phpos = col_pos(c, 1);
         A.perm8 = c->d_perm8;
         A.nel = computed_elems(c);
+        A.red = red_state(c) ? 1 : 0;
+        A.nst = c->nst;
+        A.yr = c->d_yr; A.ytr = c->d_ytr; A.y5r = c->d_y5r;
+        A.cperm_pp = tiles_of(c, 0).d_cperm;
         st[f] = A.state;
         frg::BubbleArgs bb = bubble_args(c, split, bpp, bph);
         if (sym) {
@@ -1542,8 +1612,11 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
             for (int a = 0; a < g.N; ++a)
                 (bb.rowlist_ph ? it_bub : it_bub_single).push_back(make_int2(f, (ch << 8) | a));
         for (int64_t k = 0; k < (n3 + 255) / 256; ++k) it_n3.push_back(make_int2(f, static_cast<int>(k)));
+        const int64_t nst = A.red ? c->nst : n3;
+        for (int64_t k = 0; k < (nst + 255) / 256; ++k) it_st.push_back(make_int2(f, static_cast<int>(k)));
         for (int k = 0; k < frg::layout_blocks(g.N); ++k) it_lay.push_back(make_int2(f, k));
-        for (int k = 0; k < frg::combine_tiles(g.N); ++k) it_comb.push_back(make_int2(f, k));
+        const int ncomb = A.red ? static_cast<int>((c->nst + 255) / 256) : frg::combine_tiles(g.N);
+        for (int k = 0; k < ncomb; ++k) it_comb.push_back(make_int2(f, k));
         for (int64_t k = 0; k < (3 * A.nel + frg::kSumPartsPerBlock - 1) / frg::kSumPartsPerBlock; ++k)
             it_sum.push_back(make_int2(f, static_cast<int>(k)));
         for (int k = 0; k < A.nred; ++k) it_red.push_back(make_int2(f, k));
@@ -1612,6 +1685,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     it_bub.insert(it_bub.end(), it_bub_single.begin(), it_bub_single.end());
     TRY(bupload(&b->d_it_bub, it_bub));
     TRY(bupload(&b->d_it_n3, it_n3));
+    TRY(bupload(&b->d_it_st, it_st));
     TRY(bupload(&b->d_it_red, it_red));
     TRY(bupload(&b->d_it_con, it_con));
     TRY(bupload(&b->d_it_comb, it_comb));
@@ -1620,6 +1694,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     b->n_prep = static_cast<int>(it_prep.size());
     b->n_bub = static_cast<int>(it_bub.size());
     b->n_n3 = static_cast<int>(it_n3.size());
+    b->n_st = static_cast<int>(it_st.size());
     b->n_red = static_cast<int>(it_red.size());
     b->n_con = static_cast<int>(it_con.size());
     b->n_comb = static_cast<int>(it_comb.size());
@@ -1655,11 +1730,13 @@ void batch_rhs_launch(frg_batch b, bool split, double c_stage, int src, int stag
 void batch_step_launch(frg_batch b, const frg_flow_opts *o, hipStream_t s) {
     const bool split = o->prec == FRG_PREC_SPLIT_BF16;
     frg::launch_step_ctl_b(b->d_fa, b->n, 1, nullptr, 0, o->vmax, o->max_steps, s);
+    frg::launch_vred_b(b->d_fa, b->d_it_st, b->n_st, frg::SRC_V, s);   // reduced flows: y from V
     for (int st = 1; st < 7; ++st) {
         double coef[7] = {0};
         for (int j = 0; j < st; ++j) coef[j] = DP_A[st][j];
         const int dst = st == 6 ? frg::SRC_Y5 : frg::SRC_YT;
-        frg::launch_rk_stage_b(b->d_fa, b->d_it_n3, b->n_n3, coef, st, dst, s);
+        frg::launch_rk_stage_b(b->d_fa, b->d_it_st, b->n_st, coef, st, dst, s);
+        frg::launch_vred_b(b->d_fa, b->d_it_n3, b->n_n3, dst, s);         // reduced flows: full rhs input
         batch_rhs_launch(b, split, DP_C[st], dst, st, s);
     }
     frg::launch_dp_error_b(b->d_fa, b->d_it_red, b->n_red, b->n, DP_E, o->rtol, o->atol, s);
@@ -1724,7 +1801,7 @@ frg_status frg_batch_destroy(frg_batch b) {
     if (!b) return FRG_OK;
     for (frg_ctx c : b->ctx) frg_destroy(c);
     void *ptrs[] = {b->d_fa, b->d_ba, b->d_ca[0], b->d_ca[1], b->d_ca[2], b->d_states, b->d_state_all,
-                    b->d_it_prep, b->d_it_bub, b->d_it_n3, b->d_it_red, b->d_it_con, b->d_counter,
+                    b->d_it_prep, b->d_it_bub, b->d_it_n3, b->d_it_st, b->d_it_red, b->d_it_con, b->d_counter,
                     b->d_q, b->d_it_flat, b->d_it_comb, b->d_it_sum, b->d_it_lay};
     for (void *p : ptrs)
         if (p) hipFree(p);

@@ -167,6 +167,15 @@ void launch_state_set(double *state, int slot, double v, hipStream_t s);
 void launch_pre_step(double *state, int stepper, hipStream_t s);
 void launch_dp_control(double *state, double *log, int log_cap, double vmax, int max_steps,
                        int stepper, hipStream_t s);
+// Reduced flow state of the symmetric-vertex mode (entry pos * N + m = V(cperm[pos], m)):
+// gather it from a full V, expand it into a full V (only accepted steps when gate,
+// the flow state, is given), and the rhs at the representative entries only.
+void launch_vred_gather(const double *V, int N, const int32_t *cperm, int64_t nst, double *Vr, hipStream_t s);
+void launch_vred_expand(const double *Vr, int N, const int32_t *cmap, const int16_t *perm8, const double *gate,
+                        double *V, hipStream_t s);
+void launch_combine_red(const double *Cs, int64_t n3, int N, int64_t nst, const int32_t *cperm,
+                        const int32_t *phpos, const int16_t *perm8, const double *Tdev, int scale_by_T, double *F,
+                        hipStream_t s);
 void launch_accept_copy(int64_t n, const double *state, const double *src, double *dst,
                         hipStream_t s);
 void launch_state_init(double *state, double s0, double h, double s_min, hipStream_t s);
@@ -194,8 +203,18 @@ struct FlowArgs {
     int64_t nel;   // elements per channel actually computed (ncol * N)
     const int16_t *perm8;   // [8][N] C4v patch maps
     const int32_t *ppos, *phpos;   // tile position of each pp / ph column
+    // reduced state (symmetric-vertex mode with orbit columns): the stage vectors
+    // k, yr, ytr, y5r hold nst = ncol_pp * N entries (pp representative columns
+    // cperm_pp in tile order); yt and y5 then hold the full rhs inputs
+    int red;
+    int64_t nst;
+    double *yr, *ytr, *y5r;
+    const int32_t *cperm_pp;
 };
 enum { SRC_V = 0, SRC_YT = 1, SRC_Y5 = 2 };
+// batched: dst SRC_V gathers yr from V (items over the reduced length), SRC_YT /
+// SRC_Y5 expand ytr / y5r into yt / y5 (items over n3); other flows skip
+void launch_vred_b(const FlowArgs *fa, const int2 *items, int nitems, int dst, hipStream_t s);
 
 int bubble_rows_per_block();
 // items: the first npaired belong to flows with row pairs (rowlist_ph set)

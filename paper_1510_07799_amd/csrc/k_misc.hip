@@ -399,6 +399,69 @@ __device__ void combine_body(int N, int KS, int64_t n3, const PT *__restrict__ C
     }
 }
 
+// Reduced flow state of the symmetric-vertex mode: entry i = pos * N + m holds
+// V(c, m) for the representative pp column c = cperm[pos] = j1 N + j2 (the
+// column tile order of the orbit columns); any column follows from
+//   V(c, m) = Vr[(cmap[c] >> 3) N + perm8[cmap[c] & 7][m]],
+// the relation the channel values of those columns obey.
+__device__ __forceinline__ double vred_at(const double *__restrict__ Vr, int N, const int32_t *__restrict__ cmap,
+                                          const int16_t *__restrict__ perm8, int64_t i) {
+    const int64_t c = i / N;
+    const int32_t cm = cmap[c];
+    return Vr[static_cast<int64_t>(cm >> 3) * N + perm8[(cm & 7) * N + static_cast<int>(i - c * N)]];
+}
+__device__ __forceinline__ double vred_gather_at(const double *__restrict__ V, int N,
+                                                 const int32_t *__restrict__ cperm, int64_t i) {
+    const int64_t pos = i / N;
+    return V[static_cast<int64_t>(cperm[pos]) * N + (i - pos * N)];
+}
+// -Cpp + Cc + Cd at reduced entry i (the same sums, in the same order, as the
+// full assembly above; the pp value is the stored column itself)
+__device__ __forceinline__ double combine_red_at(int N, const double *__restrict__ Cpp,
+                                                 const double *__restrict__ Cc, const double *__restrict__ Cd,
+                                                 const int32_t *__restrict__ cperm, const int32_t *__restrict__ phpos,
+                                                 const int16_t *__restrict__ perm8, int64_t i) {
+    const int64_t pos = i / N;
+    const int j3 = static_cast<int>(i - pos * N);
+    const int c = cperm[pos], j1 = c / N, j2 = c - j1 * N;
+    auto at_of = [&](int32_t cm, int m) -> int64_t {
+        return static_cast<int64_t>(cm >> 3) * N + perm8[(cm & 7) * N + m];
+    };
+    double v = -Cpp[i];
+    v += Cc[at_of(phpos[j2 * N + j3], j1)];
+    v += Cd[at_of(phpos[j1 * N + j3], j2)];
+    return v;
+}
+
+__global__ __launch_bounds__(256) void vred_gather_kernel(const double *__restrict__ V, int N,
+                                                          const int32_t *__restrict__ cperm, int64_t nst,
+                                                          double *__restrict__ Vr) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < nst) Vr[i] = vred_gather_at(V, N, cperm, i);
+}
+
+// gate: when given, only accepted steps (state slot 23) write
+__global__ __launch_bounds__(256) void vred_expand_kernel(const double *__restrict__ Vr, int N,
+                                                          const int32_t *__restrict__ cmap,
+                                                          const int16_t *__restrict__ perm8, int64_t n3,
+                                                          const double *gate, double *__restrict__ V) {
+    if (gate && gate[23] == 0.0) return;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n3) V[i] = vred_at(Vr, N, cmap, perm8, i);
+}
+
+__global__ __launch_bounds__(256) void combine_red_kernel(const double *__restrict__ Cs, int64_t n3, int N,
+                                                          int64_t nst, const int32_t *__restrict__ cperm,
+                                                          const int32_t *__restrict__ phpos,
+                                                          const int16_t *__restrict__ perm8,
+                                                          const double *__restrict__ Tdev, int scale_by_T,
+                                                          double *__restrict__ F) {
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= nst) return;
+    const double scale = scale_by_T ? Tdev[0] : 1.0;
+    F[i] = scale * combine_red_at(N, Cs, Cs + n3, Cs + 2 * n3, cperm, phpos, perm8, i);
+}
+
 // Sum of the K-part partials, four consecutive elements per thread (streams
 // of contiguous loads, one per part).
 template <typename PT>
@@ -739,8 +802,13 @@ __global__ __launch_bounds__(256) void combine_b_kernel(const FlowArgs *__restri
     const FlowArgs &f = fa[it.x];
     if (flow_stopped(f)) return;
     const int64_t n = f.n3;
-    const int KS = f.KS;
-    (void)KS;
+    if (f.red) {   // item = block of 256 reduced entries
+        const int64_t i = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x;
+        if (i < f.nst)
+            f.k[stage][i] = f.Tdev[0] * combine_red_at(f.N, f.Csum, f.Csum + n, f.Csum + 2 * n, f.cperm_pp,
+                                                       f.phpos, f.perm8, i);
+        return;
+    }
     combine_body(f.N, 1, n, static_cast<const double *>(f.Csum), f.Csum + n, f.Csum + 2 * n, f.ppos, f.phpos,
                  f.perm8, f.Tdev[0], f.k[stage], it.y, sF);
 }
@@ -764,13 +832,28 @@ __global__ void rk_stage_b_kernel(const FlowArgs *__restrict__ fa, const int2 *_
     const FlowArgs &f = fa[it.x];
     if (flow_stopped(f)) return;
     const int64_t i = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x;
-    if (i >= f.n3) return;
+    if (i >= (f.red ? f.nst : f.n3)) return;
     const double h = f.state[FRG_ST_H];
     double acc = 0.0;
     for (int j = 0; j < nk; ++j)
         if (coef.c[j] != 0.0) acc += coef.c[j] * f.k[j][i];
-    double *out = dst == SRC_YT ? f.yt : f.y5;
-    out[i] = f.V[i] + h * acc;
+    double *out = dst == SRC_YT ? (f.red ? f.ytr : f.yt) : (f.red ? f.y5r : f.y5);
+    out[i] = (f.red ? f.yr : f.V)[i] + h * acc;
+}
+
+// reduced flows: y <- the representative entries of V (step start), or the full
+// rhs input yt / y5 <- the expansion of its reduced stage vector
+__global__ __launch_bounds__(256) void vred_b_kernel(const FlowArgs *__restrict__ fa, const int2 *__restrict__ items,
+                                                     int dst) {
+    const int2 it = items[blockIdx.x];
+    const FlowArgs &f = fa[it.x];
+    if (!f.red || flow_stopped(f)) return;
+    const int64_t i = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x;
+    if (dst == SRC_V) {
+        if (i < f.nst) f.yr[i] = vred_gather_at(f.V, f.N, f.cperm_pp, i);
+    } else if (i < f.n3) {
+        (dst == SRC_YT ? f.yt : f.y5)[i] = vred_at(dst == SRC_YT ? f.ytr : f.y5r, f.N, f.ppos, f.perm8, i);
+    }
 }
 
 // error norm partials: item block it.y of flow it.x covers a grid-stride slice
@@ -782,14 +865,16 @@ __global__ void dp_error_b_kernel(const FlowArgs *__restrict__ fa, const int2 *_
     if (flow_stopped(f)) return;
     const double h = f.state[FRG_ST_H];
     double emax = 0.0, vmax = 0.0;
-    for (int64_t i = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x; i < f.n3;
+    const int64_t n = f.red ? f.nst : f.n3;
+    const double *yv = f.red ? f.yr : f.V, *y5v = f.red ? f.y5r : f.y5;
+    for (int64_t i = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x; i < n;
          i += static_cast<int64_t>(f.nred) * blockDim.x) {
         double d = 0.0;
 #pragma unroll
         for (int j = 0; j < 7; ++j) d += e.c[j] * f.k[j][i];
         d = fabs(h * d);
-        const double y5 = f.y5[i];
-        const double q = d / (atol + rtol * fmax(fabs(f.V[i]), fabs(y5)));
+        const double y5 = y5v[i];
+        const double q = d / (atol + rtol * fmax(fabs(yv[i]), fabs(y5)));
         emax = (q > emax || q != q) ? q : emax;
         const double av = fabs(y5);
         vmax = (av > vmax || av != av) ? av : vmax;
@@ -834,6 +919,11 @@ __global__ void accept_b_kernel(const FlowArgs *__restrict__ fa, const int2 *__r
     if (f.state[23] == 0.0) return;
     const int64_t i = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x;
     if (i >= f.n3) return;
+    if (f.red) {
+        f.V[i] = vred_at(f.y5r, f.N, f.ppos, f.perm8, i);
+        if (i < f.nst) f.k[0][i] = f.k[6][i];
+        return;
+    }
     f.V[i] = f.y5[i];
     f.k[0][i] = f.k[6][i];
 }
@@ -941,6 +1031,25 @@ void launch_dp_control(double *state, double *log, int log_cap, double vmax, int
 
 void launch_pre_step(double *state, int stepper, hipStream_t s) {
     hipLaunchKernelGGL(pre_step_kernel, dim3(1), dim3(64), 0, s, state, stepper);
+}
+
+void launch_vred_gather(const double *V, int N, const int32_t *cperm, int64_t nst, double *Vr, hipStream_t s) {
+    hipLaunchKernelGGL(vred_gather_kernel, dim3(blocks_for(nst, 256)), dim3(256), 0, s, V, N, cperm, nst, Vr);
+}
+void launch_vred_expand(const double *Vr, int N, const int32_t *cmap, const int16_t *perm8, const double *gate,
+                        double *V, hipStream_t s) {
+    const int64_t n3 = static_cast<int64_t>(N) * N * N;
+    hipLaunchKernelGGL(vred_expand_kernel, dim3(blocks_for(n3, 256)), dim3(256), 0, s, Vr, N, cmap, perm8, n3,
+                       gate, V);
+}
+void launch_combine_red(const double *Cs, int64_t n3, int N, int64_t nst, const int32_t *cperm,
+                        const int32_t *phpos, const int16_t *perm8, const double *Tdev, int scale_by_T, double *F,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(combine_red_kernel, dim3(blocks_for(nst, 256)), dim3(256), 0, s, Cs, n3, N, nst, cperm,
+                       phpos, perm8, Tdev, scale_by_T, F);
+}
+void launch_vred_b(const FlowArgs *fa, const int2 *items, int nitems, int dst, hipStream_t s) {
+    if (nitems > 0) hipLaunchKernelGGL(vred_b_kernel, dim3(nitems), dim3(256), 0, s, fa, items, dst);
 }
 
 void launch_accept_copy(int64_t n, const double *state, const double *src, double *dst,

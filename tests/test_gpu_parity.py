@@ -459,6 +459,82 @@ def test_symmetric_vertex_flows_single_and_batched():
     b.close()
 
 
+def test_symmetric_vertex_flow_from_random_invariant_vertex():
+    """Flows in symmetric-vertex mode keep one entry per orbit column and free
+    index and expand it for every rhs input and for V: from a random C4v-invariant
+    vertex (so a wrong gather or expansion index shows at once), fixed RK4 and
+    DP5(4) steps follow the every-column flow, and V stays exactly invariant.  In
+    the split path the two modes round differently, so both are held to the FP64
+    flow instead, the symmetric one within three times the other's error."""
+    om, g = pair(FAST32)
+    N = om.N
+    V0 = I.random_vertex(N, om.U, seed=53, amp=0.3, symmetrise=True)
+
+    def run(stepper, prec, vs):
+        kw = dict(fixed_steps=4) if stepper == "rk4" else dict(rtol=1e-6, atol=1e-10, h0=-0.05)
+        o = frg.flow_opts(stepper, prec, T0=1.0, T_min=0.3, vmax=1e6, **kw)
+        g.set_vsym(vs)
+        try:
+            V = dev(V0)
+            st = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+            g.flow_init(o, V, st)
+            for _ in range(4):
+                g.flow_step(o, V, st)
+            torch.cuda.synchronize()
+            return V.cpu().numpy(), st.cpu().numpy()
+        finally:
+            g.set_vsym(False)
+
+    for stepper in ("rk4", "dp54"):
+        (Vf, sf), (Vs, ss) = run(stepper, frg.PREC_FP64, False), run(stepper, frg.PREC_FP64, True)
+        print(f"[vsym flow] {stepper} FP64: {nrel(Vs, Vf):.2e}", flush=True)
+        # the error norm differs in its rounding (other K-part sums), so the
+        # DP5(4) step sizes differ slightly
+        assert ss[frg.ST_S] == pytest.approx(sf[frg.ST_S], abs=1e-10)
+        assert nrel(Vs, Vf) <= 1e-10
+        assert nrel(Vs, V0) > 1e-3   # the flow moved
+        for o_ in range(1, 8):
+            pm = I.c4v_patch_perm(N, o_)
+            assert np.array_equal(Vs[np.ix_(pm, pm, pm)], Vs)
+        if stepper == "rk4":
+            (Vfs, _), (Vss, _) = (run(stepper, frg.PREC_SPLIT_BF16, False),
+                                  run(stepper, frg.PREC_SPLIT_BF16, True))
+            ef, es = nrel(Vfs, Vf), nrel(Vss, Vf)
+            print(f"[vsym flow] rk4 split against FP64: every column {ef:.2e}, symmetric {es:.2e}", flush=True)
+            assert es <= max(3.0 * ef, 1e-5)
+            for o_ in range(1, 8):
+                pm = I.c4v_patch_perm(N, o_)
+                assert np.array_equal(Vss[np.ix_(pm, pm, pm)], Vss)
+
+
+def test_symmetric_vertex_toggled_mid_flow():
+    """Switching the mode between steps converts the rhs a DP5(4) flow carries to
+    its next step (first same as last) to the new form: a flow switched on after
+    two steps and off after two more follows the every-column flow."""
+    om, g = pair(FAST32)
+    N = om.N
+    V0 = I.random_vertex(N, om.U, seed=54, amp=0.3, symmetrise=True)
+    o = frg.flow_opts("dp54", frg.PREC_FP64, T0=1.0, T_min=0.2, rtol=1e-6, atol=1e-10, vmax=1e6, h0=-0.05)
+    runs = []
+    for pattern in ((False,) * 6, (False, False, True, True, False, False)):
+        V = dev(V0)
+        st = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+        g.set_vsym(False)
+        g.flow_init(o, V, st)
+        try:
+            for vs in pattern:
+                g.set_vsym(vs)
+                g.flow_step(o, V, st)
+            torch.cuda.synchronize()
+        finally:
+            g.set_vsym(False)
+        runs.append((V.cpu().numpy(), st.cpu().numpy()))
+    (Va, sa), (Vb, sb) = runs
+    print(f"[vsym toggle] {nrel(Vb, Va):.2e}", flush=True)
+    assert sb[frg.ST_S] == pytest.approx(sa[frg.ST_S], abs=1e-10)
+    assert nrel(Vb, Va) <= 1e-10
+
+
 def test_flow_step_graph_replay_matches_eager():
     """Single-flow steps replay one captured graph; with eager rhs work on the
     same context between the replays they give bit for bit the state of the
