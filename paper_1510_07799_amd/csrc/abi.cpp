@@ -799,9 +799,9 @@ static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out) {
 
     frg_ctx ctx = new frg_ctx_s();
     ctx->device = dev;
-    if (n_batch > 1) {
+    if (n_batch > 1) {   // measured at N = 96: 8 parts for 16 flows, 4 for 64
         ctx->ks_target = (6912 + n_batch - 1) / n_batch;
-        ctx->ks_lo = 2;
+        ctx->ks_lo = 4;
     }
     if (const char *e = std::getenv("FRG_KSPLIT")) ctx->ks_override = std::atoi(e);
     frg::build_geometry(*p, ctx->g);
