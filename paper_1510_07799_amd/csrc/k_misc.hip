@@ -403,17 +403,18 @@ __device__ void combine_body(int N, int KS, int64_t n3, const PT *__restrict__ C
 // V(c, m) for the representative pp column c = cperm[pos] = j1 N + j2 (the
 // column tile order of the orbit columns); any column follows from
 //   V(c, m) = Vr[(cmap[c] >> 3) N + perm8[cmap[c] & 7][m]],
-// the relation the channel values of those columns obey.
+// the relation the channel values of those columns obey.  Indices fit 32 bits
+// (N^3 <= 2^24), so the divisions by N are 32-bit ones.
 __device__ __forceinline__ double vred_at(const double *__restrict__ Vr, int N, const int32_t *__restrict__ cmap,
                                           const int16_t *__restrict__ perm8, int64_t i) {
-    const int64_t c = i / N;
+    const uint32_t ii = static_cast<uint32_t>(i), c = ii / static_cast<uint32_t>(N);
     const int32_t cm = cmap[c];
-    return Vr[static_cast<int64_t>(cm >> 3) * N + perm8[(cm & 7) * N + static_cast<int>(i - c * N)]];
+    return Vr[(cm >> 3) * N + perm8[(cm & 7) * N + static_cast<int>(ii - c * N)]];
 }
 __device__ __forceinline__ double vred_gather_at(const double *__restrict__ V, int N,
                                                  const int32_t *__restrict__ cperm, int64_t i) {
-    const int64_t pos = i / N;
-    return V[static_cast<int64_t>(cperm[pos]) * N + (i - pos * N)];
+    const uint32_t ii = static_cast<uint32_t>(i), pos = ii / static_cast<uint32_t>(N);
+    return V[static_cast<uint32_t>(cperm[pos]) * N + (ii - pos * N)];
 }
 // -Cpp + Cc + Cd at reduced entry i (the same sums, in the same order, as the
 // full assembly above; the pp value is the stored column itself)
@@ -421,8 +422,8 @@ __device__ __forceinline__ double combine_red_at(int N, const double *__restrict
                                                  const double *__restrict__ Cc, const double *__restrict__ Cd,
                                                  const int32_t *__restrict__ cperm, const int32_t *__restrict__ phpos,
                                                  const int16_t *__restrict__ perm8, int64_t i) {
-    const int64_t pos = i / N;
-    const int j3 = static_cast<int>(i - pos * N);
+    const uint32_t ii = static_cast<uint32_t>(i), pos = ii / static_cast<uint32_t>(N);
+    const int j3 = static_cast<int>(ii - pos * N);
     const int c = cperm[pos], j1 = c / N, j2 = c - j1 * N;
     auto at_of = [&](int32_t cm, int m) -> int64_t {
         return static_cast<int64_t>(cm >> 3) * N + perm8[(cm & 7) * N + m];
