@@ -638,10 +638,11 @@ enum RhsMode {
 };
 
 // full rhs: F = scale * (-Cpp + Cc + Cd); scale = T when scale_by_T.  red_out:
-// F at the representative entries only (the reduced flow state)
+// F at the representative entries only (the reduced flow state).  Vred: the
+// split path reads its input from this reduced state instead of V
 frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, double c,
                    const double *V, double *F, int scale_by_T, hipStream_t s, RhsMode mode = RHS_DT,
-                   bool red_out = false) {
+                   bool red_out = false, const double *Vred = nullptr) {
     const auto &g = ctx->g;
     const int N = g.N;
     const size_t NN = static_cast<size_t>(N) * N;
@@ -673,6 +674,8 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     {
         KTimer kt(ctx, FRG_K_LAYOUT, s);
         if (!split) frg::launch_layout_f64(V, N, ctx->d_perm, s);
+        else if (Vred) frg::launch_layout_split_red(Vred, N, col_pos(ctx, 0), col_pos(ctx, 1), ctx->d_perm8,
+                                                    ctx->d_ahl, ctx->d_g32, s);
         else frg::launch_layout_split(V, N, ctx->d_ahl, ctx->d_g32, s);
     }
     set_operands(a, split, V, ctx->d_perm, ctx->d_ahl, ctx->d_g32, n3);
@@ -1034,9 +1037,10 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
     const int N = ctx->g.N;
     double *y = red ? ctx->d_yr : V, *yt = red ? ctx->d_ytr : ctx->d_yt, *y5 = red ? ctx->d_y5r : ctx->d_y5;
     const int32_t *cperm = tiles_of(ctx, 0).d_cperm, *cmap = col_pos(ctx, 0);
-    // the rhs input of a stage whose combination went to out (its full form)
+    // the rhs input of a stage whose combination went to out (its full form;
+    // the split layout reads a reduced one directly)
     auto full_of = [&](double *out) -> const double * {
-        if (!red) return out;
+        if (!red || split) return out;
         double *full = out == y5 ? ctx->d_y5 : ctx->d_yt;
         KTimer kt(ctx, FRG_K_RK, s);
         frg::launch_vred_expand(out, N, cmap, ctx->d_perm8, nullptr, full, s);
@@ -1067,7 +1071,8 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
                 if (st == 1) frg::launch_pre_step(state, FRG_DP54, s);
                 frg::launch_rk_stage(sa, s);
             }
-            TRY(run_rhs(ctx, split, 0.0, state, DP_C[st], full_of(sa.out), ctx->d_k[st], scale, s, mode, red));
+            TRY(run_rhs(ctx, split, 0.0, state, DP_C[st], full_of(sa.out), ctx->d_k[st], scale, s, mode, red,
+                        red && split ? sa.out : nullptr));
         }
         const double *kk[7];
         for (int j = 0; j < 7; ++j) kk[j] = ctx->d_k[j];
@@ -1088,7 +1093,8 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
                 frg::launch_rk_stage(sa, s);
                 in = full_of(yt);
             }
-            TRY(run_rhs(ctx, split, 0.0, state, cs[st], in, ctx->d_k[st], scale, s, mode, red));
+            TRY(run_rhs(ctx, split, 0.0, state, cs[st], in, ctx->d_k[st], scale, s, mode, red,
+                        red && split && st > 0 ? yt : nullptr));
         }
         sa.nk = 4;
         const double b[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
@@ -1736,7 +1742,8 @@ void batch_step_launch(frg_batch b, const frg_flow_opts *o, hipStream_t s) {
         for (int j = 0; j < st; ++j) coef[j] = DP_A[st][j];
         const int dst = st == 6 ? frg::SRC_Y5 : frg::SRC_YT;
         frg::launch_rk_stage_b(b->d_fa, b->d_it_st, b->n_st, coef, st, dst, s);
-        frg::launch_vred_b(b->d_fa, b->d_it_n3, b->n_n3, dst, s);         // reduced flows: full rhs input
+        // reduced flows: the full rhs input (the split layout reads the reduced one)
+        if (!split) frg::launch_vred_b(b->d_fa, b->d_it_n3, b->n_n3, dst, s);
         batch_rhs_launch(b, split, DP_C[st], dst, st, s);
     }
     frg::launch_dp_error_b(b->d_fa, b->d_it_red, b->n_red, b->n, DP_E, o->rtol, o->atol, s);

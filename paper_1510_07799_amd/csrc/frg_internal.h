@@ -167,6 +167,9 @@ void launch_state_set(double *state, int slot, double v, hipStream_t s);
 void launch_pre_step(double *state, int stepper, hipStream_t s);
 void launch_dp_control(double *state, double *log, int log_cap, double vmax, int max_steps,
                        int stepper, hipStream_t s);
+// split layout straight from a reduced state (gather rows of representative columns only)
+void launch_layout_split_red(const double *Vr, int N, const int32_t *ppos, const int32_t *phpos,
+                             const int16_t *perm8, uint16_t *ahl, float *g32, hipStream_t s);
 // Reduced flow state of the symmetric-vertex mode (entry pos * N + m = V(cperm[pos], m)):
 // gather it from a full V, expand it into a full V (only accepted steps when gate,
 // the flow state, is given), and the rhs at the representative entries only.

@@ -193,18 +193,47 @@ __host__ __device__ __forceinline__ int layout_a_blocks(int N) {
 }
 __host__ __device__ __forceinline__ int layout_t_tiles(int N) { return (N + kLayoutTile - 1) / kLayoutTile; }
 
+// The split layout can read a flow's reduced state directly (one entry per
+// representative pp column and free index): V(a, b, m) = Vr[pos N + perm8[o][m]]
+// with (pos, o) = ppos[a N + b].  Only the gather rows of representative columns
+// are written then (the contraction reads no others).
+struct RedSrc {
+    const double *Vr;
+    const int32_t *ppos, *phpos;   // pp / ph column maps: position << 3 | C4v element
+    const int16_t *perm8;
+    __device__ __forceinline__ double at(int N, int a, int b, int m) const {
+        const int32_t cm = ppos[a * N + b];
+        return Vr[(cm >> 3) * N + perm8[(cm & 7) * N + m]];
+    }
+};
+
 // A operands of chunk c, row i
-template <bool SPLIT>
+template <bool SPLIT, bool RED = false>
 __device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int N, int64_t n3, int64_t u,
                                               uint16_t *__restrict__ ahl, float *__restrict__ g32,
-                                              double *__restrict__ perm) {
+                                              double *__restrict__ perm, const RedSrc &R) {
     const int64_t NN = static_cast<int64_t>(N) * N;
     const int i = static_cast<int>(u % N);
     const int64_t c = u / N;
     const int64_t kk0 = 8 * c;
     double pp[8], phc[8], phd[8];
+    bool write_g = true;
+    if constexpr (RED) {   // N % 8 == 0 here (a C4v-covariant grid)
+        const int j = static_cast<int>(kk0 / N), k0 = static_cast<int>(kk0 - static_cast<int64_t>(j) * N);
+        const int32_t cc = R.ppos[i * N + j], cd = R.ppos[j * N + i];
+        const double *rc = R.Vr + (cc >> 3) * N, *rd = R.Vr + (cd >> 3) * N;
+        const int16_t *pc = R.perm8 + (cc & 7) * N, *pd = R.perm8 + (cd & 7) * N;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            phc[t] = rc[pc[k0 + t]];
+            phd[t] = rd[pd[k0 + t]];
+            pp[t] = R.at(N, j, k0 + t, i);
+        }
+        write_g = (cc & 7) == 0;   // gather row (i, j) of a representative pp column
+    }
     const double *vrow = V + i * NN + kk0;
-    if (N % 8 == 0) {   // the chunk lies in one j row: contiguous 64-byte runs
+    if constexpr (RED) {
+    } else if (N % 8 == 0) {   // the chunk lies in one j row: contiguous 64-byte runs
         const int j = static_cast<int>(kk0 / N), k0 = static_cast<int>(kk0 - static_cast<int64_t>(j) * N);
         const double *drow = V + (static_cast<int64_t>(j) * N + i) * N + k0;
 #pragma unroll
@@ -223,8 +252,10 @@ __device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int 
             phd[t] = V[(j * N + i) * N + k];
         }
     }
+    if constexpr (!RED) {
 #pragma unroll
-    for (int t = 0; t < 8; ++t) pp[t] = V[(kk0 + t) * N + i];
+        for (int t = 0; t < 8; ++t) pp[t] = V[(kk0 + t) * N + i];
+    }
     const int64_t cm = (c * N + i) * 8;
     if constexpr (SPLIT) {
         float ops[4][8];
@@ -249,9 +280,11 @@ __device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int 
             *reinterpret_cast<uint4 *>(ahl + (2 * o) * n3 + cm) = make_uint4(hw[0], hw[1], hw[2], hw[3]);
             *reinterpret_cast<uint4 *>(ahl + (2 * o + 1) * n3 + cm) = make_uint4(lw[0], lw[1], lw[2], lw[3]);
         }
-        float4 *g = reinterpret_cast<float4 *>(g32 + i * NN + kk0);
-        g[0] = make_float4(ops[1][0], ops[1][1], ops[1][2], ops[1][3]);
-        g[1] = make_float4(ops[1][4], ops[1][5], ops[1][6], ops[1][7]);
+        if (write_g) {
+            float4 *g = reinterpret_cast<float4 *>(g32 + i * NN + kk0);
+            g[0] = make_float4(ops[1][0], ops[1][1], ops[1][2], ops[1][3]);
+            g[1] = make_float4(ops[1][4], ops[1][5], ops[1][6], ops[1][7]);
+        }
     } else {
 #pragma unroll
         for (int t = 0; t < 8; t += 2) {
@@ -261,6 +294,28 @@ __device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int 
                 make_double2(-2.0 * phd[t] + phc[t], -2.0 * phd[t + 1] + phc[t + 1]);
             *reinterpret_cast<double2 *>(perm + 3 * n3 + cm + t) = make_double2(phd[t], phd[t + 1]);
         }
+    }
+}
+
+// one 32 x 32 tile of out[col][r] = get(r, col) for the output rows col that
+// keep(col) accepts (rows x cols input), stored as OUT
+template <typename OUT, class GET, class KEEP>
+__device__ __forceinline__ void layout_transpose_gen(GET get, KEEP keep, int rows, int64_t cols, int r0, int64_t c0,
+                                                     OUT *__restrict__ out, int64_t ld_out,
+                                                     double (*tile)[kLayoutTile + 1]) {
+    const int tx = threadIdx.x & (kLayoutTile - 1), ty = threadIdx.x / kLayoutTile;   // 32 x 8
+#pragma unroll
+    for (int p = 0; p < kLayoutTile; p += 8) {
+        const int r = r0 + ty + p;
+        const int64_t c = c0 + tx;
+        tile[ty + p][tx] = (r < rows && c < cols && keep(c)) ? get(r, c) : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < kLayoutTile; p += 8) {
+        const int64_t c = c0 + ty + p;
+        const int r = r0 + tx;
+        if (r < rows && c < cols && keep(c)) out[c * ld_out + r] = static_cast<OUT>(tile[tx][ty + p]);
     }
 }
 
@@ -296,7 +351,7 @@ __device__ __forceinline__ void layout_block(const double *__restrict__ V, int N
     const int64_t NN = static_cast<int64_t>(N) * N;
     if (blk < na) {
         const int64_t u = static_cast<int64_t>(blk) * 256 + threadIdx.x;
-        if (u < n3 / 8) layout_a_unit<SPLIT>(V, N, n3, u, ahl, g32, perm);
+        if (u < n3 / 8) layout_a_unit<SPLIT>(V, N, n3, u, ahl, g32, perm, RedSrc{});
         return;
     }
     blk -= na;
@@ -325,6 +380,43 @@ __global__ __launch_bounds__(256) void layout_f64_kernel(const double *__restric
                                                          double *__restrict__ perm) {
     const int64_t n3 = static_cast<int64_t>(N) * N * N;
     layout_block<false>(V, N, n3, blockIdx.x, nullptr, nullptr, perm);
+}
+
+// block blk of a split layout pass from a reduced state: the same blocks as
+// layout_block<true>, gather rows of non-representative columns skipped
+__device__ __forceinline__ void layout_block_red(const RedSrc &R, int N, int64_t n3, int blk,
+                                                 uint16_t *__restrict__ ahl, float *__restrict__ g32) {
+    __shared__ double tile[kLayoutTile][kLayoutTile + 1];
+    const int na = layout_a_blocks(N), nt = layout_t_tiles(N);
+    const int64_t NN = static_cast<int64_t>(N) * N;
+    if (blk < na) {
+        const int64_t u = static_cast<int64_t>(blk) * 256 + threadIdx.x;
+        if (u < n3 / 8) layout_a_unit<true, true>(nullptr, N, n3, u, ahl, g32, nullptr, R);
+        return;
+    }
+    blk -= na;
+    const int nt1 = nt * static_cast<int>((NN + kLayoutTile - 1) / kLayoutTile);
+    if (blk < nt1) {   // block 4: out[(i, j)][k] = V(k, i, j), rows of representative ph columns
+        const int rt = blk % nt;
+        const int64_t ct = blk / nt;
+        layout_transpose_gen<float>(
+            [&](int k, int64_t c) { return R.at(N, k, static_cast<int>(c / N), static_cast<int>(c % N)); },
+            [&](int64_t c) { return (R.phpos[c] & 7) == 0; }, N, NN, rt * kLayoutTile, ct * kLayoutTile, g32 + n3,
+            N, tile);
+        return;
+    }
+    blk -= nt1;        // block 5: out[i][j][k] = V(i, k, j)
+    const int i = blk / (nt * nt), rem = blk - i * nt * nt;
+    const int rt = rem % nt, ct = rem / nt;
+    layout_transpose_gen<float>([&](int k, int64_t j) { return R.at(N, i, k, static_cast<int>(j)); },
+                                [](int64_t) { return true; }, N, N, rt * kLayoutTile, ct * kLayoutTile,
+                                g32 + 2 * n3 + i * NN, N, tile);
+}
+
+__global__ __launch_bounds__(256) void layout_split_red_kernel(RedSrc R, int N, uint16_t *__restrict__ ahl,
+                                                               float *__restrict__ g32) {
+    const int64_t n3 = static_cast<int64_t>(N) * N * N;
+    layout_block_red(R, N, n3, blockIdx.x, ahl, g32);
 }
 
 __global__ __launch_bounds__(256) void layout_split_kernel(const double *__restrict__ V, int N,
@@ -792,8 +884,14 @@ __global__ __launch_bounds__(256) void layout_b_kernel(const FlowArgs *__restric
     const int2 it = items[blockIdx.x];
     const FlowArgs &f = fa[it.x];
     if (flow_stopped(f)) return;
-    if (!split) layout_block<false>(src_of(f, src), f.N, f.n3, it.y, nullptr, nullptr, f.perm);
-    else layout_block<true>(src_of(f, src), f.N, f.n3, it.y, f.ahl, f.g32, nullptr);
+    if (!split) {
+        layout_block<false>(src_of(f, src), f.N, f.n3, it.y, nullptr, nullptr, f.perm);
+    } else if (f.red && src != SRC_V) {   // straight from the reduced stage vector
+        const RedSrc R{src == SRC_YT ? f.ytr : f.y5r, f.ppos, f.phpos, f.perm8};
+        layout_block_red(R, f.N, f.n3, it.y, f.ahl, f.g32);
+    } else {
+        layout_block<true>(src_of(f, src), f.N, f.n3, it.y, f.ahl, f.g32, nullptr);
+    }
 }
 
 __global__ __launch_bounds__(256) void combine_b_kernel(const FlowArgs *__restrict__ fa,
@@ -972,6 +1070,12 @@ int layout_blocks(int N) {
 
 void launch_layout_f64(const double *V, int N, double *perm, hipStream_t s) {
     hipLaunchKernelGGL(layout_f64_kernel, dim3(layout_blocks(N)), dim3(256), 0, s, V, N, perm);
+}
+
+void launch_layout_split_red(const double *Vr, int N, const int32_t *ppos, const int32_t *phpos,
+                             const int16_t *perm8, uint16_t *ahl, float *g32, hipStream_t s) {
+    hipLaunchKernelGGL(layout_split_red_kernel, dim3(layout_blocks(N)), dim3(256), 0, s, RedSrc{Vr, ppos, phpos, perm8},
+                       N, ahl, g32);
 }
 
 void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipStream_t s) {
