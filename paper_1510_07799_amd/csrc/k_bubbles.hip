@@ -341,15 +341,16 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     const size_t NN = static_cast<size_t>(N) * N;
 
     const int row0 = chunk * kRowsPerBlock;
+    // the wave's bins start at zero; each row's output pass clears them again
+    for (int b = lane; b < N; b += 64) bins[b] = 0.0;
+    if constexpr (PAIRED)
+        for (int b = lane; b < N; b += 64) bins2[b] = 0.0;
     for (int rr = wave; rr < kRowsPerBlock; rr += 4) {
         const int slot_out = row0 + rr;                 // output row position (wave-uniform)
         if (slot_out >= A.nrows) break;
         // transfer row (wave-uniform: kept in scalar registers with its constants);
         // a pair's second row is the ph row of the opposite transfer
         const int r = __builtin_amdgcn_readfirstlane(A.rowlist ? A.rowlist[slot_out] : slot_out);
-        for (int b = lane; b < N; b += 64) bins[b] = 0.0;
-        if constexpr (PAIRED)
-            for (int b = lane; b < N; b += 64) bins2[b] = 0.0;
         // Row-uniform factors.  pp: cos(q - p) = cos q cos p + sin q sin p and the
         // second line enters as -eps / 2T; ph: cos(p + Q) = cos p cos Q - sin p sin Q
         // and +eps / 2T, so b = k1 (cx + cy) - k2 cx cy - k3 with the channel's
@@ -442,11 +443,13 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
                                                 : static_cast<size_t>(slot_out - A.npp_out));
             const size_t base = pos * NN + static_cast<size_t>(a_patch) * N;
             void *outp = pp_out ? A.Bpp : A.Bph;
-            const double *src = k == 0 ? bins : bins2;
-            if (outp) {
-                for (int b = lane; b < N; b += 64) {
-                    if (F32) static_cast<float *>(outp)[base + b] = static_cast<float>(src[b]);
-                    else static_cast<double *>(outp)[base + b] = src[b];
+            double *src = k == 0 ? bins : bins2;
+            for (int b = lane; b < N; b += 64) {
+                const double v = src[b];
+                src[b] = 0.0;   // read and cleared by the same lane
+                if (outp) {
+                    if (F32) static_cast<float *>(outp)[base + b] = static_cast<float>(v);
+                    else static_cast<double *>(outp)[base + b] = v;
                 }
             }
         }
