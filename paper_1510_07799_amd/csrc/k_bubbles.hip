@@ -345,12 +345,20 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     for (int b = lane; b < N; b += 64) bins[b] = 0.0;
     if constexpr (PAIRED)
         for (int b = lane; b < N; b += 64) bins2[b] = 0.0;
-    for (int rr = wave; rr < kRowsPerBlock; rr += 4) {
+    // the wave's 16 transfer rows (and a pair's second rows), one per lane, read
+    // once: each row then takes them with a lane read instead of a global load
+    constexpr int kRowsPerWave = kRowsPerBlock / 4;
+    const int my_slot = row0 + wave + 4 * lane;
+    const bool my_ok = lane < kRowsPerWave && my_slot < A.nrows;
+    const int my_r = my_ok ? (A.rowlist ? A.rowlist[my_slot] : my_slot) : 0;
+    const int my_rph = (PAIRED && my_ok) ? A.rowlist_ph[my_slot] : 0;
+    for (int it = 0; it < kRowsPerWave; ++it) {
+        const int rr = wave + 4 * it;
         const int slot_out = row0 + rr;                 // output row position (wave-uniform)
         if (slot_out >= A.nrows) break;
         // transfer row (wave-uniform: kept in scalar registers with its constants);
         // a pair's second row is the ph row of the opposite transfer
-        const int r = __builtin_amdgcn_readfirstlane(A.rowlist ? A.rowlist[slot_out] : slot_out);
+        const int r = __builtin_amdgcn_readlane(my_r, it);
         // Row-uniform factors.  pp: cos(q - p) = cos q cos p + sin q sin p and the
         // second line enters as -eps / 2T; ph: cos(p + Q) = cos p cos Q - sin p sin Q
         // and +eps / 2T, so b = k1 (cx + cy) - k2 cx cy - k3 with the channel's
@@ -364,7 +372,7 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
         const double sy = uniform_f64((pp ? k1 : -k1) * A.trig_row[4 * r + 3]);
         uint32_t bw[W], bw2[PAIRED ? W : 1];
         load_bins(r, bw);
-        if constexpr (PAIRED) load_bins(__builtin_amdgcn_readfirstlane(A.rowlist_ph[slot_out]), bw2);
+        if constexpr (PAIRED) load_bins(__builtin_amdgcn_readlane(my_rph, it), bw2);
         auto bin_of = [&](const uint32_t *w, int j) -> int { return (w[j >> 2] >> (8 * (j & 3))) & 0xff; };
         // FP32 Taylor coefficients of point j: from LDS in register mode, else made
         // on the spot (w = -c2 / 4, or W = c2 for the full bubble)
