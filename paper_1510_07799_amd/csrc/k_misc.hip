@@ -93,8 +93,9 @@ __global__ void bins_export_kernel(const uint8_t *__restrict__ bins, int N, int 
 // turns; o odd: reflection about the axis at (o+1) pi/8)
 __device__ __forceinline__ int c4v_patch(int o, int j, int N) {
     const int q = N >> 2;
-    const int v = (o & 1) ? ((o + 1) >> 1) * q - 1 - j : j + (o >> 1) * q;
-    return ((v % N) + N) % N;
+    int v = (o & 1) ? ((o + 1) >> 1) * q - 1 - j : j + (o >> 1) * q;   // in (-N, 2N)
+    v += v < 0 ? N : 0;
+    return v >= N ? v - N : v;
 }
 
 // orbit[t'] = (rep row << 3) | o with t' = o . rep
@@ -200,10 +201,9 @@ __host__ __device__ __forceinline__ int layout_t_tiles(int N) { return (N + kLay
 struct RedSrc {
     const double *Vr;
     const int32_t *ppos, *phpos;   // pp / ph column maps: position << 3 | C4v element
-    const int16_t *perm8;
     __device__ __forceinline__ double at(int N, int a, int b, int m) const {
         const int32_t cm = ppos[a * N + b];
-        return Vr[(cm >> 3) * N + perm8[(cm & 7) * N + m]];
+        return Vr[(cm >> 3) * N + c4v_patch(cm & 7, m, N)];
     }
 };
 
@@ -222,11 +222,10 @@ __device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int 
         const int j = static_cast<int>(kk0 / N), k0 = static_cast<int>(kk0 - static_cast<int64_t>(j) * N);
         const int32_t cc = R.ppos[i * N + j], cd = R.ppos[j * N + i];
         const double *rc = R.Vr + (cc >> 3) * N, *rd = R.Vr + (cd >> 3) * N;
-        const int16_t *pc = R.perm8 + (cc & 7) * N, *pd = R.perm8 + (cd & 7) * N;
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            phc[t] = rc[pc[k0 + t]];
-            phd[t] = rd[pd[k0 + t]];
+            phc[t] = rc[c4v_patch(cc & 7, k0 + t, N)];
+            phd[t] = rd[c4v_patch(cd & 7, k0 + t, N)];
             pp[t] = R.at(N, j, k0 + t, i);
         }
         write_g = (cc & 7) == 0;   // gather row (i, j) of a representative pp column
@@ -887,7 +886,7 @@ __global__ __launch_bounds__(256) void layout_b_kernel(const FlowArgs *__restric
     if (!split) {
         layout_block<false>(src_of(f, src), f.N, f.n3, it.y, nullptr, nullptr, f.perm);
     } else if (f.red && src != SRC_V) {   // straight from the reduced stage vector
-        const RedSrc R{src == SRC_YT ? f.ytr : f.y5r, f.ppos, f.phpos, f.perm8};
+        const RedSrc R{src == SRC_YT ? f.ytr : f.y5r, f.ppos, f.phpos};
         layout_block_red(R, f.N, f.n3, it.y, f.ahl, f.g32);
     } else {
         layout_block<true>(src_of(f, src), f.N, f.n3, it.y, f.ahl, f.g32, nullptr);
@@ -1074,8 +1073,9 @@ void launch_layout_f64(const double *V, int N, double *perm, hipStream_t s) {
 
 void launch_layout_split_red(const double *Vr, int N, const int32_t *ppos, const int32_t *phpos,
                              const int16_t *perm8, uint16_t *ahl, float *g32, hipStream_t s) {
-    hipLaunchKernelGGL(layout_split_red_kernel, dim3(layout_blocks(N)), dim3(256), 0, s, RedSrc{Vr, ppos, phpos, perm8},
-                       N, ahl, g32);
+    (void)perm8;   // the layout computes the patch maps
+    hipLaunchKernelGGL(layout_split_red_kernel, dim3(layout_blocks(N)), dim3(256), 0, s, RedSrc{Vr, ppos, phpos}, N,
+                       ahl, g32);
 }
 
 void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipStream_t s) {
