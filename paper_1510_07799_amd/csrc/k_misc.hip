@@ -500,7 +500,8 @@ __device__ __forceinline__ double vred_at(const double *__restrict__ Vr, int N, 
                                           const int16_t *__restrict__ perm8, int64_t i) {
     const uint32_t ii = static_cast<uint32_t>(i), c = ii / static_cast<uint32_t>(N);
     const int32_t cm = cmap[c];
-    return Vr[(cm >> 3) * N + perm8[(cm & 7) * N + static_cast<int>(ii - c * N)]];
+    (void)perm8;
+    return Vr[(cm >> 3) * N + c4v_patch(cm & 7, static_cast<int>(ii - c * N), N)];
 }
 __device__ __forceinline__ double vred_gather_at(const double *__restrict__ V, int N,
                                                  const int32_t *__restrict__ cperm, int64_t i) {
@@ -516,8 +517,9 @@ __device__ __forceinline__ double combine_red_at(int N, const double *__restrict
     const uint32_t ii = static_cast<uint32_t>(i), pos = ii / static_cast<uint32_t>(N);
     const int j3 = static_cast<int>(ii - pos * N);
     const int c = cperm[pos], j1 = c / N, j2 = c - j1 * N;
+    (void)perm8;
     auto at_of = [&](int32_t cm, int m) -> int64_t {
-        return static_cast<int64_t>(cm >> 3) * N + perm8[(cm & 7) * N + m];
+        return static_cast<int64_t>(cm >> 3) * N + c4v_patch(cm & 7, m, N);
     };
     double v = -Cpp[i];
     v += Cc[at_of(phpos[j2 * N + j3], j1)];
