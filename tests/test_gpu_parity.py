@@ -507,6 +507,44 @@ def test_symmetric_vertex_flow_from_random_invariant_vertex():
                 assert np.array_equal(Vss[np.ix_(pm, pm, pm)], Vss)
 
 
+def test_batched_split_symmetric_flows_follow_every_column_flows():
+    """Batched split-BF16 steps in symmetric-vertex mode (reduced stage vectors,
+    the layout reading them directly, the reduced combine) follow the same
+    batch computing every column, from random C4v-invariant vertices."""
+    cfgs = [p for p in BATCH if p["N"] % 8 == 0]
+    V0 = [I.random_vertex(p["N"], p["U"], seed=60 + i, amp=0.3, symmetrise=True) for i, p in enumerate(cfgs)]
+    # a tolerance the truncation error dominates, so that the split rounding of the
+    # two modes does not steer the step sizes apart
+    o = frg.flow_opts("dp54", frg.PREC_SPLIT_BF16, T0=1.0, T_min=0.2, rtol=1e-3, atol=1e-6, vmax=1e6,
+                      h0=-0.05)
+    out = []
+    for vs in (False, True):
+        b = frg.Batch(cfgs)
+        try:
+            b.set_vsym(vs)
+            Vs = [dev(v) for v in V0]
+            b.flow_init(Vs, o)
+            for _ in range(4):
+                b.flow_step()
+            res, _ = b.results()
+            torch.cuda.synchronize()
+            out.append((res, [v.cpu().numpy() for v in Vs]))
+        finally:
+            b.close()
+    (rf, Vf), (rs, Vs) = out
+    for i, p in enumerate(cfgs):
+        err = nrel(Vs[i], Vf[i])
+        print(f"[batch vsym split] N={p['N']}: T {rs[i]['T_end']:.9f} / {rf[i]['T_end']:.9f}, V {err:.2e}",
+              flush=True)
+        assert rs[i]["accepted"] == rf[i]["accepted"]
+        assert rs[i]["T_end"] == pytest.approx(rf[i]["T_end"], rel=1e-4)
+        assert err <= 1e-3
+        assert nrel(Vs[i], V0[i]) > 1e-3
+        for o_ in range(1, 8):
+            pm = I.c4v_patch_perm(p["N"], o_)
+            assert np.array_equal(Vs[i][np.ix_(pm, pm, pm)], Vs[i])
+
+
 def test_symmetric_vertex_toggled_mid_flow():
     """Switching the mode between steps converts the rhs a DP5(4) flow carries to
     its next step (first same as last) to the new form: a flow switched on after
