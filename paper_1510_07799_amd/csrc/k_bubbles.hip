@@ -443,21 +443,48 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
         atomicAdd(&bins[bcur], static_cast<double>(acc));
         if constexpr (PAIRED) atomicAdd(&bins2[bcur2], static_cast<double>(acc2));
         wave_sync();
-        // outputs: a pair writes its pp row and its ph row at the same position
-        for (int k = 0; k < (PAIRED ? 2 : 1); ++k) {
+        // outputs: a pair writes its pp row and its ph row at the same position.
+        // A lane takes bins b and b + 64 of both rows at once (all reads issued
+        // before the first store), and clears them.
+        constexpr int NO = PAIRED ? 2 : 1;
+        size_t base[NO];
+        void *outp[NO];
+        double *src[NO];
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
             const bool pp_out = PAIRED ? k == 0 : slot_out < A.npp_out;
             const size_t pos = PAIRED ? static_cast<size_t>(slot_out)
                                       : (pp_out ? static_cast<size_t>(slot_out)
                                                 : static_cast<size_t>(slot_out - A.npp_out));
-            const size_t base = pos * NN + static_cast<size_t>(a_patch) * N;
-            void *outp = pp_out ? A.Bpp : A.Bph;
-            double *src = k == 0 ? bins : bins2;
-            for (int b = lane; b < N; b += 64) {
-                const double v = src[b];
-                src[b] = 0.0;   // read and cleared by the same lane
-                if (outp) {
-                    if (F32) static_cast<float *>(outp)[base + b] = static_cast<float>(v);
-                    else static_cast<double *>(outp)[base + b] = v;
+            base[k] = pos * NN + static_cast<size_t>(a_patch) * N;
+            outp[k] = pp_out ? A.Bpp : A.Bph;
+            src[k] = k == 0 ? bins : bins2;
+        }
+        for (int b0 = lane; b0 < N; b0 += 128) {
+            const int b1 = b0 + 64;
+            const bool has1 = b1 < N;
+            double v[NO][2];
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {
+                v[k][0] = src[k][b0];
+                v[k][1] = has1 ? src[k][b1] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {   // read and cleared by the same lane
+                src[k][b0] = 0.0;
+                if (has1) src[k][b1] = 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {
+                if (!outp[k]) continue;
+                if (F32) {
+                    float *o = static_cast<float *>(outp[k]) + base[k];
+                    o[b0] = static_cast<float>(v[k][0]);
+                    if (has1) o[b1] = static_cast<float>(v[k][1]);
+                } else {
+                    double *o = static_cast<double *>(outp[k]) + base[k];
+                    o[b0] = v[k][0];
+                    if (has1) o[b1] = v[k][1];
                 }
             }
         }
