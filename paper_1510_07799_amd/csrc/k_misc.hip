@@ -340,12 +340,14 @@ __device__ __forceinline__ void layout_transpose_tile(const double *__restrict__
     }
 }
 
+typedef double LayoutTile[kLayoutTile + 1];   // rows of the 32 x 33 LDS tile a layout block uses
+
 // block blk of a layout pass
 template <bool SPLIT>
 __device__ __forceinline__ void layout_block(const double *__restrict__ V, int N, int64_t n3, int blk,
                                              uint16_t *__restrict__ ahl, float *__restrict__ g32,
-                                             double *__restrict__ perm) {
-    __shared__ double tile[kLayoutTile][kLayoutTile + 1];
+                                             double *__restrict__ perm, LayoutTile *tile) {
+    
     const int na = layout_a_blocks(N), nt = layout_t_tiles(N);
     const int64_t NN = static_cast<int64_t>(N) * N;
     if (blk < na) {
@@ -378,14 +380,15 @@ __device__ __forceinline__ void layout_block(const double *__restrict__ V, int N
 __global__ __launch_bounds__(256) void layout_f64_kernel(const double *__restrict__ V, int N,
                                                          double *__restrict__ perm) {
     const int64_t n3 = static_cast<int64_t>(N) * N * N;
-    layout_block<false>(V, N, n3, blockIdx.x, nullptr, nullptr, perm);
+    __shared__ LayoutTile tile[kLayoutTile];
+    layout_block<false>(V, N, n3, blockIdx.x, nullptr, nullptr, perm, tile);
 }
 
 // block blk of a split layout pass from a reduced state: the same blocks as
 // layout_block<true>, gather rows of non-representative columns skipped
 __device__ __forceinline__ void layout_block_red(const RedSrc &R, int N, int64_t n3, int blk,
-                                                 uint16_t *__restrict__ ahl, float *__restrict__ g32) {
-    __shared__ double tile[kLayoutTile][kLayoutTile + 1];
+                                                 uint16_t *__restrict__ ahl, float *__restrict__ g32,
+                                                 LayoutTile *tile) {
     const int na = layout_a_blocks(N), nt = layout_t_tiles(N);
     const int64_t NN = static_cast<int64_t>(N) * N;
     if (blk < na) {
@@ -415,13 +418,15 @@ __device__ __forceinline__ void layout_block_red(const RedSrc &R, int N, int64_t
 __global__ __launch_bounds__(256) void layout_split_red_kernel(RedSrc R, int N, uint16_t *__restrict__ ahl,
                                                                float *__restrict__ g32) {
     const int64_t n3 = static_cast<int64_t>(N) * N * N;
-    layout_block_red(R, N, n3, blockIdx.x, ahl, g32);
+    __shared__ LayoutTile tile[kLayoutTile];
+    layout_block_red(R, N, n3, blockIdx.x, ahl, g32, tile);
 }
 
 __global__ __launch_bounds__(256) void layout_split_kernel(const double *__restrict__ V, int N,
                                                            uint16_t *__restrict__ ahl, float *__restrict__ g32) {
     const int64_t n3 = static_cast<int64_t>(N) * N * N;
-    layout_block<true>(V, N, n3, blockIdx.x, ahl, g32, nullptr);
+    __shared__ LayoutTile tile[kLayoutTile];
+    layout_block<true>(V, N, n3, blockIdx.x, ahl, g32, nullptr, tile);
 }
 
 // The channel partials are stored per column tile position, [p][m], so each
@@ -882,16 +887,17 @@ __device__ __forceinline__ const double *src_of(const FlowArgs &f, int src) {
 // items: (flow, block of that flow's layout pass)
 __global__ __launch_bounds__(256) void layout_b_kernel(const FlowArgs *__restrict__ fa,
                                                        const int2 *__restrict__ items, int src, int split) {
+    __shared__ LayoutTile tile[kLayoutTile];
     const int2 it = items[blockIdx.x];
     const FlowArgs &f = fa[it.x];
     if (flow_stopped(f)) return;
     if (!split) {
-        layout_block<false>(src_of(f, src), f.N, f.n3, it.y, nullptr, nullptr, f.perm);
+        layout_block<false>(src_of(f, src), f.N, f.n3, it.y, nullptr, nullptr, f.perm, tile);
     } else if (f.red && src != SRC_V) {   // straight from the reduced stage vector
         const RedSrc R{src == SRC_YT ? f.ytr : f.y5r, f.ppos, f.phpos};
-        layout_block_red(R, f.N, f.n3, it.y, f.ahl, f.g32);
+        layout_block_red(R, f.N, f.n3, it.y, f.ahl, f.g32, tile);
     } else {
-        layout_block<true>(src_of(f, src), f.N, f.n3, it.y, f.ahl, f.g32, nullptr);
+        layout_block<true>(src_of(f, src), f.N, f.n3, it.y, f.ahl, f.g32, nullptr, tile);
     }
 }
 
