@@ -219,7 +219,7 @@ enum { SRC_V = 0, SRC_YT = 1, SRC_Y5 = 2 };
 // SRC_Y5 expand ytr / y5r into yt / y5 (items over n3); other flows skip
 void launch_vred_b(const FlowArgs *fa, const int2 *items, int nitems, int dst, hipStream_t s);
 
-int bubble_rows_per_block();
+int bubble_rows_per_block();   // of the batched sweep (its items are (flow, chunk << 8 | patch))
 // items: the first npaired belong to flows with row pairs (rowlist_ph set)
 void launch_bubbles_batched(const BubbleArgs *args, const int2 *items, int npaired, int nitems,
                             const double *const *states, int nf, int maxN, bool fp32, hipStream_t s);

@@ -27,7 +27,9 @@ namespace frg {
 
 namespace {
 
-constexpr int kRowsPerBlock = 64;   // 16 rows per wave
+constexpr int kRowsPerBlock = 64;          // 16 rows per wave
+constexpr int kRowsPerBlockBatched = 128;  // batches have blocks to spare: 32 rows per wave
+                                           // halve the per-block point set-up
 constexpr int kThreads = 256;
 
 // Weighted divided difference w (h(a) - h(b)) / (a - b) of h(x) = x sech^2 x,
@@ -225,7 +227,7 @@ size_t bubble_lds_bytes(int N, bool paired) {
 // FULL: the full bubble L instead of dL/dT (the interaction flow).  PAIRED: each
 // output position evaluates a pp row q and the ph row of -q at once (rowlist,
 // rowlist_ph): their second lines q - p and p - q have one energy.
-template <int P, bool F32, bool FULL, bool PAIRED>
+template <int P, bool F32, bool FULL, bool PAIRED, int RPB = kRowsPerBlock>
 __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int a_patch, double *smem) {
     using PT = typename std::conditional<F32, float, double>::type;
     // The lane's P points (table positions lane*P .. lane*P+P-1, angular
@@ -340,14 +342,15 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     };
     const size_t NN = static_cast<size_t>(N) * N;
 
-    const int row0 = chunk * kRowsPerBlock;
+    const int row0 = chunk * RPB;
     // the wave's bins start at zero; each row's output pass clears them again
     for (int b = lane; b < N; b += 64) bins[b] = 0.0;
     if constexpr (PAIRED)
         for (int b = lane; b < N; b += 64) bins2[b] = 0.0;
     // the wave's 16 transfer rows (and a pair's second rows), one per lane, read
     // once: each row then takes them with a lane read instead of a global load
-    constexpr int kRowsPerWave = kRowsPerBlock / 4;
+    constexpr int kRowsPerWave = RPB / 4;
+    static_assert(kRowsPerWave <= 64, "one row index per lane");
     const int my_slot = row0 + wave + 4 * lane;
     const bool my_ok = lane < kRowsPerWave && my_slot < A.nrows;
     const int my_r = my_ok ? (A.rowlist ? A.rowlist[my_slot] : my_slot) : 0;
@@ -507,7 +510,7 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel_batched(
     extern __shared__ double smem[];
     const int2 it = items[blockIdx.x];
     if (states && states[it.x][FRG_ST_REASON] != 0.0) return;
-    bubble_body<P, F32, false, PAIRED>(args[it.x], it.y >> 8, it.y & 255, smem);
+    bubble_body<P, F32, false, PAIRED, kRowsPerBlockBatched>(args[it.x], it.y >> 8, it.y & 255, smem);
 }
 
 template <int P, bool PAIRED>
@@ -552,7 +555,7 @@ void launch_pb(const BubbleArgs *args, const int2 *items, int npaired, int nitem
 
 }  // namespace
 
-int bubble_rows_per_block() { return kRowsPerBlock; }
+int bubble_rows_per_block() { return kRowsPerBlockBatched; }
 
 void launch_bubbles_batched(const BubbleArgs *args, const int2 *items, int npaired, int nitems,
                             const double *const *states, int nf, int maxN, bool fp32, hipStream_t s) {
