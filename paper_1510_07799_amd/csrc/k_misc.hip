@@ -213,13 +213,15 @@ __device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int 
                                               uint16_t *__restrict__ ahl, float *__restrict__ g32,
                                               double *__restrict__ perm, const RedSrc &R) {
     const int64_t NN = static_cast<int64_t>(N) * N;
-    const int i = static_cast<int>(u % N);
-    const int64_t c = u / N;
+    // u < N^3 / 8 <= 2^21: 32-bit divisions
+    const uint32_t u32 = static_cast<uint32_t>(u), cu = u32 / static_cast<uint32_t>(N);
+    const int i = static_cast<int>(u32 - cu * N);
+    const int64_t c = cu;
     const int64_t kk0 = 8 * c;
     double pp[8], phc[8], phd[8];
     bool write_g = true;
     if constexpr (RED) {   // N % 8 == 0 here (a C4v-covariant grid)
-        const int j = static_cast<int>(kk0 / N), k0 = static_cast<int>(kk0 - static_cast<int64_t>(j) * N);
+        const int kk = static_cast<int>(kk0), j = kk / N, k0 = kk - j * N;
         const int32_t cc = R.ppos[i * N + j], cd = R.ppos[j * N + i];
         const double *rc = R.Vr + (cc >> 3) * N, *rd = R.Vr + (cd >> 3) * N;
 #pragma unroll
@@ -402,7 +404,10 @@ __device__ __forceinline__ void layout_block_red(const RedSrc &R, int N, int64_t
         const int rt = blk % nt;
         const int64_t ct = blk / nt;
         layout_transpose_gen<float>(
-            [&](int k, int64_t c) { return R.at(N, k, static_cast<int>(c / N), static_cast<int>(c % N)); },
+            [&](int k, int64_t c) {
+                const int ci = static_cast<int>(c), a = ci / N;   // c < N^2: 32-bit division
+                return R.at(N, k, a, ci - a * N);
+            },
             [&](int64_t c) { return (R.phpos[c] & 7) == 0; }, N, NN, rt * kLayoutTile, ct * kLayoutTile, g32 + n3,
             N, tile);
         return;
@@ -569,8 +574,10 @@ __device__ __forceinline__ void sum_parts_body(const double *__restrict__ C, int
     // q runs over [3][nel / 4] quads (nel % 4 == 0: nel = ncol * N, N % 4 == 0)
     const int64_t qpt = nel / 4;
     if (q >= 3 * qpt) return;
-    const int t = static_cast<int>(q / qpt);
-    const int64_t i = 4 * (q - t * qpt);
+    // q < 3 N^3 / 4 < 2^24: a 32-bit division
+    const uint32_t q32 = static_cast<uint32_t>(q), qpt32 = static_cast<uint32_t>(qpt);
+    const int t = static_cast<int>(q32 / qpt32);
+    const int64_t i = 4 * static_cast<int64_t>(q32 - static_cast<uint32_t>(t) * qpt32);
     const PT *Ct = reinterpret_cast<const PT *>(C + t * static_cast<int64_t>(KS) * n3);
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int s = 0; s < KS; ++s) {
