@@ -726,15 +726,30 @@ __global__ void maxabs_partial(int64_t n, const double *__restrict__ y, double *
 
 // final reduction of the partials: error norm into state[slot_e] (if >= 0),
 // max|y| into state[slot_v]; fixed order, so the result is deterministic
-__global__ void reduce_partials(const double *partial, int nblocks, double *state, int slot_e,
-                                int slot_v) {
-    if (threadIdx.x != 0) return;
-    double e = 0.0, v = 0.0;
-    for (int b = 0; b < nblocks; ++b) {
+// the largest (error, |y|) partials, NaN-propagating, by one wave: lane l takes
+// blocks l, l + 64, ..., then a butterfly.  A maximum is exact, so the result
+// is the same for any order of the partials.
+__device__ __forceinline__ void wave_max_partials(const double *partial, int nblocks, double &e, double &v) {
+    e = 0.0;
+    v = 0.0;
+    for (int b = static_cast<int>(threadIdx.x & 63); b < nblocks; b += 64) {
         const double pe = partial[2 * b], pv = partial[2 * b + 1];
         e = (pe > e || pe != pe) ? pe : e;
         v = (pv > v || pv != pv) ? pv : v;
     }
+    for (int off = 32; off > 0; off >>= 1) {
+        const double oe = __shfl_xor(e, off, 64), ov = __shfl_xor(v, off, 64);
+        e = (oe > e || oe != oe) ? oe : e;
+        v = (ov > v || ov != ov) ? ov : v;
+    }
+}
+
+// launched as one wave
+__global__ void reduce_partials(const double *partial, int nblocks, double *state, int slot_e,
+                                int slot_v) {
+    double e, v;
+    wave_max_partials(partial, nblocks, e, v);
+    if (threadIdx.x != 0) return;
     if (slot_e >= 0) state[slot_e] = e;
     state[slot_v] = v;
 }
@@ -1000,23 +1015,25 @@ __global__ void dp_error_b_kernel(const FlowArgs *__restrict__ fa, const int2 *_
     }
 }
 
-// one thread per flow: phase 0 = reduce error partials, 1 = pre-step, 2 = step control
+// one wave per flow: the error norm and max|y5| from the flow's partials
+__global__ void reduce_partials_b_kernel(const FlowArgs *__restrict__ fa) {
+    const FlowArgs &f = fa[blockIdx.x];
+    if (flow_stopped(f)) return;
+    double e, v;
+    wave_max_partials(f.partial, f.nred, e, v);
+    if (threadIdx.x != 0) return;
+    f.state[FRG_ST_ERR] = e;
+    f.state[20] = v;
+}
+
+// one thread per flow: phase 1 = pre-step, 2 = step control (the error partials
+// are reduced by reduce_partials_b_kernel)
 __global__ void step_ctl_b_kernel(const FlowArgs *__restrict__ fa, int nflows, int phase, double *log_base,
                                   int log_cap, double vmax, int max_steps) {
     const int fl = blockIdx.x * blockDim.x + threadIdx.x;
     if (fl >= nflows) return;
     const FlowArgs &f = fa[fl];
-    if (phase == 0) {
-        if (flow_stopped(f)) return;
-        double e = 0.0, v = 0.0;
-        for (int b = 0; b < f.nred; ++b) {
-            const double pe = f.partial[2 * b], pv = f.partial[2 * b + 1];
-            e = (pe > e || pe != pe) ? pe : e;
-            v = (pv > v || pv != pv) ? pv : v;
-        }
-        f.state[FRG_ST_ERR] = e;
-        f.state[20] = v;
-    } else if (phase == 1) {
+    if (phase == 1) {
         if (flow_stopped(f)) return;
         pre_step_body(f.state, FRG_DP54);
     } else {
@@ -1224,8 +1241,7 @@ void launch_dp_error_b(const FlowArgs *fa, const int2 *items, int nitems, int nf
     Coef7 c;
     for (int j = 0; j < 7; ++j) c.c[j] = e[j];
     hipLaunchKernelGGL(dp_error_b_kernel, dim3(nitems), dim3(256), 0, s, fa, items, c, rtol, atol);
-    hipLaunchKernelGGL(step_ctl_b_kernel, dim3(blocks_for(nflows, 64)), dim3(64), 0, s, fa, nflows, 0,
-                       static_cast<double *>(nullptr), 0, 0.0, 0);
+    hipLaunchKernelGGL(reduce_partials_b_kernel, dim3(nflows), dim3(64), 0, s, fa);
 }
 void launch_step_ctl_b(const FlowArgs *fa, int nflows, int phase, double *log_base, int log_cap,
                        double vmax, int max_steps, hipStream_t s) {
