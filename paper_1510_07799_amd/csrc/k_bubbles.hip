@@ -11,7 +11,7 @@
 // LDS instead, to keep the register count down): it accumulates runs of equal
 // bin in registers, flushes each run into the wave's private LDS bins with one
 // LDS add, and writes the row B_row(a, 0..N-1) with coalesced stores (no
-// block-wide barriers).  The bin table (one byte per evaluation) and the cos/sin
+// block-wide barrier after the set-up).  The bin table (one byte per evaluation) and the cos/sin
 // of points and transfers are temperature independent; eps(second line) uses
 // cos(q -/+ p) = cos q cos p +/- sin q sin p.
 //
@@ -28,8 +28,8 @@ namespace frg {
 namespace {
 
 constexpr int kRowsPerBlock = 64;          // 16 rows per wave
-constexpr int kRowsPerBlockBatched = 128;  // batches have blocks to spare: 32 rows per wave
-                                           // halve the per-block point set-up
+// Batches have blocks to spare: 32 rows per wave halve the per-block point set-up.
+constexpr int kRowsPerBlockBatched = 128;
 constexpr int kThreads = 256;
 
 // Weighted divided difference w (h(a) - h(b)) / (a - b) of h(x) = x sech^2 x,
