@@ -235,6 +235,7 @@ frg::BubbleArgs bubble_args(frg_ctx ctx, bool fp32, void *bpp, void *bph) {
     a.npp_out = g.Tpp;
     a.rowlist = nullptr;
     a.rowlist_ph = nullptr;
+    a.rpb = 0;
     return a;
 }
 
@@ -1614,7 +1615,8 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
             set_operands(a, split, V, c->d_perm, c->d_ahl, c->d_g32, n3);
         }
         for (int k = 0; k < (g.np + 255) / 256; ++k) it_prep.push_back(make_int2(f, k));
-        const int rpb = frg::bubble_rows_per_block();
+        const int rpb = frg::bubble_batched_rows_per_block(bb.nrows);
+        ba[f].rpb = rpb;
         const int chunks = (bb.nrows + rpb - 1) / rpb;
         for (int ch = 0; ch < chunks; ++ch)
             for (int a = 0; a < g.N; ++a)

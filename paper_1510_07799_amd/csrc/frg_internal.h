@@ -62,6 +62,7 @@ struct BubbleArgs {
     // pairs: when set, position o evaluates the pp row rowlist[o] into Bpp and
     // the ph row rowlist_ph[o] (the opposite transfer) into Bph, both at o
     const int32_t *rowlist_ph;
+    int rpb;   // rows per block of the batched sweep (a multiple of 4, at most 256)
 };
 // full: the bubble L itself (interaction flow) instead of dL/dT
 void launch_bubbles(const BubbleArgs &a, bool fp32, bool full, hipStream_t s);
@@ -219,7 +220,8 @@ enum { SRC_V = 0, SRC_YT = 1, SRC_Y5 = 2 };
 // SRC_Y5 expand ytr / y5r into yt / y5 (items over n3); other flows skip
 void launch_vred_b(const FlowArgs *fa, const int2 *items, int nitems, int dst, hipStream_t s);
 
-int bubble_rows_per_block();   // of the batched sweep (its items are (flow, chunk << 8 | patch))
+// rows per block of the batched sweep for nrows rows (its items are (flow, chunk << 8 | patch))
+int bubble_batched_rows_per_block(int nrows);
 // items: the first npaired belong to flows with row pairs (rowlist_ph set)
 void launch_bubbles_batched(const BubbleArgs *args, const int2 *items, int npaired, int nitems,
                             const double *const *states, int nf, int maxN, bool fp32, hipStream_t s);

@@ -18,6 +18,7 @@
 // FP64 path: everything in double.  Split path: eps in double (its absolute
 // error is divided by 2T), the integrand in FP32 with hardware exp2/rcp, runs
 // of at most P points summed in FP32, bins accumulated in double, output float.
+#include <algorithm>
 #include <cmath>
 #include <type_traits>
 
@@ -28,8 +29,9 @@ namespace frg {
 namespace {
 
 constexpr int kRowsPerBlock = 64;          // 16 rows per wave
-// Batches have blocks to spare: 32 rows per wave halve the per-block point set-up.
-constexpr int kRowsPerBlockBatched = 128;
+// Batches have blocks to spare: blocks of about 160 rows (at most 40 per wave)
+// cut the per-block point set-up, in chunks evened out over a flow's rows.
+constexpr int kRowsPerBlockBatched = 160;
 constexpr int kThreads = 256;
 
 // Weighted divided difference w (h(a) - h(b)) / (a - b) of h(x) = x sech^2 x,
@@ -227,8 +229,8 @@ size_t bubble_lds_bytes(int N, bool paired) {
 // FULL: the full bubble L instead of dL/dT (the interaction flow).  PAIRED: each
 // output position evaluates a pp row q and the ph row of -q at once (rowlist,
 // rowlist_ph): their second lines q - p and p - q have one energy.
-template <int P, bool F32, bool FULL, bool PAIRED, int RPB = kRowsPerBlock>
-__device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int a_patch, double *smem) {
+template <int P, bool F32, bool FULL, bool PAIRED>
+__device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int a_patch, double *smem, int rpb) {
     using PT = typename std::conditional<F32, float, double>::type;
     // The lane's P points (table positions lane*P .. lane*P+P-1, angular
     // neighbours at one radius): in registers for every row (split path with up
@@ -342,20 +344,19 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     };
     const size_t NN = static_cast<size_t>(N) * N;
 
-    const int row0 = chunk * RPB;
+    const int row0 = chunk * rpb;
     // the wave's bins start at zero; each row's output pass clears them again
     for (int b = lane; b < N; b += 64) bins[b] = 0.0;
     if constexpr (PAIRED)
         for (int b = lane; b < N; b += 64) bins2[b] = 0.0;
     // the wave's 16 transfer rows (and a pair's second rows), one per lane, read
     // once: each row then takes them with a lane read instead of a global load
-    constexpr int kRowsPerWave = RPB / 4;
-    static_assert(kRowsPerWave <= 64, "one row index per lane");
+    const int rows_per_wave = rpb >> 2;   // at most 64: one row index per lane
     const int my_slot = row0 + wave + 4 * lane;
-    const bool my_ok = lane < kRowsPerWave && my_slot < A.nrows;
+    const bool my_ok = lane < rows_per_wave && my_slot < A.nrows;
     const int my_r = my_ok ? (A.rowlist ? A.rowlist[my_slot] : my_slot) : 0;
     const int my_rph = (PAIRED && my_ok) ? A.rowlist_ph[my_slot] : 0;
-    for (int it = 0; it < kRowsPerWave; ++it) {
+    for (int it = 0; it < rows_per_wave; ++it) {
         const int rr = wave + 4 * it;
         const int slot_out = row0 + rr;                 // output row position (wave-uniform)
         if (slot_out >= A.nrows) break;
@@ -498,7 +499,7 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
 template <int P, bool F32, bool FULL, bool PAIRED>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void bubble_kernel(BubbleArgs A) {
     extern __shared__ double smem[];
-    bubble_body<P, F32, FULL, PAIRED>(A, blockIdx.x, blockIdx.y, smem);
+    bubble_body<P, F32, FULL, PAIRED>(A, blockIdx.x, blockIdx.y, smem, kRowsPerBlock);
 }
 
 // batched: item = (flow, chunk << 8 | patch); skips flows whose state says stop.
@@ -510,7 +511,8 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel_batched(
     extern __shared__ double smem[];
     const int2 it = items[blockIdx.x];
     if (states && states[it.x][FRG_ST_REASON] != 0.0) return;
-    bubble_body<P, F32, false, PAIRED, kRowsPerBlockBatched>(args[it.x], it.y >> 8, it.y & 255, smem);
+    const BubbleArgs &A = args[it.x];
+    bubble_body<P, F32, false, PAIRED>(A, it.y >> 8, it.y & 255, smem, A.rpb);
 }
 
 template <int P, bool PAIRED>
@@ -555,7 +557,11 @@ void launch_pb(const BubbleArgs *args, const int2 *items, int npaired, int nitem
 
 }  // namespace
 
-int bubble_rows_per_block() { return kRowsPerBlockBatched; }
+int bubble_batched_rows_per_block(int nrows) {
+    const int nch = std::max(1, (nrows + kRowsPerBlockBatched - 1) / kRowsPerBlockBatched);
+    const int per = (nrows + nch - 1) / nch;
+    return std::min(256, (per + 3) / 4 * 4);
+}
 
 void launch_bubbles_batched(const BubbleArgs *args, const int2 *items, int npaired, int nitems,
                             const double *const *states, int nf, int maxN, bool fp32, hipStream_t s) {
