@@ -545,6 +545,48 @@ def test_batched_split_symmetric_flows_follow_every_column_flows():
             assert np.array_equal(Vs[i][np.ix_(pm, pm, pm)], Vs[i])
 
 
+def test_batched_symmetric_split_step_at_benchmark_size():
+    """The benchmark's batched path at its full size (N = 96, n_f = 512: split,
+    symmetric-vertex mode, reduced stage vectors read by the layout, evened-out
+    sweep chunks, batch K parts) against the same flows stepped one at a time,
+    whose symmetric rhs is checked against the every-column rhs and that one
+    against the oracle's sampled entries above."""
+    p0 = I.model_params("C3")
+    cfgs = [p0, dict(p0, mu=-0.9, tp=-0.2, U=2.5)]
+    V0 = [I.random_vertex(p["N"], p["U"], seed=70 + i, amp=0.3, symmetrise=True) for i, p in enumerate(cfgs)]
+    o = frg.flow_opts("dp54", frg.PREC_SPLIT_BF16, T0=1.0, T_min=0.05, rtol=1e-3, atol=1e-6, vmax=1e6,
+                      h0=-0.05)
+    single = []
+    for p, v in zip(cfgs, V0):
+        g = frg.Context(**p)
+        g.set_vsym(True)
+        V = dev(v)
+        st = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+        g.flow_init(o, V, st)
+        g.flow_step(o, V, st)
+        torch.cuda.synchronize()
+        single.append((V.cpu().numpy(), st.cpu().numpy()))
+        del g
+    b = frg.Batch(cfgs)
+    try:
+        b.set_vsym(True)
+        Vs = [dev(v) for v in V0]
+        b.flow_init(Vs, o)
+        b.flow_step()
+        res, _ = b.results()
+        torch.cuda.synchronize()
+        for i, (Vsg, ssg) in enumerate(single):
+            Vb = Vs[i].cpu().numpy()
+            err = nrel(Vb, Vsg)
+            print(f"[C3 batch step] flow {i}: T {res[i]['T_end']:.9f} / {np.exp(ssg[frg.ST_S]):.9f}, V {err:.2e}",
+                  flush=True)
+            assert res[i]["T_end"] == pytest.approx(np.exp(ssg[frg.ST_S]), rel=1e-9)
+            assert err <= 1e-4
+            assert nrel(Vb, V0[i]) > 1e-4
+    finally:
+        b.close()
+
+
 def test_symmetric_vertex_toggled_mid_flow():
     """Switching the mode between steps converts the rhs a DP5(4) flow carries to
     its next step (first same as last) to the new form: a flow switched on after
