@@ -265,7 +265,9 @@ frg_status frg_batch_flow(frg_batch b, const frg_flow_opts *o, double *const *d_
 /* The same in pieces: initialise every member (first stage included), then
  * enqueue one batched step at a time (no synchronisation), then read the
  * members' results (synchronises; all_stopped nullable).  The V buffers must
- * stay valid until the flow is finished. */
+ * stay valid until the flow is finished.  frg_batch_flow_step returns EINVAL
+ * (and the batch needs frg_batch_flow_init again) if a member's workspace was
+ * reallocated in between, e.g. by an rhs on its context in another mode. */
 frg_status frg_batch_flow_init(frg_batch b, const frg_flow_opts *o, double *const *d_V, double *d_log,
                                int32_t log_cap, void *stream);
 frg_status frg_batch_flow_step(frg_batch b, void *stream);
@@ -283,8 +285,9 @@ frg_status frg_batch_results(frg_batch b, frg_flow_result *r, int32_t *all_stopp
 frg_status frg_set_symmetry(frg_ctx ctx, int32_t enable);
 frg_status frg_symmetry(frg_ctx ctx, int32_t *active, int32_t *rows_computed);
 
-/* Zero-block skipping in the channel contractions (Sec. 4, Eq. (3)-(5): the
- * sums over the loop patch pair (a, b) of a bubble row).  The entry (a, b) of
+/* Zero-block skipping in the channel contractions (Sec. 4's one-loop diagrams
+ * integrated over the Brillouin zone on N patches: here the sums over the loop
+ * patch pair (a, b) of a bubble row).  The entry (a, b) of
  * a bubble row is a sum over the fine points of patch a whose second momentum
  * lies in patch b, so it is exactly zero whenever there is no such point; the
  * pattern is fixed by the patch geometry, independent of T.  frg_create orders

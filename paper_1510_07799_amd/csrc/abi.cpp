@@ -77,6 +77,9 @@ struct frg_ctx_s {
     double *d_yr = nullptr, *d_ytr = nullptr, *d_y5r = nullptr;
     int nred = 256;
     int c_parts = 0;        // K parts the channel buffers d_C hold
+    // bumped whenever a workspace buffer is freed and allocated again: captured
+    // graphs and batch descriptors that hold its old address are stale then
+    uint64_t ws_gen = 0;
     int ks_override = 0;    // FRG_KSPLIT
     size_t ws_bytes = 0;
     // event timing (frg_profile_begin/end)
@@ -623,6 +626,12 @@ frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *sta
 frg_status ensure_c(frg_ctx ctx, int KS) {
     if (ctx->c_parts >= KS) return FRG_OK;
     if (ctx->d_C) {
+        // a captured step writes the old buffer: drop it before the buffer goes
+        if (ctx->sg.exec) {
+            hipGraphExecDestroy(ctx->sg.exec);
+            ctx->sg.exec = nullptr;
+        }
+        ctx->ws_gen++;
         hipFree(ctx->d_C);
         ctx->ws_bytes -= sizeof(double) * 3 * static_cast<size_t>(ctx->c_parts + 1) * ctx->n3;
         ctx->d_C = nullptr;
@@ -1122,11 +1131,16 @@ static frg_status flow_step_graph(frg_ctx ctx, const frg_flow_opts *o, double *V
                                   int log_cap, hipStream_t cs, bool iflow) {
     if (ctx->prof || std::getenv("FRG_NO_GRAPH")) return flow_step_impl(ctx, o, V, state, log, log_cap, cs, iflow);
     if (!iflow) ctx->iflow_prec = -1;   // a replayed temperature step overwrites the bubbles too
+    // the channel buffer the step writes is sized first, so that its address
+    // (and the generation of the workspace) is part of the key
+    TRY(ensure_c(ctx, ksplit(ctx)));
     auto P = [](const void *p) { return static_cast<double>(reinterpret_cast<uintptr_t>(p)); };
     const std::vector<double> key = {P(V), P(state), P(log), static_cast<double>(log_cap),
                                      static_cast<double>(o->stepper), static_cast<double>(o->prec), o->rtol,
                                      o->atol, o->vmax, static_cast<double>(o->max_steps), iflow ? 1.0 : 0.0,
-                                     ctx->sym_on ? 1.0 : 0.0, ctx->vsym_on ? 1.0 : 0.0, ctx->kskip_on ? 1.0 : 0.0};
+                                     ctx->sym_on ? 1.0 : 0.0, ctx->vsym_on ? 1.0 : 0.0, ctx->kskip_on ? 1.0 : 0.0,
+                                     P(ctx->d_C), static_cast<double>(ctx->c_parts),
+                                     static_cast<double>(ctx->ws_gen)};
     auto &g = ctx->sg;
     if (!g.stream) {
         HIPCHK(hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking));
@@ -1140,7 +1154,6 @@ static frg_status flow_step_graph(frg_ctx ctx, const frg_flow_opts *o, double *V
             hipGraphExecDestroy(g.exec);
             g.exec = nullptr;
         }
-        TRY(ensure_c(ctx, ksplit(ctx)));
         hipGraph_t graph = nullptr;
         HIPCHK(hipStreamBeginCapture(g.stream, hipStreamCaptureModeThreadLocal));
         const frg_status st = flow_step_impl(ctx, o, V, state, log, log_cap, g.stream, iflow);
@@ -1521,6 +1534,7 @@ struct frg_batch_s {
     bool persistent = false;
     int persistent_grid = 1024;
     int built_prec = -1;            // precision the device arrays describe
+    std::vector<uint64_t> built_gen;   // members' workspace generations the descriptors hold
     hipGraphExec_t exec = nullptr;
     int exec_prec = -1;
     double *d_log = nullptr;
@@ -1711,6 +1725,8 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
     b->n_sum = static_cast<int>(it_sum.size());
     b->n_lay = static_cast<int>(it_lay.size());
     b->built_prec = prec;
+    b->built_gen.resize(b->n);
+    for (int f = 0; f < b->n; ++f) b->built_gen[f] = b->ctx[f]->ws_gen;
     if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; b->exec_prec = -1; }
     return FRG_OK;
 }
@@ -1871,6 +1887,15 @@ frg_status frg_batch_flow_init(frg_batch b, const frg_flow_opts *o, double *cons
 
 frg_status frg_batch_flow_step(frg_batch b, void *stream) {
     if (!b || !b->initialised) return fail(FRG_EINVAL, "batch flow not initialised");
+    for (int f = 0; f < b->n; ++f)
+        if (b->ctx[f]->ws_gen != b->built_gen[f]) {
+            // a member's workspace moved (work on its context through frg_batch_context):
+            // the descriptors and the captured step point at freed memory
+            if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+            b->initialised = false;
+            return fail(FRG_EINVAL, "the workspace of a flow of the batch was reallocated since "
+                                    "frg_batch_flow_init; call it again");
+        }
     hipStream_t cs = static_cast<hipStream_t>(stream);
     hipStream_t s = b->stream;
     HIPCHK(hipEventRecord(b->ev_in, cs));

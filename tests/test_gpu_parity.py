@@ -648,3 +648,46 @@ def test_flow_step_graph_replay_matches_eager():
     print("[flow graph] state differences:", diff, flush=True)
     assert np.array_equal(Ve, Vg)
     assert not diff
+
+
+def test_flow_step_graph_after_workspace_reallocation():
+    """A captured step holds the address of the channel buffer; an eager rhs in
+    symmetric-vertex mode needs more K parts (16 against 8 at N = 32) and
+    reallocates that buffer.  Toggling the mode back must not replay the old
+    graph: the steps equal the eager launches (FRG_NO_GRAPH) bit for bit."""
+    import os
+    om, g = pair(FAST32)
+    N, U = om.N, om.U
+    V0 = I.random_vertex(N, U, seed=55, amp=0.3, symmetrise=True)
+    o = frg.flow_opts("dp54", frg.PREC_FP64, T0=1.0, T_min=0.2, rtol=1e-6, atol=1e-10, vmax=1e6, h0=-0.05)
+
+    def run(graph):
+        if graph:
+            os.environ.pop("FRG_NO_GRAPH", None)
+        else:
+            os.environ["FRG_NO_GRAPH"] = "1"
+        # a fresh context each time, so that the channel buffer starts at the
+        # every-column size
+        c = frg.Context(**FAST32)
+        try:
+            V = dev(V0)
+            st = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+            c.flow_init(o, V, st)
+            c.flow_step(o, V, st)                        # captured with 8 K parts
+            c.set_vsym(True)
+            F = c.rhs(0.3, dev(V0), frg.PREC_FP64)       # 16 K parts: the buffer moves
+            c.set_vsym(False)
+            for _ in range(3):
+                c.flow_step(o, V, st)                    # same key as the first capture
+            torch.cuda.synchronize()
+            return V.cpu().numpy(), st.cpu().numpy(), F.cpu().numpy()
+        finally:
+            os.environ.pop("FRG_NO_GRAPH", None)
+            c.close()
+
+    Ve, se, Fe = run(False)
+    Vg, sg, Fg = run(True)
+    print(f"[graph realloc] V {nrel(Vg, Ve):.2e} F {nrel(Fg, Fe):.2e}", flush=True)
+    assert np.array_equal(Ve, Vg)
+    assert np.array_equal(Fe, Fg)
+    assert np.array_equal(se, sg, equal_nan=True)
