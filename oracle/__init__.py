@@ -21,6 +21,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "frg_oracle.c")
 _LIB = os.path.join(_HERE, "libfrg_oracle.so")
+# A test that plants a mistake in a copy of the oracle (to show that a pin
+# catches it) points this at the mutant's shared library.
+_LIB_OVERRIDE = os.environ.get("FRG_ORACLE_LIB")
 
 PH, PP = 0, 1
 STOP_NONE, STOP_TMIN, STOP_DIVERGED, STOP_MAXSTEPS, STOP_NONFINITE, STOP_HMIN = range(6)
@@ -64,9 +67,12 @@ _IP = C.POINTER(C.c_int32)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=True)
-        L = C.CDLL(_LIB)
+        if _LIB_OVERRIDE:
+            L = C.CDLL(_LIB_OVERRIDE)
+        else:
+            if not os.path.exists(_LIB):
+                build(force=True)
+            L = C.CDLL(_LIB)
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(_Params)]
         L.orc_destroy.argtypes = [C.c_void_p]
