@@ -156,6 +156,19 @@ frg_status frg_bins(frg_ctx ctx, int32_t kind, uint8_t *d_out, void *stream);
 frg_status frg_bubbles(frg_ctx ctx, double T, frg_precision prec, void *d_bpp, void *d_bph,
                        void *stream);
 
+/* The bubble rows as the rhs sweeps them under the C4v row reduction (Sec. 4
+ * reduces the work with the lattice symmetries): one pp row q per C4v orbit of
+ * the transfers, evaluated together with the ph row of -q (the two second
+ * lines share one energy).  frg_bubble_reps gives their number and (host
+ * arrays of n_rep entries, nullable) their pp and ph row indices in the
+ * numbering of frg_bubbles; frg_bubbles_reps writes those rows, pp row i to
+ * d_bpp[i] and its paired ph row to d_bph[i], each [n_rep][N][N] in FP64 or
+ * FP32 by prec (the caller's device buffers).  ENOTSUP when the grid has no
+ * reduction (N % 8 != 0); EINVAL for bad T or a null or misaligned output. */
+frg_status frg_bubble_reps(frg_ctx ctx, int32_t *n_rep, int32_t *pp_rows, int32_t *ph_rows);
+frg_status frg_bubbles_reps(frg_ctx ctx, double T, frg_precision prec, void *d_bpp, void *d_bph,
+                            void *stream);
+
 /* One rhs evaluation F = dV/dT at temperature T for all N^3 entries (Eq. (1)
  * with V frozen; the three one-loop channels).  d_V and d_F are [N][N][N]
  * FP64 and must not overlap. */

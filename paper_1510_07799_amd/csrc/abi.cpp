@@ -38,6 +38,7 @@ struct frg_ctx_s {
     // C4v orbit reduction of the bubble rows
     bool sym_avail = false, sym_on = false;
     int n_rep_pp = 0, n_rep_ph = 0;
+    std::vector<int32_t> h_rowlist, h_rowlist_ph;   // host copies of the two lists below
     int32_t *d_rowlist = nullptr;      // representative pp rows
     int32_t *d_rowlist_ph = nullptr;   // per representative pp row q: the ph row of -q (its pair)
     int32_t *d_colsym_pp = nullptr, *d_colsym_ph = nullptr;   // (compact rep << 3) | element
@@ -331,6 +332,8 @@ frg_status build_orbits(frg_ctx ctx) {
     if (bad != 0) return FRG_OK;   // an exception to exact covariance: keep every row
     TRY(upload(ctx, &ctx->d_rowlist, rowlist.data(), rowlist.size()));
     TRY(upload(ctx, &ctx->d_rowlist_ph, rowlist_ph.data(), rowlist_ph.size()));
+    ctx->h_rowlist = rowlist;
+    ctx->h_rowlist_ph = rowlist_ph;
     TRY(upload(ctx, &ctx->d_colsym_pp, cs_pp.data(), cs_pp.size()));
     TRY(upload(ctx, &ctx->d_colsym_ph, cs_ph.data(), cs_ph.size()));
     ctx->n_rep_pp = npp;
@@ -981,6 +984,31 @@ frg_status frg_bubbles(frg_ctx ctx, double T, frg_precision prec, void *d_bpp, v
     TRY(ensure_rhs_ws(ctx, prec));
     return run_bubbles(ctx, prec == FRG_PREC_SPLIT_BF16, T, nullptr, 0.0, d_bpp, d_bph,
                        static_cast<hipStream_t>(stream));
+}
+
+frg_status frg_bubble_reps(frg_ctx ctx, int32_t *n_rep, int32_t *pp_rows, int32_t *ph_rows) {
+    TRY(check_ctx(ctx));
+    if (!ctx->sym_avail) return fail(FRG_ENOTSUP, "no C4v row reduction on this grid (N % 8 != 0)");
+    const size_t n = ctx->h_rowlist.size();
+    if (n_rep) *n_rep = static_cast<int32_t>(n);
+    for (size_t i = 0; i < n; ++i) {
+        if (pp_rows) pp_rows[i] = ctx->h_rowlist[i];
+        if (ph_rows) ph_rows[i] = ctx->h_rowlist_ph[i] - ctx->g.Tpp;
+    }
+    return FRG_OK;
+}
+
+frg_status frg_bubbles_reps(frg_ctx ctx, double T, frg_precision prec, void *d_bpp, void *d_bph,
+                            void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_prec(prec));
+    if (!ctx->sym_avail) return fail(FRG_ENOTSUP, "no C4v row reduction on this grid (N % 8 != 0)");
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(FRG_EINVAL, "T must be finite and > 0");
+    if (!d_bpp || !d_bph) return fail(FRG_EINVAL, "the paired sweep writes both outputs");
+    if (!aligned8(d_bpp) || !aligned8(d_bph)) return fail(FRG_EINVAL, "misaligned output");
+    TRY(ensure_rhs_ws(ctx, prec));
+    return run_bubbles(ctx, prec == FRG_PREC_SPLIT_BF16, T, nullptr, 0.0, d_bpp, d_bph,
+                       static_cast<hipStream_t>(stream), true);
 }
 
 frg_status frg_rhs(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_precision prec,

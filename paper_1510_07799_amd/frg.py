@@ -75,6 +75,8 @@ SIGNATURES = {
     "frg_host_tables": (C.c_int, [C.POINTER(Params), _DP, _DP, _DP, _DP, _DP, _IP]),
     "frg_bins": (C.c_int, [_P, C.c_int32, _P, _P]),
     "frg_bubbles": (C.c_int, [_P, C.c_double, C.c_int, _P, _P, _P]),
+    "frg_bubble_reps": (C.c_int, [_P, _IP, _IP, _IP]),
+    "frg_bubbles_reps": (C.c_int, [_P, C.c_double, C.c_int, _P, _P, _P]),
     "frg_rhs": (C.c_int, [_P, C.c_double, _P, _P, C.c_int, _P]),
     "frg_flow_init": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, _P]),
     "frg_flow_step": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, _P]),
@@ -243,6 +245,25 @@ class Context:
         Bpp = torch.empty((self.Tpp, N, N), dtype=dt, device="cuda")
         Bph = torch.empty((self.Tph, N, N), dtype=dt, device="cuda")
         _check(lib().frg_bubbles(self._h, float(T), int(prec), _ptr(Bpp), _ptr(Bph), _stream()))
+        return Bpp, Bph
+
+    def bubble_reps(self):
+        """(pp rows, paired ph rows) that the C4v-reduced sweep evaluates."""
+        n = C.c_int32()
+        _check(lib().frg_bubble_reps(self._h, C.byref(n), None, None))
+        pp = np.zeros(n.value, dtype=np.int32)
+        ph = np.zeros(n.value, dtype=np.int32)
+        _check(lib().frg_bubble_reps(self._h, C.byref(n), pp.ctypes.data_as(_IP), ph.ctypes.data_as(_IP)))
+        return pp, ph
+
+    def bubbles_reps(self, T: float, prec=PREC_FP64):
+        """The paired sweep of the rhs: rows [n_rep][N][N] of both kinds."""
+        torch = self.torch
+        dt = torch.float64 if prec == PREC_FP64 else torch.float32
+        n = len(self.bubble_reps()[0])
+        Bpp = torch.empty((n, self.N, self.N), dtype=dt, device="cuda")
+        Bph = torch.empty((n, self.N, self.N), dtype=dt, device="cuda")
+        _check(lib().frg_bubbles_reps(self._h, float(T), int(prec), _ptr(Bpp), _ptr(Bph), _stream()))
         return Bpp, Bph
 
     def bubbles_full(self, T: float, prec=PREC_FP64):
