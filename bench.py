@@ -6,10 +6,13 @@ Workload: 2D Hubbard model, N = 96 patches, 512 fine points per patch
 One timed step is one Dormand-Prince 5(4) step of the temperature flow run
 entirely on the device: six rhs evaluations (bubble sweep, operand layout,
 the fused channel contraction, combine) plus the FP64 stage sums, error norm
-and step control.  The split-BF16 and FP64 paths of one flow are timed in
-regions of their own; `value` is the batched leg's split-BF16 rhs evaluations
-per second (16 flows at N = 96 stepped together), the single-flow rates are
-reported beside it.
+and step control.  The split-BF16 and FP64 paths of one flow, and batches of
+16 flows in either precision, are timed in regions of their own; `value` is the
+batched leg's split-BF16 rhs evaluations per second (16 flows at N = 96 stepped
+together).  `ratios` holds the like-for-like speed-ups (both sides computing one
+contraction column per C4v orbit); `symmetric_vertex_gain` the speed-up of that
+reduction itself over computing every column.  `roofline` describes the
+dominant kernel of the batched leg.
 
 Prints one JSON line.  --gpus N > 1 is not supported (one GPU per process).
 """
@@ -94,62 +97,74 @@ def timed_iflow_steps(frg, torch, ctx, prec, V0, T, steps, warmup):
     return t1 - t0, prof, rhs1 - rhs0, rhs2 - rhs1, st
 
 
-def roofline(head, results, algo_flops, dense_flops, exec_share, evals_per_rhs, kernel=None):
-    prof = head["prof"]
-    dom = kernel or max(prof, key=lambda k: prof[k][0])
-    ms, cnt = prof[dom]
-    avg_s = ms / max(cnt, 1) * 1e-3
-    leg_name = "split" if "split" in results else [k for k in results][0]
-    if dom.startswith("contract"):
-        peak = PEAK["bf16_TFLOPs"] if leg_name == "split" else PEAK["fp64_TFLOPs"]
-        achieved = algo_flops[dom] / avg_s / 1e12
-        roof = {"kernel": dom, "bound": "mfma", "achieved": round(achieved, 4), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 6)}
-        passes = 3.0 if leg_name == "split" else 1.0
-        roof["executed_frac"] = round(passes * dense_flops * exec_share / avg_s / 1e12 / peak, 6)
-        roof["kskip_executed_share"] = round(exec_share, 4)
-    elif dom == "bubbles":
-        # plain ALU bound: vector FMA issue without packed FP32 (the build disables it),
-        # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s for FP32 and FP64.
-        # Algorithmic work (flop-equivalents: FMA 2, a transcendental 4): per second-line
-        # energy 12 (FP64 eps) + 9 (exp(-2|b|) and the terms a pair shares), per bubble
-        # term 10 (its divided difference's own division and the run add); the
-        # unshared Taylor branch is not counted
-        peak = PEAK["valu_TFLOPs"]
-        energies, terms = evals_per_rhs
-        achieved = (21.0 * energies + 10.0 * terms) / avg_s / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": round(achieved, 4), "peak": peak,
-                "unit": "TFLOP/s", "frac": round(achieved / peak, 6),
-                "work": {"energies_per_launch": energies, "terms_per_launch": terms}}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": PEAK["hbm_GBs"],
-                "unit": "GB/s", "frac": None}
-    roof["avg_launch_ms"] = round(avg_s * 1e3, 4)
-    traffic = None
+def load_profiles():
     try:
         with open(TRAFFIC_FILE) as fh:
             tr = json.load(fh)
-        per_leg = tr.get("kernels", {}).get(leg_name, {})
-        if tr.get("source_hash") == kernel_source_hash() and dom in per_leg:
-            traffic = per_leg[dom]["bytes_per_launch"]
     except (OSError, ValueError):
-        traffic = None
-    roof["traffic"] = traffic
-    if dom == "bubbles":
-        # hardware view from the profiler's instruction counts (same kernel sources):
-        # VALU issue cycles (4 per wave64 instruction on a 16-lane SIMD, 16 for a
-        # quarter-rate transcendental) over the 1024 SIMDs' cycles at 2.4 GHz
-        roof["valu_issue_frac"] = None
-        try:
-            with open(TRAFFIC_FILE) as fh:
-                tr = json.load(fh)
-            vb = tr.get("valu", {}).get(leg_name, {}).get("bubbles")
-            if tr.get("source_hash") == kernel_source_hash() and vb:
-                cyc = 4.0 * vb["insts_valu"] + 12.0 * vb["insts_trans_f32"]
-                roof["valu_issue_frac"] = round(cyc / (1024 * avg_s * 2.4e9), 4)
-        except (OSError, ValueError, KeyError):
-            pass
+        return None
+    return tr if tr.get("source_hash") == kernel_source_hash() else None
+
+
+def bubble_roofline(avg_s, terms, energies, leg, kernel):
+    """The sweep is bound by plain vector ALU work.  Algorithmic unit (the survey's):
+    50 FP32 operation-equivalents per dL/dT term (two cosines, two exponential-class
+    operations, one division, ~30 flops, a projection and a compensated add),
+    against the FP32 vector peak 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed)
+    x 2.4 GHz = 157.3 TFLOP/s.  The build disables packed FP32, so 78.6 TFLOP/s is
+    the rate its instructions can reach; frac_nonpacked states that view."""
+    achieved = 50.0 * terms / avg_s / 1e12
+    roof = {"kernel": kernel, "bound": "alu", "achieved": round(achieved, 4), "peak": PEAK["fp32_TFLOPs"],
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK["fp32_TFLOPs"], 6),
+            "frac_nonpacked": round(achieved / PEAK["valu_TFLOPs"], 6),
+            "work": {"terms_per_launch": int(terms), "energies_per_launch": int(energies),
+                     "op_equivalents_per_term": 50},
+            "avg_launch_ms": round(avg_s * 1e3, 4)}
+    tr = load_profiles()
+    roof["traffic"] = None
+    roof["valu_issue_frac"] = None
+    if tr:
+        k = tr.get("kernels", {}).get(leg, {}).get("bubbles")
+        if k:
+            roof["traffic"] = k["bytes_per_launch"]
+        vb = tr.get("valu", {}).get(leg, {}).get("bubbles")
+        if vb:
+            # hardware view: VALU issue cycles (4 per wave64 instruction on a 16-lane
+            # SIMD, 16 for a quarter-rate transcendental) over the 1024 SIMDs' cycles
+            cyc = 4.0 * vb["insts_valu"] + 12.0 * vb["insts_trans_f32"]
+            roof["valu_issue_frac"] = round(cyc / (1024 * avg_s * 2.4e9), 4)
     return roof
+
+
+def contract_roofline(avg_s, algo_flops, dense_flops, exec_share, split, leg, kernel):
+    """The contraction is a dense product on the matrix cores: algorithmic flops (N
+    multiply-adds per structurally nonzero bubble entry per computed column)
+    against the dense MFMA peak of its precision."""
+    peak = PEAK["bf16_TFLOPs"] if split else PEAK["fp64_TFLOPs"]
+    achieved = algo_flops / avg_s / 1e12
+    passes = 3.0 if split else 1.0
+    roof = {"kernel": kernel, "bound": "mfma", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 6),
+            "executed_frac": round(passes * dense_flops * exec_share / avg_s / 1e12 / peak, 6),
+            "kskip_executed_share": round(exec_share, 4), "avg_launch_ms": round(avg_s * 1e3, 4),
+            "traffic": None}
+    tr = load_profiles()
+    if tr:
+        k = tr.get("kernels", {}).get(leg, {}).get("contract")
+        if k:
+            roof["traffic"] = k["bytes_per_launch"]
+    return roof
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
@@ -158,12 +173,16 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--legs", default="split,fp64,batch,batch64,split_full,fp64_full,iflow",
-                    help="comma list of split, fp64, batch (16 flows), batch64 (64 flows) in "
-                         "symmetric-vertex mode; split_full, fp64_full (every column computed); "
-                         "iflow (the interaction flow of the paper's working example, N=32)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the CPU-baseline leg (default: every host core)")
+    ap.add_argument("--cpu-only", action="store_true", help="run only the CPU-baseline leg")
+    ap.add_argument("--legs", default="split,fp64,batch,batch_fp64,batch64,split_full,fp64_full,iflow",
+                    help="comma list of split, fp64 (one flow), batch, batch_fp64 (16 flows, split / FP64), "
+                         "batch64 (64 flows, split), all in symmetric-vertex mode; split_full, fp64_full "
+                         "(one flow, every column computed); iflow (the interaction flow of the paper's "
+                         "working example, N=32)")
     ap.add_argument("--batch-flows", type=int, default=16,
-                    help="flows in the batched leg (N=96, 512 points/patch, drawn parameters)")
+                    help="flows in the batched legs (N=96, 512 points/patch, drawn parameters)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes three times (calibrates "
                          "the HBM byte counters of a profiler run) and exit")
@@ -184,11 +203,17 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
-    from paper_1510_07799_amd import frg, inputs as I
+    from paper_1510_07799_amd import inputs as I
 
     p = I.model_params("C3")
     N = p["N"]
+    if args.cpu_only:
+        print(json.dumps({"cpu_baseline": cpu_baseline(args, p)}))
+        return
+
+    import torch
+    from paper_1510_07799_amd import frg
+
     nf = p["n_rad"] * p["n_ang"]
     ctx = frg.Context(**p)
     V0 = torch.full((N, N, N), float(p["U"]), dtype=torch.float64, device="cuda")
@@ -218,35 +243,44 @@ def main():
     vsym_cols = ctx.vsym()[1]
     ctx.set_vsym(False)
     algo_full = 2.0 * N * colsum_pp + 2.0 * N * colsum_ph + 4.0 * N * colsum_ph
-    algo_flops = {"contract": algo_full * vsym_cols / (N * N)}
+    algo_vsym = algo_full * vsym_cols / (N * N)
     dense_flops = 8.0 * N ** 5   # what the dense formulation executes (x3 passes in split mode)
     ctx.set_vsym(True)
     _, exec_share = ctx.kskip()   # share of the dense k chunks (all columns) the contraction visits
     # bubble terms one rhs evaluates (C4v-reduced rows) and second-line energies
     # (a pp row and the ph row of the opposite transfer share one energy)
     sym_rows = ctx.symmetry()[1]
-    evals_per_rhs = (sym_rows // 2 * N * nf, sym_rows * N * nf)
+    terms_per_rhs, energies_per_rhs = sym_rows * N * nf, sym_rows // 2 * N * nf
 
     legs = [x.strip() for x in args.legs.split(",") if x.strip()]
+    from paper_1510_07799_amd import tuning as TU
+    table = TU.load()
+    tuned = {}
     results = {}
     for leg in legs:
-        if leg in ("batch", "batch64", "iflow"):
+        if leg.startswith("batch") or leg == "iflow":
             continue
         prec = frg.PREC_FP64 if leg.startswith("fp64") else frg.PREC_SPLIT_BF16
-        ctx.set_vsym(not leg.endswith("_full"))   # the flows start from V = U: C4v invariant
+        orbit = not leg.endswith("_full")
+        ctx.set_vsym(orbit)   # the flows start from V = U: C4v invariant
+        entry = TU.lookup(N, nf, prec == frg.PREC_SPLIT_BF16, orbit, 1, table)
+        TU.apply(ctx, entry)
+        tuned[leg] = ctx.tuning()
         dt, prof, st = timed_flow_steps(frg, torch, ctx, prec, V0, args.steps, args.warmup)
         results[leg] = dict(seconds=dt, prof=prof, state=st)
     ctx.set_vsym(True)
-    batch = None
-    def run_batch(nflows):
+
+    def run_batch(nflows, prec):
         # batched workload at N = 96: (mu, t', U) from the seeded draws of the batched configuration
         draws = I.c4_flows(n_per_N=nflows, Ns=(96,), n_rad=p["n_rad"], n_ang=p["n_ang"])
         b = frg.Batch(draws)
         b.set_vsym(True)
+        if TU.apply(b, TU.lookup(N, nf, prec == frg.PREC_SPLIT_BF16, True, nflows, table)):
+            tuned[f"batch of {nflows} {'split' if prec == frg.PREC_SPLIT_BF16 else 'fp64'}"] = \
+                TU.lookup(N, nf, prec == frg.PREC_SPLIT_BF16, True, nflows, table)
         sym = b.symmetry()
         Vs = [torch.full((N, N, N), float(d["U"]), dtype=torch.float64, device="cuda") for d in draws]
-        o = frg.flow_opts("dp54", frg.PREC_SPLIT_BF16, T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10,
-                          vmax=20.0, h0=-0.01)
+        o = frg.flow_opts("dp54", prec, T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.01)
         b.flow_init(Vs, o)
         for _ in range(args.warmup):
             b.flow_step()
@@ -258,17 +292,30 @@ def main():
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
         res1, _ = b.results()
-        active_steps = sum(1 for r in res1 if r["reason"] == 0)
+        # per kernel class: a few more steps launched eagerly with events between the classes
+        b.profile_begin()
+        for _ in range(PROFILE_STEPS):
+            b.flow_step()
+        prof = b.profile_end()
+        res2, _ = b.results()
         rhs_done = sum(r1["rhs_evals"] - r0["rhs_evals"] for r0, r1 in zip(res0, res1))
-        out_b = dict(seconds=tb, rhs=rhs_done, flows=len(draws), still_running=active_steps,
+        rhs_prof = sum(r2["rhs_evals"] - r1["rhs_evals"] for r1, r2 in zip(res1, res2))
+        out_b = dict(seconds=tb, rhs=rhs_done, flows=len(draws), prof=prof, rhs_prof=rhs_prof,
+                     still_running=sum(1 for r in res1 if r["reason"] == 0),
+                     mean_active=rhs_done / (RHS_PER_STEP * args.steps),
+                     mean_active_prof=rhs_prof / (RHS_PER_STEP * PROFILE_STEPS),
                      reduced=sum(1 for a, _ in sym if a))
         b.close()
         del Vs
         torch.cuda.empty_cache()
         return out_b
 
-    batch = run_batch(args.batch_flows) if "batch" in legs else None
-    batch64 = run_batch(64) if "batch64" in legs else None
+    batches = {}
+    for leg, nfl, prec in (("batch", args.batch_flows, frg.PREC_SPLIT_BF16),
+                           ("batch_fp64", args.batch_flows, frg.PREC_FP64),
+                           ("batch64", 64, frg.PREC_SPLIT_BF16)):
+        if leg in legs:
+            batches[leg] = run_batch(nfl, prec)
 
     iflow = None
     if "iflow" in legs:
@@ -290,14 +337,17 @@ def main():
                                                if c}}
         ci.close()
 
-    head = results.get("split") or (results[next(iter(results))] if results else None)
-    if head is None and batch is None:
+    head = batches.get("batch")
+    if head is None and not results:
         print(json.dumps({"iflow_p1": iflow}))
         return
-    dt = head["seconds"] if head else batch["seconds"]
-    value = RHS_PER_STEP * args.steps / dt
-    if batch is not None:
-        value = batch["rhs"] / batch["seconds"]
+    rate = {leg: RHS_PER_STEP * args.steps / r["seconds"] for leg, r in results.items()}
+    rate.update({leg: bb["rhs"] / bb["seconds"] for leg, bb in batches.items()})
+    if head is not None:
+        value, ms_step = rate["batch"], 1e3 * head["seconds"] / args.steps
+    else:
+        leg0 = next(iter(results))
+        value, ms_step = rate[leg0], 1e3 * results[leg0]["seconds"] / args.steps
     out = {
         "metric": "fRG rhs evals/sec at N=96 (split-BF16 vs FP64, same GPU); % MFMA/HBM roofline",
         "value": round(value, 3),
@@ -305,78 +355,121 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * dt / args.steps, 4),
+        "ms_per_step": round(ms_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x3-fp32" if "split" in results else "f64",
+        "dtype": "bf16x3-fp32",
         "data": "synthetic",
-        "config": {"workload": "hubbard-2d N=96 patches, 512 fine points/patch (32x16), "
-                               "t'=-0.3 mu=-1.2 U=3, DP5(4) temperature flow step (6 rhs) from V=U",
+        "config": {"workload": "hubbard-2d N=96 patches, 512 fine points/patch (32x16), DP5(4) temperature "
+                               "flow steps (6 rhs each) from V=U at T=1; value = batched split-BF16 rhs/s of "
+                               f"{args.batch_flows} flows at N=96 with (mu, t', U) drawn as in the batched "
+                               "configuration; single-flow legs at t'=-0.3 mu=-1.2 U=3",
                    "N": N, "n_f": nf, "rhs_per_step": RHS_PER_STEP, "parallelism": "1 GPU",
-                   "symmetry": f"C4v: bubble rows per transfer orbit; vertex C4v invariant, "
-                               f"{vsym_cols} of {N * N} columns per channel computed "
-                               f"({vsym_cols * N} independent entries; split_full and fp64_full compute all)"},
+                   "symmetry": f"C4v: bubble rows per transfer orbit; vertex C4v invariant, {vsym_cols} of "
+                               f"{N * N} columns per channel computed ({vsym_cols * N} independent entries); "
+                               "the *_every_column legs compute all columns"},
     }
+    out["config"]["tuning"] = {"table": "paper_1510_07799_amd/tuning.json" if table else None, "applied": tuned}
+    names = {"split_full": "split_every_column", "fp64_full": "fp64_every_column"}
     for leg, r in results.items():
-        rps = RHS_PER_STEP * args.steps / r["seconds"]
-        out[f"{leg}_rhs_per_s"] = round(rps, 3)
-        out[f"{leg}_kernel_ms_per_rhs"] = {
+        nm = names.get(leg, leg)
+        out[f"{nm}_rhs_per_s"] = round(rate[leg], 3)
+        out[f"{nm}_kernel_ms_per_rhs"] = {
             k: round(ms / (PROFILE_STEPS * RHS_PER_STEP), 4) for k, (ms, c) in r["prof"].items()}
-    if "split" in results and "fp64" in results:
-        out["split_over_fp64"] = round(out["split_rhs_per_s"] / out["fp64_rhs_per_s"], 3)
-    if batch is not None:
-        out["batch_split_rhs_per_s"] = round(batch["rhs"] / batch["seconds"], 3)
-        out["batch"] = {"flows": batch["flows"], "rhs_evaluated": batch["rhs"],
-                        "seconds": round(batch["seconds"], 4),
-                        "flows_running_at_end": batch["still_running"],
-                        "flows_with_c4v_reduction": batch["reduced"]}
-        if "fp64" in results:
-            out["batch_split_over_fp64"] = round(out["batch_split_rhs_per_s"] / out["fp64_rhs_per_s"], 3)
-        if "fp64_full" in results:
-            out["batch_split_over_fp64_full"] = round(out["batch_split_rhs_per_s"] / out["fp64_full_rhs_per_s"], 3)
-        out["config"]["workload"] += (f"; value = batched split-BF16 rhs/s of {batch['flows']} flows "
-                                      "at N=96 with (mu, t', U) drawn as in the batched configuration")
-    if batch64 is not None:
-        out["batch64_split_rhs_per_s"] = round(batch64["rhs"] / batch64["seconds"], 3)
-        out["batch64"] = {"flows": batch64["flows"], "rhs_evaluated": batch64["rhs"],
-                          "seconds": round(batch64["seconds"], 4),
-                          "flows_running_at_end": batch64["still_running"]}
-        for ref in ("fp64", "fp64_full"):
-            if ref in results:
-                out[f"batch64_split_over_{ref}"] = round(out["batch64_split_rhs_per_s"] / out[f"{ref}_rhs_per_s"], 3)
+    for leg, bb in batches.items():
+        out[f"{leg}_rhs_per_s"] = round(rate[leg], 3)
+        out[leg] = {"flows": bb["flows"], "rhs_evaluated": bb["rhs"], "seconds": round(bb["seconds"], 4),
+                    "mean_active_flows": round(bb["mean_active"], 3), "flows_running_at_end": bb["still_running"],
+                    "flows_with_c4v_reduction": bb["reduced"],
+                    "kernel_ms_per_flow_rhs": {k: round(ms / max(1, bb["rhs_prof"]), 4)
+                                               for k, (ms, c) in bb["prof"].items()}}
+    # like-for-like ratios (both sides in the same symmetric-vertex mode); the target
+    # reading is batched split over one FP64 flow
+    ratios = {}
+    if "fp64" in rate:
+        if "split" in rate:
+            ratios["split_over_fp64"] = round(rate["split"] / rate["fp64"], 3)
+        if "batch" in rate:
+            ratios["batch_split_over_fp64"] = round(rate["batch"] / rate["fp64"], 3)
+        if "batch64" in rate:
+            ratios["batch64_split_over_fp64"] = round(rate["batch64"] / rate["fp64"], 3)
+    if "batch" in rate and "batch_fp64" in rate:
+        ratios["batch_split_over_batch_fp64"] = round(rate["batch"] / rate["batch_fp64"], 3)
+    if ratios:
+        ratios["target"] = "batch_split_over_fp64 >= 10"
+        out["ratios"] = ratios
+    # what the triple-orbit reduction (one contraction column per C4v orbit) gains,
+    # apart from precision
+    gain = {}
+    for a, b_ in (("split", "split_full"), ("fp64", "fp64_full")):
+        if a in rate and b_ in rate:
+            gain[a] = round(rate[a] / rate[b_], 3)
+    if gain:
+        out["symmetric_vertex_gain"] = gain
 
     if iflow is not None:
         out["iflow_p1"] = dict(iflow, workload="interaction flow at T=0.1, N=32, 16x16 points/patch, "
                                                "t'=-0.01 mu=-0.02, bare U(g=1)=2, DP5(4) steps from V=U, "
                                                "symmetric-vertex mode; bubbles once per flow")
 
-    # roofline of the dominant kernel of the headline leg (a single-flow leg)
-    if head is None:
-        out["roofline"] = {"kernel": None, "bound": None, "achieved": None, "peak": None, "unit": None,
-                           "frac": None, "traffic": None, "note": "needs a single-flow leg"}
-    else:
-        out["roofline"] = roofline(head, results, algo_flops, dense_flops, exec_share, evals_per_rhs)
-        if out["roofline"]["kernel"] != "contract":
-            out["contract_roofline"] = roofline(head, results, algo_flops, dense_flops, exec_share,
-                                                evals_per_rhs, kernel="contract")
+    # roofline of the dominant kernel of the value leg (the batched sweep), from the
+    # event-timed steps: one launch covers every active flow
+    if head is not None:
+        ms, cnt = head["prof"]["bubbles"]
+        act = head["mean_active_prof"]
+        out["roofline"] = bubble_roofline(ms / max(cnt, 1) * 1e-3, act * terms_per_rhs, act * energies_per_rhs,
+                                          "batch", "bubble_kernel_batched")
+        ms, cnt = head["prof"]["contract"]
+        out["contract_roofline"] = contract_roofline(ms / max(cnt, 1) * 1e-3, act * algo_vsym, act * dense_flops,
+                                                     exec_share, True, "batch", "contract_items")
+    single = {}
+    for leg in ("split", "fp64"):
+        if leg in results:
+            pr = results[leg]["prof"]
+            ms, cnt = pr["bubbles"]
+            single[f"{leg}_bubbles"] = bubble_roofline(ms / max(cnt, 1) * 1e-3, terms_per_rhs, energies_per_rhs,
+                                                       leg, "bubble_kernel")
+            ms, cnt = pr["contract"]
+            single[f"{leg}_contract"] = contract_roofline(ms / max(cnt, 1) * 1e-3, algo_vsym, dense_flops,
+                                                          exec_share, leg == "split", leg, "contract_fused")
+    if single:
+        out["single_flow_rooflines"] = single
+    if head is None and single:
+        out["roofline"] = single.get("split_bubbles") or next(iter(single.values()))
 
     if not args.no_cpu_baseline:
-        import oracle as O
-        O.build(force=False)
-        cores = os.cpu_count() or 1
-        cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
-        O.set_threads(cores)
-        m = O.Model(**p)
-        Vh = np.full((N, N, N), float(p["U"]))
-        t0 = time.perf_counter()
-        m.rhs(0.05, Vh)
-        t_cpu = time.perf_counter() - t0
-        out["cpu_baseline"] = {"value": round(1.0 / t_cpu, 6), "unit": "rhs/s", "cores": cores,
-                               "kind": "oracle",
-                               "sample": "one full FP64 oracle rhs at the benchmark workload "
-                                         "(N=96, 512 points/patch, T=0.05): bubbles + contraction"}
+        out["cpu_baseline"] = cpu_baseline(args, p)
     print(json.dumps(out))
+
+
+def cpu_baseline(args, p):
+    """The oracle as it stands: one full FP64 rhs (bubbles and contraction) at the
+    benchmark workload on the host's cores."""
+    import numpy as np
+    import oracle as O
+    O.build(force=False)
+    cores = os.cpu_count() or 1
+    cores = min(cores, int(os.environ.get("OMP_NUM_THREADS", cores)))
+    if args.cpu_threads > 0:
+        cores = args.cpu_threads
+    O.set_threads(cores)
+    m = O.Model(**p)
+    N = p["N"]
+    Vh = np.full((N, N, N), float(p["U"]))
+    t0 = time.perf_counter()
+    m.rhs(0.05, Vh)
+    t_cpu = time.perf_counter() - t0
+    out = {"value": round(1.0 / t_cpu, 6), "unit": "rhs/s", "cores": cores, "kind": "oracle",
+           "sample": "one full FP64 oracle rhs at the benchmark workload (N=96, 512 points/patch, T=0.05): "
+                     "bubbles + contraction", "cpu_model": cpu_model(), "seconds": round(t_cpu, 3)}
+    one = os.path.join(ROOT, "profiles", "cpu_oracle_n96.json")
+    if args.cpu_threads == 0 and os.path.exists(one):
+        with open(one) as fh:
+            rec = json.load(fh)
+        out["one_thread"] = {"value": rec["cpu_baseline"]["value"], "cpu_model": rec["cpu_baseline"]["cpu_model"],
+                             "source": "profiles/cpu_oracle_n96.json (bench.py --cpu-only --cpu-threads 1)"}
+    return out
 
 
 if __name__ == "__main__":

@@ -347,6 +347,48 @@ enum {
 };
 frg_status frg_profile_begin(frg_ctx ctx);
 frg_status frg_profile_end(frg_ctx ctx, double *ms, int32_t *counts);
+/* ---- Tuning (spec: tile shapes picked by an autotuner; the paper's
+ * load-balancing lessons, Alg. 2 and Sec. 6, are about the same granularity
+ * choices).  Three launch parameters of the rhs:
+ *   kparts      K parts the channel contraction is cut into for the column set
+ *               in use (every column / one per C4v orbit / dense), 1..64;
+ *   sweep_rows  bubble rows per block of the sweep, a multiple of 4 in 4..256
+ *               (single flows; for a batch, rows per block of the batched sweep);
+ *   block_rows  output rows per contraction block: 32, 64 or 96.
+ * A 0 field in frg_set_tuning keeps the current value.  Results do not change
+ * bit for bit with kparts (the K-part sums round differently) but stay within
+ * the bars of the rhs; nothing else changes the arithmetic.  frg_set_tuning
+ * drops a captured step; a batch needs frg_batch_flow_init again. */
+typedef struct {
+    int32_t kparts, sweep_rows, block_rows;
+} frg_tuning;
+frg_status frg_get_tuning(frg_ctx ctx, frg_tuning *t);
+frg_status frg_set_tuning(frg_ctx ctx, const frg_tuning *t);
+/* Autotuner: times the rhs at T on d_V (into d_F, caller's device buffers) in
+ * the context's current mode and precision with HIP events, reps evaluations
+ * per candidate after a warm-up one: first the sweep's rows per block against
+ * the bubble kernels' time, then (block_rows, kparts) against the contraction
+ * and K-part sum time; applies the best and returns it with its per-rhs kernel
+ * time in ms (best, best_ms nullable).  log (host, nullable): up to log_cap rows
+ * of 6 doubles per candidate (kparts, sweep_rows, block_rows, then ms per rhs of
+ * the bubbles, of the contraction and K-part sum, of all kernels); *log_rows
+ * (nullable) receives the number of candidates.  Synchronises. */
+frg_status frg_tune(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_precision prec, int32_t reps,
+                    frg_tuning *best, double *best_ms, double *log, int32_t log_cap, int32_t *log_rows,
+                    void *stream);
+/* The same for a batch: every member takes each candidate, the batched rhs of
+ * all flows (T[i], d_V[i] -> d_F[i]) is timed; frg_batch_set_tuning applies one
+ * tuning to every member.  Both require frg_batch_flow_init again before steps. */
+frg_status frg_batch_set_tuning(frg_batch b, const frg_tuning *t);
+frg_status frg_batch_tune(frg_batch b, const double *T, double *const *d_V, double *const *d_F,
+                          frg_precision prec, int32_t reps, frg_tuning *best, double *best_ms, double *log,
+                          int32_t log_cap, int32_t *log_rows, void *stream);
+
+/* The same for the batched kernels of a batch (one launch per class covers
+ * every flow); while it is on, frg_batch_flow_step launches eagerly instead of
+ * replaying its captured step, so that events sit between the kernels. */
+frg_status frg_batch_profile_begin(frg_batch b);
+frg_status frg_batch_profile_end(frg_batch b, double *ms, int32_t *counts);
 
 const char *frg_status_str(frg_status st);
 const char *frg_last_error(void);

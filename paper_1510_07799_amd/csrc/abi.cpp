@@ -23,6 +23,32 @@ struct TileSet {
     int kparts = 1;   // K parts the chunk lists are cut into
     int32_t *d_cperm = nullptr, *d_cmap = nullptr, *d_koff = nullptr, *d_klist = nullptr;
     int64_t chunks = 0;
+    // host copies for cutting the lists into another number of K parts: chunk id
+    // of every list entry, and where each tile's entries begin (tiles + 1 values)
+    std::vector<int32_t> h_chunk, h_begin;
+};
+
+// Kernel timing with HIP events (frg_profile_* and frg_batch_profile_*): a pool
+// of events and the (class, start, end) records made while it is on.
+struct EvProf {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec { int cls; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    hipEvent_t next() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void begin() { recs.clear(); used = 0; on = true; }
+    void destroy() {
+        for (hipEvent_t e : pool) hipEventDestroy(e);
+        pool.clear();
+    }
 };
 
 struct frg_ctx_s {
@@ -55,6 +81,9 @@ struct frg_ctx_s {
     int iflow_prec = -1;
     TileSet ts_full[2], ts_vsym[2], ts_dense[2];
     int16_t *d_perm8 = nullptr;   // [8][N] C4v patch maps (identity rows when N % 8 != 0)
+    // tuning (frg_set_tuning / frg_tune; 0 = the built-in choice): bubble rows
+    // per block of the sweep, output rows per contraction block
+    int rpb = 0, bm = 0;
     // K parts of the contraction: enough blocks (ks_target per flow) over the
     // tiles of the column set in use, at least ks_lo
     int ks_target = 3456, ks_lo = 1;
@@ -77,14 +106,14 @@ struct frg_ctx_s {
     int64_t nst = 0;
     double *d_yr = nullptr, *d_ytr = nullptr, *d_y5r = nullptr;
     int nred = 256;
-    int c_parts = 0;        // K parts the channel buffers d_C hold
+    size_t c_elems = 0;     // doubles the channel buffer d_C holds
     // bumped whenever a workspace buffer is freed and allocated again: captured
     // graphs and batch descriptors that hold its old address are stale then
     uint64_t ws_gen = 0;
     int ks_override = 0;    // FRG_KSPLIT
     size_t ws_bytes = 0;
     // event timing (frg_profile_begin/end)
-    bool prof = false;
+    EvProf pf;
     // one captured step of a single flow, replayed while its key matches
     struct StepGraph {
         hipGraphExec_t exec = nullptr;
@@ -92,10 +121,6 @@ struct frg_ctx_s {
         hipEvent_t ev_in = nullptr, ev_out = nullptr;
         std::vector<double> key;
     } sg;
-    std::vector<hipEvent_t> ev_pool;
-    size_t ev_used = 0;
-    struct Rec { int cls; hipEvent_t a, b; };
-    std::vector<Rec> recs;
 };
 
 namespace {
@@ -187,34 +212,48 @@ frg_status ensure_flow_ws(frg_ctx ctx) {
     return FRG_OK;
 }
 
-hipEvent_t next_event(frg_ctx ctx) {
-    if (ctx->ev_used == ctx->ev_pool.size()) {
-        hipEvent_t e;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        ctx->ev_pool.push_back(e);
-    }
-    return ctx->ev_pool[ctx->ev_used++];
-}
-
 // Records events around the launches made while it is alive (profiling only).
 struct KTimer {
-    frg_ctx ctx;
+    EvProf &pf;
     int cls;
     hipStream_t s;
     hipEvent_t a = nullptr;
-    KTimer(frg_ctx c, int k, hipStream_t st) : ctx(c), cls(k), s(st) {
-        if (ctx->prof && (a = next_event(ctx))) hipEventRecord(a, s);
+    KTimer(EvProf &p, int k, hipStream_t st) : pf(p), cls(k), s(st) {
+        if (pf.on && (a = pf.next())) hipEventRecord(a, s);
     }
+    KTimer(frg_ctx c, int k, hipStream_t st) : KTimer(c->pf, k, st) {}
     ~KTimer() {
         if (!a) return;
-        hipEvent_t b = next_event(ctx);
+        hipEvent_t b = pf.next();
         if (!b) return;
         hipEventRecord(b, s);
-        ctx->recs.push_back({cls, a, b});
+        pf.recs.push_back({cls, a, b});
     }
 };
 
-frg::BubbleArgs bubble_args(frg_ctx ctx, bool fp32, void *bpp, void *bph) {
+// summed milliseconds and launch counts per kernel class of the records
+frg_status prof_collect(EvProf &pf, double *ms, int32_t *counts) {
+    pf.on = false;
+    double acc[FRG_KERNEL_CLASSES] = {0};
+    int32_t cnt[FRG_KERNEL_CLASSES] = {0};
+    for (const auto &r : pf.recs) {
+        HIPCHK(hipEventSynchronize(r.b));
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+        acc[r.cls] += t;
+        cnt[r.cls] += 1;
+    }
+    pf.recs.clear();
+    pf.used = 0;
+    for (int k = 0; k < FRG_KERNEL_CLASSES; ++k) {
+        if (ms) ms[k] = acc[k];
+        if (counts) counts[k] = cnt[k];
+    }
+    return FRG_OK;
+}
+
+frg::BubbleArgs bubble_args(frg_ctx ctx, bool fp32, void *bpp, void *bph, const double *pa64, const float *pa32,
+                            const double *Tdev) {
     const auto &g = ctx->g;
     frg::BubbleArgs a;
     a.N = g.N;
@@ -230,18 +269,21 @@ frg::BubbleArgs bubble_args(frg_ctx ctx, bool fp32, void *bpp, void *bph) {
     a.bins = ctx->d_bins;
     a.trig_row = ctx->d_trig_row;
     a.trig_pt = ctx->d_trig_pt;
-    a.pa64 = fp32 ? nullptr : ctx->d_pa64;
-    a.pa32 = fp32 ? ctx->d_pa32 : nullptr;
-    a.Tdev = ctx->d_T;
+    a.pa64 = fp32 ? nullptr : pa64;
+    a.pa32 = fp32 ? pa32 : nullptr;
+    a.Tdev = Tdev;
     a.Bpp = bpp;
     a.Bph = bph;
     a.nrows = ctx->Trows;
     a.npp_out = g.Tpp;
     a.rowlist = nullptr;
     a.rowlist_ph = nullptr;
-    a.rpb = 0;
+    a.rpb = ctx->rpb;
     return a;
 }
+
+// output rows per block of the contraction (a tuning, else by N)
+int block_rows(frg_ctx ctx) { return ctx->bm > 0 ? ctx->bm : frg::contract_block_rows(ctx->g.N); }
 
 int c4v_patch_host(int o, int j, int N) {
     const int q = N / 4;
@@ -350,7 +392,7 @@ frg_status build_orbits(frg_ctx ctx) {
 int ksplit_for(frg_ctx ctx, int ncol, int hi) {
     if (ctx->ks_override > 0) return ctx->ks_override;
     const int N = ctx->g.N;
-    const int bm = frg::contract_block_rows(N);
+    const int bm = block_rows(ctx);
     const int64_t tiles = 3LL * ((N + bm - 1) / bm) * ((ncol + 63) / 64);
     const int64_t ks = (ctx->ks_target + tiles - 1) / tiles;
     return static_cast<int>(std::min<int64_t>(hi, std::max<int64_t>(ctx->ks_lo, ks)));
@@ -408,6 +450,25 @@ void cut_parts(const std::vector<int32_t> &chunk_of_entry, int begin, int end, i
     }
 }
 
+// (Re)cut every tile's chunk list of ts into KS parts (the offsets koff); the
+// lists themselves stay.  A new offset table replaces the old one.
+frg_status cut_tileset(frg_ctx ctx, TileSet &ts, int KS) {
+    const int tiles = static_cast<int>(ts.h_begin.size()) - 1;
+    const int nch = ctx->g.N * ctx->g.N / frg::kContractChunk;
+    std::vector<int32_t> koff(static_cast<size_t>(tiles) * (KS + 1));
+    for (int t = 0; t < tiles; ++t)
+        cut_parts(ts.h_chunk, ts.h_begin[t], ts.h_begin[t + 1], KS, nch, ctx->kfixed,
+                  &koff[static_cast<size_t>(t) * (KS + 1)]);
+    if (ts.d_koff) {
+        hipFree(ts.d_koff);
+        ctx->ws_bytes -= sizeof(int32_t) * static_cast<size_t>(tiles) * (ts.kparts + 1);
+        ts.d_koff = nullptr;
+    }
+    TRY(upload(ctx, &ts.d_koff, koff.data(), koff.size()));
+    ts.kparts = KS;
+    return FRG_OK;
+}
+
 // Tile set of class cls over the columns `cols` (natural indices; rep[c] and
 // h[c] give, for every natural column c, the computed column whose values it
 // takes and the C4v element carrying c's free index to it).  Hilbert order of
@@ -453,23 +514,22 @@ frg_status build_tileset(frg_ctx ctx, int cls, const std::vector<int32_t> &cols,
         if (d_flags) hipFree(d_flags);
         if (e != hipSuccess) return fail(FRG_EDEVICE, std::string("column tiles: ") + hipGetErrorString(e));
     }
-    std::vector<int32_t> koff(static_cast<size_t>(tiles) * (KS + 1)), klist, chunk;
+    std::vector<int32_t> klist, chunk, begin(tiles + 1);
     for (int t = 0; t < tiles; ++t) {
-        const int begin = static_cast<int>(klist.size());
+        begin[t] = static_cast<int32_t>(klist.size());
         for (int j = 0; j < nch; ++j)
             if (flags[static_cast<size_t>(t) * nch + j]) {
                 klist.push_back(list_entry(j, N));
                 chunk.push_back(j);
             }
-        cut_parts(chunk, begin, static_cast<int>(klist.size()), KS, nch, ctx->kfixed,
-                  &koff[static_cast<size_t>(t) * (KS + 1)]);
     }
+    begin[tiles] = static_cast<int32_t>(klist.size());
     ts.ncol = ncol;
-    ts.kparts = KS;
     ts.chunks = static_cast<int64_t>(klist.size());
-    TRY(upload(ctx, &ts.d_koff, koff.data(), koff.size()));
+    ts.h_chunk = std::move(chunk);
+    ts.h_begin = std::move(begin);
     TRY(upload(ctx, &ts.d_klist, klist.data(), klist.size()));
-    return FRG_OK;
+    return cut_tileset(ctx, ts, KS);
 }
 
 // every column computed, each its own representative
@@ -602,18 +662,44 @@ void set_tiles(frg_ctx ctx, frg::FusedContractArgs &a) {
     }
 }
 
+// Per-call workspace of one rhs: the point factors and temperature, the bubble
+// rows, the operand layout and the channel partials ([3][KS][cs], then their
+// sums [3][cs], cs = elements computed per channel).  The context's own
+// buffers (ctx_ws, sized by ensure_rhs_ws / ensure_c).
+struct RhsWs {
+    double *pa64 = nullptr, *T = nullptr;
+    float *pa32 = nullptr;
+    double *B64 = nullptr;
+    float *B32 = nullptr;
+    double *perm = nullptr;
+    uint16_t *ahl = nullptr;
+    float *g32 = nullptr;
+    double *C = nullptr;
+    bool own = true;   // the context's buffers
+};
+
+RhsWs ctx_ws(frg_ctx ctx) {
+    RhsWs w;
+    w.pa64 = ctx->d_pa64; w.T = ctx->d_T; w.pa32 = ctx->d_pa32;
+    w.B64 = ctx->d_B64; w.B32 = ctx->d_B32;
+    w.perm = ctx->d_perm; w.ahl = ctx->d_ahl; w.g32 = ctx->d_g32;
+    w.C = ctx->d_C;
+    return w;
+}
+
 // prep + bubbles into the context's bubble tensor (or caller buffers)
 frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *state, double c,
-                       void *bpp, void *bph, hipStream_t s, bool reps_only = false, bool full = false) {
+                       void *bpp, void *bph, hipStream_t s, bool reps_only = false, bool full = false,
+                       const RhsWs *wsp = nullptr) {
+    const RhsWs w = wsp ? *wsp : ctx_ws(ctx);
     {
         KTimer kt(ctx, FRG_K_PREP, s);
         frg::launch_point_prep(ctx->d_xi, ctx->d_w, ctx->g.np, T_host, state, c,
-                               split ? nullptr : ctx->d_pa64, split ? ctx->d_pa32 : nullptr,
-                               ctx->d_T, s);
+                               split ? nullptr : w.pa64, split ? w.pa32 : nullptr, w.T, s);
     }
     {
         KTimer kt(ctx, FRG_K_BUBBLES, s);
-        frg::BubbleArgs ba = bubble_args(ctx, split, bpp, bph);
+        frg::BubbleArgs ba = bubble_args(ctx, split, bpp, bph, w.pa64, w.pa32, w.T);
         if (reps_only) {
             ba.rowlist = ctx->d_rowlist;
             ba.rowlist_ph = ctx->d_rowlist_ph;
@@ -626,8 +712,19 @@ frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *sta
     return FRG_OK;
 }
 
-frg_status ensure_c(frg_ctx ctx, int KS) {
-    if (ctx->c_parts >= KS) return FRG_OK;
+// channel stride: the elements one rhs computes per channel (computed columns
+// x N; N^3 when every column is computed)
+int64_t chan_stride(frg_ctx ctx) { return computed_elems(ctx); }
+// doubles of the channel buffer for the column set in use: K-part partials
+// [3][KS][cs] (float in the split path, in the first half of each part) and
+// their FP64 sums [3][cs]
+size_t c_elems_needed(frg_ctx ctx) {
+    return 3 * static_cast<size_t>(ksplit(ctx) + 1) * static_cast<size_t>(chan_stride(ctx));
+}
+
+frg_status ensure_c(frg_ctx ctx) {
+    const size_t need = c_elems_needed(ctx);
+    if (ctx->c_elems >= need) return FRG_OK;
     if (ctx->d_C) {
         // a captured step writes the old buffer: drop it before the buffer goes
         if (ctx->sg.exec) {
@@ -636,12 +733,11 @@ frg_status ensure_c(frg_ctx ctx, int KS) {
         }
         ctx->ws_gen++;
         hipFree(ctx->d_C);
-        ctx->ws_bytes -= sizeof(double) * 3 * static_cast<size_t>(ctx->c_parts + 1) * ctx->n3;
+        ctx->ws_bytes -= sizeof(double) * ctx->c_elems;
         ctx->d_C = nullptr;
     }
-    // K-part partials [3][KS][n3], then their sums [3][n3]
-    TRY(dalloc(ctx, &ctx->d_C, 3 * static_cast<size_t>(KS + 1) * ctx->n3));
-    ctx->c_parts = KS;
+    TRY(dalloc(ctx, &ctx->d_C, need));
+    ctx->c_elems = need;
     return FRG_OK;
 }
 
@@ -657,28 +753,31 @@ enum RhsMode {
 // split path reads its input from this reduced state instead of V
 frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, double c,
                    const double *V, double *F, int scale_by_T, hipStream_t s, RhsMode mode = RHS_DT,
-                   bool red_out = false, const double *Vred = nullptr) {
+                   bool red_out = false, const double *Vred = nullptr, const RhsWs *wsp = nullptr) {
     const auto &g = ctx->g;
     const int N = g.N;
     const size_t NN = static_cast<size_t>(N) * N;
     const int64_t n3 = ctx->n3;
     const bool sym = ctx->sym_on;
-    const size_t npp_rows = sym ? static_cast<size_t>(ctx->n_rep_pp) : static_cast<size_t>(g.Tpp);
-    void *bpp = split ? static_cast<void *>(ctx->d_B32) : static_cast<void *>(ctx->d_B64);
-    void *bph = split ? static_cast<void *>(ctx->d_B32 + NN * npp_rows)
-                      : static_cast<void *>(ctx->d_B64 + NN * npp_rows);
-    if (mode != RHS_STORED) {
-        ctx->iflow_prec = -1;
-        TRY(run_bubbles(ctx, split, T_host, state, c, bpp, bph, s, sym, mode == RHS_FULL));
-    }
     const int KS = ksplit(ctx);
-    TRY(ensure_c(ctx, KS));
-    double *Cpp = ctx->d_C, *Cc = ctx->d_C + KS * n3, *Cd = ctx->d_C + 2 * KS * n3;
+    const int64_t cs = chan_stride(ctx);
+    if (!wsp) TRY(ensure_c(ctx));
+    const RhsWs w = wsp ? *wsp : ctx_ws(ctx);
+    const size_t npp_rows = sym ? static_cast<size_t>(ctx->n_rep_pp) : static_cast<size_t>(g.Tpp);
+    void *bpp = split ? static_cast<void *>(w.B32) : static_cast<void *>(w.B64);
+    void *bph = split ? static_cast<void *>(w.B32 + NN * npp_rows) : static_cast<void *>(w.B64 + NN * npp_rows);
+    if (mode != RHS_STORED) {
+        if (w.own) ctx->iflow_prec = -1;   // the context's bubble buffer is overwritten
+        TRY(run_bubbles(ctx, split, T_host, state, c, bpp, bph, s, sym, mode == RHS_FULL, &w));
+    }
+    double *Cpp = w.C, *Cc = w.C + KS * cs, *Cd = w.C + 2 * KS * cs;
     frg::FusedContractArgs a;
     std::memset(&a, 0, sizeof(a));
     a.N = N;
     a.KS = KS;
     a.n3 = n3;
+    a.pstride = cs;
+    a.bm = block_rows(ctx);
     set_bubbles(ctx, split, sym, bpp, bph, a);
     a.colrow[frg::TERM_PP] = sym ? ctx->d_colsym_pp : ctx->d_colrow_pp;
     a.colrow[frg::TERM_PHC] = a.colrow[frg::TERM_PHD] = sym ? ctx->d_colsym_ph : ctx->d_colrow_ph;
@@ -688,26 +787,26 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     a.C[frg::TERM_PHD] = Cd;
     {
         KTimer kt(ctx, FRG_K_LAYOUT, s);
-        if (!split) frg::launch_layout_f64(V, N, ctx->d_perm, s);
+        if (!split) frg::launch_layout_f64(V, N, w.perm, s);
         else if (Vred) frg::launch_layout_split_red(Vred, N, col_pos(ctx, 0), col_pos(ctx, 1), ctx->d_perm8,
-                                                    ctx->d_ahl, ctx->d_g32, s);
-        else frg::launch_layout_split(V, N, ctx->d_ahl, ctx->d_g32, s);
+                                                    w.ahl, w.g32, s);
+        else frg::launch_layout_split(V, N, w.ahl, w.g32, s);
     }
-    set_operands(a, split, V, ctx->d_perm, ctx->d_ahl, ctx->d_g32, n3);
+    set_operands(a, split, V, w.perm, w.ahl, w.g32, n3);
     {
         KTimer kt(ctx, FRG_K_CONTRACT, s);
         frg::launch_contract_fused(a, split, s);
     }
     {
         KTimer kt(ctx, FRG_K_COMBINE, s);
-        double *Cs = ctx->d_C + 3 * KS * n3;
-        frg::launch_sum_parts(ctx->d_C, split, KS, n3, computed_elems(ctx), Cs, s);
+        double *Cs = w.C + 3 * KS * cs;
+        frg::launch_sum_parts(w.C, split, KS, cs, cs, Cs, s);
         if (red_out)
-            frg::launch_combine_red(Cs, n3, N, ctx->nst, tiles_of(ctx, 0).d_cperm, col_pos(ctx, 1), ctx->d_perm8,
-                                    ctx->d_T, scale_by_T, F, s);
+            frg::launch_combine_red(Cs, cs, N, ctx->nst, tiles_of(ctx, 0).d_cperm, col_pos(ctx, 1), ctx->d_perm8,
+                                    w.T, scale_by_T, F, s);
         else
-            frg::launch_combine(Cs, Cs + n3, Cs + 2 * n3, false, N, 1, col_pos(ctx, 0), col_pos(ctx, 1),
-                                ctx->d_perm8, ctx->d_T, scale_by_T, F, s);
+            frg::launch_combine(Cs, Cs + cs, Cs + 2 * cs, false, N, 1, col_pos(ctx, 0), col_pos(ctx, 1),
+                                ctx->d_perm8, w.T, scale_by_T, F, s);
     }
     HIPCHK(hipGetLastError());
     return FRG_OK;
@@ -904,7 +1003,7 @@ frg_status frg_destroy(frg_ctx ctx) {
     for (int j = 0; j < 7; ++j)
         if (ctx->d_k[j]) hipFree(ctx->d_k[j]);
     if (ctx->h_state) hipHostFree(ctx->h_state);
-    for (hipEvent_t e : ctx->ev_pool) hipEventDestroy(e);
+    ctx->pf.destroy();
     if (ctx->sg.exec) hipGraphExecDestroy(ctx->sg.exec);
     if (ctx->sg.ev_in) hipEventDestroy(ctx->sg.ev_in);
     if (ctx->sg.ev_out) hipEventDestroy(ctx->sg.ev_out);
@@ -1157,17 +1256,17 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
 // allocated inside it.
 static frg_status flow_step_graph(frg_ctx ctx, const frg_flow_opts *o, double *V, double *state, double *log,
                                   int log_cap, hipStream_t cs, bool iflow) {
-    if (ctx->prof || std::getenv("FRG_NO_GRAPH")) return flow_step_impl(ctx, o, V, state, log, log_cap, cs, iflow);
+    if (ctx->pf.on || std::getenv("FRG_NO_GRAPH")) return flow_step_impl(ctx, o, V, state, log, log_cap, cs, iflow);
     if (!iflow) ctx->iflow_prec = -1;   // a replayed temperature step overwrites the bubbles too
     // the channel buffer the step writes is sized first, so that its address
     // (and the generation of the workspace) is part of the key
-    TRY(ensure_c(ctx, ksplit(ctx)));
+    TRY(ensure_c(ctx));
     auto P = [](const void *p) { return static_cast<double>(reinterpret_cast<uintptr_t>(p)); };
     const std::vector<double> key = {P(V), P(state), P(log), static_cast<double>(log_cap),
                                      static_cast<double>(o->stepper), static_cast<double>(o->prec), o->rtol,
                                      o->atol, o->vmax, static_cast<double>(o->max_steps), iflow ? 1.0 : 0.0,
                                      ctx->sym_on ? 1.0 : 0.0, ctx->vsym_on ? 1.0 : 0.0, ctx->kskip_on ? 1.0 : 0.0,
-                                     P(ctx->d_C), static_cast<double>(ctx->c_parts),
+                                     P(ctx->d_C), static_cast<double>(ctx->c_elems),
                                      static_cast<double>(ctx->ws_gen)};
     auto &g = ctx->sg;
     if (!g.stream) {
@@ -1497,30 +1596,165 @@ frg_status frg_kskip(frg_ctx ctx, int32_t *active, double *executed_frac) {
 
 frg_status frg_profile_begin(frg_ctx ctx) {
     TRY(check_ctx(ctx));
-    ctx->recs.clear();
-    ctx->ev_used = 0;
-    ctx->prof = true;
+    ctx->pf.begin();
     return FRG_OK;
 }
 
 frg_status frg_profile_end(frg_ctx ctx, double *ms, int32_t *counts) {
     TRY(check_ctx(ctx));
-    ctx->prof = false;
-    double acc[FRG_KERNEL_CLASSES] = {0};
-    int32_t cnt[FRG_KERNEL_CLASSES] = {0};
-    for (const auto &r : ctx->recs) {
-        HIPCHK(hipEventSynchronize(r.b));
-        float t = 0.f;
-        HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
-        acc[r.cls] += t;
-        cnt[r.cls] += 1;
+    return prof_collect(ctx->pf, ms, counts);
+}
+
+}  // extern "C"
+
+namespace {
+
+frg_status check_tuning(frg_ctx ctx, const frg_tuning *t) {
+    if (!t) return fail(FRG_EINVAL, "null tuning");
+    if (t->kparts < 0 || t->kparts > 64) return fail(FRG_EINVAL, "kparts must be in 1..64 (0: keep)");
+    if (t->sweep_rows < 0 || t->sweep_rows > 256 || t->sweep_rows % 4 != 0)
+        return fail(FRG_EINVAL, "sweep_rows must be a multiple of 4 in 4..256 (0: keep)");
+    if (t->block_rows != 0 && t->block_rows != 32 && t->block_rows != 64 && t->block_rows != 96)
+        return fail(FRG_EINVAL, "block_rows must be 32, 64 or 96 (0: keep)");
+    (void)ctx;
+    return FRG_OK;
+}
+
+// apply a checked tuning; K parts go to the tile sets of the column set in use
+frg_status apply_tuning(frg_ctx ctx, const frg_tuning *t) {
+    const bool moved = (t->kparts > 0 && t->kparts != ksplit(ctx)) || (t->block_rows > 0 && t->block_rows != block_rows(ctx));
+    if (t->kparts > 0 && t->kparts != ksplit(ctx)) {
+        const int cls_sets = 2;
+        for (int cls = 0; cls < cls_sets; ++cls) {
+            TileSet *ts = !ctx->kskip_on ? &ctx->ts_dense[cls] : (ctx->vsym_on ? &ctx->ts_vsym[cls] : &ctx->ts_full[cls]);
+            TRY(cut_tileset(ctx, *ts, t->kparts));
+        }
     }
-    ctx->recs.clear();
-    ctx->ev_used = 0;
-    for (int k = 0; k < FRG_KERNEL_CLASSES; ++k) {
-        if (ms) ms[k] = acc[k];
-        if (counts) counts[k] = cnt[k];
+    if (t->sweep_rows > 0) ctx->rpb = t->sweep_rows;
+    if (t->block_rows > 0) ctx->bm = t->block_rows;
+    // captured steps and batch descriptors hold the old offset tables and launch shapes
+    if (ctx->sg.exec) {
+        hipGraphExecDestroy(ctx->sg.exec);
+        ctx->sg.exec = nullptr;
     }
+    if (moved || t->sweep_rows > 0) ctx->ws_gen++;
+    return FRG_OK;
+}
+
+frg_tuning tuning_of(frg_ctx ctx) {
+    frg_tuning t;
+    t.kparts = ksplit(ctx);
+    t.sweep_rows = ctx->rpb > 0 ? ctx->rpb : 64;
+    t.block_rows = block_rows(ctx);
+    return t;
+}
+
+// the tuners' record of their candidates: per row kparts, sweep_rows,
+// block_rows and the per-rhs times of the bubble, contraction + K-part sum
+// classes and of all classes (ms)
+struct TuneLog {
+    double *p;
+    int cap, rows;
+    void add(const frg_tuning &t, const double *ms) {
+        if (p && rows < cap) {
+            double *r = p + 6 * static_cast<size_t>(rows);
+            double tot = 0.0;
+            for (int k = 0; k < FRG_KERNEL_CLASSES; ++k) tot += ms[k];
+            r[0] = t.kparts; r[1] = t.sweep_rows; r[2] = t.block_rows;
+            r[3] = ms[FRG_K_BUBBLES]; r[4] = ms[FRG_K_CONTRACT] + ms[FRG_K_COMBINE]; r[5] = tot;
+        }
+        rows++;
+    }
+};
+
+// candidate values searched by the tuners
+const int kTuneKparts[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+const int kTuneRows[] = {16, 32, 64, 128, 160, 256};
+const int kTuneBm[] = {32, 64, 96};
+
+}  // namespace
+
+extern "C" {
+
+frg_status frg_get_tuning(frg_ctx ctx, frg_tuning *t) {
+    TRY(check_ctx(ctx));
+    if (!t) return fail(FRG_EINVAL, "null tuning");
+    *t = tuning_of(ctx);
+    return FRG_OK;
+}
+
+frg_status frg_set_tuning(frg_ctx ctx, const frg_tuning *t) {
+    TRY(check_ctx(ctx));
+    TRY(check_tuning(ctx, t));
+    return apply_tuning(ctx, t);
+}
+
+// Coordinate search with event-timed rhs evaluations: the sweep's rows per
+// block against the bubble class time, then (block rows, K parts) against the
+// contraction and combine time (the K-part sum grows with the parts).
+frg_status frg_tune(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_precision prec, int32_t reps,
+                    frg_tuning *best, double *best_ms, double *log, int32_t log_cap, int32_t *log_rows,
+                    void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_prec(prec));
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(FRG_EINVAL, "T must be finite and > 0");
+    if (!d_V || !d_F || reps < 1) return fail(FRG_EINVAL, "need V, F and reps >= 1");
+    if (ctx->pf.on) return fail(FRG_EINVAL, "frg_tune while kernel timing is on");
+    const bool split = prec == FRG_PREC_SPLIT_BF16;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TRY(ensure_rhs_ws(ctx, prec));
+    // per-class milliseconds of one rhs, averaged over reps (one warm-up rhs first)
+    auto timed = [&](double *cls_ms) -> frg_status {
+        TRY(run_rhs(ctx, split, T, nullptr, 0.0, d_V, d_F, 0, s));
+        ctx->pf.begin();
+        for (int r = 0; r < reps; ++r) {
+            const frg_status st = run_rhs(ctx, split, T, nullptr, 0.0, d_V, d_F, 0, s);
+            if (st) { ctx->pf.on = false; return st; }
+        }
+        double ms[FRG_KERNEL_CLASSES];
+        TRY(prof_collect(ctx->pf, ms, nullptr));
+        for (int k = 0; k < FRG_KERNEL_CLASSES; ++k) cls_ms[k] = ms[k] / reps;
+        return FRG_OK;
+    };
+    TuneLog tl{log, log_cap, 0};
+    frg_tuning cur = tuning_of(ctx);
+    double ms[FRG_KERNEL_CLASSES];
+    double best_bub = 1e300;
+    for (int rows : kTuneRows) {
+        frg_tuning t = cur;
+        t.sweep_rows = rows;
+        TRY(apply_tuning(ctx, &t));
+        TRY(timed(ms));
+        tl.add(t, ms);
+        if (ms[FRG_K_BUBBLES] < best_bub) { best_bub = ms[FRG_K_BUBBLES]; cur.sweep_rows = rows; }
+    }
+    TRY(apply_tuning(ctx, &cur));
+    const int N = ctx->g.N;
+    const int ncol = std::max(tiles_of(ctx, 0).ncol, tiles_of(ctx, 1).ncol);
+    double best_con = 1e300;
+    for (int bm : kTuneBm) {
+        if (bm > 32 && bm - 32 >= N) continue;   // no larger tile than the rows need
+        for (int ks : kTuneKparts) {
+            const int64_t blocks = static_cast<int64_t>(frg::contract_kinds(split)) * ((N + bm - 1) / bm) *
+                                   ((ncol + 63) / 64) * ks;
+            if (blocks > 65536) continue;
+            frg_tuning t = cur;
+            t.block_rows = bm;
+            t.kparts = ks;
+            TRY(apply_tuning(ctx, &t));
+            TRY(timed(ms));
+            tl.add(t, ms);
+            const double c = ms[FRG_K_CONTRACT] + ms[FRG_K_COMBINE];
+            if (c < best_con) { best_con = c; cur.block_rows = bm; cur.kparts = ks; }
+        }
+    }
+    TRY(apply_tuning(ctx, &cur));
+    TRY(timed(ms));
+    double total = 0.0;
+    for (int k = 0; k < FRG_KERNEL_CLASSES; ++k) total += ms[k];
+    if (best) *best = cur;
+    if (best_ms) *best_ms = total;
+    if (log_rows) *log_rows = tl.rows;
     return FRG_OK;
 }
 
@@ -1569,6 +1803,7 @@ struct frg_batch_s {
     int log_cap = 0;
     frg_flow_opts opts{};
     bool initialised = false;
+    EvProf pf;   // frg_batch_profile_begin/end: steps run eagerly with events per kernel class
 };
 
 namespace {
@@ -1604,8 +1839,9 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         // the single-flow K split keeps concurrently running blocks of a flow on
         // one K range of its operands (L2 reuse); the same buffer serves frg_flow_init
         const int KS = ksplit(c);
-        TRY(ensure_c(c, KS));
+        TRY(ensure_c(c));
         const int64_t n3 = c->n3;
+        const int64_t cs = chan_stride(c);
         const size_t NN = static_cast<size_t>(g.N) * g.N;
         const bool sym = c->sym_on;
         const size_t npp_rows = sym ? static_cast<size_t>(c->n_rep_pp) : static_cast<size_t>(g.Tpp);
@@ -1621,7 +1857,8 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         A.yt = c->d_yt; A.y5 = c->d_y5; A.partial = c->d_partial;
         A.perm = c->d_perm; A.ahl = c->d_ahl; A.g32 = c->d_g32; A.C = c->d_C; A.KS = KS;
         A.f32parts = split ? 1 : 0;
-        A.Csum = c->d_C + 3 * KS * n3;
+        A.cs = cs;
+        A.Csum = c->d_C + 3 * KS * cs;
         A.ppos = col_pos(c, 0); A.phpos = col_pos(c, 1);
         A.perm8 = c->d_perm8;
         A.nel = computed_elems(c);
@@ -1630,7 +1867,7 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         A.yr = c->d_yr; A.ytr = c->d_ytr; A.y5r = c->d_y5r;
         A.cperm_pp = tiles_of(c, 0).d_cperm;
         st[f] = A.state;
-        frg::BubbleArgs bb = bubble_args(c, split, bpp, bph);
+        frg::BubbleArgs bb = bubble_args(c, split, bpp, bph, c->d_pa64, c->d_pa32, c->d_T);
         if (sym) {
             bb.rowlist = c->d_rowlist;
             bb.rowlist_ph = c->d_rowlist_ph;
@@ -1644,20 +1881,22 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
             std::memset(&a, 0, sizeof(a));
             const double *V = srcs[s];
             a.N = g.N; a.KS = KS; a.n3 = n3;
-            const int bm = frg::contract_block_rows(g.N);
+            const int bm = block_rows(c);
+            a.bm = bm;
             a.mtiles = (g.N + bm - 1) / bm;
             set_bubbles(c, split, sym, bpp, bph, a);
             a.colrow[frg::TERM_PP] = sym ? c->d_colsym_pp : c->d_colrow_pp;
             a.colrow[frg::TERM_PHC] = a.colrow[frg::TERM_PHD] = sym ? c->d_colsym_ph : c->d_colrow_ph;
             set_tiles(c, a);
             a.ctiles = (std::max(a.ncol[frg::TERM_PP], a.ncol[frg::TERM_PHC]) + 63) / 64;
+            a.pstride = cs;
             a.C[frg::TERM_PP] = c->d_C;
-            a.C[frg::TERM_PHC] = c->d_C + KS * n3;
-            a.C[frg::TERM_PHD] = c->d_C + 2 * KS * n3;
+            a.C[frg::TERM_PHC] = c->d_C + KS * cs;
+            a.C[frg::TERM_PHD] = c->d_C + 2 * KS * cs;
             set_operands(a, split, V, c->d_perm, c->d_ahl, c->d_g32, n3);
         }
         for (int k = 0; k < (g.np + 255) / 256; ++k) it_prep.push_back(make_int2(f, k));
-        const int rpb = frg::bubble_batched_rows_per_block(bb.nrows);
+        const int rpb = c->rpb > 0 ? c->rpb : frg::bubble_batched_rows_per_block(bb.nrows);
         ba[f].rpb = rpb;
         const int chunks = (bb.nrows + rpb - 1) / rpb;
         for (int ch = 0; ch < chunks; ++ch)
@@ -1674,9 +1913,9 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         for (int k = 0; k < A.nred; ++k) it_red.push_back(make_int2(f, k));
         const frg::FusedContractArgs &a0 = ca[0][f];
         const int per_term = a0.mtiles * a0.ctiles * KS;
-        const double kwork = static_cast<double>(NN) / KS * frg::contract_block_rows(g.N);
+        const int bm = block_rows(c);
+        const double kwork = static_cast<double>(NN) / KS * bm;
         const double fcost = 4.0 * per_term * kwork;   // whole flow
-        const int bm = frg::contract_block_rows(g.N);
         const int cls = bm == 32 ? 0 : (bm == 64 ? 1 : 2);
         // K part ks of this flow is served by the XCDs q with q * KS / 8 == ks
         std::vector<int> rr(KS, 0);
@@ -1762,9 +2001,19 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
 // rhs of every flow: input src (V, yt or y5), result T*F into k[stage]
 void batch_rhs_launch(frg_batch b, bool split, double c_stage, int src, int stage, hipStream_t s) {
     const double *const *states = b->d_states;
-    frg::launch_prep_b(b->d_fa, b->d_it_prep, b->n_prep, c_stage, split, s);
-    frg::launch_bubbles_batched(b->d_ba, b->d_it_bub, b->n_bub_pair, b->n_bub, states, b->nf, b->maxN, split, s);
-    frg::launch_layout_b(b->d_fa, b->d_it_lay, b->n_lay, src, split, s);
+    {
+        KTimer kt(b->pf, FRG_K_PREP, s);
+        frg::launch_prep_b(b->d_fa, b->d_it_prep, b->n_prep, c_stage, split, s);
+    }
+    {
+        KTimer kt(b->pf, FRG_K_BUBBLES, s);
+        frg::launch_bubbles_batched(b->d_ba, b->d_it_bub, b->n_bub_pair, b->n_bub, states, b->nf, b->maxN, split, s);
+    }
+    {
+        KTimer kt(b->pf, FRG_K_LAYOUT, s);
+        frg::launch_layout_b(b->d_fa, b->d_it_lay, b->n_lay, src, split, s);
+    }
+    KTimer kc(b->pf, FRG_K_CONTRACT, s);
     const int bms[3] = {32, 64, 96};
     for (int k = 2; k >= 0; --k) {
         if (!b->con_count[k]) continue;
@@ -1777,23 +2026,36 @@ void batch_rhs_launch(frg_batch b, bool split, double c_stage, int src, int stag
         frg::launch_contract_persistent(b->d_ca[src], b->d_it_con, b->d_q + k * 16, b->d_q + k * 16 + 8,
                                         b->d_counter + 8 * k, states, grid, bms[k], split, s);
     }
+}
+
+// channel sums and the combine of every flow (the rhs into k[stage])
+void batch_combine_launch(frg_batch b, int stage, hipStream_t s) {
+    KTimer kt(b->pf, FRG_K_COMBINE, s);
     frg::launch_sum_parts_b(b->d_fa, b->d_it_sum, b->n_sum, s);
     frg::launch_combine_b(b->d_fa, b->d_it_comb, b->n_comb, stage, s);
 }
 
 void batch_step_launch(frg_batch b, const frg_flow_opts *o, hipStream_t s) {
     const bool split = o->prec == FRG_PREC_SPLIT_BF16;
-    frg::launch_step_ctl_b(b->d_fa, b->n, 1, nullptr, 0, o->vmax, o->max_steps, s);
-    frg::launch_vred_b(b->d_fa, b->d_it_st, b->n_st, frg::SRC_V, s);   // reduced flows: y from V
+    {
+        KTimer kt(b->pf, FRG_K_RK, s);
+        frg::launch_step_ctl_b(b->d_fa, b->n, 1, nullptr, 0, o->vmax, o->max_steps, s);
+        frg::launch_vred_b(b->d_fa, b->d_it_st, b->n_st, frg::SRC_V, s);   // reduced flows: y from V
+    }
     for (int st = 1; st < 7; ++st) {
         double coef[7] = {0};
         for (int j = 0; j < st; ++j) coef[j] = DP_A[st][j];
         const int dst = st == 6 ? frg::SRC_Y5 : frg::SRC_YT;
-        frg::launch_rk_stage_b(b->d_fa, b->d_it_st, b->n_st, coef, st, dst, s);
-        // reduced flows: the full rhs input (the split layout reads the reduced one)
-        if (!split) frg::launch_vred_b(b->d_fa, b->d_it_n3, b->n_n3, dst, s);
+        {
+            KTimer kt(b->pf, FRG_K_RK, s);
+            frg::launch_rk_stage_b(b->d_fa, b->d_it_st, b->n_st, coef, st, dst, s);
+            // reduced flows: the full rhs input (the split layout reads the reduced one)
+            if (!split) frg::launch_vred_b(b->d_fa, b->d_it_n3, b->n_n3, dst, s);
+        }
         batch_rhs_launch(b, split, DP_C[st], dst, st, s);
+        batch_combine_launch(b, st, s);
     }
+    KTimer kt(b->pf, FRG_K_RK, s);
     frg::launch_dp_error_b(b->d_fa, b->d_it_red, b->n_red, b->n, DP_E, o->rtol, o->atol, s);
     frg::launch_step_ctl_b(b->d_fa, b->n, 2, b->d_log, b->log_cap, o->vmax, o->max_steps, s);
     frg::launch_accept_b(b->d_fa, b->d_it_n3, b->n_n3, s);
@@ -1865,6 +2127,7 @@ frg_status frg_batch_destroy(frg_batch b) {
     if (b->ev_in) hipEventDestroy(b->ev_in);
     if (b->ev_out) hipEventDestroy(b->ev_out);
     if (b->stream) hipStreamDestroy(b->stream);
+    b->pf.destroy();
     delete b;
     return FRG_OK;
 }
@@ -1928,7 +2191,7 @@ frg_status frg_batch_flow_step(frg_batch b, void *stream) {
     hipStream_t s = b->stream;
     HIPCHK(hipEventRecord(b->ev_in, cs));
     HIPCHK(hipStreamWaitEvent(s, b->ev_in, 0));
-    if (std::getenv("FRG_NO_GRAPH") == nullptr) {
+    if (std::getenv("FRG_NO_GRAPH") == nullptr && !b->pf.on) {
         if (!b->exec) {
             hipGraph_t graph = nullptr;
             HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -1993,6 +2256,113 @@ frg_status frg_batch_flow(frg_batch b, const frg_flow_opts *o, double *const *d_
     return st;
 }
 
+frg_status frg_batch_profile_begin(frg_batch b) {
+    if (!b) return fail(FRG_EINVAL, "null batch");
+    b->pf.begin();
+    return FRG_OK;
+}
+
+frg_status frg_batch_profile_end(frg_batch b, double *ms, int32_t *counts) {
+    if (!b) return fail(FRG_EINVAL, "null batch");
+    return prof_collect(b->pf, ms, counts);
+}
+
+frg_status frg_batch_set_tuning(frg_batch b, const frg_tuning *t) {
+    if (!b) return fail(FRG_EINVAL, "null batch");
+    TRY(check_tuning(b->ctx[0], t));
+    for (frg_ctx c : b->ctx) TRY(apply_tuning(c, t));
+    // descriptors and the captured step describe the old tuning: flow_init again
+    b->initialised = false;
+    b->built_prec = -1;
+    if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; b->exec_prec = -1; }
+    return FRG_OK;
+}
+
+// The batch's coordinate search: every member takes the same candidate; the
+// batched rhs of all flows is timed per kernel class with events.
+frg_status frg_batch_tune(frg_batch b, const double *T, double *const *d_V, double *const *d_F,
+                          frg_precision prec, int32_t reps, frg_tuning *best, double *best_ms, double *log,
+                          int32_t log_cap, int32_t *log_rows, void *stream) {
+    if (!b) return fail(FRG_EINVAL, "null batch");
+    TRY(check_prec(prec));
+    if (!T || !d_V || !d_F || reps < 1) return fail(FRG_EINVAL, "need T, V, F and reps >= 1");
+    if (b->pf.on) return fail(FRG_EINVAL, "frg_batch_tune while kernel timing is on");
+    for (int f = 0; f < b->n; ++f)
+        if (!(T[f] > 0.0) || !std::isfinite(T[f]) || !d_V[f] || !d_F[f])
+            return fail(FRG_EINVAL, "bad T, V or F of a flow");
+    const bool split = prec == FRG_PREC_SPLIT_BF16;
+    hipStream_t cs = static_cast<hipStream_t>(stream);
+    hipStream_t s = b->stream;
+    HIPCHK(hipEventRecord(b->ev_in, cs));
+    HIPCHK(hipStreamWaitEvent(s, b->ev_in, 0));
+    auto timed = [&](double *cls_ms) -> frg_status {
+        TRY(batch_build(b, prec, d_V));
+        for (int f = 0; f < b->n; ++f) {
+            double *h = b->h_state_all + f * FRG_STATE_LEN;
+            for (int i = 0; i < FRG_STATE_LEN; ++i) h[i] = 0.0;
+            h[FRG_ST_S] = std::log(T[f]);
+        }
+        HIPCHK(hipMemcpyAsync(b->d_state_all, b->h_state_all, sizeof(double) * FRG_STATE_LEN * b->n,
+                              hipMemcpyHostToDevice, s));
+        batch_rhs_launch(b, split, 0.0, frg::SRC_V, 0, s);
+        batch_combine_launch(b, 0, s);
+        b->pf.begin();
+        for (int r = 0; r < reps; ++r) {
+            batch_rhs_launch(b, split, 0.0, frg::SRC_V, 0, s);
+            batch_combine_launch(b, 0, s);
+        }
+        double ms[FRG_KERNEL_CLASSES];
+        TRY(prof_collect(b->pf, ms, nullptr));
+        for (int k = 0; k < FRG_KERNEL_CLASSES; ++k) cls_ms[k] = ms[k] / reps;
+        HIPCHK(hipGetLastError());
+        return FRG_OK;
+    };
+    TuneLog tl{log, log_cap, 0};
+    frg_tuning cur = tuning_of(b->ctx[0]);
+    cur.sweep_rows = frg::bubble_batched_rows_per_block(b->ctx[0]->sym_on ? b->ctx[0]->n_rep_pp
+                                                                           : b->ctx[0]->Trows);
+    for (frg_ctx c : b->ctx) TRY(apply_tuning(c, &cur));
+    double ms[FRG_KERNEL_CLASSES];
+    double best_bub = 1e300;
+    for (int rows : kTuneRows) {
+        frg_tuning t = cur;
+        t.sweep_rows = rows;
+        for (frg_ctx c : b->ctx) TRY(apply_tuning(c, &t));
+        TRY(timed(ms));
+        tl.add(t, ms);
+        if (ms[FRG_K_BUBBLES] < best_bub) { best_bub = ms[FRG_K_BUBBLES]; cur.sweep_rows = rows; }
+    }
+    double best_con = 1e300;
+    for (int bm : kTuneBm) {
+        if (bm > 32 && bm - 32 >= b->maxN) continue;
+        for (int ks : kTuneKparts) {
+            if (ks > 32) continue;
+            frg_tuning t = cur;
+            t.block_rows = bm;
+            t.kparts = ks;
+            for (frg_ctx c : b->ctx) TRY(apply_tuning(c, &t));
+            TRY(timed(ms));
+            tl.add(t, ms);
+            const double c = ms[FRG_K_CONTRACT] + ms[FRG_K_COMBINE];
+            if (c < best_con) { best_con = c; cur.block_rows = bm; cur.kparts = ks; }
+        }
+    }
+    for (frg_ctx c : b->ctx) TRY(apply_tuning(c, &cur));
+    TRY(timed(ms));
+    HIPCHK(hipStreamSynchronize(s));
+    double total = 0.0;
+    for (int k = 0; k < FRG_KERNEL_CLASSES; ++k) total += ms[k];
+    b->initialised = false;
+    b->built_prec = -1;
+    if (b->exec) { hipGraphExecDestroy(b->exec); b->exec = nullptr; b->exec_prec = -1; }
+    if (best) *best = cur;
+    if (best_ms) *best_ms = total;
+    if (log_rows) *log_rows = tl.rows;
+    HIPCHK(hipEventRecord(b->ev_out, s));
+    HIPCHK(hipStreamWaitEvent(cs, b->ev_out, 0));
+    return FRG_OK;
+}
+
 frg_status frg_batch_rhs(frg_batch b, const double *T, double *const *d_V, double *const *d_F,
                          frg_precision prec, void *stream) {
     if (!b) return fail(FRG_EINVAL, "null batch");
@@ -2019,13 +2389,15 @@ frg_status frg_batch_rhs(frg_batch b, const double *T, double *const *d_V, doubl
     HIPCHK(hipMemcpyAsync(b->d_state_all, b->h_state_all, sizeof(double) * FRG_STATE_LEN * b->n,
                           hipMemcpyHostToDevice, s));
     batch_rhs_launch(b, prec == FRG_PREC_SPLIT_BF16, 0.0, frg::SRC_V, 0, s);
+    batch_combine_launch(b, 0, s);
     for (int f = 0; f < b->n; ++f) {
         frg_ctx c = b->ctx[f];
         // F from the channel partials (the batched combine left T*F in k[0])
         const int KS = ksplit(c);
-        double *Cs = c->d_C + 3 * KS * c->n3;
-        frg::launch_sum_parts(c->d_C, prec == FRG_PREC_SPLIT_BF16, KS, c->n3, computed_elems(c), Cs, s);
-        frg::launch_combine(Cs, Cs + c->n3, Cs + 2 * c->n3, false, c->g.N, 1,
+        const int64_t cs = chan_stride(c);
+        double *Cs = c->d_C + 3 * KS * cs;
+        frg::launch_sum_parts(c->d_C, prec == FRG_PREC_SPLIT_BF16, KS, cs, cs, Cs, s);
+        frg::launch_combine(Cs, Cs + cs, Cs + 2 * cs, false, c->g.N, 1,
                             col_pos(c, 0), col_pos(c, 1), c->d_perm8, c->d_T, 0, d_F[f], s);
     }
     HIPCHK(hipGetLastError());

@@ -62,7 +62,7 @@ struct BubbleArgs {
     // pairs: when set, position o evaluates the pp row rowlist[o] into Bpp and
     // the ph row rowlist_ph[o] (the opposite transfer) into Bph, both at o
     const int32_t *rowlist_ph;
-    int rpb;   // rows per block of the batched sweep (a multiple of 4, at most 256)
+    int rpb;   // rows per block of the sweep (a multiple of 4, at most 256; 0: the single-flow default)
 };
 // full: the bubble L itself (interaction flow) instead of dL/dT
 void launch_bubbles(const BubbleArgs &a, bool fp32, bool full, hipStream_t s);
@@ -85,6 +85,8 @@ enum Term { TERM_PP = 0, TERM_PHC = 1, TERM_PHD = 2,
 // `part`, laid out [tile position p][m] (p holds column cperm[t][p])
 struct FusedContractArgs {
     int N, KS, mtiles, ctiles;
+    int bm;            // output rows per block: 32, 64 or 96 (0: by N)
+    int64_t pstride;   // elements between K parts of a term's partials (computed columns x N)
     int fast;   // split path: buffer-load fast path (N % 32 == 0, bubble rows < 2 GiB)
     int ncol[3];  // columns computed per term (N^2, or one per C4v orbit of column pairs)
     int64_t n3;
@@ -107,7 +109,7 @@ struct FusedContractArgs {
     const uint16_t *Ahl[3][2];
     const double *G64[3][2];
     const float *G32[3][2];
-    void *C[3];   // partials: float in the split path, double in the FP64 path
+    void *C[3];   // partials [KS][pstride]: float in the split path, double in the FP64 path
 };
 void launch_contract_fused(const FusedContractArgs &a, bool split, hipStream_t s);
 int contract_block_rows(int N);
@@ -141,9 +143,9 @@ int vsym_check_blocks(int N);
 void launch_vsym_check(const double *V, int N, const int16_t *perm8, double *partials, hipStream_t s);
 int combine_tiles(int N);   // blocks of one combine
 // out[t][i] = sum_ks C_t[ks][i] in FP64 for the three channels t and i < nel,
-// where C_t starts at double offset t*KS*n3 of C and holds float (f32parts)
-// or double partials (part stride n3); out is [3][n3]
-void launch_sum_parts(const double *C, bool f32parts, int KS, int64_t n3, int64_t nel, double *out,
+// where C_t starts at double offset t*KS*cs of C and holds float (f32parts)
+// or double partials (part stride cs); out is [3][cs]
+void launch_sum_parts(const double *C, bool f32parts, int KS, int64_t cs, int64_t nel, double *out,
                       hipStream_t s);
 constexpr int kSumPartsPerBlock = 1024;   // elements of out per block of the batched sum
 
@@ -177,7 +179,7 @@ void launch_layout_split_red(const double *Vr, int N, const int32_t *ppos, const
 void launch_vred_gather(const double *V, int N, const int32_t *cperm, int64_t nst, double *Vr, hipStream_t s);
 void launch_vred_expand(const double *Vr, int N, const int32_t *cmap, const int16_t *perm8, const double *gate,
                         double *V, hipStream_t s);
-void launch_combine_red(const double *Cs, int64_t n3, int N, int64_t nst, const int32_t *cperm,
+void launch_combine_red(const double *Cs, int64_t cs, int N, int64_t nst, const int32_t *cperm,
                         const int32_t *phpos, const int16_t *perm8, const double *Tdev, int scale_by_T, double *F,
                         hipStream_t s);
 void launch_accept_copy(int64_t n, const double *state, const double *src, double *dst,
@@ -200,10 +202,11 @@ struct FlowArgs {
     double *perm;
     uint16_t *ahl;
     float *g32;
-    double *C;   // [3][KS][n3] doubles; the split path keeps float partials in it
+    double *C;   // [3][KS][cs] doubles; the split path keeps float partials in it
     int KS;
     int f32parts;  // partials are float (split path)
-    double *Csum;  // [3][n3]: partials summed over the K parts
+    int64_t cs;    // channel stride: elements computed per channel (ncol * N)
+    double *Csum;  // [3][cs]: partials summed over the K parts
     int64_t nel;   // elements per channel actually computed (ncol * N)
     const int16_t *perm8;   // [8][N] C4v patch maps
     const int32_t *ppos, *phpos;   // tile position of each pp / ph column
@@ -245,5 +248,6 @@ void launch_dp_error_b(const FlowArgs *fa, const int2 *items, int nitems, int nf
 void launch_step_ctl_b(const FlowArgs *fa, int nflows, int phase, double *log_base, int log_cap,
                        double vmax, int max_steps, hipStream_t s);
 void launch_accept_b(const FlowArgs *fa, const int2 *items, int nitems, hipStream_t s);
+
 
 }  // namespace frg

@@ -28,7 +28,7 @@ namespace frg {
 
 namespace {
 
-constexpr int kRowsPerBlock = 64;          // 16 rows per wave
+constexpr int kRowsPerBlock = 64;          // 16 rows per wave (default; a tuning may set 4..256)
 // Batches have blocks to spare: blocks of about 160 rows (at most 40 per wave)
 // cut the per-block point set-up, in chunks evened out over a flow's rows.
 constexpr int kRowsPerBlockBatched = 160;
@@ -206,11 +206,33 @@ __device__ __forceinline__ double uniform_f64(double x) {
     return __longlong_as_double(static_cast<long long>((static_cast<uint64_t>(hi) << 32) | lo));
 }
 
-// order the LDS accesses of one wave (its bins are private to it)
+// order the LDS accesses of one wave (its bins are private to it); the fences
+// cover LDS only, so they need no wait for the wave's global loads and stores
 __device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// Pointers read from the argument block are generic to the compiler, which then
+// emits FLAT accesses: those count against the LDS wait counter as well, so
+// every LDS wait of a row would also wait for the loads in flight.  Every
+// operand here is in global memory (address space 1); the transfer-row
+// constants are wave-uniform and read through the scalar cache (address
+// space 4).
+#define GLOBAL_AS __attribute__((address_space(1)))
+#define CONST_AS __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const GLOBAL_AS T *gld(const T *p) {
+    return reinterpret_cast<const GLOBAL_AS T *>(reinterpret_cast<uintptr_t>(p));
+}
+template <class T>
+__device__ __forceinline__ GLOBAL_AS T *gst(T *p) {
+    return reinterpret_cast<GLOBAL_AS T *>(reinterpret_cast<uintptr_t>(p));
+}
+template <class T>
+__device__ __forceinline__ const CONST_AS T *cld(const T *p) {
+    return reinterpret_cast<const CONST_AS T *>(reinterpret_cast<uintptr_t>(p));
 }
 
 // Bins of wave w at smem[w*N ..) (a pair's second row's at smem[(4 + w)*N ..));
@@ -229,7 +251,9 @@ size_t bubble_lds_bytes(int N, bool paired) {
 // FULL: the full bubble L instead of dL/dT (the interaction flow).  PAIRED: each
 // output position evaluates a pp row q and the ph row of -q at once (rowlist,
 // rowlist_ph): their second lines q - p and p - q have one energy.
-template <int P, bool F32, bool FULL, bool PAIRED>
+// PF: the next row's table bytes are loaded while a row is evaluated (the
+// batched kernel; the single-flow kernel is held to 128 registers without it)
+template <int P, bool F32, bool FULL, bool PAIRED, bool PF>
 __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int a_patch, double *smem, int rpb) {
     using PT = typename std::conditional<F32, float, double>::type;
     // The lane's P points (table positions lane*P .. lane*P+P-1, angular
@@ -250,9 +274,11 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     // w = -w_p / 4T^2 (the weighted divided difference takes these); for the
     // full bubble c1 = W tanh(a), c2 = W with W = w_p / 4T = -w T
     const double Tcur = A.Tdev[0];
+    const GLOBAL_AS float *pa32 = gld(A.pa32);
+    const GLOBAL_AS double *pa64 = gld(A.pa64), *trig_pt = gld(A.trig_pt);
     auto point_consts = [&](bool ok, int i, PT &a, PT &c1, PT &c2) {
-        const double wf = ok ? (F32 ? static_cast<double>(A.pa32[2 * np + i]) : A.pa64[2 * np + i]) : 0.0;
-        const double av = ok ? (F32 ? static_cast<double>(A.pa32[i]) : A.pa64[i]) : 0.0;
+        const double wf = ok ? (F32 ? static_cast<double>(pa32[2 * np + i]) : pa64[2 * np + i]) : 0.0;
+        const double av = ok ? (F32 ? static_cast<double>(pa32[i]) : pa64[i]) : 0.0;
         a = static_cast<PT>(av);
         if constexpr (FULL) {
             const double W = -wf * Tcur;
@@ -260,7 +286,7 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             c2 = static_cast<PT>(W);
         } else {
             const PT w = static_cast<PT>(wf);
-            c1 = w * (ok ? static_cast<PT>(F32 ? A.pa32[np + i] : A.pa64[np + i]) : PT(0));
+            c1 = w * (ok ? static_cast<PT>(F32 ? pa32[np + i] : pa64[np + i]) : PT(0));
             c2 = PT(-4) * w;
         }
     };
@@ -272,15 +298,15 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             const int k = lane * P + j;   // table position; fine point (s, m) = (k % n_ang, k / n_ang)
             const bool ok = k < nf;
             const int i = a_patch * nf + (ok ? (k % A.n_ang) * A.n_rad + k / A.n_ang : 0);
-            cpx[j] = ok ? A.trig_pt[i] : 1.0;
-            spx[j] = ok ? A.trig_pt[np + i] : 0.0;
-            cpy[j] = ok ? A.trig_pt[2 * np + i] : 1.0;
-            spy[j] = ok ? A.trig_pt[3 * np + i] : 0.0;
+            cpx[j] = ok ? trig_pt[i] : 1.0;
+            spx[j] = ok ? trig_pt[np + i] : 0.0;
+            cpy[j] = ok ? trig_pt[2 * np + i] : 1.0;
+            spy[j] = ok ? trig_pt[3 * np + i] : 0.0;
             point_consts(ok, i, pa[j], pc1[j], pc2[j]);
             // the block's waves share the coefficients: wave j % 4 makes point j's
             // (expanded around the a the sweep uses, rounded to FP32)
             if ((j & 3) == wave) {
-                const double wf = ok ? static_cast<double>(A.pa32[2 * np + i]) : 0.0;
+                const double wf = ok ? static_cast<double>(pa32[2 * np + i]) : 0.0;
                 tay[j * 64 + lane] = taylor_consts<FULL>(static_cast<double>(pa[j]), FULL ? -wf * Tcur : wf);
             }
         }
@@ -290,10 +316,10 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             const int slot = (k % P) * 64 + k / P;
             const bool ok = k < nf;
             const int i = a_patch * nf + (ok ? (k % A.n_ang) * A.n_rad + k / A.n_ang : 0);
-            pt[0 * S + slot] = ok ? A.trig_pt[i] : 1.0;
-            pt[1 * S + slot] = ok ? A.trig_pt[np + i] : 0.0;
-            pt[2 * S + slot] = ok ? A.trig_pt[2 * np + i] : 1.0;
-            pt[3 * S + slot] = ok ? A.trig_pt[3 * np + i] : 0.0;
+            pt[0 * S + slot] = ok ? trig_pt[i] : 1.0;
+            pt[1 * S + slot] = ok ? trig_pt[np + i] : 0.0;
+            pt[2 * S + slot] = ok ? trig_pt[2 * np + i] : 1.0;
+            pt[3 * S + slot] = ok ? trig_pt[3 * np + i] : 0.0;
             PT a, c1, c2;
             point_consts(ok, i, a, c1, c2);
             pt[4 * S + slot] = a;
@@ -320,16 +346,20 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     const bool vec_bins = (nf % P) == 0 && (P == 4 || P == 8 || P == 16);
     constexpr int W = (P + 3) / 4;
     // second-line patches of the lane's points in table row r, four to a word
+    // the argument block's pointers, read once (stores in the row loop could alias
+    // the block for the compiler, which would otherwise reload them every row)
+    const GLOBAL_AS uint8_t *const gbins = gld(A.bins);
+    const CONST_AS double *const gtrig = cld(A.trig_row);
     auto load_bins = [&](int r, uint32_t *bw) {
-        const uint8_t *brow = A.bins + static_cast<size_t>(r) * np + static_cast<size_t>(a_patch) * nf;
+        const GLOBAL_AS uint8_t *brow = gbins + static_cast<size_t>(r) * np + static_cast<size_t>(a_patch) * nf;
         if (vec_bins) {   // wave-uniform; lanes past n_f read the patch start (zero-weight points)
-            const uint8_t *src = brow + (lane * P < nf ? lane * P : 0);
+            const GLOBAL_AS uint8_t *src = brow + (lane * P < nf ? lane * P : 0);
             if constexpr (P == 4) {
-                bw[0] = *reinterpret_cast<const uint32_t *>(src);
+                bw[0] = *reinterpret_cast<const GLOBAL_AS uint32_t *>(src);
             } else if constexpr (P >= 8) {
 #pragma unroll
                 for (int h = 0; h < P / 8; ++h) {
-                    const uint64_t v = *reinterpret_cast<const uint64_t *>(src + 8 * h);
+                    const uint64_t v = *reinterpret_cast<const GLOBAL_AS uint64_t *>(src + 8 * h);
                     bw[2 * h] = static_cast<uint32_t>(v);
                     bw[2 * h + 1] = static_cast<uint32_t>(v >> 32);
                 }
@@ -356,6 +386,14 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     const bool my_ok = lane < rows_per_wave && my_slot < A.nrows;
     const int my_r = my_ok ? (A.rowlist ? A.rowlist[my_slot] : my_slot) : 0;
     const int my_rph = (PAIRED && my_ok) ? A.rowlist_ph[my_slot] : 0;
+    // second-line patches of the lane's points, loaded one row ahead so that a
+    // row's table bytes are in flight while the previous row is evaluated
+    auto row_valid = [&](int it) { return it < rows_per_wave && row0 + wave + 4 * it < A.nrows; };
+    uint32_t nbw[W], nbw2[PAIRED ? W : 1];
+    if (PF && row_valid(0)) {
+        load_bins(__builtin_amdgcn_readlane(my_r, 0), nbw);
+        if constexpr (PAIRED) load_bins(__builtin_amdgcn_readlane(my_rph, 0), nbw2);
+    }
     for (int it = 0; it < rows_per_wave; ++it) {
         const int rr = wave + 4 * it;
         const int slot_out = row0 + rr;                 // output row position (wave-uniform)
@@ -371,12 +409,26 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
         // operations, each with one scalar operand.  In a pair, r is the pp row.
         const bool pp = PAIRED || r < A.Tpp;
         const double k1 = pp ? -K1 : K1, g = pp ? -G : G, k3 = pp ? -K3 : K3;
-        const double cqx = uniform_f64(k1 * A.trig_row[4 * r]), cqy = uniform_f64(k1 * A.trig_row[4 * r + 2]);
-        const double sx = uniform_f64((pp ? k1 : -k1) * A.trig_row[4 * r + 1]);
-        const double sy = uniform_f64((pp ? k1 : -k1) * A.trig_row[4 * r + 3]);
+        const CONST_AS double *tr = gtrig + 4 * r;
+        const double cqx = uniform_f64(k1 * tr[0]), cqy = uniform_f64(k1 * tr[2]);
+        const double sx = uniform_f64((pp ? k1 : -k1) * tr[1]);
+        const double sy = uniform_f64((pp ? k1 : -k1) * tr[3]);
         uint32_t bw[W], bw2[PAIRED ? W : 1];
-        load_bins(r, bw);
-        if constexpr (PAIRED) load_bins(__builtin_amdgcn_readlane(my_rph, it), bw2);
+        if constexpr (PF) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) bw[w] = nbw[w];
+            if constexpr (PAIRED) {
+#pragma unroll
+                for (int w = 0; w < W; ++w) bw2[w] = nbw2[w];
+            }
+            if (row_valid(it + 1)) {
+                load_bins(__builtin_amdgcn_readlane(my_r, it + 1), nbw);
+                if constexpr (PAIRED) load_bins(__builtin_amdgcn_readlane(my_rph, it + 1), nbw2);
+            }
+        } else {
+            load_bins(r, bw);
+            if constexpr (PAIRED) load_bins(__builtin_amdgcn_readlane(my_rph, it), bw2);
+        }
         auto bin_of = [&](const uint32_t *w, int j) -> int { return (w[j >> 2] >> (8 * (j & 3))) & 0xff; };
         // FP32 Taylor coefficients of point j: from LDS in register mode, else made
         // on the spot (w = -c2 / 4, or W = c2 for the full bubble)
@@ -482,11 +534,11 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             for (int k = 0; k < NO; ++k) {
                 if (!outp[k]) continue;
                 if (F32) {
-                    float *o = static_cast<float *>(outp[k]) + base[k];
+                    GLOBAL_AS float *o = gst(static_cast<float *>(outp[k])) + base[k];
                     o[b0] = static_cast<float>(v[k][0]);
                     if (has1) o[b1] = static_cast<float>(v[k][1]);
                 } else {
-                    double *o = static_cast<double *>(outp[k]) + base[k];
+                    GLOBAL_AS double *o = gst(static_cast<double *>(outp[k])) + base[k];
                     o[b0] = v[k][0];
                     if (has1) o[b1] = v[k][1];
                 }
@@ -499,7 +551,7 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
 template <int P, bool F32, bool FULL, bool PAIRED>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void bubble_kernel(BubbleArgs A) {
     extern __shared__ double smem[];
-    bubble_body<P, F32, FULL, PAIRED>(A, blockIdx.x, blockIdx.y, smem, kRowsPerBlock);
+    bubble_body<P, F32, FULL, PAIRED, false>(A, blockIdx.x, blockIdx.y, smem, A.rpb > 0 ? A.rpb : kRowsPerBlock);
 }
 
 // batched: item = (flow, chunk << 8 | patch); skips flows whose state says stop.
@@ -512,12 +564,13 @@ __global__ __launch_bounds__(kThreads) void bubble_kernel_batched(
     const int2 it = items[blockIdx.x];
     if (states && states[it.x][FRG_ST_REASON] != 0.0) return;
     const BubbleArgs &A = args[it.x];
-    bubble_body<P, F32, false, PAIRED>(A, it.y >> 8, it.y & 255, smem, A.rpb);
+    bubble_body<P, F32, false, PAIRED, true>(A, it.y >> 8, it.y & 255, smem, A.rpb);
 }
 
 template <int P, bool PAIRED>
 void launch_pp(const BubbleArgs &a, bool fp32, bool full, hipStream_t s) {
-    dim3 grid((a.nrows + kRowsPerBlock - 1) / kRowsPerBlock, a.N);
+    const int rpb = a.rpb > 0 ? a.rpb : kRowsPerBlock;
+    dim3 grid((a.nrows + rpb - 1) / rpb, a.N);
     const size_t lds = fp32 ? bubble_lds_bytes<P, true>(a.N, PAIRED) : bubble_lds_bytes<P, false>(a.N, PAIRED);
     if (fp32 && !full)
         hipLaunchKernelGGL((bubble_kernel<P, true, false, PAIRED>), grid, dim3(kThreads), lds, s, a);

@@ -335,8 +335,8 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
         __syncthreads();
     }
     // f64 16x16x4 accumulator layout: lane l, register r holds row (l>>4) + 4r, column l&15;
-    // output C[ks][tile position][m]: a block's tile is one contiguous range
-    GLOBAL_AS double *Cout = gstore_ptr(static_cast<double *>(P.C[TERM])) + static_cast<int64_t>(w.ks) * P.n3;
+    // output C[ks][tile position][m] (part stride pstride): a block's tile is one contiguous range
+    GLOBAL_AS double *Cout = gstore_ptr(static_cast<double *>(P.C[TERM])) + static_cast<int64_t>(w.ks) * P.pstride;
 #pragma unroll
     for (int ci = 0; ci < 2; ++ci) {
         const int pos = c0 + wc * 32 + ci * 16 + (lane & 15);
@@ -663,7 +663,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
 #pragma unroll
     for (int u = 0; u < NACC; ++u) {
         const int term = PH ? (u == 0 ? TERM_PHC : TERM_PHD) : TERM_PP;
-        GLOBAL_AS float *Cout = gstore_ptr(static_cast<float *>(P.C[term])) + static_cast<int64_t>(w.ks) * P.n3;
+        GLOBAL_AS float *Cout = gstore_ptr(static_cast<float *>(P.C[term])) + static_cast<int64_t>(w.ks) * P.pstride;
 #pragma unroll
         for (int ci = 0; ci < 2; ++ci) {
             const int pos = c0 + wc * 32 + ci * 16 + (lane & 15);
@@ -864,7 +864,7 @@ void launch_contract_persistent(const FusedContractArgs *args, const int2 *items
 }
 
 void launch_contract_fused(const FusedContractArgs &a, bool split, hipStream_t s) {
-    const int bm = contract_block_rows(a.N);
+    const int bm = a.bm > 0 ? a.bm : contract_block_rows(a.N);
     if (bm == 32) launch_bm<32>(a, split, s);
     else if (bm == 64) launch_bm<64>(a, split, s);
     else launch_bm<96>(a, split, s);

@@ -554,7 +554,7 @@ __global__ __launch_bounds__(256) void vred_expand_kernel(const double *__restri
     if (i < n3) V[i] = vred_at(Vr, N, cmap, perm8, i);
 }
 
-__global__ __launch_bounds__(256) void combine_red_kernel(const double *__restrict__ Cs, int64_t n3, int N,
+__global__ __launch_bounds__(256) void combine_red_kernel(const double *__restrict__ Cs, int64_t cs, int N,
                                                           int64_t nst, const int32_t *__restrict__ cperm,
                                                           const int32_t *__restrict__ phpos,
                                                           const int16_t *__restrict__ perm8,
@@ -563,13 +563,13 @@ __global__ __launch_bounds__(256) void combine_red_kernel(const double *__restri
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= nst) return;
     const double scale = scale_by_T ? Tdev[0] : 1.0;
-    F[i] = scale * combine_red_at(N, Cs, Cs + n3, Cs + 2 * n3, cperm, phpos, perm8, i);
+    F[i] = scale * combine_red_at(N, Cs, Cs + cs, Cs + 2 * cs, cperm, phpos, perm8, i);
 }
 
 // Sum of the K-part partials, four consecutive elements per thread (streams
 // of contiguous loads, one per part).
 template <typename PT>
-__device__ __forceinline__ void sum_parts_body(const double *__restrict__ C, int KS, int64_t n3, int64_t nel,
+__device__ __forceinline__ void sum_parts_body(const double *__restrict__ C, int KS, int64_t cs, int64_t nel,
                                                double *__restrict__ out, int64_t q) {
     // q runs over [3][nel / 4] quads (nel % 4 == 0: nel = ncol * N, N % 4 == 0)
     const int64_t qpt = nel / 4;
@@ -578,21 +578,21 @@ __device__ __forceinline__ void sum_parts_body(const double *__restrict__ C, int
     const uint32_t q32 = static_cast<uint32_t>(q), qpt32 = static_cast<uint32_t>(qpt);
     const int t = static_cast<int>(q32 / qpt32);
     const int64_t i = 4 * static_cast<int64_t>(q32 - static_cast<uint32_t>(t) * qpt32);
-    const PT *Ct = reinterpret_cast<const PT *>(C + t * static_cast<int64_t>(KS) * n3);
+    const PT *Ct = reinterpret_cast<const PT *>(C + t * static_cast<int64_t>(KS) * cs);
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int s = 0; s < KS; ++s) {
-        const PT *src = Ct + s * n3 + i;
+        const PT *src = Ct + s * cs + i;
 #pragma unroll
         for (int e = 0; e < 4; ++e) v[e] += static_cast<double>(src[e]);
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) out[t * n3 + i + e] = v[e];
+    for (int e = 0; e < 4; ++e) out[t * cs + i + e] = v[e];
 }
 
 template <typename PT>
-__global__ __launch_bounds__(256) void sum_parts_kernel(const double *__restrict__ C, int KS, int64_t n3,
+__global__ __launch_bounds__(256) void sum_parts_kernel(const double *__restrict__ C, int KS, int64_t cs,
                                                         int64_t nel, double *__restrict__ out) {
-    sum_parts_body<PT>(C, KS, n3, nel, out, static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x);
+    sum_parts_body<PT>(C, KS, cs, nel, out, static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x);
 }
 
 // V(g j1, g j2, g j3) - V(j1, j2, j3) over the seven non-trivial C4v elements:
@@ -933,11 +933,11 @@ __global__ __launch_bounds__(256) void combine_b_kernel(const FlowArgs *__restri
     if (f.red) {   // item = block of 256 reduced entries
         const int64_t i = static_cast<int64_t>(it.y) * blockDim.x + threadIdx.x;
         if (i < f.nst)
-            f.k[stage][i] = f.Tdev[0] * combine_red_at(f.N, f.Csum, f.Csum + n, f.Csum + 2 * n, f.cperm_pp,
+            f.k[stage][i] = f.Tdev[0] * combine_red_at(f.N, f.Csum, f.Csum + f.cs, f.Csum + 2 * f.cs, f.cperm_pp,
                                                        f.phpos, f.perm8, i);
         return;
     }
-    combine_body(f.N, 1, n, static_cast<const double *>(f.Csum), f.Csum + n, f.Csum + 2 * n, f.ppos, f.phpos,
+    combine_body(f.N, 1, n, static_cast<const double *>(f.Csum), f.Csum + f.cs, f.Csum + 2 * f.cs, f.ppos, f.phpos,
                  f.perm8, f.Tdev[0], f.k[stage], it.y, sF);
 }
 
@@ -948,8 +948,8 @@ __global__ __launch_bounds__(256) void sum_parts_b_kernel(const FlowArgs *__rest
     const FlowArgs &f = fa[it.x];
     if (flow_stopped(f)) return;
     const int64_t q = static_cast<int64_t>(it.y) * (kSumPartsPerBlock / 4) + threadIdx.x;
-    if (f.f32parts) sum_parts_body<float>(f.C, f.KS, f.n3, f.nel, f.Csum, q);
-    else sum_parts_body<double>(f.C, f.KS, f.n3, f.nel, f.Csum, q);
+    if (f.f32parts) sum_parts_body<float>(f.C, f.KS, f.cs, f.nel, f.Csum, q);
+    else sum_parts_body<double>(f.C, f.KS, f.cs, f.nel, f.Csum, q);
 }
 
 struct Coef7 { double c[7]; };
@@ -1179,10 +1179,10 @@ void launch_vred_expand(const double *Vr, int N, const int32_t *cmap, const int1
     hipLaunchKernelGGL(vred_expand_kernel, dim3(blocks_for(n3, 256)), dim3(256), 0, s, Vr, N, cmap, perm8, n3,
                        gate, V);
 }
-void launch_combine_red(const double *Cs, int64_t n3, int N, int64_t nst, const int32_t *cperm,
+void launch_combine_red(const double *Cs, int64_t cs, int N, int64_t nst, const int32_t *cperm,
                         const int32_t *phpos, const int16_t *perm8, const double *Tdev, int scale_by_T, double *F,
                         hipStream_t s) {
-    hipLaunchKernelGGL(combine_red_kernel, dim3(blocks_for(nst, 256)), dim3(256), 0, s, Cs, n3, N, nst, cperm,
+    hipLaunchKernelGGL(combine_red_kernel, dim3(blocks_for(nst, 256)), dim3(256), 0, s, Cs, cs, N, nst, cperm,
                        phpos, perm8, Tdev, scale_by_T, F);
 }
 void launch_vred_b(const FlowArgs *fa, const int2 *items, int nitems, int dst, hipStream_t s) {
@@ -1203,14 +1203,14 @@ void launch_layout_b(const FlowArgs *fa, const int2 *items, int nitems, int src,
                      hipStream_t s) {
     hipLaunchKernelGGL(layout_b_kernel, dim3(nitems), dim3(256), 0, s, fa, items, src, split ? 1 : 0);
 }
-void launch_sum_parts(const double *C, bool f32parts, int KS, int64_t n3, int64_t nel, double *out,
+void launch_sum_parts(const double *C, bool f32parts, int KS, int64_t cs, int64_t nel, double *out,
                       hipStream_t s) {
     const int64_t quads = 3 * (nel / 4);
     if (f32parts)
-        hipLaunchKernelGGL(sum_parts_kernel<float>, dim3(blocks_for(quads, 256)), dim3(256), 0, s, C, KS, n3, nel,
+        hipLaunchKernelGGL(sum_parts_kernel<float>, dim3(blocks_for(quads, 256)), dim3(256), 0, s, C, KS, cs, nel,
                            out);
     else
-        hipLaunchKernelGGL(sum_parts_kernel<double>, dim3(blocks_for(quads, 256)), dim3(256), 0, s, C, KS, n3, nel,
+        hipLaunchKernelGGL(sum_parts_kernel<double>, dim3(blocks_for(quads, 256)), dim3(256), 0, s, C, KS, cs, nel,
                            out);
 }
 

@@ -60,6 +60,10 @@ class IFlowResult(C.Structure):
                 ("rhs_evals", C.c_int32), ("first_step_rhs", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("kparts", C.c_int32), ("sweep_rows", C.c_int32), ("block_rows", C.c_int32)]
+
+
 _lib = None
 _P = C.c_void_p
 _DP = C.POINTER(C.c_double)
@@ -105,6 +109,15 @@ SIGNATURES = {
     "frg_batch_set_vsym": (C.c_int, [_P, C.c_int32]),
     "frg_profile_begin": (C.c_int, [_P]),
     "frg_profile_end": (C.c_int, [_P, _DP, _IP]),
+    "frg_get_tuning": (C.c_int, [_P, C.POINTER(Tuning)]),
+    "frg_set_tuning": (C.c_int, [_P, C.POINTER(Tuning)]),
+    "frg_tune": (C.c_int, [_P, C.c_double, _P, _P, C.c_int, C.c_int32, C.POINTER(Tuning), _DP, _DP, C.c_int32,
+                           _IP, _P]),
+    "frg_batch_set_tuning": (C.c_int, [_P, C.POINTER(Tuning)]),
+    "frg_batch_tune": (C.c_int, [_P, _DP, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int, C.c_int32,
+                                 C.POINTER(Tuning), _DP, _DP, C.c_int32, _IP, _P]),
+    "frg_batch_profile_begin": (C.c_int, [_P]),
+    "frg_batch_profile_end": (C.c_int, [_P, _DP, _IP]),
     "frg_status_str": (C.c_char_p, [C.c_int]),
     "frg_last_error": (C.c_char_p, []),
 }
@@ -351,6 +364,24 @@ class Context:
         _check(lib().frg_kskip(self._h, C.byref(a), C.byref(f)))
         return bool(a.value), float(f.value)
 
+    def tuning(self):
+        t = Tuning()
+        _check(lib().frg_get_tuning(self._h, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+    def set_tuning(self, kparts=0, sweep_rows=0, block_rows=0):
+        _check(lib().frg_set_tuning(self._h, C.byref(Tuning(int(kparts), int(sweep_rows), int(block_rows)))))
+
+    def tune(self, T, V, prec=PREC_FP64, reps=5, log_cap=256):
+        """frg_tune: search and apply the launch parameters; returns (tuning, ms per
+        rhs, candidate log [rows, 6])."""
+        F = self.torch.empty_like(V)
+        t, ms, nrow = Tuning(), C.c_double(), C.c_int32()
+        log = np.zeros((log_cap, 6))
+        _check(lib().frg_tune(self._h, float(T), _ptr(V), _ptr(F), int(prec), int(reps), C.byref(t),
+                              C.byref(ms), log.ctypes.data_as(_DP), int(log_cap), C.byref(nrow), _stream()))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}, ms.value, log[:min(nrow.value, log_cap)]
+
     def profile_begin(self):
         _check(lib().frg_profile_begin(self._h))
 
@@ -435,6 +466,32 @@ class Batch:
 
     def flow_step(self):
         _check(lib().frg_batch_flow_step(self._h, _stream()))
+
+    def set_tuning(self, kparts=0, sweep_rows=0, block_rows=0):
+        """One tuning for every member (flow_init again afterwards)."""
+        _check(lib().frg_batch_set_tuning(self._h, C.byref(Tuning(int(kparts), int(sweep_rows), int(block_rows)))))
+
+    def tune(self, Ts, Vs, prec=PREC_FP64, reps=3, log_cap=256):
+        """frg_batch_tune on the batched rhs; returns (tuning, ms per batched rhs,
+        candidate log [rows, 6])."""
+        Fs = [self.torch.empty_like(V) for V in Vs]
+        T = np.ascontiguousarray(Ts, dtype=np.float64)
+        t, ms, nrow = Tuning(), C.c_double(), C.c_int32()
+        log = np.zeros((log_cap, 6))
+        _check(lib().frg_batch_tune(self._h, T.ctypes.data_as(_DP), self._ptrs(Vs), self._ptrs(Fs), int(prec),
+                                    int(reps), C.byref(t), C.byref(ms), log.ctypes.data_as(_DP), int(log_cap),
+                                    C.byref(nrow), _stream()))
+        return {k: getattr(t, k) for k, _ in Tuning._fields_}, ms.value, log[:min(nrow.value, log_cap)]
+
+    def profile_begin(self):
+        _check(lib().frg_batch_profile_begin(self._h))
+
+    def profile_end(self):
+        """Summed event time (ms) and launch count per kernel class since profile_begin."""
+        ms = np.zeros(len(KERNEL_CLASSES))
+        cnt = np.zeros(len(KERNEL_CLASSES), dtype=np.int32)
+        _check(lib().frg_batch_profile_end(self._h, ms.ctypes.data_as(_DP), cnt.ctypes.data_as(_IP)))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
     def results(self):
         res = (FlowResult * self.n)()
