@@ -175,6 +175,24 @@ frg_status frg_bubbles_reps(frg_ctx ctx, double T, frg_precision prec, void *d_b
 frg_status frg_rhs(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_precision prec,
                    void *stream);
 
+/* frg_rhs for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, result and settings (symmetry, zero-chunk skipping,
+ * symmetric-vertex mode) as frg_rhs, with the same kernels; the per-call
+ * workspace (point factors, bubble rows, operand layout, channel partials)
+ * lives in the library's static device scratch of FRG_NOALLOC_SCRATCH_BYTES
+ * bytes instead of the context.  The call allocates nothing and needs no
+ * earlier frg_rhs.  Every call on one device shares that device's scratch:
+ * calls that overlap on one device (other streams, other threads, other
+ * contexts) race and must be ordered by the caller.  Nothing in the scratch
+ * needs to start at zero (each piece is written in full before it is read).
+ * Returns ENOTSUP, before any launch, when the workspace of this context and
+ * precision exceeds the scratch (e.g. N = 96 fits in symmetric-vertex mode,
+ * not with every column computed in FP64); other errors as frg_rhs. */
+#define FRG_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+frg_status frg_rhs_noalloc(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_precision prec,
+                           void *stream);
+
 /* Initialise a device flow state (FRG_STATE_LEN doubles) for o: s = ln T0,
  * h = first step, counters zero.  d_V is the initial vertex (unchanged). */
 frg_status frg_flow_init(frg_ctx ctx, const frg_flow_opts *o, const double *d_V,

@@ -112,6 +112,8 @@ struct frg_ctx_s {
     uint64_t ws_gen = 0;
     int ks_override = 0;    // FRG_KSPLIT
     size_t ws_bytes = 0;
+    // the library's static scratch on this context's device (frg_rhs_noalloc)
+    void *d_scratch = nullptr;
     // event timing (frg_profile_begin/end)
     EvProf pf;
     // one captured step of a single flow, replayed while its key matches
@@ -665,7 +667,8 @@ void set_tiles(frg_ctx ctx, frg::FusedContractArgs &a) {
 // Per-call workspace of one rhs: the point factors and temperature, the bubble
 // rows, the operand layout and the channel partials ([3][KS][cs], then their
 // sums [3][cs], cs = elements computed per channel).  The context's own
-// buffers (ctx_ws, sized by ensure_rhs_ws / ensure_c).
+// buffers (ctx_ws, sized by ensure_rhs_ws / ensure_c), or pieces of the static
+// scratch (frg_rhs_noalloc).
 struct RhsWs {
     double *pa64 = nullptr, *T = nullptr;
     float *pa32 = nullptr;
@@ -916,6 +919,13 @@ static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out) {
 
     frg_ctx ctx = new frg_ctx_s();
     ctx->device = dev;
+    {   // the static scratch of this device, looked up once per device with it current
+        const hipError_t e = frg::scratch_address(&ctx->d_scratch);
+        if (e != hipSuccess) {
+            delete ctx;
+            return fail(FRG_EDEVICE, std::string("static scratch: ") + hipGetErrorString(e));
+        }
+    }
     if (n_batch > 1) {   // measured at N = 96: 8 parts for 16 flows, 4 for 64
         ctx->ks_target = (6912 + n_batch - 1) / n_batch;
         ctx->ks_lo = 4;
@@ -1122,6 +1132,65 @@ frg_status frg_rhs(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_pr
     TRY(ensure_rhs_ws(ctx, prec));
     return run_rhs(ctx, prec == FRG_PREC_SPLIT_BF16, T, nullptr, 0.0, d_V, d_F, 0,
                    static_cast<hipStream_t>(stream));
+}
+
+frg_status frg_rhs_noalloc(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_precision prec,
+                           void *stream) {
+    TRY(check_ctx(ctx));
+    TRY(check_prec(prec));
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(FRG_EINVAL, "T must be finite and > 0");
+    if (!d_V || !d_F) return fail(FRG_EINVAL, "null V or F");
+    if (!aligned8(d_V) || !aligned8(d_F)) return fail(FRG_EINVAL, "V and F must be 8-byte aligned");
+    const size_t bytes = sizeof(double) * static_cast<size_t>(ctx->n3);
+    if (overlap(d_V, bytes, d_F, bytes)) return fail(FRG_EINVAL, "V and F overlap");
+    if (!ctx->d_scratch) return fail(FRG_EDEVICE, "no static scratch on this device");
+    // the workspace of one rhs, carved from the scratch in 256-byte aligned pieces
+    const bool split = prec == FRG_PREC_SPLIT_BF16;
+    const auto &g = ctx->g;
+    const size_t NN = static_cast<size_t>(g.N) * g.N, n3 = static_cast<size_t>(ctx->n3);
+    const size_t np = static_cast<size_t>(g.np);
+    const size_t rows = ctx->sym_on ? static_cast<size_t>(ctx->n_rep_pp + ctx->n_rep_ph)
+                                    : static_cast<size_t>(ctx->Trows);
+    size_t off = 0;
+    auto take = [&off](size_t nbytes) {
+        const size_t o = off;
+        off += (nbytes + 255) & ~static_cast<size_t>(255);
+        return o;
+    };
+    const size_t o_T = take(4 * sizeof(double));
+    const size_t esz = split ? sizeof(float) : sizeof(double);
+    const size_t o_pa = take(3 * np * esz);
+    const size_t o_B = take(rows * NN * esz);
+    const size_t o_perm = split ? 0 : take(6 * n3 * sizeof(double));
+    const size_t o_ahl = split ? take(8 * n3 * sizeof(uint16_t)) : 0;
+    const size_t o_g32 = split ? take(3 * n3 * sizeof(float)) : 0;
+    const size_t o_C = take(c_elems_needed(ctx) * sizeof(double));
+    if (off > frg::kScratchBytes)
+        return fail(FRG_ENOTSUP, "frg_rhs_noalloc: this context and precision need " + std::to_string(off) +
+                                     " bytes of workspace; the static scratch holds " +
+                                     std::to_string(frg::kScratchBytes));
+    char *base = static_cast<char *>(ctx->d_scratch);
+    RhsWs w;
+    w.own = false;
+    w.T = reinterpret_cast<double *>(base + o_T);
+    if (split) {
+        w.pa32 = reinterpret_cast<float *>(base + o_pa);
+        w.B32 = reinterpret_cast<float *>(base + o_B);
+        w.ahl = reinterpret_cast<uint16_t *>(base + o_ahl);
+        w.g32 = reinterpret_cast<float *>(base + o_g32);
+    } else {
+        w.pa64 = reinterpret_cast<double *>(base + o_pa);
+        w.B64 = reinterpret_cast<double *>(base + o_B);
+        w.perm = reinterpret_cast<double *>(base + o_perm);
+    }
+    w.C = reinterpret_cast<double *>(base + o_C);
+    // event timing would create events: not in this call
+    const bool prof = ctx->pf.on;
+    ctx->pf.on = false;
+    const frg_status st = run_rhs(ctx, split, T, nullptr, 0.0, d_V, d_F, 0, static_cast<hipStream_t>(stream),
+                                  RHS_DT, false, nullptr, &w);
+    ctx->pf.on = prof;
+    return st;
 }
 
 frg_status frg_flow_init(frg_ctx ctx, const frg_flow_opts *o, const double *d_V, double *d_state,

@@ -249,5 +249,11 @@ void launch_step_ctl_b(const FlowArgs *fa, int nflows, int phase, double *log_ba
                        double vmax, int max_steps, hipStream_t s);
 void launch_accept_b(const FlowArgs *fa, const int2 *items, int nitems, hipStream_t s);
 
+// ----------------------------------------------------------------- static scratch
+// bytes of the library's static device scratch (frg_rhs_noalloc)
+constexpr size_t kScratchBytes = FRG_NOALLOC_SCRATCH_BYTES;
+// device address of the scratch on the current device (looked up once per
+// device; host code passes this, never the array's own name)
+hipError_t scratch_address(void **out);
 
 }  // namespace frg

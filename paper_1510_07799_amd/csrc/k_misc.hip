@@ -4,6 +4,9 @@
 #include <algorithm>
 #include <cmath>
 
+#include <mutex>
+#include <vector>
+
 #include "frg_internal.h"
 
 namespace frg {
@@ -1254,6 +1257,33 @@ void launch_accept_b(const FlowArgs *fa, const int2 *items, int nitems, hipStrea
 
 void launch_state_init(double *state, double s0, double h, double s_min, hipStream_t s) {
     hipLaunchKernelGGL(state_init_kernel, dim3(1), dim3(64), 0, s, state, s0, h, s_min);
+}
+
+// ----------------------------------------------------------------- static scratch
+// Workspace of frg_rhs_noalloc: a file-scope device array, so that callers that
+// cannot allocate (code under graph capture, tight serving loops) get an rhs
+// without hipMalloc.  Every device the library runs on holds its own copy from
+// the load of the code object until the process ends.  In host code the name
+// is only a stand-in: kernels receive the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void **out) {
+    static std::mutex mu;
+    static std::vector<void *> addr;   // per device
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(mu);
+    if (static_cast<int>(addr.size()) <= dev) addr.resize(static_cast<size_t>(dev) + 1, nullptr);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace frg

@@ -82,6 +82,7 @@ SIGNATURES = {
     "frg_bubble_reps": (C.c_int, [_P, _IP, _IP, _IP]),
     "frg_bubbles_reps": (C.c_int, [_P, C.c_double, C.c_int, _P, _P, _P]),
     "frg_rhs": (C.c_int, [_P, C.c_double, _P, _P, C.c_int, _P]),
+    "frg_rhs_noalloc": (C.c_int, [_P, C.c_double, _P, _P, C.c_int, _P]),
     "frg_flow_init": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, _P]),
     "frg_flow_step": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, _P]),
     "frg_flow": (C.c_int, [_P, C.POINTER(FlowOpts), _P, _P, C.c_int32, C.POINTER(FlowResult), _P]),
@@ -323,6 +324,15 @@ class Context:
         assert V.dtype == torch.float64 and V.is_cuda and V.is_contiguous() and V.numel() == N ** 3
         F = out if out is not None else torch.empty_like(V)
         _check(lib().frg_rhs(self._h, float(T), _ptr(V), _ptr(F), int(prec), _stream()))
+        return F
+
+    def rhs_noalloc(self, T: float, V, F, prec=PREC_FP64):
+        """frg_rhs_noalloc: F (caller's buffer) from the library's static scratch."""
+        torch = self.torch
+        N = self.N
+        assert V.dtype == torch.float64 and V.is_cuda and V.is_contiguous() and V.numel() == N ** 3
+        assert F.dtype == torch.float64 and F.is_cuda and F.is_contiguous() and F.numel() == N ** 3
+        _check(lib().frg_rhs_noalloc(self._h, float(T), _ptr(V), _ptr(F), int(prec), _stream()))
         return F
 
     def flow_init(self, opts: FlowOpts, V, state):
