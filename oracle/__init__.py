@@ -44,6 +44,10 @@ class _Params(C.Structure):
                 ("N", C.c_int32), ("n_rad", C.c_int32), ("n_ang", C.c_int32)]
 
 
+class _Egrid(C.Structure):
+    _fields_ = [("n_E", C.c_int32), ("max_level", C.c_int32), ("rtol", C.c_double)]
+
+
 class _OdeResult(C.Structure):
     _fields_ = [("reason", C.c_int32), ("s_end", C.c_double), ("s_c", C.c_double),
                 ("s_c_interp", C.c_double), ("accepted", C.c_int32), ("rejected", C.c_int32),
@@ -75,6 +79,8 @@ def lib():
             L = C.CDLL(_LIB)
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(_Params)]
+        L.orc_create_egrid.restype = C.c_void_p
+        L.orc_create_egrid.argtypes = [C.POINTER(_Params), C.POINTER(_Egrid)]
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_get_threads.restype = C.c_int
@@ -178,17 +184,27 @@ def dp54(f, y0, s0, s_min, h0, rtol, atol, vmax, max_steps=0, log_cap=4096):
 
 
 class Model:
-    """Geometry + rhs of one parameter set (t, t', mu, U, N, n_rad, n_ang)."""
+    """Geometry + rhs of one parameter set (t, t', mu, U, N, n_rad, n_ang).
 
-    def __init__(self, t=1.0, tp=0.0, mu=0.0, U=2.0, N=16, n_rad=8, n_ang=8):
+    egrid = dict(n_E=..., max_level=..., rtol=...) replaces the polar fine grid
+    by the energy-angle quadrature (Sec. 4); n_rad and n_ang are then ignored and
+    every patch holds nf points (the longest sector's count, the others padded
+    with zero weight)."""
+
+    def __init__(self, t=1.0, tp=0.0, mu=0.0, U=2.0, N=16, n_rad=8, n_ang=8, egrid=None):
         t, tp, mu, U = float(t), float(tp), float(mu), float(U)
         self.params = dict(t=t, tp=tp, mu=mu, U=U, N=N, n_rad=n_rad, n_ang=n_ang)
         p = _Params(t, tp, mu, U, N, n_rad, n_ang)
-        self._h = lib().orc_create(C.byref(p))
+        if egrid is None:
+            self._h = lib().orc_create(C.byref(p))
+        else:
+            e = _Egrid(int(egrid["n_E"]), int(egrid["max_level"]), float(egrid["rtol"]))
+            self.params["egrid"] = dict(n_E=e.n_E, max_level=e.max_level, rtol=e.rtol)
+            self._h = lib().orc_create_egrid(C.byref(p), C.byref(e))
         if not self._h:
             raise ValueError(f"oracle rejected parameters {self.params}")
         self.N = N
-        self.nf = n_rad * n_ang
+        self.nf = lib().orc_nf(self._h)
         self.U = U
         self.Tpp = lib().orc_num_pp(self._h)
         self.Tph = lib().orc_num_ph(self._h)

@@ -36,6 +36,8 @@ static const double TWO_PI_D = 2.0 * ORC_PI;  /* exactly twice PI_D */
 struct orc_model {
     orc_params p;
     int N, nf, Tpp, Tph;
+    int egrid;             /* 1: energy-angle fine grid (eg_* below), 0: polar grid */
+    double *eg_pts;        /* [patches built][nf][3] x, y, w of the energy-angle grid */
     double dth;            /* sector width 2 pi / N */
     double *kc;            /* [N][2] patch centres */
     double *bnd;           /* [N+1][2] sector boundary directions */
@@ -196,6 +198,15 @@ static void raw_centre(const orc_model *m, int j, double *x, double *y)
     *y = r * sn;
 }
 
+/* fine point (wedge or direct patch j, index s) of the energy-angle grid */
+static void egrid_point(const orc_model *m, int j, int s, double *x, double *y, double *wt)
+{
+    const double *q = m->eg_pts + 3 * ((size_t)j * m->nf + s);
+    *x = q[0];
+    *y = q[1];
+    *wt = q[2];
+}
+
 static int build_geometry(orc_model *m)
 {
     int N = m->N, nf = m->nf, na = m->p.n_ang, nr = m->p.n_rad;
@@ -226,7 +237,10 @@ static int build_geometry(orc_model *m)
                     int o, j, s;
                     wedge_src(N, na, J, sp, &o, &j, &s);
                     double x, y, wt;
-                    raw_point(m, j, s, mm, &x, &y, &wt);
+                    /* the energy-angle list keeps its order in every octant, so that
+                     * its zero-weight padding stays at the end of each patch */
+                    if (m->egrid) egrid_point(m, j, sp, &x, &y, &wt);
+                    else raw_point(m, j, s, mm, &x, &y, &wt);
                     int idx = J * nf + sp * nr + mm;
                     c4v(o, x, y, &m->px[idx], &m->py[idx]);
                     m->w[idx] = wt;
@@ -238,15 +252,19 @@ static int build_geometry(orc_model *m)
             for (int s = 0; s < na; s++)
                 for (int mm = 0; mm < nr; mm++) {
                     int idx = J * nf + s * nr + mm;
-                    raw_point(m, J, s, mm, &m->px[idx], &m->py[idx], &m->w[idx]);
+                    if (m->egrid) egrid_point(m, J, s, &m->px[idx], &m->py[idx], &m->w[idx]);
+                    else raw_point(m, J, s, mm, &m->px[idx], &m->py[idx], &m->w[idx]);
                 }
     }
     m->bnd[2 * N] = m->bnd[0];
     m->bnd[2 * N + 1] = m->bnd[1];
-    /* normalise the weights: sum over the whole grid in index order */
-    double S = 0.0;
-    for (int i = 0; i < N * nf; i++) S += m->w[i];
-    for (int i = 0; i < N * nf; i++) m->w[i] = m->w[i] / S;
+    /* normalise the polar weights: sum over the whole grid in index order (the
+     * energy-angle weights are used as the quadrature gives them) */
+    if (!m->egrid) {
+        double S = 0.0;
+        for (int i = 0; i < N * nf; i++) S += m->w[i];
+        for (int i = 0; i < N * nf; i++) m->w[i] = m->w[i] / S;
+    }
     for (int i = 0; i < N * nf; i++) m->xi[i] = eps_k(&m->p, m->px[i], m->py[i]);
     /* transfers */
     int t = 0;
@@ -305,8 +323,247 @@ void orc_destroy(orc_model *m)
 {
     if (!m) return;
     free(m->kc); free(m->bnd); free(m->px); free(m->py); free(m->w); free(m->xi);
-    free(m->qpp); free(m->qph); free(m->rpp); free(m->rph);
+    free(m->qpp); free(m->qph); free(m->rpp); free(m->rph); free(m->eg_pts);
     free(m);
+}
+
+/* ------------------------------------------------------------------ energy-angle grid */
+/* The paper's quadrature (Sec. 4): the Brillouin-zone integral split into an
+ * outer integral over energy, on a fixed grid of equidistant midpoints across
+ * the band, and an inner integral along the line of that energy by a locally
+ * adaptive midpoint rule (readings in the design notes).  The inner coordinate
+ * is the angle theta of the ray from Gamma: eps increases monotonically along
+ * every ray (|t'| < t/2), so energy E is met at one radius r(E, theta) or not
+ * at all inside the zone, and d^2k = r dr dtheta = r / (d eps/dr) dE dtheta. */
+
+/* density r / (d eps / dr) at the point of energy E on the ray (c, s), or 0 when
+ * the ray does not reach E inside the zone; the point in *x, *y */
+static double energy_density(const orc_params *p, double c, double s, double E, double *x, double *y)
+{
+    double R = ray_extent(c, s);
+    *x = 0.0;
+    *y = 0.0;
+    if (!(eps_k(p, R * c, R * s) >= E)) return 0.0;
+    double lo = 0.0, hi = R;
+    for (int it = 0; it < 100; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (eps_k(p, mid * c, mid * s) < E) lo = mid;
+        else hi = mid;
+    }
+    double r = 0.5 * (lo + hi);
+    double kx = r * c, ky = r * s;
+    double sx = sin(kx), sy = sin(ky), cx = cos(kx), cy = cos(ky);
+    double dx = (2.0 * p->t) * sx + (4.0 * p->tp) * (sx * cy);
+    double dy = (2.0 * p->t) * sy + (4.0 * p->tp) * (cx * sy);
+    double dedr = c * dx + s * dy;
+    *x = kx;
+    *y = ky;
+    if (!(dedr > 0.0)) return 0.0;
+    return r / dedr;
+}
+
+typedef struct {
+    double *pts;          /* growing list of x, y, w */
+    int n, cap;
+} egrid_list;
+
+static void eg_push(egrid_list *L, double x, double y, double w)
+{
+    if (L->n == L->cap) {
+        L->cap = L->cap ? 2 * L->cap : 256;
+        L->pts = realloc(L->pts, sizeof(double) * 3 * L->cap);
+    }
+    L->pts[3 * L->n] = x;
+    L->pts[3 * L->n + 1] = y;
+    L->pts[3 * L->n + 2] = w;
+    L->n++;
+}
+
+/* One cell [a, a + h) of the trisection midpoint rule on the shell of energy E
+ * (weight factor dE / (2 pi)^2 in wf) whose midpoint density fmid is known.  The
+ * three thirds' midpoints give I3; the cell's own midpoint gives I1 (it is the
+ * middle third's midpoint, so refining reuses it).  A cell is refined while
+ * |I3 - I1| exceeds its share of the shell's target, tol_rate * h (tol_rate =
+ * rtol I_shell / 2 pi), and its thirds are above the deepest level; otherwise its
+ * three thirds are the quadrature points (zero-density points dropped). */
+static void eg_cell(const orc_params *p, double E, double wf, double a, double h, double fmid, double xm, double ym,
+                    int level, int max_level, double tol_rate, egrid_list *L)
+{
+    double tol = tol_rate * h;
+    double h3 = h / 3.0;
+    double t1 = a + 0.5 * h3, t3 = a + 2.0 * h3 + 0.5 * h3;
+    double x1, y1, x3, y3;
+    double f1 = energy_density(p, cos(t1), sin(t1), E, &x1, &y1);
+    double f3 = energy_density(p, cos(t3), sin(t3), E, &x3, &y3);
+    double I1 = h * fmid;
+    double I3 = h3 * (f1 + fmid + f3);
+    if (level + 1 < max_level && fabs(I3 - I1) > tol) {
+        eg_cell(p, E, wf, a, h3, f1, x1, y1, level + 1, max_level, tol_rate, L);
+        eg_cell(p, E, wf, a + h3, h3, fmid, xm, ym, level + 1, max_level, tol_rate, L);
+        eg_cell(p, E, wf, a + 2.0 * h3, h3, f3, x3, y3, level + 1, max_level, tol_rate, L);
+        return;
+    }
+    if (f1 > 0.0) eg_push(L, x1, y1, wf * h3 * f1);
+    if (fmid > 0.0) eg_push(L, xm, ym, wf * h3 * fmid);
+    if (f3 > 0.0) eg_push(L, x3, y3, wf * h3 * f3);
+}
+
+/* Energy at the zone-boundary end of the ray at angle th: within each octant
+ * (between consecutive multiples of pi/4) it is monotone in th, since on the
+ * boundary edge it reads 2t + (4t' - 2t) cos(y) - mu with |y| rising to pi
+ * towards the corner (|t'| < t/2). */
+static double end_energy(const orc_params *p, double th)
+{
+    double c = cos(th), s = sin(th);
+    double R = ray_extent(c, s);
+    return eps_k(p, R * c, R * s);
+}
+
+/* The angles of [a0, a1) (inside one octant) whose ray reaches energy E: an
+ * interval [*c0, *c1), empty when *c1 <= *c0.  The end energy is monotone, so
+ * the covered part starts or ends at its one crossing of E (bisected). */
+static void covered_piece(const orc_params *p, double E, double a0, double a1, double *c0, double *c1)
+{
+    double e0 = end_energy(p, a0), e1 = end_energy(p, a1);
+    *c0 = a0;
+    *c1 = a1;
+    if (e0 >= E && e1 >= E) return;
+    if (e0 < E && e1 < E) { *c1 = a0; return; }
+    double lo = a0, hi = a1;
+    int rising = (e1 >= E);
+    for (int it = 0; it < 100; it++) {
+        double mid = 0.5 * (lo + hi);
+        if ((end_energy(p, mid) >= E) == rising) hi = mid;
+        else lo = mid;
+    }
+    double x = 0.5 * (lo + hi);
+    if (rising) *c0 = x;
+    else *c1 = x;
+}
+
+/* The octant pieces of sector j: its angle range cut at multiples of pi/4;
+ * returns their count (at most 3), bounds in cut[]. */
+static int sector_pieces(const orc_model *m, int j, double *cut)
+{
+    double a = (double)j * m->dth, b = (double)(j + 1) * m->dth;
+    int n = 0;
+    cut[n++] = a;
+    int k0 = (int)floor(a / (0.25 * PI_D)) + 1;
+    for (int k = k0; (double)k * (0.25 * PI_D) < b; k++) cut[n++] = (double)k * (0.25 * PI_D);
+    cut[n] = b;
+    return n;
+}
+
+/* Points of sector j for every energy shell, shells in increasing energy, each
+ * shell's points in increasing angle.  Only the covered part of each octant
+ * piece is integrated (outside it the ray stays below E: no contour there), so
+ * narrow contour arcs near the band top are never missed by the coarse samples.
+ * I_shell[i]: a three-point-per-piece estimate of shell i's inner integral over
+ * the whole circle, the scale of the relative target rtol. */
+static void eg_sector(const orc_model *m, const orc_egrid *e, const double *I_shell, double Emin, double dE, int j,
+                      egrid_list *L)
+{
+    double wf = dE / (4.0 * PI_D * PI_D);
+    double cut[5];
+    int np = sector_pieces(m, j, cut);
+    for (int i = 0; i < e->n_E; i++) {
+        double E = Emin + ((double)i + 0.5) * dE;
+        for (int q = 0; q < np; q++) {
+            double c0, c1;
+            covered_piece(&m->p, E, cut[q], cut[q + 1], &c0, &c1);
+            if (!(c1 > c0)) continue;
+            double h = c1 - c0, tm = c0 + 0.5 * h, xm, ym;
+            double fm = energy_density(&m->p, cos(tm), sin(tm), E, &xm, &ym);
+            eg_cell(&m->p, E, wf, c0, h, fm, xm, ym, 0, e->max_level, e->rtol * I_shell[i] / TWO_PI_D, L);
+        }
+    }
+}
+
+/* three-point midpoint estimate of shell E's inner integral over sector j's covered pieces */
+static double eg_coarse(const orc_model *m, double E, int j)
+{
+    double cut[5], acc = 0.0;
+    int np = sector_pieces(m, j, cut);
+    for (int q = 0; q < np; q++) {
+        double c0, c1;
+        covered_piece(&m->p, E, cut[q], cut[q + 1], &c0, &c1);
+        if (!(c1 > c0)) continue;
+        double h3 = (c1 - c0) / 3.0;
+        for (int k = 0; k < 3; k++) {
+            double t = c0 + ((double)k + 0.5) * h3, x, y;
+            acc += h3 * energy_density(&m->p, cos(t), sin(t), E, &x, &y);
+        }
+    }
+    return acc;
+}
+
+orc_model *orc_create_egrid(const orc_params *p, const orc_egrid *e)
+{
+    if (!p || !e) return NULL;
+    if (p->N < 4 || p->N > 256 || p->N % 4 != 0) return NULL;
+    if (e->n_E < 1 || e->max_level < 1 || e->max_level > 12 || !(e->rtol > 0.0)) return NULL;
+    if (!isfinite(p->t) || !isfinite(p->tp) || !isfinite(p->mu) || !isfinite(p->U)) return NULL;
+    if (!(fabs(p->tp) < 0.5 * fabs(p->t))) return NULL;   /* eps monotone along the rays */
+    orc_model *m = calloc(1, sizeof(orc_model));
+    m->p = *p;
+    m->N = p->N;
+    m->egrid = 1;
+    m->dth = TWO_PI_D / (double)p->N;
+    /* band edges: the minimum of eps at Gamma, the maximum at (pi, pi) */
+    double Emin = eps_k(p, 0.0, 0.0), Emax = eps_k(p, PI_D, PI_D);
+    double dE = (Emax - Emin) / (double)e->n_E;
+    int sym = (m->N % 8 == 0);
+    int nb = sym ? m->N / 8 : m->N;   /* sectors built: the first octant's, else all */
+    /* the scale of each shell: three midpoints per sector of the sectors built */
+    double *I_shell = calloc(e->n_E, sizeof(double));
+    for (int i = 0; i < e->n_E; i++) {
+        double E = Emin + ((double)i + 0.5) * dE, acc = 0.0;
+        for (int j = 0; j < nb; j++) acc += eg_coarse(m, E, j);
+        I_shell[i] = acc * (double)(m->N / nb);
+    }
+    egrid_list *lists = calloc(nb, sizeof(egrid_list));
+    int nf = 1;
+    for (int j = 0; j < nb; j++) {
+        eg_sector(m, e, I_shell, Emin, dE, j, &lists[j]);
+        if (lists[j].n > nf) nf = lists[j].n;
+    }
+    free(I_shell);
+    /* every sector padded to nf points with zero weight at its first point */
+    m->nf = nf;
+    m->eg_pts = calloc((size_t)nb * nf * 3, sizeof(double));
+    for (int j = 0; j < nb; j++) {
+        for (int k = 0; k < nf; k++) {
+            double *q = m->eg_pts + 3 * ((size_t)j * nf + k);
+            if (k < lists[j].n) {
+                q[0] = lists[j].pts[3 * k];
+                q[1] = lists[j].pts[3 * k + 1];
+                q[2] = lists[j].pts[3 * k + 2];
+            } else {
+                q[0] = lists[j].n ? lists[j].pts[0] : 0.0;
+                q[1] = lists[j].n ? lists[j].pts[1] : 0.0;
+                q[2] = 0.0;
+            }
+        }
+        free(lists[j].pts);
+    }
+    free(lists);
+    m->p.n_rad = 1;
+    m->p.n_ang = nf;
+    m->Tpp = m->N * (m->N + 1) / 2;
+    m->Tph = m->N * (m->N - 1) + 1;
+    size_t np = (size_t)m->N * m->nf;
+    m->kc = calloc(2 * m->N, sizeof(double));
+    m->bnd = calloc(2 * (m->N + 1), sizeof(double));
+    m->px = calloc(np, sizeof(double));
+    m->py = calloc(np, sizeof(double));
+    m->w = calloc(np, sizeof(double));
+    m->xi = calloc(np, sizeof(double));
+    m->qpp = calloc(2 * m->Tpp, sizeof(double));
+    m->qph = calloc(2 * m->Tph, sizeof(double));
+    m->rpp = calloc((size_t)m->N * m->N, sizeof(int32_t));
+    m->rph = calloc((size_t)m->N * m->N, sizeof(int32_t));
+    build_geometry(m);
+    return m;
 }
 
 int32_t orc_N(const orc_model *m) { return m->N; }

@@ -42,6 +42,20 @@ typedef struct {
 /* Build the geometry (patch centres, sector boundaries, fine grid, transfer
  * momenta).  Returns NULL on invalid parameters. */
 orc_model *orc_create(const orc_params *p);
+
+/* The same with the paper's quadrature as the fine grid (Sec. 4): n_E
+ * equidistant energy midpoints across the band, and along each energy, per
+ * patch sector, a locally adaptive trisection midpoint rule in the angle of the
+ * ray from Gamma (relative target rtol of the shell's inner integral, at most
+ * 3^max_level points per sector and shell).  The weights are those of the
+ * quadrature (not normalised).  Every patch holds nf points (orc_nf), padded
+ * with zero-weight points; p->n_rad, p->n_ang are ignored (the model reports
+ * 1 and nf).  NULL on invalid parameters or |t'| >= t/2. */
+typedef struct {
+    int32_t n_E, max_level;
+    double rtol;
+} orc_egrid;
+orc_model *orc_create_egrid(const orc_params *p, const orc_egrid *e);
 void orc_destroy(orc_model *m);
 void orc_set_threads(int n);          /* OpenMP threads used by the heavy loops */
 int orc_get_threads(void);

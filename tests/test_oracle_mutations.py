@@ -19,6 +19,8 @@ HDR = os.path.join(ROOT, "oracle", "frg_oracle.h")
 SU2 = ["tests/test_oracle_symmetries.py::test_su2_spinful_equation_exact_momentum_closure",
        "tests/test_oracle_symmetries.py::test_su2_spinful_equation_general_geometry"]
 WEIGHTS = ["tests/test_oracle_symmetries.py::test_weights_integrate_closed_forms"]
+EGRID = ["tests/test_oracle_egrid.py::test_points_lie_on_their_shells",
+         "tests/test_oracle_egrid.py::test_dos_nearest_neighbour_band_is_the_elliptic_integral"]
 
 # (name, original text, planted text, pins that must fail)
 CASES = [
@@ -28,6 +30,12 @@ CASES = [
      "-2.0 * VI(j1, b, j3) * VI(a, j2, b)", "-2.0 * VI(j1, a, j3) * VI(b, j2, a)", SU2),
     ("fine-grid weight without the radial Jacobian r",
      "*wt = r * (R / (double)m->p.n_rad)", "*wt = (R / (double)m->p.n_rad)", WEIGHTS),
+    ("energy-angle density without the radius r of r dr dtheta",
+     "return r / dedr;", "return 1.0 / dedr;", EGRID),
+    ("energy shells at their lower edges instead of their midpoints",
+     "double E = Emin + ((double)i + 0.5) * dE", "double E = Emin + (double)i * dE", EGRID),
+    ("every angle of a sector integrated, also where the ray stays below the shell energy",
+     "    *c1 = a1;\n    if (e0 >= E && e1 >= E) return;", "    *c1 = a1;\n    return;", EGRID),
 ]
 
 
@@ -55,11 +63,12 @@ def _run_pins(pins, lib=None):
 
 
 def test_pins_pass_on_the_oracle():
-    r = _run_pins(SU2 + WEIGHTS)
+    r = _run_pins(SU2 + WEIGHTS + EGRID)
     assert r.returncode == 0, r.stdout[-2000:]
 
 
-@pytest.mark.parametrize("name,old,new,pins", CASES, ids=["crossed-swap", "direct-swap", "no-jacobian"])
+@pytest.mark.parametrize("name,old,new,pins", CASES, ids=["crossed-swap", "direct-swap", "no-jacobian", "egrid-no-r", "egrid-edge-energies",
+                              "egrid-uncovered-angles"])
 def test_planted_mistake_fails_its_pin(tmp_path, name, old, new, pins):
     lib = _build(tmp_path, old, new)
     r = _run_pins(pins, lib)
