@@ -30,10 +30,11 @@ STOP_NONE, STOP_TMIN, STOP_DIVERGED, STOP_MAXSTEPS, STOP_NONFINITE, STOP_HMIN = 
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no fast-math, no FP contraction)."""
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FP contraction, sin and cos
+    as separate libm calls)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC",
-               "-shared", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fno-builtin-sin",
+               "-fno-builtin-cos", "-fPIC", "-shared", "-Wall", "-o", _LIB + ".tmp", _SRC, "-lm"]
         subprocess.run(cmd, check=True, cwd=_HERE)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB

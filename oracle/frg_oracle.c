@@ -17,8 +17,11 @@
  *   G5 loop lines, G6 projection, G7 vertex, G8 rhs, G9 flow variable,
  *   G10 DP5(4) control -- spelled out next to each function.
  *
- * Build: gcc -O2 -fopenmp -ffp-contract=off -fPIC -shared (no fast-math), so
- * every floating-point operation is the one written.
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -fno-builtin-sin -fno-builtin-cos
+ * -fPIC -shared (no fast-math), so every floating-point operation is the one
+ * written and every sin and cos is its own libm call (gcc would otherwise merge
+ * a sin and a cos of one argument into one sincos call, whose last bit can
+ * differ from theirs).
  */
 #include "frg_oracle.h"
 

@@ -48,7 +48,8 @@ def _build(tmp_path, old, new):
     (d / "frg_oracle.c").write_text(src.replace(old, new))
     (d / "frg_oracle.h").write_text(open(HDR).read())
     lib = d / "libmutant.so"
-    subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", "-o", str(lib),
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-builtin-sin", "-fno-builtin-cos",
+                    "-fPIC", "-shared", "-o", str(lib),
                     str(d / "frg_oracle.c"), "-lm"], check=True)
     return str(lib)
 
