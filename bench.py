@@ -176,11 +176,12 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the CPU-baseline leg (default: every host core)")
     ap.add_argument("--cpu-only", action="store_true", help="run only the CPU-baseline leg")
-    ap.add_argument("--legs", default="split,fp64,batch,batch_fp64,batch64,split_full,fp64_full,iflow",
+    ap.add_argument("--legs", default="split,fp64,batch,batch_fp64,batch64,split_full,fp64_full,iflow,egrid",
                     help="comma list of split, fp64 (one flow), batch, batch_fp64 (16 flows, split / FP64), "
                          "batch64 (64 flows, split), all in symmetric-vertex mode; split_full, fp64_full "
                          "(one flow, every column computed); iflow (the interaction flow of the paper's "
-                         "working example, N=32)")
+                         "working example, N=32); egrid (one flow at N=96 on the paper's quadrature: "
+                         "1600 energies, adaptive inner rule)")
     ap.add_argument("--batch-flows", type=int, default=16,
                     help="flows in the batched legs (N=96, 512 points/patch, drawn parameters)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
@@ -337,9 +338,40 @@ def main():
                                                if c}}
         ci.close()
 
+    egrid = None
+    if "egrid" in legs:
+        # the paper's quadrature on the N = 96 model (split and FP64 single flows,
+        # symmetric-vertex mode); the sweep walks each patch's live points
+        pe = I.model_params("E1")
+        Ne = pe["N"]
+        t_c = time.perf_counter()
+        ce = frg.Context(**pe)
+        t_c = time.perf_counter() - t_c
+        ce.set_vsym(True)
+        live = int(ce.counts().sum())
+        rows_e = ce.symmetry()[1]
+        terms_e, energies_e = rows_e * live, rows_e // 2 * live
+        Ve = torch.full((Ne, Ne, Ne), float(pe["U"]), dtype=torch.float64, device="cuda")
+        egrid = {"workload": "N=96, t'=-0.3 mu=-1.2 U=3; paper's quadrature: 1600 midpoint energies across the "
+                             "band, inner adaptive trisection midpoint rule in the ray angle per patch sector "
+                             "(rtol 1e-4, at most 27 points per sector and shell); DP5(4) steps from V=U at T=1, "
+                             "symmetric-vertex mode",
+                 "points_per_patch_stride": ce.nf, "live_points": live, "context_create_s": round(t_c, 2)}
+        for prec, nm in ((frg.PREC_SPLIT_BF16, "split"), (frg.PREC_FP64, "fp64")):
+            dt, prof, st = timed_flow_steps(frg, torch, ce, prec, Ve, args.steps, args.warmup)
+            ms, cnt = prof["bubbles"]
+            egrid[nm] = {"rhs_per_s": round(RHS_PER_STEP * args.steps / dt, 3),
+                         "kernel_ms_per_rhs": {k: round(v / (PROFILE_STEPS * RHS_PER_STEP), 4)
+                                               for k, (v, c) in prof.items()},
+                         "bubble_roofline": bubble_roofline(ms / max(cnt, 1) * 1e-3, terms_e, energies_e,
+                                                            "egrid_" + nm, "bubble_seg_kernel")}
+        ce.close()
+        del Ve
+        torch.cuda.empty_cache()
+
     head = batches.get("batch")
     if head is None and not results:
-        print(json.dumps({"iflow_p1": iflow}))
+        print(json.dumps({"iflow_p1": iflow, "egrid": egrid}))
         return
     rate = {leg: RHS_PER_STEP * args.steps / r["seconds"] for leg, r in results.items()}
     rate.update({leg: bb["rhs"] / bb["seconds"] for leg, bb in batches.items()})
@@ -412,6 +444,9 @@ def main():
         out["iflow_p1"] = dict(iflow, workload="interaction flow at T=0.1, N=32, 16x16 points/patch, "
                                                "t'=-0.01 mu=-0.02, bare U(g=1)=2, DP5(4) steps from V=U, "
                                                "symmetric-vertex mode; bubbles once per flow")
+
+    if egrid is not None:
+        out["egrid_e1"] = egrid
 
     # roofline of the dominant kernel of the value leg (the batched sweep), from the
     # event-timed steps: one launch covers every active flow

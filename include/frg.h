@@ -142,6 +142,38 @@ frg_status frg_tables(frg_ctx ctx, double *kc, double *bnd, double *fine, double
 frg_status frg_host_tables(const frg_params *p, double *kc, double *bnd, double *fine,
                            double *qpp, double *qph, int32_t *idx4);
 
+/* The paper's quadrature as the fine grid (Sec. 4: an outer fixed midpoint
+ * grid in energy, an inner locally adaptive midpoint rule along each energy).
+ * n_E shells at the midpoints of [eps(0,0), eps(pi,pi)] (the band for
+ * |t'| < t/2); along each shell, per patch sector and octant piece of it, the
+ * angles whose ray from Gamma reaches the shell energy are integrated by a
+ * trisection midpoint rule in the ray angle, a cell cut in thirds while its
+ * one- and three-point values differ by more than rtol * I_E * h / 2pi (I_E a
+ * coarse estimate of the shell's whole inner integral, h the cell width), to
+ * at most 3^max_level points per piece and shell.  Point weights are
+ * dE h r / (d eps / dr) / (2pi)^2, not normalised.  p->n_rad and p->n_ang are
+ * ignored.  Every patch holds n_f points (frg_points): its live points first,
+ * then zero-weight padding; n_f is a multiple of 512.  Needs |t'| < t/2,
+ * n_E >= 1, 1 <= max_level <= 12, rtol > 0 (EINVAL); ENOTSUP when a patch
+ * would hold more than 131072 points; otherwise as frg_create.  Single flows
+ * only (batches take polar grids). */
+typedef struct {
+    int32_t n_E, max_level;
+    double rtol;
+} frg_egrid;
+frg_status frg_create_egrid(const frg_params *p, const frg_egrid *e, frg_ctx *out);
+
+/* Points per patch: n_f, the table stride of a patch, and counts[N], each
+ * patch's live points (n_f for every patch of a polar grid).  Either may be NULL. */
+frg_status frg_points(frg_ctx ctx, int32_t *n_f, int32_t *counts);
+
+/* Host-only frg_host_tables for the energy-angle grid: n_f and counts as
+ * frg_points; call with fine = NULL first to learn n_f (fine holds N * n_f
+ * rows). */
+frg_status frg_host_tables_egrid(const frg_params *p, const frg_egrid *e, int32_t *n_f, int32_t *counts,
+                                 double *kc, double *bnd, double *fine, double *qpp, double *qph,
+                                 int32_t *idx4);
+
 /* Copy the device table of second-line patches (kind 0 = ph, 1 = pp) into
  * d_out[rows][N*n_f] (uint8), points in the fine-grid order of frg_tables
  * (the device keeps each patch's points in its own order). */

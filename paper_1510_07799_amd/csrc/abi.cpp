@@ -60,6 +60,7 @@ struct frg_ctx_s {
     double *d_bnd = nullptr, *d_xi = nullptr, *d_w = nullptr, *d_trig_row = nullptr,
            *d_trig_pt = nullptr;
     uint8_t *d_bins = nullptr;
+    int32_t *d_count = nullptr;   // energy-angle grid: live points per patch
     int32_t *d_colrow_pp = nullptr, *d_colrow_ph = nullptr;   // (row << 3): every row stored
     // C4v orbit reduction of the bubble rows
     bool sym_avail = false, sym_on = false;
@@ -281,6 +282,7 @@ frg::BubbleArgs bubble_args(frg_ctx ctx, bool fp32, void *bpp, void *bph, const 
     a.rowlist = nullptr;
     a.rowlist_ph = nullptr;
     a.rpb = ctx->rpb;
+    a.count = ctx->d_count;
     return a;
 }
 
@@ -365,7 +367,9 @@ frg_status build_orbits(frg_ctx ctx) {
     TRY(upload(ctx, &d_orbit, orbit.data(), orbit.size()));
     TRY(dalloc(ctx, &d_bad, 1));
     HIPCHK(hipMemset(d_bad, 0, sizeof(int)));
-    frg::launch_sym_check(ctx->d_bins, d_orbit, N, g.n_rad, g.n_ang, ctx->Trows, d_bad, nullptr);
+    // a reflected polar patch lists its sub-rays in reverse; the energy-angle
+    // lists keep their order
+    frg::launch_sym_check(ctx->d_bins, d_orbit, N, g.n_rad, g.n_ang, ctx->Trows, !g.egrid, d_bad, nullptr);
     int bad = -1;
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpy(&bad, d_bad, sizeof(int), hipMemcpyDeviceToHost);
@@ -898,16 +902,50 @@ const char *frg_status_str(frg_status st) {
 
 const char *frg_last_error(void) { return g_err.c_str(); }
 
-static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out);
+static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out, const frg_egrid *eg = nullptr);
 
 frg_status frg_create(const frg_params *p, frg_ctx *out) { return create_impl(p, 1, out); }
 
-// n_batch: flows of the batch this context belongs to (1 alone): a batch
-// needs fewer K parts per flow to fill the chip; FRG_KSPLIT overrides
-static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out) {
+// largest padded n_f of the energy-angle grid
+constexpr int kMaxEgridPoints = 1 << 17;
+
+static frg_status check_egrid(const frg_params *p, const frg_egrid *e) {
+    if (!p || !e) return fail(FRG_EINVAL, "null parameters");
+    if (p->N < 4 || p->N > 256 || p->N % 4 != 0)
+        return fail(FRG_EINVAL, "N must satisfy 4 <= N <= 256 and N % 4 == 0");
+    if (!std::isfinite(p->t) || !std::isfinite(p->tp) || !std::isfinite(p->mu) || !std::isfinite(p->U) ||
+        p->t == 0.0)
+        return fail(FRG_EINVAL, "model parameters must be finite and t != 0");
+    if (!(std::fabs(p->tp) < 0.5 * std::fabs(p->t)))
+        return fail(FRG_EINVAL, "the energy-angle grid needs |t'| < t/2 (eps monotone along rays from Gamma)");
+    if (e->n_E < 1 || e->max_level < 1 || e->max_level > 12 || !(e->rtol > 0.0) || !std::isfinite(e->rtol))
+        return fail(FRG_EINVAL, "egrid needs n_E >= 1, 1 <= max_level <= 12 and rtol > 0");
+    return FRG_OK;
+}
+
+frg_status frg_create_egrid(const frg_params *p, const frg_egrid *e, frg_ctx *out) {
     if (!out) return fail(FRG_EINVAL, "null output handle");
     *out = nullptr;
-    TRY(check_params(p));
+    TRY(check_egrid(p, e));
+    return create_impl(p, 1, out, e);
+}
+
+frg_status frg_points(frg_ctx ctx, int32_t *n_f, int32_t *counts) {
+    TRY(check_ctx(ctx));
+    const auto &g = ctx->g;
+    if (n_f) *n_f = g.nf;
+    if (counts)
+        for (int a = 0; a < g.N; ++a) counts[a] = g.egrid ? g.count[a] : g.nf;
+    return FRG_OK;
+}
+
+// n_batch: flows of the batch this context belongs to (1 alone): a batch
+// needs fewer K parts per flow to fill the chip; FRG_KSPLIT overrides
+static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out, const frg_egrid *eg) {
+    if (!out) return fail(FRG_EINVAL, "null output handle");
+    *out = nullptr;
+    if (eg) TRY(check_egrid(p, eg));
+    else TRY(check_params(p));
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(FRG_EDEVICE, "no HIP device");
     int dev = 0;
@@ -931,7 +969,13 @@ static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out) {
         ctx->ks_lo = 4;
     }
     if (const char *e = std::getenv("FRG_KSPLIT")) ctx->ks_override = std::atoi(e);
-    frg::build_geometry(*p, ctx->g);
+    if (!eg) {
+        frg::build_geometry(*p, ctx->g);
+    } else if (!frg::build_geometry_egrid(*p, *eg, kMaxEgridPoints, ctx->g)) {
+        delete ctx;
+        return fail(FRG_ENOTSUP, "energy-angle grid: more than " + std::to_string(kMaxEgridPoints) +
+                                     " points in a patch");
+    }
     const auto &g = ctx->g;
     ctx->Trows = g.Tpp + g.Tph;
     ctx->n3 = static_cast<int64_t>(g.N) * g.N * g.N;
@@ -969,7 +1013,8 @@ static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out) {
         (st = upload(ctx, &ctx->d_trig_pt, trig_pt.data(), trig_pt.size())) ||
         (st = upload(ctx, &ctx->d_colrow_pp, cpp.data(), cpp.size())) ||
         (st = upload(ctx, &ctx->d_colrow_ph, cph.data(), cph.size())) ||
-        (st = dalloc(ctx, &ctx->d_bins, static_cast<size_t>(ctx->Trows) * g.np)))
+        (st = dalloc(ctx, &ctx->d_bins, static_cast<size_t>(ctx->Trows) * g.np)) ||
+        (g.egrid && (st = upload(ctx, &ctx->d_count, g.count.data(), g.count.size()))))
         return bail(st);
     size_t tmp_bytes = 0;
     if ((st = upload(ctx, &d_px, g.px.data(), g.px.size())) ||
@@ -999,7 +1044,7 @@ static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out) {
 
 frg_status frg_destroy(frg_ctx ctx) {
     if (!ctx) return FRG_OK;
-    void *ptrs[] = {ctx->d_bnd, ctx->d_xi, ctx->d_w, ctx->d_trig_row, ctx->d_trig_pt, ctx->d_bins,
+    void *ptrs[] = {ctx->d_bnd, ctx->d_xi, ctx->d_w, ctx->d_trig_row, ctx->d_trig_pt, ctx->d_bins, ctx->d_count,
                     ctx->d_colrow_pp, ctx->d_colrow_ph, ctx->d_pa64, ctx->d_T, ctx->d_pa32,
                     ctx->d_B64, ctx->d_B32, ctx->d_perm, ctx->d_ahl, ctx->d_g32, ctx->d_C,
                     ctx->d_yt, ctx->d_y5, ctx->d_partial, ctx->d_state, ctx->d_rowlist, ctx->d_rowlist_ph,
@@ -1069,6 +1114,17 @@ frg_status frg_host_tables(const frg_params *p, double *kc, double *bnd, double 
     TRY(check_params(p));
     frg_ctx_s tmp;
     frg::build_geometry(*p, tmp.g);
+    return frg_tables(&tmp, kc, bnd, fine, qpp, qph, idx4);
+}
+
+frg_status frg_host_tables_egrid(const frg_params *p, const frg_egrid *e, int32_t *n_f, int32_t *counts,
+                                 double *kc, double *bnd, double *fine, double *qpp, double *qph, int32_t *idx4) {
+    TRY(check_egrid(p, e));
+    frg_ctx_s tmp;
+    if (!frg::build_geometry_egrid(*p, *e, kMaxEgridPoints, tmp.g))
+        return fail(FRG_ENOTSUP, "energy-angle grid: more than " + std::to_string(kMaxEgridPoints) +
+                                     " points in a patch");
+    TRY(frg_points(&tmp, n_f, counts));
     return frg_tables(&tmp, kc, bnd, fine, qpp, qph, idx4);
 }
 

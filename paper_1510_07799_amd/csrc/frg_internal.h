@@ -16,6 +16,10 @@ namespace frg {
 struct Geometry {
     int N = 0, n_rad = 0, n_ang = 0, nf = 0, np = 0, Tpp = 0, Tph = 0;
     double t = 0, tp = 0, mu = 0, U = 0, dth = 0;
+    // energy-angle grid: each patch's live points first, then zero-weight
+    // padding up to nf (a multiple of kSegPoints); count[a] live points
+    bool egrid = false;
+    std::vector<int32_t> count;           // [N], egrid only
     std::vector<double> kc, bnd;          // [N][2], [N+1][2]
     std::vector<double> px, py, w, xi;    // [np]
     std::vector<double> qpp, qph;         // [Tpp][2], [Tph][2]
@@ -23,6 +27,11 @@ struct Geometry {
 };
 
 void build_geometry(const frg_params &p, Geometry &g);
+// points per segment of the energy-angle sweep; the padded n_f is a multiple
+constexpr int kSegPoints = 512;
+// the energy-angle quadrature (frg_create_egrid) as the fine grid; false when
+// the points of a patch exceed max_nf
+bool build_geometry_egrid(const frg_params &p, const frg_egrid &e, int max_nf, Geometry &g);
 double fold_bz(double x);
 int32_t host_patch(const Geometry &g, double kx, double ky);
 void host_idx4(const Geometry &g, int32_t *out);
@@ -63,6 +72,9 @@ struct BubbleArgs {
     // the ph row rowlist_ph[o] (the opposite transfer) into Bph, both at o
     const int32_t *rowlist_ph;
     int rpb;   // rows per block of the sweep (a multiple of 4, at most 256; 0: the single-flow default)
+    // energy-angle grid: live points of each patch ([N]); the sweep then walks
+    // them in segments of kSegPoints (nullptr: polar grid, n_f <= 1024)
+    const int32_t *count;
 };
 // full: the bubble L itself (interaction flow) instead of dL/dT
 void launch_bubbles(const BubbleArgs &a, bool fp32, bool full, hipStream_t s);
@@ -70,7 +82,7 @@ void launch_bubbles(const BubbleArgs &a, bool fp32, bool full, hipStream_t s);
 // verify B_{g t}(g a, g b) = B_t(a, b) on the second-line table: counts the
 // (row, point) entries where bins[t'][p'] != g(bins[rep(t')][g^-1 p'])
 void launch_sym_check(const uint8_t *bins, const int32_t *orbit, int N, int n_rad, int n_ang,
-                      int Trows, int *mismatch, hipStream_t s);
+                      int Trows, bool rev, int *mismatch, hipStream_t s);
 
 // permuted copies of V used as contraction operands (FP64)
 void launch_layout_f64(const double *V, int N, double *perm, hipStream_t s);

@@ -548,6 +548,259 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     }
 }
 
+// ----------------------------------------------------------------- segmented sweep
+// The energy-angle grid holds thousands of points per patch (A.count[a] live,
+// the rest zero-weight padding up to n_f, a multiple of kSegPoints).  A block
+// (patch a, chunk of rows) walks the patch's live points in segments of
+// kSegPoints = 64 lanes x 8: per segment the points are set up once (registers
+// or LDS as in the unsegmented sweep), then every row of the block is evaluated
+// on them into that row's own FP64 LDS bins, which therefore hold a whole
+// block's rows (rpb x N doubles, twice for pairs) until the last segment; the
+// rows are written after it.
+constexpr int kSegP = kSegPoints / 64;
+
+template <bool F32>
+size_t seg_point_lds_bytes() {
+    return points_in_registers<kSegP, F32>() ? sizeof(float4) * kSegPoints : sizeof(double) * 7 * kSegPoints;
+}
+
+// rows per block of the segmented sweep: the request (a multiple of 4), cut so
+// that the block's LDS stays within 64 KB
+template <bool F32>
+int seg_rows_per_block(int N, bool paired, int req) {
+    const size_t per_row = sizeof(double) * static_cast<size_t>(N) * (paired ? 2 : 1);
+    const size_t room = 65536 - seg_point_lds_bytes<F32>();
+    int lim = static_cast<int>(room / per_row) / 4 * 4;
+    lim = std::max(4, lim);
+    const int r = req > 0 ? req : 16;
+    return std::min(std::min(r, lim), 256);   // at most 64 rows per wave
+}
+
+template <bool F32>
+size_t seg_lds_bytes(int N, bool paired, int rpb) {
+    return sizeof(double) * static_cast<size_t>(rpb) * N * (paired ? 2 : 1) + seg_point_lds_bytes<F32>();
+}
+
+template <bool F32, bool FULL, bool PAIRED>
+__global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int rpb) {
+    extern __shared__ double smem[];
+    using PT = typename std::conditional<F32, float, double>::type;
+    constexpr int P = kSegP;
+    constexpr bool REG = points_in_registers<P, F32>();
+    constexpr int PR = REG ? P : 1;
+    constexpr int S = kSegPoints;
+    const int N = A.N, nf = A.nf, np = A.np;
+    const int chunk = blockIdx.x, a_patch = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rpw = rpb >> 2;   // rows per wave
+    double *bins = smem + static_cast<size_t>(wave) * rpw * N;               // [rpw][N]
+    double *bins2 = smem + static_cast<size_t>(4 + wave) * rpw * N;          // pairs' ph rows
+    double *pt = smem + static_cast<size_t>(PAIRED ? 8 : 4) * rpw * N;       // LDS mode: [7][S]
+    float4 *tay = reinterpret_cast<float4 *>(pt);                            // register mode: [S]
+
+    const double Tcur = A.Tdev[0];
+    const GLOBAL_AS float *pa32 = gld(A.pa32);
+    const GLOBAL_AS double *pa64 = gld(A.pa64), *trig_pt = gld(A.trig_pt);
+    const GLOBAL_AS uint8_t *const gbins = gld(A.bins);
+    const CONST_AS double *const gtrig = cld(A.trig_row);
+    auto point_consts = [&](int i, PT &a, PT &c1, PT &c2) {
+        const double wf = F32 ? static_cast<double>(pa32[2 * np + i]) : pa64[2 * np + i];
+        const double av = F32 ? static_cast<double>(pa32[i]) : pa64[i];
+        a = static_cast<PT>(av);
+        if constexpr (FULL) {
+            const double W = -wf * Tcur;
+            c1 = static_cast<PT>(W * tanh_d(av));
+            c2 = static_cast<PT>(W);
+        } else {
+            const PT w = static_cast<PT>(wf);
+            c1 = w * static_cast<PT>(F32 ? pa32[np + i] : pa64[np + i]);
+            c2 = PT(-4) * w;
+        }
+    };
+    const double inv2T = A.Tdev[1];
+    const double K1 = uniform_f64(A.mt2 * inv2T), K3 = uniform_f64(A.mu * inv2T);
+    const double G = uniform_f64(A.mt4p / (A.mt2 * A.mt2) * (1.0 / inv2T));
+    const size_t NN = static_cast<size_t>(N) * N;
+
+    const int row0 = chunk * rpb;
+    for (int k = lane; k < rpw * N; k += 64) bins[k] = 0.0;
+    if constexpr (PAIRED)
+        for (int k = lane; k < rpw * N; k += 64) bins2[k] = 0.0;
+    // the wave's rows, one per lane (at most 64 rows per wave)
+    const int my_slot = row0 + wave + 4 * lane;
+    const bool my_ok = lane < rpw && my_slot < A.nrows;
+    const int my_r = my_ok ? (A.rowlist ? A.rowlist[my_slot] : my_slot) : 0;
+    const int my_rph = (PAIRED && my_ok) ? A.rowlist_ph[my_slot] : 0;
+    int nrow_w = 0;   // rows this wave evaluates
+    while (nrow_w < rpw && row0 + wave + 4 * nrow_w < A.nrows) ++nrow_w;
+
+    const int nseg = (A.count[a_patch] + S - 1) / S;
+    double cpx[PR], spx[PR], cpy[PR], spy[PR];
+    PT pa[PR], pc1[PR], pc2[PR];
+    for (int sg = 0; sg < nseg; ++sg) {
+        const int k0 = sg * S;
+        // every wave is done with the previous segment's shared point data
+        if (sg > 0) __syncthreads();
+        if constexpr (REG) {
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                const int i = a_patch * nf + k0 + lane * P + j;
+                cpx[j] = trig_pt[i];
+                spx[j] = trig_pt[np + i];
+                cpy[j] = trig_pt[2 * np + i];
+                spy[j] = trig_pt[3 * np + i];
+                point_consts(i, pa[j], pc1[j], pc2[j]);
+                if ((j & 3) == wave) {
+                    const double wf = static_cast<double>(pa32[2 * np + i]);
+                    tay[j * 64 + lane] = taylor_consts<FULL>(static_cast<double>(pa[j]), FULL ? -wf * Tcur : wf);
+                }
+            }
+        } else {
+            for (int k = threadIdx.x; k < S; k += kThreads) {
+                const int slot = (k % P) * 64 + k / P;
+                const int i = a_patch * nf + k0 + k;
+                pt[0 * S + slot] = trig_pt[i];
+                pt[1 * S + slot] = trig_pt[np + i];
+                pt[2 * S + slot] = trig_pt[2 * np + i];
+                pt[3 * S + slot] = trig_pt[3 * np + i];
+                PT a, c1, c2;
+                point_consts(i, a, c1, c2);
+                pt[4 * S + slot] = a;
+                pt[5 * S + slot] = c1;
+                pt[6 * S + slot] = c2;
+            }
+        }
+        __syncthreads();
+        auto pval = [&](int q, int j) -> double {
+            if constexpr (REG) {
+                return q == 0 ? cpx[j] : q == 1 ? spx[j] : q == 2 ? cpy[j] : q == 3 ? spy[j]
+                     : q == 4 ? static_cast<double>(pa[j]) : q == 5 ? static_cast<double>(pc1[j])
+                     : static_cast<double>(pc2[j]);
+            } else {
+                return pt[q * S + j * 64 + lane];
+            }
+        };
+        auto coef = [&](int j) -> float4 {
+            if constexpr (REG) {
+                return tay[j * 64 + lane];
+            } else {
+                const double c2 = pval(6, j);
+                return taylor_consts<FULL>(pval(4, j), FULL ? c2 : -0.25 * c2);
+            }
+        };
+        // the lane's 8 table bytes of row r in this segment (in bounds: n_f is a
+        // multiple of the segment)
+        auto load_bins = [&](int r, uint32_t *bw) {
+            const GLOBAL_AS uint8_t *src = gbins + static_cast<size_t>(r) * np + static_cast<size_t>(a_patch) * nf +
+                                           k0 + lane * P;
+            const uint64_t v = *reinterpret_cast<const GLOBAL_AS uint64_t *>(src);
+            bw[0] = static_cast<uint32_t>(v);
+            bw[1] = static_cast<uint32_t>(v >> 32);
+        };
+        auto bin_of = [&](const uint32_t *w, int j) -> int { return (w[j >> 2] >> (8 * (j & 3))) & 0xff; };
+        for (int it = 0; it < nrow_w; ++it) {
+            const int r = __builtin_amdgcn_readlane(my_r, it);
+            const bool pp = PAIRED || r < A.Tpp;
+            const double k1 = pp ? -K1 : K1, g = pp ? -G : G, k3 = pp ? -K3 : K3;
+            const CONST_AS double *tr = gtrig + 4 * r;
+            const double cqx = uniform_f64(k1 * tr[0]), cqy = uniform_f64(k1 * tr[2]);
+            const double sx = uniform_f64((pp ? k1 : -k1) * tr[1]);
+            const double sy = uniform_f64((pp ? k1 : -k1) * tr[3]);
+            uint32_t bw[2], bw2[2];
+            load_bins(r, bw);
+            if constexpr (PAIRED) load_bins(__builtin_amdgcn_readlane(my_rph, it), bw2);
+            auto value = [&](int j, PT &v, PT &v2) {
+                const double Y = cqy * pval(2, j) + sy * pval(3, j);
+                const double X = cqx * pval(0, j) + sx * pval(1, j);
+                const PT b = static_cast<PT>(fma(X, fma(-g, Y, 1.0), Y - k3));
+                const PT a = static_cast<PT>(pval(4, j)), c1 = static_cast<PT>(pval(5, j)),
+                         c2 = static_cast<PT>(pval(6, j));
+                if constexpr (PAIRED) {
+                    if constexpr (F32 && FULL) wdiv_t32_pair(a, c1, c2, b, [&] { return coef(j); }, v, v2);
+                    else if constexpr (F32) wdiv_h32_pair(a, c1, c2, b, [&] { return coef(j); }, v, v2);
+                    else if constexpr (FULL) wdiv_t64_pair(a, c1, c2, b, v, v2);
+                    else wdiv_h64_pair(a, c1, c2, b, v, v2);
+                    return;
+                }
+                const PT d = a - b;
+                if constexpr (F32) {
+                    v = FULL ? wdiv_t32_far(c1, c2, b, d) : wdiv_h32_far(c1, c2, b, d);
+                    if (fabsf(d) < kTaylor32) v = taylor_poly(coef(j), d);
+                } else {
+                    if constexpr (FULL) {
+                        v = wdiv_t64_far(c1, c2, b, d);
+                        if (fabs(d) < kTaylor64) v = wdiv_t64_near(a, c2, b);
+                    } else {
+                        v = wdiv_h64_far(c1, c2, b, d);
+                        if (fabs(d) < kTaylor64) v = wdiv_h64_near(a, c2, b);
+                    }
+                }
+            };
+            double *rb = bins + static_cast<size_t>(it) * N;
+            double *rb2 = bins2 + static_cast<size_t>(it) * N;
+            PT acc, acc2 = PT(0);
+            value(0, acc, acc2);
+            int bcur = bin_of(bw, 0), bcur2 = PAIRED ? bin_of(bw2, 0) : 0;
+#pragma unroll
+            for (int j = 1; j < P; ++j) {
+                PT v, v2 = PT(0);
+                value(j, v, v2);
+                const int bin = bin_of(bw, j);
+                if (bin != bcur) {
+                    atomicAdd(&rb[bcur], static_cast<double>(acc));
+                    acc = PT(0);
+                }
+                acc += v;
+                bcur = bin;
+                if constexpr (PAIRED) {
+                    const int bin2 = bin_of(bw2, j);
+                    if (bin2 != bcur2) {
+                        atomicAdd(&rb2[bcur2], static_cast<double>(acc2));
+                        acc2 = PT(0);
+                    }
+                    acc2 += v2;
+                    bcur2 = bin2;
+                }
+            }
+            atomicAdd(&rb[bcur], static_cast<double>(acc));
+            if constexpr (PAIRED) atomicAdd(&rb2[bcur2], static_cast<double>(acc2));
+        }
+    }
+    wave_sync();
+    // the wave's rows out (each row's bins were written by this wave only)
+    constexpr int NO = PAIRED ? 2 : 1;
+    for (int it = 0; it < nrow_w; ++it) {
+        const int slot_out = row0 + wave + 4 * it;
+#pragma unroll
+        for (int k = 0; k < NO; ++k) {
+            const bool pp_out = PAIRED ? k == 0 : slot_out < A.npp_out;
+            const size_t pos = PAIRED ? static_cast<size_t>(slot_out)
+                                      : (pp_out ? static_cast<size_t>(slot_out)
+                                                : static_cast<size_t>(slot_out - A.npp_out));
+            const size_t base = pos * NN + static_cast<size_t>(a_patch) * N;
+            void *outp = pp_out ? A.Bpp : A.Bph;
+            if (!outp) continue;
+            const double *src = (k == 0 ? bins : bins2) + static_cast<size_t>(it) * N;
+            for (int b = lane; b < N; b += 64) {
+                if (F32) gst(static_cast<float *>(outp))[base + b] = static_cast<float>(src[b]);
+                else gst(static_cast<double *>(outp))[base + b] = src[b];
+            }
+        }
+    }
+}
+
+template <bool F32, bool FULL>
+void launch_seg(const BubbleArgs &a, hipStream_t s) {
+    const bool paired = a.rowlist_ph != nullptr;
+    const int rpb = seg_rows_per_block<F32>(a.N, paired, a.rpb);
+    dim3 grid((a.nrows + rpb - 1) / rpb, a.N);
+    const size_t lds = seg_lds_bytes<F32>(a.N, paired, rpb);
+    if (paired)
+        hipLaunchKernelGGL((bubble_seg_kernel<F32, FULL, true>), grid, dim3(kThreads), lds, s, a, rpb);
+    else
+        hipLaunchKernelGGL((bubble_seg_kernel<F32, FULL, false>), grid, dim3(kThreads), lds, s, a, rpb);
+}
+
 template <int P, bool F32, bool FULL, bool PAIRED>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void bubble_kernel(BubbleArgs A) {
     extern __shared__ double smem[];
@@ -627,6 +880,13 @@ void launch_bubbles_batched(const BubbleArgs *args, const int2 *items, int npair
 }
 
 void launch_bubbles(const BubbleArgs &a, bool fp32, bool full, hipStream_t s) {
+    if (a.count) {   // energy-angle grid: segments of the patch's live points
+        if (fp32 && !full) launch_seg<true, false>(a, s);
+        else if (!fp32 && !full) launch_seg<false, false>(a, s);
+        else if (fp32) launch_seg<true, true>(a, s);
+        else launch_seg<false, true>(a, s);
+        return;
+    }
     const int P = (a.nf + 63) / 64;
     if (P <= 1) launch_p<1>(a, fp32, full, s);
     else if (P <= 2) launch_p<2>(a, fp32, full, s);

@@ -103,7 +103,7 @@ __device__ __forceinline__ int c4v_patch(int o, int j, int N) {
 
 // orbit[t'] = (rep row << 3) | o with t' = o . rep
 __global__ void sym_check_kernel(const uint8_t *__restrict__ bins, const int32_t *__restrict__ orbit,
-                                 int N, int n_rad, int n_ang, int Trows, int *mismatch) {
+                                 int N, int n_rad, int n_ang, int Trows, bool rev, int *mismatch) {
     const int nf = n_rad * n_ang, np = N * nf;
     const int ip = blockIdx.x * blockDim.x + threadIdx.x;
     if (ip >= np) return;
@@ -116,7 +116,7 @@ __global__ void sym_check_kernel(const uint8_t *__restrict__ bins, const int32_t
         if (o == 0) continue;
         const int oinv = (o & 1) ? o : ((8 - o) & 7);
         const int a = c4v_patch(oinv, a1, N);
-        const int s = (o & 1) ? n_ang - 1 - s1 : s1;
+        const int s = (rev && (o & 1)) ? n_ang - 1 - s1 : s1;
         const int b = bins[static_cast<size_t>(rep) * np + a * nf + m * n_ang + s];
         if (bins[static_cast<size_t>(t) * np + a1 * nf + m * n_ang + s1] != c4v_patch(o, b, N)) ++bad;
     }
@@ -1082,10 +1082,10 @@ void launch_bins_export(const uint8_t *bins, int N, int n_rad, int n_ang, int r0
 }
 
 void launch_sym_check(const uint8_t *bins, const int32_t *orbit, int N, int n_rad, int n_ang,
-                      int Trows, int *mismatch, hipStream_t s) {
+                      int Trows, bool rev, int *mismatch, hipStream_t s) {
     const int np = N * n_rad * n_ang;
     dim3 grid(blocks_for(np, 256), Trows < 4096 ? Trows : 4096);
-    hipLaunchKernelGGL(sym_check_kernel, grid, dim3(256), 0, s, bins, orbit, N, n_rad, n_ang, Trows,
+    hipLaunchKernelGGL(sym_check_kernel, grid, dim3(256), 0, s, bins, orbit, N, n_rad, n_ang, Trows, rev,
                        mismatch);
 }
 

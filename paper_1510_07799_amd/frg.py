@@ -60,6 +60,10 @@ class IFlowResult(C.Structure):
                 ("rhs_evals", C.c_int32), ("first_step_rhs", C.c_int32)]
 
 
+class Egrid(C.Structure):
+    _fields_ = [("n_E", C.c_int32), ("max_level", C.c_int32), ("rtol", C.c_double)]
+
+
 class Tuning(C.Structure):
     _fields_ = [("kparts", C.c_int32), ("sweep_rows", C.c_int32), ("block_rows", C.c_int32)]
 
@@ -77,6 +81,10 @@ SIGNATURES = {
     "frg_sizes": (C.c_int, [_P, _SZ, _SZ, _SZ, _SZ]),
     "frg_tables": (C.c_int, [_P, _DP, _DP, _DP, _DP, _DP, _IP]),
     "frg_host_tables": (C.c_int, [C.POINTER(Params), _DP, _DP, _DP, _DP, _DP, _IP]),
+    "frg_create_egrid": (C.c_int, [C.POINTER(Params), C.POINTER(Egrid), C.POINTER(_P)]),
+    "frg_points": (C.c_int, [_P, _IP, _IP]),
+    "frg_host_tables_egrid": (C.c_int, [C.POINTER(Params), C.POINTER(Egrid), _IP, _IP, _DP, _DP, _DP, _DP, _DP,
+                                        _IP]),
     "frg_bins": (C.c_int, [_P, C.c_int32, _P, _P]),
     "frg_bubbles": (C.c_int, [_P, C.c_double, C.c_int, _P, _P, _P]),
     "frg_bubble_reps": (C.c_int, [_P, _IP, _IP, _IP]),
@@ -159,11 +167,39 @@ def params(t=1.0, tp=0.0, mu=0.0, U=2.0, N=16, n_rad=8, n_ang=8) -> Params:
     return Params(float(t), float(tp), float(mu), float(U), int(N), int(n_rad), int(n_ang))
 
 
-def host_tables(t=1.0, tp=0.0, mu=0.0, U=2.0, N=16, n_rad=8, n_ang=8, idx4=True) -> dict:
-    """Geometry tables built by the library's host code (no device needed)."""
+def egrid(n_E, max_level, rtol) -> Egrid:
+    return Egrid(int(n_E), int(max_level), float(rtol))
+
+
+def host_tables(t=1.0, tp=0.0, mu=0.0, U=2.0, N=16, n_rad=8, n_ang=8, idx4=True, egrid=None) -> dict:
+    """Geometry tables built by the library's host code (no device needed).
+    egrid = dict(n_E, max_level, rtol): the energy-angle grid (adds n_f and the
+    per-patch live counts)."""
     p = params(t, tp, mu, U, N, n_rad, n_ang)
-    nf = n_rad * n_ang
     Tpp, Tph = N * (N + 1) // 2, N * (N - 1) + 1
+    if egrid is not None:
+        e = Egrid(int(egrid["n_E"]), int(egrid["max_level"]), float(egrid["rtol"]))
+        nfv = C.c_int32()
+        cnt = np.zeros(N, dtype=np.int32)
+        _check(lib().frg_host_tables_egrid(C.byref(p), C.byref(e), C.byref(nfv), None, None, None, None, None,
+                                           None, None))
+        nf = nfv.value
+        kc = np.zeros((N, 2))
+        bnd = np.zeros((N + 1, 2))
+        fine = np.zeros((N * nf, 4))
+        qpp = np.zeros((Tpp, 2))
+        qph = np.zeros((Tph, 2))
+        i4 = np.zeros((N, N, N), dtype=np.int32) if idx4 else None
+        dp = lambda a: a.ctypes.data_as(_DP)
+        _check(lib().frg_host_tables_egrid(C.byref(p), C.byref(e), C.byref(nfv), cnt.ctypes.data_as(_IP), dp(kc),
+                                           dp(bnd), dp(fine), dp(qpp), dp(qph),
+                                           i4.ctypes.data_as(_IP) if idx4 else None))
+        out = dict(kc=kc, bnd=bnd, px=fine[:, 0].copy(), py=fine[:, 1].copy(), w=fine[:, 2].copy(),
+                   xi=fine[:, 3].copy(), qpp=qpp, qph=qph, nf=nf, count=cnt)
+        if idx4:
+            out["idx4"] = i4
+        return out
+    nf = n_rad * n_ang
     kc = np.zeros((N, 2))
     bnd = np.zeros((N + 1, 2))
     fine = np.zeros((N * nf, 4))
@@ -197,7 +233,7 @@ def iflow_opts(stepper="rk4", prec=PREC_FP64, T=0.1, g0=0.0, g1=1.0, rtol=1e-6, 
 class Context:
     """One parameter set on the current HIP device (owns geometry + workspace)."""
 
-    def __init__(self, t=1.0, tp=0.0, mu=0.0, U=2.0, N=16, n_rad=8, n_ang=8):
+    def __init__(self, t=1.0, tp=0.0, mu=0.0, U=2.0, N=16, n_rad=8, n_ang=8, egrid=None):
         import torch
         self.torch = torch
         self.N, self.nf, self.U = int(N), int(n_rad) * int(n_ang), float(U)
@@ -205,8 +241,22 @@ class Context:
         self.params = dict(t=t, tp=tp, mu=mu, U=U, N=N, n_rad=n_rad, n_ang=n_ang)
         p = params(t, tp, mu, U, N, n_rad, n_ang)
         h = _P()
-        _check(lib().frg_create(C.byref(p), C.byref(h)))
+        if egrid is None:
+            _check(lib().frg_create(C.byref(p), C.byref(h)))
+        else:
+            e = Egrid(int(egrid["n_E"]), int(egrid["max_level"]), float(egrid["rtol"]))
+            self.params["egrid"] = dict(n_E=e.n_E, max_level=e.max_level, rtol=e.rtol)
+            _check(lib().frg_create_egrid(C.byref(p), C.byref(e), C.byref(h)))
         self._h = h
+        nfv = C.c_int32()
+        _check(lib().frg_points(h, C.byref(nfv), None))
+        self.nf = nfv.value
+
+    def counts(self):
+        """live points of every patch (n_f each on a polar grid)"""
+        c = np.zeros(self.N, dtype=np.int32)
+        _check(lib().frg_points(self._h, None, c.ctypes.data_as(_IP)))
+        return c
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

@@ -12,7 +12,7 @@ from __future__ import annotations
 
 import numpy as np
 
-# Parameter sets of the five workloads (t = 1 throughout).
+# Parameter sets of the workloads (t = 1 throughout).
 CONFIGS = {
     # plain FP64, small: half filling, 40 fixed RK4 steps T = 1 -> 0.05
     "C1": dict(t=1.0, tp=0.0, mu=0.0, U=2.0, N=16, n_rad=8, n_ang=8,
@@ -35,6 +35,14 @@ CONFIGS = {
     "C5": dict(t=1.0, tp=-0.25, mu=-1.0, U=2.5, N=192, n_rad=32, n_ang=32,
                flow=dict(stepper="dp54", T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10,
                          vmax=20.0, h0=-0.01, max_steps=30)),
+    # the paper's quadrature (Sec. 4: 1600 energies 0.005t apart across the 8t
+    # band, adaptive inner rule with relative target 1e-4) on the N = 96 model;
+    # at most 27 points per patch sector and shell (2592 per shell at N = 96,
+    # the paper's 2187 per inner integral to within the power of three)
+    "E1": dict(t=1.0, tp=-0.3, mu=-1.2, U=3.0, N=96, n_rad=1, n_ang=1,
+               egrid=dict(n_E=1600, max_level=3, rtol=1e-4),
+               flow=dict(stepper="dp54", T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10,
+                         vmax=20.0, h0=-0.01)),
 }
 
 C4_SEED = 151007799
@@ -43,7 +51,10 @@ C4_NS = (32, 48, 64, 96)
 
 def model_params(name: str) -> dict:
     c = CONFIGS[name]
-    return {k: c[k] for k in ("t", "tp", "mu", "U", "N", "n_rad", "n_ang")}
+    out = {k: c[k] for k in ("t", "tp", "mu", "U", "N", "n_rad", "n_ang")}
+    if "egrid" in c:
+        out["egrid"] = dict(c["egrid"])
+    return out
 
 
 def c4_flows(n_per_N: int = 64, seed: int = C4_SEED, Ns=C4_NS, n_rad=16, n_ang=16):
