@@ -13,6 +13,7 @@ G1-G10 documented in ``frg_oracle.c``.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -106,6 +107,10 @@ def lib():
         L.orc_rhs.argtypes = [C.c_void_p, C.c_double, _DP, _DP]
         L.orc_contract.argtypes = [C.c_void_p, _DP, _DP, _DP, _DP]
         L.orc_rhs_entries.argtypes = [C.c_void_p, C.c_double, _DP, C.c_int64, _IP, _DP]
+        L.orc_bubbles_se.argtypes = [C.c_void_p, C.c_double, C.c_int32, _DP, _DP, _DP]
+        L.orc_dsigma.argtypes = [C.c_void_p, C.c_double, _DP, _DP, _DP]
+        L.orc_rhs_se.argtypes = [C.c_void_p, C.c_double, _DP, _DP, _DP, _DP]
+        L.orc_rhs_entries_se.argtypes = [C.c_void_p, C.c_double, _DP, _DP, C.c_int64, _IP, _DP]
         L.orc_rk4.restype = C.c_int32
         L.orc_rk4.argtypes = [ODE_FN, C.c_void_p, C.c_int64, _DP, C.c_double, C.c_double,
                               C.c_int32, C.c_double, C.POINTER(_OdeResult)]
@@ -301,6 +306,64 @@ class Model:
         out = np.zeros(idx.shape[0])
         lib().orc_rhs_entries(self._h, float(T), _dp(V), idx.shape[0], _ip(idx), _dp(out))
         return out
+
+    # self-energy ----------------------------------------------------------
+    def bubbles_se(self, T: float, S, deriv: int = 1):
+        N = self.N
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(N)
+        Bpp = np.zeros((self.Tpp, N, N))
+        Bph = np.zeros((self.Tph, N, N))
+        lib().orc_bubbles_se(self._h, float(T), int(deriv), _dp(S), _dp(Bpp), _dp(Bph))
+        return Bpp, Bph
+
+    def dsigma(self, T: float, V, S) -> np.ndarray:
+        N = self.N
+        V = np.ascontiguousarray(V, dtype=np.float64).reshape(N, N, N)
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(N)
+        out = np.zeros(N)
+        lib().orc_dsigma(self._h, float(T), _dp(V), _dp(S), _dp(out))
+        return out
+
+    def rhs_se(self, T: float, V, S):
+        """(dV/dT, dS/dT) with the self-energy S in every loop line."""
+        N = self.N
+        V = np.ascontiguousarray(V, dtype=np.float64).reshape(N, N, N)
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(N)
+        F = np.zeros_like(V)
+        dS = np.zeros(N)
+        lib().orc_rhs_se(self._h, float(T), _dp(V), _dp(S), _dp(F), _dp(dS))
+        return F, dS
+
+    def rhs_entries_se(self, T: float, V, S, j123) -> np.ndarray:
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(self.N)
+        idx = np.ascontiguousarray(np.asarray(j123, dtype=np.int32).reshape(-1, 3))
+        out = np.zeros(idx.shape[0])
+        lib().orc_rhs_entries_se(self._h, float(T), _dp(V), _dp(S), idx.shape[0], _ip(idx), _dp(out))
+        return out
+
+    def flow_se(self, V0=None, S0=None, stepper="dp54", T0=1.0, T_min=0.05, fixed_steps=40, rtol=1e-6,
+                atol=1e-10, vmax=20.0, h0=-0.01, max_steps=0, log_cap=4096):
+        """Temperature flow of the vertex and the self-energy together: y = (V, S)
+        in s = ln T with dy/ds = T (dV/dT, dS/dT); returns (V, S, result, log)."""
+        N = self.N
+        n3 = N ** 3
+        V = (np.full((N, N, N), float(self.U)) if V0 is None
+             else np.ascontiguousarray(V0, dtype=np.float64))
+        S = np.zeros(N) if S0 is None else np.ascontiguousarray(S0, dtype=np.float64)
+        y0 = np.concatenate([V.ravel(), S.ravel()])
+
+        def f(s, y):
+            T = math.exp(s)
+            F, dS = self.rhs_se(T, y[:n3], y[n3:])
+            return T * np.concatenate([F.ravel(), dS])
+        s0, s1 = math.log(T0), math.log(T_min)
+        if stepper == "rk4":
+            y, res = rk4(f, y0, s0, s1, fixed_steps, vmax)
+            log = np.zeros((0, 6))
+        else:
+            y, res, log = dp54(f, y0, s0, s1, h0, rtol, atol, vmax, max_steps, log_cap)
+        return y[:n3].reshape(N, N, N), y[n3:].copy(), res, log
 
     def flow(self, V0=None, stepper="rk4", T0=1.0, T_min=0.05, fixed_steps=40, rtol=1e-6,
              atol=1e-10, vmax=20.0, h0=-0.01, max_steps=0, log_cap=4096):

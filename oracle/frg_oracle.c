@@ -688,8 +688,10 @@ void orc_bins(const orc_model *m, int32_t kind, int32_t *out)
 }
 
 /* B_t(a,b) = sum over fine points p in patch a whose second line lies in
- * patch b of w_p L(xi_p, eps(second line)). */
-static void bubble_kind(const orc_model *m, int kind, double T, int deriv, double *B)
+ * patch b of w_p L(xi_p, eps(second line)); with a self-energy S (one value
+ * per patch, nullable) each line's energy carries its own patch's S:
+ * L(xi_p + S_a, eps(second line) + S_b). */
+static void bubble_kind(const orc_model *m, int kind, double T, int deriv, const double *S, double *B)
 {
     int N = m->N, nf = m->nf;
     int Tn = kind == 1 ? m->Tpp : m->Tph;
@@ -704,16 +706,26 @@ static void bubble_kind(const orc_model *m, int kind, double T, int deriv, doubl
                 double kx, ky;
                 second_line(m, kind, t, i, &kx, &ky);
                 int b = orc_project(m, kx, ky);
-                double xi2 = eps_k(&m->p, kx, ky);
-                Bt[a * N + b] += m->w[i] * orc_L(kind, deriv, m->xi[i], xi2, T);
+                double xi1 = m->xi[i], xi2 = eps_k(&m->p, kx, ky);
+                if (S) {
+                    xi1 = xi1 + S[a];
+                    xi2 = xi2 + S[b];
+                }
+                Bt[a * N + b] += m->w[i] * orc_L(kind, deriv, xi1, xi2, T);
             }
     }
 }
 
 void orc_bubbles(const orc_model *m, double T, int32_t deriv, double *Bpp, double *Bph)
 {
-    if (Bpp) bubble_kind(m, 1, T, deriv, Bpp);
-    if (Bph) bubble_kind(m, 0, T, deriv, Bph);
+    if (Bpp) bubble_kind(m, 1, T, deriv, NULL, Bpp);
+    if (Bph) bubble_kind(m, 0, T, deriv, NULL, Bph);
+}
+
+void orc_bubbles_se(const orc_model *m, double T, int32_t deriv, const double *S, double *Bpp, double *Bph)
+{
+    if (Bpp) bubble_kind(m, 1, T, deriv, S, Bpp);
+    if (Bph) bubble_kind(m, 0, T, deriv, S, Bph);
 }
 
 /* ------------------------------------------------------------------ G8 */
@@ -765,7 +777,7 @@ void orc_rhs(const orc_model *m, double T, const double *V, double *F)
 
 /* Brute force: the same three diagrams as a direct sum over every fine point,
  * projecting each second line on the spot, without bubble tensors. */
-static double rhs_entry(const orc_model *m, double T, const double *V, int j1, int j2, int j3)
+static double rhs_entry(const orc_model *m, double T, const double *V, const double *S, int j1, int j2, int j3)
 {
     int N = m->N, nf = m->nf;
     const double *kc = m->kc;
@@ -776,20 +788,20 @@ static double rhs_entry(const orc_model *m, double T, const double *V, int j1, i
     for (int a = 0; a < N; a++)
         for (int k = 0; k < nf; k++) {
             int i = a * nf + k;
-            double px = m->px[i], py = m->py[i], w = m->w[i], x1 = m->xi[i];
+            double px = m->px[i], py = m->py[i], w = m->w[i], x1 = m->xi[i] + (S ? S[a] : 0.0);
             double kx, ky, v;
             int b;
             kx = orc_fold(qx - px); ky = orc_fold(qy - py);
             b = orc_project(m, kx, ky);
-            v = w * orc_L(1, 1, x1, eps_k(&m->p, kx, ky), T);
+            v = w * orc_L(1, 1, x1, eps_k(&m->p, kx, ky) + (S ? S[b] : 0.0), T);
             s -= v * VI(j1, j2, a) * VI(a, b, j3);
             kx = orc_fold(px + cx); ky = orc_fold(py + cy);
             b = orc_project(m, kx, ky);
-            v = w * orc_L(0, 1, x1, eps_k(&m->p, kx, ky), T);
+            v = w * orc_L(0, 1, x1, eps_k(&m->p, kx, ky) + (S ? S[b] : 0.0), T);
             s += v * VI(j1, a, b) * VI(b, j2, j3);
             kx = orc_fold(px + dx); ky = orc_fold(py + dy);
             b = orc_project(m, kx, ky);
-            v = w * orc_L(0, 1, x1, eps_k(&m->p, kx, ky), T);
+            v = w * orc_L(0, 1, x1, eps_k(&m->p, kx, ky) + (S ? S[b] : 0.0), T);
             s += v * (-2.0 * VI(j1, b, j3) * VI(a, j2, b) + VI(j1, b, a) * VI(a, j2, b)
                       + VI(j1, b, j3) * VI(j2, a, b));
         }
@@ -801,7 +813,62 @@ void orc_rhs_entries(const orc_model *m, double T, const double *V, int64_t n,
 {
 #pragma omp parallel for schedule(dynamic, 1) num_threads(NT)
     for (int64_t e = 0; e < n; e++)
-        out[e] = rhs_entry(m, T, V, j123[3 * e], j123[3 * e + 1], j123[3 * e + 2]);
+        out[e] = rhs_entry(m, T, V, NULL, j123[3 * e], j123[3 * e + 1], j123[3 * e + 2]);
+}
+
+void orc_rhs_entries_se(const orc_model *m, double T, const double *V, const double *S, int64_t n,
+                        const int32_t *j123, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 1) num_threads(NT)
+    for (int64_t e = 0; e < n; e++)
+        out[e] = rhs_entry(m, T, V, S, j123[3 * e], j123[3 * e + 1], j123[3 * e + 2]);
+}
+
+/* ------------------------------------------------------------------ self-energy */
+/* The self-energy extension the paper names (Sec. 2) in its simplest form (a
+ * reading): a static self-energy S_j, one value per patch, flowing with the
+ * vertex.  Every loop line carries its patch's S (bubble_kind), and S flows by
+ * the one-loop tadpole with the flowing vertex and the temperature derivative
+ * of the occupation at fixed S:
+ *   dS_j/dT = sum_a D_a [2 V(j, a, j) - V(a, j, j)],
+ *   D_a = sum_{p in a} w_p d/dT n_F((xi_p + S_a)/T),
+ *   d/dT n_F(x/T) = x/(4 T^2) sech^2(x/2T)   (x fixed).
+ * The bracket is the spin sum of the antisymmetrised vertex at k3 = k1 (direct
+ * term 2V, exchange term V with the legs crossed); at first order with V = U
+ * it is the Hartree-Fock shift U n per spin. */
+void orc_dsigma(const orc_model *m, double T, const double *V, const double *S, double *dS)
+{
+    int N = m->N, nf = m->nf;
+    double *D = malloc(sizeof(double) * N);
+    for (int a = 0; a < N; a++) {
+        double acc = 0.0;
+        for (int k = 0; k < nf; k++) {
+            int i = a * nf + k;
+            double x = m->xi[i] + (S ? S[a] : 0.0);
+            double Sh, tau;
+            sech2_tanh(x / (2.0 * T), &Sh, &tau);
+            acc += m->w[i] * (x / (4.0 * T * T) * Sh);
+        }
+        D[a] = acc;
+    }
+    for (int j = 0; j < N; j++) {
+        double acc = 0.0;
+        for (int a = 0; a < N; a++) acc += D[a] * (2.0 * VI(j, a, j) - VI(a, j, j));
+        dS[j] = acc;
+    }
+    free(D);
+}
+
+void orc_rhs_se(const orc_model *m, double T, const double *V, const double *S, double *F, double *dS)
+{
+    size_t NN = (size_t)m->N * m->N;
+    double *Bpp = malloc(sizeof(double) * NN * m->Tpp);
+    double *Bph = malloc(sizeof(double) * NN * m->Tph);
+    orc_bubbles_se(m, T, 1, S, Bpp, Bph);
+    orc_contract(m, Bpp, Bph, V, F);
+    free(Bpp);
+    free(Bph);
+    orc_dsigma(m, T, V, S, dS);
 }
 
 /* ------------------------------------------------------------------ steppers */

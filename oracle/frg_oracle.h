@@ -99,6 +99,20 @@ void orc_contract(const orc_model *m, const double *Bpp, const double *Bph,
 void orc_rhs_entries(const orc_model *m, double T, const double *V, int64_t n,
                      const int32_t *j123, double *out);
 
+/* Self-energy (a static value S_j per patch flowing with the vertex; S may be
+ * NULL for zero).  Every loop line carries its own patch's S:
+ * L(xi_p + S_a, eps(second line) + S_b).
+ *   orc_bubbles_se: the bubble tensors with S;
+ *   orc_dsigma: dS_j/dT = sum_a D_a [2 V(j,a,j) - V(a,j,j)],
+ *               D_a = sum_{p in a} w_p d/dT n_F((xi_p + S_a)/T) at fixed S;
+ *   orc_rhs_se: F (as orc_rhs, with S in the bubbles) and dS;
+ *   orc_rhs_entries_se: brute-force F entries with S. */
+void orc_bubbles_se(const orc_model *m, double T, int32_t deriv, const double *S, double *Bpp, double *Bph);
+void orc_dsigma(const orc_model *m, double T, const double *V, const double *S, double *dS);
+void orc_rhs_se(const orc_model *m, double T, const double *V, const double *S, double *F, double *dS);
+void orc_rhs_entries_se(const orc_model *m, double T, const double *V, const double *S, int64_t n,
+                        const int32_t *j123, double *out);
+
 /* Generic explicit steppers in s for dy/ds = f(s, y). */
 typedef void (*orc_ode_fn)(void *ctx, double s, const double *y, double *dyds, int64_t n);
 

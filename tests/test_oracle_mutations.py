@@ -19,6 +19,9 @@ HDR = os.path.join(ROOT, "oracle", "frg_oracle.h")
 SU2 = ["tests/test_oracle_symmetries.py::test_su2_spinful_equation_exact_momentum_closure",
        "tests/test_oracle_symmetries.py::test_su2_spinful_equation_general_geometry"]
 WEIGHTS = ["tests/test_oracle_symmetries.py::test_weights_integrate_closed_forms"]
+SE = ["tests/test_oracle_self_energy.py::test_tadpole_is_the_spin_sum_of_the_antisymmetrised_vertex",
+      "tests/test_oracle_self_energy.py::test_hartree_shift_against_the_closed_form_density_of_states",
+      "tests/test_oracle_self_energy.py::test_binned_equals_brute_force_with_a_self_energy"]
 EGRID = ["tests/test_oracle_egrid.py::test_points_lie_on_their_shells",
          "tests/test_oracle_egrid.py::test_dos_nearest_neighbour_band_is_the_elliptic_integral"]
 
@@ -36,6 +39,12 @@ CASES = [
      "double E = Emin + ((double)i + 0.5) * dE", "double E = Emin + (double)i * dE", EGRID),
     ("every angle of a sector integrated, also where the ray stays below the shell energy",
      "    *c1 = a1;\n    if (e0 >= E && e1 >= E) return;", "    *c1 = a1;\n    return;", EGRID),
+    ("self-energy exchange term with the legs of the wrong pair crossed",
+     "(2.0 * VI(j, a, j) - VI(a, j, j))", "(2.0 * VI(j, a, j) - VI(j, a, a))", SE),
+    ("self-energy direct term without its spin sum",
+     "(2.0 * VI(j, a, j) - VI(a, j, j))", "(VI(j, a, j) - VI(a, j, j))", SE),
+    ("self-energy left out of the second loop line",
+     "xi2 = xi2 + S[b];", "xi2 = xi2;", SE),
 ]
 
 
@@ -64,12 +73,13 @@ def _run_pins(pins, lib=None):
 
 
 def test_pins_pass_on_the_oracle():
-    r = _run_pins(SU2 + WEIGHTS + EGRID)
+    r = _run_pins(SU2 + WEIGHTS + EGRID + SE)
     assert r.returncode == 0, r.stdout[-2000:]
 
 
 @pytest.mark.parametrize("name,old,new,pins", CASES, ids=["crossed-swap", "direct-swap", "no-jacobian", "egrid-no-r", "egrid-edge-energies",
-                              "egrid-uncovered-angles"])
+                              "egrid-uncovered-angles", "se-exchange-legs", "se-no-spin-sum",
+                              "se-second-line"])
 def test_planted_mistake_fails_its_pin(tmp_path, name, old, new, pins):
     lib = _build(tmp_path, old, new)
     r = _run_pins(pins, lib)
