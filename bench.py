@@ -34,6 +34,11 @@ PEAK = {"hbm_GBs": 8000.0, "bf16_TFLOPs": 2500.0, "fp64_TFLOPs": 78.6, "fp32_TFL
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
+def progress(msg: str) -> None:
+    """one line per finished leg on stderr (stdout carries the single JSON line)"""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("k_contract.hip", "k_bubbles.hip"):
@@ -176,12 +181,13 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the CPU-baseline leg (default: every host core)")
     ap.add_argument("--cpu-only", action="store_true", help="run only the CPU-baseline leg")
-    ap.add_argument("--legs", default="split,fp64,batch,batch_fp64,batch64,split_full,fp64_full,iflow,egrid",
+    ap.add_argument("--legs", default="split,fp64,batch,batch_fp64,batch64,split_full,fp64_full,iflow,egrid,se",
                     help="comma list of split, fp64 (one flow), batch, batch_fp64 (16 flows, split / FP64), "
                          "batch64 (64 flows, split), all in symmetric-vertex mode; split_full, fp64_full "
                          "(one flow, every column computed); iflow (the interaction flow of the paper's "
                          "working example, N=32); egrid (one flow at N=96 on the paper's quadrature: "
-                         "1600 energies, adaptive inner rule)")
+                         "1600 energies, adaptive inner rule); se (one flow at N=96 with the self-energy "
+                         "flowing along: every bubble row, every column)")
     ap.add_argument("--batch-flows", type=int, default=16,
                     help="flows in the batched legs (N=96, 512 points/patch, drawn parameters)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
@@ -269,6 +275,7 @@ def main():
         tuned[leg] = ctx.tuning()
         dt, prof, st = timed_flow_steps(frg, torch, ctx, prec, V0, args.steps, args.warmup)
         results[leg] = dict(seconds=dt, prof=prof, state=st)
+        progress(f"leg {leg}: {RHS_PER_STEP * args.steps / dt:.1f} rhs/s")
     ctx.set_vsym(True)
 
     def run_batch(nflows, prec):
@@ -317,6 +324,7 @@ def main():
                            ("batch64", 64, frg.PREC_SPLIT_BF16)):
         if leg in legs:
             batches[leg] = run_batch(nfl, prec)
+            progress(f"leg {leg}: {batches[leg]['rhs'] / batches[leg]['seconds']:.1f} rhs/s")
 
     iflow = None
     if "iflow" in legs:
@@ -360,6 +368,7 @@ def main():
         for prec, nm in ((frg.PREC_SPLIT_BF16, "split"), (frg.PREC_FP64, "fp64")):
             dt, prof, st = timed_flow_steps(frg, torch, ce, prec, Ve, args.steps, args.warmup)
             ms, cnt = prof["bubbles"]
+            progress(f"leg egrid {nm}: {RHS_PER_STEP * args.steps / dt:.1f} rhs/s")
             egrid[nm] = {"rhs_per_s": round(RHS_PER_STEP * args.steps / dt, 3),
                          "kernel_ms_per_rhs": {k: round(v / (PROFILE_STEPS * RHS_PER_STEP), 4)
                                                for k, (v, c) in prof.items()},
@@ -369,9 +378,31 @@ def main():
         del Ve
         torch.cuda.empty_cache()
 
+    se_leg = None
+    if "se" in legs:
+        # the vertex and a self-energy per patch flowing together (N = 96, 512
+        # points per patch): every bubble row and every contraction column
+        cs_ = frg.Context(**p)
+        cs_.set_vsym(False)
+        cs_.set_self_energy(True)
+        Vse = torch.cat([torch.full((N ** 3,), float(p["U"]), dtype=torch.float64, device="cuda"),
+                         torch.zeros(N, dtype=torch.float64, device="cuda")]).contiguous()
+        se_leg = {"workload": "N=96, 512 points/patch, t'=-0.3 mu=-1.2 U=3; vertex and self-energy per patch "
+                              "flowing together (DP5(4) steps from V=U, S=0 at T=1); every bubble row, every "
+                              "contraction column"}
+        for prec, nm in ((frg.PREC_SPLIT_BF16, "split"), (frg.PREC_FP64, "fp64")):
+            dt, prof, st = timed_flow_steps(frg, torch, cs_, prec, Vse, args.steps, args.warmup)
+            progress(f"leg se {nm}: {RHS_PER_STEP * args.steps / dt:.1f} rhs/s")
+            se_leg[nm] = {"rhs_per_s": round(RHS_PER_STEP * args.steps / dt, 3),
+                          "kernel_ms_per_rhs": {k: round(v / (PROFILE_STEPS * RHS_PER_STEP), 4)
+                                                for k, (v, c) in prof.items()}}
+        cs_.close()
+        del Vse
+        torch.cuda.empty_cache()
+
     head = batches.get("batch")
     if head is None and not results:
-        print(json.dumps({"iflow_p1": iflow, "egrid": egrid}))
+        print(json.dumps({"iflow_p1": iflow, "egrid": egrid, "se": se_leg}))
         return
     rate = {leg: RHS_PER_STEP * args.steps / r["seconds"] for leg, r in results.items()}
     rate.update({leg: bb["rhs"] / bb["seconds"] for leg, bb in batches.items()})
@@ -447,6 +478,8 @@ def main():
 
     if egrid is not None:
         out["egrid_e1"] = egrid
+    if se_leg is not None:
+        out["self_energy"] = se_leg
 
     # roofline of the dominant kernel of the value leg (the batched sweep), from the
     # event-timed steps: one launch covers every active flow

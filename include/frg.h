@@ -220,10 +220,27 @@ frg_status frg_rhs(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_pr
  * needs to start at zero (each piece is written in full before it is read).
  * Returns ENOTSUP, before any launch, when the workspace of this context and
  * precision exceeds the scratch (e.g. N = 96 fits in symmetric-vertex mode,
- * not with every column computed in FP64); other errors as frg_rhs. */
+ * not with every column computed in FP64) or with the self-energy on; other
+ * errors as frg_rhs. */
 #define FRG_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
 frg_status frg_rhs_noalloc(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_precision prec,
                            void *stream);
+
+/* Self-energy flowing with the vertex (Sec. 2 names self-energies as the
+ * extension of the four-point flow; the form here is the reading of the design
+ * notes): a static value S_j per patch, stored after the vertex, so that with
+ * the switch on every V and F of frg_rhs, frg_flow_init, frg_flow_step and
+ * frg_flow holds N^3 + N doubles ([V, S]).  Every loop line carries its patch's
+ * S (the fine point's patch and the second line's), and
+ *   dS_j/dT = sum_a D_a [2 V(j,a,j) - V(a,j,j)],
+ *   D_a = sum_{p in a} w_p d/dT n_F((xi_p + S_a)/T)  (at fixed S),
+ * in FP64 in both precisions.  Every bubble row is computed (no C4v row
+ * reduction: S need not be symmetric), unpaired.  Polar grids and single flows
+ * only (ENOTSUP otherwise); EINVAL while the symmetric-vertex mode is on (and
+ * frg_set_vsym(1) is refused while the self-energy is on).  The interaction
+ * flow (frg_rhs_full, frg_iflow*) ignores it.  Initial S = 0 is the caller's. */
+frg_status frg_set_self_energy(frg_ctx ctx, int32_t enable);
+frg_status frg_self_energy(frg_ctx ctx, int32_t *active);
 
 /* Initialise a device flow state (FRG_STATE_LEN doubles) for o: s = ln T0,
  * h = first step, counters zero.  d_V is the initial vertex (unchanged). */

@@ -61,6 +61,10 @@ struct frg_ctx_s {
            *d_trig_pt = nullptr;
     uint8_t *d_bins = nullptr;
     int32_t *d_count = nullptr;   // energy-angle grid: live points per patch
+    // self-energy flowing with the vertex: V and F hold N^3 + N doubles (S after V)
+    bool se_on = false;
+    bool batch_member = false;    // owned by a batch (frg_batch_context)
+    double *d_sigD = nullptr;     // [N] patch sums of the self-energy flow
     int32_t *d_colrow_pp = nullptr, *d_colrow_ph = nullptr;   // (row << 3): every row stored
     // C4v orbit reduction of the bubble rows
     bool sym_avail = false, sym_on = false;
@@ -200,9 +204,11 @@ frg_status ensure_rhs_ws(frg_ctx ctx, frg_precision prec) {
 }
 
 frg_status ensure_flow_ws(frg_ctx ctx) {
-    for (int j = 0; j < 7; ++j) TRY(dalloc(ctx, &ctx->d_k[j], ctx->n3));
-    TRY(dalloc(ctx, &ctx->d_yt, ctx->n3));
-    TRY(dalloc(ctx, &ctx->d_y5, ctx->n3));
+    // N more entries after V: the self-energy's place when it flows along
+    const size_t nfull = static_cast<size_t>(ctx->n3) + static_cast<size_t>(ctx->g.N);
+    for (int j = 0; j < 7; ++j) TRY(dalloc(ctx, &ctx->d_k[j], nfull));
+    TRY(dalloc(ctx, &ctx->d_yt, nfull));
+    TRY(dalloc(ctx, &ctx->d_y5, nfull));
     if (ctx->nst > 0) {
         TRY(dalloc(ctx, &ctx->d_yr, static_cast<size_t>(ctx->nst)));
         TRY(dalloc(ctx, &ctx->d_ytr, static_cast<size_t>(ctx->nst)));
@@ -283,6 +289,7 @@ frg::BubbleArgs bubble_args(frg_ctx ctx, bool fp32, void *bpp, void *bph, const 
     a.rowlist_ph = nullptr;
     a.rpb = ctx->rpb;
     a.count = ctx->d_count;
+    a.sigma = nullptr;
     return a;
 }
 
@@ -649,7 +656,7 @@ const int32_t *col_pos(frg_ctx ctx, int cls) { return tiles_of(ctx, cls).d_cmap;
 // Flows keep their stage vectors reduced while the orbit columns are computed:
 // the rhs is then known at the representative columns only, and every other
 // entry is a copy (a C4v-invariant vertex stays invariant).
-bool red_state(frg_ctx ctx) { return ctx->vsym_on && ctx->kskip_on && ctx->nst > 0; }
+bool red_state(frg_ctx ctx) { return ctx->vsym_on && ctx->kskip_on && ctx->nst > 0 && !ctx->se_on; }
 // K parts of the column set in use
 int ksplit(frg_ctx ctx) { return tiles_of(ctx, 0).kparts; }
 
@@ -697,16 +704,17 @@ RhsWs ctx_ws(frg_ctx ctx) {
 // prep + bubbles into the context's bubble tensor (or caller buffers)
 frg_status run_bubbles(frg_ctx ctx, bool split, double T_host, const double *state, double c,
                        void *bpp, void *bph, hipStream_t s, bool reps_only = false, bool full = false,
-                       const RhsWs *wsp = nullptr) {
+                       const RhsWs *wsp = nullptr, const double *sigma = nullptr) {
     const RhsWs w = wsp ? *wsp : ctx_ws(ctx);
     {
         KTimer kt(ctx, FRG_K_PREP, s);
         frg::launch_point_prep(ctx->d_xi, ctx->d_w, ctx->g.np, T_host, state, c,
-                               split ? nullptr : w.pa64, split ? w.pa32 : nullptr, w.T, s);
+                               split ? nullptr : w.pa64, split ? w.pa32 : nullptr, w.T, s, sigma, ctx->g.nf);
     }
     {
         KTimer kt(ctx, FRG_K_BUBBLES, s);
         frg::BubbleArgs ba = bubble_args(ctx, split, bpp, bph, w.pa64, w.pa32, w.T);
+        ba.sigma = sigma;
         if (reps_only) {
             ba.rowlist = ctx->d_rowlist;
             ba.rowlist_ph = ctx->d_rowlist_ph;
@@ -765,7 +773,9 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     const int N = g.N;
     const size_t NN = static_cast<size_t>(N) * N;
     const int64_t n3 = ctx->n3;
-    const bool sym = ctx->sym_on;
+    // with a self-energy the rows are not C4v images of each other: every row
+    const bool se = ctx->se_on && mode == RHS_DT;
+    const bool sym = ctx->sym_on && !se;
     const int KS = ksplit(ctx);
     const int64_t cs = chan_stride(ctx);
     if (!wsp) TRY(ensure_c(ctx));
@@ -775,7 +785,8 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     void *bph = split ? static_cast<void *>(w.B32 + NN * npp_rows) : static_cast<void *>(w.B64 + NN * npp_rows);
     if (mode != RHS_STORED) {
         if (w.own) ctx->iflow_prec = -1;   // the context's bubble buffer is overwritten
-        TRY(run_bubbles(ctx, split, T_host, state, c, bpp, bph, s, sym, mode == RHS_FULL, &w));
+        TRY(run_bubbles(ctx, split, T_host, state, c, bpp, bph, s, sym, mode == RHS_FULL, &w,
+                        se ? V + n3 : nullptr));
     }
     double *Cpp = w.C, *Cc = w.C + KS * cs, *Cd = w.C + 2 * KS * cs;
     frg::FusedContractArgs a;
@@ -814,6 +825,8 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
         else
             frg::launch_combine(Cs, Cs + cs, Cs + 2 * cs, false, N, 1, col_pos(ctx, 0), col_pos(ctx, 1),
                                 ctx->d_perm8, w.T, scale_by_T, F, s);
+        if (se)   // the self-energy's derivative after F (always FP64)
+            frg::launch_dsigma(ctx->d_xi, ctx->d_w, N, g.nf, V, V + n3, w.T, scale_by_T, ctx->d_sigD, F + n3, s);
     }
     HIPCHK(hipGetLastError());
     return FRG_OK;
@@ -1045,6 +1058,7 @@ static frg_status create_impl(const frg_params *p, int n_batch, frg_ctx *out, co
 frg_status frg_destroy(frg_ctx ctx) {
     if (!ctx) return FRG_OK;
     void *ptrs[] = {ctx->d_bnd, ctx->d_xi, ctx->d_w, ctx->d_trig_row, ctx->d_trig_pt, ctx->d_bins, ctx->d_count,
+                    ctx->d_sigD,
                     ctx->d_colrow_pp, ctx->d_colrow_ph, ctx->d_pa64, ctx->d_T, ctx->d_pa32,
                     ctx->d_B64, ctx->d_B32, ctx->d_perm, ctx->d_ahl, ctx->d_g32, ctx->d_C,
                     ctx->d_yt, ctx->d_y5, ctx->d_partial, ctx->d_state, ctx->d_rowlist, ctx->d_rowlist_ph,
@@ -1183,7 +1197,7 @@ frg_status frg_rhs(frg_ctx ctx, double T, const double *d_V, double *d_F, frg_pr
     if (!(T > 0.0) || !std::isfinite(T)) return fail(FRG_EINVAL, "T must be finite and > 0");
     if (!d_V || !d_F) return fail(FRG_EINVAL, "null V or F");
     if (!aligned8(d_V) || !aligned8(d_F)) return fail(FRG_EINVAL, "V and F must be 8-byte aligned");
-    const size_t bytes = sizeof(double) * static_cast<size_t>(ctx->n3);
+    const size_t bytes = sizeof(double) * (static_cast<size_t>(ctx->n3) + (ctx->se_on ? ctx->g.N : 0));
     if (overlap(d_V, bytes, d_F, bytes)) return fail(FRG_EINVAL, "V and F overlap");
     TRY(ensure_rhs_ws(ctx, prec));
     return run_rhs(ctx, prec == FRG_PREC_SPLIT_BF16, T, nullptr, 0.0, d_V, d_F, 0,
@@ -1200,6 +1214,7 @@ frg_status frg_rhs_noalloc(frg_ctx ctx, double T, const double *d_V, double *d_F
     const size_t bytes = sizeof(double) * static_cast<size_t>(ctx->n3);
     if (overlap(d_V, bytes, d_F, bytes)) return fail(FRG_EINVAL, "V and F overlap");
     if (!ctx->d_scratch) return fail(FRG_EDEVICE, "no static scratch on this device");
+    if (ctx->se_on) return fail(FRG_ENOTSUP, "frg_rhs_noalloc takes no self-energy");
     // the workspace of one rhs, carved from the scratch in 256-byte aligned pieces
     const bool split = prec == FRG_PREC_SPLIT_BF16;
     const auto &g = ctx->g;
@@ -1276,7 +1291,8 @@ frg_status frg_flow_init(frg_ctx ctx, const frg_flow_opts *o, const double *d_V,
     }
     frg::launch_state_init(d_state, s0, h, smin, s);
     if (o->stepper == FRG_RK4) frg::launch_state_set(d_state, 27, o->fixed_steps, s);
-    frg::launch_maxabs_to(ctx->n3, d_V, d_state, 24, ctx->d_partial, red_blocks(ctx->n3), s);
+    const int64_t nflow = ctx->n3 + (ctx->se_on ? ctx->g.N : 0);
+    frg::launch_maxabs_to(nflow, d_V, d_state, 24, ctx->d_partial, red_blocks(nflow), s);
     if (o->stepper == FRG_DP54) {
         // first stage of the first step (later steps reuse the last stage: FSAL)
         TRY(run_rhs(ctx, o->prec == FRG_PREC_SPLIT_BF16, 0.0, d_state, 0.0, d_V, ctx->d_k[0], 1, s, RHS_DT,
@@ -1297,7 +1313,8 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
     // reduced state: the stages combine nst-entry vectors (y gathered from V),
     // and each stage input is expanded into a full vertex for the rhs
     const bool red = red_state(ctx);
-    const int64_t n = red ? ctx->nst : ctx->n3;
+    // the self-energy flows in the same array, after V
+    const int64_t n = red ? ctx->nst : ctx->n3 + (ctx->se_on && !iflow ? ctx->g.N : 0);
     const int N = ctx->g.N;
     double *y = red ? ctx->d_yr : V, *yt = red ? ctx->d_ytr : ctx->d_yt, *y5 = red ? ctx->d_y5r : ctx->d_y5;
     const int32_t *cperm = tiles_of(ctx, 0).d_cperm, *cmap = col_pos(ctx, 0);
@@ -1391,6 +1408,7 @@ static frg_status flow_step_graph(frg_ctx ctx, const frg_flow_opts *o, double *V
                                      static_cast<double>(o->stepper), static_cast<double>(o->prec), o->rtol,
                                      o->atol, o->vmax, static_cast<double>(o->max_steps), iflow ? 1.0 : 0.0,
                                      ctx->sym_on ? 1.0 : 0.0, ctx->vsym_on ? 1.0 : 0.0, ctx->kskip_on ? 1.0 : 0.0,
+                                     ctx->se_on ? 1.0 : 0.0,
                                      P(ctx->d_C), static_cast<double>(ctx->c_elems),
                                      static_cast<double>(ctx->ws_gen)};
     auto &g = ctx->sg;
@@ -1676,11 +1694,32 @@ frg_status frg_symmetry(frg_ctx ctx, int32_t *active, int32_t *rows_computed) {
 
 frg_status frg_set_vsym(frg_ctx ctx, int32_t enable) {
     TRY(check_ctx(ctx));
+    if (enable && ctx->se_on)
+        return fail(FRG_EINVAL, "symmetric-vertex mode with a flowing self-energy is not supported");
     if (enable && !ctx->sym_avail)
         return fail(FRG_ENOTSUP, "symmetric-vertex mode needs an exactly C4v covariant grid (N % 8 == 0)");
     const bool was_red = red_state(ctx);
     ctx->vsym_on = enable != 0;
     return convert_k0(ctx, was_red);
+}
+
+frg_status frg_set_self_energy(frg_ctx ctx, int32_t enable) {
+    TRY(check_ctx(ctx));
+    if (enable && ctx->g.egrid)
+        return fail(FRG_ENOTSUP, "the self-energy runs on polar grids only");
+    if (enable && ctx->vsym_on)
+        return fail(FRG_EINVAL, "switch the symmetric-vertex mode off before the self-energy");
+    if (enable && ctx->batch_member)
+        return fail(FRG_ENOTSUP, "the self-energy runs on single flows only");
+    if (enable && !ctx->d_sigD) TRY(dalloc(ctx, &ctx->d_sigD, static_cast<size_t>(ctx->g.N)));
+    ctx->se_on = enable != 0;
+    return FRG_OK;
+}
+
+frg_status frg_self_energy(frg_ctx ctx, int32_t *active) {
+    TRY(check_ctx(ctx));
+    if (active) *active = ctx->se_on ? 1 : 0;
+    return FRG_OK;
 }
 
 frg_status frg_vsym(frg_ctx ctx, int32_t *active, int32_t *columns) {
@@ -2213,6 +2252,7 @@ frg_status frg_batch_create(const frg_params *params, int32_t n_flows, frg_batch
         frg_ctx c = nullptr;
         frg_status st = create_impl(&params[f], n_flows, &c);
         if (st) { std::string m = g_err; frg_batch_destroy(b); g_err = m; return st; }
+        c->batch_member = true;
         b->ctx.push_back(c);
         b->maxN = std::max(b->maxN, params[f].N);
     }

@@ -50,7 +50,13 @@ void launch_bins_export(const uint8_t *bins, int N, int n_rad, int n_ang, int r0
 // either T_host, or exp(state[s] + c*state[h]) when state != nullptr
 void launch_point_prep(const double *xi, const double *w, int np, double T_host,
                        const double *state, double c_stage, double *pa64, float *pa32,
-                       double *Tout, hipStream_t s);
+                       double *Tout, hipStream_t s, const double *sigma = nullptr, int nf = 1);
+
+// self-energy flow (one value per patch): D[a] = sum_{p in a} w_p d/dT n_F((xi_p + S_a)/T)
+// (one block per patch, fixed-order sums), then
+// dS[j] = scale * sum_a D[a] (2 V(j,a,j) - V(a,j,j)), scale = T when scale_by_T
+void launch_dsigma(const double *xi, const double *w, int N, int nf, const double *V, const double *S,
+                   const double *Tdev, int scale_by_T, double *D, double *dS, hipStream_t s);
 
 struct BubbleArgs {
     int N, nf, np, Tpp, Trows;
@@ -75,6 +81,9 @@ struct BubbleArgs {
     // energy-angle grid: live points of each patch ([N]); the sweep then walks
     // them in segments of kSegPoints (nullptr: polar grid, n_f <= 1024)
     const int32_t *count;
+    // self-energy per patch ([N], nullptr: none): the second line's energy
+    // carries S of its patch (the first line's is in pa); unpaired rows only
+    const double *sigma;
 };
 // full: the bubble L itself (interaction flow) instead of dL/dT
 void launch_bubbles(const BubbleArgs &a, bool fp32, bool full, hipStream_t s);

@@ -253,8 +253,12 @@ size_t bubble_lds_bytes(int N, bool paired) {
 // rowlist_ph): their second lines q - p and p - q have one energy.
 // PF: the next row's table bytes are loaded while a row is evaluated (the
 // batched kernel; the single-flow kernel is held to 128 registers without it)
-template <int P, bool F32, bool FULL, bool PAIRED, bool PF>
+// SE: a self-energy per patch (A.sigma) shifts the second line's energy by
+// its bin's value (unpaired rows, dL/dT only); the table S/2T sits in LDS
+// after the point data.
+template <int P, bool F32, bool FULL, bool PAIRED, bool PF, bool SE = false>
 __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int a_patch, double *smem, int rpb) {
+    static_assert(!SE || (!PAIRED && !FULL), "self-energy rows are unpaired dL/dT rows");
     using PT = typename std::conditional<F32, float, double>::type;
     // The lane's P points (table positions lane*P .. lane*P+P-1, angular
     // neighbours at one radius): in registers for every row (split path with up
@@ -269,6 +273,9 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     double *bins2 = smem + (4 + wave) * N;     // a pair's ph row
     double *pt = smem + (PAIRED ? 8 : 4) * N;  // LDS mode: [7][S] cpx spx cpy spy a c1 c2
     float4 *tay = reinterpret_cast<float4 *>(pt);  // register mode: [S] Taylor coefficients
+    double *sgl = pt + (REG ? 2 * S : 7 * S);      // SE: S_b / 2T of every patch b
+    if constexpr (SE)
+        for (int b = threadIdx.x; b < N; b += kThreads) sgl[b] = A.sigma[b] * A.Tdev[1];
 
     // per point: cos/sin of px, py; a = xi / 2T; c1 = w h(a), c2 = -4 w with
     // w = -w_p / 4T^2 (the weighted divided difference takes these); for the
@@ -445,7 +452,10 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
         auto value = [&](int j, PT &v, PT &v2) {
             const double Y = cqy * pval(2, j) + sy * pval(3, j);
             const double X = cqx * pval(0, j) + sx * pval(1, j);
-            const PT b = static_cast<PT>(fma(X, fma(-g, Y, 1.0), Y - k3));
+            double bd = fma(X, fma(-g, Y, 1.0), Y - k3);
+            // pp rows take the second line's energy with a minus sign
+            if constexpr (SE) bd += (pp ? -1.0 : 1.0) * sgl[bin_of(bw, j)];
+            const PT b = static_cast<PT>(bd);
             const PT a = static_cast<PT>(pval(4, j)), c1 = static_cast<PT>(pval(5, j)),
                      c2 = static_cast<PT>(pval(6, j));
             if constexpr (PAIRED) {
@@ -565,14 +575,17 @@ size_t seg_point_lds_bytes() {
 }
 
 // rows per block of the segmented sweep: the request (a multiple of 4), cut so
-// that the block's LDS stays within 64 KB
+// that the block's LDS stays within 64 KB.  Default (measured at N = 96 with
+// the paper's quadrature, 4..36 rows): 24 for the split path, where more rows
+// amortise the per-segment point set-up until the LDS bins cut the blocks per
+// CU; 8 for FP64, whose points sit in LDS and whose rows cost more registers.
 template <bool F32>
 int seg_rows_per_block(int N, bool paired, int req) {
     const size_t per_row = sizeof(double) * static_cast<size_t>(N) * (paired ? 2 : 1);
     const size_t room = 65536 - seg_point_lds_bytes<F32>();
     int lim = static_cast<int>(room / per_row) / 4 * 4;
     lim = std::max(4, lim);
-    const int r = req > 0 ? req : 16;
+    const int r = req > 0 ? req : (F32 ? 24 : 8);
     return std::min(std::min(r, lim), 256);   // at most 64 rows per wave
 }
 
@@ -801,10 +814,11 @@ void launch_seg(const BubbleArgs &a, hipStream_t s) {
         hipLaunchKernelGGL((bubble_seg_kernel<F32, FULL, false>), grid, dim3(kThreads), lds, s, a, rpb);
 }
 
-template <int P, bool F32, bool FULL, bool PAIRED>
+template <int P, bool F32, bool FULL, bool PAIRED, bool SE = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void bubble_kernel(BubbleArgs A) {
     extern __shared__ double smem[];
-    bubble_body<P, F32, FULL, PAIRED, false>(A, blockIdx.x, blockIdx.y, smem, A.rpb > 0 ? A.rpb : kRowsPerBlock);
+    bubble_body<P, F32, FULL, PAIRED, false, SE>(A, blockIdx.x, blockIdx.y, smem,
+                                                 A.rpb > 0 ? A.rpb : kRowsPerBlock);
 }
 
 // batched: item = (flow, chunk << 8 | patch); skips flows whose state says stop.
@@ -825,6 +839,14 @@ void launch_pp(const BubbleArgs &a, bool fp32, bool full, hipStream_t s) {
     const int rpb = a.rpb > 0 ? a.rpb : kRowsPerBlock;
     dim3 grid((a.nrows + rpb - 1) / rpb, a.N);
     const size_t lds = fp32 ? bubble_lds_bytes<P, true>(a.N, PAIRED) : bubble_lds_bytes<P, false>(a.N, PAIRED);
+    if constexpr (!PAIRED) {
+        if (a.sigma && !full) {   // the host allows a self-energy only with unpaired dL/dT rows
+            const size_t l = lds + sizeof(double) * static_cast<size_t>(a.N);
+            if (fp32) hipLaunchKernelGGL((bubble_kernel<P, true, false, false, true>), grid, dim3(kThreads), l, s, a);
+            else hipLaunchKernelGGL((bubble_kernel<P, false, false, false, true>), grid, dim3(kThreads), l, s, a);
+            return;
+        }
+    }
     if (fp32 && !full)
         hipLaunchKernelGGL((bubble_kernel<P, true, false, PAIRED>), grid, dim3(kThreads), lds, s, a);
     else if (!fp32 && !full)

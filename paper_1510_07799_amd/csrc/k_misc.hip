@@ -132,7 +132,8 @@ __device__ __forceinline__ double sech2_d(double x) {
 __global__ void point_prep_kernel(const double *__restrict__ xi, const double *__restrict__ w,
                                   int np, double T_host, const double *__restrict__ state,
                                   double c_stage, double *__restrict__ pa64,
-                                  float *__restrict__ pa32, double *__restrict__ Tout) {
+                                  float *__restrict__ pa32, double *__restrict__ Tout,
+                                  const double *__restrict__ sigma, int nf) {
     const double T = state ? exp(state[FRG_ST_S] + c_stage * state[FRG_ST_H]) : T_host;
     const double inv2T = 0.5 / T;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -141,7 +142,8 @@ __global__ void point_prep_kernel(const double *__restrict__ xi, const double *_
         Tout[1] = inv2T;
     }
     if (i >= np) return;
-    const double a = xi[i] * inv2T;
+    // with a self-energy the point's energy carries its patch's value
+    const double a = (sigma ? xi[i] + sigma[i / nf] : xi[i]) * inv2T;
     const double ha = a * sech2_d(a);
     const double wf = -w[i] / (4.0 * T * T);
     if (pa64) {
@@ -154,6 +156,48 @@ __global__ void point_prep_kernel(const double *__restrict__ xi, const double *_
         pa32[np + i] = static_cast<float>(ha);
         pa32[2 * np + i] = static_cast<float>(wf);
     }
+}
+
+// Self-energy flow, patch sums: block a adds w_p d/dT n_F(x/T) = w_p x/(4T^2)
+// sech^2(x/2T), x = xi_p + S_a, over the patch's points (thread t takes points
+// t, t + 256, ...; then a fixed tree over the block), so the sum is reproducible.
+__global__ __launch_bounds__(256) void dsigma_patch_kernel(const double *__restrict__ xi,
+                                                           const double *__restrict__ w, int nf,
+                                                           const double *__restrict__ S,
+                                                           const double *__restrict__ Tdev,
+                                                           double *__restrict__ D) {
+    __shared__ double part[256];
+    const int a = blockIdx.x;
+    const double T = Tdev[0];
+    const double sa = S[a];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nf; k += 256) {
+        const int i = a * nf + k;
+        const double x = xi[i] + sa;
+        acc += w[i] * (x / (4.0 * T * T) * sech2_d(x / (2.0 * T)));
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (static_cast<int>(threadIdx.x) < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) D[a] = part[0];
+}
+
+// dS_j = scale * sum_a D_a (2 V(j,a,j) - V(a,j,j)): thread j, a in order
+__global__ __launch_bounds__(256) void dsigma_kernel(int N, const double *__restrict__ V,
+                                                     const double *__restrict__ D,
+                                                     const double *__restrict__ Tdev, int scale_by_T,
+                                                     double *__restrict__ dS) {
+    const int j = threadIdx.x;
+    if (j >= N) return;
+    const size_t NN = static_cast<size_t>(N) * N;
+    double acc = 0.0;
+    for (int a = 0; a < N; ++a)
+        acc += D[a] * (2.0 * V[static_cast<size_t>(j) * NN + static_cast<size_t>(a) * N + j] -
+                       V[static_cast<size_t>(a) * NN + static_cast<size_t>(j) * N + j]);
+    dS[j] = (scale_by_T ? Tdev[0] : 1.0) * acc;
 }
 
 // Contraction operands of V (each N^3; row m = i, contraction index
@@ -1091,9 +1135,15 @@ void launch_sym_check(const uint8_t *bins, const int32_t *orbit, int N, int n_ra
 
 void launch_point_prep(const double *xi, const double *w, int np, double T_host,
                        const double *state, double c_stage, double *pa64, float *pa32,
-                       double *Tout, hipStream_t s) {
+                       double *Tout, hipStream_t s, const double *sigma, int nf) {
     hipLaunchKernelGGL(point_prep_kernel, dim3(blocks_for(np, 256)), dim3(256), 0, s, xi, w, np,
-                       T_host, state, c_stage, pa64, pa32, Tout);
+                       T_host, state, c_stage, pa64, pa32, Tout, sigma, nf);
+}
+
+void launch_dsigma(const double *xi, const double *w, int N, int nf, const double *V, const double *S,
+                   const double *Tdev, int scale_by_T, double *D, double *dS, hipStream_t s) {
+    hipLaunchKernelGGL(dsigma_patch_kernel, dim3(N), dim3(256), 0, s, xi, w, nf, S, Tdev, D);
+    hipLaunchKernelGGL(dsigma_kernel, dim3(1), dim3(256), 0, s, N, V, D, Tdev, scale_by_T, dS);
 }
 
 int layout_blocks(int N) {

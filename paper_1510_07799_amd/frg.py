@@ -83,6 +83,8 @@ SIGNATURES = {
     "frg_host_tables": (C.c_int, [C.POINTER(Params), _DP, _DP, _DP, _DP, _DP, _IP]),
     "frg_create_egrid": (C.c_int, [C.POINTER(Params), C.POINTER(Egrid), C.POINTER(_P)]),
     "frg_points": (C.c_int, [_P, _IP, _IP]),
+    "frg_set_self_energy": (C.c_int, [_P, C.c_int32]),
+    "frg_self_energy": (C.c_int, [_P, _IP]),
     "frg_host_tables_egrid": (C.c_int, [C.POINTER(Params), C.POINTER(Egrid), _IP, _IP, _DP, _DP, _DP, _DP, _DP,
                                         _IP]),
     "frg_bins": (C.c_int, [_P, C.c_int32, _P, _P]),
@@ -371,7 +373,8 @@ class Context:
     def rhs(self, T: float, V, prec=PREC_FP64, out=None):
         torch = self.torch
         N = self.N
-        assert V.dtype == torch.float64 and V.is_cuda and V.is_contiguous() and V.numel() == N ** 3
+        n = N ** 3 + (N if self.self_energy() else 0)
+        assert V.dtype == torch.float64 and V.is_cuda and V.is_contiguous() and V.numel() == n
         F = out if out is not None else torch.empty_like(V)
         _check(lib().frg_rhs(self._h, float(T), _ptr(V), _ptr(F), int(prec), _stream()))
         return F
@@ -390,6 +393,26 @@ class Context:
 
     def flow_step(self, opts: FlowOpts, V, state):
         _check(lib().frg_flow_step(self._h, C.byref(opts), _ptr(V), _ptr(state), _stream()))
+
+    def set_self_energy(self, enable: bool):
+        """frg_set_self_energy: V and F then hold N^3 + N doubles (the self-energy after V)."""
+        _check(lib().frg_set_self_energy(self._h, 1 if enable else 0))
+
+    def self_energy(self) -> bool:
+        a = C.c_int32()
+        _check(lib().frg_self_energy(self._h, C.byref(a)))
+        return bool(a.value)
+
+    def rhs_se(self, T: float, V, S, prec=PREC_FP64):
+        """(dV/dT, dS/dT) with the self-energy on (switched on here if it is not)."""
+        torch = self.torch
+        if not self.self_energy():
+            self.set_self_energy(True)
+        y = torch.cat([V.reshape(-1), S.reshape(-1)]).contiguous()
+        F = torch.empty_like(y)
+        _check(lib().frg_rhs(self._h, float(T), _ptr(y), _ptr(F), int(prec), _stream()))
+        n3 = self.N ** 3
+        return F[:n3].reshape(self.N, self.N, self.N), F[n3:]
 
     def set_symmetry(self, enable: bool):
         _check(lib().frg_set_symmetry(self._h, 1 if enable else 0))

@@ -1,0 +1,151 @@
+"""The self-energy flowing with the vertex on the GPU, against the oracle, through
+the C ABI.
+
+With the switch on, V and F hold N^3 + N doubles (the self-energy S after the
+vertex).  Every loop line carries its patch's S; S flows by the one-loop
+tadpole.  Compared with the oracle's rhs_se / flow_se:
+
+  * the rhs (vertex part and self-energy part) for random V and S at T = 1,
+    0.05 and 1e-3, FP64 and split, at N = 16 and N = 24 (ragged lanes);
+  * S = 0 reproduces the plain rhs bit for bit;
+  * a DP5(4) FP64 flow of (V, S) step for step;
+  * at N = 48, sampled entries against the oracle's brute-force sum;
+  * the switch's rules (energy-angle grids, symmetric-vertex mode, batches,
+    the no-allocation entry point).
+
+Bars (normwise): FP64 vertex part 1e-10, self-energy part 1e-12; split vertex
+part 2e-4, self-energy part 1e-12 (it is FP64 in both precisions).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1510_07799_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1510_07799_amd import frg  # noqa: E402
+
+P16 = dict(t=1.0, tp=-0.25, mu=-0.8, U=2.5, N=16, n_rad=8, n_ang=8)
+P24 = dict(t=1.0, tp=-0.2, mu=-0.6, U=2.0, N=24, n_rad=5, n_ang=5)   # n_f = 25: ragged lanes
+
+
+def nrel(x, ref):
+    x = np.asarray(x, dtype=np.float64)
+    return float(np.abs(x - ref).max() / np.abs(ref).max())
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+@pytest.mark.parametrize("p", [P16, P24], ids=["n16", "n24"])
+def test_rhs_with_self_energy_against_the_oracle(p):
+    N = p["N"]
+    m, g = O.Model(**p), frg.Context(**p)
+    g.set_self_energy(True)
+    rng = np.random.default_rng(601)
+    V = I.random_vertex(N, p["U"], seed=602, amp=0.4, symmetrise=False)
+    S = 0.3 * rng.standard_normal(N)
+    for T in (1.0, 0.05, 1e-3):
+        Fr, dSr = m.rhs_se(T, V, S)
+        for prec, tol in ((frg.PREC_FP64, 1e-10), (frg.PREC_SPLIT_BF16, 2e-4)):
+            F, dS = g.rhs_se(T, dev(V), dev(S), prec)
+            eF, eS = nrel(F.cpu().numpy(), Fr), nrel(dS.cpu().numpy(), dSr)
+            print(f"[se rhs] N={N} T={T} prec={prec}: F {eF:.2e} dS {eS:.2e}", flush=True)
+            assert eF <= tol and eS <= 1e-12
+    g.close()
+
+
+def test_zero_self_energy_is_the_plain_rhs():
+    p = P16
+    N = p["N"]
+    g = frg.Context(**p)
+    g.set_symmetry(False)
+    V = dev(I.random_vertex(N, p["U"], seed=603, amp=0.4, symmetrise=False))
+    for prec in (frg.PREC_FP64, frg.PREC_SPLIT_BF16):
+        F0 = g.rhs(0.1, V, prec).cpu().numpy()
+        F, dS = g.rhs_se(0.1, V, torch.zeros(N, dtype=torch.float64, device="cuda"), prec)
+        assert np.array_equal(F.cpu().numpy(), F0)
+        g.set_self_energy(False)
+    g.close()
+
+
+def test_flow_of_vertex_and_self_energy_step_for_step():
+    p = dict(t=1.0, tp=-0.2, mu=-0.6, U=2.0, N=12, n_rad=6, n_ang=6)
+    N = p["N"]
+    m, g = O.Model(**p), frg.Context(**p)
+    f = dict(stepper="dp54", T0=1.0, T_min=0.02, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.01)
+    Vo, So, ro, logo = m.flow_se(**f)
+    g.set_self_energy(True)
+    y = torch.cat([torch.full((N ** 3,), float(p["U"]), dtype=torch.float64, device="cuda"),
+                   torch.zeros(N, dtype=torch.float64, device="cuda")]).contiguous()
+    rg, logg = g.flow(y, frg.flow_opts(prec=frg.PREC_FP64, **f))
+    yg = y.cpu().numpy()
+    print(f"[se flow] oracle {ro['accepted']}/{ro['rejected']} reason {ro['reason']}; GPU {rg['accepted']}/"
+          f"{rg['rejected']} reason {rg['reason']}; S range {So.min():.4f}..{So.max():.4f}", flush=True)
+    assert (rg["accepted"], rg["rejected"], rg["reason"]) == (ro["accepted"], ro["rejected"], ro["reason"])
+    assert np.allclose(logg[:, 0], logo[:, 0], rtol=0, atol=1e-9)
+    assert nrel(yg[:N ** 3].reshape(N, N, N), Vo) <= 1e-9
+    assert nrel(yg[N ** 3:], So) <= 1e-9
+    assert np.abs(So).max() > 1e-3
+    g.close()
+
+
+def test_sampled_entries_against_brute_force():
+    p = I.model_params("C2")
+    N = p["N"]
+    m, g = O.Model(**p), frg.Context(**p)
+    g.set_self_energy(True)
+    rng = np.random.default_rng(604)
+    V = I.random_vertex(N, p["U"], seed=605, amp=0.3, symmetrise=False)
+    S = 0.2 * rng.standard_normal(N)
+    T = 0.05
+    idx = I.random_entries(N, 48, seed=606)
+    ref = m.rhs_entries_se(T, V, S, idx)
+    dSr = m.dsigma(T, V, S)
+    for prec, tol in ((frg.PREC_FP64, 1e-10), (frg.PREC_SPLIT_BF16, 2e-4)):
+        F, dS = g.rhs_se(T, dev(V), dev(S), prec)
+        got = F.cpu().numpy()[idx[:, 0], idx[:, 1], idx[:, 2]]
+        e = float(np.abs(got - ref).max() / np.abs(ref).max())
+        eS = nrel(dS.cpu().numpy(), dSr)
+        print(f"[se N=48] prec={prec}: sampled F {e:.2e}, dS {eS:.2e}", flush=True)
+        assert e <= tol and eS <= 1e-12
+    g.close()
+
+
+def test_switch_rules():
+    g = frg.Context(**P16)
+    g.set_vsym(True)
+    with pytest.raises(frg.FRGError) as e:
+        g.set_self_energy(True)
+    assert e.value.status == frg.EINVAL
+    g.set_vsym(False)
+    g.set_self_energy(True)
+    with pytest.raises(frg.FRGError) as e:
+        g.set_vsym(True)
+    assert e.value.status == frg.EINVAL
+    y = torch.zeros(16 ** 3 + 16, dtype=torch.float64, device="cuda")
+    F = torch.empty_like(y)
+    st = frg.lib().frg_rhs_noalloc(g.handle, ctypes.c_double(0.1), ctypes.c_void_p(y.data_ptr()),
+                                   ctypes.c_void_p(F.data_ptr()), frg.PREC_FP64, None)
+    assert st == frg.ENOTSUP
+    g.close()
+    ge = frg.Context(t=1.0, tp=-0.2, mu=-0.5, U=2.0, N=12, egrid=dict(n_E=16, max_level=3, rtol=1e-3))
+    with pytest.raises(frg.FRGError) as e:
+        ge.set_self_energy(True)
+    assert e.value.status == frg.ENOTSUP
+    ge.close()
+    b = frg.Batch([P16, P16])
+    try:
+        c = ctypes.c_void_p()
+        assert frg.lib().frg_batch_context(b._h, 0, ctypes.byref(c)) == frg.OK
+        assert frg.lib().frg_set_self_energy(c, 1) == frg.ENOTSUP
+    finally:
+        b.close()
