@@ -387,6 +387,20 @@ frg_status build_orbits(frg_ctx ctx) {
     if (bad != 0) return FRG_OK;   // an exception to exact covariance: keep every row
     TRY(upload(ctx, &ctx->d_rowlist, rowlist.data(), rowlist.size()));
     TRY(upload(ctx, &ctx->d_rowlist_ph, rowlist_ph.data(), rowlist_ph.size()));
+    {   // the paired sweep takes the ph row's patches from the pp row's (+ N/2)
+        int *d_pbad = nullptr;
+        TRY(dalloc(ctx, &d_pbad, 1));
+        HIPCHK(hipMemset(d_pbad, 0, sizeof(int)));
+        frg::launch_pair_check(ctx->d_bins, ctx->d_rowlist, ctx->d_rowlist_ph, static_cast<int>(rowlist.size()),
+                               g.np, N, d_pbad, nullptr);
+        int pbad = -1;
+        hipError_t pe = hipGetLastError();
+        if (pe == hipSuccess) pe = hipMemcpy(&pbad, d_pbad, sizeof(int), hipMemcpyDeviceToHost);
+        hipFree(d_pbad);
+        ctx->ws_bytes -= sizeof(int);
+        if (pe != hipSuccess) return fail(FRG_EDEVICE, std::string("pair check: ") + hipGetErrorString(pe));
+        if (pbad != 0) return FRG_OK;   // keep every row, unpaired
+    }
     ctx->h_rowlist = rowlist;
     ctx->h_rowlist_ph = rowlist_ph;
     TRY(upload(ctx, &ctx->d_colsym_pp, cs_pp.data(), cs_pp.size()));

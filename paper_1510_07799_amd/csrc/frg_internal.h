@@ -88,6 +88,11 @@ struct BubbleArgs {
 // full: the bubble L itself (interaction flow) instead of dL/dT
 void launch_bubbles(const BubbleArgs &a, bool fp32, bool full, hipStream_t s);
 
+// verify the pair identity of the second-line table: at every point the ph row
+// of -q has the pp row q's patch + N/2 (counts the mismatches)
+void launch_pair_check(const uint8_t *bins, const int32_t *rows_pp, const int32_t *rows_ph, int npairs, int np,
+                       int N, int *mismatch, hipStream_t s);
+
 // verify B_{g t}(g a, g b) = B_t(a, b) on the second-line table: counts the
 // (row, point) entries where bins[t'][p'] != g(bins[rep(t')][g^-1 p'])
 void launch_sym_check(const uint8_t *bins, const int32_t *orbit, int N, int n_rad, int n_ang,

@@ -252,7 +252,8 @@ size_t bubble_lds_bytes(int N, bool paired) {
 // output position evaluates a pp row q and the ph row of -q at once (rowlist,
 // rowlist_ph): their second lines q - p and p - q have one energy.
 // PF: the next row's table bytes are loaded while a row is evaluated (the
-// batched kernel; the single-flow kernel is held to 128 registers without it)
+// batched kernel and the paired single-flow kernel, which then stay within 128
+// registers; the unpaired single-flow kernel spills with it)
 // SE: a self-energy per patch (A.sigma) shifts the second line's energy by
 // its bin's value (unpaired rows, dL/dT only); the table S/2T sits in LDS
 // after the point data.
@@ -270,7 +271,10 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     const int N = A.N, nf = A.nf, np = A.np;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *bins = smem + wave * N;
-    double *bins2 = smem + (4 + wave) * N;     // a pair's ph row
+    // a pair's ph row, indexed by the pp row's bin: the ph second line p - q is
+    // the inverse of the pp one q - p, so its patch is the pp bin + N/2 (checked
+    // on the table at context creation); the output pass undoes the shift
+    double *bins2 = smem + (4 + wave) * N;
     double *pt = smem + (PAIRED ? 8 : 4) * N;  // LDS mode: [7][S] cpx spx cpy spy a c1 c2
     float4 *tay = reinterpret_cast<float4 *>(pt);  // register mode: [S] Taylor coefficients
     double *sgl = pt + (REG ? 2 * S : 7 * S);      // SE: S_b / 2T of every patch b
@@ -392,15 +396,11 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     const int my_slot = row0 + wave + 4 * lane;
     const bool my_ok = lane < rows_per_wave && my_slot < A.nrows;
     const int my_r = my_ok ? (A.rowlist ? A.rowlist[my_slot] : my_slot) : 0;
-    const int my_rph = (PAIRED && my_ok) ? A.rowlist_ph[my_slot] : 0;
     // second-line patches of the lane's points, loaded one row ahead so that a
     // row's table bytes are in flight while the previous row is evaluated
     auto row_valid = [&](int it) { return it < rows_per_wave && row0 + wave + 4 * it < A.nrows; };
-    uint32_t nbw[W], nbw2[PAIRED ? W : 1];
-    if (PF && row_valid(0)) {
-        load_bins(__builtin_amdgcn_readlane(my_r, 0), nbw);
-        if constexpr (PAIRED) load_bins(__builtin_amdgcn_readlane(my_rph, 0), nbw2);
-    }
+    uint32_t nbw[W];
+    if (PF && row_valid(0)) load_bins(__builtin_amdgcn_readlane(my_r, 0), nbw);
     for (int it = 0; it < rows_per_wave; ++it) {
         const int rr = wave + 4 * it;
         const int slot_out = row0 + rr;                 // output row position (wave-uniform)
@@ -420,21 +420,13 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
         const double cqx = uniform_f64(k1 * tr[0]), cqy = uniform_f64(k1 * tr[2]);
         const double sx = uniform_f64((pp ? k1 : -k1) * tr[1]);
         const double sy = uniform_f64((pp ? k1 : -k1) * tr[3]);
-        uint32_t bw[W], bw2[PAIRED ? W : 1];
+        uint32_t bw[W];
         if constexpr (PF) {
 #pragma unroll
             for (int w = 0; w < W; ++w) bw[w] = nbw[w];
-            if constexpr (PAIRED) {
-#pragma unroll
-                for (int w = 0; w < W; ++w) bw2[w] = nbw2[w];
-            }
-            if (row_valid(it + 1)) {
-                load_bins(__builtin_amdgcn_readlane(my_r, it + 1), nbw);
-                if constexpr (PAIRED) load_bins(__builtin_amdgcn_readlane(my_rph, it + 1), nbw2);
-            }
+            if (row_valid(it + 1)) load_bins(__builtin_amdgcn_readlane(my_r, it + 1), nbw);
         } else {
             load_bins(r, bw);
-            if constexpr (PAIRED) load_bins(__builtin_amdgcn_readlane(my_rph, it), bw2);
         }
         auto bin_of = [&](const uint32_t *w, int j) -> int { return (w[j >> 2] >> (8 * (j & 3))) & 0xff; };
         // FP32 Taylor coefficients of point j: from LDS in register mode, else made
@@ -484,30 +476,26 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
         // add per run.  Padding points (past n_f) carry zero weight.
         PT acc, acc2 = PT(0);
         value(0, acc, acc2);
-        int bcur = bin_of(bw, 0), bcur2 = PAIRED ? bin_of(bw2, 0) : 0;
+        int bcur = bin_of(bw, 0);
 #pragma unroll
         for (int j = 1; j < P; ++j) {
             PT v, v2 = PT(0);
             value(j, v, v2);
             const int bin = bin_of(bw, j);
-            if (bin != bcur) {
+            if (bin != bcur) {   // a pair's ph run ends with its pp run
                 atomicAdd(&bins[bcur], static_cast<double>(acc));
                 acc = PT(0);
-            }
-            acc += v;
-            bcur = bin;
-            if constexpr (PAIRED) {
-                const int bin2 = bin_of(bw2, j);
-                if (bin2 != bcur2) {
-                    atomicAdd(&bins2[bcur2], static_cast<double>(acc2));
+                if constexpr (PAIRED) {
+                    atomicAdd(&bins2[bcur], static_cast<double>(acc2));
                     acc2 = PT(0);
                 }
-                acc2 += v2;
-                bcur2 = bin2;
             }
+            acc += v;
+            if constexpr (PAIRED) acc2 += v2;
+            bcur = bin;
         }
         atomicAdd(&bins[bcur], static_cast<double>(acc));
-        if constexpr (PAIRED) atomicAdd(&bins2[bcur2], static_cast<double>(acc2));
+        if constexpr (PAIRED) atomicAdd(&bins2[bcur], static_cast<double>(acc2));
         wave_sync();
         // outputs: a pair writes its pp row and its ph row at the same position.
         // A lane takes bins b and b + 64 of both rows at once (all reads issued
@@ -526,19 +514,28 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             outp[k] = pp_out ? A.Bpp : A.Bph;
             src[k] = k == 0 ? bins : bins2;
         }
+        const int H = N >> 1;
         for (int b0 = lane; b0 < N; b0 += 128) {
             const int b1 = b0 + 64;
             const bool has1 = b1 < N;
+            // ph output bin b sits at pp-bin position b + N/2 (an involution, so
+            // every position is read and cleared by exactly one lane)
+            int i0[NO], i1[NO];
+#pragma unroll
+            for (int k = 0; k < NO; ++k) {
+                i0[k] = k == 0 ? b0 : (b0 + H >= N ? b0 + H - N : b0 + H);
+                i1[k] = k == 0 ? b1 : (b1 + H >= N ? b1 + H - N : b1 + H);
+            }
             double v[NO][2];
 #pragma unroll
             for (int k = 0; k < NO; ++k) {
-                v[k][0] = src[k][b0];
-                v[k][1] = has1 ? src[k][b1] : 0.0;
+                v[k][0] = src[k][i0[k]];
+                v[k][1] = has1 ? src[k][i1[k]] : 0.0;
             }
 #pragma unroll
             for (int k = 0; k < NO; ++k) {   // read and cleared by the same lane
-                src[k][b0] = 0.0;
-                if (has1) src[k][b1] = 0.0;
+                src[k][i0[k]] = 0.0;
+                if (has1) src[k][i1[k]] = 0.0;
             }
 #pragma unroll
             for (int k = 0; k < NO; ++k) {
@@ -643,7 +640,6 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
     const int my_slot = row0 + wave + 4 * lane;
     const bool my_ok = lane < rpw && my_slot < A.nrows;
     const int my_r = my_ok ? (A.rowlist ? A.rowlist[my_slot] : my_slot) : 0;
-    const int my_rph = (PAIRED && my_ok) ? A.rowlist_ph[my_slot] : 0;
     int nrow_w = 0;   // rows this wave evaluates
     while (nrow_w < rpw && row0 + wave + 4 * nrow_w < A.nrows) ++nrow_w;
 
@@ -719,9 +715,8 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
             const double cqx = uniform_f64(k1 * tr[0]), cqy = uniform_f64(k1 * tr[2]);
             const double sx = uniform_f64((pp ? k1 : -k1) * tr[1]);
             const double sy = uniform_f64((pp ? k1 : -k1) * tr[3]);
-            uint32_t bw[2], bw2[2];
+            uint32_t bw[2];
             load_bins(r, bw);
-            if constexpr (PAIRED) load_bins(__builtin_amdgcn_readlane(my_rph, it), bw2);
             auto value = [&](int j, PT &v, PT &v2) {
                 const double Y = cqy * pval(2, j) + sy * pval(3, j);
                 const double X = cqx * pval(0, j) + sx * pval(1, j);
@@ -753,30 +748,26 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
             double *rb2 = bins2 + static_cast<size_t>(it) * N;
             PT acc, acc2 = PT(0);
             value(0, acc, acc2);
-            int bcur = bin_of(bw, 0), bcur2 = PAIRED ? bin_of(bw2, 0) : 0;
+            int bcur = bin_of(bw, 0);
 #pragma unroll
             for (int j = 1; j < P; ++j) {
                 PT v, v2 = PT(0);
                 value(j, v, v2);
                 const int bin = bin_of(bw, j);
-                if (bin != bcur) {
+                if (bin != bcur) {   // a pair's ph run ends with its pp run
                     atomicAdd(&rb[bcur], static_cast<double>(acc));
                     acc = PT(0);
-                }
-                acc += v;
-                bcur = bin;
-                if constexpr (PAIRED) {
-                    const int bin2 = bin_of(bw2, j);
-                    if (bin2 != bcur2) {
-                        atomicAdd(&rb2[bcur2], static_cast<double>(acc2));
+                    if constexpr (PAIRED) {
+                        atomicAdd(&rb2[bcur], static_cast<double>(acc2));
                         acc2 = PT(0);
                     }
-                    acc2 += v2;
-                    bcur2 = bin2;
                 }
+                acc += v;
+                if constexpr (PAIRED) acc2 += v2;
+                bcur = bin;
             }
             atomicAdd(&rb[bcur], static_cast<double>(acc));
-            if constexpr (PAIRED) atomicAdd(&rb2[bcur2], static_cast<double>(acc2));
+            if constexpr (PAIRED) atomicAdd(&rb2[bcur], static_cast<double>(acc2));
         }
     }
     wave_sync();
@@ -794,9 +785,11 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
             void *outp = pp_out ? A.Bpp : A.Bph;
             if (!outp) continue;
             const double *src = (k == 0 ? bins : bins2) + static_cast<size_t>(it) * N;
+            const int sh = k == 0 ? 0 : N >> 1;   // ph bins sit at the pp bin + N/2
             for (int b = lane; b < N; b += 64) {
-                if (F32) gst(static_cast<float *>(outp))[base + b] = static_cast<float>(src[b]);
-                else gst(static_cast<double *>(outp))[base + b] = src[b];
+                const int i = b + sh >= N ? b + sh - N : b + sh;
+                if (F32) gst(static_cast<float *>(outp))[base + b] = static_cast<float>(src[i]);
+                else gst(static_cast<double *>(outp))[base + b] = src[i];
             }
         }
     }
@@ -817,8 +810,8 @@ void launch_seg(const BubbleArgs &a, hipStream_t s) {
 template <int P, bool F32, bool FULL, bool PAIRED, bool SE = false>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void bubble_kernel(BubbleArgs A) {
     extern __shared__ double smem[];
-    bubble_body<P, F32, FULL, PAIRED, false, SE>(A, blockIdx.x, blockIdx.y, smem,
-                                                 A.rpb > 0 ? A.rpb : kRowsPerBlock);
+    bubble_body<P, F32, FULL, PAIRED, PAIRED, SE>(A, blockIdx.x, blockIdx.y, smem,
+                                                  A.rpb > 0 ? A.rpb : kRowsPerBlock);
 }
 
 // batched: item = (flow, chunk << 8 | patch); skips flows whose state says stop.

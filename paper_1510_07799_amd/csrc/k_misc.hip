@@ -123,6 +123,24 @@ __global__ void sym_check_kernel(const uint8_t *__restrict__ bins, const int32_t
     if (bad) atomicAdd(mismatch, bad);
 }
 
+// pairs of bubble rows (pp row q, ph row of -q): the ph second line p - q is
+// the inverse of the pp one q - p, so its patch must be the pp patch + N/2 at
+// every point; counts the (pair, point) entries where the table says otherwise
+__global__ void pair_check_kernel(const uint8_t *__restrict__ bins, const int32_t *__restrict__ rows_pp,
+                                  const int32_t *__restrict__ rows_ph, int npairs, int np, int N,
+                                  int *mismatch) {
+    const int ip = blockIdx.x * blockDim.x + threadIdx.x;
+    if (ip >= np) return;
+    const int H = N >> 1;
+    int bad = 0;
+    for (int i = blockIdx.y; i < npairs; i += gridDim.y) {
+        const int b = bins[static_cast<size_t>(rows_pp[i]) * np + ip];
+        const int b2 = bins[static_cast<size_t>(rows_ph[i]) * np + ip];
+        if (b2 != (b + H >= N ? b + H - N : b + H)) ++bad;
+    }
+    if (bad) atomicAdd(mismatch, bad);
+}
+
 __device__ __forceinline__ double sech2_d(double x) {
     const double e = exp(-2.0 * fabs(x));
     const double d = 1.0 + e;
@@ -1131,6 +1149,13 @@ void launch_sym_check(const uint8_t *bins, const int32_t *orbit, int N, int n_ra
     dim3 grid(blocks_for(np, 256), Trows < 4096 ? Trows : 4096);
     hipLaunchKernelGGL(sym_check_kernel, grid, dim3(256), 0, s, bins, orbit, N, n_rad, n_ang, Trows, rev,
                        mismatch);
+}
+
+void launch_pair_check(const uint8_t *bins, const int32_t *rows_pp, const int32_t *rows_ph, int npairs, int np,
+                       int N, int *mismatch, hipStream_t s) {
+    if (npairs <= 0) return;
+    dim3 grid(blocks_for(np, 256), npairs < 4096 ? npairs : 4096);
+    hipLaunchKernelGGL(pair_check_kernel, grid, dim3(256), 0, s, bins, rows_pp, rows_ph, npairs, np, N, mismatch);
 }
 
 void launch_point_prep(const double *xi, const double *w, int np, double T_host,
