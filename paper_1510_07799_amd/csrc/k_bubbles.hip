@@ -235,8 +235,8 @@ __device__ __forceinline__ const CONST_AS T *cld(const T *p) {
     return reinterpret_cast<const CONST_AS T *>(reinterpret_cast<uintptr_t>(p));
 }
 
-// Bins of wave w at smem[w*N ..) (a pair's second row's at smem[(4 + w)*N ..));
-// in LDS mode the point data follow them.
+// Bins of wave w at smem[w*N ..) (a pair's two rows interleaved at
+// smem[2*w*N ..)); in LDS mode the point data follow them.
 template <int P, bool F32>
 constexpr bool points_in_registers() { return F32 && P <= 8; }
 
@@ -270,11 +270,13 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
     constexpr int S = P * 64;
     const int N = A.N, nf = A.nf, np = A.np;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double *bins = smem + wave * N;
+    // a pair's two rows interleaved (pp at 2b, ph at 2b + 1): one address per run
+    constexpr int BS = PAIRED ? 2 : 1;
+    double *bins = smem + wave * N * BS;
     // a pair's ph row, indexed by the pp row's bin: the ph second line p - q is
     // the inverse of the pp one q - p, so its patch is the pp bin + N/2 (checked
     // on the table at context creation); the output pass undoes the shift
-    double *bins2 = smem + (4 + wave) * N;
+    double *bins2 = bins + 1;
     double *pt = smem + (PAIRED ? 8 : 4) * N;  // LDS mode: [7][S] cpx spx cpy spy a c1 c2
     float4 *tay = reinterpret_cast<float4 *>(pt);  // register mode: [S] Taylor coefficients
     double *sgl = pt + (REG ? 2 * S : 7 * S);      // SE: S_b / 2T of every patch b
@@ -387,9 +389,9 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
 
     const int row0 = chunk * rpb;
     // the wave's bins start at zero; each row's output pass clears them again
-    for (int b = lane; b < N; b += 64) bins[b] = 0.0;
+    for (int b = lane; b < N; b += 64) bins[BS * b] = 0.0;
     if constexpr (PAIRED)
-        for (int b = lane; b < N; b += 64) bins2[b] = 0.0;
+        for (int b = lane; b < N; b += 64) bins2[BS * b] = 0.0;
     // the wave's 16 transfer rows (and a pair's second rows), one per lane, read
     // once: each row then takes them with a lane read instead of a global load
     const int rows_per_wave = rpb >> 2;   // at most 64: one row index per lane
@@ -483,10 +485,10 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             value(j, v, v2);
             const int bin = bin_of(bw, j);
             if (bin != bcur) {   // a pair's ph run ends with its pp run
-                atomicAdd(&bins[bcur], static_cast<double>(acc));
+                atomicAdd(&bins[BS * bcur], static_cast<double>(acc));
                 acc = PT(0);
                 if constexpr (PAIRED) {
-                    atomicAdd(&bins2[bcur], static_cast<double>(acc2));
+                    atomicAdd(&bins2[BS * bcur], static_cast<double>(acc2));
                     acc2 = PT(0);
                 }
             }
@@ -494,8 +496,8 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             if constexpr (PAIRED) acc2 += v2;
             bcur = bin;
         }
-        atomicAdd(&bins[bcur], static_cast<double>(acc));
-        if constexpr (PAIRED) atomicAdd(&bins2[bcur], static_cast<double>(acc2));
+        atomicAdd(&bins[BS * bcur], static_cast<double>(acc));
+        if constexpr (PAIRED) atomicAdd(&bins2[BS * bcur], static_cast<double>(acc2));
         wave_sync();
         // outputs: a pair writes its pp row and its ph row at the same position.
         // A lane takes bins b and b + 64 of both rows at once (all reads issued
@@ -529,13 +531,13 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             double v[NO][2];
 #pragma unroll
             for (int k = 0; k < NO; ++k) {
-                v[k][0] = src[k][i0[k]];
-                v[k][1] = has1 ? src[k][i1[k]] : 0.0;
+                v[k][0] = src[k][BS * i0[k]];
+                v[k][1] = has1 ? src[k][BS * i1[k]] : 0.0;
             }
 #pragma unroll
             for (int k = 0; k < NO; ++k) {   // read and cleared by the same lane
-                src[k][i0[k]] = 0.0;
-                if (has1) src[k][i1[k]] = 0.0;
+                src[k][BS * i0[k]] = 0.0;
+                if (has1) src[k][BS * i1[k]] = 0.0;
             }
 #pragma unroll
             for (int k = 0; k < NO; ++k) {

@@ -175,3 +175,34 @@ def test_workload_size_sampled_against_brute_force():
                 assert e <= tol
     finally:
         g.close()
+
+
+def test_captured_steps_equal_eager_steps():
+    """Flow steps on the energy-angle grid replayed from the captured graph equal
+    the eager launches bit for bit."""
+    import os
+    p = E24
+    o = frg.flow_opts("dp54", frg.PREC_SPLIT_BF16, T0=1.0, T_min=0.1, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.02)
+
+    def run(graph):
+        if graph:
+            os.environ.pop("FRG_NO_GRAPH", None)
+        else:
+            os.environ["FRG_NO_GRAPH"] = "1"
+        g = frg.Context(**p)
+        try:
+            g.set_vsym(True)
+            V = torch.full((p["N"],) * 3, p["U"], dtype=torch.float64, device="cuda")
+            st = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+            g.flow_init(o, V, st)
+            for _ in range(4):
+                g.flow_step(o, V, st)
+            torch.cuda.synchronize()
+            return V.cpu().numpy(), st.cpu().numpy()
+        finally:
+            os.environ.pop("FRG_NO_GRAPH", None)
+            g.close()
+
+    (Ve, se), (Vg, sg) = run(False), run(True)
+    assert np.array_equal(Ve, Vg)
+    assert np.array_equal(se, sg, equal_nan=True)

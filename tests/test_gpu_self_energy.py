@@ -149,3 +149,37 @@ def test_switch_rules():
         assert frg.lib().frg_set_self_energy(c, 1) == frg.ENOTSUP
     finally:
         b.close()
+
+
+def test_captured_steps_equal_eager_steps_with_self_energy():
+    """A flow of (V, S) replayed from the captured step graph equals the eager
+    launches bit for bit (the graph key includes the self-energy switch)."""
+    import os
+    p = P16
+    N = p["N"]
+    o = frg.flow_opts("dp54", frg.PREC_SPLIT_BF16, T0=1.0, T_min=0.1, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.02)
+
+    def run(graph):
+        if graph:
+            os.environ.pop("FRG_NO_GRAPH", None)
+        else:
+            os.environ["FRG_NO_GRAPH"] = "1"
+        g = frg.Context(**p)
+        try:
+            g.set_self_energy(True)
+            y = torch.cat([torch.full((N ** 3,), float(p["U"]), dtype=torch.float64, device="cuda"),
+                           torch.zeros(N, dtype=torch.float64, device="cuda")]).contiguous()
+            st = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+            g.flow_init(o, y, st)
+            for _ in range(4):
+                g.flow_step(o, y, st)
+            torch.cuda.synchronize()
+            return y.cpu().numpy(), st.cpu().numpy()
+        finally:
+            os.environ.pop("FRG_NO_GRAPH", None)
+            g.close()
+
+    (ye, se), (yg, sg) = run(False), run(True)
+    assert np.array_equal(ye, yg)
+    assert np.array_equal(se, sg, equal_nan=True)
+    assert np.abs(ye[N ** 3:]).max() > 0.0
