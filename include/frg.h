@@ -235,8 +235,8 @@ frg_status frg_rhs_noalloc(frg_ctx ctx, double T, const double *d_V, double *d_F
  *   dS_j/dT = sum_a D_a [2 V(j,a,j) - V(a,j,j)],
  *   D_a = sum_{p in a} w_p d/dT n_F((xi_p + S_a)/T)  (at fixed S),
  * in FP64 in both precisions.  Every bubble row is computed (no C4v row
- * reduction: S need not be symmetric), unpaired.  Polar grids and single flows
- * only (ENOTSUP otherwise); EINVAL while the symmetric-vertex mode is on (and
+ * reduction: S need not be symmetric), unpaired.  Polar and energy-angle grids,
+ * single flows only (ENOTSUP in a batch); EINVAL while the symmetric-vertex mode is on (and
  * frg_set_vsym(1) is refused while the self-energy is on).  The interaction
  * flow (frg_rhs_full, frg_iflow*) ignores it.  Initial S = 0 is the caller's. */
 frg_status frg_set_self_energy(frg_ctx ctx, int32_t enable);

@@ -1719,8 +1719,6 @@ frg_status frg_set_vsym(frg_ctx ctx, int32_t enable) {
 
 frg_status frg_set_self_energy(frg_ctx ctx, int32_t enable) {
     TRY(check_ctx(ctx));
-    if (enable && ctx->g.egrid)
-        return fail(FRG_ENOTSUP, "the self-energy runs on polar grids only");
     if (enable && ctx->vsym_on)
         return fail(FRG_EINVAL, "switch the symmetric-vertex mode off before the self-energy");
     if (enable && ctx->batch_member)

@@ -581,7 +581,8 @@ size_t seg_point_lds_bytes() {
 template <bool F32>
 int seg_rows_per_block(int N, bool paired, int req) {
     const size_t per_row = sizeof(double) * static_cast<size_t>(N) * (paired ? 2 : 1);
-    const size_t room = 65536 - seg_point_lds_bytes<F32>();
+    // the points and a self-energy table (N doubles) take their part first
+    const size_t room = 65536 - seg_point_lds_bytes<F32>() - sizeof(double) * static_cast<size_t>(N);
     int lim = static_cast<int>(room / per_row) / 4 * 4;
     lim = std::max(4, lim);
     const int r = req > 0 ? req : (F32 ? 24 : 8);
@@ -589,12 +590,16 @@ int seg_rows_per_block(int N, bool paired, int req) {
 }
 
 template <bool F32>
-size_t seg_lds_bytes(int N, bool paired, int rpb) {
-    return sizeof(double) * static_cast<size_t>(rpb) * N * (paired ? 2 : 1) + seg_point_lds_bytes<F32>();
+size_t seg_lds_bytes(int N, bool paired, int rpb, bool se) {
+    return sizeof(double) * static_cast<size_t>(rpb) * N * (paired ? 2 : 1) + seg_point_lds_bytes<F32>() +
+           (se ? sizeof(double) * static_cast<size_t>(N) : 0);
 }
 
-template <bool F32, bool FULL, bool PAIRED>
+// SE: the second line's energy carries its bin's self-energy (A.sigma, as S/2T
+// in LDS after the point data); unpaired dL/dT rows only
+template <bool F32, bool FULL, bool PAIRED, bool SE = false>
 __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int rpb) {
+    static_assert(!SE || (!PAIRED && !FULL), "self-energy rows are unpaired dL/dT rows");
     extern __shared__ double smem[];
     using PT = typename std::conditional<F32, float, double>::type;
     constexpr int P = kSegP;
@@ -605,10 +610,13 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
     const int chunk = blockIdx.x, a_patch = blockIdx.y;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int rpw = rpb >> 2;   // rows per wave
-    double *bins = smem + static_cast<size_t>(wave) * rpw * N;               // [rpw][N]
-    double *bins2 = smem + static_cast<size_t>(4 + wave) * rpw * N;          // pairs' ph rows
+    constexpr int BS = PAIRED ? 2 : 1;   // a pair's rows interleaved: pp at 2b, ph (at the pp bin) at 2b + 1
+    double *bins = smem + static_cast<size_t>(wave) * rpw * N * BS;          // [rpw][N][BS]
     double *pt = smem + static_cast<size_t>(PAIRED ? 8 : 4) * rpw * N;       // LDS mode: [7][S]
     float4 *tay = reinterpret_cast<float4 *>(pt);                            // register mode: [S]
+    double *sgl = pt + (REG ? 2 * S : 7 * S);                                // SE: S_b / 2T
+    if constexpr (SE)
+        for (int b = threadIdx.x; b < N; b += kThreads) sgl[b] = A.sigma[b] * A.Tdev[1];
 
     const double Tcur = A.Tdev[0];
     const GLOBAL_AS float *pa32 = gld(A.pa32);
@@ -635,9 +643,7 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
     const size_t NN = static_cast<size_t>(N) * N;
 
     const int row0 = chunk * rpb;
-    for (int k = lane; k < rpw * N; k += 64) bins[k] = 0.0;
-    if constexpr (PAIRED)
-        for (int k = lane; k < rpw * N; k += 64) bins2[k] = 0.0;
+    for (int k = lane; k < rpw * N * BS; k += 64) bins[k] = 0.0;
     // the wave's rows, one per lane (at most 64 rows per wave)
     const int my_slot = row0 + wave + 4 * lane;
     const bool my_ok = lane < rpw && my_slot < A.nrows;
@@ -722,7 +728,10 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
             auto value = [&](int j, PT &v, PT &v2) {
                 const double Y = cqy * pval(2, j) + sy * pval(3, j);
                 const double X = cqx * pval(0, j) + sx * pval(1, j);
-                const PT b = static_cast<PT>(fma(X, fma(-g, Y, 1.0), Y - k3));
+                double bd = fma(X, fma(-g, Y, 1.0), Y - k3);
+                // pp rows take the second line's energy with a minus sign
+                if constexpr (SE) bd += (pp ? -1.0 : 1.0) * sgl[bin_of(bw, j)];
+                const PT b = static_cast<PT>(bd);
                 const PT a = static_cast<PT>(pval(4, j)), c1 = static_cast<PT>(pval(5, j)),
                          c2 = static_cast<PT>(pval(6, j));
                 if constexpr (PAIRED) {
@@ -746,8 +755,8 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
                     }
                 }
             };
-            double *rb = bins + static_cast<size_t>(it) * N;
-            double *rb2 = bins2 + static_cast<size_t>(it) * N;
+            double *rb = bins + static_cast<size_t>(it) * N * BS;
+            double *rb2 = rb + 1;
             PT acc, acc2 = PT(0);
             value(0, acc, acc2);
             int bcur = bin_of(bw, 0);
@@ -757,10 +766,10 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
                 value(j, v, v2);
                 const int bin = bin_of(bw, j);
                 if (bin != bcur) {   // a pair's ph run ends with its pp run
-                    atomicAdd(&rb[bcur], static_cast<double>(acc));
+                    atomicAdd(&rb[BS * bcur], static_cast<double>(acc));
                     acc = PT(0);
                     if constexpr (PAIRED) {
-                        atomicAdd(&rb2[bcur], static_cast<double>(acc2));
+                        atomicAdd(&rb2[BS * bcur], static_cast<double>(acc2));
                         acc2 = PT(0);
                     }
                 }
@@ -768,8 +777,8 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
                 if constexpr (PAIRED) acc2 += v2;
                 bcur = bin;
             }
-            atomicAdd(&rb[bcur], static_cast<double>(acc));
-            if constexpr (PAIRED) atomicAdd(&rb2[bcur], static_cast<double>(acc2));
+            atomicAdd(&rb[BS * bcur], static_cast<double>(acc));
+            if constexpr (PAIRED) atomicAdd(&rb2[BS * bcur], static_cast<double>(acc2));
         }
     }
     wave_sync();
@@ -786,12 +795,12 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
             const size_t base = pos * NN + static_cast<size_t>(a_patch) * N;
             void *outp = pp_out ? A.Bpp : A.Bph;
             if (!outp) continue;
-            const double *src = (k == 0 ? bins : bins2) + static_cast<size_t>(it) * N;
+            const double *src = bins + static_cast<size_t>(it) * N * BS + k;
             const int sh = k == 0 ? 0 : N >> 1;   // ph bins sit at the pp bin + N/2
             for (int b = lane; b < N; b += 64) {
                 const int i = b + sh >= N ? b + sh - N : b + sh;
-                if (F32) gst(static_cast<float *>(outp))[base + b] = static_cast<float>(src[i]);
-                else gst(static_cast<double *>(outp))[base + b] = src[i];
+                if (F32) gst(static_cast<float *>(outp))[base + b] = static_cast<float>(src[BS * i]);
+                else gst(static_cast<double *>(outp))[base + b] = src[BS * i];
             }
         }
     }
@@ -802,10 +811,14 @@ void launch_seg(const BubbleArgs &a, hipStream_t s) {
     const bool paired = a.rowlist_ph != nullptr;
     const int rpb = seg_rows_per_block<F32>(a.N, paired, a.rpb);
     dim3 grid((a.nrows + rpb - 1) / rpb, a.N);
-    const size_t lds = seg_lds_bytes<F32>(a.N, paired, rpb);
+    const bool se = a.sigma != nullptr && !paired && !FULL;   // the host pairs no rows with a self-energy
+    const size_t lds = seg_lds_bytes<F32>(a.N, paired, rpb, se);
     if (paired)
         hipLaunchKernelGGL((bubble_seg_kernel<F32, FULL, true>), grid, dim3(kThreads), lds, s, a, rpb);
-    else
+    else if (se) {
+        if constexpr (!FULL)
+            hipLaunchKernelGGL((bubble_seg_kernel<F32, false, false, true>), grid, dim3(kThreads), lds, s, a, rpb);
+    } else
         hipLaunchKernelGGL((bubble_seg_kernel<F32, FULL, false>), grid, dim3(kThreads), lds, s, a, rpb);
 }
 

@@ -10,8 +10,10 @@ tadpole.  Compared with the oracle's rhs_se / flow_se:
   * S = 0 reproduces the plain rhs bit for bit;
   * a DP5(4) FP64 flow of (V, S) step for step;
   * at N = 48, sampled entries against the oracle's brute-force sum;
-  * the switch's rules (energy-angle grids, symmetric-vertex mode, batches,
-    the no-allocation entry point).
+  * on the energy-angle grid (the paper's quadrature), the rhs against the
+    oracle's on the same grid;
+  * the switch's rules (symmetric-vertex mode, batches, the no-allocation entry
+    point).
 
 Bars (normwise): FP64 vertex part 1e-10, self-energy part 1e-12; split vertex
 part 2e-4, self-energy part 1e-12 (it is FP64 in both precisions).
@@ -120,6 +122,24 @@ def test_sampled_entries_against_brute_force():
     g.close()
 
 
+def test_self_energy_on_the_energy_angle_grid():
+    p = dict(t=1.0, tp=-0.3, mu=-1.2, U=3.0, N=24, n_rad=1, n_ang=1, egrid=dict(n_E=32, max_level=4, rtol=1e-4))
+    N = p["N"]
+    m, g = O.Model(**p), frg.Context(**p)
+    g.set_self_energy(True)
+    rng = np.random.default_rng(607)
+    V = I.random_vertex(N, p["U"], seed=608, amp=0.4, symmetrise=False)
+    S = 0.3 * rng.standard_normal(N)
+    for T in (0.5, 0.02):
+        Fr, dSr = m.rhs_se(T, V, S)
+        for prec, tol in ((frg.PREC_FP64, 1e-10), (frg.PREC_SPLIT_BF16, 2e-4)):
+            F, dS = g.rhs_se(T, dev(V), dev(S), prec)
+            eF, eS = nrel(F.cpu().numpy(), Fr), nrel(dS.cpu().numpy(), dSr)
+            print(f"[se egrid] T={T} prec={prec}: F {eF:.2e} dS {eS:.2e}", flush=True)
+            assert eF <= tol and eS <= 1e-12
+    g.close()
+
+
 def test_switch_rules():
     g = frg.Context(**P16)
     g.set_vsym(True)
@@ -137,11 +157,6 @@ def test_switch_rules():
                                    ctypes.c_void_p(F.data_ptr()), frg.PREC_FP64, None)
     assert st == frg.ENOTSUP
     g.close()
-    ge = frg.Context(t=1.0, tp=-0.2, mu=-0.5, U=2.0, N=12, egrid=dict(n_E=16, max_level=3, rtol=1e-3))
-    with pytest.raises(frg.FRGError) as e:
-        ge.set_self_energy(True)
-    assert e.value.status == frg.ENOTSUP
-    ge.close()
     b = frg.Batch([P16, P16])
     try:
         c = ctypes.c_void_p()
