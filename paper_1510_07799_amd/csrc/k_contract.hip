@@ -362,6 +362,10 @@ __device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 
 // products in one block; all three read the same ph bubble row of a column,
 // so its window (and the index work around it) is loaded once for three
 // Z tiles.  Product p feeds accumulator 0 (phc) for p = 0, else 1 (phd).
+// The phd sum (-2 V(a,j2,b) + V(j2,a,b)) V(j1,b,j3) + V(a,j2,b) V(j1,b,a) is
+// regrouped as V(j2,a,b) V(j1,b,j3) + V(a,j2,b) (V(j1,b,a) - 2 V(j1,b,j3)): its
+// first operand is then the phc operand V(m,a,b), so the block streams two A
+// operands for three products (operand aop(p): 0 for p = 0, 1; 1 for p = 2).
 template <int KIND, int BM, bool FAST>
 __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Work &w, uint16_t *smem) {
     constexpr bool PH = KIND == TERM_PH;
@@ -369,13 +373,14 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     constexpr int BK = 32;
     constexpr int ZK = BK / 4;    // k per thread in the Z loader
     constexpr int LD = BK;        // bf16 row pitch; chunks swizzled by swz()
-    constexpr int NP = PH ? 3 : 1;
+    constexpr int NP = PH ? 3 : 1;     // products (Z tiles)
+    constexpr int NA = PH ? 2 : 1;     // A operands
     constexpr int NACC = PH ? 2 : 1;
     constexpr int G = BK / kContractChunk;
     constexpr int NCH = G * BM;                         // 16-byte A pieces (one chunk of one row)
     constexpr int ACH = (NCH + kThreads - 1) / kThreads;
-    uint16_t *sA = smem;                           // [NP][2][BM][LD]
-    uint16_t *sZ = smem + NP * 2 * BM * LD;        // [NP][2][BC][LD]
+    uint16_t *sA = smem;                           // [NA][2][BM][LD]
+    uint16_t *sZ = smem + NA * 2 * BM * LD;        // [NP][2][BC][LD]
     const int N = P.N;
     const int K = N * N;
     const int NC = P.ncol[TT];
@@ -384,11 +389,10 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     if (c0 >= NC) return;
     const TileK<G> tk(P, TT, w);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const GLOBAL_AS uint16_t *Ahl[NP];
+    const GLOBAL_AS uint16_t *Ahl[NA];
     if constexpr (PH) {
         Ahl[0] = gload_ptr(P.Ahl[TERM_PHC][0]);
-        Ahl[1] = gload_ptr(P.Ahl[TERM_PHD][0]);
-        Ahl[2] = gload_ptr(P.Ahl[TERM_PHD][1]);
+        Ahl[1] = gload_ptr(P.Ahl[TERM_PHD][1]);
     } else {
         Ahl[0] = gload_ptr(P.Ahl[TERM_PP][0]);
     }
@@ -410,7 +414,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     const GLOBAL_AS float *gd = PH ? gload_ptr(P.G32[TERM_PHD][0]) + static_cast<int64_t>(c) * N : nullptr;
     const GLOBAL_AS float *g1 = PH ? gload_ptr(P.G32[TERM_PHD][1]) + static_cast<int64_t>(c / N) * K : nullptr;
 
-    u32x4_t ra[NP][2][ACH];
+    u32x4_t ra[NA][2][ACH];
     float rb[ZK], rg[NP][ZK];
 
     // Buffer resources for the FAST path: 32-bit offsets, and an offset past
@@ -420,12 +424,11 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     // rows below 2 GiB; the host checks both.
     constexpr uint32_t kOOB = 0x80000000u;
     constexpr int kFlags = 0x00020000;   // raw buffer, 32-bit data format (gfx9)
-    __amdgpu_buffer_rsrc_t rA[NP], rB, rG0, rGd, rG1;
+    __amdgpu_buffer_rsrc_t rA[NA], rB, rG0, rGd, rG1;
     if constexpr (FAST) {
-        const uint16_t *Araw[3] = {PH ? P.Ahl[TERM_PHC][0] : P.Ahl[TERM_PP][0], P.Ahl[TERM_PHD][0],
-                                   P.Ahl[TERM_PHD][1]};
+        const uint16_t *Araw[2] = {PH ? P.Ahl[TERM_PHC][0] : P.Ahl[TERM_PP][0], P.Ahl[TERM_PHD][1]};
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+        for (int p = 0; p < NA; ++p)
             rA[p] = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t *>(Araw[p]), 0, static_cast<int>(4 * n3),
                                                       kFlags);
         rB = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(P.B[TT]), 0, static_cast<int>(P.Bbytes[TT]),
@@ -446,7 +449,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
 
     auto load_fast = [&](const int (&ea)[ACH], int e) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+        for (int p = 0; p < NA; ++p)
 #pragma unroll
             for (int hl = 0; hl < 2; ++hl)
 #pragma unroll
@@ -500,7 +503,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     // ea[i]: list entry of the slot of A piece i; e: of the Z window
     auto load_general = [&](const int (&ea)[ACH], int e) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+        for (int p = 0; p < NA; ++p)
 #pragma unroll
             for (int hl = 0; hl < 2; ++hl)
 #pragma unroll
@@ -576,7 +579,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     };
     auto store = [&]() {
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
+        for (int p = 0; p < NA; ++p)
 #pragma unroll
             for (int hl = 0; hl < 2; ++hl)
 #pragma unroll
@@ -590,7 +593,9 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
             bf8_t hi, lo;   // round-to-nearest-even conversions (v_cvt_pk_bf16_f32)
 #pragma unroll
             for (int q = 0; q < ZK; ++q) {
-                const float z = rb[q] * rg[p][q];
+                // product 2: V(j1,b,a) - 2 V(j1,b,j3) (the regrouped phd term)
+                const float gq = (PH && p == 2) ? fmaf(-2.0f, rg[1][q], rg[2][q]) : rg[p][q];
+                const float z = rb[q] * gq;
                 const __bf16 zh = static_cast<__bf16>(z);
                 hi[q] = zh;
                 lo[q] = static_cast<__bf16>(z - static_cast<float>(zh));
@@ -643,8 +648,9 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
 #pragma unroll
             for (int ri = 0; ri < RT; ++ri) {
                 const int ar = wm * (BM / 2) + ri * 16 + (lane & 15);
-                const bf8_t ah = *reinterpret_cast<const bf8_t *>(sA + (p * 2 + 0) * BM * LD + swz(ar, kch));
-                const bf8_t al = *reinterpret_cast<const bf8_t *>(sA + (p * 2 + 1) * BM * LD + swz(ar, kch));
+                const int aop = (PH && p == 2) ? 1 : 0;
+                const bf8_t ah = *reinterpret_cast<const bf8_t *>(sA + (aop * 2 + 0) * BM * LD + swz(ar, kch));
+                const bf8_t al = *reinterpret_cast<const bf8_t *>(sA + (aop * 2 + 1) * BM * LD + swz(ar, kch));
 #pragma unroll
                 for (int ci = 0; ci < 2; ++ci) {
                     f4_t &d = acc[u][ri][ci];
@@ -762,10 +768,10 @@ __global__ void reset_counters(int *counters, int n) {
 
 constexpr int contract_kinds_of(bool split) { return split ? 2 : 3; }
 
-// LDS of one block: split [3 products][hi, lo] A (BM x 32) and Z (64 x 32)
-// bf16 tiles; FP64 [2 products] A (BM x 17) and Z (64 x 17) tiles
+// LDS of one block: split [2 A operands][hi, lo] A (BM x 32) and [3 products]
+// [hi, lo] Z (64 x 32) bf16 tiles; FP64 [2 products] A (BM x 17) and Z (64 x 17) tiles
 constexpr size_t lds_bytes(bool split, int bm) {
-    return split ? sizeof(uint16_t) * (3 * 2 * bm * 32 + 3 * 2 * BC * 32)
+    return split ? sizeof(uint16_t) * (2 * 2 * bm * 32 + 3 * 2 * BC * 32)
                  : sizeof(double) * (2 * bm * 17 + 2 * BC * 17);
 }
 

@@ -231,8 +231,10 @@ __global__ __launch_bounds__(256) void dsigma_kernel(int N, const double *__rest
 //     4: V[k][i][j]                phc gather (column (y, x) = (i, j), b = k)
 //     5: V[i][k][j]                phd gather (column (y, x) = (i, j), b = k;
 //                                              and y = i, (a, b) = (j, k))
-//   split: ahl = the four A blocks as bf16 hi, lo ([4][2][N^3], chunk-major);
-//          g32 = [V (pp gather), block 4, block 5] in FP32.
+//   split: ahl = A blocks 0, 1 and 3 as bf16 hi, lo ([4][2][N^3], chunk-major;
+//          slot 2 unused: the split contraction regroups the phd products so
+//          that blocks 1 and 3 serve them); g32 = [V (pp gather), block 4,
+//          block 5] in FP32.
 //
 // One layout pass is a grid of layout_blocks(N) blocks of 256 threads:
 //  - A part: a thread makes one (chunk c, row i) run of 8 entries of every A
@@ -329,11 +331,11 @@ __device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int 
         for (int t = 0; t < 8; ++t) {
             ops[0][t] = static_cast<float>(pp[t]);
             ops[1][t] = static_cast<float>(phc[t]);
-            ops[2][t] = static_cast<float>(-2.0 * phd[t] + phc[t]);
             ops[3][t] = static_cast<float>(phd[t]);
         }
 #pragma unroll
         for (int o = 0; o < 4; ++o) {
+            if (o == 2) continue;
             uint32_t hw[4], lw[4];
 #pragma unroll
             for (int t = 0; t < 8; t += 2) {
