@@ -623,9 +623,11 @@ frg_status ensure_dense_tiles(frg_ctx ctx) {
 }
 
 // Operand pointers of the fused contraction in the layout the layout kernels
-// write: FP64 perm = [pp A, phc A, phd A0, phd A1 (chunk-major), phc gather,
-// phd gather]; split ahl = four A operands x (hi, lo), g32 = [V, phc gather,
-// phd gather].
+// write: FP64 perm = [pp A, phc A, (unused), phd A1 (chunk-major), phc gather,
+// phd gather]; split ahl = four A slots x (hi, lo) (slot 2 unused), g32 = [V,
+// phc gather, phd gather].  Both contractions take the direct-ph sum as
+// V(j2,a,b) V(j1,b,j3) + V(a,j2,b) (V(j1,b,a) - 2 V(j1,b,j3)), so the first phd
+// operand is the phc operand V(m,a,b).
 void set_operands(frg::FusedContractArgs &a, bool split, const double *V, const double *P, const uint16_t *H,
                   const float *G, int64_t n3) {
     using frg::TERM_PP;
@@ -634,12 +636,12 @@ void set_operands(frg::FusedContractArgs &a, bool split, const double *V, const 
     if (!split) {
         a.A64[TERM_PP][0] = P;           a.G64[TERM_PP][0] = V;
         a.A64[TERM_PHC][0] = P + n3;     a.G64[TERM_PHC][0] = P + 4 * n3;
-        a.A64[TERM_PHD][0] = P + 2 * n3; a.G64[TERM_PHD][0] = P + 5 * n3;
+        a.A64[TERM_PHD][0] = P + n3;     a.G64[TERM_PHD][0] = P + 5 * n3;
         a.A64[TERM_PHD][1] = P + 3 * n3; a.G64[TERM_PHD][1] = P + 5 * n3;
     } else {
         a.Ahl[TERM_PP][0] = H;           a.G32[TERM_PP][0] = G;
         a.Ahl[TERM_PHC][0] = H + 2 * n3; a.G32[TERM_PHC][0] = G + n3;
-        a.Ahl[TERM_PHD][0] = H + 4 * n3; a.G32[TERM_PHD][0] = G + 2 * n3;
+        a.Ahl[TERM_PHD][0] = H + 2 * n3; a.G32[TERM_PHD][0] = G + 2 * n3;
         a.Ahl[TERM_PHD][1] = H + 6 * n3; a.G32[TERM_PHD][1] = G + 2 * n3;
     }
 }

@@ -281,7 +281,8 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
 #pragma unroll
         for (int q = 0; q < ZK; ++q) {
             sZ[cl * LDA + zk + q] = rb[q] * rg0[q];
-            if (TERM == TERM_PHD) sZ[(BC + cl) * LDA + zk + q] = rb[q] * rg1[q];
+            // second phd product: V(j1,b,a) - 2 V(j1,b,j3) (the regrouped phd term)
+            if (TERM == TERM_PHD) sZ[(BC + cl) * LDA + zk + q] = rb[q] * fma(-2.0, rg0[q], rg1[q]);
         }
     };
 

@@ -226,15 +226,16 @@ __global__ __launch_bounds__(256) void dsigma_kernel(int N, const double *__rest
 //   FP64 perm blocks:
 //     0: V[j][k][i]                pp A       (row j3 = i)
 //     1: V[i][j][k]                phc A      (row j1 = i)
-//     2: -2 V[j][i][k] + V[i][j][k]  phd A      (row j2 = i)
-//     3: V[j][i][k]                phd A
+//     2: (unused)
+//     3: V[j][i][k]                phd A      (row j2 = i)
 //     4: V[k][i][j]                phc gather (column (y, x) = (i, j), b = k)
 //     5: V[i][k][j]                phd gather (column (y, x) = (i, j), b = k;
 //                                              and y = i, (a, b) = (j, k))
-//   split: ahl = A blocks 0, 1 and 3 as bf16 hi, lo ([4][2][N^3], chunk-major;
-//          slot 2 unused: the split contraction regroups the phd products so
-//          that blocks 1 and 3 serve them); g32 = [V (pp gather), block 4,
-//          block 5] in FP32.
+//   The contractions take the direct-ph sum (-2 V(a,j2,b) + V(j2,a,b)) V(j1,b,j3)
+//   + V(a,j2,b) V(j1,b,a) as V(j2,a,b) V(j1,b,j3) + V(a,j2,b) (V(j1,b,a) -
+//   2 V(j1,b,j3)): blocks 1 and 3 serve it, and slot 2 is not written.
+//   split: ahl = A blocks 0, 1 and 3 as bf16 hi, lo ([4][2][N^3], chunk-major);
+//          g32 = [V (pp gather), block 4, block 5] in FP32.
 //
 // One layout pass is a grid of layout_blocks(N) blocks of 256 threads:
 //  - A part: a thread makes one (chunk c, row i) run of 8 entries of every A
@@ -358,8 +359,6 @@ __device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int 
         for (int t = 0; t < 8; t += 2) {
             *reinterpret_cast<double2 *>(perm + cm + t) = make_double2(pp[t], pp[t + 1]);
             *reinterpret_cast<double2 *>(perm + n3 + cm + t) = make_double2(phc[t], phc[t + 1]);
-            *reinterpret_cast<double2 *>(perm + 2 * n3 + cm + t) =
-                make_double2(-2.0 * phd[t] + phc[t], -2.0 * phd[t + 1] + phc[t + 1]);
             *reinterpret_cast<double2 *>(perm + 3 * n3 + cm + t) = make_double2(phd[t], phd[t + 1]);
         }
     }
