@@ -822,8 +822,8 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     {
         KTimer kt(ctx, FRG_K_LAYOUT, s);
         if (!split) frg::launch_layout_f64(V, N, w.perm, s);
-        else if (Vred) frg::launch_layout_split_red(Vred, N, col_pos(ctx, 0), col_pos(ctx, 1), ctx->d_perm8,
-                                                    w.ahl, w.g32, s);
+        else if (Vred) frg::launch_layout_split_red(Vred, N, col_pos(ctx, 0), tiles_of(ctx, 1).d_cperm,
+                                                    tiles_of(ctx, 1).ncol, w.ahl, w.g32, s);
         else frg::launch_layout_split(V, N, w.ahl, w.g32, s);
     }
     set_operands(a, split, V, w.perm, w.ahl, w.g32, n3);
@@ -2044,6 +2044,8 @@ frg_status batch_build(frg_batch b, frg_precision prec, double *const *Vs) {
         A.nst = c->nst;
         A.yr = c->d_yr; A.ytr = c->d_ytr; A.y5r = c->d_y5r;
         A.cperm_pp = tiles_of(c, 0).d_cperm;
+        A.cperm_ph = tiles_of(c, 1).d_cperm;
+        A.ncol_ph = tiles_of(c, 1).ncol;
         st[f] = A.state;
         frg::BubbleArgs bb = bubble_args(c, split, bpp, bph, c->d_pa64, c->d_pa32, c->d_T);
         if (sym) {

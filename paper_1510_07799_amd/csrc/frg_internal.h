@@ -197,8 +197,8 @@ void launch_pre_step(double *state, int stepper, hipStream_t s);
 void launch_dp_control(double *state, double *log, int log_cap, double vmax, int max_steps,
                        int stepper, hipStream_t s);
 // split layout straight from a reduced state (gather rows of representative columns only)
-void launch_layout_split_red(const double *Vr, int N, const int32_t *ppos, const int32_t *phpos,
-                             const int16_t *perm8, uint16_t *ahl, float *g32, hipStream_t s);
+void launch_layout_split_red(const double *Vr, int N, const int32_t *ppos, const int32_t *cperm_ph, int ncol_ph,
+                             uint16_t *ahl, float *g32, hipStream_t s);
 // Reduced flow state of the symmetric-vertex mode (entry pos * N + m = V(cperm[pos], m)):
 // gather it from a full V, expand it into a full V (only accepted steps when gate,
 // the flow state, is given), and the rhs at the representative entries only.
@@ -243,6 +243,8 @@ struct FlowArgs {
     int64_t nst;
     double *yr, *ytr, *y5r;
     const int32_t *cperm_pp;
+    const int32_t *cperm_ph;   // representative ph columns (the layout's phc gather rows)
+    int ncol_ph;
 };
 enum { SRC_V = 0, SRC_YT = 1, SRC_Y5 = 2 };
 // batched: dst SRC_V gathers yr from V (items over the reduced length), SRC_YT /

@@ -268,7 +268,9 @@ __host__ __device__ __forceinline__ int layout_t_tiles(int N) { return (N + kLay
 // are written then (the contraction reads no others).
 struct RedSrc {
     const double *Vr;
-    const int32_t *ppos, *phpos;   // pp / ph column maps: position << 3 | C4v element
+    const int32_t *ppos;           // pp column map: position << 3 | C4v element
+    const int32_t *cperm_ph;       // representative ph columns (natural index), ncol_ph of them
+    int ncol_ph;
     __device__ __forceinline__ double at(int N, int a, int b, int m) const {
         const int32_t cm = ppos[a * N + b];
         return Vr[(cm >> 3) * N + c4v_patch(cm & 7, m, N)];
@@ -366,9 +368,9 @@ __device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int 
 
 // one 32 x 32 tile of out[col][r] = get(r, col) for the output rows col that
 // keep(col) accepts (rows x cols input), stored as OUT
-template <typename OUT, class GET, class KEEP>
-__device__ __forceinline__ void layout_transpose_gen(GET get, KEEP keep, int rows, int64_t cols, int r0, int64_t c0,
-                                                     OUT *__restrict__ out, int64_t ld_out,
+template <typename OUT, class GET, class KEEP, class OROW>
+__device__ __forceinline__ void layout_transpose_gen(GET get, KEEP keep, OROW orow, int rows, int64_t cols, int r0,
+                                                     int64_t c0, OUT *__restrict__ out, int64_t ld_out,
                                                      double (*tile)[kLayoutTile + 1]) {
     const int tx = threadIdx.x & (kLayoutTile - 1), ty = threadIdx.x / kLayoutTile;   // 32 x 8
 #pragma unroll
@@ -382,7 +384,7 @@ __device__ __forceinline__ void layout_transpose_gen(GET get, KEEP keep, int row
     for (int p = 0; p < kLayoutTile; p += 8) {
         const int64_t c = c0 + ty + p;
         const int r = r0 + tx;
-        if (r < rows && c < cols && keep(c)) out[c * ld_out + r] = static_cast<OUT>(tile[tx][ty + p]);
+        if (r < rows && c < cols && keep(c)) out[orow(c) * ld_out + r] = static_cast<OUT>(tile[tx][ty + p]);
     }
 }
 
@@ -452,8 +454,15 @@ __global__ __launch_bounds__(256) void layout_f64_kernel(const double *__restric
     layout_block<false>(V, N, n3, blockIdx.x, nullptr, nullptr, perm, tile);
 }
 
-// block blk of a split layout pass from a reduced state: the same blocks as
-// layout_block<true>, gather rows of non-representative columns skipped
+// block blk of a split layout pass from a reduced state: the A units as in
+// layout_block<true>, then the phd gather (block 5) in full, then the phc gather
+// (block 4) of the representative ph columns only, in 32 x 32 tiles of (k,
+// position in the representative list); blocks past layout_blocks_red(N, ncol_ph)
+// have nothing to do
+__host__ __device__ __forceinline__ int layout_blocks_red(int N, int ncol_ph) {
+    const int nt = layout_t_tiles(N);
+    return layout_a_blocks(N) + N * nt * nt + nt * ((ncol_ph + kLayoutTile - 1) / kLayoutTile);
+}
 __device__ __forceinline__ void layout_block_red(const RedSrc &R, int N, int64_t n3, int blk,
                                                  uint16_t *__restrict__ ahl, float *__restrict__ g32,
                                                  LayoutTile *tile) {
@@ -465,25 +474,27 @@ __device__ __forceinline__ void layout_block_red(const RedSrc &R, int N, int64_t
         return;
     }
     blk -= na;
-    const int nt1 = nt * static_cast<int>((NN + kLayoutTile - 1) / kLayoutTile);
-    if (blk < nt1) {   // block 4: out[(i, j)][k] = V(k, i, j), rows of representative ph columns
-        const int rt = blk % nt;
-        const int64_t ct = blk / nt;
-        layout_transpose_gen<float>(
-            [&](int k, int64_t c) {
-                const int ci = static_cast<int>(c), a = ci / N;   // c < N^2: 32-bit division
-                return R.at(N, k, a, ci - a * N);
-            },
-            [&](int64_t c) { return (R.phpos[c] & 7) == 0; }, N, NN, rt * kLayoutTile, ct * kLayoutTile, g32 + n3,
-            N, tile);
+    const int n5 = N * nt * nt;
+    if (blk < n5) {    // block 5: out[i][j][k] = V(i, k, j)
+        const int i = blk / (nt * nt), rem = blk - i * nt * nt;
+        const int rt = rem % nt, ct = rem / nt;
+        layout_transpose_gen<float>([&](int k, int64_t j) { return R.at(N, i, k, static_cast<int>(j)); },
+                                    [](int64_t) { return true; }, [](int64_t j) { return j; }, N, N,
+                                    rt * kLayoutTile, ct * kLayoutTile, g32 + 2 * n3 + i * NN, N, tile);
         return;
     }
-    blk -= nt1;        // block 5: out[i][j][k] = V(i, k, j)
-    const int i = blk / (nt * nt), rem = blk - i * nt * nt;
-    const int rt = rem % nt, ct = rem / nt;
-    layout_transpose_gen<float>([&](int k, int64_t j) { return R.at(N, i, k, static_cast<int>(j)); },
-                                [](int64_t) { return true; }, N, N, rt * kLayoutTile, ct * kLayoutTile,
-                                g32 + 2 * n3 + i * NN, N, tile);
+    blk -= n5;
+    const int npt = (R.ncol_ph + kLayoutTile - 1) / kLayoutTile;
+    if (blk >= nt * npt) return;
+    // block 4: out[c][k] = V(k, i, j) for the representative ph columns c = (i, j)
+    const int rt = blk % nt, pt = blk / nt;
+    layout_transpose_gen<float>(
+        [&](int k, int64_t pos) {
+            const int c = R.cperm_ph[pos], i = c / N;   // c < N^2: 32-bit division
+            return R.at(N, k, i, c - i * N);
+        },
+        [](int64_t) { return true; }, [&](int64_t pos) { return static_cast<int64_t>(R.cperm_ph[pos]); }, N,
+        R.ncol_ph, rt * kLayoutTile, pt * kLayoutTile, g32 + n3, N, tile);
 }
 
 __global__ __launch_bounds__(256) void layout_split_red_kernel(RedSrc R, int N, uint16_t *__restrict__ ahl,
@@ -982,7 +993,7 @@ __global__ __launch_bounds__(256) void layout_b_kernel(const FlowArgs *__restric
     if (!split) {
         layout_block<false>(src_of(f, src), f.N, f.n3, it.y, nullptr, nullptr, f.perm, tile);
     } else if (f.red && src != SRC_V) {   // straight from the reduced stage vector
-        const RedSrc R{src == SRC_YT ? f.ytr : f.y5r, f.ppos, f.phpos};
+        const RedSrc R{src == SRC_YT ? f.ytr : f.y5r, f.ppos, f.cperm_ph, f.ncol_ph};
         layout_block_red(R, f.N, f.n3, it.y, f.ahl, f.g32, tile);
     } else {
         layout_block<true>(src_of(f, src), f.N, f.n3, it.y, f.ahl, f.g32, nullptr, tile);
@@ -1182,11 +1193,10 @@ void launch_layout_f64(const double *V, int N, double *perm, hipStream_t s) {
     hipLaunchKernelGGL(layout_f64_kernel, dim3(layout_blocks(N)), dim3(256), 0, s, V, N, perm);
 }
 
-void launch_layout_split_red(const double *Vr, int N, const int32_t *ppos, const int32_t *phpos,
-                             const int16_t *perm8, uint16_t *ahl, float *g32, hipStream_t s) {
-    (void)perm8;   // the layout computes the patch maps
-    hipLaunchKernelGGL(layout_split_red_kernel, dim3(layout_blocks(N)), dim3(256), 0, s, RedSrc{Vr, ppos, phpos}, N,
-                       ahl, g32);
+void launch_layout_split_red(const double *Vr, int N, const int32_t *ppos, const int32_t *cperm_ph, int ncol_ph,
+                             uint16_t *ahl, float *g32, hipStream_t s) {
+    hipLaunchKernelGGL(layout_split_red_kernel, dim3(layout_blocks_red(N, ncol_ph)), dim3(256), 0, s,
+                       RedSrc{Vr, ppos, cperm_ph, ncol_ph}, N, ahl, g32);
 }
 
 void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipStream_t s) {
