@@ -294,12 +294,34 @@ __device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int 
         const int kk = static_cast<int>(kk0), j = kk / N, k0 = kk - j * N;
         const int32_t cc = R.ppos[i * N + j], cd = R.ppos[j * N + i];
         const double *rc = R.Vr + (cc >> 3) * N, *rd = R.Vr + (cd >> 3) * N;
+        if (N % 32 == 0) {
+            // k0 and the rotations' shifts (multiples of N/4) are multiples of 8, so
+            // the 8 patches k0 .. k0+7 map to one aligned run of 8 entries of the
+            // row, in reverse order for a reflection: 16-byte loads
+            auto run8 = [&](const double *row, int o, double *out) {
+                const bool refl = (o & 1) != 0;
+                const double2 *src = reinterpret_cast<const double2 *>(row + c4v_patch(o, refl ? k0 + 7 : k0, N));
+                double tmp[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            phc[t] = rc[c4v_patch(cc & 7, k0 + t, N)];
-            phd[t] = rd[c4v_patch(cd & 7, k0 + t, N)];
-            pp[t] = R.at(N, j, k0 + t, i);
+                for (int h = 0; h < 4; ++h) {
+                    const double2 v = src[h];
+                    tmp[2 * h] = v.x;
+                    tmp[2 * h + 1] = v.y;
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) out[t] = refl ? tmp[7 - t] : tmp[t];
+            };
+            run8(rc, cc & 7, phc);
+            run8(rd, cd & 7, phd);
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                phc[t] = rc[c4v_patch(cc & 7, k0 + t, N)];
+                phd[t] = rd[c4v_patch(cd & 7, k0 + t, N)];
+            }
         }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) pp[t] = R.at(N, j, k0 + t, i);
         write_g = (cc & 7) == 0;   // gather row (i, j) of a representative pp column
     }
     const double *vrow = V + i * NN + kk0;
