@@ -193,11 +193,11 @@ frg_status ensure_rhs_ws(frg_ctx ctx, frg_precision prec) {
     if (prec == FRG_PREC_FP64) {
         TRY(dalloc(ctx, &ctx->d_pa64, 3 * static_cast<size_t>(g.np)));
         TRY(dalloc(ctx, &ctx->d_B64, NN * ctx->Trows));
-        TRY(dalloc(ctx, &ctx->d_perm, 6 * static_cast<size_t>(ctx->n3)));
+        TRY(dalloc(ctx, &ctx->d_perm, 5 * static_cast<size_t>(ctx->n3)));
     } else {
         TRY(dalloc(ctx, &ctx->d_pa32, 3 * static_cast<size_t>(g.np)));
         TRY(dalloc(ctx, &ctx->d_B32, NN * ctx->Trows));
-        TRY(dalloc(ctx, &ctx->d_ahl, 8 * static_cast<size_t>(ctx->n3)));
+        TRY(dalloc(ctx, &ctx->d_ahl, 6 * static_cast<size_t>(ctx->n3)));
         TRY(dalloc(ctx, &ctx->d_g32, 3 * static_cast<size_t>(ctx->n3)));
     }
     return FRG_OK;
@@ -623,9 +623,9 @@ frg_status ensure_dense_tiles(frg_ctx ctx) {
 }
 
 // Operand pointers of the fused contraction in the layout the layout kernels
-// write: FP64 perm = [pp A, phc A, (unused), phd A1 (chunk-major), phc gather,
-// phd gather]; split ahl = four A slots x (hi, lo) (slot 2 unused), g32 = [V,
-// phc gather, phd gather].  Both contractions take the direct-ph sum as
+// write: FP64 perm = [pp A, phc A, phd A (chunk-major), phc gather, phd
+// gather]; split ahl = the three A operands x (hi, lo), g32 = [V, phc gather,
+// phd gather].  Both contractions take the direct-ph sum as
 // V(j2,a,b) V(j1,b,j3) + V(a,j2,b) (V(j1,b,a) - 2 V(j1,b,j3)), so the first phd
 // operand is the phc operand V(m,a,b).
 void set_operands(frg::FusedContractArgs &a, bool split, const double *V, const double *P, const uint16_t *H,
@@ -635,14 +635,14 @@ void set_operands(frg::FusedContractArgs &a, bool split, const double *V, const 
     using frg::TERM_PHD;
     if (!split) {
         a.A64[TERM_PP][0] = P;           a.G64[TERM_PP][0] = V;
-        a.A64[TERM_PHC][0] = P + n3;     a.G64[TERM_PHC][0] = P + 4 * n3;
-        a.A64[TERM_PHD][0] = P + n3;     a.G64[TERM_PHD][0] = P + 5 * n3;
-        a.A64[TERM_PHD][1] = P + 3 * n3; a.G64[TERM_PHD][1] = P + 5 * n3;
+        a.A64[TERM_PHC][0] = P + n3;     a.G64[TERM_PHC][0] = P + 3 * n3;
+        a.A64[TERM_PHD][0] = P + n3;     a.G64[TERM_PHD][0] = P + 4 * n3;
+        a.A64[TERM_PHD][1] = P + 2 * n3; a.G64[TERM_PHD][1] = P + 4 * n3;
     } else {
         a.Ahl[TERM_PP][0] = H;           a.G32[TERM_PP][0] = G;
         a.Ahl[TERM_PHC][0] = H + 2 * n3; a.G32[TERM_PHC][0] = G + n3;
         a.Ahl[TERM_PHD][0] = H + 2 * n3; a.G32[TERM_PHD][0] = G + 2 * n3;
-        a.Ahl[TERM_PHD][1] = H + 6 * n3; a.G32[TERM_PHD][1] = G + 2 * n3;
+        a.Ahl[TERM_PHD][1] = H + 4 * n3; a.G32[TERM_PHD][1] = G + 2 * n3;
     }
 }
 
@@ -1248,8 +1248,8 @@ frg_status frg_rhs_noalloc(frg_ctx ctx, double T, const double *d_V, double *d_F
     const size_t esz = split ? sizeof(float) : sizeof(double);
     const size_t o_pa = take(3 * np * esz);
     const size_t o_B = take(rows * NN * esz);
-    const size_t o_perm = split ? 0 : take(6 * n3 * sizeof(double));
-    const size_t o_ahl = split ? take(8 * n3 * sizeof(uint16_t)) : 0;
+    const size_t o_perm = split ? 0 : take(5 * n3 * sizeof(double));
+    const size_t o_ahl = split ? take(6 * n3 * sizeof(uint16_t)) : 0;
     const size_t o_g32 = split ? take(3 * n3 * sizeof(float)) : 0;
     const size_t o_C = take(c_elems_needed(ctx) * sizeof(double));
     if (off > frg::kScratchBytes)

@@ -226,16 +226,15 @@ __global__ __launch_bounds__(256) void dsigma_kernel(int N, const double *__rest
 //   FP64 perm blocks:
 //     0: V[j][k][i]                pp A       (row j3 = i)
 //     1: V[i][j][k]                phc A      (row j1 = i)
-//     2: (unused)
-//     3: V[j][i][k]                phd A      (row j2 = i)
-//     4: V[k][i][j]                phc gather (column (y, x) = (i, j), b = k)
-//     5: V[i][k][j]                phd gather (column (y, x) = (i, j), b = k;
+//     2: V[j][i][k]                phd A      (row j2 = i)
+//     3: V[k][i][j]                phc gather (column (y, x) = (i, j), b = k)
+//     4: V[i][k][j]                phd gather (column (y, x) = (i, j), b = k;
 //                                              and y = i, (a, b) = (j, k))
 //   The contractions take the direct-ph sum (-2 V(a,j2,b) + V(j2,a,b)) V(j1,b,j3)
 //   + V(a,j2,b) V(j1,b,a) as V(j2,a,b) V(j1,b,j3) + V(a,j2,b) (V(j1,b,a) -
-//   2 V(j1,b,j3)): blocks 1 and 3 serve it, and slot 2 is not written.
-//   split: ahl = A blocks 0, 1 and 3 as bf16 hi, lo ([4][2][N^3], chunk-major);
-//          g32 = [V (pp gather), block 4, block 5] in FP32.
+//   2 V(j1,b,j3)): blocks 1 and 2 serve it.
+//   split: ahl = A blocks 0, 1 and 2 as bf16 hi, lo ([3][2][N^3], chunk-major);
+//          g32 = [V (pp gather), block 3, block 4] in FP32.
 //
 // One layout pass is a grid of layout_blocks(N) blocks of 256 threads:
 //  - A part: a thread makes one (chunk c, row i) run of 8 entries of every A
@@ -351,16 +350,15 @@ __device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int 
     }
     const int64_t cm = (c * N + i) * 8;
     if constexpr (SPLIT) {
-        float ops[4][8];
+        float ops[3][8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
             ops[0][t] = static_cast<float>(pp[t]);
             ops[1][t] = static_cast<float>(phc[t]);
-            ops[3][t] = static_cast<float>(phd[t]);
+            ops[2][t] = static_cast<float>(phd[t]);
         }
 #pragma unroll
-        for (int o = 0; o < 4; ++o) {
-            if (o == 2) continue;
+        for (int o = 0; o < 3; ++o) {
             uint32_t hw[4], lw[4];
 #pragma unroll
             for (int t = 0; t < 8; t += 2) {
@@ -383,7 +381,7 @@ __device__ __forceinline__ void layout_a_unit(const double *__restrict__ V, int 
         for (int t = 0; t < 8; t += 2) {
             *reinterpret_cast<double2 *>(perm + cm + t) = make_double2(pp[t], pp[t + 1]);
             *reinterpret_cast<double2 *>(perm + n3 + cm + t) = make_double2(phc[t], phc[t + 1]);
-            *reinterpret_cast<double2 *>(perm + 3 * n3 + cm + t) = make_double2(phd[t], phd[t + 1]);
+            *reinterpret_cast<double2 *>(perm + 2 * n3 + cm + t) = make_double2(phd[t], phd[t + 1]);
         }
     }
 }
@@ -455,7 +453,7 @@ __device__ __forceinline__ void layout_block(const double *__restrict__ V, int N
         if constexpr (SPLIT)
             layout_transpose_tile<float>(V, N, NN, NN, rt * kLayoutTile, ct * kLayoutTile, g32 + n3, N, tile);
         else
-            layout_transpose_tile<double>(V, N, NN, NN, rt * kLayoutTile, ct * kLayoutTile, perm + 4 * n3, N, tile);
+            layout_transpose_tile<double>(V, N, NN, NN, rt * kLayoutTile, ct * kLayoutTile, perm + 3 * n3, N, tile);
         return;
     }
     blk -= nt1;        // block 5: out[i][j][k] = V[i][k][j]
@@ -466,7 +464,7 @@ __device__ __forceinline__ void layout_block(const double *__restrict__ V, int N
                                      N, tile);
     else
         layout_transpose_tile<double>(V + i * NN, N, N, N, rt * kLayoutTile, ct * kLayoutTile,
-                                      perm + 5 * n3 + i * NN, N, tile);
+                                      perm + 4 * n3 + i * NN, N, tile);
 }
 
 __global__ __launch_bounds__(256) void layout_f64_kernel(const double *__restrict__ V, int N,
