@@ -654,6 +654,19 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
     const int nseg = (A.count[a_patch] + S - 1) / S;
     double cpx[PR], spx[PR], cpy[PR], spy[PR];
     PT pa[PR], pc1[PR], pc2[PR];
+    // the lane's 8 table bytes of row r in segment sg (in bounds: n_f is a
+    // multiple of the segment)
+    auto load_bins = [&](int r, int sg, uint32_t *bw) {
+        const GLOBAL_AS uint8_t *src = gbins + static_cast<size_t>(r) * np + static_cast<size_t>(a_patch) * nf +
+                                       sg * S + lane * P;
+        const uint64_t v = *reinterpret_cast<const GLOBAL_AS uint64_t *>(src);
+        bw[0] = static_cast<uint32_t>(v);
+        bw[1] = static_cast<uint32_t>(v >> 32);
+    };
+    // the next row's table bytes are loaded while a row is evaluated (and the
+    // first row's of a segment while its points are set up)
+    uint32_t nbw[2] = {0u, 0u};
+    if (nseg > 0 && nrow_w > 0) load_bins(__builtin_amdgcn_readlane(my_r, 0), 0, nbw);
     for (int sg = 0; sg < nseg; ++sg) {
         const int k0 = sg * S;
         // every wave is done with the previous segment's shared point data
@@ -705,15 +718,6 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
                 return taylor_consts<FULL>(pval(4, j), FULL ? c2 : -0.25 * c2);
             }
         };
-        // the lane's 8 table bytes of row r in this segment (in bounds: n_f is a
-        // multiple of the segment)
-        auto load_bins = [&](int r, uint32_t *bw) {
-            const GLOBAL_AS uint8_t *src = gbins + static_cast<size_t>(r) * np + static_cast<size_t>(a_patch) * nf +
-                                           k0 + lane * P;
-            const uint64_t v = *reinterpret_cast<const GLOBAL_AS uint64_t *>(src);
-            bw[0] = static_cast<uint32_t>(v);
-            bw[1] = static_cast<uint32_t>(v >> 32);
-        };
         auto bin_of = [&](const uint32_t *w, int j) -> int { return (w[j >> 2] >> (8 * (j & 3))) & 0xff; };
         for (int it = 0; it < nrow_w; ++it) {
             const int r = __builtin_amdgcn_readlane(my_r, it);
@@ -723,8 +727,9 @@ __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int 
             const double cqx = uniform_f64(k1 * tr[0]), cqy = uniform_f64(k1 * tr[2]);
             const double sx = uniform_f64((pp ? k1 : -k1) * tr[1]);
             const double sy = uniform_f64((pp ? k1 : -k1) * tr[3]);
-            uint32_t bw[2];
-            load_bins(r, bw);
+            uint32_t bw[2] = {nbw[0], nbw[1]};
+            if (it + 1 < nrow_w) load_bins(__builtin_amdgcn_readlane(my_r, it + 1), sg, nbw);
+            else if (sg + 1 < nseg) load_bins(__builtin_amdgcn_readlane(my_r, 0), sg + 1, nbw);
             auto value = [&](int j, PT &v, PT &v2) {
                 const double Y = cqy * pval(2, j) + sy * pval(3, j);
                 const double X = cqx * pval(0, j) + sx * pval(1, j);
