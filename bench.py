@@ -112,8 +112,8 @@ def load_profiles():
 
 
 def bubble_roofline(avg_s, terms, energies, leg, kernel):
-    """The sweep is bound by plain vector ALU work.  Algorithmic unit (the survey's):
-    50 FP32 operation-equivalents per dL/dT term (two cosines, two exponential-class
+    """The sweep is bound by plain vector ALU work.  Algorithmic unit: 50 FP32
+    operation-equivalents per dL/dT term (two cosines, two exponential-class
     operations, one division, ~30 flops, a projection and a compensated add),
     against the FP32 vector peak 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed)
     x 2.4 GHz = 157.3 TFLOP/s.  The build disables packed FP32, so 78.6 TFLOP/s is

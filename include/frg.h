@@ -414,9 +414,9 @@ enum {
 };
 frg_status frg_profile_begin(frg_ctx ctx);
 frg_status frg_profile_end(frg_ctx ctx, double *ms, int32_t *counts);
-/* ---- Tuning (spec: tile shapes picked by an autotuner; the paper's
- * load-balancing lessons, Alg. 2 and Sec. 6, are about the same granularity
- * choices).  Three launch parameters of the rhs:
+/* ---- Tuning (tile shapes and work granularity picked by measurement; the
+ * paper's load-balancing lessons, Alg. 2 and Sec. 6, are about the same
+ * granularity choices).  Three launch parameters of the rhs:
  *   kparts      K parts the channel contraction is cut into for the column set
  *               in use (every column / one per C4v orbit / dense), 1..64;
  *   sweep_rows  bubble rows per block of the sweep, a multiple of 4 in 4..256
