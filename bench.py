@@ -21,6 +21,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -111,6 +112,78 @@ def load_profiles():
     return tr if tr.get("source_hash") == kernel_source_hash() else None
 
 
+def rhs_micro(frg, torch, ctx, p, entry64, entry32, runs=50, warm=5):
+    """frg_rhs alone at the benchmark workload, symmetric-vertex mode: HIP events
+    recorded on the launch stream around each call, `warm` untimed and `runs`
+    timed calls, median and 90th percentile.  State classes: (i) V = U; (ii)
+    states of an FP64 DP5(4) flow from V = U at T = 1, the first past
+    max|V| = 5 and 10 and the last one before the flow stops above 20 (the flow
+    starts at max|V| = U = 3); (iii) a seeded
+    C4v-symmetric V = U (1 + 0.5 eta), eta uniform on [-1, 1].  Each at
+    T = 0.05 and 1e-3, FP64 and split; the split result is compared with the
+    FP64 one on the same state (cost does not depend on V, the error does)."""
+    from paper_1510_07799_amd import inputs as I
+    from paper_1510_07799_amd import tuning as TU
+    N, U = p["N"], float(p["U"])
+    ctx.set_vsym(True)
+    states = {"V=U": torch.full((N, N, N), U, dtype=torch.float64, device="cuda")}
+    # (ii) flow states
+    TU.apply(ctx, entry64)
+    V = states["V=U"].clone()
+    st = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+    o = frg.flow_opts("dp54", frg.PREC_FP64, T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.01)
+    ctx.flow_init(o, V, st)
+    targets = [5.0, 10.0]
+    last = None
+    for _ in range(4000):
+        ctx.flow_step(o, V, st)
+        sh = st.cpu().numpy()
+        if sh[frg.ST_REASON] != 0:
+            break
+        m = float(V.abs().max())
+        last = (V.clone(), m, math.exp(sh[frg.ST_S]))
+        while targets and m >= targets[0]:
+            states[f"flow state past max|V|={targets[0]:g}"] = V.clone()
+            targets.pop(0)
+    if last is not None:
+        states["last flow state before the stop at max|V| > 20"] = last[0]
+    # (iii) random symmetric state
+    states["U(1+0.5 eta)"] = torch.from_numpy(I.random_vertex(N, U, seed=151007799, amp=0.5,
+                                                              symmetrise=True)).cuda()
+    stream = torch.cuda.current_stream()
+    out = {"protocol": f"frg_rhs alone, HIP events on the launch stream around each call, {warm} untimed "
+                       f"+ {runs} timed calls; N=96, 512 points/patch, symmetric-vertex mode, tuned "
+                       "parameters of one flow",
+           "flow_T_at_last_state": round(last[2], 6) if last else None, "states": {}}
+    F = {prec: torch.empty_like(states["V=U"]) for prec in (frg.PREC_FP64, frg.PREC_SPLIT_BF16)}
+    for name, Vs in states.items():
+        rec = {"max_abs_V": round(float(Vs.abs().max()), 4)}
+        for T in (0.05, 1e-3):
+            rt = {}
+            for prec, nm, entry in ((frg.PREC_FP64, "fp64", entry64), (frg.PREC_SPLIT_BF16, "split", entry32)):
+                TU.apply(ctx, entry)
+                for _ in range(warm):
+                    ctx.rhs(T, Vs, prec, out=F[prec])
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                      for _ in range(runs)]
+                for a, b in ev:
+                    a.record(stream)
+                    ctx.rhs(T, Vs, prec, out=F[prec])
+                    b.record(stream)
+                torch.cuda.synchronize()
+                ms = sorted(a.elapsed_time(b) for a, b in ev)
+                med, p90 = ms[len(ms) // 2], ms[min(len(ms) - 1, int(0.9 * len(ms)))]
+                rt[nm] = {"median_ms": round(med, 4), "p90_ms": round(p90, 4), "rhs_per_s": round(1e3 / med, 1)}
+            d = (F[frg.PREC_SPLIT_BF16] - F[frg.PREC_FP64]).abs()
+            ref = float(F[frg.PREC_FP64].abs().max())
+            rt["split_vs_fp64"] = {"max_abs": float(d.max()), "rel": float(d.max()) / ref if ref > 0 else None}
+            rec[f"T={T:g}"] = rt
+        out["states"][name] = rec
+        progress(f"rhs micro {name}: max|V| {rec['max_abs_V']}, T=0.05 split "
+                 f"{rec['T=0.05']['split']['median_ms']} ms, fp64 {rec['T=0.05']['fp64']['median_ms']} ms")
+    return out
+
+
 def bubble_roofline(avg_s, terms, energies, leg, kernel):
     """The sweep is bound by plain vector ALU work.  Algorithmic unit: 50 FP32
     operation-equivalents per dL/dT term (two cosines, two exponential-class
@@ -181,13 +254,16 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the CPU-baseline leg (default: every host core)")
     ap.add_argument("--cpu-only", action="store_true", help="run only the CPU-baseline leg")
-    ap.add_argument("--legs", default="split,fp64,batch,batch_fp64,batch64,split_full,fp64_full,iflow,egrid,se",
+    ap.add_argument("--legs", default="split,fp64,batch,batch_fp64,batch64,split_full,fp64_full,rhs,iflow,egrid,se",
                     help="comma list of split, fp64 (one flow), batch, batch_fp64 (16 flows, split / FP64), "
                          "batch64 (64 flows, split), all in symmetric-vertex mode; split_full, fp64_full "
                          "(one flow, every column computed); iflow (the interaction flow of the paper's "
                          "working example, N=32); egrid (one flow at N=96 on the paper's quadrature: "
                          "1600 energies, adaptive inner rule); se (one flow at N=96 with the self-energy "
-                         "flowing along: every bubble row, every column)")
+                         "flowing along: every bubble row, every column); rhs (frg_rhs alone, event-timed, "
+                         "over V = U, FP64 flow states past max|V| 5, 10 and before the stop at 20, and "
+                         "a random symmetric V, at "
+                         "T = 0.05 and 1e-3)")
     ap.add_argument("--batch-flows", type=int, default=16,
                     help="flows in the batched legs (N=96, 512 points/patch, drawn parameters)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
@@ -265,7 +341,7 @@ def main():
     tuned = {}
     results = {}
     for leg in legs:
-        if leg.startswith("batch") or leg in ("iflow", "egrid", "se"):
+        if leg.startswith("batch") or leg in ("rhs", "iflow", "egrid", "se"):
             continue
         prec = frg.PREC_FP64 if leg.startswith("fp64") else frg.PREC_SPLIT_BF16
         orbit = not leg.endswith("_full")
@@ -277,6 +353,11 @@ def main():
         results[leg] = dict(seconds=dt, prof=prof, state=st)
         progress(f"leg {leg}: {RHS_PER_STEP * args.steps / dt:.1f} rhs/s")
     ctx.set_vsym(True)
+    micro = None
+    if "rhs" in legs:
+        micro = rhs_micro(frg, torch, ctx, p, TU.lookup(N, nf, False, True, 1, table),
+                          TU.lookup(N, nf, True, True, 1, table))
+        ctx.set_vsym(True)
 
     def run_batch(nflows, prec):
         # batched workload at N = 96: (mu, t', U) from the seeded draws of the batched configuration
@@ -402,7 +483,7 @@ def main():
 
     head = batches.get("batch")
     if head is None and not results:
-        print(json.dumps({"iflow_p1": iflow, "egrid": egrid, "se": se_leg}))
+        print(json.dumps({"rhs_micro": micro, "iflow_p1": iflow, "egrid": egrid, "se": se_leg}))
         return
     rate = {leg: RHS_PER_STEP * args.steps / r["seconds"] for leg, r in results.items()}
     rate.update({leg: bb["rhs"] / bb["seconds"] for leg, bb in batches.items()})
@@ -476,6 +557,8 @@ def main():
                                                "t'=-0.01 mu=-0.02, bare U(g=1)=2, DP5(4) steps from V=U, "
                                                "symmetric-vertex mode; bubbles once per flow")
 
+    if micro is not None:
+        out["rhs_micro"] = micro
     if egrid is not None:
         out["egrid_e1"] = egrid
     if se_leg is not None:
