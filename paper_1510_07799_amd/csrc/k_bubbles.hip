@@ -517,6 +517,38 @@ __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int 
             src[k] = k == 0 ? bins : bins2;
         }
         const int H = N >> 1;
+        if constexpr (PAIRED) {
+            // a lane takes bins b, b + 1 (b even) of both rows: 32 contiguous bytes
+            // of the interleaved bins; the ph row's values at pp-bin positions b,
+            // b + 1 are its output bins b + N/2, b + N/2 + 1 (mod N; N % 8 == 0, so
+            // the pair does not wrap), so both rows take one 2-wide store
+            for (int b = 2 * lane; b < N; b += 128) {
+                double2 *q = reinterpret_cast<double2 *>(bins + 2 * b);
+                const double2 u0 = q[0], u1 = q[1];   // (pp b, ph@b), (pp b+1, ph@b+1)
+                q[0] = make_double2(0.0, 0.0);
+                q[1] = make_double2(0.0, 0.0);
+                const int bph = b + H >= N ? b + H - N : b + H;
+                typedef float f2v __attribute__((ext_vector_type(2)));
+                typedef double d2v __attribute__((ext_vector_type(2)));
+                if (F32) {
+                    if (outp[0])
+                        *reinterpret_cast<GLOBAL_AS f2v *>(gst(static_cast<float *>(outp[0])) + base[0] + b) =
+                            f2v{static_cast<float>(u0.x), static_cast<float>(u1.x)};
+                    if (outp[1])
+                        *reinterpret_cast<GLOBAL_AS f2v *>(gst(static_cast<float *>(outp[1])) + base[1] + bph) =
+                            f2v{static_cast<float>(u0.y), static_cast<float>(u1.y)};
+                } else {
+                    if (outp[0])
+                        *reinterpret_cast<GLOBAL_AS d2v *>(gst(static_cast<double *>(outp[0])) + base[0] + b) =
+                            d2v{u0.x, u1.x};
+                    if (outp[1])
+                        *reinterpret_cast<GLOBAL_AS d2v *>(gst(static_cast<double *>(outp[1])) + base[1] + bph) =
+                            d2v{u0.y, u1.y};
+                }
+            }
+            wave_sync();
+            continue;
+        }
         for (int b0 = lane; b0 < N; b0 += 128) {
             const int b1 = b0 + 64;
             const bool has1 = b1 < N;
