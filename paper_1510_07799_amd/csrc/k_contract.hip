@@ -9,7 +9,9 @@
 //   pp : m = j3, c = (j1,j2), A = V(a,b,j3),   g = V(j1,j2,a)
 //   phc: m = j1, c = (j2,j3), A = V(j1,a,b),   g = V(b,j2,j3)
 //   phd: m = j2, c = (j1,j3), A = -2V(a,j2,b)+V(j2,a,b) with g = V(j1,b,j3),
-//                              plus A = V(a,j2,b)           with g = V(j1,b,a)
+//                              plus A = V(a,j2,b)           with g = V(j1,b,a),
+//        computed regrouped: A = V(j2,a,b) (the phc operand) with g = V(j1,b,j3),
+//                       plus A = V(a,j2,b) with g = V(j1,b,a) - 2 V(j1,b,j3)
 //
 // One launch covers all three channels.  A block owns a BM x BC output tile
 // of one channel over one K range (K split in KS parts to fill the chip; the
