@@ -462,21 +462,26 @@ def main():
     se_leg = None
     if "se" in legs:
         # the vertex and a self-energy per patch flowing together (N = 96, 512
-        # points per patch): every bubble row and every contraction column
+        # points per patch), every contraction column: with the self-energy
+        # announced C4v invariant (the flow from V = U, S = 0 keeps it so) the
+        # bubble rows are computed per C4v orbit and paired; in the general
+        # mode every row
         cs_ = frg.Context(**p)
         cs_.set_vsym(False)
-        cs_.set_self_energy(True)
         Vse = torch.cat([torch.full((N ** 3,), float(p["U"]), dtype=torch.float64, device="cuda"),
                          torch.zeros(N, dtype=torch.float64, device="cuda")]).contiguous()
         se_leg = {"workload": "N=96, 512 points/patch, t'=-0.3 mu=-1.2 U=3; vertex and self-energy per patch "
-                              "flowing together (DP5(4) steps from V=U, S=0 at T=1); every bubble row, every "
-                              "contraction column"}
-        for prec, nm in ((frg.PREC_SPLIT_BF16, "split"), (frg.PREC_FP64, "fp64")):
-            dt, prof, st = timed_flow_steps(frg, torch, cs_, prec, Vse, args.steps, args.warmup)
-            progress(f"leg se {nm}: {RHS_PER_STEP * args.steps / dt:.1f} rhs/s")
-            se_leg[nm] = {"rhs_per_s": round(RHS_PER_STEP * args.steps / dt, 3),
-                          "kernel_ms_per_rhs": {k: round(v / (PROFILE_STEPS * RHS_PER_STEP), 4)
-                                                for k, (v, c) in prof.items()}}
+                              "flowing together (DP5(4) steps from V=U, S=0 at T=1); every contraction column; "
+                              "c4v_invariant_S: bubble rows per C4v orbit, paired; general_S: every bubble row"}
+        for symmetric, mode in ((True, "c4v_invariant_S"), (False, "general_S")):
+            cs_.set_self_energy(True, symmetric=symmetric)
+            se_leg[mode] = {}
+            for prec, nm in ((frg.PREC_SPLIT_BF16, "split"), (frg.PREC_FP64, "fp64")):
+                dt, prof, st = timed_flow_steps(frg, torch, cs_, prec, Vse, args.steps, args.warmup)
+                progress(f"leg se {mode} {nm}: {RHS_PER_STEP * args.steps / dt:.1f} rhs/s")
+                se_leg[mode][nm] = {"rhs_per_s": round(RHS_PER_STEP * args.steps / dt, 3),
+                                    "kernel_ms_per_rhs": {k: round(v / (PROFILE_STEPS * RHS_PER_STEP), 4)
+                                                          for k, (v, c) in prof.items()}}
         cs_.close()
         del Vse
         torch.cuda.empty_cache()

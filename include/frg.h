@@ -227,18 +227,28 @@ frg_status frg_rhs_noalloc(frg_ctx ctx, double T, const double *d_V, double *d_F
                            void *stream);
 
 /* Self-energy flowing with the vertex (Sec. 2 names self-energies as the
- * extension of the four-point flow; the form here is the reading of the design
- * notes): a static value S_j per patch, stored after the vertex, so that with
+ * extension of the four-point flow and gives no form; the one here is a
+ * reading): a static value S_j per patch, stored after the vertex, so that with
  * the switch on every V and F of frg_rhs, frg_flow_init, frg_flow_step and
  * frg_flow holds N^3 + N doubles ([V, S]).  Every loop line carries its patch's
  * S (the fine point's patch and the second line's), and
  *   dS_j/dT = sum_a D_a [2 V(j,a,j) - V(a,j,j)],
  *   D_a = sum_{p in a} w_p d/dT n_F((xi_p + S_a)/T)  (at fixed S),
- * in FP64 in both precisions.  Every bubble row is computed (no C4v row
- * reduction: S need not be symmetric), unpaired.  Polar and energy-angle grids,
- * single flows only (ENOTSUP in a batch); EINVAL while the symmetric-vertex mode is on (and
- * frg_set_vsym(1) is refused while the self-energy is on).  The interaction
- * flow (frg_rhs_full, frg_iflow*) ignores it.  Initial S = 0 is the caller's. */
+ * in FP64 in both precisions.
+ *   enable = 1: a general S; every bubble row is computed, unpaired.
+ *   enable = 2: the caller's S is C4v invariant (S(g j) = S(j)), which a flow
+ *               from a C4v-invariant V and S keeps: the bubble rows are then
+ *               still C4v images of each other and pp/ph pairs, and the C4v
+ *               row reduction applies as without a self-energy.  frg_flow_init
+ *               checks S (EINVAL beyond 1e-12 relative); a direct frg_rhs
+ *               call takes it on trust.  ENOTSUP on a grid without exact C4v
+ *               covariance (N % 8 != 0).
+ *   enable = 0: off.  Other values: EINVAL.
+ * Polar and energy-angle grids, single flows only (ENOTSUP in a batch); EINVAL
+ * while the symmetric-vertex mode is on (and frg_set_vsym(1) is refused while
+ * the self-energy is on).  The interaction flow (frg_rhs_full, frg_iflow*)
+ * ignores it.  Initial S = 0 is the caller's.  frg_self_energy reports the
+ * switch (0, 1 or 2). */
 frg_status frg_set_self_energy(frg_ctx ctx, int32_t enable);
 frg_status frg_self_energy(frg_ctx ctx, int32_t *active);
 

@@ -61,8 +61,10 @@ struct frg_ctx_s {
            *d_trig_pt = nullptr;
     uint8_t *d_bins = nullptr;
     int32_t *d_count = nullptr;   // energy-angle grid: live points per patch
-    // self-energy flowing with the vertex: V and F hold N^3 + N doubles (S after V)
-    bool se_on = false;
+    // self-energy flowing with the vertex: V and F hold N^3 + N doubles (S after V);
+    // se_sym: the caller's S is C4v invariant, so the bubble rows stay C4v images
+    // of each other and pp/ph pairs (checked at flow start)
+    bool se_on = false, se_sym = false;
     bool batch_member = false;    // owned by a batch (frg_batch_context)
     double *d_sigD = nullptr;     // [N] patch sums of the self-energy flow
     int32_t *d_colrow_pp = nullptr, *d_colrow_ph = nullptr;   // (row << 3): every row stored
@@ -789,9 +791,10 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     const int N = g.N;
     const size_t NN = static_cast<size_t>(N) * N;
     const int64_t n3 = ctx->n3;
-    // with a self-energy the rows are not C4v images of each other: every row
+    // with a general self-energy the rows are not C4v images of each other:
+    // every row; with a C4v-invariant one they are, and the pairs hold
     const bool se = ctx->se_on && mode == RHS_DT;
-    const bool sym = ctx->sym_on && !se;
+    const bool sym = ctx->sym_on && (!se || ctx->se_sym);
     const int KS = ksplit(ctx);
     const int64_t cs = chan_stride(ctx);
     if (!wsp) TRY(ensure_c(ctx));
@@ -867,6 +870,24 @@ frg_status vsym_deviation(frg_ctx ctx, const double *V, hipStream_t s, double *r
         vmax = std::max(vmax, h[nb + i]);
     }
     *rel = vmax > 0.0 ? dev / vmax : dev;
+    return FRG_OK;
+}
+
+// S (N doubles on the device) C4v invariant to 1e-12 relative: S(g j) = S(j)
+// for every C4v element g (synchronises the stream)
+frg_status check_se_sym(frg_ctx ctx, const double *d_S, hipStream_t s) {
+    const int N = ctx->g.N;
+    std::vector<double> S(static_cast<size_t>(N));
+    HIPCHK(hipMemcpyAsync(S.data(), d_S, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double dev = 0.0, smax = 0.0;
+    for (int j = 0; j < N; ++j) {
+        smax = std::max(smax, std::fabs(S[j]));
+        for (int o = 1; o < 8; ++o) dev = std::max(dev, std::fabs(S[c4v_patch_host(o, j, N)] - S[j]));
+    }
+    if (!(dev <= kVsymTol * smax))
+        return fail(FRG_EINVAL, "a C4v-invariant self-energy was announced, but S deviates by " +
+                                    std::to_string(dev) + " (max |S| " + std::to_string(smax) + ")");
     return FRG_OK;
 }
 
@@ -1293,6 +1314,7 @@ frg_status frg_flow_init(frg_ctx ctx, const frg_flow_opts *o, const double *d_V,
             return fail(FRG_EINVAL, "symmetric-vertex mode needs a C4v-invariant V (relative deviation " +
                                         std::to_string(dev) + ")");
     }
+    if (ctx->se_on && ctx->se_sym) TRY(check_se_sym(ctx, d_V + ctx->n3, static_cast<hipStream_t>(stream)));
     TRY(ensure_rhs_ws(ctx, o->prec));
     TRY(ensure_flow_ws(ctx));
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1424,7 +1446,7 @@ static frg_status flow_step_graph(frg_ctx ctx, const frg_flow_opts *o, double *V
                                      static_cast<double>(o->stepper), static_cast<double>(o->prec), o->rtol,
                                      o->atol, o->vmax, static_cast<double>(o->max_steps), iflow ? 1.0 : 0.0,
                                      ctx->sym_on ? 1.0 : 0.0, ctx->vsym_on ? 1.0 : 0.0, ctx->kskip_on ? 1.0 : 0.0,
-                                     ctx->se_on ? 1.0 : 0.0,
+                                     ctx->se_on ? 1.0 : 0.0, ctx->se_sym ? 1.0 : 0.0,
                                      P(ctx->d_C), static_cast<double>(ctx->c_elems),
                                      static_cast<double>(ctx->ws_gen)};
     auto &g = ctx->sg;
@@ -1721,18 +1743,22 @@ frg_status frg_set_vsym(frg_ctx ctx, int32_t enable) {
 
 frg_status frg_set_self_energy(frg_ctx ctx, int32_t enable) {
     TRY(check_ctx(ctx));
+    if (enable < 0 || enable > 2) return fail(FRG_EINVAL, "self-energy switch: 0, 1 (general) or 2 (C4v invariant)");
     if (enable && ctx->vsym_on)
         return fail(FRG_EINVAL, "switch the symmetric-vertex mode off before the self-energy");
     if (enable && ctx->batch_member)
         return fail(FRG_ENOTSUP, "the self-energy runs on single flows only");
+    if (enable == 2 && !ctx->sym_avail)
+        return fail(FRG_ENOTSUP, "a C4v-invariant self-energy needs an exactly C4v covariant grid (N % 8 == 0)");
     if (enable && !ctx->d_sigD) TRY(dalloc(ctx, &ctx->d_sigD, static_cast<size_t>(ctx->g.N)));
     ctx->se_on = enable != 0;
+    ctx->se_sym = enable == 2;
     return FRG_OK;
 }
 
 frg_status frg_self_energy(frg_ctx ctx, int32_t *active) {
     TRY(check_ctx(ctx));
-    if (active) *active = ctx->se_on ? 1 : 0;
+    if (active) *active = ctx->se_on ? (ctx->se_sym ? 2 : 1) : 0;
     return FRG_OK;
 }
 

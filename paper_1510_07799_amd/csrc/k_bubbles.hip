@@ -255,11 +255,13 @@ size_t bubble_lds_bytes(int N, bool paired) {
 // batched kernel and the paired single-flow kernel, which then stay within 128
 // registers; the unpaired single-flow kernel spills with it)
 // SE: a self-energy per patch (A.sigma) shifts the second line's energy by
-// its bin's value (unpaired rows, dL/dT only); the table S/2T sits in LDS
-// after the point data.
+// its bin's value (dL/dT only); the table S/2T sits in LDS after the point
+// data.  A pair takes the pp row's bin: the ph row's bin is the pp bin + N/2,
+// whose self-energy is the same when S is C4v invariant (the host pairs rows
+// only then), so the ph energy stays the negative of the pp one.
 template <int P, bool F32, bool FULL, bool PAIRED, bool PF, bool SE = false>
 __device__ __forceinline__ void bubble_body(const BubbleArgs &A, int chunk, int a_patch, double *smem, int rpb) {
-    static_assert(!SE || (!PAIRED && !FULL), "self-energy rows are unpaired dL/dT rows");
+    static_assert(!SE || !FULL, "self-energy rows are dL/dT rows");
     using PT = typename std::conditional<F32, float, double>::type;
     // The lane's P points (table positions lane*P .. lane*P+P-1, angular
     // neighbours at one radius): in registers for every row (split path with up
@@ -628,10 +630,10 @@ size_t seg_lds_bytes(int N, bool paired, int rpb, bool se) {
 }
 
 // SE: the second line's energy carries its bin's self-energy (A.sigma, as S/2T
-// in LDS after the point data); unpaired dL/dT rows only
+// in LDS after the point data); dL/dT rows only, paired as in bubble_body
 template <bool F32, bool FULL, bool PAIRED, bool SE = false>
 __global__ __launch_bounds__(kThreads) void bubble_seg_kernel(BubbleArgs A, int rpb) {
-    static_assert(!SE || (!PAIRED && !FULL), "self-energy rows are unpaired dL/dT rows");
+    static_assert(!SE || !FULL, "self-energy rows are dL/dT rows");
     extern __shared__ double smem[];
     using PT = typename std::conditional<F32, float, double>::type;
     constexpr int P = kSegP;
@@ -848,15 +850,21 @@ void launch_seg(const BubbleArgs &a, hipStream_t s) {
     const bool paired = a.rowlist_ph != nullptr;
     const int rpb = seg_rows_per_block<F32>(a.N, paired, a.rpb);
     dim3 grid((a.nrows + rpb - 1) / rpb, a.N);
-    const bool se = a.sigma != nullptr && !paired && !FULL;   // the host pairs no rows with a self-energy
+    const bool se = a.sigma != nullptr && !FULL;   // dL/dT rows only
     const size_t lds = seg_lds_bytes<F32>(a.N, paired, rpb, se);
-    if (paired)
+    if (se) {
+        if constexpr (!FULL) {
+            if (paired)
+                hipLaunchKernelGGL((bubble_seg_kernel<F32, false, true, true>), grid, dim3(kThreads), lds, s, a, rpb);
+            else
+                hipLaunchKernelGGL((bubble_seg_kernel<F32, false, false, true>), grid, dim3(kThreads), lds, s, a,
+                                   rpb);
+        }
+    } else if (paired) {
         hipLaunchKernelGGL((bubble_seg_kernel<F32, FULL, true>), grid, dim3(kThreads), lds, s, a, rpb);
-    else if (se) {
-        if constexpr (!FULL)
-            hipLaunchKernelGGL((bubble_seg_kernel<F32, false, false, true>), grid, dim3(kThreads), lds, s, a, rpb);
-    } else
+    } else {
         hipLaunchKernelGGL((bubble_seg_kernel<F32, FULL, false>), grid, dim3(kThreads), lds, s, a, rpb);
+    }
 }
 
 template <int P, bool F32, bool FULL, bool PAIRED, bool SE = false>
@@ -884,13 +892,11 @@ void launch_pp(const BubbleArgs &a, bool fp32, bool full, hipStream_t s) {
     const int rpb = a.rpb > 0 ? a.rpb : kRowsPerBlock;
     dim3 grid((a.nrows + rpb - 1) / rpb, a.N);
     const size_t lds = fp32 ? bubble_lds_bytes<P, true>(a.N, PAIRED) : bubble_lds_bytes<P, false>(a.N, PAIRED);
-    if constexpr (!PAIRED) {
-        if (a.sigma && !full) {   // the host allows a self-energy only with unpaired dL/dT rows
-            const size_t l = lds + sizeof(double) * static_cast<size_t>(a.N);
-            if (fp32) hipLaunchKernelGGL((bubble_kernel<P, true, false, false, true>), grid, dim3(kThreads), l, s, a);
-            else hipLaunchKernelGGL((bubble_kernel<P, false, false, false, true>), grid, dim3(kThreads), l, s, a);
-            return;
-        }
+    if (a.sigma && !full) {   // a self-energy: dL/dT rows only (paired when it is C4v invariant)
+        const size_t l = lds + sizeof(double) * static_cast<size_t>(a.N);
+        if (fp32) hipLaunchKernelGGL((bubble_kernel<P, true, false, PAIRED, true>), grid, dim3(kThreads), l, s, a);
+        else hipLaunchKernelGGL((bubble_kernel<P, false, false, PAIRED, true>), grid, dim3(kThreads), l, s, a);
+        return;
     }
     if (fp32 && !full)
         hipLaunchKernelGGL((bubble_kernel<P, true, false, PAIRED>), grid, dim3(kThreads), lds, s, a);

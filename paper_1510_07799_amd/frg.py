@@ -394,14 +394,19 @@ class Context:
     def flow_step(self, opts: FlowOpts, V, state):
         _check(lib().frg_flow_step(self._h, C.byref(opts), _ptr(V), _ptr(state), _stream()))
 
-    def set_self_energy(self, enable: bool):
-        """frg_set_self_energy: V and F then hold N^3 + N doubles (the self-energy after V)."""
-        _check(lib().frg_set_self_energy(self._h, 1 if enable else 0))
+    def set_self_energy(self, enable: bool, symmetric: bool = False):
+        """frg_set_self_energy: V and F then hold N^3 + N doubles (the self-energy after V);
+        symmetric: the self-energy is C4v invariant (switch value 2)."""
+        _check(lib().frg_set_self_energy(self._h, (2 if symmetric else 1) if enable else 0))
 
     def self_energy(self) -> bool:
+        return self.self_energy_mode() != 0
+
+    def self_energy_mode(self) -> int:
+        """0 off, 1 general, 2 C4v invariant."""
         a = C.c_int32()
         _check(lib().frg_self_energy(self._h, C.byref(a)))
-        return bool(a.value)
+        return int(a.value)
 
     def rhs_se(self, T: float, V, S, prec=PREC_FP64):
         """(dV/dT, dS/dT) with the self-energy on (switched on here if it is not)."""

@@ -198,3 +198,120 @@ def test_captured_steps_equal_eager_steps_with_self_energy():
     assert np.array_equal(ye, yg)
     assert np.array_equal(se, sg, equal_nan=True)
     assert np.abs(ye[N ** 3:]).max() > 0.0
+
+
+# ---- a C4v-invariant self-energy (switch value 2): row reduction and pairs
+
+def symmetric_S(N, seed, amp=0.3):
+    """A random self-energy averaged over the C4v images of the patches."""
+    rng = np.random.default_rng(seed)
+    S = amp * rng.standard_normal(N)
+    return np.mean([S[I.c4v_patch_perm(N, o)] for o in range(8)], axis=0)
+
+
+@pytest.mark.parametrize("p", [P16, P24], ids=["n16", "n24"])
+def test_symmetric_self_energy_rhs_against_the_oracle(p):
+    """With S C4v invariant the bubble rows are computed per C4v orbit with the
+    pp/ph pairs; the rhs (any V) and dS/dT still match the oracle, and the
+    general mode on the GPU."""
+    N = p["N"]
+    m, g = O.Model(**p), frg.Context(**p)
+    g.set_self_energy(True, symmetric=True)
+    assert g.self_energy_mode() == 2
+    active, rows = g.symmetry()
+    assert active and rows < (g.Tpp + g.Tph) / 6
+    V = I.random_vertex(N, p["U"], seed=611, amp=0.4, symmetrise=False)
+    S = symmetric_S(N, 612)
+    for T in (1.0, 0.05, 1e-3):
+        Fr, dSr = m.rhs_se(T, V, S)
+        for prec, tol in ((frg.PREC_FP64, 1e-10), (frg.PREC_SPLIT_BF16, 2e-4)):
+            F, dS = g.rhs_se(T, dev(V), dev(S), prec)
+            F2, dS2 = F.cpu().numpy(), dS.cpu().numpy()
+            eF, eS = nrel(F2, Fr), nrel(dS2, dSr)
+            g.set_self_energy(True)   # the general mode: every row, unpaired
+            Fg, dSg = g.rhs_se(T, dev(V), dev(S), prec)
+            g.set_self_energy(True, symmetric=True)
+            eG = nrel(F2, Fg.cpu().numpy())
+            print(f"[se sym rhs] N={N} T={T} prec={prec}: F {eF:.2e} dS {eS:.2e}; against the general mode {eG:.2e}",
+                  flush=True)
+            assert eF <= tol and eS <= 1e-12
+            if prec == frg.PREC_FP64:
+                assert eG <= 1e-12
+    g.close()
+
+
+def test_symmetric_self_energy_flow_step_for_step():
+    """A DP5(4) FP64 flow of (V, S) from V = U, S = 0 (both stay C4v invariant)
+    with the reduced, paired sweep, against the oracle step for step and
+    against the general mode on the GPU.  The reduced sweep sums a patch's
+    points in another order than the oracle (and than the general mode); the
+    step control's error estimate, a difference of two nearly equal
+    solutions, lifts that rounding to ~1e-8 in the step sizes, hence 1e-7
+    (the rhs itself is checked to 1e-10 above)."""
+    p = P16
+    N = p["N"]
+    m, g = O.Model(**p), frg.Context(**p)
+    f = dict(stepper="dp54", T0=1.0, T_min=0.05, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.01)
+    Vo, So, ro, logo = m.flow_se(**f)
+    runs = {}
+    for symmetric in (True, False):
+        g.set_self_energy(True, symmetric=symmetric)
+        y = torch.cat([torch.full((N ** 3,), float(p["U"]), dtype=torch.float64, device="cuda"),
+                       torch.zeros(N, dtype=torch.float64, device="cuda")]).contiguous()
+        rg, logg = g.flow(y, frg.flow_opts(prec=frg.PREC_FP64, **f))
+        runs[symmetric] = (rg, logg, y.cpu().numpy())
+    rg, logg, yg = runs[True]
+    rg1, logg1, yg1 = runs[False]
+    es = float(np.abs(logg[:, 0] - logo[:, 0]).max())
+    eV, eS = nrel(yg[:N ** 3].reshape(N, N, N), Vo), nrel(yg[N ** 3:], So)
+    eV1 = nrel(yg[:N ** 3], yg1[:N ** 3])
+    print(f"[se sym flow] oracle {ro['accepted']}/{ro['rejected']} reason {ro['reason']}; GPU {rg['accepted']}/"
+          f"{rg['rejected']} reason {rg['reason']}; s {es:.1e}, V {eV:.1e}, S {eS:.1e}; against the general "
+          f"mode V {eV1:.1e}; S range {So.min():.4f}..{So.max():.4f}", flush=True)
+    assert (rg["accepted"], rg["rejected"], rg["reason"]) == (ro["accepted"], ro["rejected"], ro["reason"])
+    assert (rg1["accepted"], rg1["rejected"], rg1["reason"]) == (ro["accepted"], ro["rejected"], ro["reason"])
+    assert es <= 1e-7 and eV <= 1e-7 and eS <= 1e-7 and eV1 <= 1e-7
+    assert np.abs(So).max() > 1e-3
+    g.close()
+
+
+def test_symmetric_self_energy_on_the_energy_angle_grid():
+    p = dict(t=1.0, tp=-0.3, mu=-1.2, U=3.0, N=24, n_rad=1, n_ang=1, egrid=dict(n_E=32, max_level=4, rtol=1e-4))
+    N = p["N"]
+    m, g = O.Model(**p), frg.Context(**p)
+    g.set_self_energy(True, symmetric=True)
+    V = I.random_vertex(N, p["U"], seed=613, amp=0.4, symmetrise=False)
+    S = symmetric_S(N, 614)
+    for T in (0.5, 0.02):
+        Fr, dSr = m.rhs_se(T, V, S)
+        for prec, tol in ((frg.PREC_FP64, 1e-10), (frg.PREC_SPLIT_BF16, 2e-4)):
+            F, dS = g.rhs_se(T, dev(V), dev(S), prec)
+            eF, eS = nrel(F.cpu().numpy(), Fr), nrel(dS.cpu().numpy(), dSr)
+            print(f"[se sym egrid] T={T} prec={prec}: F {eF:.2e} dS {eS:.2e}", flush=True)
+            assert eF <= tol and eS <= 1e-12
+    g.close()
+
+
+def test_symmetric_self_energy_rules():
+    """The flow refuses a self-energy that is not C4v invariant; grids without
+    exact C4v covariance refuse the switch value 2."""
+    p = P16
+    N = p["N"]
+    g = frg.Context(**p)
+    g.set_self_energy(True, symmetric=True)
+    S = symmetric_S(N, 615)
+    S[0] += 0.1
+    y = torch.cat([torch.full((N ** 3,), float(p["U"]), dtype=torch.float64, device="cuda"),
+                   torch.from_numpy(S).cuda()]).contiguous()
+    st = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+    o = frg.flow_opts("dp54", frg.PREC_FP64, T0=1.0, T_min=0.1, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.01)
+    with pytest.raises(frg.FRGError) as e:
+        g.flow_init(o, y, st)
+    assert e.value.status == frg.EINVAL
+    assert frg.lib().frg_set_self_energy(g.handle, 3) == frg.EINVAL
+    g.close()
+    g12 = frg.Context(t=1.0, tp=-0.2, mu=-0.6, U=2.0, N=12, n_rad=6, n_ang=6)
+    with pytest.raises(frg.FRGError) as e:
+        g12.set_self_energy(True, symmetric=True)
+    assert e.value.status == frg.ENOTSUP
+    g12.close()
