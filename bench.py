@@ -462,21 +462,24 @@ def main():
     se_leg = None
     if "se" in legs:
         # the vertex and a self-energy per patch flowing together (N = 96, 512
-        # points per patch), every contraction column: with the self-energy
-        # announced C4v invariant (the flow from V = U, S = 0 keeps it so) the
-        # bubble rows are computed per C4v orbit and paired; in the general
-        # mode every row
+        # points per patch): with the self-energy announced C4v invariant (the
+        # flow from V = U, S = 0 keeps it so) as without one (bubble rows per C4v
+        # orbit, paired; one contraction column per orbit; reduced flow state);
+        # in the general mode every row and every column
         cs_ = frg.Context(**p)
-        cs_.set_vsym(False)
         Vse = torch.cat([torch.full((N ** 3,), float(p["U"]), dtype=torch.float64, device="cuda"),
                          torch.zeros(N, dtype=torch.float64, device="cuda")]).contiguous()
         se_leg = {"workload": "N=96, 512 points/patch, t'=-0.3 mu=-1.2 U=3; vertex and self-energy per patch "
-                              "flowing together (DP5(4) steps from V=U, S=0 at T=1); every contraction column; "
-                              "c4v_invariant_S: bubble rows per C4v orbit, paired; general_S: every bubble row"}
+                              "flowing together (DP5(4) steps from V=U, S=0 at T=1); c4v_invariant_S: bubble "
+                              "rows per C4v orbit, paired, one contraction column per orbit, reduced flow state; "
+                              "general_S: every bubble row, every column"}
         for symmetric, mode in ((True, "c4v_invariant_S"), (False, "general_S")):
+            cs_.set_self_energy(False)
+            cs_.set_vsym(symmetric)
             cs_.set_self_energy(True, symmetric=symmetric)
             se_leg[mode] = {}
             for prec, nm in ((frg.PREC_SPLIT_BF16, "split"), (frg.PREC_FP64, "fp64")):
+                TU.apply(cs_, TU.lookup(N, nf, prec == frg.PREC_SPLIT_BF16, symmetric, 1, table))
                 dt, prof, st = timed_flow_steps(frg, torch, cs_, prec, Vse, args.steps, args.warmup)
                 progress(f"leg se {mode} {nm}: {RHS_PER_STEP * args.steps / dt:.1f} rhs/s")
                 se_leg[mode][nm] = {"rhs_per_s": round(RHS_PER_STEP * args.steps / dt, 3),

@@ -212,9 +212,10 @@ frg_status ensure_flow_ws(frg_ctx ctx) {
     TRY(dalloc(ctx, &ctx->d_yt, nfull));
     TRY(dalloc(ctx, &ctx->d_y5, nfull));
     if (ctx->nst > 0) {
-        TRY(dalloc(ctx, &ctx->d_yr, static_cast<size_t>(ctx->nst)));
-        TRY(dalloc(ctx, &ctx->d_ytr, static_cast<size_t>(ctx->nst)));
-        TRY(dalloc(ctx, &ctx->d_y5r, static_cast<size_t>(ctx->nst)));
+        // a reduced stage vector holds nst entries and, with a self-energy, N more
+        TRY(dalloc(ctx, &ctx->d_yr, static_cast<size_t>(ctx->nst + ctx->g.N)));
+        TRY(dalloc(ctx, &ctx->d_ytr, static_cast<size_t>(ctx->nst + ctx->g.N)));
+        TRY(dalloc(ctx, &ctx->d_y5r, static_cast<size_t>(ctx->nst + ctx->g.N)));
     }
     TRY(dalloc(ctx, &ctx->d_partial, 2 * static_cast<size_t>(ctx->nred)));
     TRY(dalloc(ctx, &ctx->d_state, FRG_STATE_LEN));
@@ -674,7 +675,10 @@ const int32_t *col_pos(frg_ctx ctx, int cls) { return tiles_of(ctx, cls).d_cmap;
 // Flows keep their stage vectors reduced while the orbit columns are computed:
 // the rhs is then known at the representative columns only, and every other
 // entry is a copy (a C4v-invariant vertex stays invariant).
-bool red_state(frg_ctx ctx) { return ctx->vsym_on && ctx->kskip_on && ctx->nst > 0 && !ctx->se_on; }
+// A C4v-invariant self-energy rides along after the nst reduced entries.
+bool red_state(frg_ctx ctx) {
+    return ctx->vsym_on && ctx->kskip_on && ctx->nst > 0 && (!ctx->se_on || ctx->se_sym);
+}
 // K parts of the column set in use
 int ksplit(frg_ctx ctx) { return tiles_of(ctx, 0).kparts; }
 
@@ -795,6 +799,9 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     // every row; with a C4v-invariant one they are, and the pairs hold
     const bool se = ctx->se_on && mode == RHS_DT;
     const bool sym = ctx->sym_on && (!se || ctx->se_sym);
+    // the self-energy: after V, or, when a split stage of a reduced flow hands
+    // over the reduced vector itself (V == Vred), after its nst entries
+    const double *Sv = se ? (Vred ? Vred + ctx->nst : V + ctx->n3) : nullptr;
     const int KS = ksplit(ctx);
     const int64_t cs = chan_stride(ctx);
     if (!wsp) TRY(ensure_c(ctx));
@@ -804,8 +811,7 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
     void *bph = split ? static_cast<void *>(w.B32 + NN * npp_rows) : static_cast<void *>(w.B64 + NN * npp_rows);
     if (mode != RHS_STORED) {
         if (w.own) ctx->iflow_prec = -1;   // the context's bubble buffer is overwritten
-        TRY(run_bubbles(ctx, split, T_host, state, c, bpp, bph, s, sym, mode == RHS_FULL, &w,
-                        se ? V + n3 : nullptr));
+        TRY(run_bubbles(ctx, split, T_host, state, c, bpp, bph, s, sym, mode == RHS_FULL, &w, Sv));
     }
     double *Cpp = w.C, *Cc = w.C + KS * cs, *Cd = w.C + 2 * KS * cs;
     frg::FusedContractArgs a;
@@ -845,7 +851,8 @@ frg_status run_rhs(frg_ctx ctx, bool split, double T_host, const double *state, 
             frg::launch_combine(Cs, Cs + cs, Cs + 2 * cs, false, N, 1, col_pos(ctx, 0), col_pos(ctx, 1),
                                 ctx->d_perm8, w.T, scale_by_T, F, s);
         if (se)   // the self-energy's derivative after F (always FP64)
-            frg::launch_dsigma(ctx->d_xi, ctx->d_w, N, g.nf, V, V + n3, w.T, scale_by_T, ctx->d_sigD, F + n3, s);
+            frg::launch_dsigma(ctx->d_xi, ctx->d_w, N, g.nf, Vred ? Vred : V, Sv, w.T, scale_by_T, ctx->d_sigD,
+                               F + (red_out ? ctx->nst : n3), s, Vred ? col_pos(ctx, 0) : nullptr);
     }
     HIPCHK(hipGetLastError());
     return FRG_OK;
@@ -1351,9 +1358,11 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
     // reduced state: the stages combine nst-entry vectors (y gathered from V),
     // and each stage input is expanded into a full vertex for the rhs
     const bool red = red_state(ctx);
-    // the self-energy flows in the same array, after V
-    const int64_t n = red ? ctx->nst : ctx->n3 + (ctx->se_on && !iflow ? ctx->g.N : 0);
+    // the self-energy flows in the same array, after V (after the reduced
+    // entries in a reduced state)
+    const bool se = ctx->se_on && !iflow;
     const int N = ctx->g.N;
+    const int64_t n = (red ? ctx->nst : ctx->n3) + (se ? N : 0);
     double *y = red ? ctx->d_yr : V, *yt = red ? ctx->d_ytr : ctx->d_yt, *y5 = red ? ctx->d_y5r : ctx->d_y5;
     const int32_t *cperm = tiles_of(ctx, 0).d_cperm, *cmap = col_pos(ctx, 0);
     // the rhs input of a stage whose combination went to out (its full form;
@@ -1363,16 +1372,22 @@ static frg_status flow_step_impl(frg_ctx ctx, const frg_flow_opts *o, double *V,
         double *full = out == y5 ? ctx->d_y5 : ctx->d_yt;
         KTimer kt(ctx, FRG_K_RK, s);
         frg::launch_vred_expand(out, N, cmap, ctx->d_perm8, nullptr, full, s);
+        if (se) frg::launch_accept_copy(N, nullptr, out + ctx->nst, full + ctx->n3, s);
         return full;
     };
     // accepted step: V <- y5 (expanded when reduced)
     auto accept_v = [&]() {
-        if (red) frg::launch_vred_expand(y5, N, cmap, ctx->d_perm8, state, V, s);
-        else frg::launch_accept_copy(n, state, y5, V, s);
+        if (red) {
+            frg::launch_vred_expand(y5, N, cmap, ctx->d_perm8, state, V, s);
+            if (se) frg::launch_accept_copy(N, state, y5 + ctx->nst, V + ctx->n3, s);
+        } else {
+            frg::launch_accept_copy(n, state, y5, V, s);
+        }
     };
     if (red) {
         KTimer kt(ctx, FRG_K_RK, s);
-        frg::launch_vred_gather(V, N, cperm, n, y, s);
+        frg::launch_vred_gather(V, N, cperm, ctx->nst, y, s);
+        if (se) frg::launch_accept_copy(N, nullptr, V + ctx->n3, y + ctx->nst, s);
     }
     frg::RkStageArgs sa;
     std::memset(&sa, 0, sizeof(sa));
@@ -1573,14 +1588,19 @@ frg_status convert_k0(frg_ctx ctx, bool was_red) {
     if (was_red == now || !ctx->d_k[0] || !ctx->d_ytr) return FRG_OK;
     HIPCHK(hipDeviceSynchronize());
     const int N = ctx->g.N;
+    // a self-energy's N entries follow the nst reduced or the N^3 full entries
+    const size_t tail = ctx->se_on ? static_cast<size_t>(N) : 0;
+    double *k0 = ctx->d_k[0];
     if (now) {
-        frg::launch_vred_gather(ctx->d_k[0], N, ctx->ts_vsym[0].d_cperm, ctx->nst, ctx->d_ytr, nullptr);
+        frg::launch_vred_gather(k0, N, ctx->ts_vsym[0].d_cperm, ctx->nst, ctx->d_ytr, nullptr);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpy(ctx->d_k[0], ctx->d_ytr, sizeof(double) * ctx->nst, hipMemcpyDeviceToDevice));
+        if (tail) HIPCHK(hipMemcpy(ctx->d_ytr + ctx->nst, k0 + ctx->n3, sizeof(double) * tail, hipMemcpyDeviceToDevice));
+        HIPCHK(hipMemcpy(k0, ctx->d_ytr, sizeof(double) * (ctx->nst + tail), hipMemcpyDeviceToDevice));
     } else {
-        frg::launch_vred_expand(ctx->d_k[0], N, ctx->ts_vsym[0].d_cmap, ctx->d_perm8, nullptr, ctx->d_yt, nullptr);
+        if (tail) HIPCHK(hipMemcpy(ctx->d_yt + ctx->n3, k0 + ctx->nst, sizeof(double) * tail, hipMemcpyDeviceToDevice));
+        frg::launch_vred_expand(k0, N, ctx->ts_vsym[0].d_cmap, ctx->d_perm8, nullptr, ctx->d_yt, nullptr);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpy(ctx->d_k[0], ctx->d_yt, sizeof(double) * ctx->n3, hipMemcpyDeviceToDevice));
+        HIPCHK(hipMemcpy(k0, ctx->d_yt, sizeof(double) * (ctx->n3 + tail), hipMemcpyDeviceToDevice));
     }
     HIPCHK(hipDeviceSynchronize());
     return FRG_OK;
@@ -1732,8 +1752,8 @@ frg_status frg_symmetry(frg_ctx ctx, int32_t *active, int32_t *rows_computed) {
 
 frg_status frg_set_vsym(frg_ctx ctx, int32_t enable) {
     TRY(check_ctx(ctx));
-    if (enable && ctx->se_on)
-        return fail(FRG_EINVAL, "symmetric-vertex mode with a flowing self-energy is not supported");
+    if (enable && ctx->se_on && !ctx->se_sym)
+        return fail(FRG_EINVAL, "symmetric-vertex mode with a general (not C4v-invariant) self-energy");
     if (enable && !ctx->sym_avail)
         return fail(FRG_ENOTSUP, "symmetric-vertex mode needs an exactly C4v covariant grid (N % 8 == 0)");
     const bool was_red = red_state(ctx);
@@ -1744,8 +1764,8 @@ frg_status frg_set_vsym(frg_ctx ctx, int32_t enable) {
 frg_status frg_set_self_energy(frg_ctx ctx, int32_t enable) {
     TRY(check_ctx(ctx));
     if (enable < 0 || enable > 2) return fail(FRG_EINVAL, "self-energy switch: 0, 1 (general) or 2 (C4v invariant)");
-    if (enable && ctx->vsym_on)
-        return fail(FRG_EINVAL, "switch the symmetric-vertex mode off before the self-energy");
+    if (enable == 1 && ctx->vsym_on)
+        return fail(FRG_EINVAL, "a general self-energy needs the symmetric-vertex mode off");
     if (enable && ctx->batch_member)
         return fail(FRG_ENOTSUP, "the self-energy runs on single flows only");
     if (enable == 2 && !ctx->sym_avail)

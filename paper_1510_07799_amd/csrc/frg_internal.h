@@ -54,9 +54,11 @@ void launch_point_prep(const double *xi, const double *w, int np, double T_host,
 
 // self-energy flow (one value per patch): D[a] = sum_{p in a} w_p d/dT n_F((xi_p + S_a)/T)
 // (one block per patch, fixed-order sums), then
-// dS[j] = scale * sum_a D[a] (2 V(j,a,j) - V(a,j,j)), scale = T when scale_by_T
+// dS[j] = scale * sum_a D[a] (2 V(j,a,j) - V(a,j,j)), scale = T when scale_by_T;
+// V a full vertex, or a reduced flow state when ppos (the pp column map) is given
 void launch_dsigma(const double *xi, const double *w, int N, int nf, const double *V, const double *S,
-                   const double *Tdev, int scale_by_T, double *D, double *dS, hipStream_t s);
+                   const double *Tdev, int scale_by_T, double *D, double *dS, hipStream_t s,
+                   const int32_t *ppos = nullptr);
 
 struct BubbleArgs {
     int N, nf, np, Tpp, Trows;
@@ -208,6 +210,7 @@ void launch_vred_expand(const double *Vr, int N, const int32_t *cmap, const int1
 void launch_combine_red(const double *Cs, int64_t cs, int N, int64_t nst, const int32_t *cperm,
                         const int32_t *phpos, const int16_t *perm8, const double *Tdev, int scale_by_T, double *F,
                         hipStream_t s);
+// dst <- src when the flow state says the step was accepted (state null: always)
 void launch_accept_copy(int64_t n, const double *state, const double *src, double *dst,
                         hipStream_t s);
 void launch_state_init(double *state, double s0, double h, double s_min, hipStream_t s);

@@ -203,19 +203,31 @@ __global__ __launch_bounds__(256) void dsigma_patch_kernel(const double *__restr
     if (threadIdx.x == 0) D[a] = part[0];
 }
 
-// dS_j = scale * sum_a D_a (2 V(j,a,j) - V(a,j,j)): thread j, a in order
+// dS_j = scale * sum_a D_a (2 V(j,a,j) - V(a,j,j)): block j, thread a, summed
+// by a fixed tree (bit-reproducible).  V is the full vertex, or (ppos given) a
+// reduced flow state read through the pp column map: V(a, b, m) =
+// Vr[pos N + patch of m under the column's element] with (pos, element) =
+// ppos[a N + b], the same values an expansion writes.  N <= 256.
 __global__ __launch_bounds__(256) void dsigma_kernel(int N, const double *__restrict__ V,
+                                                     const int32_t *__restrict__ ppos,
                                                      const double *__restrict__ D,
                                                      const double *__restrict__ Tdev, int scale_by_T,
                                                      double *__restrict__ dS) {
-    const int j = threadIdx.x;
-    if (j >= N) return;
+    __shared__ double part[256];
+    const int j = blockIdx.x, a = threadIdx.x;
     const size_t NN = static_cast<size_t>(N) * N;
-    double acc = 0.0;
-    for (int a = 0; a < N; ++a)
-        acc += D[a] * (2.0 * V[static_cast<size_t>(j) * NN + static_cast<size_t>(a) * N + j] -
-                       V[static_cast<size_t>(a) * NN + static_cast<size_t>(j) * N + j]);
-    dS[j] = (scale_by_T ? Tdev[0] : 1.0) * acc;
+    auto at = [&](int x, int y, int m) -> double {
+        if (!ppos) return V[static_cast<size_t>(x) * NN + static_cast<size_t>(y) * N + m];
+        const int32_t cm = ppos[x * N + y];
+        return V[static_cast<size_t>(cm >> 3) * N + c4v_patch(cm & 7, m, N)];
+    };
+    part[a] = a < N ? D[a] * (2.0 * at(j, a, j) - at(a, j, j)) : 0.0;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (a < h) part[a] += part[a + h];
+        __syncthreads();
+    }
+    if (a == 0) dS[j] = (scale_by_T ? Tdev[0] : 1.0) * part[0];
 }
 
 // Contraction operands of V (each N^3; row m = i, contraction index
@@ -951,7 +963,7 @@ __global__ void control_kernel(double *state, double *log, int log_cap, double v
 
 __global__ void accept_copy_kernel(int64_t n, const double *state, const double *__restrict__ src,
                                    double *__restrict__ dst) {
-    if (state[23] == 0.0) return;
+    if (state && state[23] == 0.0) return;   // no state: copy unconditionally
     const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[i];
 }
@@ -1198,9 +1210,10 @@ void launch_point_prep(const double *xi, const double *w, int np, double T_host,
 }
 
 void launch_dsigma(const double *xi, const double *w, int N, int nf, const double *V, const double *S,
-                   const double *Tdev, int scale_by_T, double *D, double *dS, hipStream_t s) {
+                   const double *Tdev, int scale_by_T, double *D, double *dS, hipStream_t s,
+                   const int32_t *ppos) {
     hipLaunchKernelGGL(dsigma_patch_kernel, dim3(N), dim3(256), 0, s, xi, w, nf, S, Tdev, D);
-    hipLaunchKernelGGL(dsigma_kernel, dim3(1), dim3(256), 0, s, N, V, D, Tdev, scale_by_T, dS);
+    hipLaunchKernelGGL(dsigma_kernel, dim3(N), dim3(256), 0, s, N, V, ppos, D, Tdev, scale_by_T, dS);
 }
 
 int layout_blocks(int N) {

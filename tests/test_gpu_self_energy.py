@@ -143,9 +143,11 @@ def test_self_energy_on_the_energy_angle_grid():
 def test_switch_rules():
     g = frg.Context(**P16)
     g.set_vsym(True)
-    with pytest.raises(frg.FRGError) as e:
+    with pytest.raises(frg.FRGError) as e:   # a general self-energy breaks the orbit columns
         g.set_self_energy(True)
     assert e.value.status == frg.EINVAL
+    g.set_self_energy(True, symmetric=True)    # a C4v-invariant one does not
+    g.set_self_energy(False)
     g.set_vsym(False)
     g.set_self_energy(True)
     with pytest.raises(frg.FRGError) as e:
@@ -315,3 +317,112 @@ def test_symmetric_self_energy_rules():
         g12.set_self_energy(True, symmetric=True)
     assert e.value.status == frg.ENOTSUP
     g12.close()
+
+
+# ---- a C4v-invariant self-energy with the symmetric-vertex mode (orbit columns,
+#      reduced flow state with S after the reduced entries)
+
+@pytest.mark.parametrize("p", [P16, P24], ids=["n16", "n24"])
+def test_symmetric_self_energy_in_symmetric_vertex_mode_rhs(p):
+    N = p["N"]
+    m, g = O.Model(**p), frg.Context(**p)
+    g.set_vsym(True)
+    g.set_self_energy(True, symmetric=True)
+    V = I.random_vertex(N, p["U"], seed=621, amp=0.4, symmetrise=True)
+    S = symmetric_S(N, 622)
+    for T in (1.0, 0.05, 1e-3):
+        Fr, dSr = m.rhs_se(T, V, S)
+        for prec, tol in ((frg.PREC_FP64, 1e-10), (frg.PREC_SPLIT_BF16, 2e-4)):
+            F, dS = g.rhs_se(T, dev(V), dev(S), prec)
+            eF, eS = nrel(F.cpu().numpy(), Fr), nrel(dS.cpu().numpy(), dSr)
+            print(f"[se vsym rhs] N={N} T={T} prec={prec}: F {eF:.2e} dS {eS:.2e}", flush=True)
+            assert eF <= tol and eS <= 1e-12
+    g.close()
+
+
+def test_symmetric_self_energy_in_symmetric_vertex_mode_flow():
+    """DP5(4) FP64 flow of (V, S) from V = U, S = 0 with the reduced flow state
+    (S after the reduced entries): the oracle's steps, and the same flow
+    without the symmetric-vertex mode (tolerances as in the flow test above)."""
+    p = P16
+    N = p["N"]
+    m, g = O.Model(**p), frg.Context(**p)
+    f = dict(stepper="dp54", T0=1.0, T_min=0.05, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.01)
+    Vo, So, ro, logo = m.flow_se(**f)
+    runs = {}
+    for vsym in (True, False):
+        g.set_self_energy(False)
+        g.set_vsym(vsym)
+        g.set_self_energy(True, symmetric=True)
+        y = torch.cat([torch.full((N ** 3,), float(p["U"]), dtype=torch.float64, device="cuda"),
+                       torch.zeros(N, dtype=torch.float64, device="cuda")]).contiguous()
+        rg, logg = g.flow(y, frg.flow_opts(prec=frg.PREC_FP64, **f))
+        runs[vsym] = (rg, logg, y.cpu().numpy())
+    rg, logg, yg = runs[True]
+    _, _, yg0 = runs[False]
+    es = float(np.abs(logg[:, 0] - logo[:, 0]).max())
+    eV, eS = nrel(yg[:N ** 3].reshape(N, N, N), Vo), nrel(yg[N ** 3:], So)
+    e0 = nrel(yg, yg0)
+    print(f"[se vsym flow] oracle {ro['accepted']}/{ro['rejected']} reason {ro['reason']}; GPU {rg['accepted']}/"
+          f"{rg['rejected']} reason {rg['reason']}; s {es:.1e}, V {eV:.1e}, S {eS:.1e}; against every column "
+          f"{e0:.1e}", flush=True)
+    assert (rg["accepted"], rg["rejected"], rg["reason"]) == (ro["accepted"], ro["rejected"], ro["reason"])
+    assert es <= 1e-7 and eV <= 1e-7 and eS <= 1e-7 and e0 <= 1e-7
+    g.close()
+
+
+def test_symmetric_self_energy_split_reduced_flow_steps():
+    """Four fixed RK4 steps of a split flow of (V, S) with the reduced state (the
+    split stages hand the reduced vector itself to the layout and the tadpole)
+    against the oracle's FP64 steps."""
+    p = P16
+    N = p["N"]
+    m, g = O.Model(**p), frg.Context(**p)
+    f = dict(stepper="rk4", T0=1.0, T_min=0.2, fixed_steps=4, vmax=1e9)
+    Vo, So, ro, logo = m.flow_se(**f)
+    g.set_vsym(True)
+    g.set_self_energy(True, symmetric=True)
+    y = torch.cat([torch.full((N ** 3,), float(p["U"]), dtype=torch.float64, device="cuda"),
+                   torch.zeros(N, dtype=torch.float64, device="cuda")]).contiguous()
+    rg, _ = g.flow(y, frg.flow_opts(prec=frg.PREC_SPLIT_BF16, **f))
+    yg = y.cpu().numpy()
+    eV, eS = nrel(yg[:N ** 3].reshape(N, N, N), Vo), nrel(yg[N ** 3:], So)
+    dV = np.abs(Vo - p["U"]).max() / np.abs(Vo).max()
+    print(f"[se vsym split rk4] accepted {rg['accepted']}; V {eV:.1e} (V moved by {dV:.1e}), S {eS:.1e}", flush=True)
+    assert rg["accepted"] == ro["accepted"] == 4
+    assert eV <= 1e-4
+    assert eS <= 1e-4 and np.abs(So).max() > 1e-3
+    g.close()
+
+
+def test_captured_steps_equal_eager_steps_with_reduced_self_energy():
+    import os
+    p = P16
+    N = p["N"]
+    o = frg.flow_opts("dp54", frg.PREC_SPLIT_BF16, T0=1.0, T_min=0.1, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.02)
+
+    def run(graph):
+        if graph:
+            os.environ.pop("FRG_NO_GRAPH", None)
+        else:
+            os.environ["FRG_NO_GRAPH"] = "1"
+        g = frg.Context(**p)
+        try:
+            g.set_vsym(True)
+            g.set_self_energy(True, symmetric=True)
+            y = torch.cat([torch.full((N ** 3,), float(p["U"]), dtype=torch.float64, device="cuda"),
+                           torch.zeros(N, dtype=torch.float64, device="cuda")]).contiguous()
+            st = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+            g.flow_init(o, y, st)
+            for _ in range(4):
+                g.flow_step(o, y, st)
+            torch.cuda.synchronize()
+            return y.cpu().numpy(), st.cpu().numpy()
+        finally:
+            os.environ.pop("FRG_NO_GRAPH", None)
+            g.close()
+
+    (ye, se), (yg, sg) = run(False), run(True)
+    assert np.array_equal(ye, yg)
+    assert np.array_equal(se, sg, equal_nan=True)
+    assert np.abs(ye[N ** 3:]).max() > 0.0
