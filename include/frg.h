@@ -239,16 +239,19 @@ frg_status frg_rhs_noalloc(frg_ctx ctx, double T, const double *d_V, double *d_F
  *   enable = 2: the caller's S is C4v invariant (S(g j) = S(j)), which a flow
  *               from a C4v-invariant V and S keeps: the bubble rows are then
  *               still C4v images of each other and pp/ph pairs, and the C4v
- *               row reduction applies as without a self-energy.  frg_flow_init
- *               checks S (EINVAL beyond 1e-12 relative); a direct frg_rhs
- *               call takes it on trust.  ENOTSUP on a grid without exact C4v
- *               covariance (N % 8 != 0).
+ *               row reduction applies as without a self-energy; so does the
+ *               symmetric-vertex mode (frg_set_vsym), whose reduced flow
+ *               state then carries S after its reduced entries.
+ *               frg_flow_init checks S (EINVAL beyond 1e-12 relative); a
+ *               direct frg_rhs call takes it on trust.  ENOTSUP on a grid
+ *               without exact C4v covariance (N % 8 != 0).
  *   enable = 0: off.  Other values: EINVAL.
- * Polar and energy-angle grids, single flows only (ENOTSUP in a batch); EINVAL
- * while the symmetric-vertex mode is on (and frg_set_vsym(1) is refused while
- * the self-energy is on).  The interaction flow (frg_rhs_full, frg_iflow*)
- * ignores it.  Initial S = 0 is the caller's.  frg_self_energy reports the
- * switch (0, 1 or 2). */
+ * Polar and energy-angle grids, single flows only (ENOTSUP in a batch).
+ * enable = 1 is refused (EINVAL) while the symmetric-vertex mode is on, and
+ * frg_set_vsym(1) while a general self-energy is on.  Switching changes the
+ * length of the flowing array: start flows again (frg_flow_init) afterwards.
+ * The interaction flow (frg_rhs_full, frg_iflow*) ignores it.  Initial S = 0 is
+ * the caller's.  frg_self_energy reports the switch (0, 1 or 2). */
 frg_status frg_set_self_energy(frg_ctx ctx, int32_t enable);
 frg_status frg_self_energy(frg_ctx ctx, int32_t *active);
 
@@ -406,7 +409,9 @@ frg_status frg_kskip(frg_ctx ctx, int32_t *active, double *executed_frac);
  * creation failed.  frg_vsym reports the mode and the columns computed per
  * channel.  frg_check_vsym computes max_{g,j} |V(g j) - V(j)| / max |V| for a
  * device V (synchronises the stream).  frg_batch_set_vsym sets the mode for
- * every flow of a batch; the batch must be flow_init'ed again afterwards. */
+ * every flow of a batch; the batch must be flow_init'ed again afterwards.
+ * With a self-energy flowing along the mode needs it C4v invariant
+ * (frg_set_self_energy value 2; EINVAL with a general one). */
 frg_status frg_set_vsym(frg_ctx ctx, int32_t enable);
 frg_status frg_vsym(frg_ctx ctx, int32_t *active, int32_t *columns);
 frg_status frg_check_vsym(frg_ctx ctx, const double *d_V, double *rel_dev, void *stream);
