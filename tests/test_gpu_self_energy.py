@@ -278,19 +278,24 @@ def test_symmetric_self_energy_flow_step_for_step():
 
 
 def test_symmetric_self_energy_on_the_energy_angle_grid():
+    """The segmented sweep's paired rows with a C4v-invariant self-energy, with
+    every column (any V) and with one column per orbit (C4v-invariant V)."""
     p = dict(t=1.0, tp=-0.3, mu=-1.2, U=3.0, N=24, n_rad=1, n_ang=1, egrid=dict(n_E=32, max_level=4, rtol=1e-4))
     N = p["N"]
     m, g = O.Model(**p), frg.Context(**p)
-    g.set_self_energy(True, symmetric=True)
-    V = I.random_vertex(N, p["U"], seed=613, amp=0.4, symmetrise=False)
     S = symmetric_S(N, 614)
-    for T in (0.5, 0.02):
-        Fr, dSr = m.rhs_se(T, V, S)
-        for prec, tol in ((frg.PREC_FP64, 1e-10), (frg.PREC_SPLIT_BF16, 2e-4)):
-            F, dS = g.rhs_se(T, dev(V), dev(S), prec)
-            eF, eS = nrel(F.cpu().numpy(), Fr), nrel(dS.cpu().numpy(), dSr)
-            print(f"[se sym egrid] T={T} prec={prec}: F {eF:.2e} dS {eS:.2e}", flush=True)
-            assert eF <= tol and eS <= 1e-12
+    for vsym in (False, True):
+        g.set_self_energy(False)
+        g.set_vsym(vsym)
+        g.set_self_energy(True, symmetric=True)
+        V = I.random_vertex(N, p["U"], seed=613, amp=0.4, symmetrise=vsym)
+        for T in (0.5, 0.02):
+            Fr, dSr = m.rhs_se(T, V, S)
+            for prec, tol in ((frg.PREC_FP64, 1e-10), (frg.PREC_SPLIT_BF16, 2e-4)):
+                F, dS = g.rhs_se(T, dev(V), dev(S), prec)
+                eF, eS = nrel(F.cpu().numpy(), Fr), nrel(dS.cpu().numpy(), dSr)
+                print(f"[se sym egrid] vsym={vsym} T={T} prec={prec}: F {eF:.2e} dS {eS:.2e}", flush=True)
+                assert eF <= tol and eS <= 1e-12
     g.close()
 
 
