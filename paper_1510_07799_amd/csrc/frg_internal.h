@@ -84,7 +84,8 @@ struct BubbleArgs {
     // them in segments of kSegPoints (nullptr: polar grid, n_f <= 1024)
     const int32_t *count;
     // self-energy per patch ([N], nullptr: none): the second line's energy
-    // carries S of its patch (the first line's is in pa); unpaired rows only
+    // carries S of its patch (the first line's is in pa); dL/dT rows, paired
+    // only when S is C4v invariant
     const double *sigma;
 };
 // full: the bubble L itself (interaction flow) instead of dL/dT
