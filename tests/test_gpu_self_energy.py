@@ -431,3 +431,36 @@ def test_captured_steps_equal_eager_steps_with_reduced_self_energy():
     assert np.array_equal(ye, yg)
     assert np.array_equal(se, sg, equal_nan=True)
     assert np.abs(ye[N ** 3:]).max() > 0.0
+
+
+def test_symmetric_vertex_mode_toggled_mid_flow_with_self_energy():
+    """Switching the symmetric-vertex mode between steps converts the carried rhs
+    (first same as last), self-energy part included: a (V, S) flow switched on
+    after two steps and off after two more follows the every-column flow."""
+    p = P16
+    N = p["N"]
+    g = frg.Context(**p)
+    V0 = I.random_vertex(N, p["U"], seed=631, amp=0.3, symmetrise=True)
+    S0 = symmetric_S(N, 632, amp=0.05)
+    o = frg.flow_opts("dp54", frg.PREC_FP64, T0=1.0, T_min=0.2, rtol=1e-6, atol=1e-10, vmax=1e6, h0=-0.05)
+    runs = []
+    for pattern in ((False,) * 6, (False, False, True, True, False, False)):
+        g.set_self_energy(False)
+        g.set_vsym(False)
+        g.set_self_energy(True, symmetric=True)
+        y = torch.cat([dev(V0).reshape(-1), dev(S0)]).contiguous()
+        st = torch.zeros(frg.STATE_LEN, dtype=torch.float64, device="cuda")
+        g.flow_init(o, y, st)
+        for vs in pattern:
+            g.set_vsym(vs)
+            g.flow_step(o, y, st)
+        torch.cuda.synchronize()
+        g.set_vsym(False)
+        runs.append((y.cpu().numpy(), st.cpu().numpy()))
+    (ya, sa), (yb, sb) = runs
+    eV, eS = nrel(yb[:N ** 3], ya[:N ** 3]), nrel(yb[N ** 3:], ya[N ** 3:])
+    print(f"[se vsym toggle] V {eV:.2e} S {eS:.2e}", flush=True)
+    assert sb[frg.ST_S] == pytest.approx(sa[frg.ST_S], abs=1e-10)
+    assert eV <= 1e-10 and eS <= 1e-10
+    assert np.abs(ya[N ** 3:] - S0).max() > 1e-4
+    g.close()
