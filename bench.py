@@ -254,7 +254,7 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the CPU-baseline leg (default: every host core)")
     ap.add_argument("--cpu-only", action="store_true", help="run only the CPU-baseline leg")
-    ap.add_argument("--legs", default="split,fp64,batch,batch_fp64,batch64,split_full,fp64_full,rhs,iflow,egrid,se",
+    ap.add_argument("--legs", default="split,fp64,batch,batch_fp64,batch64,split_full,fp64_full,rhs,c4,iflow,egrid,se",
                     help="comma list of split, fp64 (one flow), batch, batch_fp64 (16 flows, split / FP64), "
                          "batch64 (64 flows, split), all in symmetric-vertex mode; split_full, fp64_full "
                          "(one flow, every column computed); iflow (the interaction flow of the paper's "
@@ -263,7 +263,8 @@ def main():
                          "flowing along: every bubble row, every column); rhs (frg_rhs alone, event-timed, "
                          "over V = U, FP64 flow states past max|V| 5, 10 and before the stop at 20, and "
                          "a random symmetric V, at "
-                         "T = 0.05 and 1e-3)")
+                         "T = 0.05 and 1e-3); c4 (the mixed batch of 256 flows, N = 32..96, in N = 96-"
+                         "equivalent rhs/s)")
     ap.add_argument("--batch-flows", type=int, default=16,
                     help="flows in the batched legs (N=96, 512 points/patch, drawn parameters)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="BYTES",
@@ -341,7 +342,7 @@ def main():
     tuned = {}
     results = {}
     for leg in legs:
-        if leg.startswith("batch") or leg in ("rhs", "iflow", "egrid", "se"):
+        if leg.startswith("batch") or leg in ("rhs", "c4", "iflow", "egrid", "se"):
             continue
         prec = frg.PREC_FP64 if leg.startswith("fp64") else frg.PREC_SPLIT_BF16
         orbit = not leg.endswith("_full")
@@ -406,6 +407,43 @@ def main():
         if leg in legs:
             batches[leg] = run_batch(nfl, prec)
             progress(f"leg {leg}: {batches[leg]['rhs'] / batches[leg]['seconds']:.1f} rhs/s")
+
+    c4 = None
+    if "c4" in legs:
+        # the mixed batch: 256 flows, 64 each of N = 32, 48, 64, 96 (16 x 16 points
+        # per patch, drawn mu, t', U), symmetric-vertex mode, in N = 96-equivalent
+        # work (the contraction's N^5)
+        draws = I.c4_flows()
+        eqv = [(d["N"] / 96.0) ** 5 for d in draws]
+        t_c = time.perf_counter()
+        b4 = frg.Batch(draws)
+        t_c = time.perf_counter() - t_c
+        b4.set_vsym(True)
+        c4 = {"workload": "256 flows, 64 each of N=32,48,64,96, 16x16 points/patch, (mu, t', U) drawn as in "
+                          "the batched configuration; DP5(4) steps from V=U at T=1, symmetric-vertex mode; "
+                          "default launch parameters", "batch_create_s": round(t_c, 2)}
+        for prec, nm in ((frg.PREC_SPLIT_BF16, "split"), (frg.PREC_FP64, "fp64")):
+            Vs4 = [torch.full((d["N"],) * 3, float(d["U"]), dtype=torch.float64, device="cuda") for d in draws]
+            o4 = frg.flow_opts("dp54", prec, T0=1.0, T_min=1e-3, rtol=1e-6, atol=1e-10, vmax=20.0, h0=-0.01)
+            b4.flow_init(Vs4, o4)
+            for _ in range(args.warmup):
+                b4.flow_step()
+            r0, _ = b4.results()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                b4.flow_step()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            r1, _ = b4.results()
+            d_rhs = [y["rhs_evals"] - x["rhs_evals"] for x, y in zip(r0, r1)]
+            c4[nm] = {"n96_equivalent_rhs_per_s": round(sum(e * k for e, k in zip(eqv, d_rhs)) / dt, 1),
+                      "rhs_per_s": round(sum(d_rhs) / dt, 1),
+                      "mean_active_flows": round(sum(d_rhs) / (RHS_PER_STEP * args.steps), 2)}
+            progress(f"leg c4 {nm}: {c4[nm]['n96_equivalent_rhs_per_s']:.1f} N=96-equivalent rhs/s")
+            del Vs4
+        b4.close()
+        torch.cuda.empty_cache()
 
     iflow = None
     if "iflow" in legs:
@@ -491,7 +529,7 @@ def main():
 
     head = batches.get("batch")
     if head is None and not results:
-        print(json.dumps({"rhs_micro": micro, "iflow_p1": iflow, "egrid": egrid, "se": se_leg}))
+        print(json.dumps({"rhs_micro": micro, "c4": c4, "iflow_p1": iflow, "egrid": egrid, "se": se_leg}))
         return
     rate = {leg: RHS_PER_STEP * args.steps / r["seconds"] for leg, r in results.items()}
     rate.update({leg: bb["rhs"] / bb["seconds"] for leg, bb in batches.items()})
@@ -567,6 +605,8 @@ def main():
 
     if micro is not None:
         out["rhs_micro"] = micro
+    if c4 is not None:
+        out["c4_mixed_batch"] = c4
     if egrid is not None:
         out["egrid_e1"] = egrid
     if se_leg is not None:
