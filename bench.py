@@ -42,7 +42,8 @@ def progress(msg: str) -> None:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("k_contract.hip", "k_bubbles.hip"):
+    # the kernels and the host code that builds their work lists and launch shapes
+    for f in ("k_contract.hip", "k_bubbles.hip", "abi.cpp"):
         with open(os.path.join(ROOT, "paper_1510_07799_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
