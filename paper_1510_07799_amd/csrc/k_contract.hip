@@ -355,11 +355,15 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
 }
 
 // ------------------------------------------------------------------ split BF16
-// bf16 offset of (row r, 16-byte chunk c) in a [rows][32] LDS tile: the four
-// chunks of a row are XOR-swizzled by bits 2-3 of the row, so the 16 rows an
-// MFMA operand read touches (and the rows written together) fall in distinct
-// banks without padding the rows.
-__device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ ((r >> 2) & 3)) << 3); }
+// bf16 offset of (row r, 16-byte chunk c) in a [rows][32] LDS tile (64-byte
+// rows): the four chunks of a row are XOR-swizzled by (r >> 1) ^ (r >> 3), so
+// any 8 aligned consecutive rows at one chunk fill the 8 16-byte slots of a
+// 128-byte bank line, and any 16 those of a 256-byte line.  The MFMA operand
+// reads (16 consecutive rows per chunk) and the A stores (consecutive rows)
+// then avoid the address conflicts of a 128-bit access served 8 or 16 lanes at
+// a time; XOR with bits 2-3 alone gives rows r and r + 2 the same banks in the
+// former case.
+__device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ (((r >> 1) ^ (r >> 3)) & 3)) << 3); }
 
 // KIND = TERM_PP: one product.  KIND = TERM_PH: the phc product and both phd
 // products in one block; all three read the same ph bubble row of a column,
