@@ -107,8 +107,7 @@ void launch_layout_f64(const double *V, int N, double *perm, hipStream_t s);
 void launch_layout_split(const double *V, int N, uint16_t *ahl, float *g32, hipStream_t s);
 int layout_blocks(int N);   // blocks (of 256 threads) of one layout pass
 
-enum Term { TERM_PP = 0, TERM_PHC = 1, TERM_PHD = 2,
-            TERM_PH = 3 };   // TERM_PH: phc and phd in one block (split path)
+enum Term { TERM_PP = 0, TERM_PHC = 1, TERM_PHD = 2 };
 
 // all three channels in one launch; term t writes C[t] + part * n3 for K part
 // `part`, laid out [tile position p][m] (p holds column cperm[t][p])
@@ -143,8 +142,7 @@ struct FusedContractArgs {
 void launch_contract_fused(const FusedContractArgs &a, bool split, hipStream_t s);
 int contract_block_rows(int N);
 // block kinds of one (m tile, column tile, K part), heaviest first, and the
-// number of products each multiplies: FP64 {phd: 2, phc: 1, pp: 1},
-// split {phc+phd: 3, pp: 1}
+// number of products each multiplies: {phd: 2, phc: 1, pp: 1} in both paths
 int contract_kinds(bool split);
 int contract_kind_products(bool split, int kind);
 constexpr int kContractCols = 64;     // columns per contraction tile

@@ -155,8 +155,7 @@ __device__ __forceinline__ Work decode_block(const FusedContractArgs &P, int id)
     const int per_term = P.mtiles * P.ctiles * P.KS;
     Work w;
     const int t = id / per_term;
-    if (SPLIT) w.term = t == 0 ? TERM_PH : TERM_PP;
-    else w.term = t == 0 ? TERM_PHD : (t == 1 ? TERM_PHC : TERM_PP);
+    w.term = t == 0 ? TERM_PHD : (t == 1 ? TERM_PHC : TERM_PP);
     id -= t * per_term;
     w.ks = id % P.KS;
     id /= P.KS;
@@ -365,24 +364,27 @@ __device__ __forceinline__ void body_f64(const FusedContractArgs &P, const Work 
 // former case.
 __device__ __forceinline__ int swz(int r, int c) { return r * 32 + ((c ^ (((r >> 1) ^ (r >> 3)) & 3)) << 3); }
 
-// KIND = TERM_PP: one product.  KIND = TERM_PH: the phc product and both phd
-// products in one block; all three read the same ph bubble row of a column,
-// so its window (and the index work around it) is loaded once for three
-// Z tiles.  Product p feeds accumulator 0 (phc) for p = 0, else 1 (phd).
-// The phd sum (-2 V(a,j2,b) + V(j2,a,b)) V(j1,b,j3) + V(a,j2,b) V(j1,b,a) is
-// regrouped as V(j2,a,b) V(j1,b,j3) + V(a,j2,b) (V(j1,b,a) - 2 V(j1,b,j3)): its
-// first operand is then the phc operand V(m,a,b), so the block streams two A
-// operands for three products (operand aop(p): 0 for p = 0, 1; 1 for p = 2).
+// KIND = TERM_PP or TERM_PHC: one product.  KIND = TERM_PHD: two products into
+// one accumulator.  The phd sum (-2 V(a,j2,b) + V(j2,a,b)) V(j1,b,j3) +
+// V(a,j2,b) V(j1,b,a) is regrouped as V(j2,a,b) V(j1,b,j3) + V(a,j2,b)
+// (V(j1,b,a) - 2 V(j1,b,j3)): its first operand is the phc operand V(m,a,b)
+// (operand aop(p): 0 for p = 0, 1 for p = 1).  The phc and phd kinds read the
+// same ph bubble rows and tile lists.  Computing phc and both phd products in
+// one block would load each window once, but its two accumulator sets hold the
+// kernel at 2 waves per SIMD (137 VGPRs + 48 AGPRs); apart, the kinds need at
+// most 115 + 24 and run 3 waves per SIMD, which outweighs reading the phc
+// operand and the windows twice.
 template <int KIND, int BM, bool FAST>
 __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Work &w, uint16_t *smem) {
-    constexpr bool PH = KIND == TERM_PH;
+    constexpr bool PHD = KIND == TERM_PHD;
+    constexpr bool PH = KIND != TERM_PP;          // a ph kind (phc or phd)
     constexpr int TT = PH ? TERM_PHC : TERM_PP;   // term whose bubble rows and tile lists are read
     constexpr int BK = 32;
     constexpr int ZK = BK / 4;    // k per thread in the Z loader
     constexpr int LD = BK;        // bf16 row pitch; chunks swizzled by swz()
-    constexpr int NP = PH ? 3 : 1;     // products (Z tiles)
-    constexpr int NA = PH ? 2 : 1;     // A operands
-    constexpr int NACC = PH ? 2 : 1;
+    constexpr int NP = PHD ? 2 : 1;    // products (Z tiles)
+    constexpr int NA = PHD ? 2 : 1;    // A operands
+    constexpr int NACC = 1;
     constexpr int G = BK / kContractChunk;
     constexpr int NCH = G * BM;                         // 16-byte A pieces (one chunk of one row)
     constexpr int ACH = (NCH + kThreads - 1) / kThreads;
@@ -399,7 +401,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     const GLOBAL_AS uint16_t *Ahl[NA];
     if constexpr (PH) {
         Ahl[0] = gload_ptr(P.Ahl[TERM_PHC][0]);
-        Ahl[1] = gload_ptr(P.Ahl[TERM_PHD][1]);
+        if constexpr (PHD) Ahl[1] = gload_ptr(P.Ahl[TERM_PHD][1]);
     } else {
         Ahl[0] = gload_ptr(P.Ahl[TERM_PP][0]);
     }
@@ -418,11 +420,11 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     const GLOBAL_AS float *brow = B + static_cast<int64_t>(rm.row) * K;
     // gather factors: pp V(j1,j2,a); phc V(b,j2,j3); phd V(j1,b,j3) and V(j1,b,a)
     const GLOBAL_AS float *g0 = gload_ptr(P.G32[TT][0]) + static_cast<int64_t>(c) * N;
-    const GLOBAL_AS float *gd = PH ? gload_ptr(P.G32[TERM_PHD][0]) + static_cast<int64_t>(c) * N : nullptr;
-    const GLOBAL_AS float *g1 = PH ? gload_ptr(P.G32[TERM_PHD][1]) + static_cast<int64_t>(c / N) * K : nullptr;
+    const GLOBAL_AS float *gd = PHD ? gload_ptr(P.G32[TERM_PHD][0]) + static_cast<int64_t>(c) * N : nullptr;
+    const GLOBAL_AS float *g1 = PHD ? gload_ptr(P.G32[TERM_PHD][1]) + static_cast<int64_t>(c / N) * K : nullptr;
 
     u32x4_t ra[NA][2][ACH];
-    float rb[ZK], rg[NP][ZK];
+    float rb[ZK], rg[2][ZK];   // pp, phc: rg[0] = the gather; phd: V(j1,b,j3), V(j1,b,a)
 
     // Buffer resources for the FAST path: 32-bit offsets, and an offset past
     // the end (kOOB) reads zeros, so padding entries and invalid columns need
@@ -442,7 +444,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
                                                kFlags);
         rG0 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(P.G32[TT][0]), 0, static_cast<int>(4 * n3),
                                                 kFlags);
-        if constexpr (PH) {
+        if constexpr (PHD) {
             rGd = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(P.G32[TERM_PHD][0]), 0,
                                                     static_cast<int>(4 * n3), kFlags);
             rG1 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(P.G32[TERM_PHD][1]), 0,
@@ -489,20 +491,23 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
             const float v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rG0, go, 0, 0));
 #pragma unroll
             for (int q = 0; q < ZK; ++q) rg[0][q] = v;
+        } else if constexpr (!PHD) {
+            const uint32_t go = zok ? g0_off + static_cast<uint32_t>(b) * 4u : kOOB;
+            const f4_t u0 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rG0, go, 0, 0));
+            const f4_t u1 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rG0, go + 16u, 0, 0));
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { rg[0][q] = u0[q]; rg[0][q + 4] = u1[q]; }
         } else {
             const uint32_t go = zok ? g0_off + static_cast<uint32_t>(b) * 4u : kOOB;
             const uint32_t g1o = zok ? g1_off + static_cast<uint32_t>(ent_chunk(e) * kContractChunk) * 4u : kOOB;
-            const f4_t u0 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rG0, go, 0, 0));
-            const f4_t u1 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rG0, go + 16u, 0, 0));
             const f4_t v0 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rGd, go, 0, 0));
             const f4_t v1 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rGd, go + 16u, 0, 0));
             const f4_t x0 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rG1, g1o, 0, 0));
             const f4_t x1 = __builtin_bit_cast(f4_t, __builtin_amdgcn_raw_buffer_load_b128(rG1, g1o + 16u, 0, 0));
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                rg[0][q] = u0[q]; rg[0][q + 4] = u1[q];
-                rg[1][q] = v0[q]; rg[1][q + 4] = v1[q];
-                rg[2][q] = x0[q]; rg[2][q + 4] = x1[q];
+                rg[0][q] = v0[q]; rg[0][q + 4] = v1[q];
+                rg[1][q] = x0[q]; rg[1][q + 4] = x1[q];
             }
         }
     };
@@ -529,7 +534,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
         load_bubble_window<ZK, 4, float, f4_t>(brow, rm, N, K, kb, a, b, zok, rb);
         if (!zok) {
 #pragma unroll
-            for (int p = 0; p < NP; ++p)
+            for (int p = 0; p < 2; ++p)
 #pragma unroll
                 for (int q = 0; q < ZK; ++q) rg[p][q] = 0.f;
             return;
@@ -549,34 +554,35 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
                 }
             }
         } else {
+            // phc: V(b,j2,j3) from g0; phd: V(j1,b,j3) from gd, then V(j1,b,a) from g1
+            const GLOBAL_AS float *gb = PHD ? gd : g0;
             if (inrow && (b & 3) == 0) {
 #pragma unroll
                 for (int q = 0; q < ZK; q += 4) {
-                    const f4_t u = *reinterpret_cast<const GLOBAL_AS f4_t *>(g0 + b + q);
-                    const f4_t v = *reinterpret_cast<const GLOBAL_AS f4_t *>(gd + b + q);
+                    const f4_t u = *reinterpret_cast<const GLOBAL_AS f4_t *>(gb + b + q);
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) { rg[0][q + t] = u[t]; rg[1][q + t] = v[t]; }
+                    for (int t = 0; t < 4; ++t) rg[0][q + t] = u[t];
                 }
             } else {
                 int bb = b;
 #pragma unroll
                 for (int q = 0; q < ZK; ++q) {
-                    const bool ok = kb + q < K;
-                    rg[0][q] = ok ? g0[bb] : 0.f;
-                    rg[1][q] = ok ? gd[bb] : 0.f;
+                    rg[0][q] = kb + q < K ? gb[bb] : 0.f;
                     if (++bb == N) bb = 0;
                 }
             }
-            if (kb + ZK <= K) {
+            if constexpr (PHD) {
+                if (kb + ZK <= K) {
 #pragma unroll
-                for (int q = 0; q < ZK; q += 4) {
-                    const f4_t v = *reinterpret_cast<const GLOBAL_AS f4_t *>(g1 + kb + q);
+                    for (int q = 0; q < ZK; q += 4) {
+                        const f4_t v = *reinterpret_cast<const GLOBAL_AS f4_t *>(g1 + kb + q);
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) rg[2][q + t] = v[t];
+                        for (int t = 0; t < 4; ++t) rg[1][q + t] = v[t];
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < ZK; ++q) rg[1][q] = kb + q < K ? g1[kb + q] : 0.f;
                 }
-            } else {
-#pragma unroll
-                for (int q = 0; q < ZK; ++q) rg[2][q] = kb + q < K ? g1[kb + q] : 0.f;
             }
         }
     };
@@ -600,8 +606,8 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
             bf8_t hi, lo;   // round-to-nearest-even conversions (v_cvt_pk_bf16_f32)
 #pragma unroll
             for (int q = 0; q < ZK; ++q) {
-                // product 2: V(j1,b,a) - 2 V(j1,b,j3) (the regrouped phd term)
-                const float gq = (PH && p == 2) ? fmaf(-2.0f, rg[1][q], rg[2][q]) : rg[p][q];
+                // phd product 1: V(j1,b,a) - 2 V(j1,b,j3) (the regrouped phd term)
+                const float gq = (PHD && p == 1) ? fmaf(-2.0f, rg[0][q], rg[1][q]) : rg[0][q];
                 const float z = rb[q] * gq;
                 const __bf16 zh = static_cast<__bf16>(z);
                 hi[q] = zh;
@@ -644,7 +650,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
         const int kch = lane >> 4;   // the lane's 8-wide k chunk of the step
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            const int u = (PH && p > 0) ? 1 : 0;
+            constexpr int u = 0;
             bf8_t zh[2], zl[2];
 #pragma unroll
             for (int ci = 0; ci < 2; ++ci) {
@@ -655,7 +661,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
 #pragma unroll
             for (int ri = 0; ri < RT; ++ri) {
                 const int ar = wm * (BM / 2) + ri * 16 + (lane & 15);
-                const int aop = (PH && p == 2) ? 1 : 0;
+                const int aop = (PHD && p == 1) ? 1 : 0;
                 const bf8_t ah = *reinterpret_cast<const bf8_t *>(sA + (aop * 2 + 0) * BM * LD + swz(ar, kch));
                 const bf8_t al = *reinterpret_cast<const bf8_t *>(sA + (aop * 2 + 1) * BM * LD + swz(ar, kch));
 #pragma unroll
@@ -675,7 +681,7 @@ __device__ __forceinline__ void body_split(const FusedContractArgs &P, const Wor
     // four rows is either wholly inside or outside)
 #pragma unroll
     for (int u = 0; u < NACC; ++u) {
-        const int term = PH ? (u == 0 ? TERM_PHC : TERM_PHD) : TERM_PP;
+        const int term = PHD ? TERM_PHD : (PH ? TERM_PHC : TERM_PP);
         GLOBAL_AS float *Cout = gstore_ptr(static_cast<float *>(P.C[term])) + static_cast<int64_t>(w.ks) * P.pstride;
 #pragma unroll
         for (int ci = 0; ci < 2; ++ci) {
@@ -696,10 +702,12 @@ __device__ __forceinline__ void run_work(const FusedContractArgs &P, const Work 
     if (SPLIT) {
         uint16_t *smem = reinterpret_cast<uint16_t *>(smem_d);
         if (P.fast) {
-            if (w.term == TERM_PH) body_split<TERM_PH, BM, true>(P, w, smem);
+            if (w.term == TERM_PHD) body_split<TERM_PHD, BM, true>(P, w, smem);
+            else if (w.term == TERM_PHC) body_split<TERM_PHC, BM, true>(P, w, smem);
             else body_split<TERM_PP, BM, true>(P, w, smem);
         } else {
-            if (w.term == TERM_PH) body_split<TERM_PH, BM, false>(P, w, smem);
+            if (w.term == TERM_PHD) body_split<TERM_PHD, BM, false>(P, w, smem);
+            else if (w.term == TERM_PHC) body_split<TERM_PHC, BM, false>(P, w, smem);
             else body_split<TERM_PP, BM, false>(P, w, smem);
         }
     } else {
@@ -773,12 +781,13 @@ __global__ void reset_counters(int *counters, int n) {
     if (static_cast<int>(threadIdx.x) < n) counters[threadIdx.x] = 0;
 }
 
-constexpr int contract_kinds_of(bool split) { return split ? 2 : 3; }
+constexpr int contract_kinds_of(bool) { return 3; }
 
-// LDS of one block: split [2 A operands][hi, lo] A (BM x 32) and [3 products]
-// [hi, lo] Z (64 x 32) bf16 tiles; FP64 [2 products] A (BM x 17) and Z (64 x 17) tiles
+// LDS of one block: split [2 A operands][hi, lo] A (BM x 32) and [2 products]
+// [hi, lo] Z (64 x 32) bf16 tiles (40 KB at BM = 96: three blocks per CU);
+// FP64 [2 products] A (BM x 17) and Z (64 x 17) tiles
 constexpr size_t lds_bytes(bool split, int bm) {
-    return split ? sizeof(uint16_t) * (2 * 2 * bm * 32 + 3 * 2 * BC * 32)
+    return split ? sizeof(uint16_t) * (2 * 2 * bm * 32 + 2 * 2 * BC * 32)
                  : sizeof(double) * (2 * bm * 17 + 2 * BC * 17);
 }
 
@@ -828,7 +837,7 @@ size_t contract_lds_bytes(bool split) { return lds_bytes(split, 96); }
 int contract_kinds(bool split) { return contract_kinds_of(split); }
 
 int contract_kind_products(bool split, int kind) {
-    if (split) return kind == 0 ? 3 : 1;
+    if (split) return kind == 0 ? 2 : 1;
     return kind == 0 ? 2 : 1;
 }
 
