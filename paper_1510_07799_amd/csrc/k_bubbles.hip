@@ -136,9 +136,12 @@ __device__ __forceinline__ float wdiv_t32_far(float c1, float c2, float b, float
 
 // Both rows of a pair (reading below): the second lines of the pp row q and of
 // the ph row -q have one energy, so b_ph = -b_pp exactly, and the two weighted
-// divided differences share exp(-2|b|) and the numerator's terms.  Each value
-// is bitwise the one the single-row form gives.
-// In FP32 the near forms of a pair fetch the point's coefficients once (coef()).
+// divided differences share exp(-2|b|) and the numerator's terms.  In FP32 each
+// value is bitwise the one the single-row form gives, and the near forms of a
+// pair fetch the point's coefficients once (coef()).  The FP64 temperature
+// derivative pair takes both quotients from one division, 1 / (t0 t1) with
+// t = (1+e)^2 d (a few ulp instead of a correctly rounded quotient each; an
+// FP64 division is a dozen instructions).
 template <class G>
 __device__ __forceinline__ void near32_pair(const G &coef, float d0, float d1, float &v0, float &v1) {
     const bool n0 = fabsf(d0) < kTaylor32, n1 = fabsf(d1) < kTaylor32;
@@ -177,10 +180,15 @@ __device__ __forceinline__ void wdiv_h64_pair(double a, double c1, double c2, do
     const double q2 = q * q;
     const double A = c1 * q2, be = b * e;
     const double d0 = a - b, d1 = a + b;
-    v0 = fma(c2, be, A) / (q2 * d0);
-    v1 = fma(c2, -be, A) / (q2 * d1);
-    if (fabs(d0) < kTaylor64) v0 = wdiv_h64_near(a, c2, b);
-    if (fabs(d1) < kTaylor64) v1 = wdiv_h64_near(a, c2, -b);
+    const bool n0 = fabs(d0) < kTaylor64, n1 = fabs(d1) < kTaylor64;
+    // a near term's denominator is replaced by 1 (its value comes from the
+    // Taylor form), so a zero d cannot reach the other term
+    const double t0 = q2 * (n0 ? 1.0 : d0), t1 = q2 * (n1 ? 1.0 : d1);
+    const double inv = 1.0 / (t0 * t1);
+    v0 = fma(c2, be, A) * (t1 * inv);
+    v1 = fma(c2, -be, A) * (t0 * inv);
+    if (n0) v0 = wdiv_h64_near(a, c2, b);
+    if (n1) v1 = wdiv_h64_near(a, c2, -b);
 }
 __device__ __forceinline__ void wdiv_t64_pair(double a, double c1, double c2, double b, double &v0, double &v1) {
     const double e = exp(-2.0 * fabs(b));
